@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled phase-field step on one MI355X.
+
+One "step" is one call-level pass of the whole hot path: the mechanical
+equilibrium solve (Jacobi-PCG to the workload's tolerance, warm-started from
+the previous step), the J2 return map, the elastic / chemical driving forces,
+the fluxes and reaction, the explicit update of the five fields and the FP64
+ledger.  The default workload is the 128^3 core-shell recipe (wuestite sphere
+of radius 48 cells in a 4-cell ferrite shell, gas outside, +-0.01 noise,
+plasticity on, FP32 state with FP64 reductions, CG to 1e-6).
+
+Prints ONE JSON line.  Besides the throughput it reports the dominant
+kernel's roofline figures (average launch duration measured with HIP events
+over the timed region), the same workload on the plain FP64 GPU path, the
+field / increment error of the mixed path against the FP64 CPU oracle on a
+small instance of the same recipe, and the oracle's own throughput on a
+bounded sample (``cpu_baseline``).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
+
+
+def algorithmic_bytes_per_cell(kind, dim, es):
+    """Bytes a kernel must move per cell (reads + writes of the arrays the
+    method needs), by kernel class; es = element size of the state."""
+    nc = 4 if dim == 2 else 6
+    if kind == "apply":        # read z, p_old (dim each), K, G; write p_new, q (dim each)
+        return (4 * dim + 2) * es
+    if kind == "update":       # read u, p, r, q, D^-1; write u, r, z (dim each)
+        return 8 * dim * es
+    if kind == "step":         # read 5 fields, mu, u, eps_p, eps_P; write 5 fields, eps_p, eps_P
+        return (5 + 1 + dim + nc + 1 + 5 + nc + 1) * es
+    if kind == "mu":           # read phi_f, phi_w, x_O; write mu
+        return 4 * es
+    if kind == "solve_setup":  # average of ||b|| (K, G, phi_f, eps_p), residual (+u, r, z, D^-1), true residual
+        return ((2 + 1 + nc) + (dim + 2 + 1 + nc + 3 * dim) + (dim + 2 + 1 + nc)) * es / 3.0
+    return 0.0
+
+
+def run_gpu(wl, precision, steps, warmup, timing, rtol):
+    import torch
+    from paper_2111_11538_amd import pf
+    ctx = pf.Context(wl.dim, wl.shape, wl.h, wl.dt, wl.params, device=0, precision=precision,
+                     plasticity=wl.plasticity, cg_rtol=rtol, warm="prev")
+    ctx.set_fields(wl.fields)
+    print(f"[bench] {precision}: warmup {warmup} steps", file=sys.stderr, flush=True)
+    st0 = ctx.step(warmup) if warmup > 0 else ctx.step(0)
+    it0 = st0["cg_iters_total"]
+    if timing:
+        ctx.timing(True)
+    torch.cuda.synchronize()
+    print(f"[bench] {precision}: timing {steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    st = ctx.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = ctx.timing_report() if timing else None
+    if timing:
+        ctx.timing(False)
+    ctx.close()
+    return {"seconds": t1 - t0, "stats": st, "cg_iters": st["cg_iters_total"] - it0, "kernels": rep}
+
+
+def accuracy_sample(n=32, steps=10):
+    """Mixed GPU path against the FP64 oracle on an n^3 instance of the recipe."""
+    import numpy as np
+    from paper_2111_11538_amd import inputs as I
+    from paper_2111_11538_amd import pf
+    from oracle import oracle as O
+    wl = I.workload("core_shell_3d", n=n)
+    g = pf.Context(3, wl.shape, wl.h, wl.dt, wl.params, precision="mixed", plasticity=True, cg_rtol=wl.cg_rtol)
+    g.set_fields(wl.fields)
+    o = O.OracleSim(3, wl.shape, wl.h, wl.dt, wl.params, wl.fields, plasticity=True, cg_rtol=wl.cg_rtol)
+    for _ in range(steps):
+        g.step()
+        o.step()
+    out = g.fields()
+    g.close()
+    fe, ie = {}, {}
+    for k in ("phi_f", "phi_w", "xO", "xH", "xW"):
+        b, a, b0 = o.f[k], out[k], wl.fields[k]
+        rms = float(np.sqrt(np.mean(b * b)))
+        fe[k] = float(np.linalg.norm(a - b) / np.linalg.norm(b)) if rms >= 1e-6 else float(np.sqrt(np.mean((a - b) ** 2)))
+        db = b - b0
+        ie[k] = float(np.linalg.norm((a - b0) - db) / np.linalg.norm(db)) if np.linalg.norm(db) > 0 else 0.0
+    ue = float(np.linalg.norm(out["uz"] - o.uz) / np.linalg.norm(o.uz))
+    return {"sample": f"{n}^3 core-shell recipe, {steps} steps, mixed GPU vs FP64 oracle",
+            "max_field_rel_err": max(fe.values()), "field_err": fe, "incr_rel_err": ie, "u_rel_err": ue}
+
+
+def cpu_baseline(n=64, steps=4):
+    """The FP64 oracle on a bounded sample: an n^3 instance of the core-shell
+    recipe, one untimed cold-start step, then `steps` timed warm-started steps."""
+    from paper_2111_11538_amd import inputs as I
+    from oracle import oracle as O
+    wl = I.workload("core_shell_3d", n=n)
+    o = O.OracleSim(3, wl.shape, wl.h, wl.dt, wl.params, wl.fields, plasticity=True, cg_rtol=wl.cg_rtol)
+    o.step()
+    t0 = time.perf_counter()
+    st = None
+    iters = 0
+    for _ in range(steps):
+        st = o.step()
+        iters += st["cg_iters"]
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": n ** 3 * steps / dt, "unit": "voxel-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 C oracle (OpenMP), {n}^3 instance of the core-shell recipe, steps 2-{steps + 1} "
+                      f"(warm-started, {iters / steps:.0f} CG iterations/step), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="core_shell_3d")
+    ap.add_argument("--n", type=int, default=None, help="grid side override (reduced runs)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2111_11538_amd import inputs as I
+    wl = I.workload(args.workload, n=args.n)
+    ncell = 1
+    for s in wl.shape:
+        ncell *= s
+    es = 4 if wl.precision == "mixed" else 8
+
+    res = run_gpu(wl, wl.precision, args.steps, args.warmup, True, wl.cg_rtol)
+    ms = 1e3 * res["seconds"] / args.steps
+    value = ncell * args.steps / res["seconds"]
+
+    # dominant kernel and its roofline
+    kern = res["kernels"]
+    dom = max((k for k in ("apply", "update", "step", "mu", "solve_setup")), key=lambda k: kern[k][0])
+    tot_ms, nl = kern[dom]
+    avg_s = tot_ms / 1e3 / max(nl, 1)
+    bytes_per_launch = algorithmic_bytes_per_cell(dom, wl.dim, es) * ncell
+    achieved = bytes_per_launch / avg_s / 1e9
+    kernels = {k: {"total_ms": round(v[0], 3), "launches": v[1],
+                   "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None,
+                   "GBps_algorithmic": (round(algorithmic_bytes_per_cell(k, wl.dim, es) * ncell / (v[0] / 1e3 / v[1]) / 1e9, 1)
+                                        if v[1] and algorithmic_bytes_per_cell(k, wl.dim, es) > 0 else None)}
+               for k, v in kern.items()}
+
+    line = {
+        "metric": "voxel-steps/s at <=1e-4 rel err vs FP64 oracle; % of HBM peak; CG iters/step",
+        "value": value, "unit": "voxel-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 state + f64 reductions" if wl.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name} {'x'.join(str(s) for s in reversed(wl.shape))}, plasticity on, "
+                               f"CG rtol {wl.cg_rtol:g}, warm start = previous step",
+                   "cells": ncell, "dt_s": wl.dt, "h_m": wl.h},
+        "cg_iters_per_step": res["cg_iters"] / args.steps,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)},
+        "kernels": kernels,
+    }
+    if not args.no_fp64:
+        r64 = run_gpu(wl, "fp64", max(4, args.steps // 2), args.warmup, False, wl.cg_rtol)
+        s64 = max(4, args.steps // 2)
+        line["fp64_gpu"] = {"value": ncell * s64 / r64["seconds"], "ms_per_step": 1e3 * r64["seconds"] / s64,
+                            "cg_iters_per_step": r64["cg_iters"] / s64}
+    if not args.no_accuracy:
+        print("[bench] accuracy sample", file=sys.stderr, flush=True)
+        line["accuracy"] = accuracy_sample()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/* pf.h -- C ABI of the MI355X (gfx950) library that advances the
+ * chemo-mechanically coupled phase-field model of wuestite-to-iron reduction
+ * by hydrogen (Bai, Mianroodi, Ma, Kwiatkowski da Silva, Svendsen, Raabe,
+ * arXiv:2111.11538) on a regular 2D/3D voxel grid.
+ *
+ * One call of pf_step advances the unknowns of the model's field relations
+ * (Section 2.4, Eq. 29): the phase fields phi_f, phi_w (Allen-Cahn, Eq. 29
+ * lines 5-6 with Eq. 33), the species x_O, x_H, x_H2O (Eq. 29 lines 1-3 with
+ * the variational O flux of Eq. 24, Eq. 30 and Section 3.2), the plastic
+ * strain (J2 with linear hardening, Eq. 25 and Eq. 34) and the displacement
+ * of the quasi-static momentum balance (Eq. 29 line 4), in a small-strain
+ * reading of the kinematics (eigenstrain d_T^(1/3) - 1 from Eq. 9, moduli of
+ * Eq. 32).  All arithmetic runs in the library's HIP kernels.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns pf_status and never throws.  pf_last_error()
+ *    gives a human-readable message for the last failure on a context.
+ *  - Device memory is owned by the caller: pf_init receives one device
+ *    workspace of pf_workspace_bytes() bytes (e.g. a torch uint8 tensor) and
+ *    a HIP stream; the library carves all state out of it and never frees it.
+ *    pf_destroy frees only host-side objects.
+ *  - Calls on one context are stream-ordered on that stream and are not
+ *    thread-safe; different contexts are independent.
+ *  - Field exchange (pf_fields) always uses FP64, compact, x-fastest arrays:
+ *    cells [nz][ny][nx] (2D: [ny][nx]); staggered displacement faces
+ *    u_x [nz][ny][nx+1], u_y [nz][ny+1][nx], u_z [nz+1][ny][nx]; plastic
+ *    strain component-major with components xx, yy, zz, xy (2D, plane strain)
+ *    or xx, yy, zz, xy, xz, yz (3D).  Internally the library may hold the
+ *    state in FP32 (PF_MIXED) and in a padded layout.
+ *  - SI units throughout.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_ctx pf_ctx;
+
+typedef enum {
+  PF_OK = 0,
+  PF_ERR_INVALID_ARG = 1,       /* bad pointer, size or configuration */
+  PF_ERR_HIP = 2,               /* a HIP runtime call failed */
+  PF_ERR_OOM = 3,               /* workspace smaller than pf_workspace_bytes() */
+  PF_ERR_CG_NOT_CONVERGED = 4,  /* mechanics solve hit cg_max_iter */
+  PF_ERR_NONFINITE = 5,         /* a NaN/Inf appeared in the fields */
+  PF_ERR_LEDGER = 6,            /* oxygen ledger drift above ledger_tol */
+  PF_ERR_BAD_STATE = 7,         /* context failed earlier; restore fields first */
+  PF_ERR_UNSUPPORTED = 8
+} pf_status;
+
+typedef enum { PF_FP64 = 0, PF_MIXED = 1 } pf_precision;   /* MIXED: FP32 state and stencils, FP64 reductions */
+typedef enum { PF_WARM_ZERO = 0, PF_WARM_PREV = 1 } pf_warm;
+
+typedef enum {
+  PF_FIELD_PHI_F = 0, PF_FIELD_PHI_W = 1, PF_FIELD_XO = 2, PF_FIELD_XH = 3, PF_FIELD_XW = 4,
+  PF_FIELD_UX = 5, PF_FIELD_UY = 6, PF_FIELD_UZ = 7,
+  PF_FIELD_EPSP = 8,            /* plastic strain tensor, 4 (2D) or 6 (3D) components */
+  PF_FIELD_EPSP_ACC = 9         /* accumulated plastic strain epsilon_P */
+} pf_field;
+
+typedef struct {
+  int dim;                /* 2 (plane strain) or 3 */
+  int nx, ny, nz;         /* cells; nz must be 1 when dim == 2; each >= 1 */
+  double h;               /* cell size (m) */
+  double dt;              /* explicit time step (s) */
+  int precision;          /* pf_precision */
+  int mechanics;          /* 1: elastic energy, eigenstrain and the equilibrium solve are on */
+  int plasticity;         /* 1: J2 return map after each solve */
+  int dirichlet;          /* 1: x_H = xH_bc and x_H2O = xW_bc on every outer face; 0: closed box */
+  int chem_phase;         /* 1 (the model): chemical energy drives the phase fields */
+  double cg_rtol;         /* stop when ||b - A u|| <= cg_rtol ||b|| */
+  int cg_max_iter;        /* reaching it is an error */
+  int warm;               /* pf_warm: start of each step's solve */
+  double ledger_tol;      /* |O drift| above this raises PF_ERR_LEDGER; <= 0 disables */
+} pf_config;
+
+/* Material and model parameters, Table 1 of the paper; phase index 0 ferrite,
+ * 1 gas, 2 wuestite. */
+typedef struct {
+  double R, theta, Vmol;  /* gas constant, temperature, molar volume */
+  double w[3];            /* barrier heights w_a (J/m^3) */
+  double eps[3];          /* phase gradient energy coefficients (J/m) */
+  double L[3];            /* phase mobilities (m^3/(J s)) */
+  double kappaO;          /* oxygen gradient energy coefficient (J/m) */
+  double K[3], G[3];      /* bulk and shear moduli (Pa) */
+  double sigY, Hhard;     /* yield stress and linear hardening modulus (Pa) */
+  double DO[3], DH[3], DW[3];   /* diffusivities of O, H, H2O per phase (m^2/s) */
+  double kfor;            /* forward reaction constant (1/s) */
+  double Omega_f;         /* relative volume decrease of the transformation */
+  double xH_bc, xW_bc;    /* boundary values of x_H and x_H2O */
+  int m_form;             /* 0: m(x) = 16 x^2 (1-x)^2 ; 1: m(x) = x^2 (1-x)^2 */
+  int pad_;
+} pf_params;
+
+typedef struct {
+  int cg_iters;           /* CG iterations of the last solve */
+  int warm_used;          /* pf_warm used by the last solve */
+  double cg_rel_resid;    /* true ||b - A u|| / ||b|| after the last solve */
+  double O_tot, O_out, O_drift;   /* h^d sum (x_O + x_H2O); cumulative outflux; relative drift */
+  double H_tot, H_out, H_drift;   /* same for hydrogen, h^d sum (x_H + 2 x_H2O) */
+  double red_degree;      /* reduction degree f = 1 - sum x_O / sum x_O(ledger reset), Eq. 39 */
+  double max_vm;          /* largest cell von Mises stress after the return map (Pa) */
+  double max_epsP;        /* largest accumulated plastic strain */
+  long long step;         /* steps taken since pf_init */
+  int nonfinite;          /* number of cells with a non-finite field value in the last step */
+  int pad_;
+  long long cg_iters_total;   /* CG iterations summed over every solve since pf_init */
+} pf_step_stats;
+
+/* Bytes of device workspace pf_init needs for this configuration (0 if the
+ * configuration is invalid). */
+size_t pf_workspace_bytes(const pf_config *cfg);
+
+/* Create a context.  `workspace` is a device pointer (256-byte aligned) to at
+ * least pf_workspace_bytes(cfg) bytes, owned by the caller and kept alive
+ * until pf_destroy; `hip_stream` is a hipStream_t (NULL = default stream).
+ * All fields start at zero; set them with pf_fields, then step.  The ledger
+ * reference (initial O, H and x_O totals) is taken at the first pf_step after
+ * any field was set, or by pf_ledger_reset. */
+pf_status pf_init(const pf_config *cfg, const pf_params *params, void *workspace, size_t workspace_bytes,
+                  void *hip_stream, pf_ctx **out);
+
+/* Advance `nsteps` explicit steps (Section 2.4 field relations; each step:
+ * equilibrium solve with phi^n and eps_p^n, return map, driving forces,
+ * fluxes and reaction, explicit Euler update, FP64 ledger).  Synchronises the
+ * stream once at the end; `last` (nullable) receives the stats of the last
+ * step.  After an error the context is in BAD_STATE until fields are set. */
+pf_status pf_step(pf_ctx *ctx, int nsteps, pf_step_stats *last);
+
+/* Solve only the mechanical equilibrium (Eq. 29 line 4) for the current phase
+ * fields and plastic strain, starting from zero (PF_WARM_ZERO) or from the
+ * current displacement (PF_WARM_PREV).  Fills cg_iters, warm_used and
+ * cg_rel_resid of `stats` (nullable). */
+pf_status pf_mech_solve(pf_ctx *ctx, int warm, pf_step_stats *stats);
+
+/* Copy one field between the context and caller memory.  dir 0: get (context
+ * -> ptr), 1: set (ptr -> context).  ptr holds FP64 compact data (layouts
+ * above) of exactly nbytes; ptr_is_device selects a device or host pointer.
+ * Displacement values on the roller faces are forced to zero on set.
+ * Stream-ordered; a get on a host pointer synchronises the stream. */
+pf_status pf_fields(pf_ctx *ctx, int field_id, int dir, void *ptr, size_t nbytes, int ptr_is_device);
+
+/* Take the current fields as the ledger reference (O, H and x_O totals) and
+ * zero the cumulative boundary fluxes. */
+pf_status pf_ledger_reset(pf_ctx *ctx);
+
+/* Message of the last error on this context ("" if none); ctx may be NULL for
+ * errors raised before a context existed. */
+const char *pf_last_error(const pf_ctx *ctx);
+
+/* Kernel classes reported by the timing interface. */
+typedef enum {
+  PF_K_APPLY = 0,     /* q = A p with the fused direction update (one per CG iteration) */
+  PF_K_UPDATE = 1,    /* u, r, z update with FP64 partial dots (one per CG iteration) */
+  PF_K_SOLVE_SETUP = 2, /* ||b||, initial residual / diagonal, true residual (three per solve) */
+  PF_K_STEP = 3,      /* fused chemistry, phase-field and plasticity update (one per step) */
+  PF_K_MU = 4,        /* oxygen chemical potential (one per step) */
+  PF_K_OTHER = 5,     /* moduli, convergence checks, ledger (small kernels), and the
+                         CG launches queued past convergence, which exit at once */
+  PF_K_COUNT = 6
+} pf_kernel_kind;
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch.  enable = 1 clears the accumulators and starts recording,
+ * 0 stops.  Recording adds a few microseconds per launch; leave it off for
+ * throughput runs. */
+pf_status pf_timing(pf_ctx *ctx, int enable);
+
+/* Accumulated device time (ms) and launch count of one pf_kernel_kind since
+ * timing was enabled.  Synchronises the stream. */
+pf_status pf_timing_get(pf_ctx *ctx, int kind, double *total_ms, long long *launches);
+
+/* Free the host-side context (never the caller's workspace). */
+void pf_destroy(pf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

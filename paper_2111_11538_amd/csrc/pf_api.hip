@@ -1,0 +1,613 @@
+// Host side of the C ABI declared in include/pf.h: context, workspace layout,
+// device-side CG control and field exchange.  Every numerical step runs in the
+// kernels of pf_kernels.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "pf_kernels.h"
+
+using namespace pfk;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kUpdBlocksMax = 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  Grid g;
+  int nc;                  // plastic strain components
+  size_t es;               // element size (4 or 8)
+  int kz;
+  dim3 gel, gcell;
+  int nb_el, nb_cell, nb_upd;
+  size_t stage_elems;
+  // byte offsets into the workspace
+  size_t o_fld[2][5], o_u[3], o_epsp, o_epsP, o_mu, o_K, o_G;
+  size_t o_r[3], o_z[3], o_pa[3], o_pb[3], o_q[3], o_di[3];
+  size_t o_scal, o_part_u, o_part_a, o_part_b, o_part_c, o_stage;
+  size_t total;
+};
+
+bool valid_cfg(const pf_config* c, char* msg, size_t len) {
+  if (!c) { snprintf(msg, len, "config is NULL"); return false; }
+  if (c->dim != 2 && c->dim != 3) { snprintf(msg, len, "dim must be 2 or 3 (got %d)", c->dim); return false; }
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) { snprintf(msg, len, "grid sizes must be >= 1"); return false; }
+  if (c->dim == 2 && c->nz != 1) { snprintf(msg, len, "nz must be 1 when dim == 2"); return false; }
+  if (!(c->h > 0.0) || !(c->dt > 0.0)) { snprintf(msg, len, "h and dt must be positive"); return false; }
+  if (c->precision != PF_FP64 && c->precision != PF_MIXED) { snprintf(msg, len, "unknown precision %d", c->precision); return false; }
+  if (c->mechanics && (!(c->cg_rtol > 0.0) || c->cg_max_iter < 1)) { snprintf(msg, len, "cg_rtol > 0 and cg_max_iter >= 1 required"); return false; }
+  if (c->warm != PF_WARM_ZERO && c->warm != PF_WARM_PREV) { snprintf(msg, len, "unknown warm start %d", c->warm); return false; }
+  long long px = (c->nx + 15) / 16 * 16;
+  if (px * c->ny * (long long)c->nz >= (1LL << 31) / 8) { snprintf(msg, len, "grid too large for 32-bit indexing"); return false; }
+  return true;
+}
+
+Layout make_layout(const pf_config* c) {
+  Layout L{};
+  Grid& g = L.g;
+  g.nx = c->nx; g.ny = c->ny; g.nz = c->nz;
+  g.px = (c->nx + 15) / 16 * 16;
+  g.n = g.px * g.ny * g.nz;
+  L.nc = c->dim == 2 ? 4 : 6;
+  L.es = c->precision == PF_FP64 ? 8 : 4;
+  int nbx = (g.nx + TX - 1) / TX, nby = (g.ny + TY - 1) / TY;
+  L.kz = 1;
+  if (c->dim == 3) {
+    L.kz = 8;
+    while (L.kz > 1 && (long long)nbx * nby * ((g.nz + L.kz - 1) / L.kz) < 2048) L.kz /= 2;
+  }
+  L.gel = dim3(nbx, nby, c->dim == 3 ? (g.nz + L.kz - 1) / L.kz : 1);
+  L.nb_el = nbx * nby * (int)L.gel.z;
+  L.gcell = dim3(nbx, nby, g.nz);
+  L.nb_cell = nbx * nby * g.nz;
+  int vn = (int)(16 / L.es);
+  L.nb_upd = std::max(1, std::min(kUpdBlocksMax, (g.n / vn + NT - 1) / NT));
+  size_t fx = (size_t)(g.nx + 1) * g.ny * g.nz, fy = (size_t)g.nx * (g.ny + 1) * g.nz;
+  size_t fz = (size_t)g.nx * g.ny * (g.nz + 1);
+  L.stage_elems = std::max(fx, std::max(fy, fz));
+  size_t off = 0;
+  size_t arr = align_up((size_t)g.n * L.es);
+  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+  for (int s = 0; s < 2; ++s)
+    for (int f = 0; f < 5; ++f) L.o_fld[s][f] = take(arr);
+  for (int d = 0; d < 3; ++d) L.o_u[d] = d < c->dim ? take(arr) : 0;
+  L.o_epsp = take(arr * L.nc);
+  L.o_epsP = take(arr);
+  L.o_mu = take(arr);
+  L.o_K = take(arr);
+  L.o_G = take(arr);
+  for (int d = 0; d < c->dim; ++d) {
+    L.o_r[d] = take(arr); L.o_z[d] = take(arr); L.o_pa[d] = take(arr);
+    L.o_pb[d] = take(arr); L.o_q[d] = take(arr); L.o_di[d] = take(arr);
+  }
+  L.o_scal = take(S_COUNT * sizeof(double));
+  int nbmax = std::max(L.nb_el, std::max(L.nb_cell, L.nb_upd));
+  L.o_part_u = take(2 * (size_t)nbmax * sizeof(double));
+  L.o_part_a = take(2 * (size_t)nbmax * sizeof(double));
+  L.o_part_b = take(2 * (size_t)nbmax * sizeof(double));
+  L.o_part_c = take(NQ_STEP * (size_t)nbmax * sizeof(double));
+  L.o_stage = take(L.stage_elems * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+KP<T> make_kp(const pf_config* c, const pf_params* p) {
+  KP<T> k{};
+  k.scale = (T)(p->R * p->theta / p->Vmol);
+  for (int a = 0; a < 3; ++a) {
+    k.w[a] = (T)p->w[a]; k.eps[a] = (T)p->eps[a]; k.L[a] = (T)p->L[a];
+    k.K[a] = (T)p->K[a]; k.G[a] = (T)p->G[a];
+    k.DO[a] = (T)p->DO[a]; k.DH[a] = (T)p->DH[a]; k.DW[a] = (T)p->DW[a];
+  }
+  k.kappaO = (T)p->kappaO;
+  k.sigY = (T)p->sigY; k.Hh = (T)p->Hhard;
+  k.kfor = (T)p->kfor; k.Omega = (T)p->Omega_f;
+  k.xHbc = (T)p->xH_bc; k.xWbc = (T)p->xW_bc;
+  k.h = (T)c->h; k.ih = (T)(1.0 / c->h); k.ih2 = (T)(1.0 / (c->h * c->h)); k.dt = (T)c->dt;
+  k.mform = p->m_form; k.dirichlet = c->dirichlet; k.chem = c->chem_phase;
+  k.plastic = c->plasticity; k.mech = c->mechanics;
+  return k;
+}
+
+}  // namespace
+
+struct pf_ctx {
+  pf_config cfg;
+  pf_params prm;
+  hipStream_t stream;
+  Layout L;
+  char* ws;
+  double* host_scal;       // pinned copy of the device scalars
+  char err[512];
+  bool bad;
+  bool ledger_valid;
+  int cur;                 // which field buffer holds the current state
+  long long steps;
+  int last_iters;
+  int warm_used;
+  // per-kernel event timing
+  bool timing;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec { int kind, ev, launch; };
+  std::vector<Rec> pending;   // start event index ev, stop ev + 1; launch = CG launch index or -1
+  long long iters_total;
+  int ev_next;
+  double t_ms[PF_K_COUNT];
+  long long t_n[PF_K_COUNT];
+  template <typename T> T* arr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  double* scal() const { return arr<double>(L.o_scal); }
+};
+
+static char g_err[512] = "";
+
+static pf_status fail(pf_ctx* c, pf_status s, const char* fmt, ...) {
+  char* dst = c ? c->err : g_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return fail((ctx), PF_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCHCHK(ctx)                                                                               \
+  do {                                                                                               \
+    hipError_t e_ = hipGetLastError();                                                               \
+    if (e_ != hipSuccess) return fail((ctx), PF_ERR_HIP, "kernel launch: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+// Resolve recorded event pairs into the per-kind accumulators (after a sync).
+static void timing_flush(pf_ctx* c) {
+  for (auto& pr : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[pr.ev], c->ev_pool[pr.ev + 1]) == hipSuccess) {
+      c->t_ms[pr.kind] += ms;
+      c->t_n[pr.kind] += 1;
+    }
+  }
+  c->pending.clear();
+  c->ev_next = 0;
+}
+
+// Launch helper: brackets the launch with events when timing is on.
+template <typename F>
+static void timed(pf_ctx* c, int kind, F&& launch, int cg_launch = -1) {
+  if (!c->timing) {
+    launch();
+    return;
+  }
+  if (c->ev_next + 2 > (int)c->ev_pool.size()) {
+    (void)hipStreamSynchronize(c->stream);
+    timing_flush(c);
+  }
+  int i = c->ev_next;
+  c->ev_next += 2;
+  (void)hipEventRecord(c->ev_pool[i], c->stream);
+  launch();
+  (void)hipEventRecord(c->ev_pool[i + 1], c->stream);
+  c->pending.push_back({kind, i, cg_launch});
+}
+
+// ---------------------------------------------------------------------------
+// typed implementation
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+struct Impl {
+  static CellArgs<T> cell_args(pf_ctx* c) {
+    const Layout& L = c->L;
+    CellArgs<T> a{};
+    a.g = L.g;
+    a.p = make_kp<T>(&c->cfg, &c->prm);
+    int s = c->cur;
+    a.pf = c->arr<T>(L.o_fld[s][0]); a.pw = c->arr<T>(L.o_fld[s][1]); a.xO = c->arr<T>(L.o_fld[s][2]);
+    a.xH = c->arr<T>(L.o_fld[s][3]); a.xW = c->arr<T>(L.o_fld[s][4]);
+    a.npf = c->arr<T>(L.o_fld[s ^ 1][0]); a.npw = c->arr<T>(L.o_fld[s ^ 1][1]); a.nxO = c->arr<T>(L.o_fld[s ^ 1][2]);
+    a.nxH = c->arr<T>(L.o_fld[s ^ 1][3]); a.nxW = c->arr<T>(L.o_fld[s ^ 1][4]);
+    a.mu = c->arr<T>(L.o_mu);
+    a.mu_out = c->arr<T>(L.o_mu);
+    for (int d = 0; d < DIM; ++d) a.u[d] = c->arr<T>(L.o_u[d]);
+    a.epsp = c->arr<T>(L.o_epsp);
+    a.epsP = c->arr<T>(L.o_epsP);
+    a.K = c->arr<T>(L.o_K);
+    a.G = c->arr<T>(L.o_G);
+    return a;
+  }
+
+  static ElastArgs<T> elast_args(pf_ctx* c) {
+    const Layout& L = c->L;
+    ElastArgs<T> a{};
+    a.g = L.g;
+    a.p = make_kp<T>(&c->cfg, &c->prm);
+    a.K = c->arr<T>(L.o_K);
+    a.G = c->arr<T>(L.o_G);
+    a.phi_f = c->arr<T>(L.o_fld[c->cur][0]);
+    a.epsp = c->arr<T>(L.o_epsp);
+    a.scal = c->scal();
+    a.tol2 = c->cfg.cg_rtol * c->cfg.cg_rtol;
+    a.kz = L.kz;
+    return a;
+  }
+
+  static pf_status ledger_reset(pf_ctx* c) {
+    const Layout& L = c->L;
+    CellArgs<T> a = cell_args(c);
+    a.part = c->arr<double>(L.o_part_c);
+    timed(c, PF_K_OTHER, [&] { hipLaunchKernelGGL((k_totals<T, DIM>), L.gcell, dim3(NT), 0, c->stream, a); });
+    double vol = std::pow(c->cfg.h, DIM);
+    hipLaunchKernelGGL(k_ledger, dim3(1), dim3(NT), 0, c->stream, (const double*)a.part, L.nb_cell, c->scal(), vol, 0.0, 0);
+    LAUNCHCHK(c);
+    c->ledger_valid = true;
+    return PF_OK;
+  }
+
+  // Solve A u = b for the current phase fields and plastic strain.
+  static pf_status solve(pf_ctx* c, int warm) {
+    const Layout& L = c->L;
+    hipStream_t st = c->stream;
+    if (c->timing) {   // keep every launch of this solve in the pending list until it is retagged below
+      HIPCHK(c, hipStreamSynchronize(st));
+      timing_flush(c);
+    }
+    if (warm == PF_WARM_ZERO)
+      for (int d = 0; d < DIM; ++d) HIPCHK(c, hipMemsetAsync(c->ws + L.o_u[d], 0, (size_t)L.g.n * sizeof(T), st));
+    c->warm_used = warm;
+    CellArgs<T> ca = cell_args(c);
+    timed(c, PF_K_OTHER, [&] { hipLaunchKernelGGL((k_moduli<T, DIM>), L.gcell, dim3(NT), 0, st, ca); });
+
+    ElastArgs<T> e = elast_args(c);
+    double* part_u = c->arr<double>(L.o_part_u);
+    double* part_a = c->arr<double>(L.o_part_a);
+    double* part_b = c->arr<double>(L.o_part_b);
+    // ||b||^2
+    e.part = part_b;
+    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_BNORM>), L.gel, dim3(NT), 0, st, e); });
+    // r = b - A u, D^-1, z, and the partials of r.z and r.r
+    ElastArgs<T> r = e;
+    for (int d = 0; d < DIM; ++d) {
+      r.u[d] = c->arr<T>(L.o_u[d]);
+      r.o1[d] = c->arr<T>(L.o_r[d]);
+      r.o2[d] = c->arr<T>(L.o_z[d]);
+      r.dinv[d] = c->arr<T>(L.o_di[d]);
+    }
+    r.part_in = part_b;
+    r.n_in = L.nb_el;
+    r.part = part_u;
+    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_RESID>), L.gel, dim3(NT), 0, st, r); });
+    LAUNCHCHK(c);
+
+    ElastArgs<T> ap = elast_args(c);
+    UpdArgs<T> up{};
+    up.n = L.g.n;
+    up.scal = c->scal();
+    up.part = part_u;
+    up.part_in = part_a;
+    up.n_in = L.nb_el;
+    for (int d = 0; d < DIM; ++d) {
+      ap.z[d] = c->arr<T>(L.o_z[d]);
+      ap.o2[d] = c->arr<T>(L.o_q[d]);
+      up.u[d] = c->arr<T>(L.o_u[d]);
+      up.r[d] = c->arr<T>(L.o_r[d]);
+      up.q[d] = c->arr<T>(L.o_q[d]);
+      up.dinv[d] = c->arr<T>(L.o_di[d]);
+      up.z[d] = c->arr<T>(L.o_z[d]);
+    }
+    ap.part = part_a;
+    ap.part_in = part_u;
+
+    const int maxit = c->cfg.cg_max_iter;
+    int launched = 0;
+    bool conv = false;
+    int chunk = std::max(2, c->last_iters + 2);
+    while (true) {
+      int n = std::min(chunk, maxit - launched);
+      for (int q = 0; q < n; ++q) {
+        const int par = launched & 1;
+        const size_t* pold = par ? L.o_pb : L.o_pa;
+        const size_t* pnew = par ? L.o_pa : L.o_pb;
+        for (int d = 0; d < DIM; ++d) {
+          ap.u[d] = c->arr<T>(pold[d]);
+          ap.o1[d] = c->arr<T>(pnew[d]);
+          up.p[d] = c->arr<T>(pnew[d]);
+        }
+        ap.parity = par;
+        ap.n_in = launched == 0 ? L.nb_el : L.nb_upd;
+        up.parity = par;
+        timed(c, PF_K_APPLY, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_APPLY>), L.gel, dim3(NT), 0, st, ap); }, launched);
+        timed(c, PF_K_UPDATE, [&] { hipLaunchKernelGGL((k_cg_update<T, DIM>), dim3(L.nb_upd), dim3(NT), 0, st, up); }, launched);
+        ++launched;
+      }
+      timed(c, PF_K_OTHER, [&] {
+        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(NT), 0, st, (const double*)part_u,
+                           launched == 0 ? L.nb_el : L.nb_upd, c->scal(), c->cfg.cg_rtol * c->cfg.cg_rtol);
+      });
+      LAUNCHCHK(c);
+      HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal(), S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipStreamSynchronize(st));
+      if (c->host_scal[S_CONV] != 0.0) { conv = true; break; }
+      if (launched >= maxit) break;
+      chunk = std::max(4, std::min(64, launched / 4));
+    }
+    c->last_iters = (int)c->host_scal[S_ITERS];
+    c->iters_total += c->last_iters;
+    // launches queued past convergence exit at entry: account them as small kernels
+    for (auto& pr : c->pending)
+      if (pr.launch >= c->last_iters && (pr.kind == PF_K_APPLY || pr.kind == PF_K_UPDATE)) pr.kind = PF_K_OTHER;
+    // true residual ||b - A u||
+    ElastArgs<T> t = e;
+    for (int d = 0; d < DIM; ++d) t.u[d] = c->arr<T>(L.o_u[d]);
+    t.part = part_b;
+    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_TRUE>), L.gel, dim3(NT), 0, st, t); });
+    timed(c, PF_K_OTHER, [&] {
+      hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part_b, L.nb_el, c->scal(), (int)S_TRUE);
+    });
+    LAUNCHCHK(c);
+    if (!conv)
+      return fail(c, PF_ERR_CG_NOT_CONVERGED, "CG did not reach rtol %.3g in %d iterations", c->cfg.cg_rtol, maxit);
+    return PF_OK;
+  }
+
+  static pf_status step_once(pf_ctx* c) {
+    const Layout& L = c->L;
+    if (!c->ledger_valid) {
+      pf_status s = ledger_reset(c);
+      if (s != PF_OK) return s;
+    }
+    if (c->cfg.mechanics) {
+      pf_status s = solve(c, c->cfg.warm);
+      if (s != PF_OK) return s;
+    }
+    CellArgs<T> a = cell_args(c);
+    a.part = c->arr<double>(L.o_part_c);
+    timed(c, PF_K_MU, [&] { hipLaunchKernelGGL((k_mu<T, DIM>), L.gcell, dim3(NT), 0, c->stream, a); });
+    timed(c, PF_K_STEP, [&] { hipLaunchKernelGGL((k_step<T, DIM>), L.gcell, dim3(NT), 0, c->stream, a); });
+    double vol = std::pow(c->cfg.h, DIM), area = std::pow(c->cfg.h, DIM - 1);
+    timed(c, PF_K_OTHER, [&] {
+      hipLaunchKernelGGL(k_ledger, dim3(1), dim3(NT), 0, c->stream, (const double*)a.part, L.nb_cell, c->scal(), vol,
+                         area * c->cfg.dt, 1);
+    });
+    LAUNCHCHK(c);
+    c->cur ^= 1;
+    c->steps += 1;
+    return PF_OK;
+  }
+};
+
+template <typename F>
+static pf_status dispatch(pf_ctx* c, F&& f) {
+  if (c->cfg.precision == PF_FP64) {
+    if (c->cfg.dim == 2) return f(Impl<double, 2>());
+    return f(Impl<double, 3>());
+  }
+  if (c->cfg.dim == 2) return f(Impl<float, 2>());
+  return f(Impl<float, 3>());
+}
+
+static void fill_stats(pf_ctx* c, pf_step_stats* s) {
+  const double* h = c->host_scal;
+  memset(s, 0, sizeof(*s));
+  s->cg_iters = (int)h[S_ITERS];
+  s->warm_used = c->warm_used;
+  s->cg_rel_resid = h[S_BB] > 0.0 ? std::sqrt(h[S_TRUE] / h[S_BB]) : 0.0;
+  s->O_tot = h[S_OTOT];
+  s->O_out = h[S_OOUT];
+  s->O_drift = h[S_O0] != 0.0 ? (h[S_OTOT] + h[S_OOUT] - h[S_O0]) / h[S_O0] : 0.0;
+  s->H_tot = h[S_HTOT];
+  s->H_out = h[S_HOUT];
+  s->H_drift = h[S_H0] != 0.0 ? (h[S_HTOT] + h[S_HOUT] - h[S_H0]) / h[S_H0] : 0.0;
+  s->red_degree = h[S_XO0] != 0.0 ? 1.0 - h[S_XOSUM] / h[S_XO0] : 0.0;
+  s->max_vm = h[S_MAXVM];
+  s->max_epsP = h[S_MAXEP];
+  s->step = c->steps;
+  s->nonfinite = (int)h[S_NONFIN];
+  s->cg_iters_total = c->iters_total;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t pf_workspace_bytes(const pf_config* cfg) {
+  char msg[256];
+  if (!valid_cfg(cfg, msg, sizeof msg)) return 0;
+  return make_layout(cfg).total;
+}
+
+pf_status pf_init(const pf_config* cfg, const pf_params* params, void* workspace, size_t workspace_bytes,
+                  void* hip_stream, pf_ctx** out) {
+  if (!out) return fail(nullptr, PF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  char msg[256];
+  if (!valid_cfg(cfg, msg, sizeof msg)) return fail(nullptr, PF_ERR_INVALID_ARG, "%s", msg);
+  if (!params) return fail(nullptr, PF_ERR_INVALID_ARG, "params is NULL");
+  if (params->m_form != 0 && params->m_form != 1) return fail(nullptr, PF_ERR_INVALID_ARG, "m_form must be 0 or 1");
+  if (!workspace) return fail(nullptr, PF_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(nullptr, PF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Layout L = make_layout(cfg);
+  if (workspace_bytes < L.total)
+    return fail(nullptr, PF_ERR_OOM, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
+  pf_ctx* c = new (std::nothrow) pf_ctx();
+  if (!c) return fail(nullptr, PF_ERR_OOM, "host allocation failed");
+  c->cfg = *cfg;
+  c->prm = *params;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->L = L;
+  c->ws = reinterpret_cast<char*>(workspace);
+  c->err[0] = 0;
+  c->bad = false;
+  c->ledger_valid = false;
+  c->cur = 0;
+  c->steps = 0;
+  c->last_iters = 0;
+  c->warm_used = cfg->warm;
+  c->timing = false;
+  c->ev_next = 0;
+  c->iters_total = 0;
+  for (int k = 0; k < PF_K_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_scal), S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(nullptr, PF_ERR_HIP, "hipHostMalloc of the stats block failed");
+  }
+  memset(c->host_scal, 0, S_COUNT * sizeof(double));
+  hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    (void)hipHostFree(c->host_scal);
+    delete c;
+    return fail(nullptr, PF_ERR_HIP, "clearing the workspace failed: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return PF_OK;
+}
+
+pf_status pf_step(pf_ctx* c, int nsteps, pf_step_stats* last) {
+  if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->bad) return fail(c, PF_ERR_BAD_STATE, "context failed earlier; set the fields to restore it");
+  if (nsteps < 0) return fail(c, PF_ERR_INVALID_ARG, "nsteps < 0");
+  for (int s = 0; s < nsteps; ++s) {
+    pf_status st = dispatch(c, [&](auto impl) { return decltype(impl)::step_once(c); });
+    if (st != PF_OK) { c->bad = true; return st; }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal(), S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  pf_step_stats s;
+  fill_stats(c, &s);
+  if (last) *last = s;
+  if (nsteps > 0 && s.nonfinite > 0) {
+    c->bad = true;
+    return fail(c, PF_ERR_NONFINITE, "%d cells hold non-finite values after step %lld", s.nonfinite, c->steps);
+  }
+  if (nsteps > 0 && c->cfg.ledger_tol > 0.0 && std::fabs(s.O_drift) > c->cfg.ledger_tol) {
+    c->bad = true;
+    return fail(c, PF_ERR_LEDGER, "oxygen ledger drift %.3e exceeds %.3e", s.O_drift, c->cfg.ledger_tol);
+  }
+  return PF_OK;
+}
+
+pf_status pf_mech_solve(pf_ctx* c, int warm, pf_step_stats* stats) {
+  if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->bad) return fail(c, PF_ERR_BAD_STATE, "context failed earlier; set the fields to restore it");
+  if (warm != PF_WARM_ZERO && warm != PF_WARM_PREV) return fail(c, PF_ERR_INVALID_ARG, "unknown warm start %d", warm);
+  if (!c->cfg.mechanics) return fail(c, PF_ERR_INVALID_ARG, "mechanics is off in this context");
+  pf_status st = dispatch(c, [&](auto impl) { return decltype(impl)::solve(c, warm); });
+  HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal(), S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (stats) fill_stats(c, stats);
+  return st;
+}
+
+pf_status pf_ledger_reset(pf_ctx* c) {
+  if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  pf_status st = dispatch(c, [&](auto impl) { return decltype(impl)::ledger_reset(c); });
+  if (st != PF_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PF_OK;
+}
+
+pf_status pf_fields(pf_ctx* c, int field_id, int dir, void* ptr, size_t nbytes, int ptr_is_device) {
+  if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  if (!ptr) return fail(c, PF_ERR_INVALID_ARG, "ptr is NULL");
+  if (dir != 0 && dir != 1) return fail(c, PF_ERR_INVALID_ARG, "dir must be 0 (get) or 1 (set)");
+  const Layout& L = c->L;
+  const Grid& g = L.g;
+  const int dim = c->cfg.dim;
+  int cx = g.nx, cy = g.ny, cz = g.nz, zaxis = -1, ncomp = 1;
+  size_t base = 0;
+  switch (field_id) {
+    case PF_FIELD_PHI_F: case PF_FIELD_PHI_W: case PF_FIELD_XO: case PF_FIELD_XH: case PF_FIELD_XW:
+      base = L.o_fld[c->cur][field_id]; break;
+    case PF_FIELD_UX: base = L.o_u[0]; cx += 1; zaxis = 0; break;
+    case PF_FIELD_UY: base = L.o_u[1]; cy += 1; zaxis = 1; break;
+    case PF_FIELD_UZ:
+      if (dim != 3) return fail(c, PF_ERR_INVALID_ARG, "u_z exists only in 3D");
+      base = L.o_u[2]; cz += 1; zaxis = 2; break;
+    case PF_FIELD_EPSP: base = L.o_epsp; ncomp = L.nc; break;
+    case PF_FIELD_EPSP_ACC: base = L.o_epsP; break;
+    default: return fail(c, PF_ERR_INVALID_ARG, "unknown field id %d", field_id);
+  }
+  size_t per = (size_t)cx * cy * cz;
+  if (nbytes != per * ncomp * sizeof(double))
+    return fail(c, PF_ERR_INVALID_ARG, "field %d needs %zu bytes, got %zu", field_id, per * ncomp * sizeof(double), nbytes);
+  double* stage = c->arr<double>(L.o_stage);
+  const int nthr = 256;
+  const int nblk = (int)((per + nthr - 1) / nthr);
+  for (int comp = 0; comp < ncomp; ++comp) {
+    size_t dev_off = base + (size_t)comp * g.n * L.es;   // plastic strain components are g.n elements apart
+    char* user = reinterpret_cast<char*>(ptr) + comp * per * sizeof(double);
+    double* buf = ptr_is_device ? reinterpret_cast<double*>(user) : stage;
+    if (dir == 1) {
+      if (!ptr_is_device) HIPCHK(c, hipMemcpyAsync(stage, user, per * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      if (L.es == 8)
+        hipLaunchKernelGGL(k_unpack<double>, dim3(nblk), dim3(nthr), 0, c->stream, (const double*)buf, c->arr<double>(dev_off), g, cx, cy, cz, zaxis);
+      else
+        hipLaunchKernelGGL(k_unpack<float>, dim3(nblk), dim3(nthr), 0, c->stream, (const double*)buf, c->arr<float>(dev_off), g, cx, cy, cz, zaxis);
+      LAUNCHCHK(c);
+    } else {
+      if (L.es == 8)
+        hipLaunchKernelGGL(k_pack<double>, dim3(nblk), dim3(nthr), 0, c->stream, (const double*)c->arr<double>(dev_off), buf, g, cx, cy, cz);
+      else
+        hipLaunchKernelGGL(k_pack<float>, dim3(nblk), dim3(nthr), 0, c->stream, (const float*)c->arr<float>(dev_off), buf, g, cx, cy, cz);
+      LAUNCHCHK(c);
+      if (!ptr_is_device) HIPCHK(c, hipMemcpyAsync(user, stage, per * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+  }
+  if (dir == 1) {
+    c->bad = false;
+    if (field_id <= PF_FIELD_XW) c->ledger_valid = false;
+  }
+  if (dir == 0 || !ptr_is_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PF_OK;
+}
+
+pf_status pf_timing(pf_ctx* c, int enable) {
+  if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  timing_flush(c);
+  if (enable) {
+    if (c->ev_pool.empty()) {
+      c->ev_pool.resize(32768);
+      for (auto& e : c->ev_pool) HIPCHK(c, hipEventCreate(&e));
+    }
+    for (int k = 0; k < PF_K_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
+  }
+  c->timing = enable != 0;
+  return PF_OK;
+}
+
+pf_status pf_timing_get(pf_ctx* c, int kind, double* total_ms, long long* launches) {
+  if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  if (kind < 0 || kind >= PF_K_COUNT) return fail(c, PF_ERR_INVALID_ARG, "unknown kernel kind %d", kind);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  timing_flush(c);
+  if (total_ms) *total_ms = c->t_ms[kind];
+  if (launches) *launches = c->t_n[kind];
+  return PF_OK;
+}
+
+const char* pf_last_error(const pf_ctx* c) { return c ? c->err : g_err; }
+
+void pf_destroy(pf_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->host_scal) (void)hipHostFree(c->host_scal);
+  delete c;
+}
+
+}  // extern "C"

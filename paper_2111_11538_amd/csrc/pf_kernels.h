@@ -1,0 +1,813 @@
+// HIP kernels (gfx950) of the phase-field step.
+//
+//  k_elast      staggered-grid small-strain elasticity (quasi-static momentum
+//               balance, Eq. 29 line 4): q = A p with the CG direction update
+//               fused in, the initial residual with the eigenstrain, norms.
+//               LDS-staged 64x4 tiles marching along z (2.5D blocking).
+//  k_cg_update  x += alpha p, r -= alpha q, z = D^-1 r with FP64 partial dots.
+//  k_mu, k_step fused chemistry / phase-field / plasticity update.
+//  small kernels for moduli, ledger, checks and field packing.
+//
+// Every dot product and ledger sum is FP64 and deterministic: each block
+// writes one partial, and consumers reduce the partials in a fixed order.
+#pragma once
+
+#include "pf_device.h"
+
+namespace pfk {
+
+enum ElastMode { M_APPLY = 0, M_RESID = 1, M_BNORM = 2, M_TRUE = 3 };
+
+template <typename T>
+struct ElastArgs {
+  Grid g;
+  KP<T> p;
+  const T* K;
+  const T* G;
+  const T* phi_f;          // eigenstrain source (modes other than APPLY)
+  const T* epsp;           // plastic strain, component-major with stride g.n
+  T* u[3];                 // APPLY: previous direction p; RESID/TRUE: displacement
+  const T* z[3];           // APPLY: preconditioned residual
+  T* o1[3];                // APPLY: new direction; RESID: residual r
+  T* o2[3];                // APPLY: q = A p; RESID: z = D^-1 r
+  T* dinv[3];              // RESID: inverse diagonal of A
+  double* part;            // partial sums out, [quantity][block]
+  const double* part_in;   // partial sums to reduce at entry
+  int n_in;
+  double* scal;
+  double tol2;             // cg_rtol^2
+  int parity;              // launch position parity inside the CG loop
+  int kz;                  // z planes per block
+};
+
+// Local tile coordinates: lx = i - i0 + 1 in [0, TX+1], ly = j - j0 + 1 in [0, TY+1].
+constexpr int LW = TX + 2, LH = TY + 2, LS = LW * LH;
+__device__ __forceinline__ int L(int ly, int lx) { return ly * LW + lx; }
+
+template <typename T, int DIM, int MODE>
+__global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
+  constexpr bool EIG = (MODE != M_APPLY);
+  constexpr int ES = EIG ? LS : 1;
+  constexpr int DS = (MODE == M_RESID) ? LS : 1;
+  constexpr int D3 = (DIM == 3) ? LS : 1;
+  __shared__ T sP[2][DIM][LS];
+  __shared__ T sK[LS];
+  __shared__ T sG[2][LS];
+  __shared__ T sSxx[LS], sSyy[LS], sSzz[LS], sSxy[LS];
+  __shared__ T sSxz[2][D3], sSyz[2][D3];
+  __shared__ T sEt[ES], sEn[3][ES], sExy[ES];
+  __shared__ T sExz[2][(EIG && DIM == 3) ? LS : 1], sEyz[2][(EIG && DIM == 3) ? LS : 1];
+  __shared__ T sGxz[2][(MODE == M_RESID && DIM == 3) ? LS : 1], sGyz[2][(MODE == M_RESID && DIM == 3) ? LS : 1];
+  __shared__ double red[NT / 64];
+  (void)DS;
+
+  const Grid& g = a.g;
+  const KP<T>& p = a.p;
+  const int nbx = gridDim.x, nby = gridDim.y;
+  const int bid = (blockIdx.z * nby + blockIdx.y) * nbx + blockIdx.x;
+  const int nblk = nbx * nby * gridDim.z;
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int i = i0 + tx, j = j0 + ty;
+  const int lx = tx + 1, ly = ty + 1;
+  const bool own = (i < g.nx) && (j < g.ny);
+  const T ih = p.ih;
+
+  // ---- entry: scalars of the CG recurrence --------------------------------
+  double beta = 0.0;
+  bool first = false, zero_u = false;
+  if (MODE == M_APPLY) {
+    if (a.scal[S_CONV] != 0.0) return;
+    double rz = sum_partials(a.part_in, a.n_in, red);
+    double rr = sum_partials(a.part_in + a.n_in, a.n_in, red);
+    if (rr <= a.tol2 * a.scal[S_BB]) {
+      if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = 1.0;
+      return;
+    }
+    first = a.scal[S_FIRST] != 0.0;
+    beta = first ? 0.0 : rz / a.scal[S_RZ + (a.parity ^ 1)];
+    if (bid == 0 && threadIdx.x == 0) {
+      a.scal[S_RZ + a.parity] = rz;
+      a.scal[S_RR] = rr;
+    }
+  } else if (MODE == M_RESID) {
+    double bb = sum_partials(a.part_in, a.n_in, red);
+    zero_u = (bb == 0.0);
+    if (bid == 0 && threadIdx.x == 0) {
+      a.scal[S_BB] = bb;
+      a.scal[S_FIRST] = 1.0;
+      a.scal[S_CONV] = 0.0;
+      a.scal[S_ITERS] = 0.0;
+    }
+  }
+  const T tbeta = (T)beta;
+
+  // ---- plane loaders ------------------------------------------------------
+  auto in_dom = [&](int ii, int jj, int kk) {
+    return ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
+  };
+  auto load_vec = [&](int kk, int slot) {
+    for (int t = threadIdx.x; t < LS; t += NT) {
+      int yy = t / LW, xx = t - yy * LW;
+      int ii = i0 + xx - 1, jj = j0 + yy - 1;
+      bool in = in_dom(ii, jj, kk);
+      int e = in ? gidx(g, ii, jj, kk) : 0;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        T v = T(0);
+        if (in) {
+          if (MODE == M_APPLY) v = first ? a.z[c][e] : a.z[c][e] + tbeta * a.u[c][e];
+          else if (MODE == M_BNORM) v = T(0);
+          else v = zero_u ? T(0) : a.u[c][e];
+        }
+        sP[slot][c][t] = v;
+      }
+    }
+  };
+  auto load_cell = [&](const T* src, T* dst, int kk) {
+    for (int t = threadIdx.x; t < LS; t += NT) {
+      int yy = t / LW, xx = t - yy * LW;
+      int ii = i0 + xx - 1, jj = j0 + yy - 1;
+      dst[t] = in_dom(ii, jj, kk) ? src[gidx(g, ii, jj, kk)] : T(0);
+    }
+  };
+  auto load_eig = [&](int kk) {   // eigenstrain eT and plastic strain of plane kk
+    for (int t = threadIdx.x; t < LS; t += NT) {
+      int yy = t / LW, xx = t - yy * LW;
+      int ii = i0 + xx - 1, jj = j0 + yy - 1;
+      bool in = in_dom(ii, jj, kk);
+      int e = in ? gidx(g, ii, jj, kk) : 0;
+      sEt[t] = in ? eigen_strain(p, a.phi_f[e]) : T(0);
+      sEn[0][t] = in ? a.epsp[e] : T(0);
+      sEn[1][t] = in ? a.epsp[g.n + e] : T(0);
+      sEn[2][t] = in ? a.epsp[2 * g.n + e] : T(0);
+      sExy[t] = in ? a.epsp[3 * g.n + e] : T(0);
+    }
+  };
+  auto load_eig_shear3 = [&](int kk, int slot) {   // xz, yz plastic strain of plane kk
+    if constexpr (EIG && DIM == 3) {
+      for (int t = threadIdx.x; t < LS; t += NT) {
+        int yy = t / LW, xx = t - yy * LW;
+        int ii = i0 + xx - 1, jj = j0 + yy - 1;
+        bool in = in_dom(ii, jj, kk);
+        int e = in ? gidx(g, ii, jj, kk) : 0;
+        sExz[slot][t] = in ? a.epsp[4 * g.n + e] : T(0);
+        sEyz[slot][t] = in ? a.epsp[5 * g.n + e] : T(0);
+      }
+    }
+  };
+
+  // ---- stress evaluations ---------------------------------------------------
+  // cell normal stresses of plane k on cells lx in [0, TX], ly in [0, TY]
+  auto cell_stress = [&](int sk, int sk1) {
+    for (int t = threadIdx.x; t < (TX + 1) * (TY + 1); t += NT) {
+      int yy = t / (TX + 1), xx = t - yy * (TX + 1);
+      int c = L(yy, xx);
+      T exx = (sP[sk][0][c + 1] - sP[sk][0][c]) * ih;
+      T eyy = (sP[sk][1][c + LW] - sP[sk][1][c]) * ih;
+      T ezz = T(0);
+      if constexpr (DIM == 3) ezz = (sP[sk1][2][c] - sP[sk][2][c]) * ih;
+      if constexpr (EIG) {
+        exx -= sEt[c] + sEn[0][c];
+        eyy -= sEt[c] + sEn[1][c];
+        ezz -= sEt[c] + sEn[2][c];
+      }
+      T tr = exx + eyy + ezz;
+      T Kc = sK[c], G2 = T(2) * sG[sk][c];
+      T lam = Kc * tr - G2 * tr * T(1.0 / 3.0);
+      sSxx[c] = lam + G2 * exx;
+      sSyy[c] = lam + G2 * eyy;
+      sSzz[c] = lam + G2 * ezz;
+    }
+  };
+  // xy edge stresses of plane k on edges lx in [1, TX+1], ly in [1, TY+1]
+  auto edge_xy = [&](int sk, int kk) {
+    for (int t = threadIdx.x; t < (TX + 1) * (TY + 1); t += NT) {
+      int yy = t / (TX + 1) + 1, xx = t - (yy - 1) * (TX + 1) + 1;
+      int c = L(yy, xx);
+      int ii = i0 + xx - 1, jj = j0 + yy - 1;
+      T s = T(0);
+      if (ii > 0 && ii < g.nx && jj > 0 && jj < g.ny) {
+        T ge = T(0.25) * (sG[sk][c - LW - 1] + sG[sk][c - LW] + sG[sk][c - 1] + sG[sk][c]);
+        T e = T(0.5) * ((sP[sk][0][c] - sP[sk][0][c - LW]) + (sP[sk][1][c] - sP[sk][1][c - 1])) * ih;
+        if constexpr (EIG) e -= T(0.25) * (sExy[c - LW - 1] + sExy[c - LW] + sExy[c - 1] + sExy[c]);
+        s = T(2) * ge * e;
+      }
+      sSxy[c] = s;
+    }
+    (void)kk;
+  };
+  // xz / yz edge stresses at level kk (between planes kk-1 in slot s0 and kk in slot s1)
+  auto edge_z = [&](int kk, int s0, int s1, int out) {
+    if constexpr (DIM == 3) {
+      bool zin = kk > 0 && kk < g.nz;
+      for (int t = threadIdx.x; t < (TX + 1) * (TY + 1); t += NT) {
+        int yy = t / (TX + 1) + 1, xx = t - (yy - 1) * (TX + 1) + 1;
+        int c = L(yy, xx);
+        int ii = i0 + xx - 1, jj = j0 + yy - 1;
+        T sxz = T(0), syz = T(0), gxz = T(0), gyz = T(0);
+        if (zin && ii > 0 && ii < g.nx && jj < g.ny && yy <= TY) {
+          gxz = T(0.25) * (sG[s0][c - 1] + sG[s0][c] + sG[s1][c - 1] + sG[s1][c]);
+          T e = T(0.5) * ((sP[s1][0][c] - sP[s0][0][c]) + (sP[s1][2][c] - sP[s1][2][c - 1])) * ih;
+          if constexpr (EIG) e -= T(0.25) * (sExz[s0][c - 1] + sExz[s0][c] + sExz[s1][c - 1] + sExz[s1][c]);
+          sxz = T(2) * gxz * e;
+        }
+        if (zin && jj > 0 && jj < g.ny && ii < g.nx && xx <= TX) {
+          gyz = T(0.25) * (sG[s0][c - LW] + sG[s0][c] + sG[s1][c - LW] + sG[s1][c]);
+          T e = T(0.5) * ((sP[s1][1][c] - sP[s0][1][c]) + (sP[s1][2][c] - sP[s1][2][c - LW])) * ih;
+          if constexpr (EIG) e -= T(0.25) * (sEyz[s0][c - LW] + sEyz[s0][c] + sEyz[s1][c - LW] + sEyz[s1][c]);
+          syz = T(2) * gyz * e;
+        }
+        sSxz[out][c] = sxz;
+        sSyz[out][c] = syz;
+        if constexpr (MODE == M_RESID) {
+          sGxz[out][c] = gxz;
+          sGyz[out][c] = gyz;
+        }
+      }
+    }
+    (void)kk; (void)s0; (void)s1; (void)out;
+  };
+
+  // ---- z march --------------------------------------------------------------
+  const int k0 = (DIM == 3) ? blockIdx.z * a.kz : 0;
+  const int k1 = (DIM == 3) ? min(k0 + a.kz, g.nz) : 1;
+  double acc0 = 0.0, acc1 = 0.0;
+  T szz_prev = T(0), m_prev = T(0);
+
+  if constexpr (DIM == 3) {
+    // prologue: planes k0-1 and k0, sigma_zz of the own cell below, edges at level k0
+    int sa = (k0 - 1) & 1, sb = k0 & 1;
+    load_vec(k0, sb);
+    load_cell(a.G, sG[sb], k0);
+    load_eig_shear3(k0, sb);
+    if (k0 > 0) {
+      load_vec(k0 - 1, sa);
+      load_cell(a.G, sG[sa], k0 - 1);
+      load_cell(a.K, sK, k0 - 1);
+      if constexpr (EIG) load_eig(k0 - 1);
+      load_eig_shear3(k0 - 1, sa);
+    }
+    __syncthreads();
+    if (k0 > 0) {
+      int c = L(ly, lx);
+      T exx = (sP[sa][0][c + 1] - sP[sa][0][c]) * ih;
+      T eyy = (sP[sa][1][c + LW] - sP[sa][1][c]) * ih;
+      T ezz = (sP[sb][2][c] - sP[sa][2][c]) * ih;
+      if constexpr (EIG) {
+        exx -= sEt[c] + sEn[0][c];
+        eyy -= sEt[c] + sEn[1][c];
+        ezz -= sEt[c] + sEn[2][c];
+      }
+      T tr = exx + eyy + ezz;
+      T G2 = T(2) * sG[sa][c];
+      szz_prev = sK[c] * tr - G2 * tr * T(1.0 / 3.0) + G2 * ezz;
+      m_prev = sK[c] + T(2.0 / 3.0) * G2;
+    }
+    edge_z(k0, sa, sb, sb);
+  }
+
+  for (int k = k0; k < k1; ++k) {
+    const int sk = k & 1, sk1 = (k + 1) & 1;
+    __syncthreads();
+    if constexpr (DIM == 3) {
+      load_vec(k + 1, sk1);
+      load_cell(a.G, sG[sk1], k + 1);
+      load_eig_shear3(k + 1, sk1);
+    } else {
+      load_vec(k, sk);
+      load_cell(a.G, sG[sk], k);
+    }
+    load_cell(a.K, sK, k);
+    if constexpr (EIG) load_eig(k);
+    __syncthreads();
+    cell_stress(sk, sk1);
+    edge_xy(sk, k);
+    if constexpr (DIM == 3) edge_z(k + 1, sk, sk1, sk1);
+    __syncthreads();
+    if (own) {
+      const int c = L(ly, lx);
+      const int e = gidx(g, i, j, k);
+      T q[3] = {T(0), T(0), T(0)};
+      if (i > 0) {
+        q[0] = sSxx[c - 1] - sSxx[c] + sSxy[c] - sSxy[c + LW];
+        if constexpr (DIM == 3) q[0] += sSxz[sk][c] - sSxz[sk1][c];
+      }
+      if (j > 0) {
+        q[1] = sSyy[c - LW] - sSyy[c] + sSxy[c] - sSxy[c + 1];
+        if constexpr (DIM == 3) q[1] += sSyz[sk][c] - sSyz[sk1][c];
+      }
+      if constexpr (DIM == 3) {
+        if (k > 0) q[2] = szz_prev - sSzz[c] + sSxz[sk][c] - sSxz[sk][c + 1] + sSyz[sk][c] - sSyz[sk][c + LW];
+      }
+      if constexpr (MODE == M_APPLY) {
+#pragma unroll
+        for (int cc = 0; cc < DIM; ++cc) {
+          T pn = sP[sk][cc][c];
+          a.o1[cc][e] = pn;
+          a.o2[cc][e] = q[cc];
+          acc0 += (double)pn * (double)q[cc];
+        }
+      } else if constexpr (MODE == M_RESID) {
+        // inverse diagonal: (M_left + M_right + adjacent interior edge G_e) / h
+        T Mc = sK[c] + T(4.0 / 3.0) * sG[sk][c];
+        T d[3] = {T(0), T(0), T(0)};
+        auto gxy = [&](int cc2, int ii, int jj) -> T {
+          if (ii > 0 && ii < g.nx && jj > 0 && jj < g.ny)
+            return T(0.25) * (sG[sk][cc2 - LW - 1] + sG[sk][cc2 - LW] + sG[sk][cc2 - 1] + sG[sk][cc2]);
+          return T(0);
+        };
+        if (i > 0) {
+          d[0] = sK[c - 1] + T(4.0 / 3.0) * sG[sk][c - 1] + Mc + gxy(c, i, j) + gxy(c + LW, i, j + 1);
+          if constexpr (DIM == 3) d[0] += sGxz[sk][c] + sGxz[sk1][c];
+        }
+        if (j > 0) {
+          d[1] = sK[c - LW] + T(4.0 / 3.0) * sG[sk][c - LW] + Mc + gxy(c, i, j) + gxy(c + 1, i + 1, j);
+          if constexpr (DIM == 3) d[1] += sGyz[sk][c] + sGyz[sk1][c];
+        }
+        if constexpr (DIM == 3) {
+          if (k > 0) d[2] = m_prev + Mc + sGxz[sk][c] + sGxz[sk][c + 1] + sGyz[sk][c] + sGyz[sk][c + LW];
+          m_prev = Mc;
+        }
+#pragma unroll
+        for (int cc = 0; cc < DIM; ++cc) {
+          T di = d[cc] > T(0) ? T(1) / (d[cc] * ih) : T(0);
+          T r = -q[cc];
+          T zz = di * r;
+          a.o1[cc][e] = r;
+          a.o2[cc][e] = zz;
+          a.dinv[cc][e] = di;
+          if (zero_u) a.u[cc][e] = T(0);
+          acc0 += (double)r * (double)zz;
+          acc1 += (double)r * (double)r;
+        }
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < DIM; ++cc) acc0 += (double)q[cc] * (double)q[cc];
+      }
+      if constexpr (DIM == 3) szz_prev = sSzz[c];
+    }
+  }
+  double s0 = block_sum(acc0, red);
+  if (threadIdx.x == 0) a.part[bid] = s0;
+  if (MODE == M_RESID) {
+    double s1 = block_sum(acc1, red);
+    if (threadIdx.x == 0) a.part[nblk + bid] = s1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CG update: u += alpha p, r -= alpha q, z = D^-1 r; partials of r.z and r.r
+// ---------------------------------------------------------------------------
+template <typename T>
+struct UpdArgs {
+  int n;                   // elements per component array (multiple of 16)
+  T* u[3];
+  const T* p[3];
+  T* r[3];
+  const T* q[3];
+  const T* dinv[3];
+  T* z[3];
+  double* part;            // [2][nblocks]
+  const double* part_in;   // APPLY partials (p.q)
+  int n_in;
+  double* scal;
+  int parity;
+};
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double2; };
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
+  __shared__ double red[NT / 64];
+  if (a.scal[S_CONV] != 0.0) return;
+  double pq = sum_partials(a.part_in, a.n_in, red);
+  double alpha = a.scal[S_RZ + a.parity] / pq;
+  const T al = (T)alpha;
+  using V = typename Vec4<T>::type;
+  constexpr int VN = sizeof(V) / sizeof(T);
+  const int nv = a.n / VN;
+  double rz = 0.0, rr = 0.0;
+  const int stride = gridDim.x * NT;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    V* uu = reinterpret_cast<V*>(a.u[c]);
+    const V* pp = reinterpret_cast<const V*>(a.p[c]);
+    V* rrp = reinterpret_cast<V*>(a.r[c]);
+    const V* qq = reinterpret_cast<const V*>(a.q[c]);
+    const V* dd = reinterpret_cast<const V*>(a.dinv[c]);
+    V* zz = reinterpret_cast<V*>(a.z[c]);
+    for (int v = blockIdx.x * NT + threadIdx.x; v < nv; v += stride) {
+      V uv = uu[v], pv = pp[v], rv = rrp[v], qv = qq[v], dv = dd[v], zv;
+      T* ue = reinterpret_cast<T*>(&uv);
+      const T* pe = reinterpret_cast<const T*>(&pv);
+      T* re = reinterpret_cast<T*>(&rv);
+      const T* qe = reinterpret_cast<const T*>(&qv);
+      const T* de = reinterpret_cast<const T*>(&dv);
+      T* ze = reinterpret_cast<T*>(&zv);
+#pragma unroll
+      for (int l = 0; l < VN; ++l) {
+        ue[l] += al * pe[l];
+        re[l] -= al * qe[l];
+        ze[l] = de[l] * re[l];
+        rz += (double)re[l] * (double)ze[l];
+        rr += (double)re[l] * (double)re[l];
+      }
+      uu[v] = uv;
+      rrp[v] = rv;
+      zz[v] = zv;
+    }
+  }
+  double s0 = block_sum(rz, red);
+  double s1 = block_sum(rr, red);
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = s0;
+    a.part[gridDim.x + blockIdx.x] = s1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal[S_FIRST] = 0.0;
+    a.scal[S_ITERS] += 1.0;
+  }
+}
+
+// After a chunk of CG launches: mark convergence from the latest residual.
+__global__ __launch_bounds__(NT) void k_cg_check(const double* part_in, int n_in, double* scal, double tol2) {
+  __shared__ double red[NT / 64];
+  if (scal[S_CONV] != 0.0) return;
+  double rr = sum_partials(part_in + n_in, n_in, red);
+  if (threadIdx.x == 0) {
+    scal[S_RR] = rr;
+    if (rr <= tol2 * scal[S_BB]) scal[S_CONV] = 1.0;
+  }
+}
+
+// Sum of partials into one scalar slot.
+__global__ __launch_bounds__(NT) void k_sum_to(const double* part, int n, double* scal, int slot) {
+  __shared__ double red[NT / 64];
+  double s = sum_partials(part, n, red);
+  if (threadIdx.x == 0) scal[slot] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Step kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+struct CellArgs {
+  Grid g;
+  KP<T> p;
+  const T *pf, *pw, *xO, *xH, *xW, *mu;
+  T *npf, *npw, *nxO, *nxH, *nxW;
+  const T* u[3];
+  T* epsp;
+  T* epsP;
+  T* K;
+  T* G;
+  T* mu_out;
+  double* part;            // [NQ][nblocks]
+};
+
+constexpr int NQ_STEP = 8;   // O total, H total, x_O sum, O outflux, H outflux, max vm, max epsP, nonfinite
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_moduli(CellArgs<T> a) {
+  const int i = blockIdx.x * TX + (threadIdx.x & (TX - 1));
+  const int j = blockIdx.y * TY + threadIdx.x / TX;
+  const int k = blockIdx.z;
+  if (i >= a.g.nx || j >= a.g.ny) return;
+  const int e = gidx(a.g, i, j, k);
+  T K, G;
+  moduli(a.p, a.pf[e], a.pw[e], K, G);
+  a.K[e] = K;
+  a.G[e] = G;
+}
+
+// mu_O = d psi_che / d x_O - kappa_O lap(x_O), mirror (no-flux) ghosts
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_mu(CellArgs<T> a) {
+  const Grid& g = a.g;
+  const int i = blockIdx.x * TX + (threadIdx.x & (TX - 1));
+  const int j = blockIdx.y * TY + threadIdx.x / TX;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int e = gidx(g, i, j, k);
+  const T xc = a.xO[e];
+  T lap = (a.xO[i + 1 < g.nx ? e + 1 : e] - xc) - (xc - a.xO[i > 0 ? e - 1 : e]);
+  lap += (a.xO[j + 1 < g.ny ? e + g.px : e] - xc) - (xc - a.xO[j > 0 ? e - g.px : e]);
+  if constexpr (DIM == 3) {
+    const int pl = g.px * g.ny;
+    lap += (a.xO[k + 1 < g.nz ? e + pl : e] - xc) - (xc - a.xO[k > 0 ? e - pl : e]);
+  }
+  T mu, MO, DH, DW;
+  transport(a.p, a.pf[e], a.pw[e], xc, mu, MO, DH, DW);
+  a.mu_out[e] = mu - a.p.kappaO * lap * a.p.ih2;
+}
+
+template <typename T>
+__device__ __forceinline__ T face_flux(T ca, T cb, T va, T vb, T ih) {
+  return T(-0.5) * (ca + cb) * (vb - va) * ih;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ T shear_xy(const Grid& g, const T* ux, const T* uy, int i, int j, int k, T ih) {
+  if (i <= 0 || i >= g.nx || j <= 0 || j >= g.ny) return T(0);
+  const int e = gidx(g, i, j, k);
+  return T(0.5) * ((ux[e] - ux[e - g.px]) + (uy[e] - uy[e - 1])) * ih;
+}
+template <typename T>
+__device__ __forceinline__ T shear_xz(const Grid& g, const T* ux, const T* uz, int i, int j, int k, T ih) {
+  if (i <= 0 || i >= g.nx || k <= 0 || k >= g.nz) return T(0);
+  const int e = gidx(g, i, j, k), pl = g.px * g.ny;
+  return T(0.5) * ((ux[e] - ux[e - pl]) + (uz[e] - uz[e - 1])) * ih;
+}
+template <typename T>
+__device__ __forceinline__ T shear_yz(const Grid& g, const T* uy, const T* uz, int i, int j, int k, T ih) {
+  if (j <= 0 || j >= g.ny || k <= 0 || k >= g.nz) return T(0);
+  const int e = gidx(g, i, j, k), pl = g.px * g.ny;
+  return T(0.5) * ((uy[e] - uy[e - pl]) + (uz[e] - uz[e - g.px])) * ih;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_step(CellArgs<T> a) {
+  __shared__ double red[NT / 64];
+  const Grid& g = a.g;
+  const KP<T>& p = a.p;
+  const int i = blockIdx.x * TX + (threadIdx.x & (TX - 1));
+  const int j = blockIdx.y * TY + threadIdx.x / TX;
+  const int k = blockIdx.z;
+  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int nblk = gridDim.x * gridDim.y * gridDim.z;
+  double acc[NQ_STEP] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < g.nx && j < g.ny) {
+    const int e = gidx(g, i, j, k);
+    const int pl = g.px * g.ny;
+    const T ih = p.ih;
+    const T pf = a.pf[e], pw = a.pw[e], xO = a.xO[e], xH = a.xH[e], xW = a.xW[e], muc = a.mu[e];
+    T mu_l, MOc, DHc, DWc;
+    transport(p, pf, pw, xO, mu_l, MOc, DHc, DWc);
+    (void)mu_l;
+    T lf = T(0), lw = T(0), divO = T(0), divH = T(0), divW = T(0);
+    T bO = T(0), bH = T(0);   // outward boundary fluxes (J_H2O and J_H) summed over this cell's outer faces
+    const int coord[3] = {i, j, k};
+    const int lim[3] = {g.nx, g.ny, g.nz};
+    const int step[3] = {1, g.px, pl};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const bool has_lo = coord[d] > 0, has_hi = coord[d] + 1 < lim[d];
+      const int el = has_lo ? e - step[d] : e, eh = has_hi ? e + step[d] : e;
+      const T pfl = a.pf[el], pfh = a.pf[eh], pwl = a.pw[el], pwh = a.pw[eh];
+      lf += (pfh - pf) - (pf - pfl);
+      lw += (pwh - pw) - (pw - pwl);
+      T JOm = T(0), JOp = T(0), JHm, JHp, JWm, JWp;
+      if (has_lo) {
+        T m_, M, DHn, DWn;
+        transport(p, pfl, pwl, a.xO[el], m_, M, DHn, DWn);
+        JOm = face_flux(M, MOc, a.mu[el], muc, ih);
+        JHm = face_flux(DHn, DHc, a.xH[el], xH, ih);
+        JWm = face_flux(DWn, DWc, a.xW[el], xW, ih);
+      } else if (p.dirichlet) {
+        JHm = -DHc * (xH - p.xHbc) * (T(2) * ih);
+        JWm = -DWc * (xW - p.xWbc) * (T(2) * ih);
+        bH -= JHm;
+        bO -= JWm;
+      } else {
+        JHm = T(0);
+        JWm = T(0);
+      }
+      if (has_hi) {
+        T m_, M, DHn, DWn;
+        transport(p, pfh, pwh, a.xO[eh], m_, M, DHn, DWn);
+        JOp = face_flux(MOc, M, muc, a.mu[eh], ih);
+        JHp = face_flux(DHc, DHn, xH, a.xH[eh], ih);
+        JWp = face_flux(DWc, DWn, xW, a.xW[eh], ih);
+      } else if (p.dirichlet) {
+        JHp = -DHc * (p.xHbc - xH) * (T(2) * ih);
+        JWp = -DWc * (p.xWbc - xW) * (T(2) * ih);
+        bH += JHp;
+        bO += JWp;
+      } else {
+        JHp = T(0);
+        JWp = T(0);
+      }
+      divO += (JOp - JOm) * ih;
+      divH += (JHp - JHm) * ih;
+      divW += (JWp - JWm) * ih;
+    }
+    lf *= p.ih2;
+    lw *= p.ih2;
+
+    // phase quantities and the chemical / barrier driving forces (Eq. 33)
+    Phase<T> q;
+    phase_eval(p, pf, pw, q);
+    const T pg = T(1) - pf - pw;
+    T gf = p.w[0] * interp_dm(pf, p.mform) - p.w[1] * interp_dm(pg, p.mform);
+    T gw = p.w[2] * interp_dm(pw, p.mform) - p.w[1] * interp_dm(pg, p.mform);
+    if (p.chem) {
+      T f0, f1, f2, g0, g1, g2, w0, w1, w2;
+      fe_ferrite(xO, f0, f1, f2);
+      fe_gas(xO, g0, g1, g2);
+      fe_wuestite(xO, w0, w1, w2);
+      gf += p.scale * (q.dhf * f0 - q.dhg * g0);
+      gw += p.scale * (q.dhw * w0 - q.dhg * g0);
+    }
+    T vm = T(0), epsPn = T(0);
+    if (p.mech) {
+      // cell strain: normal from faces, shear as the mean of four edges
+      const T* ux = a.u[0];
+      const T* uy = a.u[1];
+      T eb[6];
+      eb[0] = ((i + 1 < g.nx ? ux[e + 1] : T(0)) - ux[e]) * ih;
+      eb[1] = ((j + 1 < g.ny ? uy[e + g.px] : T(0)) - uy[e]) * ih;
+      eb[2] = T(0);
+      eb[3] = T(0.25) * (shear_xy<T, DIM>(g, ux, uy, i, j, k, ih) + shear_xy<T, DIM>(g, ux, uy, i + 1, j, k, ih) +
+                         shear_xy<T, DIM>(g, ux, uy, i, j + 1, k, ih) + shear_xy<T, DIM>(g, ux, uy, i + 1, j + 1, k, ih));
+      eb[4] = T(0);
+      eb[5] = T(0);
+      if constexpr (DIM == 3) {
+        const T* uz = a.u[2];
+        eb[2] = ((k + 1 < g.nz ? uz[e + pl] : T(0)) - uz[e]) * ih;
+        eb[4] = T(0.25) * (shear_xz(g, ux, uz, i, j, k, ih) + shear_xz(g, ux, uz, i + 1, j, k, ih) +
+                           shear_xz(g, ux, uz, i, j, k + 1, ih) + shear_xz(g, ux, uz, i + 1, j, k + 1, ih));
+        eb[5] = T(0.25) * (shear_yz(g, uy, uz, i, j, k, ih) + shear_yz(g, uy, uz, i, j + 1, k, ih) +
+                           shear_yz(g, uy, uz, i, j, k + 1, ih) + shear_yz(g, uy, uz, i, j + 1, k + 1, ih));
+      }
+      constexpr int NC = (DIM == 2) ? 4 : 6;
+      T ep[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ep[c] = a.epsp[c * g.n + e];
+      const T epsP0 = a.epsP[e];
+      epsPn = epsP0;
+      // elastic strain and its deviator
+      T ee[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ee[c] = eb[c] - ep[c];
+      ee[0] -= q.eT; ee[1] -= q.eT; ee[2] -= q.eT;
+      T tr = ee[0] + ee[1] + ee[2];
+      T dv[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) dv[c] = ee[c];
+      dv[0] -= tr * T(1.0 / 3.0); dv[1] -= tr * T(1.0 / 3.0); dv[2] -= tr * T(1.0 / 3.0);
+      T nd2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2] + T(2) * (dv[3] * dv[3] + dv[4] * dv[4] + dv[5] * dv[5]);
+      T nd = tsqrt(nd2);
+      if (p.plastic) {
+        // J2 radial return, backward Euler (Eq. 25, Eq. 34)
+        const T r23 = T(0.816496580927726032732428024902);   // sqrt(2/3)
+        T ftr = T(2) * q.G * nd - r23 * (p.sigY + p.Hh * epsP0);
+        if (ftr > T(0)) {
+          T dl = ftr / (T(2) * q.G + r23 * p.Hh);
+          T sc = dl / nd;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) ep[c] += sc * dv[c];
+          epsPn = epsP0 + dl;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) a.epsp[c * g.n + e] = ep[c];
+          a.epsP[e] = epsPn;
+          // the return keeps tr and scales the deviator
+          T f = T(1) - T(2) * q.G * dl / (T(2) * q.G * nd);
+#pragma unroll
+          for (int c = 0; c < 6; ++c) dv[c] *= f;
+          nd2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2] + T(2) * (dv[3] * dv[3] + dv[4] * dv[4] + dv[5] * dv[5]);
+          nd = tsqrt(nd2);
+        }
+      }
+      // elastic driving force: derivative of d_T sum h(phi_a) (K_a tr^2/2 + G_a |dev|^2)
+      T pe_f = T(0.5) * p.K[0] * tr * tr + p.G[0] * nd2;
+      T pe_g = T(0.5) * p.K[1] * tr * tr + p.G[1] * nd2;
+      T pe_w = T(0.5) * p.K[2] * tr * tr + p.G[2] * nd2;
+      T phi_el = q.hf * pe_f + q.hg * pe_g + q.hw * pe_w;
+      gf += q.dTp * phi_el + q.dT * (q.dhf * pe_f - q.dhg * pe_g) - q.eTp * T(3) * q.K * tr;
+      gw += q.dT * (q.dhw * pe_w - q.dhg * pe_g);
+      vm = T(1.2247448713915890491) * T(2) * q.G * nd;   // sqrt(3/2) |dev sigma|
+    }
+    // reaction (Eq. 27, 28): zero once the cell is full of water
+    const T r = xW < T(1) ? interp_m(pg, p.mform) * p.kfor * xO * xH : T(0);
+    const T nf = pf + p.dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf);
+    const T nw = pw + p.dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw);
+    const T nO = xO + p.dt * (-divO - r);
+    const T nH = xH + p.dt * (-divH - T(2) * r);
+    const T nW = xW + p.dt * (-divW + r);
+    a.npf[e] = nf;
+    a.npw[e] = nw;
+    a.nxO[e] = nO;
+    a.nxH[e] = nH;
+    a.nxW[e] = nW;
+    acc[0] = (double)nO + (double)nW;
+    acc[1] = (double)nH + 2.0 * (double)nW;
+    acc[2] = (double)nO;
+    acc[3] = (double)bO;
+    acc[4] = (double)bH + 2.0 * (double)bO;
+    acc[5] = (double)vm;
+    acc[6] = (double)epsPn;
+    bool fin = isfinite(nf) && isfinite(nw) && isfinite(nO) && isfinite(nH) && isfinite(nW) && isfinite(vm);
+    acc[7] = fin ? 0.0 : 1.0;
+  }
+#pragma unroll
+  for (int qn = 0; qn < NQ_STEP; ++qn) {
+    double s = (qn == 5 || qn == 6) ? block_max(acc[qn], red) : block_sum(acc[qn], red);
+    if (threadIdx.x == 0) a.part[qn * nblk + bid] = s;
+  }
+}
+
+// Totals for a ledger reset: sum (x_O + x_W), sum (x_H + 2 x_W), sum x_O.
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_totals(CellArgs<T> a) {
+  __shared__ double red[NT / 64];
+  const int i = blockIdx.x * TX + (threadIdx.x & (TX - 1));
+  const int j = blockIdx.y * TY + threadIdx.x / TX;
+  const int k = blockIdx.z;
+  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int nblk = gridDim.x * gridDim.y * gridDim.z;
+  double s0 = 0, s1 = 0, s2 = 0;
+  if (i < a.g.nx && j < a.g.ny) {
+    const int e = gidx(a.g, i, j, k);
+    s0 = (double)a.xO[e] + (double)a.xW[e];
+    s1 = (double)a.xH[e] + 2.0 * (double)a.xW[e];
+    s2 = (double)a.xO[e];
+  }
+  s0 = block_sum(s0, red);
+  s1 = block_sum(s1, red);
+  s2 = block_sum(s2, red);
+  if (threadIdx.x == 0) {
+    a.part[bid] = s0;
+    a.part[nblk + bid] = s1;
+    a.part[2 * nblk + bid] = s2;
+  }
+}
+
+// mode 0: ledger reset from k_totals partials; mode 1: end of step from k_step partials
+__global__ __launch_bounds__(NT) void k_ledger(const double* part, int n, double* scal, double vol, double area_dt,
+                                               int mode) {
+  __shared__ double red[NT / 64];
+  if (mode == 0) {
+    double O = sum_partials(part, n, red), H = sum_partials(part + n, n, red), X = sum_partials(part + 2 * n, n, red);
+    if (threadIdx.x == 0) {
+      scal[S_O0] = O * vol;
+      scal[S_H0] = H * vol;
+      scal[S_XO0] = X;
+      scal[S_OOUT] = 0.0;
+      scal[S_HOUT] = 0.0;
+      scal[S_OTOT] = O * vol;
+      scal[S_HTOT] = H * vol;
+      scal[S_XOSUM] = X;
+    }
+    return;
+  }
+  double O = sum_partials(part, n, red), H = sum_partials(part + n, n, red), X = sum_partials(part + 2 * n, n, red);
+  double bo = sum_partials(part + 3 * n, n, red), bh = sum_partials(part + 4 * n, n, red);
+  double vm = 0.0, ep = 0.0;
+  for (int q = threadIdx.x; q < n; q += NT) {
+    vm = fmax(vm, part[5 * n + q]);
+    ep = fmax(ep, part[6 * n + q]);
+  }
+  vm = block_max(vm, red);
+  ep = block_max(ep, red);
+  double nf = sum_partials(part + 7 * n, n, red);
+  if (threadIdx.x == 0) {
+    scal[S_OOUT] += area_dt * bo;
+    scal[S_HOUT] += area_dt * bh;
+    scal[S_OTOT] = O * vol;
+    scal[S_HTOT] = H * vol;
+    scal[S_XOSUM] = X;
+    scal[S_MAXVM] = vm;
+    scal[S_MAXEP] = ep;
+    scal[S_NONFIN] = nf;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Field exchange: FP64 compact <-> internal padded layout.
+// The compact array has dims (cx, cy, cz); entries beyond the stored range
+// (the high roller faces) are dropped on set and read as zero on get.
+// `zero_axis` (0, 1, 2 or -1) forces the low roller face to zero on set.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_unpack(const double* src, T* dst, Grid g, int cx, int cy, int cz, int zero_axis) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long total = (long long)cx * cy * cz;
+  if (t >= total) return;
+  int ii = (int)(t % cx);
+  long long rest = t / cx;
+  int jj = (int)(rest % cy);
+  int kk = (int)(rest / cy);
+  if (ii >= g.nx || jj >= g.ny || kk >= g.nz) return;
+  double v = src[t];
+  if ((zero_axis == 0 && ii == 0) || (zero_axis == 1 && jj == 0) || (zero_axis == 2 && kk == 0)) v = 0.0;
+  dst[gidx(g, ii, jj, kk)] = (T)v;
+}
+
+template <typename T>
+__global__ void k_pack(const T* src, double* dst, Grid g, int cx, int cy, int cz) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long total = (long long)cx * cy * cz;
+  if (t >= total) return;
+  int ii = (int)(t % cx);
+  long long rest = t / cx;
+  int jj = (int)(rest % cy);
+  int kk = (int)(rest / cy);
+  double v = 0.0;
+  if (ii < g.nx && jj < g.ny && kk < g.nz) v = (double)src[gidx(g, ii, jj, kk)];
+  dst[t] = v;
+}
+
+}  // namespace pfk

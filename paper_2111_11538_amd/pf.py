@@ -1,0 +1,247 @@
+"""Python binding of the C ABI in ``include/pf.h`` (argument marshalling only).
+
+Every numerical step runs in ``libpf.so``'s HIP kernels; this module loads the
+library, mirrors its structs with ctypes and uses PyTorch only to allocate the
+device workspace and to name the stream.  There is no fallback: if the library
+is missing, importing the binding's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpf.so")
+
+PF_OK, PF_ERR_INVALID_ARG, PF_ERR_HIP, PF_ERR_OOM, PF_ERR_CG_NOT_CONVERGED = 0, 1, 2, 3, 4
+PF_ERR_NONFINITE, PF_ERR_LEDGER, PF_ERR_BAD_STATE, PF_ERR_UNSUPPORTED = 5, 6, 7, 8
+PF_FP64, PF_MIXED = 0, 1
+PF_WARM_ZERO, PF_WARM_PREV = 0, 1
+FIELDS = {"phi_f": 0, "phi_w": 1, "xO": 2, "xH": 3, "xW": 4, "ux": 5, "uy": 6, "uz": 7, "epsp": 8, "epsP": 9}
+
+
+class pf_config(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("h", C.c_double), ("dt", C.c_double),
+                ("precision", C.c_int), ("mechanics", C.c_int), ("plasticity", C.c_int),
+                ("dirichlet", C.c_int), ("chem_phase", C.c_int),
+                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("warm", C.c_int),
+                ("ledger_tol", C.c_double)]
+
+
+class pf_params(C.Structure):
+    _fields_ = [("R", C.c_double), ("theta", C.c_double), ("Vmol", C.c_double),
+                ("w", C.c_double * 3), ("eps", C.c_double * 3), ("L", C.c_double * 3),
+                ("kappaO", C.c_double), ("K", C.c_double * 3), ("G", C.c_double * 3),
+                ("sigY", C.c_double), ("Hhard", C.c_double),
+                ("DO", C.c_double * 3), ("DH", C.c_double * 3), ("DW", C.c_double * 3),
+                ("kfor", C.c_double), ("Omega_f", C.c_double), ("xH_bc", C.c_double), ("xW_bc", C.c_double),
+                ("m_form", C.c_int), ("pad_", C.c_int)]
+
+
+class pf_step_stats(C.Structure):
+    _fields_ = [("cg_iters", C.c_int), ("warm_used", C.c_int), ("cg_rel_resid", C.c_double),
+                ("O_tot", C.c_double), ("O_out", C.c_double), ("O_drift", C.c_double),
+                ("H_tot", C.c_double), ("H_out", C.c_double), ("H_drift", C.c_double),
+                ("red_degree", C.c_double), ("max_vm", C.c_double), ("max_epsP", C.c_double),
+                ("step", C.c_longlong), ("nonfinite", C.c_int), ("pad_", C.c_int),
+                ("cg_iters_total", C.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
+EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_fields", "pf_ledger_reset",
+           "pf_timing", "pf_timing_get", "pf_last_error", "pf_destroy")
+KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other")
+
+_lib = None
+
+
+def lib():
+    """Load ``libpf.so`` (built in-tree by ``build.py``); raises if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2111_11538_amd/build.py (or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        L.pf_workspace_bytes.argtypes = [C.POINTER(pf_config)]
+        L.pf_workspace_bytes.restype = C.c_size_t
+        L.pf_init.argtypes = [C.POINTER(pf_config), C.POINTER(pf_params), C.c_void_p, C.c_size_t, C.c_void_p,
+                              C.POINTER(C.c_void_p)]
+        L.pf_init.restype = C.c_int
+        L.pf_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(pf_step_stats)]
+        L.pf_step.restype = C.c_int
+        L.pf_mech_solve.argtypes = [C.c_void_p, C.c_int, C.POINTER(pf_step_stats)]
+        L.pf_mech_solve.restype = C.c_int
+        L.pf_fields.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_int]
+        L.pf_fields.restype = C.c_int
+        L.pf_ledger_reset.argtypes = [C.c_void_p]
+        L.pf_ledger_reset.restype = C.c_int
+        L.pf_timing.argtypes = [C.c_void_p, C.c_int]
+        L.pf_timing.restype = C.c_int
+        L.pf_timing_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
+        L.pf_timing_get.restype = C.c_int
+        L.pf_last_error.argtypes = [C.c_void_p]
+        L.pf_last_error.restype = C.c_char_p
+        L.pf_destroy.argtypes = [C.c_void_p]
+        L.pf_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+class PFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pf status {status}: {msg}")
+        self.status = status
+
+
+def make_params(p) -> pf_params:
+    o = pf_params()
+    for name in ("R", "theta", "Vmol", "kappaO", "sigY", "Hhard", "kfor", "Omega_f", "xH_bc", "xW_bc"):
+        setattr(o, name, float(getattr(p, name)))
+    for name in ("w", "eps", "L", "K", "G", "DO", "DH", "DW"):
+        arr = getattr(o, name)
+        for a, v in enumerate(getattr(p, name)):
+            arr[a] = float(v)
+    o.m_form = int(p.m_form)
+    return o
+
+
+def make_config(dim, shape, h, dt, precision="fp64", mechanics=True, plasticity=False, dirichlet=True,
+                chem_phase=True, cg_rtol=1e-10, cg_max_iter=200000, warm="prev", ledger_tol=0.0) -> pf_config:
+    c = pf_config()
+    c.dim = dim
+    if dim == 2:
+        c.ny, c.nx = shape
+        c.nz = 1
+    else:
+        c.nz, c.ny, c.nx = shape
+    c.h, c.dt = h, dt
+    c.precision = {"fp64": PF_FP64, "mixed": PF_MIXED}[precision]
+    c.mechanics, c.plasticity, c.dirichlet, c.chem_phase = int(mechanics), int(plasticity), int(dirichlet), int(chem_phase)
+    c.cg_rtol, c.cg_max_iter = cg_rtol, cg_max_iter
+    c.warm = {"zero": PF_WARM_ZERO, "prev": PF_WARM_PREV}[warm]
+    c.ledger_tol = ledger_tol
+    return c
+
+
+def field_shape(name, dim, shape):
+    if dim == 2:
+        ny, nx = shape
+        nz = None
+    else:
+        nz, ny, nx = shape
+    nc = 4 if dim == 2 else 6
+    cell = tuple(shape)
+    if name == "ux":
+        return (ny, nx + 1) if dim == 2 else (nz, ny, nx + 1)
+    if name == "uy":
+        return (ny + 1, nx) if dim == 2 else (nz, ny + 1, nx)
+    if name == "uz":
+        return (nz + 1, ny, nx)
+    if name == "epsp":
+        return (nc,) + cell
+    return cell
+
+
+class Context:
+    """One simulation on one GPU: a thin owner of a ``pf_ctx`` and of the
+    torch-allocated device workspace it lives in."""
+
+    def __init__(self, dim, shape, h, dt, params, device=0, stream=None, **cfg_kw):
+        import torch
+        self.dim, self.shape = dim, tuple(shape)
+        self.cfg = make_config(dim, shape, h, dt, **cfg_kw)
+        self.params = make_params(params)
+        L = lib()
+        nbytes = L.pf_workspace_bytes(C.byref(self.cfg))
+        if nbytes == 0:
+            raise PFError(PF_ERR_INVALID_ARG, "invalid configuration")
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        rc = L.pf_init(C.byref(self.cfg), C.byref(self.params), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                       C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx))
+        if rc != PF_OK:
+            raise PFError(rc, L.pf_last_error(None).decode())
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, rc):
+        if rc != PF_OK:
+            raise PFError(rc, lib().pf_last_error(self.ctx).decode())
+
+    def set(self, name, value):
+        """Set one field from a numpy array or a torch tensor (any device)."""
+        import torch
+        shp = field_shape(name, self.dim, self.shape)
+        if isinstance(value, torch.Tensor):
+            t = value.detach().to(dtype=torch.float64)
+            if t.device.type == "cuda":
+                t = t.contiguous()
+                assert tuple(t.shape) == shp, (name, t.shape, shp)
+                self._check(lib().pf_fields(self.ctx, FIELDS[name], 1, C.c_void_p(t.data_ptr()), t.numel() * 8, 1))
+                return
+            value = t.numpy()
+        a = np.ascontiguousarray(value, dtype=np.float64)
+        assert a.shape == shp, (name, a.shape, shp)
+        self._check(lib().pf_fields(self.ctx, FIELDS[name], 1, a.ctypes.data_as(C.c_void_p), a.nbytes, 0))
+
+    def get(self, name):
+        a = np.zeros(field_shape(name, self.dim, self.shape), dtype=np.float64)
+        self._check(lib().pf_fields(self.ctx, FIELDS[name], 0, a.ctypes.data_as(C.c_void_p), a.nbytes, 0))
+        return a
+
+    def get_device(self, name):
+        """Field as an FP64 torch tensor on the context's device."""
+        import torch
+        t = torch.empty(field_shape(name, self.dim, self.shape), dtype=torch.float64, device=self.device)
+        self._check(lib().pf_fields(self.ctx, FIELDS[name], 0, C.c_void_p(t.data_ptr()), t.numel() * 8, 1))
+        return t
+
+    def set_fields(self, fields: dict):
+        for k, v in fields.items():
+            if k in FIELDS:
+                self.set(k, v)
+
+    def fields(self, names=None):
+        names = names or [n for n in FIELDS if not (n == "uz" and self.dim == 2)]
+        return {n: self.get(n) for n in names}
+
+    def step(self, n=1):
+        st = pf_step_stats()
+        self._check(lib().pf_step(self.ctx, int(n), C.byref(st)))
+        return st.as_dict()
+
+    def mech_solve(self, warm="zero"):
+        st = pf_step_stats()
+        self._check(lib().pf_mech_solve(self.ctx, {"zero": PF_WARM_ZERO, "prev": PF_WARM_PREV}[warm], C.byref(st)))
+        return st.as_dict()
+
+    def timing(self, enable=True):
+        self._check(lib().pf_timing(self.ctx, int(enable)))
+
+    def timing_report(self):
+        out = {}
+        for k, name in enumerate(KERNEL_KINDS):
+            ms, n = C.c_double(), C.c_longlong()
+            self._check(lib().pf_timing_get(self.ctx, k, C.byref(ms), C.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
+    def ledger_reset(self):
+        self._check(lib().pf_ledger_reset(self.ctx))
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            lib().pf_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

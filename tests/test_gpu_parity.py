@@ -1,0 +1,221 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (derived in the design doc):
+  * FP64 path: both sides stop CG at ||b - A u|| <= rtol ||b||; with rtol =
+    1e-12 the displacements may differ by the conditioning times rtol, so u is
+    compared at 1e-7 relative; the per-step increments of the five fields
+    inherit that through the elastic driving force (1e-6 relative); the fields
+    themselves agree to 1e-12 relative.
+  * Mixed path (FP32 state, FP64 reductions): 1e-4 relative field error, the
+    accuracy gate of the target metric; the increment error is reported.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2111_11538_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("phi_f", "phi_w", "xO", "xH", "xW")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def field_err(a, b):
+    """Relative L2 error; for a field whose RMS is below 1e-6 (x_H2O before
+    any reaction has happened: rounding noise only) the RMS absolute error."""
+    rms = np.sqrt(np.mean(b * b))
+    if rms < 1e-6:
+        return np.sqrt(np.mean((a - b) ** 2))
+    return rel(a, b)
+
+
+def _ctx(dim, shape, h, dt, p, **kw):
+    from paper_2111_11538_amd import pf
+    return pf.Context(dim, shape, h, dt, p, **kw)
+
+
+def _run_pair(oracle, dim, shape, fields, p, dt, steps, precision="fp64", plasticity=True, dirichlet=True,
+              mechanics=True, rtol=1e-12, h=I.H_DEFAULT):
+    say(f"case dim={dim} shape={shape} precision={precision} plasticity={plasticity} steps={steps}")
+    o = oracle.OracleSim(dim, shape, h, dt, p, fields, mechanics=mechanics, plasticity=plasticity,
+                         dirichlet=dirichlet, cg_rtol=rtol)
+    g = _ctx(dim, shape, h, dt, p, precision=precision, mechanics=mechanics, plasticity=plasticity,
+             dirichlet=dirichlet, cg_rtol=rtol)
+    g.set_fields(fields)
+    f0 = {k: np.array(fields[k], dtype=np.float64) for k in NAMES}
+    ost = gst = None
+    for _ in range(steps):
+        ost = o.step()
+        gst = g.step()
+    out = g.fields()
+    g.close()
+    return o, ost, out, gst, f0
+
+
+def _check_fp64(o, ost, out, gst, f0, u_tol=1e-7, inc_tol=1e-6):
+    for k in NAMES:
+        assert rel(out[k], o.f[k]) < 1e-12, k
+        d_or = o.f[k] - f0[k]
+        if np.linalg.norm(d_or) > 0:
+            assert rel(out[k] - f0[k], d_or) < inc_tol, (k, rel(out[k] - f0[k], d_or))
+    assert rel(out["ux"], o.ux) < u_tol
+    assert rel(out["uy"], o.uy) < u_tol
+    if o.uz is not None:
+        assert rel(out["uz"], o.uz) < u_tol
+    if np.max(o.epsP) > 0:
+        assert rel(out["epsP"], o.epsP) < 1e-6
+        assert rel(out["epsp"], o.epsp) < 1e-6
+    assert abs(gst["cg_iters"] - ost["cg_iters"]) <= 2, (gst["cg_iters"], ost["cg_iters"])
+    assert abs(gst["O_drift"]) < 1e-13 and abs(ost["O_drift"]) < 1e-13
+    assert abs(gst["red_degree"] - ost["red_degree"]) < 1e-12
+    assert abs(gst["max_vm"] - ost["max_vm"]) <= 1e-6 * ost["max_vm"] + 1.0
+    assert gst["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("shape,plastic", [((24, 24), False), ((64, 64), False), ((43, 67), True)])
+def test_fp64_2d_core_shell(oracle, shape, plastic):
+    wl = I.workload("core_shell_2d", n=shape[0])
+    f = I.ic_core_shell(shape, r_core=0.3 * min(shape), frame=2, noise_seed=I.SEED_BASE + 1)
+    res = _run_pair(oracle, 2, shape, f, wl.params, wl.dt, 6, plasticity=plastic)
+    _check_fp64(*res)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (13, 17, 20)])
+def test_fp64_3d_core_shell(oracle, shape):
+    n = min(shape)
+    f = I.ic_core_shell(shape, r_core=0.35 * n, r_shell=0.43 * n, noise_seed=I.SEED_BASE + 2)
+    p = I.Params()
+    res = _run_pair(oracle, 3, shape, f, p, I.stable_dt(p, I.H_DEFAULT, 3), 3, plasticity=True)
+    _check_fp64(*res)
+
+
+def test_fp64_2d_porous_ragged(oracle):
+    wl = I.workload("porous_2d", n=96)
+    res = _run_pair(oracle, 2, wl.shape, wl.fields, wl.params, wl.dt, 4, plasticity=True)
+    _check_fp64(*res)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 64), (3, 24)])
+def test_mixed_precision_field_error(oracle, dim, n):
+    if dim == 2:
+        wl = I.workload("core_shell_2d", n=n)
+    else:
+        wl = I.workload("core_shell_3d", n=n)
+    o, ost, out, gst, f0 = _run_pair(oracle, dim, wl.shape, wl.fields, wl.params, wl.dt, 10, precision="mixed",
+                                     plasticity=True, rtol=1e-6)
+    errs = {k: field_err(out[k], o.f[k]) for k in NAMES}
+    say("oracle field rms", {k: float(np.sqrt(np.mean(o.f[k] ** 2))) for k in NAMES})
+    incr = {k: rel(out[k] - f0[k], o.f[k] - f0[k]) for k in NAMES}
+    say("mixed field errors", errs)
+    say("mixed increment errors", incr)
+    for k in NAMES:
+        assert errs[k] < 1e-4, k
+    assert rel(out["ux"], o.ux) < 1e-3
+    assert gst["nonfinite"] == 0
+
+
+def test_laminate_solve_is_exact(oracle):
+    p = I.Params()
+    n = 12
+    shape = (4, n)
+    layer = np.array([0, 0, 1, 1, 1, 2, 2, 0, 0, 1, 2, 2])
+    f = {k: np.zeros(shape) for k in NAMES}
+    f["phi_f"][...] = (layer == 0)
+    f["phi_w"][...] = (layer == 2)
+    h = I.H_DEFAULT
+    g = _ctx(2, shape, h, 1e-9, p, cg_rtol=1e-14)
+    g.set_fields(f)
+    st = g.mech_solve("zero")
+    ux = g.get("ux")
+    g.close()
+    dT = np.where(layer == 0, 1 - p.Omega_f, 1.0)
+    Kl = dT * np.array([p.K[a] for a in layer])
+    Gl = dT * np.array([p.G[a] for a in layer])
+    el = np.where(layer == 0, (1 - p.Omega_f) ** (1 / 3) - 1, 0.0)
+    Ml = Kl + 4 * Gl / 3
+    sig = -np.sum(3 * Kl * el / Ml) / np.sum(1 / Ml)
+    sig_num = Ml * np.diff(ux, axis=-1) / h - 3 * Kl * el
+    assert np.max(np.abs(sig_num - sig)) < 1e-9 * abs(sig)
+    assert st["cg_rel_resid"] < 1e-13
+
+
+def test_closed_box_conserves_oxygen():
+    wl = I.workload("core_shell_2d", n=32)
+    g = _ctx(2, wl.shape, wl.h, wl.dt, wl.params, dirichlet=False, plasticity=True)
+    g.set_fields(wl.fields)
+    st = g.step(20)
+    g.close()
+    assert abs(st["O_drift"]) < 1e-13 and abs(st["H_drift"]) < 1e-13
+
+
+def test_determinism_bitwise():
+    wl = I.workload("core_shell_3d", n=20)
+    outs = []
+    for _ in range(2):
+        g = _ctx(3, wl.shape, wl.h, wl.dt, wl.params, precision="mixed", plasticity=True, cg_rtol=1e-6)
+        g.set_fields(wl.fields)
+        st = g.step(3)
+        outs.append((g.fields(), st))
+        g.close()
+    for k in outs[0][0]:
+        assert np.array_equal(outs[0][0][k], outs[1][0][k]), k
+    assert outs[0][1]["O_tot"] == outs[1][1]["O_tot"]
+
+
+def test_field_roundtrip_and_roller_faces():
+    shape = (9, 7)
+    rng = np.random.default_rng(1)
+    g = _ctx(2, shape, I.H_DEFAULT, 1e-9, I.Params())
+    for name in ("phi_f", "xO", "epsP"):
+        v = rng.standard_normal(shape)
+        g.set(name, v)
+        assert np.array_equal(g.get(name), v)
+    ux = rng.standard_normal((9, 8))
+    g.set("ux", ux)
+    back = g.get("ux")
+    assert np.all(back[:, 0] == 0) and np.all(back[:, -1] == 0)
+    assert np.array_equal(back[:, 1:-1], ux[:, 1:-1])
+    ep = rng.standard_normal((4,) + shape)
+    g.set("epsp", ep)
+    assert np.array_equal(g.get("epsp"), ep)
+    g.close()
+
+
+def test_error_paths():
+    from paper_2111_11538_amd import pf
+    wl = I.workload("core_shell_2d", n=24)
+    g = _ctx(2, wl.shape, wl.h, wl.dt, wl.params, cg_max_iter=1, cg_rtol=1e-12)
+    g.set_fields(wl.fields)
+    with pytest.raises(pf.PFError) as e:
+        g.step()
+    assert e.value.status == pf.PF_ERR_CG_NOT_CONVERGED
+    with pytest.raises(pf.PFError) as e:
+        g.step()
+    assert e.value.status == pf.PF_ERR_BAD_STATE
+    g.close()
+    g = _ctx(2, wl.shape, wl.h, wl.dt, wl.params)
+    f = dict(wl.fields)
+    f["xH"] = f["xH"].copy()
+    f["xH"][3, 4] = np.nan
+    g.set_fields(f)
+    with pytest.raises(pf.PFError) as e:
+        g.step()
+    assert e.value.status == pf.PF_ERR_NONFINITE
+    g.close()
+    g = _ctx(2, wl.shape, wl.h, wl.dt, wl.params, precision="mixed", cg_rtol=1e-6, ledger_tol=1e-300)
+    g.set_fields(wl.fields)
+    with pytest.raises(pf.PFError) as e:
+        g.step(5)
+    assert e.value.status == pf.PF_ERR_LEDGER
+    g.close()
