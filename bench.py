@@ -127,11 +127,23 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="first copy this many MiB with a plain device copy (counter calibration under a profiler)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_probe > 0:
+        import torch
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     from paper_2111_11538_amd import inputs as I
     wl = I.workload(args.workload, n=args.n)

@@ -19,7 +19,8 @@ using namespace pfk;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kUpdBlocksMax = 1024;
+constexpr int kUpdBlocksMax = 512;
+constexpr int kApplyBY = 8;          // tile height of the 3D apply kernel (block = 64 x 8 threads)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -29,6 +30,8 @@ struct Layout {
   size_t es;               // element size (4 or 8)
   int kz;
   dim3 gel, gcell;
+  int kz_ap;               // z planes per block of the 3D apply kernel
+  dim3 gap;                // its grid (64 x kApplyBY tiles)
   int nb_el, nb_cell, nb_upd;
   size_t stage_elems;
   // byte offsets into the workspace
@@ -67,6 +70,13 @@ Layout make_layout(const pf_config* c) {
     while (L.kz > 1 && (long long)nbx * nby * ((g.nz + L.kz - 1) / L.kz) < 2048) L.kz /= 2;
   }
   L.gel = dim3(nbx, nby, c->dim == 3 ? (g.nz + L.kz - 1) / L.kz : 1);
+  {
+    // deeper z chunks and taller tiles cut the re-fetched halo; keep >= 256 blocks (one per CU)
+    int nby8 = (g.ny + kApplyBY - 1) / kApplyBY;
+    L.kz_ap = 16;
+    while (L.kz_ap > 1 && (long long)nbx * nby8 * ((g.nz + L.kz_ap - 1) / L.kz_ap) < 256) L.kz_ap /= 2;
+    L.gap = dim3(nbx, nby8, (g.nz + L.kz_ap - 1) / L.kz_ap);
+  }
   L.nb_el = nbx * nby * (int)L.gel.z;
   L.gcell = dim3(nbx, nby, g.nz);
   L.nb_cell = nbx * nby * g.nz;
@@ -91,7 +101,7 @@ Layout make_layout(const pf_config* c) {
     L.o_pb[d] = take(arr); L.o_q[d] = take(arr); L.o_di[d] = take(arr);
   }
   L.o_scal = take(S_COUNT * sizeof(double));
-  int nbmax = std::max(L.nb_el, std::max(L.nb_cell, L.nb_upd));
+  int nbmax = std::max(std::max(L.nb_el, (int)(L.gap.x * L.gap.y * L.gap.z)), std::max(L.nb_cell, L.nb_upd));
   L.o_part_u = take(2 * (size_t)nbmax * sizeof(double));
   L.o_part_a = take(2 * (size_t)nbmax * sizeof(double));
   L.o_part_b = take(2 * (size_t)nbmax * sizeof(double));
@@ -297,7 +307,7 @@ struct Impl {
     up.scal = c->scal();
     up.part = part_u;
     up.part_in = part_a;
-    up.n_in = L.nb_el;
+    up.n_in = DIM == 3 ? (int)(L.gap.x * L.gap.y * L.gap.z) : L.nb_el;
     for (int d = 0; d < DIM; ++d) {
       ap.z[d] = c->arr<T>(L.o_z[d]);
       ap.o2[d] = c->arr<T>(L.o_q[d]);
@@ -309,6 +319,7 @@ struct Impl {
     }
     ap.part = part_a;
     ap.part_in = part_u;
+    if (DIM == 3) ap.kz = L.kz_ap;
 
     const int maxit = c->cfg.cg_max_iter;
     int launched = 0;
@@ -328,7 +339,12 @@ struct Impl {
         ap.parity = par;
         ap.n_in = launched == 0 ? L.nb_el : L.nb_upd;
         up.parity = par;
-        timed(c, PF_K_APPLY, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_APPLY>), L.gel, dim3(NT), 0, st, ap); }, launched);
+        if constexpr (DIM == 3)
+          timed(c, PF_K_APPLY, [&] {
+            hipLaunchKernelGGL((k_apply3<T, kApplyBY>), L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
+          }, launched);
+        else
+          timed(c, PF_K_APPLY, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_APPLY>), L.gel, dim3(NT), 0, st, ap); }, launched);
         timed(c, PF_K_UPDATE, [&] { hipLaunchKernelGGL((k_cg_update<T, DIM>), dim3(L.nb_upd), dim3(NT), 0, st, up); }, launched);
         ++launched;
       }

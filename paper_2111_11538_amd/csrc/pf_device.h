@@ -194,6 +194,20 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return s;
 }
 
+// Sum over a block of NTB threads (a multiple of 64); every thread gets the result.
+template <int NTB>
+__device__ __forceinline__ double block_sum_n(double v, double* sh) {
+  v = wave_sum(v);
+  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NTB / 64; ++q) s += sh[q];
+  return s;
+}
+
 // Sum of part[0..n) in a fixed order; identical in every block.
 __device__ __forceinline__ double sum_partials(const double* part, int n, double* sh) {
   double v = 0.0;

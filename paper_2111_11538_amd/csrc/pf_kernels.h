@@ -357,6 +357,277 @@ __global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// 3D q = A p with the direction update p = z + beta p fused in.
+//
+// Block = 64 x BY threads over a 64 x BY column tile, marching along z.  Each
+// thread keeps its own column's displacement, moduli and stresses in
+// registers (so the z neighbours never touch LDS); the x / y neighbours come
+// from an LDS plane tile with a one-cell ring.  The stresses the tile needs on
+// the ring (cell stresses below / left of it, edge stresses above / right of
+// it) are a separate short work list.  Global loads of plane k+3 are issued
+// as raw values while plane k is computed and only combined when stored.
+// ---------------------------------------------------------------------------
+template <int BY>
+struct ApplyTile {
+  static constexpr int NTB = TX * BY;
+  static constexpr int W = TX + 2, H = BY + 2, S = W * H;
+  static constexpr int NRING = 2 * W + 2 * BY;       // ring positions of the plane tile
+  static constexpr int NHALO = 3 * (TX + BY);        // ring stress items per plane
+};
+
+template <typename T, int BY>
+__global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
+  using TL = ApplyTile<BY>;
+  constexpr int W = TL::W, S = TL::S, NTB = TL::NTB;
+  __shared__ T sP[2][3][S];
+  __shared__ T sG[2][S];
+  __shared__ T sK[2][S];
+  __shared__ T sSxx[S], sSyy[S], sSxy[S];
+  __shared__ T sSxz[2][S], sSyz[2][S];
+  __shared__ double red[NTB / 64];
+
+  const Grid& g = a.g;
+  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * BY;
+  const int i = i0 + tx, j = j0 + ty;
+  const int c = (ty + 1) * W + tx + 1;              // own position in the plane tile
+  const bool own = (i < g.nx) && (j < g.ny);
+  const T ih = a.p.ih;
+  const int pl = g.px * g.ny;
+
+  // CG scalars (identical in every block)
+  if (a.scal[S_CONV] != 0.0) return;
+  double rzv = 0.0, rrv = 0.0;
+  {
+    double v0 = 0.0, v1 = 0.0;
+    for (int q = threadIdx.x; q < a.n_in; q += NTB) { v0 += a.part_in[q]; v1 += a.part_in[a.n_in + q]; }
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    __shared__ double sh2[2][NTB / 64];
+    if ((threadIdx.x & 63) == 0) { sh2[0][threadIdx.x >> 6] = v0; sh2[1][threadIdx.x >> 6] = v1; }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NTB / 64; ++w) { rzv += sh2[0][w]; rrv += sh2[1][w]; }
+  }
+  if (rrv <= a.tol2 * a.scal[S_BB]) {
+    if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = 1.0;
+    return;
+  }
+  const bool first = a.scal[S_FIRST] != 0.0;
+  const double beta = first ? 0.0 : rzv / a.scal[S_RZ + (a.parity ^ 1)];
+  if (bid == 0 && threadIdx.x == 0) {
+    a.scal[S_RZ + a.parity] = rzv;
+    a.scal[S_RR] = rrv;
+  }
+  const T tb = (T)beta;
+
+  // ring position handled by this thread (threads >= NRING have none)
+  int rg_t = S, rg_e = 0;
+  bool rg_in = false;
+  if (threadIdx.x < TL::NRING) {
+    int t = threadIdx.x, yy, xx;
+    if (t < W) { yy = 0; xx = t; }
+    else if (t < 2 * W) { yy = BY + 1; xx = t - W; }
+    else { t -= 2 * W; yy = 1 + (t >> 1); xx = (t & 1) ? TX + 1 : 0; }
+    const int ii = i0 + xx - 1, jj = j0 + yy - 1;
+    rg_t = yy * W + xx;
+    rg_in = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny;
+    rg_e = rg_in ? jj * g.px + ii : 0;
+  }
+  const int own_e = own ? j * g.px + i : 0;
+
+  // raw (in-flight) loads of one plane: own column and ring position
+  T oz[3], op[3], og, ok, hz[3], hp[3], hg, hk;
+  bool oin = false, hin = false;
+  auto fetch = [&](int kk) {
+    const bool zin = kk >= 0 && kk < g.nz;
+    oin = own && zin;
+    hin = rg_in && zin;
+    const int eo = oin ? own_e + kk * pl : 0;
+    const int eh = hin ? rg_e + kk * pl : 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      oz[d] = a.z[d][eo];
+      op[d] = a.u[d][eo];
+      hz[d] = a.z[d][eh];
+      hp[d] = a.u[d][eh];
+    }
+    og = a.G[eo]; ok = a.K[eo];
+    hg = a.G[eh]; hk = a.K[eh];
+  };
+  // combine, store the plane into LDS slot `slot`, and return the own values
+  auto stash = [&](int slot, T (&vp)[3], T& vg, T& vk) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vp[d] = oin ? (first ? oz[d] : oz[d] + tb * op[d]) : T(0);
+    vg = oin ? og : T(0);
+    vk = oin ? ok : T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sP[slot][d][c] = vp[d];
+    sG[slot][c] = vg;
+    sK[slot][c] = vk;
+    if (rg_t < S) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sP[slot][d][rg_t] = hin ? (first ? hz[d] : hz[d] + tb * hp[d]) : T(0);
+      sG[slot][rg_t] = hin ? hg : T(0);
+      sK[slot][rg_t] = hin ? hk : T(0);
+    }
+  };
+  // stresses from LDS at tile position q (all neighbours from LDS)
+  auto cell_lds = [&](int q, int sk, int sk1, T& sxx, T& syy) {
+    const T exx = (sP[sk][0][q + 1] - sP[sk][0][q]) * ih;
+    const T eyy = (sP[sk][1][q + W] - sP[sk][1][q]) * ih;
+    const T ezz = (sP[sk1][2][q] - sP[sk][2][q]) * ih;
+    const T tr = exx + eyy + ezz;
+    const T G2 = T(2) * sG[sk][q];
+    const T lam = sK[sk][q] * tr - G2 * tr * T(1.0 / 3.0);
+    sxx = lam + G2 * exx;
+    syy = lam + G2 * eyy;
+  };
+  auto xy_lds = [&](int q, int ii, int jj, int sk) -> T {
+    if (!(ii > 0 && ii < g.nx && jj > 0 && jj < g.ny)) return T(0);
+    const T ge = T(0.25) * (sG[sk][q - W - 1] + sG[sk][q - W] + sG[sk][q - 1] + sG[sk][q]);
+    return ge * ((sP[sk][0][q] - sP[sk][0][q - W]) + (sP[sk][1][q] - sP[sk][1][q - 1])) * ih;
+  };
+  auto xz_lds = [&](int q, int ii, int jj, int kk, int s0, int s1) -> T {
+    if (!(kk > 0 && kk < g.nz && ii > 0 && ii < g.nx && jj < g.ny)) return T(0);
+    const T ge = T(0.25) * (sG[s0][q - 1] + sG[s0][q] + sG[s1][q - 1] + sG[s1][q]);
+    return ge * ((sP[s1][0][q] - sP[s0][0][q]) + (sP[s1][2][q] - sP[s1][2][q - 1])) * ih;
+  };
+  auto yz_lds = [&](int q, int ii, int jj, int kk, int s0, int s1) -> T {
+    if (!(kk > 0 && kk < g.nz && jj > 0 && jj < g.ny && ii < g.nx)) return T(0);
+    const T ge = T(0.25) * (sG[s0][q - W] + sG[s0][q] + sG[s1][q - W] + sG[s1][q]);
+    return ge * ((sP[s1][1][q] - sP[s0][1][q]) + (sP[s1][2][q] - sP[s1][2][q - W])) * ih;
+  };
+  // ring stress items: cells left / below the tile, xy edges above / right,
+  // z edges right (xz) / above (yz) at level kk
+  auto ring_items = [&](int sk, int sk1, int kk_edge, int s0, int s1, int zout, bool cells_and_xy) {
+    for (int w = threadIdx.x; w < TL::NHALO; w += NTB) {
+      const int grp = w / (TX + BY), r = w - grp * (TX + BY);
+      if (grp == 0) {
+        if (!cells_and_xy) continue;
+        const int yy = r < TX ? 0 : 1 + (r - TX), xx = r < TX ? 1 + r : 0;
+        const int q = yy * W + xx;
+        T sxx, syy;
+        cell_lds(q, sk, sk1, sxx, syy);
+        sSxx[q] = sxx;
+        sSyy[q] = syy;
+      } else if (grp == 1) {
+        if (!cells_and_xy) continue;
+        const int yy = r < TX ? BY + 1 : 1 + (r - TX), xx = r < TX ? 1 + r : TX + 1;
+        const int q = yy * W + xx;
+        sSxy[q] = xy_lds(q, i0 + xx - 1, j0 + yy - 1, sk);
+      } else {
+        if (r < TX) {    // yz edge above the tile
+          const int q = (BY + 1) * W + 1 + r;
+          sSyz[zout][q] = yz_lds(q, i0 + r, j0 + BY, kk_edge, s0, s1);
+        } else {         // xz edge right of the tile
+          const int yy = 1 + (r - TX);
+          const int q = yy * W + TX + 1;
+          sSxz[zout][q] = xz_lds(q, i0 + TX, j0 + yy - 1, kk_edge, s0, s1);
+        }
+      }
+    }
+  };
+
+  const int k0 = blockIdx.z * a.kz;
+  const int k1 = min(k0 + a.kz, g.nz);
+  T pc[3], gc, kc, pn[3], gn, kn;     // own values of planes k (c) and k+1 (n)
+  T szz_prev = T(0), sxz_c = T(0), syz_c = T(0);
+
+  // prologue: planes k0-1, k0; sigma_zz of the own cell below; z edges at level k0
+  {
+    T pb[3], gb, kb;
+    fetch(k0 - 1);
+    stash((k0 - 1) & 1, pb, gb, kb);
+    fetch(k0);
+    stash(k0 & 1, pc, gc, kc);
+    __syncthreads();
+    const int sa = (k0 - 1) & 1, sb = k0 & 1;
+    if (k0 > 0) {
+      const T exx = (sP[sa][0][c + 1] - pb[0]) * ih;
+      const T eyy = (sP[sa][1][c + W] - pb[1]) * ih;
+      const T ezz = (pc[2] - pb[2]) * ih;
+      const T tr = exx + eyy + ezz;
+      const T G2 = T(2) * gb;
+      szz_prev = kb * tr - G2 * tr * T(1.0 / 3.0) + G2 * ezz;
+    }
+    sxz_c = xz_lds(c, i, j, k0, sa, sb);
+    syz_c = yz_lds(c, i, j, k0, sa, sb);
+    sSxz[sb][c] = sxz_c;
+    sSyz[sb][c] = syz_c;
+    ring_items(sa, sb, k0, sa, sb, sb, false);
+    __syncthreads();
+    fetch(k0 + 1);
+    stash((k0 + 1) & 1, pn, gn, kn);
+    fetch(k0 + 2);
+    __syncthreads();
+  }
+
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const int sk = k & 1, sk1 = (k + 1) & 1;
+    // (A) own stresses of plane k and own z edges at level k+1
+    const T exx = (sP[sk][0][c + 1] - pc[0]) * ih;
+    const T eyy = (sP[sk][1][c + W] - pc[1]) * ih;
+    const T ezz = (pn[2] - pc[2]) * ih;
+    const T tr = exx + eyy + ezz;
+    const T G2 = T(2) * gc;
+    const T lam = kc * tr - G2 * tr * T(1.0 / 3.0);
+    const T sxx = lam + G2 * exx, syy = lam + G2 * eyy, szz = lam + G2 * ezz;
+    T sxy = T(0);
+    if (i > 0 && i < g.nx && j > 0 && j < g.ny) {
+      const T ge = T(0.25) * (sG[sk][c - W - 1] + sG[sk][c - W] + sG[sk][c - 1] + gc);
+      sxy = ge * ((pc[0] - sP[sk][0][c - W]) + (pc[1] - sP[sk][1][c - 1])) * ih;
+    }
+    const int kn1 = k + 1;
+    T sxz_n = T(0), syz_n = T(0);
+    if (kn1 < g.nz) {
+      if (i > 0 && i < g.nx) {
+        const T ge = T(0.25) * (sG[sk][c - 1] + gc + sG[sk1][c - 1] + gn);
+        sxz_n = ge * ((pn[0] - pc[0]) + (pn[2] - sP[sk1][2][c - 1])) * ih;
+      }
+      if (j > 0 && j < g.ny) {
+        const T ge = T(0.25) * (sG[sk][c - W] + gc + sG[sk1][c - W] + gn);
+        syz_n = ge * ((pn[1] - pc[1]) + (pn[2] - sP[sk1][2][c - W])) * ih;
+      }
+    }
+    sSxx[c] = sxx;
+    sSyy[c] = syy;
+    sSxy[c] = sxy;
+    sSxz[sk1][c] = sxz_n;
+    sSyz[sk1][c] = syz_n;
+    ring_items(sk, sk1, kn1, sk, sk1, sk1, true);
+    __syncthreads();
+    // (C) divergence onto the own faces of plane k
+    if (own) {
+      const int e = own_e + k * pl;
+      T q0 = T(0), q1 = T(0), q2 = T(0);
+      if (i > 0) q0 = sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n;
+      if (j > 0) q1 = sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n;
+      if (k > 0) q2 = szz_prev - szz + sxz_c - sSxz[sk][c + 1] + syz_c - sSyz[sk][c + W];
+      a.o1[0][e] = pc[0]; a.o1[1][e] = pc[1]; a.o1[2][e] = pc[2];
+      a.o2[0][e] = q0; a.o2[1][e] = q1; a.o2[2][e] = q2;
+      acc += (double)pc[0] * (double)q0 + (double)pc[1] * (double)q1 + (double)pc[2] * (double)q2;
+    }
+    szz_prev = szz;
+    sxz_c = sxz_n;
+    syz_c = syz_n;
+    if (k + 1 < k1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) pc[d] = pn[d];
+      gc = gn;
+      kc = kn;
+      stash(sk, pn, gn, kn);   // plane k+2 into the slot of plane k
+      fetch(k + 3);
+    }
+    __syncthreads();
+  }
+  const double s0 = block_sum_n<NTB>(acc, red);
+  if (threadIdx.x == 0) a.part[bid] = s0;
+}
+
+// ---------------------------------------------------------------------------
 // CG update: u += alpha p, r -= alpha q, z = D^-1 r; partials of r.z and r.r
 // ---------------------------------------------------------------------------
 template <typename T>
