@@ -70,12 +70,18 @@ Layout make_layout(const pf_config* c) {
     while (L.kz > 1 && (long long)nbx * nby * ((g.nz + L.kz - 1) / L.kz) < 2048) L.kz /= 2;
   }
   L.gel = dim3(nbx, nby, c->dim == 3 ? (g.nz + L.kz - 1) / L.kz : 1);
-  {
-    // deeper z chunks and taller tiles cut the re-fetched halo; keep >= 256 blocks (one per CU)
+  if (c->dim == 3) {
+    // deeper z chunks and taller tiles cut the re-fetched halo; keep >= 512 blocks
     int nby8 = (g.ny + kApplyBY - 1) / kApplyBY;
-    L.kz_ap = 16;
-    while (L.kz_ap > 1 && (long long)nbx * nby8 * ((g.nz + L.kz_ap - 1) / L.kz_ap) < 256) L.kz_ap /= 2;
+    L.kz_ap = 8;
+    while (L.kz_ap > 1 && (long long)nbx * nby8 * ((g.nz + L.kz_ap - 1) / L.kz_ap) < 512) L.kz_ap /= 2;
     L.gap = dim3(nbx, nby8, (g.nz + L.kz_ap - 1) / L.kz_ap);
+  } else {
+    // rows of A2W columns marching along y over kz_ap rows; keep >= 512 blocks
+    int nbx2 = (g.nx + A2W - 1) / A2W;
+    L.kz_ap = 32;
+    while (L.kz_ap > 1 && (long long)nbx2 * ((g.ny + L.kz_ap - 1) / L.kz_ap) < 512) L.kz_ap /= 2;
+    L.gap = dim3(nbx2, (g.ny + L.kz_ap - 1) / L.kz_ap, 1);
   }
   L.nb_el = nbx * nby * (int)L.gel.z;
   L.gcell = dim3(nbx, nby, g.nz);
@@ -307,7 +313,7 @@ struct Impl {
     up.scal = c->scal();
     up.part = part_u;
     up.part_in = part_a;
-    up.n_in = DIM == 3 ? (int)(L.gap.x * L.gap.y * L.gap.z) : L.nb_el;
+    up.n_in = (int)(L.gap.x * L.gap.y * L.gap.z);
     for (int d = 0; d < DIM; ++d) {
       ap.z[d] = c->arr<T>(L.o_z[d]);
       ap.o2[d] = c->arr<T>(L.o_q[d]);
@@ -319,7 +325,7 @@ struct Impl {
     }
     ap.part = part_a;
     ap.part_in = part_u;
-    if (DIM == 3) ap.kz = L.kz_ap;
+    ap.kz = L.kz_ap;
 
     const int maxit = c->cfg.cg_max_iter;
     int launched = 0;
@@ -344,7 +350,7 @@ struct Impl {
             hipLaunchKernelGGL((k_apply3<T, kApplyBY>), L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
           }, launched);
         else
-          timed(c, PF_K_APPLY, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_APPLY>), L.gel, dim3(NT), 0, st, ap); }, launched);
+          timed(c, PF_K_APPLY, [&] { hipLaunchKernelGGL((k_apply2<T>), L.gap, dim3(A2W), 0, st, ap); }, launched);
         timed(c, PF_K_UPDATE, [&] { hipLaunchKernelGGL((k_cg_update<T, DIM>), dim3(L.nb_upd), dim3(NT), 0, st, up); }, launched);
         ++launched;
       }

@@ -53,6 +53,16 @@ struct Grid {
 
 __device__ __forceinline__ int gidx(const Grid& g, int i, int j, int k) { return (k * g.ny + j) * g.px + i; }
 
+// MI355X has 8 XCDs, each with its own L2; workgroups are dispatched to them
+// round robin by linear block id.  Map block id b to tile id so that XCD
+// (b mod 8) owns the contiguous tile range [x * nb/8, (x+1) * nb/8).  Identity
+// when nb is not a multiple of 8.
+constexpr int kXCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if (nb % kXCD) return b;
+  return (b % kXCD) * (nb / kXCD) + b / kXCD;
+}
+
 template <typename T> __device__ __forceinline__ T tcbrt(T x);
 template <> __device__ __forceinline__ float tcbrt<float>(float x) { return cbrtf(x); }
 template <> __device__ __forceinline__ double tcbrt<double>(double x) { return cbrt(x); }

@@ -388,8 +388,13 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
 
   const Grid& g = a.g;
   const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  // Consecutive hardware block ids go to different XCDs (round robin over 8);
+  // give each XCD a contiguous run of tiles so that tile halos are re-read
+  // from that XCD's own L2.
+  const int tile = xcd_tile(bid, gridDim.x * gridDim.y * gridDim.z);
+  const int bx = tile % gridDim.x, by = (tile / gridDim.x) % gridDim.y, bz = tile / (gridDim.x * gridDim.y);
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * BY;
+  const int i0 = bx * TX, j0 = by * BY;
   const int i = i0 + tx, j = j0 + ty;
   const int c = (ty + 1) * W + tx + 1;              // own position in the plane tile
   const bool own = (i < g.nx) && (j < g.ny);
@@ -530,7 +535,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
     }
   };
 
-  const int k0 = blockIdx.z * a.kz;
+  const int k0 = bz * a.kz;
   const int k1 = min(k0 + a.kz, g.nz);
   T pc[3], gc, kc, pn[3], gn, kn;     // own values of planes k (c) and k+1 (n)
   T szz_prev = T(0), sxz_c = T(0), syz_c = T(0);
@@ -624,6 +629,188 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
     __syncthreads();
   }
   const double s0 = block_sum_n<NTB>(acc, red);
+  if (threadIdx.x == 0) a.part[bid] = s0;
+}
+
+// ---------------------------------------------------------------------------
+// 2D (plane strain) q = A p with the direction update fused in.
+//
+// Block = 256 threads over 256 consecutive x columns, marching along y over
+// `kz` rows.  Each thread keeps its own column's values of rows j and j+1 in
+// registers; only the x neighbours go through a one-row LDS tile (width 258).
+// The two stresses the tile needs outside it (sigma_xx of the cell left of
+// the tile, the xy edge right of it) are computed by two threads.
+// ---------------------------------------------------------------------------
+constexpr int A2W = 256;                 // columns per block
+template <typename T>
+__global__ __launch_bounds__(A2W) void k_apply2(ElastArgs<T> a) {
+  constexpr int W = A2W + 2;
+  __shared__ T sP[2][2][W];              // [row slot][component][x]
+  __shared__ T sG[2][W];
+  __shared__ T sK[2];                    // K of the ring cell left of the tile, per row slot
+  __shared__ T sSxx[W];
+  __shared__ T sSxy[2][W];               // xy edge stresses at two y levels
+  __shared__ double red[A2W / 64];
+
+  const Grid& g = a.g;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  const int tile = xcd_tile(bid, gridDim.x * gridDim.y);
+  const int bx = tile % gridDim.x, by = tile / gridDim.x;
+  const int i0 = bx * A2W;
+  const int i = i0 + threadIdx.x;
+  const int c = threadIdx.x + 1;         // own x position in the row tile
+  const bool own = i < g.nx;
+  const T ih = a.p.ih;
+
+  if (a.scal[S_CONV] != 0.0) return;
+  double rzv = 0.0, rrv = 0.0;
+  {
+    double v0 = 0.0, v1 = 0.0;
+    for (int q = threadIdx.x; q < a.n_in; q += A2W) { v0 += a.part_in[q]; v1 += a.part_in[a.n_in + q]; }
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    __shared__ double sh2[2][A2W / 64];
+    if ((threadIdx.x & 63) == 0) { sh2[0][threadIdx.x >> 6] = v0; sh2[1][threadIdx.x >> 6] = v1; }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < A2W / 64; ++w) { rzv += sh2[0][w]; rrv += sh2[1][w]; }
+  }
+  if (rrv <= a.tol2 * a.scal[S_BB]) {
+    if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = 1.0;
+    return;
+  }
+  const bool first = a.scal[S_FIRST] != 0.0;
+  const double beta = first ? 0.0 : rzv / a.scal[S_RZ + (a.parity ^ 1)];
+  if (bid == 0 && threadIdx.x == 0) {
+    a.scal[S_RZ + a.parity] = rzv;
+    a.scal[S_RR] = rrv;
+  }
+  const T tb = (T)beta;
+
+  // ring positions: thread 0 -> x = i0 - 1 (tile slot 0), thread 1 -> x = i0 + A2W (slot W - 1)
+  const int rg_x = threadIdx.x == 0 ? i0 - 1 : i0 + A2W;
+  const int rg_t = threadIdx.x == 0 ? 0 : (threadIdx.x == 1 ? W - 1 : -1);
+  const bool rg_ok = rg_t >= 0 && rg_x >= 0 && rg_x < g.nx;
+
+  T oz[2], op[2], og, ok, hz[2], hp[2], hg, hk;
+  bool oin = false, hin = false;
+  auto fetch = [&](int jj) {
+    const bool yin = jj >= 0 && jj < g.ny;
+    oin = own && yin;
+    hin = rg_ok && yin;
+    const int eo = oin ? jj * g.px + i : 0;
+    const int eh = hin ? jj * g.px + rg_x : 0;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      oz[d] = a.z[d][eo];
+      op[d] = a.u[d][eo];
+      hz[d] = a.z[d][eh];
+      hp[d] = a.u[d][eh];
+    }
+    og = a.G[eo]; ok = a.K[eo];
+    hg = a.G[eh]; hk = a.K[eh];
+  };
+  auto stash = [&](int slot, T (&vp)[2], T& vg, T& vk) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) vp[d] = oin ? (first ? oz[d] : oz[d] + tb * op[d]) : T(0);
+    vg = oin ? og : T(0);
+    vk = oin ? ok : T(0);
+    sP[slot][0][c] = vp[0];
+    sP[slot][1][c] = vp[1];
+    sG[slot][c] = vg;
+    if (rg_t >= 0) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) sP[slot][d][rg_t] = hin ? (first ? hz[d] : hz[d] + tb * hp[d]) : T(0);
+      sG[slot][rg_t] = hin ? hg : T(0);
+      if (rg_t == 0) sK[slot] = hin ? hk : T(0);
+    }
+  };
+  // xy edge stress at node (ii, jn) between rows jn-1 (slot s0) and jn (slot s1),
+  // tile position q (x = ii)
+  auto xy_edge = [&](int q, int ii, int jn, int s0, int s1) -> T {
+    if (!(ii > 0 && ii < g.nx && jn > 0 && jn < g.ny)) return T(0);
+    const T ge = T(0.25) * (sG[s0][q - 1] + sG[s0][q] + sG[s1][q - 1] + sG[s1][q]);
+    return ge * ((sP[s1][0][q] - sP[s0][0][q]) + (sP[s1][1][q] - sP[s1][1][q - 1])) * ih;
+  };
+
+  const int j0 = by * a.kz;
+  const int j1 = min(j0 + a.kz, g.ny);
+  T pc[2], gc, kc, pn[2], gn, kn;
+  T syy_prev = T(0), sxy_c = T(0);
+
+  // prologue: rows j0-1 and j0; sigma_yy of the own cell below; xy edges at level j0
+  {
+    T pb[2], gb, kb;
+    fetch(j0 - 1);
+    stash((j0 - 1) & 1, pb, gb, kb);
+    fetch(j0);
+    stash(j0 & 1, pc, gc, kc);
+    __syncthreads();
+    const int sa = (j0 - 1) & 1, sb = j0 & 1;
+    if (j0 > 0) {
+      const T exx = (sP[sa][0][c + 1] - pb[0]) * ih;
+      const T eyy = (pc[1] - pb[1]) * ih;
+      const T tr = exx + eyy;
+      const T G2 = T(2) * gb;
+      syy_prev = kb * tr - G2 * tr * T(1.0 / 3.0) + G2 * eyy;
+    }
+    sxy_c = xy_edge(c, i, j0, sa, sb);
+    sSxy[sb][c] = sxy_c;
+    if (threadIdx.x == 1) sSxy[sb][W - 1] = xy_edge(W - 1, i0 + A2W, j0, sa, sb);
+    __syncthreads();
+    fetch(j0 + 1);
+    stash((j0 + 1) & 1, pn, gn, kn);
+    fetch(j0 + 2);
+    __syncthreads();
+  }
+
+  double acc = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const int sj = j & 1, sj1 = (j + 1) & 1;
+    // own cell stresses of row j (plane strain: eps_zz = 0) and own xy edge at level j+1
+    const T exx = (sP[sj][0][c + 1] - pc[0]) * ih;
+    const T eyy = (pn[1] - pc[1]) * ih;
+    const T tr = exx + eyy;
+    const T G2 = T(2) * gc;
+    const T lam = kc * tr - G2 * tr * T(1.0 / 3.0);
+    const T sxx = lam + G2 * exx, syy = lam + G2 * eyy;
+    T sxy_n = T(0);
+    if (i > 0 && i < g.nx && j + 1 < g.ny) {
+      const T ge = T(0.25) * (sG[sj][c - 1] + gc + sG[sj1][c - 1] + gn);
+      sxy_n = ge * ((pn[0] - pc[0]) + (pn[1] - sP[sj1][1][c - 1])) * ih;
+    }
+    sSxx[c] = sxx;
+    sSxy[sj1][c] = sxy_n;
+    if (threadIdx.x == 0) {              // sigma_xx of the cell left of the tile
+      const T hexx = (sP[sj][0][1] - sP[sj][0][0]) * ih;
+      const T heyy = (sP[sj1][1][0] - sP[sj][1][0]) * ih;
+      const T htr = hexx + heyy;
+      const T hG2 = T(2) * sG[sj][0];
+      sSxx[0] = sK[sj] * htr - hG2 * htr * T(1.0 / 3.0) + hG2 * hexx;
+    }
+    if (threadIdx.x == 1) sSxy[sj1][W - 1] = xy_edge(W - 1, i0 + A2W, j + 1, sj, sj1);
+    __syncthreads();
+    if (own) {
+      const int e = j * g.px + i;
+      T q0 = T(0), q1 = T(0);
+      if (i > 0) q0 = sSxx[c - 1] - sxx + sxy_c - sxy_n;
+      if (j > 0) q1 = syy_prev - syy + sxy_c - sSxy[sj][c + 1];
+      a.o1[0][e] = pc[0]; a.o1[1][e] = pc[1];
+      a.o2[0][e] = q0; a.o2[1][e] = q1;
+      acc += (double)pc[0] * (double)q0 + (double)pc[1] * (double)q1;
+    }
+    syy_prev = syy;
+    sxy_c = sxy_n;
+    if (j + 1 < j1) {
+      pc[0] = pn[0]; pc[1] = pn[1];
+      gc = gn;
+      kc = kn;
+      stash(sj, pn, gn, kn);   // row j+2 into the slot of row j
+      fetch(j + 3);
+    }
+    __syncthreads();
+  }
+  const double s0 = block_sum_n<A2W>(acc, red);
   if (threadIdx.x == 0) a.part[bid] = s0;
 }
 
