@@ -174,6 +174,60 @@ pf_status pf_timing(pf_ctx *ctx, int enable);
  * timing was enabled.  Synchronises the stream. */
 pf_status pf_timing_get(pf_ctx *ctx, int kind, double *total_ms, long long *launches);
 
+/* ------------------------------------------------------------------------ */
+/* Batches: many uneven 2D instances advanced together.                      */
+/* Each instance has its own grid, fields, CG recurrence (and convergence)   */
+/* and ledger; one step of the whole batch is ONE persistent kernel launch   */
+/* (moduli, right-hand side, the data-dependent CG loop of every instance,   */
+/* return map, chemistry and ledger, separated by bounded grid barriers),    */
+/* replayed from a hipGraph.  The caller's workspace holds every array and   */
+/* the tile tables.                                                          */
+/* ------------------------------------------------------------------------ */
+typedef struct pf_batch pf_batch;
+
+typedef struct { int nx, ny, nz; } pf_extent;   /* one instance's cells (2D: nz = 1) */
+
+/* Work decomposition of a batch step (chosen by an autotuner):
+ *  apply_rows     rows per block of the 256-column elasticity apply tiles (4..256)
+ *  update_chunk   16-byte vectors per CG-update work item (256..65536)
+ *  blocks_per_cu  persistent blocks per compute unit (1..occupancy limit)
+ *  spin_limit     polls before a grid barrier gives up and reports an error */
+typedef struct {
+  int apply_rows;
+  int update_chunk;
+  int blocks_per_cu;
+  int pad_;
+  long long spin_limit;
+} pf_batch_tiles;
+
+/* Workspace bytes for `count` instances (1..256) with the shared settings of
+ * `cfg` (dim must be 2; cfg->nx/ny/nz are ignored); 0 if invalid. */
+size_t pf_batch_workspace_bytes(const pf_config *cfg, const pf_extent *ext, int count);
+
+/* Create a batch.  Same ownership rules as pf_init; every instance starts at
+ * zero.  Requires dim == 2, mechanics == 1 and warm == PF_WARM_PREV (the
+ * first step of an instance starts its solve from u = 0). */
+pf_status pf_batch_init(const pf_config *cfg, const pf_params *params, const pf_extent *ext, int count,
+                        void *workspace, size_t workspace_bytes, void *hip_stream, pf_batch **out);
+
+/* Replace the work decomposition (rebuilds the tile tables and the graphs). */
+pf_status pf_batch_set_tiles(pf_batch *b, const pf_batch_tiles *tiles);
+pf_status pf_batch_get_tiles(const pf_batch *b, pf_batch_tiles *tiles);
+
+/* pf_fields for instance `instance` of the batch (same layouts and rules). */
+pf_status pf_batch_fields(pf_batch *b, int instance, int field_id, int dir, void *ptr, size_t nbytes,
+                          int ptr_is_device);
+
+/* Advance every instance `nsteps` steps, one graph launch per step; `stats`
+ * (nullable) receives `count` entries for the last step.  Returns
+ * PF_ERR_CG_NOT_CONVERGED if an instance's solve reached cg_max_iter (the
+ * step is still taken with the last iterate), PF_ERR_NONFINITE /
+ * PF_ERR_LEDGER as pf_step, PF_ERR_HIP if a grid barrier timed out. */
+pf_status pf_batch_step(pf_batch *b, int nsteps, pf_step_stats *stats);
+
+const char *pf_batch_last_error(const pf_batch *b);
+void pf_batch_destroy(pf_batch *b);
+
 /* Free the host-side context (never the caller's workspace). */
 void pf_destroy(pf_ctx *ctx);
 

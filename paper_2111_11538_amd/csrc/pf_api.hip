@@ -61,6 +61,7 @@ Layout make_layout(const pf_config* c) {
   g.nx = c->nx; g.ny = c->ny; g.nz = c->nz;
   g.px = (c->nx + 15) / 16 * 16;
   g.n = g.px * g.ny * g.nz;
+  g.ns = g.n;
   L.nc = c->dim == 2 ? 4 : 6;
   L.es = c->precision == PF_FP64 ? 8 : 4;
   int nbx = (g.nx + TX - 1) / TX, nby = (g.ny + TY - 1) / TY;
@@ -633,3 +634,5 @@ void pf_destroy(pf_ctx* c) {
 }
 
 }  // extern "C"
+
+#include "pf_batch_api.h"

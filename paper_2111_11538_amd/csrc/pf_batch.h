@@ -1,0 +1,395 @@
+// Batched 2D stepping of many uneven instances in one persistent launch.
+//
+// Every instance keeps its own grid, CG recurrence and ledger; their arrays
+// are packed one after another in shared buffers.  Work is described by tile
+// tables (elasticity 64x4 tiles, apply row tiles, cell tiles, CG update
+// chunks) that the persistent blocks walk with a fixed stride; phases are
+// separated by a grid barrier whose wait is bounded (a timeout raises an error
+// flag and every block leaves), so the launch always drains.
+#pragma once
+
+#include "pf_kernels.h"
+
+namespace pfk {
+
+constexpr int kMaxBatch = 256;
+
+struct InstDesc {
+  Grid g;          // the instance's own grid; g.ns = packed component stride of eps_p
+  int off;         // element offset of the instance in every packed array (multiple of 64)
+  int el0, eln;    // range in the elasticity tile table
+  int ap0, apn;    // range in the apply tile table
+  int ce0, cen;    // range in the cell tile table
+  int up0, upn;    // range in the update chunk table
+};
+struct TileRef {
+  int inst, bx, by, bz;
+};
+struct ChunkRef {
+  int inst, v0, v1, pad;   // 16-byte vector range relative to the instance
+};
+
+template <typename T>
+struct BatchArgs {
+  int count;
+  const InstDesc* inst;
+  const TileRef* el;
+  int n_el;
+  const TileRef* ap;
+  int n_ap;
+  const TileRef* ce;
+  int n_ce;
+  const ChunkRef* up;
+  int n_up;
+  KP<T> p;
+  T* f_old[5];             // current fields phi_f, phi_w, x_O, x_H, x_H2O
+  T* f_new[5];             // where the step writes the next ones
+  T* u[2];
+  T* epsp;
+  T* epsP;
+  T* mu;
+  T* K;
+  T* G;
+  T* r[2];
+  T* z[2];
+  T* pa[2];
+  T* pb[2];
+  T* q[2];
+  T* dinv[2];
+  double* part_bn;         // [n_el]
+  double* part_r;          // [2][n_el]
+  double* part_a;          // [n_ap]
+  double* part_u;          // [2 parity][2][n_up]
+  double* part_t;          // [n_el]
+  double* part_c;          // [NQ_STEP][n_ce]
+  double* iscal;           // [count][S_COUNT]
+  unsigned* bar;           // {arrivals, generation, error}
+  double tol2;
+  int max_iter;
+  int kz_ap;
+  double area_dt;
+  double vol;
+  long long spin_limit;
+};
+
+// Grid-wide barrier for a launch whose blocks are all resident.  Thread 0 of
+// each block arrives on a global counter; the last arrival resets it and
+// publishes the next generation.  Waiting is bounded: after `spin_limit`
+// polls the block sets the error word and returns false, and a block that sees
+// the error word set also returns false, so every block leaves the kernel.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen, long long spin_limit,
+                                             int* flag_sh) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __threadfence();
+    const unsigned target = gen + 1u;
+    const unsigned prev = atomicAdd(&bar[0], 1u);
+    if (prev == nblocks - 1u) {
+      atomicExch(&bar[0], 0u);
+      __threadfence();
+      atomicExch(&bar[1], target);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+        if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { ok = 0; break; }
+        if (++spins > spin_limit) { atomicExch(&bar[2], 1u); ok = 0; break; }
+        __builtin_amdgcn_s_sleep(4);
+      }
+    }
+    __threadfence();
+    gen = target;
+    *flag_sh = ok;
+  }
+  __syncthreads();
+  return *flag_sh != 0;
+}
+
+__device__ __forceinline__ double range_sum(const double* part, int r0, int n) {
+  double s = 0.0;
+  for (int q = 0; q < n; ++q) s += part[r0 + q];
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ ElastArgs<T> elast_view(const BatchArgs<T>& B, const InstDesc& d) {
+  ElastArgs<T> a{};
+  a.g = d.g;
+  a.p = B.p;
+  a.K = B.K + d.off;
+  a.G = B.G + d.off;
+  a.phi_f = B.f_old[0] + d.off;
+  a.epsp = B.epsp + d.off;
+  a.kz = B.kz_ap;
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ CellArgs<T> cell_view(const BatchArgs<T>& B, const InstDesc& d) {
+  CellArgs<T> a{};
+  a.g = d.g;
+  a.p = B.p;
+  a.pf = B.f_old[0] + d.off; a.pw = B.f_old[1] + d.off; a.xO = B.f_old[2] + d.off;
+  a.xH = B.f_old[3] + d.off; a.xW = B.f_old[4] + d.off;
+  a.npf = B.f_new[0] + d.off; a.npw = B.f_new[1] + d.off; a.nxO = B.f_new[2] + d.off;
+  a.nxH = B.f_new[3] + d.off; a.nxW = B.f_new[4] + d.off;
+  a.mu = B.mu + d.off;
+  a.mu_out = B.mu + d.off;
+  a.u[0] = B.u[0] + d.off;
+  a.u[1] = B.u[1] + d.off;
+  a.epsp = B.epsp + d.off;
+  a.epsP = B.epsP + d.off;
+  a.K = B.K + d.off;
+  a.G = B.G + d.off;
+  a.part = B.part_c;
+  return a;
+}
+
+template <typename T>
+constexpr size_t batch_smem() {
+  size_t a = sizeof(ElastSmem<T, 2, M_RESID>);
+  size_t b = sizeof(Apply2Smem<T>);
+  return a > b ? a : b;
+}
+
+#define PF_BARRIER()                                                           \
+  do {                                                                         \
+    if (!grid_barrier(B.bar, nbk, gen, B.spin_limit, &flag_sh)) return;        \
+  } while (0)
+
+// One explicit step of every instance (2D): moduli, ||b||, initial residual,
+// the CG loop until every instance has converged, true residual, mu, the
+// fused field update and the per-instance ledger.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
+  __shared__ __align__(16) char smem[batch_smem<T>()];
+  __shared__ double shA[kMaxBatch], shB[kMaxBatch], shBB[kMaxBatch];
+  __shared__ int shC[kMaxBatch];
+  __shared__ int flag_sh, all_sh;
+  __shared__ double red[NT / 64];
+  unsigned gen = 0u;
+  if (threadIdx.x == 0) gen = __hip_atomic_load(&B.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned nbk = gridDim.x;
+  const int tid = threadIdx.x;
+  const int S = S_COUNT;
+
+  // (1) effective moduli
+  for (int w = blockIdx.x; w < B.n_ce; w += nbk) {
+    const TileRef tr = B.ce[w];
+    const CellArgs<T> a = cell_view(B, B.inst[tr.inst]);
+    moduli_tile<T, 2>(a, tr.bx, tr.by, tr.bz);
+  }
+  PF_BARRIER();
+  // (2) ||b||^2 partials
+  for (int w = blockIdx.x; w < B.n_el; w += nbk) {
+    const TileRef tr = B.el[w];
+    ElastArgs<T> a = elast_view(B, B.inst[tr.inst]);
+    a.part = B.part_bn;
+    elast_tile<T, 2, M_BNORM>(a, tr.bx, tr.by, tr.bz, false, w, B.n_el, smem);
+  }
+  PF_BARRIER();
+  for (int b = tid; b < B.count; b += NT) shBB[b] = range_sum(B.part_bn, B.inst[b].el0, B.inst[b].eln);
+  __syncthreads();
+  // (3) initial residual r = b - A u, D^-1, z
+  for (int w = blockIdx.x; w < B.n_el; w += nbk) {
+    const TileRef tr = B.el[w];
+    const InstDesc& d = B.inst[tr.inst];
+    ElastArgs<T> a = elast_view(B, d);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      a.u[c] = B.u[c] + d.off;
+      a.o1[c] = B.r[c] + d.off;
+      a.o2[c] = B.z[c] + d.off;
+      a.dinv[c] = B.dinv[c] + d.off;
+    }
+    a.part = B.part_r;
+    elast_tile<T, 2, M_RESID>(a, tr.bx, tr.by, tr.bz, shBB[tr.inst] == 0.0, w, B.n_el, smem);
+  }
+  if (tid == 0)
+    for (int b = blockIdx.x; b < B.count; b += nbk) {
+      B.iscal[b * S + S_BB] = shBB[b];
+      B.iscal[b * S + S_ITERS] = 0.0;
+      B.iscal[b * S + S_CONV] = 0.0;
+    }
+  PF_BARRIER();
+
+  // (4) CG, one recurrence per instance
+  for (int L = 0;; ++L) {
+    for (int b = tid; b < B.count; b += NT) {
+      const InstDesc& d = B.inst[b];
+      double rz, rr, rzp = 1.0;
+      if (L == 0) {
+        rz = range_sum(B.part_r, d.el0, d.eln);
+        rr = range_sum(B.part_r + B.n_el, d.el0, d.eln);
+      } else {
+        const double* pu = B.part_u + ((L - 1) & 1) * 2 * B.n_up;
+        rz = range_sum(pu, d.up0, d.upn);
+        rr = range_sum(pu + B.n_up, d.up0, d.upn);
+        rzp = (L == 1) ? range_sum(B.part_r, d.el0, d.eln) : range_sum(B.part_u + (L & 1) * 2 * B.n_up, d.up0, d.upn);
+      }
+      const int conv = (B.iscal[b * S + S_CONV] != 0.0) || (rr <= B.tol2 * shBB[b]);
+      shC[b] = conv;
+      shA[b] = rz;
+      shB[b] = (L == 0) ? 0.0 : rz / rzp;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int all = 1;
+      for (int b = 0; b < B.count; ++b) all &= shC[b];
+      all_sh = all;
+      for (int b = blockIdx.x; b < B.count; b += nbk) {
+        B.iscal[b * S + S_CONV] = (double)shC[b];
+        B.iscal[b * S + S_RR] = shA[b];
+      }
+    }
+    __syncthreads();
+    if (all_sh || L >= B.max_iter) break;
+    // apply: q = A p with p = z + beta p
+    T* const pold[2] = {(L & 1) ? B.pb[0] : B.pa[0], (L & 1) ? B.pb[1] : B.pa[1]};
+    T* const pnew[2] = {(L & 1) ? B.pa[0] : B.pb[0], (L & 1) ? B.pa[1] : B.pb[1]};
+    for (int w = blockIdx.x; w < B.n_ap; w += nbk) {
+      const TileRef tr = B.ap[w];
+      if (shC[tr.inst]) continue;
+      const InstDesc& d = B.inst[tr.inst];
+      ElastArgs<T> a = elast_view(B, d);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        a.u[c] = pold[c] + d.off;
+        a.z[c] = B.z[c] + d.off;
+        a.o1[c] = pnew[c] + d.off;
+        a.o2[c] = B.q[c] + d.off;
+      }
+      a.part = B.part_a;
+      apply2_tile(a, tr.bx, tr.by, shB[tr.inst], L == 0, w, smem);
+    }
+    PF_BARRIER();
+    for (int b = tid; b < B.count; b += NT)
+      if (!shC[b]) shB[b] = shA[b] / range_sum(B.part_a, B.inst[b].ap0, B.inst[b].apn);
+    __syncthreads();
+    // update: u += alpha p, r -= alpha q, z = D^-1 r
+    double* pu = B.part_u + (L & 1) * 2 * B.n_up;
+    for (int w = blockIdx.x; w < B.n_up; w += nbk) {
+      const ChunkRef cr = B.up[w];
+      if (shC[cr.inst]) continue;
+      const InstDesc& d = B.inst[cr.inst];
+      UpdArgs<T> a{};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        a.u[c] = B.u[c] + d.off;
+        a.p[c] = pnew[c] + d.off;
+        a.r[c] = B.r[c] + d.off;
+        a.q[c] = B.q[c] + d.off;
+        a.dinv[c] = B.dinv[c] + d.off;
+        a.z[c] = B.z[c] + d.off;
+      }
+      double rz = 0.0, rr = 0.0;
+      cg_update_range<T, 2>(a, cr.v0 + tid, cr.v1, NT, shB[cr.inst], rz, rr);
+      rz = block_sum(rz, red);
+      rr = block_sum(rr, red);
+      if (tid == 0) {
+        pu[w] = rz;
+        pu[B.n_up + w] = rr;
+      }
+    }
+    if (tid == 0)
+      for (int b = blockIdx.x; b < B.count; b += nbk)
+        if (!shC[b]) B.iscal[b * S + S_ITERS] += 1.0;
+    PF_BARRIER();
+  }
+
+  // (5) true residual
+  for (int w = blockIdx.x; w < B.n_el; w += nbk) {
+    const TileRef tr = B.el[w];
+    const InstDesc& d = B.inst[tr.inst];
+    ElastArgs<T> a = elast_view(B, d);
+    a.u[0] = B.u[0] + d.off;
+    a.u[1] = B.u[1] + d.off;
+    a.part = B.part_t;
+    elast_tile<T, 2, M_TRUE>(a, tr.bx, tr.by, tr.bz, false, w, B.n_el, smem);
+  }
+  // (6) oxygen chemical potential
+  for (int w = blockIdx.x; w < B.n_ce; w += nbk) {
+    const TileRef tr = B.ce[w];
+    const CellArgs<T> a = cell_view(B, B.inst[tr.inst]);
+    mu_tile<T, 2>(a, tr.bx, tr.by, tr.bz);
+  }
+  PF_BARRIER();
+  if (tid == 0)
+    for (int b = blockIdx.x; b < B.count; b += nbk) B.iscal[b * S + S_TRUE] = range_sum(B.part_t, B.inst[b].el0, B.inst[b].eln);
+  // (7) fused chemistry / phase-field / plasticity update
+  for (int w = blockIdx.x; w < B.n_ce; w += nbk) {
+    const TileRef tr = B.ce[w];
+    const CellArgs<T> a = cell_view(B, B.inst[tr.inst]);
+    step_tile<T, 2>(a, tr.bx, tr.by, tr.bz, w, B.n_ce);
+  }
+  PF_BARRIER();
+  // (8) per-instance ledger and statistics
+  for (int b = blockIdx.x; b < B.count; b += nbk) {
+    const InstDesc& d = B.inst[b];
+    const double* P = B.part_c;
+    double v[5], mx[2], nf = 0.0;
+    for (int qn = 0; qn < 5; ++qn) {
+      double s = 0.0;
+      for (int q = tid; q < d.cen; q += NT) s += P[qn * B.n_ce + d.ce0 + q];
+      v[qn] = block_sum(s, red);
+    }
+    for (int qn = 0; qn < 2; ++qn) {
+      double m = 0.0;
+      for (int q = tid; q < d.cen; q += NT) m = fmax(m, P[(5 + qn) * B.n_ce + d.ce0 + q]);
+      mx[qn] = block_max(m, red);
+    }
+    {
+      double s = 0.0;
+      for (int q = tid; q < d.cen; q += NT) s += P[7 * B.n_ce + d.ce0 + q];
+      nf = block_sum(s, red);
+    }
+    if (tid == 0) {
+      double* sc = B.iscal + b * S;
+      sc[S_OOUT] += B.area_dt * v[3];
+      sc[S_HOUT] += B.area_dt * v[4];
+      sc[S_OTOT] = v[0] * B.vol;
+      sc[S_HTOT] = v[1] * B.vol;
+      sc[S_XOSUM] = v[2];
+      sc[S_MAXVM] = mx[0];
+      sc[S_MAXEP] = mx[1];
+      sc[S_NONFIN] = nf;
+    }
+  }
+}
+
+// Ledger reset of every instance: totals of the current fields.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_batch_totals(BatchArgs<T> B) {
+  const int w = blockIdx.x;
+  if (w >= B.n_ce) return;
+  const TileRef tr = B.ce[w];
+  const CellArgs<T> a = cell_view(B, B.inst[tr.inst]);
+  totals_tile<T, 2>(a, tr.bx, tr.by, tr.bz, w, B.n_ce);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_batch_ledger_init(BatchArgs<T> B) {
+  __shared__ double red[NT / 64];
+  const int b = blockIdx.x;
+  if (b >= B.count) return;
+  const InstDesc& d = B.inst[b];
+  double v[3];
+  for (int qn = 0; qn < 3; ++qn) {
+    double s = 0.0;
+    for (int q = threadIdx.x; q < d.cen; q += NT) s += B.part_c[qn * B.n_ce + d.ce0 + q];
+    v[qn] = block_sum(s, red);
+  }
+  if (threadIdx.x == 0) {
+    double* sc = B.iscal + b * S_COUNT;
+    sc[S_O0] = v[0] * B.vol;
+    sc[S_H0] = v[1] * B.vol;
+    sc[S_XO0] = v[2];
+    sc[S_OOUT] = 0.0;
+    sc[S_HOUT] = 0.0;
+    sc[S_OTOT] = v[0] * B.vol;
+    sc[S_HTOT] = v[1] * B.vol;
+    sc[S_XOSUM] = v[2];
+  }
+}
+
+}  // namespace pfk

@@ -49,6 +49,7 @@ struct KP {
 struct Grid {
   int nx, ny, nz, px;
   int n;                   // px * ny * nz elements per array
+  int ns;                  // element stride between the components of the plastic strain
 };
 
 __device__ __forceinline__ int gidx(const Grid& g, int i, int j, int k) { return (k * g.ny + j) * g.px + i; }

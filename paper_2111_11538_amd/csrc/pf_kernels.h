@@ -25,7 +25,7 @@ struct ElastArgs {
   const T* K;
   const T* G;
   const T* phi_f;          // eigenstrain source (modes other than APPLY)
-  const T* epsp;           // plastic strain, component-major with stride g.n
+  const T* epsp;           // plastic strain, component-major with stride g.ns
   T* u[3];                 // APPLY: previous direction p; RESID/TRUE: displacement
   const T* z[3];           // APPLY: preconditioned residual
   T* o1[3];                // APPLY: new direction; RESID: residual r
@@ -44,63 +44,60 @@ struct ElastArgs {
 constexpr int LW = TX + 2, LH = TY + 2, LS = LW * LH;
 __device__ __forceinline__ int L(int ly, int lx) { return ly * LW + lx; }
 
+// One 64 x 4 tile (marching over kz planes in 3D) of the elasticity operator
+// in the modes RESID (r = b - A u, z = D^-1 r, D^-1; partials r.z, r.r),
+// BNORM (||b||^2 partial) and TRUE (||b - A u||^2 partial).  Partials go to
+// a.part[pidx] and a.part[pstride + pidx].
+// LDS layout of elast_tile (carved from a caller-provided shared buffer so that
+// several tile functions in one kernel share the same LDS).
 template <typename T, int DIM, int MODE>
-__global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
-  constexpr bool EIG = (MODE != M_APPLY);
-  constexpr int ES = EIG ? LS : 1;
-  constexpr int DS = (MODE == M_RESID) ? LS : 1;
-  constexpr int D3 = (DIM == 3) ? LS : 1;
-  __shared__ T sP[2][DIM][LS];
-  __shared__ T sK[LS];
-  __shared__ T sG[2][LS];
-  __shared__ T sSxx[LS], sSyy[LS], sSzz[LS], sSxy[LS];
-  __shared__ T sSxz[2][D3], sSyz[2][D3];
-  __shared__ T sEt[ES], sEn[3][ES], sExy[ES];
-  __shared__ T sExz[2][(EIG && DIM == 3) ? LS : 1], sEyz[2][(EIG && DIM == 3) ? LS : 1];
-  __shared__ T sGxz[2][(MODE == M_RESID && DIM == 3) ? LS : 1], sGyz[2][(MODE == M_RESID && DIM == 3) ? LS : 1];
-  __shared__ double red[NT / 64];
-  (void)DS;
+struct ElastSmem {
+  static constexpr int D3 = (DIM == 3) ? LS : 1;
+  static constexpr int R3 = (MODE == M_RESID && DIM == 3) ? LS : 1;
+  double red[NT / 64];
+  T sP[2][DIM][LS];
+  T sK[LS];
+  T sG[2][LS];
+  T sSxx[LS], sSyy[LS], sSzz[LS], sSxy[LS];
+  T sSxz[2][D3], sSyz[2][D3];
+  T sEt[LS], sEn[3][LS], sExy[LS];
+  T sExz[2][D3], sEyz[2][D3];
+  T sGxz[2][R3], sGyz[2][R3];
+};
+
+template <typename T, int DIM, int MODE>
+__device__ __forceinline__ void elast_tile(const ElastArgs<T>& a, int bx, int by, int bz, bool zero_u, int pidx,
+                                           int pstride, char* smem) {
+  static_assert(MODE != M_APPLY, "the apply has its own kernels");
+  constexpr bool EIG = true;
+  ElastSmem<T, DIM, MODE>& SM = *reinterpret_cast<ElastSmem<T, DIM, MODE>*>(smem);
+  auto& sP = SM.sP;
+  auto& sK = SM.sK;
+  auto& sG = SM.sG;
+  auto& sSxx = SM.sSxx;
+  auto& sSyy = SM.sSyy;
+  auto& sSzz = SM.sSzz;
+  auto& sSxy = SM.sSxy;
+  auto& sSxz = SM.sSxz;
+  auto& sSyz = SM.sSyz;
+  auto& sEt = SM.sEt;
+  auto& sEn = SM.sEn;
+  auto& sExy = SM.sExy;
+  auto& sExz = SM.sExz;
+  auto& sEyz = SM.sEyz;
+  auto& sGxz = SM.sGxz;
+  auto& sGyz = SM.sGyz;
+  double* red = SM.red;
+  (void)sGxz; (void)sGyz; (void)sExz; (void)sEyz; (void)sSxz; (void)sSyz;
 
   const Grid& g = a.g;
   const KP<T>& p = a.p;
-  const int nbx = gridDim.x, nby = gridDim.y;
-  const int bid = (blockIdx.z * nby + blockIdx.y) * nbx + blockIdx.x;
-  const int nblk = nbx * nby * gridDim.z;
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int i0 = bx * TX, j0 = by * TY;
   const int i = i0 + tx, j = j0 + ty;
   const int lx = tx + 1, ly = ty + 1;
   const bool own = (i < g.nx) && (j < g.ny);
   const T ih = p.ih;
-
-  // ---- entry: scalars of the CG recurrence --------------------------------
-  double beta = 0.0;
-  bool first = false, zero_u = false;
-  if (MODE == M_APPLY) {
-    if (a.scal[S_CONV] != 0.0) return;
-    double rz = sum_partials(a.part_in, a.n_in, red);
-    double rr = sum_partials(a.part_in + a.n_in, a.n_in, red);
-    if (rr <= a.tol2 * a.scal[S_BB]) {
-      if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = 1.0;
-      return;
-    }
-    first = a.scal[S_FIRST] != 0.0;
-    beta = first ? 0.0 : rz / a.scal[S_RZ + (a.parity ^ 1)];
-    if (bid == 0 && threadIdx.x == 0) {
-      a.scal[S_RZ + a.parity] = rz;
-      a.scal[S_RR] = rr;
-    }
-  } else if (MODE == M_RESID) {
-    double bb = sum_partials(a.part_in, a.n_in, red);
-    zero_u = (bb == 0.0);
-    if (bid == 0 && threadIdx.x == 0) {
-      a.scal[S_BB] = bb;
-      a.scal[S_FIRST] = 1.0;
-      a.scal[S_CONV] = 0.0;
-      a.scal[S_ITERS] = 0.0;
-    }
-  }
-  const T tbeta = (T)beta;
 
   // ---- plane loaders ------------------------------------------------------
   auto in_dom = [&](int ii, int jj, int kk) {
@@ -116,8 +113,7 @@ __global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
       for (int c = 0; c < DIM; ++c) {
         T v = T(0);
         if (in) {
-          if (MODE == M_APPLY) v = first ? a.z[c][e] : a.z[c][e] + tbeta * a.u[c][e];
-          else if (MODE == M_BNORM) v = T(0);
+          if (MODE == M_BNORM) v = T(0);
           else v = zero_u ? T(0) : a.u[c][e];
         }
         sP[slot][c][t] = v;
@@ -139,9 +135,9 @@ __global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
       int e = in ? gidx(g, ii, jj, kk) : 0;
       sEt[t] = in ? eigen_strain(p, a.phi_f[e]) : T(0);
       sEn[0][t] = in ? a.epsp[e] : T(0);
-      sEn[1][t] = in ? a.epsp[g.n + e] : T(0);
-      sEn[2][t] = in ? a.epsp[2 * g.n + e] : T(0);
-      sExy[t] = in ? a.epsp[3 * g.n + e] : T(0);
+      sEn[1][t] = in ? a.epsp[g.ns + e] : T(0);
+      sEn[2][t] = in ? a.epsp[2 * g.ns + e] : T(0);
+      sExy[t] = in ? a.epsp[3 * g.ns + e] : T(0);
     }
   };
   auto load_eig_shear3 = [&](int kk, int slot) {   // xz, yz plastic strain of plane kk
@@ -151,8 +147,8 @@ __global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
         int ii = i0 + xx - 1, jj = j0 + yy - 1;
         bool in = in_dom(ii, jj, kk);
         int e = in ? gidx(g, ii, jj, kk) : 0;
-        sExz[slot][t] = in ? a.epsp[4 * g.n + e] : T(0);
-        sEyz[slot][t] = in ? a.epsp[5 * g.n + e] : T(0);
+        sExz[slot][t] = in ? a.epsp[4 * g.ns + e] : T(0);
+        sEyz[slot][t] = in ? a.epsp[5 * g.ns + e] : T(0);
       }
     }
   };
@@ -230,7 +226,7 @@ __global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
   };
 
   // ---- z march --------------------------------------------------------------
-  const int k0 = (DIM == 3) ? blockIdx.z * a.kz : 0;
+  const int k0 = (DIM == 3) ? bz * a.kz : 0;
   const int k1 = (DIM == 3) ? min(k0 + a.kz, g.nz) : 1;
   double acc0 = 0.0, acc1 = 0.0;
   T szz_prev = T(0), m_prev = T(0);
@@ -300,15 +296,7 @@ __global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
       if constexpr (DIM == 3) {
         if (k > 0) q[2] = szz_prev - sSzz[c] + sSxz[sk][c] - sSxz[sk][c + 1] + sSyz[sk][c] - sSyz[sk][c + LW];
       }
-      if constexpr (MODE == M_APPLY) {
-#pragma unroll
-        for (int cc = 0; cc < DIM; ++cc) {
-          T pn = sP[sk][cc][c];
-          a.o1[cc][e] = pn;
-          a.o2[cc][e] = q[cc];
-          acc0 += (double)pn * (double)q[cc];
-        }
-      } else if constexpr (MODE == M_RESID) {
+      if constexpr (MODE == M_RESID) {
         // inverse diagonal: (M_left + M_right + adjacent interior edge G_e) / h
         T Mc = sK[c] + T(4.0 / 3.0) * sG[sk][c];
         T d[3] = {T(0), T(0), T(0)};
@@ -349,11 +337,31 @@ __global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
     }
   }
   double s0 = block_sum(acc0, red);
-  if (threadIdx.x == 0) a.part[bid] = s0;
+  if (threadIdx.x == 0) a.part[pidx] = s0;
   if (MODE == M_RESID) {
     double s1 = block_sum(acc1, red);
-    if (threadIdx.x == 0) a.part[nblk + bid] = s1;
+    if (threadIdx.x == 0) a.part[pstride + pidx] = s1;
   }
+}
+
+template <typename T, int DIM, int MODE>
+__global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
+  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int nblk = gridDim.x * gridDim.y * gridDim.z;
+  bool zero_u = false;
+  if (MODE == M_RESID) {
+    __shared__ double red0[NT / 64];
+    const double bb = sum_partials(a.part_in, a.n_in, red0);
+    zero_u = (bb == 0.0);
+    if (bid == 0 && threadIdx.x == 0) {
+      a.scal[S_BB] = bb;
+      a.scal[S_FIRST] = 1.0;
+      a.scal[S_CONV] = 0.0;
+      a.scal[S_ITERS] = 0.0;
+    }
+  }
+  __shared__ __align__(16) char smem[sizeof(ElastSmem<T, DIM, MODE>)];
+  elast_tile<T, DIM, MODE>(a, blockIdx.x, blockIdx.y, blockIdx.z, zero_u, bid, nblk, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -643,48 +651,34 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
 // ---------------------------------------------------------------------------
 constexpr int A2W = 256;                 // columns per block
 template <typename T>
-__global__ __launch_bounds__(A2W) void k_apply2(ElastArgs<T> a) {
+struct Apply2Smem {
+  static constexpr int W = A2W + 2;
+  double red[A2W / 64];
+  T sP[2][2][W];                         // [row slot][component][x]
+  T sG[2][W];
+  T sK[2];                               // K of the ring cell left of the tile, per row slot
+  T sSxx[W];
+  T sSxy[2][W];                          // xy edge stresses at two y levels
+};
+
+template <typename T>
+__device__ __forceinline__ void apply2_tile(const ElastArgs<T>& a, int bx, int by, double beta, bool first, int pidx,
+                                            char* smem) {
   constexpr int W = A2W + 2;
-  __shared__ T sP[2][2][W];              // [row slot][component][x]
-  __shared__ T sG[2][W];
-  __shared__ T sK[2];                    // K of the ring cell left of the tile, per row slot
-  __shared__ T sSxx[W];
-  __shared__ T sSxy[2][W];               // xy edge stresses at two y levels
-  __shared__ double red[A2W / 64];
+  Apply2Smem<T>& SM = *reinterpret_cast<Apply2Smem<T>*>(smem);
+  auto& sP = SM.sP;
+  auto& sG = SM.sG;
+  auto& sK = SM.sK;
+  auto& sSxx = SM.sSxx;
+  auto& sSxy = SM.sSxy;
+  double* red = SM.red;
 
   const Grid& g = a.g;
-  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-  const int tile = xcd_tile(bid, gridDim.x * gridDim.y);
-  const int bx = tile % gridDim.x, by = tile / gridDim.x;
   const int i0 = bx * A2W;
   const int i = i0 + threadIdx.x;
   const int c = threadIdx.x + 1;         // own x position in the row tile
   const bool own = i < g.nx;
   const T ih = a.p.ih;
-
-  if (a.scal[S_CONV] != 0.0) return;
-  double rzv = 0.0, rrv = 0.0;
-  {
-    double v0 = 0.0, v1 = 0.0;
-    for (int q = threadIdx.x; q < a.n_in; q += A2W) { v0 += a.part_in[q]; v1 += a.part_in[a.n_in + q]; }
-    v0 = wave_sum(v0);
-    v1 = wave_sum(v1);
-    __shared__ double sh2[2][A2W / 64];
-    if ((threadIdx.x & 63) == 0) { sh2[0][threadIdx.x >> 6] = v0; sh2[1][threadIdx.x >> 6] = v1; }
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < A2W / 64; ++w) { rzv += sh2[0][w]; rrv += sh2[1][w]; }
-  }
-  if (rrv <= a.tol2 * a.scal[S_BB]) {
-    if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = 1.0;
-    return;
-  }
-  const bool first = a.scal[S_FIRST] != 0.0;
-  const double beta = first ? 0.0 : rzv / a.scal[S_RZ + (a.parity ^ 1)];
-  if (bid == 0 && threadIdx.x == 0) {
-    a.scal[S_RZ + a.parity] = rzv;
-    a.scal[S_RR] = rrv;
-  }
   const T tb = (T)beta;
 
   // ring positions: thread 0 -> x = i0 - 1 (tile slot 0), thread 1 -> x = i0 + A2W (slot W - 1)
@@ -811,7 +805,46 @@ __global__ __launch_bounds__(A2W) void k_apply2(ElastArgs<T> a) {
     __syncthreads();
   }
   const double s0 = block_sum_n<A2W>(acc, red);
-  if (threadIdx.x == 0) a.part[bid] = s0;
+  if (threadIdx.x == 0) a.part[pidx] = s0;
+}
+
+// CG scalars at the start of an apply: r.z and r.r of the latest residual
+// (partials part_in[0..n) and part_in[n..2n)); identical in every block.
+template <int NTB>
+__device__ __forceinline__ void cg_entry_sums(const double* part_in, int n, double& rz, double& rr) {
+  __shared__ double sh2[2][NTB / 64];
+  double v0 = 0.0, v1 = 0.0;
+  for (int q = threadIdx.x; q < n; q += NTB) { v0 += part_in[q]; v1 += part_in[n + q]; }
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { sh2[0][threadIdx.x >> 6] = v0; sh2[1][threadIdx.x >> 6] = v1; }
+  __syncthreads();
+  rz = 0.0;
+  rr = 0.0;
+#pragma unroll
+  for (int w = 0; w < NTB / 64; ++w) { rz += sh2[0][w]; rr += sh2[1][w]; }
+}
+
+template <typename T>
+__global__ __launch_bounds__(A2W) void k_apply2(ElastArgs<T> a) {
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  const int tile = xcd_tile(bid, gridDim.x * gridDim.y);
+  if (a.scal[S_CONV] != 0.0) return;
+  double rzv, rrv;
+  cg_entry_sums<A2W>(a.part_in, a.n_in, rzv, rrv);
+  if (rrv <= a.tol2 * a.scal[S_BB]) {
+    if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = 1.0;
+    return;
+  }
+  const bool first = a.scal[S_FIRST] != 0.0;
+  const double beta = first ? 0.0 : rzv / a.scal[S_RZ + (a.parity ^ 1)];
+  if (bid == 0 && threadIdx.x == 0) {
+    a.scal[S_RZ + a.parity] = rzv;
+    a.scal[S_RR] = rrv;
+  }
+  __shared__ __align__(16) char smem[sizeof(Apply2Smem<T>)];
+  apply2_tile(a, tile % gridDim.x, tile / gridDim.x, beta, first, bid, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -837,18 +870,14 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double2; };
 
+// u += alpha p, r -= alpha q, z = D^-1 r over the vector range [v0, v1) of
+// every component (vectors of 16 bytes); accumulates r.z and r.r.
 template <typename T, int DIM>
-__global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
-  __shared__ double red[NT / 64];
-  if (a.scal[S_CONV] != 0.0) return;
-  double pq = sum_partials(a.part_in, a.n_in, red);
-  double alpha = a.scal[S_RZ + a.parity] / pq;
+__device__ __forceinline__ void cg_update_range(const UpdArgs<T>& a, int v0, int v1, int vstride, double alpha,
+                                                double& rz, double& rr) {
   const T al = (T)alpha;
   using V = typename Vec4<T>::type;
   constexpr int VN = sizeof(V) / sizeof(T);
-  const int nv = a.n / VN;
-  double rz = 0.0, rr = 0.0;
-  const int stride = gridDim.x * NT;
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
     V* uu = reinterpret_cast<V*>(a.u[c]);
@@ -857,7 +886,7 @@ __global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
     const V* qq = reinterpret_cast<const V*>(a.q[c]);
     const V* dd = reinterpret_cast<const V*>(a.dinv[c]);
     V* zz = reinterpret_cast<V*>(a.z[c]);
-    for (int v = blockIdx.x * NT + threadIdx.x; v < nv; v += stride) {
+    for (int v = v0; v < v1; v += vstride) {
       V uv = uu[v], pv = pp[v], rv = rrp[v], qv = qq[v], dv = dd[v], zv;
       T* ue = reinterpret_cast<T*>(&uv);
       const T* pe = reinterpret_cast<const T*>(&pv);
@@ -878,8 +907,20 @@ __global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
       zz[v] = zv;
     }
   }
-  double s0 = block_sum(rz, red);
-  double s1 = block_sum(rr, red);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
+  __shared__ double red[NT / 64];
+  if (a.scal[S_CONV] != 0.0) return;
+  const double pq = sum_partials(a.part_in, a.n_in, red);
+  const double alpha = a.scal[S_RZ + a.parity] / pq;
+  using V = typename Vec4<T>::type;
+  constexpr int VN = sizeof(V) / sizeof(T);
+  double rz = 0.0, rr = 0.0;
+  cg_update_range<T, DIM>(a, blockIdx.x * NT + threadIdx.x, a.n / VN, gridDim.x * NT, alpha, rz, rr);
+  const double s0 = block_sum(rz, red);
+  const double s1 = block_sum(rr, red);
   if (threadIdx.x == 0) {
     a.part[blockIdx.x] = s0;
     a.part[gridDim.x + blockIdx.x] = s1;
@@ -929,10 +970,10 @@ struct CellArgs {
 constexpr int NQ_STEP = 8;   // O total, H total, x_O sum, O outflux, H outflux, max vm, max epsP, nonfinite
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(NT) void k_moduli(CellArgs<T> a) {
-  const int i = blockIdx.x * TX + (threadIdx.x & (TX - 1));
-  const int j = blockIdx.y * TY + threadIdx.x / TX;
-  const int k = blockIdx.z;
+__device__ __forceinline__ void moduli_tile(const CellArgs<T>& a, int bx, int by, int bz) {
+  const int i = bx * TX + (threadIdx.x & (TX - 1));
+  const int j = by * TY + threadIdx.x / TX;
+  const int k = bz;
   if (i >= a.g.nx || j >= a.g.ny) return;
   const int e = gidx(a.g, i, j, k);
   T K, G;
@@ -941,13 +982,18 @@ __global__ __launch_bounds__(NT) void k_moduli(CellArgs<T> a) {
   a.G[e] = G;
 }
 
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_moduli(CellArgs<T> a) {
+  moduli_tile<T, DIM>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // mu_O = d psi_che / d x_O - kappa_O lap(x_O), mirror (no-flux) ghosts
 template <typename T, int DIM>
-__global__ __launch_bounds__(NT) void k_mu(CellArgs<T> a) {
+__device__ __forceinline__ void mu_tile(const CellArgs<T>& a, int bx, int by, int bz) {
   const Grid& g = a.g;
-  const int i = blockIdx.x * TX + (threadIdx.x & (TX - 1));
-  const int j = blockIdx.y * TY + threadIdx.x / TX;
-  const int k = blockIdx.z;
+  const int i = bx * TX + (threadIdx.x & (TX - 1));
+  const int j = by * TY + threadIdx.x / TX;
+  const int k = bz;
   if (i >= g.nx || j >= g.ny) return;
   const int e = gidx(g, i, j, k);
   const T xc = a.xO[e];
@@ -960,6 +1006,11 @@ __global__ __launch_bounds__(NT) void k_mu(CellArgs<T> a) {
   T mu, MO, DH, DW;
   transport(a.p, a.pf[e], a.pw[e], xc, mu, MO, DH, DW);
   a.mu_out[e] = mu - a.p.kappaO * lap * a.p.ih2;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_mu(CellArgs<T> a) {
+  mu_tile<T, DIM>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <typename T>
@@ -987,15 +1038,13 @@ __device__ __forceinline__ T shear_yz(const Grid& g, const T* uy, const T* uz, i
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(NT) void k_step(CellArgs<T> a) {
+__device__ __forceinline__ void step_tile(const CellArgs<T>& a, int bx, int by, int bz, int pidx, int pstride) {
   __shared__ double red[NT / 64];
   const Grid& g = a.g;
   const KP<T>& p = a.p;
-  const int i = blockIdx.x * TX + (threadIdx.x & (TX - 1));
-  const int j = blockIdx.y * TY + threadIdx.x / TX;
-  const int k = blockIdx.z;
-  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  const int nblk = gridDim.x * gridDim.y * gridDim.z;
+  const int i = bx * TX + (threadIdx.x & (TX - 1));
+  const int j = by * TY + threadIdx.x / TX;
+  const int k = bz;
   double acc[NQ_STEP] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (i < g.nx && j < g.ny) {
     const int e = gidx(g, i, j, k);
@@ -1093,7 +1142,7 @@ __global__ __launch_bounds__(NT) void k_step(CellArgs<T> a) {
       constexpr int NC = (DIM == 2) ? 4 : 6;
       T ep[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int c = 0; c < NC; ++c) ep[c] = a.epsp[c * g.n + e];
+      for (int c = 0; c < NC; ++c) ep[c] = a.epsp[c * g.ns + e];
       const T epsP0 = a.epsP[e];
       epsPn = epsP0;
       // elastic strain and its deviator
@@ -1119,7 +1168,7 @@ __global__ __launch_bounds__(NT) void k_step(CellArgs<T> a) {
           for (int c = 0; c < 6; ++c) ep[c] += sc * dv[c];
           epsPn = epsP0 + dl;
 #pragma unroll
-          for (int c = 0; c < NC; ++c) a.epsp[c * g.n + e] = ep[c];
+          for (int c = 0; c < NC; ++c) a.epsp[c * g.ns + e] = ep[c];
           a.epsP[e] = epsPn;
           // the return keeps tr and scales the deviator
           T f = T(1) - T(2) * q.G * dl / (T(2) * q.G * nd);
@@ -1163,19 +1212,23 @@ __global__ __launch_bounds__(NT) void k_step(CellArgs<T> a) {
 #pragma unroll
   for (int qn = 0; qn < NQ_STEP; ++qn) {
     double s = (qn == 5 || qn == 6) ? block_max(acc[qn], red) : block_sum(acc[qn], red);
-    if (threadIdx.x == 0) a.part[qn * nblk + bid] = s;
+    if (threadIdx.x == 0) a.part[qn * pstride + pidx] = s;
   }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_step(CellArgs<T> a) {
+  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  step_tile<T, DIM>(a, blockIdx.x, blockIdx.y, blockIdx.z, bid, gridDim.x * gridDim.y * gridDim.z);
 }
 
 // Totals for a ledger reset: sum (x_O + x_W), sum (x_H + 2 x_W), sum x_O.
 template <typename T, int DIM>
-__global__ __launch_bounds__(NT) void k_totals(CellArgs<T> a) {
+__device__ __forceinline__ void totals_tile(const CellArgs<T>& a, int bx, int by, int bz, int pidx, int pstride) {
   __shared__ double red[NT / 64];
-  const int i = blockIdx.x * TX + (threadIdx.x & (TX - 1));
-  const int j = blockIdx.y * TY + threadIdx.x / TX;
-  const int k = blockIdx.z;
-  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  const int nblk = gridDim.x * gridDim.y * gridDim.z;
+  const int i = bx * TX + (threadIdx.x & (TX - 1));
+  const int j = by * TY + threadIdx.x / TX;
+  const int k = bz;
   double s0 = 0, s1 = 0, s2 = 0;
   if (i < a.g.nx && j < a.g.ny) {
     const int e = gidx(a.g, i, j, k);
@@ -1187,10 +1240,16 @@ __global__ __launch_bounds__(NT) void k_totals(CellArgs<T> a) {
   s1 = block_sum(s1, red);
   s2 = block_sum(s2, red);
   if (threadIdx.x == 0) {
-    a.part[bid] = s0;
-    a.part[nblk + bid] = s1;
-    a.part[2 * nblk + bid] = s2;
+    a.part[pidx] = s0;
+    a.part[pstride + pidx] = s1;
+    a.part[2 * pstride + pidx] = s2;
   }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(NT) void k_totals(CellArgs<T> a) {
+  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  totals_tile<T, DIM>(a, blockIdx.x, blockIdx.y, blockIdx.z, bid, gridDim.x * gridDim.y * gridDim.z);
 }
 
 // mode 0: ledger reset from k_totals partials; mode 1: end of step from k_step partials

@@ -41,6 +41,15 @@ class pf_params(C.Structure):
                 ("m_form", C.c_int), ("pad_", C.c_int)]
 
 
+class pf_extent(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int)]
+
+
+class pf_batch_tiles(C.Structure):
+    _fields_ = [("apply_rows", C.c_int), ("update_chunk", C.c_int), ("blocks_per_cu", C.c_int), ("pad_", C.c_int),
+                ("spin_limit", C.c_longlong)]
+
+
 class pf_step_stats(C.Structure):
     _fields_ = [("cg_iters", C.c_int), ("warm_used", C.c_int), ("cg_rel_resid", C.c_double),
                 ("O_tot", C.c_double), ("O_out", C.c_double), ("O_drift", C.c_double),
@@ -54,7 +63,9 @@ class pf_step_stats(C.Structure):
 
 
 EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_fields", "pf_ledger_reset",
-           "pf_timing", "pf_timing_get", "pf_last_error", "pf_destroy")
+           "pf_timing", "pf_timing_get", "pf_last_error", "pf_destroy",
+           "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_set_tiles", "pf_batch_get_tiles",
+           "pf_batch_fields", "pf_batch_step", "pf_batch_last_error", "pf_batch_destroy")
 KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other")
 
 _lib = None
@@ -84,6 +95,23 @@ def lib():
         L.pf_timing.restype = C.c_int
         L.pf_timing_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
         L.pf_timing_get.restype = C.c_int
+        L.pf_batch_workspace_bytes.argtypes = [C.POINTER(pf_config), C.POINTER(pf_extent), C.c_int]
+        L.pf_batch_workspace_bytes.restype = C.c_size_t
+        L.pf_batch_init.argtypes = [C.POINTER(pf_config), C.POINTER(pf_params), C.POINTER(pf_extent), C.c_int,
+                                    C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.pf_batch_init.restype = C.c_int
+        L.pf_batch_set_tiles.argtypes = [C.c_void_p, C.POINTER(pf_batch_tiles)]
+        L.pf_batch_set_tiles.restype = C.c_int
+        L.pf_batch_get_tiles.argtypes = [C.c_void_p, C.POINTER(pf_batch_tiles)]
+        L.pf_batch_get_tiles.restype = C.c_int
+        L.pf_batch_fields.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_int]
+        L.pf_batch_fields.restype = C.c_int
+        L.pf_batch_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(pf_step_stats)]
+        L.pf_batch_step.restype = C.c_int
+        L.pf_batch_last_error.argtypes = [C.c_void_p]
+        L.pf_batch_last_error.restype = C.c_char_p
+        L.pf_batch_destroy.argtypes = [C.c_void_p]
+        L.pf_batch_destroy.restype = None
         L.pf_last_error.argtypes = [C.c_void_p]
         L.pf_last_error.restype = C.c_char_p
         L.pf_destroy.argtypes = [C.c_void_p]
@@ -238,6 +266,87 @@ class Context:
     def close(self):
         if getattr(self, "ctx", None) and self.ctx.value:
             lib().pf_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many uneven 2D instances advanced together (one persistent graph launch
+    per step).  `shapes` is a list of (ny, nx)."""
+
+    def __init__(self, shapes, h, dt, params, device=0, stream=None, **cfg_kw):
+        import torch
+        self.shapes = [tuple(s) for s in shapes]
+        self.count = len(self.shapes)
+        self.cfg = make_config(2, self.shapes[0], h, dt, **cfg_kw)
+        self.params = make_params(params)
+        self.ext = (pf_extent * self.count)()
+        for k, (ny, nx) in enumerate(self.shapes):
+            self.ext[k].nx, self.ext[k].ny, self.ext[k].nz = nx, ny, 1
+        L = lib()
+        nbytes = L.pf_batch_workspace_bytes(C.byref(self.cfg), self.ext, self.count)
+        if nbytes == 0:
+            raise PFError(PF_ERR_INVALID_ARG, "invalid batch configuration")
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        rc = L.pf_batch_init(C.byref(self.cfg), C.byref(self.params), self.ext, self.count,
+                             C.c_void_p(self.workspace.data_ptr()), nbytes, C.c_void_p(self.stream.cuda_stream),
+                             C.byref(self.ctx))
+        if rc != PF_OK:
+            raise PFError(rc, L.pf_batch_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != PF_OK:
+            raise PFError(rc, lib().pf_batch_last_error(self.ctx).decode())
+
+    def set(self, k, name, value):
+        a = np.ascontiguousarray(value, dtype=np.float64)
+        assert a.shape == field_shape(name, 2, self.shapes[k]), (name, a.shape)
+        self._check(lib().pf_batch_fields(self.ctx, k, FIELDS[name], 1, a.ctypes.data_as(C.c_void_p), a.nbytes, 0))
+
+    def get(self, k, name):
+        a = np.zeros(field_shape(name, 2, self.shapes[k]), dtype=np.float64)
+        self._check(lib().pf_batch_fields(self.ctx, k, FIELDS[name], 0, a.ctypes.data_as(C.c_void_p), a.nbytes, 0))
+        return a
+
+    def set_fields(self, k, fields):
+        for name, v in fields.items():
+            if name in FIELDS and name != "uz":
+                self.set(k, name, v)
+
+    def fields(self, k):
+        return {n: self.get(k, n) for n in FIELDS if n != "uz"}
+
+    def step(self, n=1):
+        st = (pf_step_stats * self.count)()
+        self._check(lib().pf_batch_step(self.ctx, int(n), st))
+        return [s.as_dict() for s in st]
+
+    def tiles(self):
+        t = pf_batch_tiles()
+        self._check(lib().pf_batch_get_tiles(self.ctx, C.byref(t)))
+        return {"apply_rows": t.apply_rows, "update_chunk": t.update_chunk, "blocks_per_cu": t.blocks_per_cu,
+                "spin_limit": t.spin_limit}
+
+    def set_tiles(self, apply_rows=None, update_chunk=None, blocks_per_cu=None, spin_limit=None):
+        cur = self.tiles()
+        t = pf_batch_tiles()
+        t.apply_rows = apply_rows if apply_rows is not None else cur["apply_rows"]
+        t.update_chunk = update_chunk if update_chunk is not None else cur["update_chunk"]
+        t.blocks_per_cu = blocks_per_cu if blocks_per_cu is not None else cur["blocks_per_cu"]
+        t.spin_limit = spin_limit if spin_limit is not None else cur["spin_limit"]
+        self._check(lib().pf_batch_set_tiles(self.ctx, C.byref(t)))
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            lib().pf_batch_destroy(self.ctx)
             self.ctx = C.c_void_p()
 
     def __del__(self):

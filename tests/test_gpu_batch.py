@@ -1,0 +1,138 @@
+"""The batched path (one persistent graph launch per step for many uneven 2D
+instances) against the FP64 oracle and against single-instance contexts."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2111_11538_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+NAMES = ("phi_f", "phi_w", "xO", "xH", "xW")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def _instances(shapes, seed0=7):
+    out = []
+    for k, shp in enumerate(shapes):
+        out.append(I.ic_core_shell(shp, r_core=0.3 * min(shp), frame=2, noise_seed=seed0 + k))
+    return out
+
+
+def test_fp64_batch_matches_oracle(oracle):
+    from paper_2111_11538_amd import pf
+    shapes = [(24, 24), (31, 40), (64, 57)]
+    p = I.Params()
+    h = I.H_DEFAULT
+    dt = I.stable_dt(p, h, 2)
+    fields = _instances(shapes)
+    say("batch fp64", shapes)
+    b = pf.Batch(shapes, h, dt, p, precision="fp64", plasticity=True, cg_rtol=1e-12)
+    for k, f in enumerate(fields):
+        b.set_fields(k, f)
+    sims = [oracle.OracleSim(2, s, h, dt, p, f, plasticity=True, cg_rtol=1e-12) for s, f in zip(shapes, fields)]
+    for _ in range(4):
+        bst = b.step()
+        ost = [s.step() for s in sims]
+    for k, s in enumerate(sims):
+        out = b.fields(k)
+        for n in NAMES:
+            assert rel(out[n], s.f[n]) < 1e-12, (k, n)
+            d = s.f[n] - fields[k][n]
+            if np.linalg.norm(d) > 0:
+                assert rel(out[n] - fields[k][n], d) < 1e-6, (k, n)
+        assert rel(out["ux"], s.ux) < 1e-7 and rel(out["uy"], s.uy) < 1e-7
+        assert abs(bst[k]["cg_iters"] - ost[k]["cg_iters"]) <= max(2, 0.1 * ost[k]["cg_iters"])
+        assert abs(bst[k]["O_drift"]) < 1e-13
+        assert abs(bst[k]["red_degree"] - ost[k]["red_degree"]) < 1e-12
+    b.close()
+
+
+def test_mixed_batch_matches_single_contexts():
+    from paper_2111_11538_amd import pf
+    shapes = [(64, 64), (80, 112), (96, 70), (130, 130), (64, 200), (150, 90)]
+    p = I.Params()
+    h = I.H_DEFAULT
+    dt = I.stable_dt(p, h, 2)
+    fields = _instances(shapes, 20)
+    b = pf.Batch(shapes, h, dt, p, precision="mixed", plasticity=True, cg_rtol=1e-6)
+    for k, f in enumerate(fields):
+        b.set_fields(k, f)
+    bst = b.step(5)
+    for k, shp in enumerate(shapes):
+        c = pf.Context(2, shp, h, dt, p, precision="mixed", plasticity=True, cg_rtol=1e-6)
+        c.set_fields(fields[k])
+        cst = c.step(5)
+        single = c.fields()
+        c.close()
+        out = b.fields(k)
+        for n in NAMES:
+            assert rel(out[n], single[n]) < 1e-6, (k, n)
+        assert rel(out["ux"], single["ux"]) < 1e-3
+        assert abs(bst[k]["cg_iters"] - cst["cg_iters"]) <= max(3, 0.1 * cst["cg_iters"])
+    b.close()
+
+
+def test_tile_choice_does_not_change_results():
+    from paper_2111_11538_amd import pf
+    shapes = [(40, 72), (90, 33)]
+    p = I.Params()
+    h = I.H_DEFAULT
+    dt = I.stable_dt(p, h, 2)
+    fields = _instances(shapes, 40)
+    outs = []
+    for tiles in ({"apply_rows": 4, "update_chunk": 256, "blocks_per_cu": 1},
+                  {"apply_rows": 64, "update_chunk": 4096, "blocks_per_cu": 2}):
+        b = pf.Batch(shapes, h, dt, p, precision="fp64", plasticity=True, cg_rtol=1e-12)
+        b.set_tiles(**tiles)
+        for k, f in enumerate(fields):
+            b.set_fields(k, f)
+        b.step(3)
+        outs.append([b.fields(k) for k in range(len(shapes))])
+        b.close()
+    for k in range(len(shapes)):
+        for n in NAMES:
+            assert rel(outs[0][k][n], outs[1][k][n]) < 1e-12
+        assert rel(outs[0][k]["ux"], outs[1][k]["ux"]) < 1e-7
+
+
+def test_batch_is_deterministic():
+    from paper_2111_11538_amd import pf
+    shapes = [(48, 48), (70, 55), (33, 91)]
+    p = I.Params()
+    h = I.H_DEFAULT
+    fields = _instances(shapes, 60)
+    outs = []
+    for _ in range(2):
+        b = pf.Batch(shapes, h, I.stable_dt(p, h, 2), p, precision="mixed", plasticity=True, cg_rtol=1e-6)
+        for k, f in enumerate(fields):
+            b.set_fields(k, f)
+        b.step(3)
+        outs.append([b.fields(k) for k in range(len(shapes))])
+        b.close()
+    for k in range(len(shapes)):
+        for n in outs[0][k]:
+            assert np.array_equal(outs[0][k][n], outs[1][k][n]), (k, n)
+
+
+def test_barrier_timeout_is_reported_not_hung():
+    from paper_2111_11538_amd import pf
+    shapes = [(32, 32), (40, 24)]
+    p = I.Params()
+    b = pf.Batch(shapes, I.H_DEFAULT, I.stable_dt(p, I.H_DEFAULT, 2), p, precision="mixed", cg_rtol=1e-6)
+    for k, f in enumerate(_instances(shapes)):
+        b.set_fields(k, f)
+    b.set_tiles(spin_limit=0)          # every wait gives up at once
+    with pytest.raises(pf.PFError) as e:
+        b.step()
+    assert e.value.status == pf.PF_ERR_HIP
+    b.close()
