@@ -53,7 +53,12 @@ typedef enum {
 } pf_status;
 
 typedef enum { PF_FP64 = 0, PF_MIXED = 1 } pf_precision;   /* MIXED: FP32 state and stencils, FP64 reductions */
-typedef enum { PF_WARM_ZERO = 0, PF_WARM_PREV = 1 } pf_warm;
+typedef enum {
+  PF_WARM_ZERO = 0,       /* each solve starts from u = 0 */
+  PF_WARM_PREV = 1,       /* from the displacement of the previous solve */
+  PF_WARM_LEARNED = 2     /* from the previous displacement plus the increment an attached
+                             network predicts, when its residual is the smaller (3D only) */
+} pf_warm;
 
 typedef enum {
   PF_FIELD_PHI_F = 0, PF_FIELD_PHI_W = 1, PF_FIELD_XO = 2, PF_FIELD_XH = 3, PF_FIELD_XW = 4,
@@ -109,6 +114,8 @@ typedef struct {
   int nonfinite;          /* number of cells with a non-finite field value in the last step */
   int pad_;
   long long cg_iters_total;   /* CG iterations summed over every solve since pf_init */
+  double r0_learned;      /* learned start: ||b - A u0|| / ||b|| of the network's start, 0 if not evaluated */
+  double r0_prev;         /* learned start: the same for the previous displacement, 0 if not evaluated */
 } pf_step_stats;
 
 /* Bytes of device workspace pf_init needs for this configuration (0 if the
@@ -132,8 +139,9 @@ pf_status pf_init(const pf_config *cfg, const pf_params *params, void *workspace
 pf_status pf_step(pf_ctx *ctx, int nsteps, pf_step_stats *last);
 
 /* Solve only the mechanical equilibrium (Eq. 29 line 4) for the current phase
- * fields and plastic strain, starting from zero (PF_WARM_ZERO) or from the
- * current displacement (PF_WARM_PREV).  Fills cg_iters, warm_used and
+ * fields and plastic strain, starting from zero (PF_WARM_ZERO), from the
+ * current displacement (PF_WARM_PREV) or from the learned start
+ * (PF_WARM_LEARNED, contexts created with it only).  Fills cg_iters, warm_used and
  * cg_rel_resid of `stats` (nullable). */
 pf_status pf_mech_solve(pf_ctx *ctx, int warm, pf_step_stats *stats);
 
@@ -227,6 +235,119 @@ pf_status pf_batch_step(pf_batch *b, int nsteps, pf_step_stats *stats);
 
 const char *pf_batch_last_error(const pf_batch *b);
 void pf_batch_destroy(pf_batch *b);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start.  An extension of the method: the paper solves the
+ * mechanical equilibrium (Eq. 29, last line) without any learned component.
+ * A network of four 3x3x3 'same' convolutions (zero padding) with 6 -> 32 ->
+ * 32 -> 32 -> 3 channels, ReLU between layers and a linear output, predicts
+ * the displacement increment of the next solve; the CG residual decides
+ * whether the solve starts from it or from the previous displacement.
+ *
+ * Tensors are device arrays, channel-last: voxel v of n volumes of D x H x W
+ * voxels (x fastest), channel c at v * C + c.  Activations and inputs are
+ * bfloat16 (uint16 bit patterns); the network output is FP32 with 4
+ * channels (the 4th is zero).  The arithmetic is bf16 x bf16 products with
+ * FP32 accumulation on the matrix cores.
+ *
+ * Inputs per voxel (8 channels, the last 2 zero): phi_f, phi_w,
+ * (eps_T(phi_f) - eps_T(phi_f of the previous solve)) * 32 h / s and the
+ * previous increment of u_x, u_y, u_z on the cell's low faces divided by s,
+ * where eps_T = cbrt(1 - Omega_f h(phi_f)) - 1 (Eq. 9, small strain) and s is
+ * the root mean square of the previous increment over the low faces of all
+ * cells.  Output channel c times s is the predicted increment of the low
+ * face of direction c (zero on the low boundary faces, fixed by the rollers).
+ *
+ * Parameters are one FP32 vector: per layer W[27][cout][cin] (tap
+ * t = 9 (dz+1) + 3 (dy+1) + (dx+1) reads voxel (z+dz, y+dy, x+dx)) then
+ * b[cout].  All calls are ordered on the stream given at creation and
+ * return without waiting unless stated.
+ * ------------------------------------------------------------------------- */
+typedef struct pf_nn pf_nn;
+
+typedef struct {
+  long long max_voxels;   /* capacity: the largest n * D * H * W of any call (and the grid of an attached context) */
+  int training;           /* 1: also allocate targets, loss gradient and backward buffers */
+  int pad_;
+  unsigned long long seed;  /* He-uniform initial weights from SplitMix64(seed); biases 0 */
+} pf_nn_config;
+
+typedef enum { PF_NN_OP_FORWARD = 0, PF_NN_OP_BACKWARD_DATA = 1, PF_NN_OP_BACKWARD_WEIGHT = 2 } pf_nn_op;
+typedef enum { PF_NN_BUF_INPUT = 0, PF_NN_BUF_OUTPUT = 1, PF_NN_BUF_TARGET = 2, PF_NN_BUF_LOSS_GRAD = 3 } pf_nn_buffer_id;
+
+/* Number of FP32 parameters (63 171). */
+size_t pf_nn_param_count(void);
+
+/* Create a network; the library allocates and owns its device memory
+ * (about 224 bytes per voxel of capacity, 384 with training buffers). */
+pf_status pf_nn_create(const pf_nn_config *cfg, void *hip_stream, pf_nn **out);
+void pf_nn_destroy(pf_nn *nn);
+const char *pf_nn_last_error(const pf_nn *nn);
+
+/* Parameters to (dir 0) or from (dir 1) the host, or the gradients of the
+ * last pf_nn_backward to the host (dir 2); `count` must equal
+ * pf_nn_param_count().  Synchronises. */
+pf_status pf_nn_params(pf_nn *nn, int dir, float *host, size_t count);
+
+/* Copy the first `bytes` bytes of an internal buffer (pf_nn_buffer_id: the
+ * packed input [cap][8] bf16, the output [cap][4] FP32, the packed target
+ * [cap][4] FP32, the loss gradient [cap][8] bf16) to the device array `dev`
+ * (dir 0), or from it into the buffer (dir 1). */
+pf_status pf_nn_copy(pf_nn *nn, int which, int dir, void *dev, size_t bytes);
+
+/* Forward pass over n volumes of D x H x W voxels: x (8 channels; NULL: the
+ * packed input buffer) -> y (4 channels FP32; NULL: the output buffer).  The
+ * activations are kept for pf_nn_loss and pf_nn_backward. */
+pf_status pf_nn_forward(pf_nn *nn, const void *x, float *y, int n, int D, int H, int W);
+
+/* Relative mean-square loss of the last forward pass against `target`
+ * (4 channels FP32 per voxel, the first 3 count; NULL: the packed targets):
+ * L = (1/n) sum_s |p_s - q_s|^2 / |q_s|^2 (denominator 1 if q_s = 0).  Writes
+ * dL/dp into the loss-gradient buffer; `mean_loss` (nullable, synchronises)
+ * receives L. */
+pf_status pf_nn_loss(pf_nn *nn, const float *target, double *mean_loss);
+
+/* Gradients of the last forward pass for the output gradient dy (8 channels
+ * bf16; NULL: the loss-gradient buffer), into the gradient vector. */
+pf_status pf_nn_backward(pf_nn *nn, const void *dy);
+
+/* One Adam step (bias-corrected, Kingma and Ba 2015) on the gradient vector. */
+pf_status pf_nn_adam(pf_nn *nn, double lr, double b1, double b2, double eps);
+
+/* One convolution kernel alone (pf_nn_op), for layer 0..3 over n volumes:
+ *  FORWARD:          in = layer input (8 channels for layer 0, else 32) ->
+ *                    out = max(conv + b, 0) as 32 bf16 channels (layers 0-2)
+ *                    or conv + b as 4 FP32 channels (layer 3);
+ *  BACKWARD_DATA:    (layers 1-3) in = output gradient (8 channels for layer 3,
+ *                    else 32), aux = the layer's input (32 channels) ->
+ *                    out = input gradient where aux > 0, else 0 (32 bf16);
+ *  BACKWARD_WEIGHT:  in = layer input, aux = output gradient ->
+ *                    out = FP32 dW[27][cout][cin] followed by db[cout]
+ *                    (needs training buffers). */
+pf_status pf_nn_layer(pf_nn *nn, int op, int layer, const void *in, const void *aux, void *out, int n, int D, int H,
+                      int W);
+
+/* s = root mean square of u1 - u0 over the low faces of every cell (u0 may be
+ * NULL: zero).  u1, u0 are 3 device FP64 arrays in the exchange layout of
+ * pf_fields.  Kept for pf_nn_pack; `s_out` (nullable, synchronises). */
+pf_status pf_nn_increment_scale(pf_nn *nn, const double *const *u1, const double *const *u0, int nx, int ny, int nz,
+                                double *s_out);
+
+/* Pack the crop [x0, x0+cx) x [y0, y0+cy) x [z0, z0+cz) of a state into volume
+ * `slot` of the input buffer (voxels outside the grid get zero), with the
+ * scale of the last pf_nn_increment_scale: previous increment u1 - u0; when u2
+ * is given also the target (u2 - u1) / s into the target buffer.  Device FP64
+ * arrays in the exchange layout of pf_fields. */
+pf_status pf_nn_pack(pf_nn *nn, const double *phi_f, const double *phi_w, const double *phi_prev,
+                     const double *const *u1, const double *const *u0, const double *const *u2, int nx, int ny, int nz,
+                     int x0, int y0, int z0, int cx, int cy, int cz, int slot, double Omega, double h);
+
+/* Attach a network to a context created with warm == PF_WARM_LEARNED (3D,
+ * grid within the network's capacity); NULL detaches.  The context does not
+ * own the network.  From the second solve on, each solve packs the state,
+ * runs the network, evaluates ||b - A u0|| for the learned and the previous
+ * start and starts CG from the smaller; stats report both. */
+pf_status pf_nn_attach(pf_ctx *ctx, pf_nn *nn);
 
 /* Free the host-side context (never the caller's workspace). */
 void pf_destroy(pf_ctx *ctx);

@@ -38,6 +38,7 @@ struct Layout {
   size_t o_fld[2][5], o_u[3], o_epsp, o_epsP, o_mu, o_K, o_G;
   size_t o_r[3], o_z[3], o_pa[3], o_pb[3], o_q[3], o_di[3];
   size_t o_scal, o_part_u, o_part_a, o_part_b, o_part_c, o_stage;
+  size_t o_uo[3], o_du[3], o_phiprev;   // learned start only
   size_t total;
 };
 
@@ -49,7 +50,8 @@ bool valid_cfg(const pf_config* c, char* msg, size_t len) {
   if (!(c->h > 0.0) || !(c->dt > 0.0)) { snprintf(msg, len, "h and dt must be positive"); return false; }
   if (c->precision != PF_FP64 && c->precision != PF_MIXED) { snprintf(msg, len, "unknown precision %d", c->precision); return false; }
   if (c->mechanics && (!(c->cg_rtol > 0.0) || c->cg_max_iter < 1)) { snprintf(msg, len, "cg_rtol > 0 and cg_max_iter >= 1 required"); return false; }
-  if (c->warm != PF_WARM_ZERO && c->warm != PF_WARM_PREV) { snprintf(msg, len, "unknown warm start %d", c->warm); return false; }
+  if (c->warm != PF_WARM_ZERO && c->warm != PF_WARM_PREV && c->warm != PF_WARM_LEARNED) { snprintf(msg, len, "unknown warm start %d", c->warm); return false; }
+  if (c->warm == PF_WARM_LEARNED && (c->dim != 3 || !c->mechanics)) { snprintf(msg, len, "the learned warm start needs dim 3 and mechanics"); return false; }
   long long px = (c->nx + 15) / 16 * 16;
   if (px * c->ny * (long long)c->nz >= (1LL << 31) / 8) { snprintf(msg, len, "grid too large for 32-bit indexing"); return false; }
   return true;
@@ -114,6 +116,10 @@ Layout make_layout(const pf_config* c) {
   L.o_part_b = take(2 * (size_t)nbmax * sizeof(double));
   L.o_part_c = take(NQ_STEP * (size_t)nbmax * sizeof(double));
   L.o_stage = take(L.stage_elems * sizeof(double));
+  if (c->warm == PF_WARM_LEARNED) {
+    for (int d = 0; d < 3; ++d) { L.o_uo[d] = take(arr); L.o_du[d] = take(arr); }
+    L.o_phiprev = take(arr);
+  }
   L.total = off;
   return L;
 }
@@ -162,6 +168,10 @@ struct pf_ctx {
   int ev_next;
   double t_ms[PF_K_COUNT];
   long long t_n[PF_K_COUNT];
+  // learned start
+  pf_nn* net;
+  bool have_prev_incr;
+  double r0_learned, r0_prev;
   template <typename T> T* arr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   double* scal() const { return arr<double>(L.o_scal); }
 };
@@ -220,6 +230,10 @@ static void timed(pf_ctx* c, int kind, F&& launch, int cg_launch = -1) {
   (void)hipEventRecord(c->ev_pool[i + 1], c->stream);
   c->pending.push_back({kind, i, cg_launch});
 }
+
+// learned start (defined with the network code at the end of this file)
+template <typename T, int DIM> static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part);
+template <typename T, int DIM> static pf_status learned_after_solve(pf_ctx* c);
 
 // ---------------------------------------------------------------------------
 // typed implementation
@@ -294,6 +308,10 @@ struct Impl {
     // ||b||^2
     e.part = part_b;
     timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_BNORM>), L.gel, dim3(NT), 0, st, e); });
+    if (warm == PF_WARM_LEARNED) {
+      pf_status s = learned_start<T, DIM>(c, e, part_a);
+      if (s != PF_OK) return s;
+    }
     // r = b - A u, D^-1, z, and the partials of r.z and r.r
     ElastArgs<T> r = e;
     for (int d = 0; d < DIM; ++d) {
@@ -382,6 +400,7 @@ struct Impl {
     LAUNCHCHK(c);
     if (!conv)
       return fail(c, PF_ERR_CG_NOT_CONVERGED, "CG did not reach rtol %.3g in %d iterations", c->cfg.cg_rtol, maxit);
+    if (warm == PF_WARM_LEARNED) return learned_after_solve<T, DIM>(c);
     return PF_OK;
   }
 
@@ -439,6 +458,8 @@ static void fill_stats(pf_ctx* c, pf_step_stats* s) {
   s->step = c->steps;
   s->nonfinite = (int)h[S_NONFIN];
   s->cg_iters_total = c->iters_total;
+  s->r0_learned = c->r0_learned;
+  s->r0_prev = c->r0_prev;
 }
 
 // ---------------------------------------------------------------------------
@@ -482,6 +503,10 @@ pf_status pf_init(const pf_config* cfg, const pf_params* params, void* workspace
   c->timing = false;
   c->ev_next = 0;
   c->iters_total = 0;
+  c->net = nullptr;
+  c->have_prev_incr = false;
+  c->r0_learned = 0.0;
+  c->r0_prev = 0.0;
   for (int k = 0; k < PF_K_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host_scal), S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete c;
@@ -526,7 +551,10 @@ pf_status pf_step(pf_ctx* c, int nsteps, pf_step_stats* last) {
 pf_status pf_mech_solve(pf_ctx* c, int warm, pf_step_stats* stats) {
   if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
   if (c->bad) return fail(c, PF_ERR_BAD_STATE, "context failed earlier; set the fields to restore it");
-  if (warm != PF_WARM_ZERO && warm != PF_WARM_PREV) return fail(c, PF_ERR_INVALID_ARG, "unknown warm start %d", warm);
+  if (warm != PF_WARM_ZERO && warm != PF_WARM_PREV && warm != PF_WARM_LEARNED)
+    return fail(c, PF_ERR_INVALID_ARG, "unknown warm start %d", warm);
+  if (warm == PF_WARM_LEARNED && c->cfg.warm != PF_WARM_LEARNED)
+    return fail(c, PF_ERR_INVALID_ARG, "the context was not created with the learned warm start");
   if (!c->cfg.mechanics) return fail(c, PF_ERR_INVALID_ARG, "mechanics is off in this context");
   pf_status st = dispatch(c, [&](auto impl) { return decltype(impl)::solve(c, warm); });
   HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal(), S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -592,6 +620,7 @@ pf_status pf_fields(pf_ctx* c, int field_id, int dir, void* ptr, size_t nbytes, 
   }
   if (dir == 1) {
     c->bad = false;
+    c->have_prev_incr = false;
     if (field_id <= PF_FIELD_XW) c->ledger_valid = false;
   }
   if (dir == 0 || !ptr_is_device) HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -636,3 +665,4 @@ void pf_destroy(pf_ctx* c) {
 }  // extern "C"
 
 #include "pf_batch_api.h"
+#include "pf_nn_api.h"

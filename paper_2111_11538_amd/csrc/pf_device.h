@@ -25,6 +25,8 @@ enum Scal {
   S_O0 = 10, S_H0 = 11, S_XO0 = 12, S_OOUT = 13, S_HOUT = 14,
   // last-step statistics
   S_OTOT = 16, S_HTOT = 17, S_XOSUM = 18, S_MAXVM = 19, S_MAXEP = 20, S_NONFIN = 21,
+  // learned start: ||b - A u0||^2 of the learned and of the previous start
+  S_JL = 22, S_JP = 23, S_JB = 24,
   S_COUNT = 32
 };
 

@@ -1,0 +1,472 @@
+// Device kernels of the learned warm start: a stack of 3x3x3 'same'
+// convolutions (zero padding, ReLU between layers, linear output) on the
+// gfx950 matrix cores (v_mfma_f32_16x16x32_bf16: bf16 operands, fp32
+// accumulation), its backward passes, the relative mean-square loss, Adam,
+// and the packing between the simulation state and the network.
+//
+// Tensors are channel-last bf16: voxel v of n volumes of D x H x W voxels,
+// channel c at v * C + c.  Layer l maps C_in to C_out channels with weights
+// W[t][co][ci], t = 9 (dz + 1) + 3 (dy + 1) + (dx + 1) reading voxel
+// (z + dz, y + dy, x + dx).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pf_device.h"
+
+namespace pfn {
+
+using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
+using f32x4 = float __attribute__((ext_vector_type(4)));
+
+constexpr int CNT = 256;       // threads per block (4 waves)
+constexpr int SEG = 64;        // voxels per wave along x in the convolutions (4 column blocks of 16)
+constexpr int NBW = SEG / 16;
+constexpr int kTaps = 27;
+
+struct Vol {
+  int n, D, H, W;              // n volumes of D x H x W voxels
+};
+
+__device__ __forceinline__ uint16_t f2bf(float f) {     // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ bool bf_pos(uint32_t h) { return (h & 0x8000u) == 0u && (h & 0x7FFFu) != 0u; }
+__device__ __forceinline__ bf16x8 as_bf8(uint4 v) {
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+__device__ __forceinline__ uint32_t pack2(float a, float b) { return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16); }
+
+__device__ __forceinline__ void tap_offset(int t, int& dz, int& dy, int& dx) {
+  dz = t / 9 - 1;
+  dy = (t / 3) % 3 - 1;
+  dx = t % 3 - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Convolution as an implicit GEMM: out^T (co x voxels) = W (co x k) * in (k x voxels),
+// k = t * CIN + ci.  The weights arrive as an image in MFMA operand order: for
+// output block mb and 32-wide k chunk kc, lane l holds the 8 values
+// W(co = 16 mb + l % 16, k = 32 kc + 8 (l / 16) + j), j = 0..7; entries past
+// the real channel counts or past tap 26 are zero.  One wave computes 64
+// consecutive voxels of one row for all output channels.
+//   EPI_RELU:   out (bf16, 16 MB channels) = max(acc + bias, 0)
+//   EPI_LINEAR: out (fp32, 4 channels)     = acc + bias, channels 0..3 of block 0
+//   EPI_MASK:   out (bf16, 16 MB channels) = acc where mask > 0, else 0
+// ---------------------------------------------------------------------------
+enum Epi { EPI_RELU = 0, EPI_LINEAR = 1, EPI_MASK = 2 };
+
+template <int CIN>
+constexpr int k_chunks() { return (kTaps * CIN + 31) / 32; }
+
+template <int CIN, int MB, int EPI>
+__global__ __launch_bounds__(CNT) void k_conv(const uint4* __restrict__ wimg, const float* __restrict__ bias,
+                                              const uint16_t* __restrict__ x, void* __restrict__ out,
+                                              const uint16_t* __restrict__ mask, Vol v) {
+  constexpr int KC = k_chunks<CIN>();
+  constexpr int COUT = MB * 16;
+  extern __shared__ uint4 sW[];
+  for (int i = threadIdx.x; i < MB * KC * 64; i += CNT) sW[i] = wimg[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int nseg = (v.W + SEG - 1) / SEG, nyt = (v.H + 3) / 4;
+  const long ntiles = (long)nseg * nyt * v.D * v.n;
+  for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int xs = (int)(t % nseg);
+    long r = t / nseg;
+    const int y = (int)(r % nyt) * 4 + wv;
+    r /= nyt;
+    const int z = (int)(r % v.D);
+    const int n = (int)(r / v.D);
+    if (y >= v.H) continue;                     // whole wave; no block barrier follows
+    f32x4 acc[MB][NBW];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < KC; ++kc) {
+      const int k0 = kc * 32 + lg * 8;
+      const int tap = k0 / CIN, ci0 = k0 % CIN;
+      int dz, dy, dx;
+      tap_offset(tap, dz, dy, dx);
+      const int zz = z + dz, yy = y + dy;
+      const bool rok = tap < kTaps && zz >= 0 && zz < v.D && yy >= 0 && yy < v.H;
+      const uint16_t* row = x + ((((long)n * v.D + zz) * v.H + yy) * v.W) * CIN + ci0;
+      bf16x8 b[NBW];
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        const int xx = xs * SEG + nb * 16 + lr + dx;
+        uint4 q = {0u, 0u, 0u, 0u};
+        if (rok && xx >= 0 && xx < v.W) q = *reinterpret_cast<const uint4*>(row + (long)xx * CIN);
+        b[nb] = as_bf8(q);
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const bf16x8 a = as_bf8(sW[(mb * KC + kc) * 64 + lane]);
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[mb][nb], 0, 0, 0);
+      }
+    }
+    // lane holds out(co = 16 mb + 4 lg + i, voxel = 16 nb + lr)
+    const long vrow = (((long)n * v.D + z) * v.H + y) * v.W;
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) {
+      const int xx = xs * SEG + nb * 16 + lr;
+      if (xx >= v.W) continue;
+      const long vox = vrow + xx;
+      if constexpr (EPI == EPI_LINEAR) {
+        if (lg == 0) {
+          float4 o;
+          o.x = acc[0][nb][0] + bias[0];
+          o.y = acc[0][nb][1] + bias[1];
+          o.z = acc[0][nb][2] + bias[2];
+          o.w = acc[0][nb][3] + bias[3];
+          reinterpret_cast<float4*>(out)[vox] = o;
+        }
+      } else {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const int co0 = mb * 16 + lg * 4;
+          float o[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) o[i] = acc[mb][nb][i];
+          if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[i] = fmaxf(o[i] + bias[co0 + i], 0.f);
+          } else {
+            const uint2 mk = *reinterpret_cast<const uint2*>(mask + vox * COUT + co0);
+            if (!bf_pos(mk.x & 0xFFFFu)) o[0] = 0.f;
+            if (!bf_pos(mk.x >> 16)) o[1] = 0.f;
+            if (!bf_pos(mk.y & 0xFFFFu)) o[2] = 0.f;
+            if (!bf_pos(mk.y >> 16)) o[3] = 0.f;
+          }
+          uint2 st;
+          st.x = pack2(o[0], o[1]);
+          st.y = pack2(o[2], o[3]);
+          *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + vox * COUT + co0) = st;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[t][co][ci] = sum_v dy(v, co) x(v + d(t), ci).  Grid
+// (nsplit, 27): block (s, t) contracts its share of voxel rows for tap t on
+// MFMA with M = output channel, N = input channel and K = 32 voxels along x,
+// then reduces its 4 waves in a fixed order and writes one partial
+// part[s][t][COUTP][CINP].  dy holds CG channels (CG <= COUTP), x holds CIN.
+// ---------------------------------------------------------------------------
+template <int CIN, int CG, int MB>
+__global__ __launch_bounds__(CNT) void k_conv_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy,
+                                                    float* __restrict__ part, Vol v) {
+  constexpr int NB = (CIN + 15) / 16;
+  constexpr int COUTP = MB * 16, CINP = NB * 16;
+  constexpr int NACC = MB * NB * 4;
+  __shared__ float red[4][NACC][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int tap = blockIdx.y;
+  int dz, dyo, dx;
+  tap_offset(tap, dz, dyo, dx);
+  const long rows = (long)v.n * v.D * v.H;
+  const long r0 = rows * blockIdx.x / gridDim.x, r1 = rows * (blockIdx.x + 1) / gridDim.x;
+  f32x4 acc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (long r = r0 + wv; r < r1; r += 4) {
+    const int y = (int)(r % v.H);
+    const long q = r / v.H;
+    const int z = (int)(q % v.D);
+    const int n = (int)(q / v.D);
+    const int zz = z + dz, yy = y + dyo;
+    const bool rok = zz >= 0 && zz < v.D && yy >= 0 && yy < v.H;
+    const uint16_t* grow = dy + r * v.W * CG;
+    const uint16_t* xrow = x + ((((long)n * v.D + zz) * v.H + yy) * v.W) * CIN;
+    for (int xs = 0; xs < v.W; xs += 32) {
+      bf16x8 a[MB], b[NB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int co = mb * 16 + lr;
+        uint16_t h[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int xv = xs + 8 * lg + j;
+          h[j] = (co < CG && xv < v.W) ? grow[(long)xv * CG + co] : (uint16_t)0;
+        }
+        __builtin_memcpy(&a[mb], h, 16);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int ci = nb * 16 + lr;
+        uint16_t h[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int xv = xs + 8 * lg + j + dx;
+          h[j] = (rok && ci < CIN && xv >= 0 && xv < v.W && xs + 8 * lg + j < v.W) ? xrow[(long)xv * CIN + ci] : (uint16_t)0;
+        }
+        __builtin_memcpy(&b[nb], h, 16);
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[wv][(mb * NB + nb) * 4 + i][lane] = acc[mb][nb][i];
+  __syncthreads();
+  float* dst = part + ((long)blockIdx.x * kTaps + tap) * COUTP * CINP;
+  for (int e = threadIdx.x; e < NACC * 64; e += CNT) {
+    const int slot = e / 64, l = e % 64;
+    const float s = ((red[0][slot][l] + red[1][slot][l]) + red[2][slot][l]) + red[3][slot][l];
+    const int mb = slot / (NB * 4), nb = (slot / 4) % NB, i = slot % 4;
+    const int co = mb * 16 + 4 * (l >> 4) + i, ci = nb * 16 + (l & 15);
+    dst[co * CINP + ci] = s;
+  }
+}
+
+// Sum of the weight-gradient partials over splits in a fixed order (FP64),
+// written in the canonical layout W[t][co][ci] of the real channel counts.
+__global__ __launch_bounds__(CNT) void k_wgrad_reduce(const float* __restrict__ part, int nsplit, int coutp, int cinp,
+                                                      int cout, int cin, float* __restrict__ grad) {
+  const int n = kTaps * cout * cin;
+  for (int e = blockIdx.x * CNT + threadIdx.x; e < n; e += gridDim.x * CNT) {
+    const int t = e / (cout * cin), co = (e / cin) % cout, ci = e % cin;
+    const long off = ((long)t * coutp + co) * cinp + ci;
+    double s = 0.0;
+    for (int q = 0; q < nsplit; ++q) s += (double)part[(long)q * kTaps * coutp * cinp + off];
+    grad[e] = (float)s;
+  }
+}
+
+// Bias gradient: db[c] = sum_v dy(v, c); block s sums its voxel range per
+// channel (FP64), the reduction over blocks is done by k_bgrad_reduce.
+__global__ __launch_bounds__(CNT) void k_bgrad_part(const uint16_t* __restrict__ dy, int cg, long nvox, double* __restrict__ part) {
+  __shared__ double sh[CNT];
+  const long v0 = nvox * blockIdx.x / gridDim.x, v1 = nvox * (blockIdx.x + 1) / gridDim.x;
+  const int per = CNT / cg;                    // threads per channel (cg divides 256)
+  const int c = threadIdx.x % cg, sub = threadIdx.x / cg;
+  double s = 0.0;
+  if (sub < per)
+    for (long vv = v0 + sub; vv < v1; vv += per) s += (double)bf2f(dy[vv * cg + c]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < cg) {
+    double t = 0.0;
+    for (int q = 0; q < per; ++q) t += sh[q * cg + threadIdx.x];
+    part[(long)blockIdx.x * cg + threadIdx.x] = t;
+  }
+}
+__global__ void k_bgrad_reduce(const double* __restrict__ part, int nblk, int cg, int cout, float* __restrict__ grad) {
+  const int c = threadIdx.x;
+  if (c >= cout) return;
+  double s = 0.0;
+  for (int q = 0; q < nblk; ++q) s += part[(long)q * cg + c];
+  grad[c] = (float)s;
+}
+
+// ---------------------------------------------------------------------------
+// Parameters: one FP32 vector, per layer W[t][co][ci] then b[co].  Adam with
+// bias correction; c1 = lr / (1 - b1^t), c2 = 1 / (1 - b2^t).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CNT) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ vv, int n, float b1, float b2, float eps, float c1,
+                                              float c2) {
+  for (int e = blockIdx.x * CNT + threadIdx.x; e < n; e += gridDim.x * CNT) {
+    const float gi = g[e];
+    const float mi = b1 * m[e] + (1.f - b1) * gi;
+    const float vi = b2 * vv[e] + (1.f - b2) * gi * gi;
+    m[e] = mi;
+    vv[e] = vi;
+    p[e] -= c1 * mi / (sqrtf(vi * c2) + eps);
+  }
+}
+
+// Operand images of one layer from the parameter vector.
+//   fwd: out channel co = 16 mb + l%16, k = t * cinp + ci            (MB = coutp/16 blocks, cinp in {8, 32})
+//   bwd: out channel ci = 16 mb + l%16, k = t' * coutq + co, weight W[26 - t'][co][ci]
+//        (the transposed, flipped kernel that maps output gradients to input gradients)
+__global__ __launch_bounds__(CNT) void k_pack_image(const float* __restrict__ W, int cout, int cin, int mblocks,
+                                                    int kin, int backward, uint16_t* __restrict__ img) {
+  const int kc_n = (kTaps * kin + 31) / 32;
+  const int n = mblocks * kc_n * 64 * 8;
+  for (int e = blockIdx.x * CNT + threadIdx.x; e < n; e += gridDim.x * CNT) {
+    const int j = e % 8, l = (e / 8) % 64, kc = (e / 512) % kc_n, mb = e / (512 * kc_n);
+    const int row = mb * 16 + (l & 15);
+    const int k = kc * 32 + 8 * (l >> 4) + j;
+    const int t = k / kin, col = k % kin;
+    float w = 0.f;
+    if (t < kTaps) {
+      if (!backward) {
+        if (row < cout && col < cin) w = W[((long)t * cout + row) * cin + col];
+      } else {
+        if (row < cin && col < cout) w = W[((long)(kTaps - 1 - t) * cout + col) * cin + row];
+      }
+    }
+    img[e] = f2bf(w);
+  }
+}
+__global__ void k_pack_bias(const float* __restrict__ b, int cout, int coutp, float* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c < coutp) out[c] = c < cout ? b[c] : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Relative mean-square loss over samples of V voxels: L = (1/n) sum_s
+// |p_s - q_s|^2 / |q_s|^2 (denominator 1 if q_s = 0); prediction and target
+// hold 4 channels per voxel of which the first 3 count.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CNT) void k_loss_part(const float* __restrict__ p, const float* __restrict__ q, long V,
+                                                   double* __restrict__ part) {
+  __shared__ double red[CNT / 64];
+  const int s = blockIdx.y;
+  const long v0 = V * blockIdx.x / gridDim.x, v1 = V * (blockIdx.x + 1) / gridDim.x;
+  double a = 0.0, b = 0.0;
+  for (long v = v0 + threadIdx.x; v < v1; v += CNT) {
+    const float4 pv = reinterpret_cast<const float4*>(p)[s * V + v];
+    const float4 qv = reinterpret_cast<const float4*>(q)[s * V + v];
+    const double d0 = (double)pv.x - qv.x, d1 = (double)pv.y - qv.y, d2 = (double)pv.z - qv.z;
+    a += d0 * d0 + d1 * d1 + d2 * d2;
+    b += (double)qv.x * qv.x + (double)qv.y * qv.y + (double)qv.z * qv.z;
+  }
+  a = pfk::block_sum(a, red);
+  b = pfk::block_sum(b, red);
+  if (threadIdx.x == 0) {
+    part[((long)s * gridDim.x + blockIdx.x) * 2] = a;
+    part[((long)s * gridDim.x + blockIdx.x) * 2 + 1] = b;
+  }
+}
+// dL/dp as bf16 with 8 channels (3 used); sample losses to loss[s].
+__global__ __launch_bounds__(CNT) void k_loss_grad(const float* __restrict__ p, const float* __restrict__ q, long V,
+                                                   const double* __restrict__ part, int nblk, int nsamp,
+                                                   uint16_t* __restrict__ g, double* __restrict__ loss) {
+  __shared__ double red[CNT / 64];
+  const int s = blockIdx.y;
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += CNT) {
+    a += part[((long)s * nblk + k) * 2];
+    b += part[((long)s * nblk + k) * 2 + 1];
+  }
+  a = pfk::block_sum(a, red);
+  b = pfk::block_sum(b, red);
+  const double den = b > 0.0 ? b : 1.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) loss[s] = a / den;
+  const float sc = (float)(2.0 / (den * nsamp));
+  const long v0 = V * blockIdx.x / gridDim.x, v1 = V * (blockIdx.x + 1) / gridDim.x;
+  for (long v = v0 + threadIdx.x; v < v1; v += CNT) {
+    const float4 pv = reinterpret_cast<const float4*>(p)[s * V + v];
+    const float4 qv = reinterpret_cast<const float4*>(q)[s * V + v];
+    uint4 o;
+    o.x = pack2(sc * (pv.x - qv.x), sc * (pv.y - qv.y));
+    o.y = pack2(sc * (pv.z - qv.z), 0.f);
+    o.z = 0u;
+    o.w = 0u;
+    reinterpret_cast<uint4*>(g)[s * V + v] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packing between the simulation state and the network (3D).
+// A strided view of a cell or face array: element (i, j, k) at k*ps + j*rs + i.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct View {
+  const T* p;
+  long rs, ps;
+  __device__ __forceinline__ double at(int i, int j, int k) const { return (double)p[(long)k * ps + (long)j * rs + i]; }
+};
+
+template <typename T>
+struct PackArgs {
+  View<T> phi_f, phi_w, phi_prev;
+  View<T> u1[3], u0[3];        // previous increment = u1 - u0 (u0 may be null: zero)
+  View<T> u2[3];               // current state for targets (u2 - u1), null when no target is wanted
+  int nx, ny, nz;              // full grid
+  int x0, y0, z0;              // crop origin
+  int cx, cy, cz;              // crop size
+  double Omega, h;
+  const double* s;             // device scalar: increment scale
+  uint16_t* x;                 // out: [cz][cy][cx][8] bf16
+  float* target;               // out (nullable): [cz][cy][cx][4] fp32
+};
+
+__device__ __forceinline__ double eigen_strain_d(double pf, double Omega) {
+  const double hf = pf * pf * pf * (pf * (6.0 * pf - 15.0) + 10.0);
+  return cbrt(1.0 - Omega * hf) - 1.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(CNT) void k_pack_inputs(PackArgs<T> a) {
+  const double s = *a.s;
+  const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  const long nv = (long)a.cx * a.cy * a.cz;
+  for (long v = blockIdx.x * (long)CNT + threadIdx.x; v < nv; v += (long)gridDim.x * CNT) {
+    const int li = (int)(v % a.cx), lj = (int)((v / a.cx) % a.cy), lk = (int)(v / ((long)a.cx * a.cy));
+    const int i = a.x0 + li, j = a.y0 + lj, k = a.z0 + lk;
+    float c[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float tg[4] = {0.f, 0.f, 0.f, 0.f};
+    if (i < a.nx && j < a.ny && k < a.nz) {
+      const double pf = a.phi_f.at(i, j, k);
+      c[0] = (float)pf;
+      c[1] = (float)a.phi_w.at(i, j, k);
+      c[2] = (float)((eigen_strain_d(pf, a.Omega) - eigen_strain_d(a.phi_prev.at(i, j, k), a.Omega)) *
+                     (32.0 * a.h * inv));
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double u1 = a.u1[d].at(i, j, k);
+        const double u0 = a.u0[d].p ? a.u0[d].at(i, j, k) : 0.0;
+        c[3 + d] = (float)((u1 - u0) * inv);
+        if (a.target) tg[d] = (float)((a.u2[d].at(i, j, k) - u1) * inv);
+      }
+    }
+    uint4 o;
+    o.x = pack2(c[0], c[1]);
+    o.y = pack2(c[2], c[3]);
+    o.z = pack2(c[4], c[5]);
+    o.w = pack2(c[6], c[7]);
+    reinterpret_cast<uint4*>(a.x)[v] = o;
+    if (a.target) reinterpret_cast<float4*>(a.target)[v] = make_float4(tg[0], tg[1], tg[2], 0.f);
+  }
+}
+
+// Partials of sum over all stored faces of (u1 - u0)^2 (FP64) and the count.
+template <typename T>
+__global__ __launch_bounds__(CNT) void k_incr_sumsq(PackArgs<T> a, double* __restrict__ part) {
+  __shared__ double red[CNT / 64];
+  const long nv = (long)a.nx * a.ny * a.nz;
+  double s = 0.0;
+  for (long v = blockIdx.x * (long)CNT + threadIdx.x; v < nv; v += (long)gridDim.x * CNT) {
+    const int i = (int)(v % a.nx), j = (int)((v / a.nx) % a.ny), k = (int)(v / ((long)a.nx * a.ny));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double du = a.u1[d].at(i, j, k) - (a.u0[d].p ? a.u0[d].at(i, j, k) : 0.0);
+      s += du * du;
+    }
+  }
+  s = pfk::block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+// s = sqrt(sum / count), count = 3 * cells (the low faces of every cell).
+__global__ __launch_bounds__(CNT) void k_incr_scale(const double* __restrict__ part, int n, double count, double* __restrict__ s) {
+  __shared__ double red[CNT / 64];
+  double v = 0.0;
+  for (int q = threadIdx.x; q < n; q += CNT) v += part[q];
+  v = pfk::block_sum(v, red);
+  if (threadIdx.x == 0) *s = sqrt(v / count);
+}
+
+}  // namespace pfn

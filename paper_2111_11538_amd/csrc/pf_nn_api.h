@@ -1,0 +1,645 @@
+// Host side of the learned warm start (pf_nn_* in include/pf.h) and its use
+// inside a context's solve.  Included at the end of pf_api.hip.
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+
+#include "pf_nn.h"
+
+using pfn::Vol;
+
+namespace {
+
+// The network: 6 -> 32 -> 32 -> 32 -> 3 channels, 3x3x3 kernels.
+struct LayerDef {
+  int cin, cout;
+  int cinp;     // input channels as stored (8 or 32)
+  int mb;       // 16-row blocks of output channels in the forward image
+  int kinb;     // input channels of the backward-data convolution (8 or 32; 0: not needed)
+};
+constexpr int kLayers = 4;
+constexpr LayerDef kDef[kLayers] = {{6, 32, 8, 2, 0}, {32, 32, 32, 2, 32}, {32, 32, 32, 2, 32}, {32, 3, 32, 1, 8}};
+constexpr int kWgradSplitMax = 96;
+constexpr int kBgradBlocks = 256;
+
+inline int kchunks(int cin) { return (pfn::kTaps * cin + 31) / 32; }
+
+size_t nn_param_count() {
+  size_t n = 0;
+  for (int l = 0; l < kLayers; ++l) n += (size_t)pfn::kTaps * kDef[l].cout * kDef[l].cin + kDef[l].cout;
+  return n;
+}
+
+uint64_t splitmix64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+struct pf_nn {
+  pf_nn_config cfg;
+  hipStream_t stream;
+  long long cap;                 // voxels
+  size_t np;
+  size_t off_w[kLayers], off_b[kLayers];
+  float *P, *G, *M, *V;          // parameters, gradients, Adam moments (FP32)
+  uint16_t* img_f[kLayers];
+  uint16_t* img_b[kLayers];
+  float* bias_p[kLayers];        // bias padded to 32
+  uint16_t* x0;                  // packed input [cap][8]
+  uint16_t* act[3];              // outputs of layers 0..2 [cap][32]
+  float* out;                    // network output [cap][4]
+  float* target;                 // packed targets [cap][4]
+  uint16_t* dpred;               // loss gradient [cap][8]
+  uint16_t* g[2];                // backward ping-pong [cap][32]
+  float* wpart;                  // weight-gradient partials
+  double* dpart;                 // FP64 partials (bias gradient, loss, scale)
+  double* dscal;                 // [0] increment scale, [1..] sample losses
+  int adam_t;
+  // last forward, for backward and loss
+  Vol last_v;
+  const uint16_t* last_x;
+  float* last_y;
+  bool have_fwd;
+  char err[512];
+};
+
+static char g_nn_err[512] = "";
+
+static pf_status nn_fail(pf_nn* n, pf_status s, const char* fmt, ...) {
+  char* dst = n ? n->err : g_nn_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define NNCHK(nn, call)                                                                           \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess) return nn_fail((nn), PF_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define NNLAUNCH(nn)                                                                                      \
+  do {                                                                                                    \
+    hipError_t e_ = hipGetLastError();                                                                    \
+    if (e_ != hipSuccess) return nn_fail((nn), PF_ERR_HIP, "kernel launch: %s", hipGetErrorString(e_));   \
+  } while (0)
+
+static long long vol_voxels(const Vol& v) { return (long long)v.n * v.D * v.H * v.W; }
+
+static pf_status nn_check_vol(pf_nn* nn, const Vol& v) {
+  if (v.n < 1 || v.D < 1 || v.H < 1 || v.W < 1) return nn_fail(nn, PF_ERR_INVALID_ARG, "volume sizes must be >= 1");
+  if (vol_voxels(v) > nn->cap)
+    return nn_fail(nn, PF_ERR_INVALID_ARG, "%lld voxels exceed the capacity %lld", vol_voxels(v), nn->cap);
+  return PF_OK;
+}
+
+static int conv_grid(const Vol& v, int cap) {
+  long long nt = (long long)((v.W + pfn::SEG - 1) / pfn::SEG) * ((v.H + 3) / 4) * v.D * v.n;
+  return (int)std::max(1LL, std::min(nt, (long long)cap));
+}
+
+// Forward convolution of layer l: x (cinp channels) -> y.
+static pf_status nn_conv_fwd(pf_nn* nn, int l, const uint16_t* x, void* y, const Vol& v, hipStream_t st) {
+  const LayerDef& d = kDef[l];
+  const size_t smem = (size_t)d.mb * kchunks(d.cinp) * 64 * 16;
+  const uint4* w = reinterpret_cast<const uint4*>(nn->img_f[l]);
+  if (l == 0)
+    hipLaunchKernelGGL((pfn::k_conv<8, 2, pfn::EPI_RELU>), dim3(conv_grid(v, 4096)), dim3(pfn::CNT), smem, st, w,
+                       (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
+  else if (l < 3)
+    hipLaunchKernelGGL((pfn::k_conv<32, 2, pfn::EPI_RELU>), dim3(conv_grid(v, 2048)), dim3(pfn::CNT), smem, st, w,
+                       (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
+  else
+    hipLaunchKernelGGL((pfn::k_conv<32, 1, pfn::EPI_LINEAR>), dim3(conv_grid(v, 4096)), dim3(pfn::CNT), smem, st, w,
+                       (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
+  NNLAUNCH(nn);
+  return PF_OK;
+}
+
+// Backward-data convolution of layer l (1..3): dy -> dx masked by (mask > 0).
+static pf_status nn_conv_bwd(pf_nn* nn, int l, const uint16_t* dy, const uint16_t* mask, uint16_t* dx, const Vol& v,
+                             hipStream_t st) {
+  const LayerDef& d = kDef[l];
+  const size_t smem = (size_t)2 * kchunks(d.kinb) * 64 * 16;
+  const uint4* w = reinterpret_cast<const uint4*>(nn->img_b[l]);
+  if (d.kinb == 8)
+    hipLaunchKernelGGL((pfn::k_conv<8, 2, pfn::EPI_MASK>), dim3(conv_grid(v, 4096)), dim3(pfn::CNT), smem, st, w,
+                       (const float*)nullptr, dy, (void*)dx, mask, v);
+  else
+    hipLaunchKernelGGL((pfn::k_conv<32, 2, pfn::EPI_MASK>), dim3(conv_grid(v, 2048)), dim3(pfn::CNT), smem, st, w,
+                       (const float*)nullptr, dy, (void*)dx, mask, v);
+  NNLAUNCH(nn);
+  return PF_OK;
+}
+
+// Weight and bias gradients of layer l from its input x and output gradient dy,
+// written to gw (27 * cout * cin) and gb (cout) in FP32.
+static pf_status nn_conv_wgrad(pf_nn* nn, int l, const uint16_t* x, const uint16_t* dy, float* gw, float* gb, const Vol& v,
+                               hipStream_t st) {
+  const LayerDef& d = kDef[l];
+  const long long rows = (long long)v.n * v.D * v.H;
+  const int nsplit = (int)std::max(1LL, std::min(rows, (long long)kWgradSplitMax));
+  const dim3 grid(nsplit, pfn::kTaps);
+  const int cg = l == 3 ? 8 : 32;
+  const int coutp = l == 3 ? 16 : 32;
+  if (l == 0)
+    hipLaunchKernelGGL((pfn::k_conv_wgrad<8, 32, 2>), grid, dim3(pfn::CNT), 0, st, x, dy, nn->wpart, v);
+  else if (l < 3)
+    hipLaunchKernelGGL((pfn::k_conv_wgrad<32, 32, 2>), grid, dim3(pfn::CNT), 0, st, x, dy, nn->wpart, v);
+  else
+    hipLaunchKernelGGL((pfn::k_conv_wgrad<32, 8, 1>), grid, dim3(pfn::CNT), 0, st, x, dy, nn->wpart, v);
+  NNLAUNCH(nn);
+  const int cinp = d.cinp == 8 ? 16 : 32;
+  const int nw = pfn::kTaps * d.cout * d.cin;
+  hipLaunchKernelGGL(pfn::k_wgrad_reduce, dim3((nw + pfn::CNT - 1) / pfn::CNT), dim3(pfn::CNT), 0, st,
+                     (const float*)nn->wpart, nsplit, coutp, cinp, d.cout, d.cin, gw);
+  const long long nvox = vol_voxels(v);
+  hipLaunchKernelGGL(pfn::k_bgrad_part, dim3(kBgradBlocks), dim3(pfn::CNT), 0, st, dy, cg, (long)nvox, nn->dpart);
+  hipLaunchKernelGGL(pfn::k_bgrad_reduce, dim3(1), dim3(64), 0, st, (const double*)nn->dpart, kBgradBlocks, cg, d.cout, gb);
+  NNLAUNCH(nn);
+  return PF_OK;
+}
+
+static pf_status nn_repack(pf_nn* nn, hipStream_t st) {
+  for (int l = 0; l < kLayers; ++l) {
+    const LayerDef& d = kDef[l];
+    const float* W = nn->P + nn->off_w[l];
+    int n = d.mb * kchunks(d.cinp) * 512;
+    hipLaunchKernelGGL(pfn::k_pack_image, dim3((n + pfn::CNT - 1) / pfn::CNT), dim3(pfn::CNT), 0, st, W, d.cout, d.cin,
+                       d.mb, d.cinp, 0, nn->img_f[l]);
+    if (d.kinb) {
+      n = 2 * kchunks(d.kinb) * 512;
+      hipLaunchKernelGGL(pfn::k_pack_image, dim3((n + pfn::CNT - 1) / pfn::CNT), dim3(pfn::CNT), 0, st, W, d.cout,
+                         d.cin, 2, d.kinb, 1, nn->img_b[l]);
+    }
+    hipLaunchKernelGGL(pfn::k_pack_bias, dim3(1), dim3(32), 0, st, (const float*)(nn->P + nn->off_b[l]), d.cout, 32,
+                       nn->bias_p[l]);
+  }
+  NNLAUNCH(nn);
+  return PF_OK;
+}
+
+static pf_status nn_forward(pf_nn* nn, const uint16_t* x, float* y, const Vol& v, hipStream_t st) {
+  pf_status s;
+  if ((s = nn_check_vol(nn, v)) != PF_OK) return s;
+  if ((s = nn_conv_fwd(nn, 0, x, nn->act[0], v, st)) != PF_OK) return s;
+  if ((s = nn_conv_fwd(nn, 1, nn->act[0], nn->act[1], v, st)) != PF_OK) return s;
+  if ((s = nn_conv_fwd(nn, 2, nn->act[1], nn->act[2], v, st)) != PF_OK) return s;
+  if ((s = nn_conv_fwd(nn, 3, nn->act[2], y, v, st)) != PF_OK) return s;
+  nn->last_v = v;
+  nn->last_x = x;
+  nn->last_y = y;
+  nn->have_fwd = true;
+  return PF_OK;
+}
+
+// Views of the exchange-format arrays (compact FP64, x fastest): cells
+// [nz][ny][nx], faces u_x [nz][ny][nx+1], u_y [nz][ny+1][nx], u_z [nz+1][ny][nx].
+static pfn::View<double> xview_cell(const double* p, int nx, int ny) { return {p, nx, (long)nx * ny}; }
+static pfn::View<double> xview_face(const double* p, int c, int nx, int ny) {
+  if (c == 0) return {p, nx + 1, (long)(nx + 1) * ny};
+  if (c == 1) return {p, nx, (long)nx * (ny + 1)};
+  return {p, nx, (long)nx * ny};
+}
+
+// ---------------------------------------------------------------------------
+// Learned start inside a context's solve (3D).  The context holds, when its
+// warm start is PF_WARM_LEARNED, the displacement before the solve (uo), the
+// increment of the previous solve (du) and the ferrite phase of the previous
+// solve (phi_prev).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(pfn::CNT) void k_learned_start(T* __restrict__ u0, T* __restrict__ u1, T* __restrict__ u2,
+                                                           const T* __restrict__ o0, const T* __restrict__ o1,
+                                                           const T* __restrict__ o2, const float* __restrict__ y,
+                                                           const double* __restrict__ s, Grid g) {
+  const double sc = *s;
+  const long nv = (long)g.nx * g.ny * g.nz;
+  for (long v = blockIdx.x * (long)pfn::CNT + threadIdx.x; v < nv; v += (long)gridDim.x * pfn::CNT) {
+    const int i = (int)(v % g.nx), j = (int)((v / g.nx) % g.ny), k = (int)(v / ((long)g.nx * g.ny));
+    const long e = ((long)k * g.ny + j) * g.px + i;
+    const float4 o = reinterpret_cast<const float4*>(y)[v];
+    u0[e] = i > 0 ? (T)((double)o0[e] + sc * o.x) : o0[e];
+    u1[e] = j > 0 ? (T)((double)o1[e] + sc * o.y) : o1[e];
+    u2[e] = k > 0 ? (T)((double)o2[e] + sc * o.z) : o2[e];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(pfn::CNT) void k_after_solve(const T* __restrict__ u0, const T* __restrict__ u1,
+                                                         const T* __restrict__ u2, const T* __restrict__ o0,
+                                                         const T* __restrict__ o1, const T* __restrict__ o2,
+                                                         T* __restrict__ d0, T* __restrict__ d1, T* __restrict__ d2,
+                                                         const T* __restrict__ phi, T* __restrict__ phi_prev, long n) {
+  for (long e = blockIdx.x * (long)pfn::CNT + threadIdx.x; e < n; e += (long)gridDim.x * pfn::CNT) {
+    d0[e] = u0[e] - o0[e];
+    d1[e] = u1[e] - o1[e];
+    d2[e] = u2[e] - o2[e];
+    phi_prev[e] = phi[e];
+  }
+}
+
+template <typename T>
+static pfn::PackArgs<T> ctx_pack_args(pf_ctx* c) {
+  const Layout& L = c->L;
+  const Grid& g = L.g;
+  pfn::PackArgs<T> a{};
+  const long rs = g.px, ps = (long)g.px * g.ny;
+  a.phi_f = {c->arr<T>(L.o_fld[c->cur][0]), rs, ps};
+  a.phi_w = {c->arr<T>(L.o_fld[c->cur][1]), rs, ps};
+  a.phi_prev = {c->arr<T>(L.o_phiprev), rs, ps};
+  for (int d = 0; d < 3; ++d) {
+    a.u1[d] = {c->arr<T>(L.o_du[d]), rs, ps};
+    a.u0[d] = {nullptr, rs, ps};
+    a.u2[d] = {nullptr, rs, ps};
+  }
+  a.nx = g.nx; a.ny = g.ny; a.nz = g.nz;
+  a.cx = g.nx; a.cy = g.ny; a.cz = g.nz;
+  a.Omega = c->prm.Omega_f;
+  a.h = c->cfg.h;
+  return a;
+}
+
+// Evaluate the learned start and keep it if its residual beats the previous
+// displacement's.  `part` holds 2 * nb_el doubles of scratch.
+template <typename T, int DIM>
+static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
+  const Layout& L = c->L;
+  hipStream_t st = c->stream;
+  c->r0_learned = 0.0;
+  c->r0_prev = 0.0;
+  for (int d = 0; d < DIM; ++d)
+    HIPCHK(c, hipMemcpyAsync(c->ws + L.o_uo[d], c->ws + L.o_u[d], (size_t)L.g.n * sizeof(T), hipMemcpyDeviceToDevice, st));
+  c->warm_used = PF_WARM_PREV;
+  if constexpr (DIM == 3) {
+    pf_nn* nn = c->net;
+    if (!nn || !c->have_prev_incr) return PF_OK;
+    const Vol v{1, L.g.nz, L.g.ny, L.g.nx};
+    if (vol_voxels(v) > nn->cap) return fail(c, PF_ERR_INVALID_ARG, "the grid exceeds the network's capacity");
+    pfn::PackArgs<T> a = ctx_pack_args<T>(c);
+    a.s = nn->dscal;
+    a.x = nn->x0;
+    a.target = nullptr;
+    const int nblk = 1024;
+    hipLaunchKernelGGL((pfn::k_incr_sumsq<T>), dim3(nblk), dim3(pfn::CNT), 0, st, a, nn->dpart);
+    hipLaunchKernelGGL(pfn::k_incr_scale, dim3(1), dim3(pfn::CNT), 0, st, (const double*)nn->dpart, nblk,
+                       3.0 * (double)vol_voxels(v), nn->dscal);
+    hipLaunchKernelGGL((pfn::k_pack_inputs<T>), dim3(2048), dim3(pfn::CNT), 0, st, a);
+    LAUNCHCHK(c);
+    if (nn_forward(nn, nn->x0, nn->out, v, st) != PF_OK) return fail(c, PF_ERR_HIP, "network: %s", nn->err);
+    nn->have_fwd = false;    // the activations now belong to this inference, not to a training step
+    T* u[3] = {c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2])};
+    const T* uo[3] = {c->arr<T>(L.o_uo[0]), c->arr<T>(L.o_uo[1]), c->arr<T>(L.o_uo[2])};
+    hipLaunchKernelGGL((k_learned_start<T>), dim3(2048), dim3(pfn::CNT), 0, st, u[0], u[1], u[2], uo[0], uo[1], uo[2],
+                       (const float*)nn->out, (const double*)nn->dscal, L.g);
+    // judge: ||b - A u||^2 for both starts
+    ElastArgs<T> t = e;
+    t.part = part;
+    for (int d = 0; d < 3; ++d) t.u[d] = u[d];
+    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_TRUE>), L.gel, dim3(NT), 0, st, t); });
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part, L.nb_el, c->scal(), (int)S_JL);
+    for (int d = 0; d < 3; ++d) t.u[d] = const_cast<T*>(uo[d]);
+    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_TRUE>), L.gel, dim3(NT), 0, st, t); });
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part, L.nb_el, c->scal(), (int)S_JP);
+    // ||b||^2 from the partials of the b-norm pass
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)c->arr<double>(L.o_part_b), L.nb_el,
+                       c->scal(), (int)S_JB);
+    LAUNCHCHK(c);
+    double js[3];
+    HIPCHK(c, hipMemcpyAsync(js, c->scal() + S_JL, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const double bb = js[2];
+    c->r0_learned = bb > 0.0 ? std::sqrt(js[0] / bb) : 0.0;
+    c->r0_prev = bb > 0.0 ? std::sqrt(js[1] / bb) : 0.0;
+    if (js[0] < js[1]) {
+      c->warm_used = PF_WARM_LEARNED;
+    } else {
+      for (int d = 0; d < 3; ++d)
+        HIPCHK(c, hipMemcpyAsync(u[d], uo[d], (size_t)L.g.n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    }
+  }
+  return PF_OK;
+}
+
+template <typename T, int DIM>
+static pf_status learned_after_solve(pf_ctx* c) {
+  const Layout& L = c->L;
+  if constexpr (DIM == 3) {
+    hipLaunchKernelGGL((k_after_solve<T>), dim3(2048), dim3(pfn::CNT), 0, c->stream, (const T*)c->arr<T>(L.o_u[0]),
+                       (const T*)c->arr<T>(L.o_u[1]), (const T*)c->arr<T>(L.o_u[2]), (const T*)c->arr<T>(L.o_uo[0]),
+                       (const T*)c->arr<T>(L.o_uo[1]), (const T*)c->arr<T>(L.o_uo[2]), c->arr<T>(L.o_du[0]),
+                       c->arr<T>(L.o_du[1]), c->arr<T>(L.o_du[2]), (const T*)c->arr<T>(L.o_fld[c->cur][0]),
+                       c->arr<T>(L.o_phiprev), (long)L.g.n);
+    LAUNCHCHK(c);
+    c->have_prev_incr = true;
+  }
+  return PF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t pf_nn_param_count(void) { return nn_param_count(); }
+
+pf_status pf_nn_create(const pf_nn_config* cfg, void* hip_stream, pf_nn** out) {
+  if (!out) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "config is NULL");
+  if (cfg->max_voxels < 1) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "max_voxels must be >= 1");
+  pf_nn* nn = new (std::nothrow) pf_nn();
+  if (!nn) return nn_fail(nullptr, PF_ERR_OOM, "host allocation failed");
+  nn->cfg = *cfg;
+  nn->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  nn->cap = cfg->max_voxels;
+  nn->np = nn_param_count();
+  size_t off = 0;
+  for (int l = 0; l < kLayers; ++l) {
+    nn->off_w[l] = off;
+    off += (size_t)pfn::kTaps * kDef[l].cout * kDef[l].cin;
+    nn->off_b[l] = off;
+    off += kDef[l].cout;
+  }
+  const size_t cap = (size_t)nn->cap;
+  bool ok = true;
+  auto alloc = [&](auto*& p, size_t bytes) {
+    if (!ok) return;
+    if (hipMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(bytes, 256)) != hipSuccess) { ok = false; p = nullptr; }
+  };
+  alloc(nn->P, nn->np * 4);
+  alloc(nn->G, nn->np * 4);
+  alloc(nn->M, nn->np * 4);
+  alloc(nn->V, nn->np * 4);
+  for (int l = 0; l < kLayers; ++l) {
+    alloc(nn->img_f[l], (size_t)kDef[l].mb * kchunks(kDef[l].cinp) * 1024);
+    if (kDef[l].kinb) alloc(nn->img_b[l], (size_t)2 * kchunks(kDef[l].kinb) * 1024);
+    alloc(nn->bias_p[l], 32 * 4);
+  }
+  alloc(nn->x0, cap * 8 * 2);
+  for (int q = 0; q < 3; ++q) alloc(nn->act[q], cap * 32 * 2);
+  alloc(nn->out, cap * 4 * 4);
+  alloc(nn->dscal, 1024 * 8);
+  alloc(nn->dpart, (size_t)std::max(kBgradBlocks * 32, 4096) * 8 * 2);
+  if (cfg->training) {
+    alloc(nn->target, cap * 4 * 4);
+    alloc(nn->dpred, cap * 8 * 2);
+    alloc(nn->g[0], cap * 32 * 2);
+    alloc(nn->g[1], cap * 32 * 2);
+    alloc(nn->wpart, (size_t)kWgradSplitMax * pfn::kTaps * 32 * 32 * 4);
+  }
+  if (!ok) {
+    pf_nn_destroy(nn);
+    return nn_fail(nullptr, PF_ERR_OOM, "device allocation failed");
+  }
+  // He-uniform initialisation from SplitMix64; the output layer is scaled by 0.1
+  std::vector<float> P(nn->np, 0.f);
+  uint64_t s = cfg->seed;
+  for (int l = 0; l < kLayers; ++l) {
+    const double bound = std::sqrt(6.0 / (pfn::kTaps * kDef[l].cin)) * (l == kLayers - 1 ? 0.1 : 1.0);
+    const size_t nw = (size_t)pfn::kTaps * kDef[l].cout * kDef[l].cin;
+    for (size_t q = 0; q < nw; ++q) {
+      const double u = (double)(splitmix64(s) >> 11) * 0x1.0p-53;
+      P[nn->off_w[l] + q] = (float)((2.0 * u - 1.0) * bound);
+    }
+  }
+  hipError_t e = hipMemcpyAsync(nn->P, P.data(), nn->np * 4, hipMemcpyHostToDevice, nn->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(nn->M, 0, nn->np * 4, nn->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(nn->V, 0, nn->np * 4, nn->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(nn->G, 0, nn->np * 4, nn->stream);
+  if (e == hipSuccess && nn_repack(nn, nn->stream) != PF_OK) e = hipErrorUnknown;
+  if (e == hipSuccess) e = hipStreamSynchronize(nn->stream);
+  if (e != hipSuccess) {
+    pf_nn_destroy(nn);
+    return nn_fail(nullptr, PF_ERR_HIP, "initialisation failed: %s", hipGetErrorString(e));
+  }
+  nn->adam_t = 0;
+  nn->have_fwd = false;
+  nn->err[0] = 0;
+  *out = nn;
+  return PF_OK;
+}
+
+void pf_nn_destroy(pf_nn* nn) {
+  if (!nn) return;
+  (void)hipStreamSynchronize(nn->stream);
+  void* ptrs[] = {nn->P, nn->G, nn->M, nn->V, nn->x0, nn->act[0], nn->act[1], nn->act[2], nn->out, nn->target,
+                  nn->dpred, nn->g[0], nn->g[1], nn->wpart, nn->dpart, nn->dscal};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int l = 0; l < kLayers; ++l) {
+    if (nn->img_f[l]) (void)hipFree(nn->img_f[l]);
+    if (nn->img_b[l]) (void)hipFree(nn->img_b[l]);
+    if (nn->bias_p[l]) (void)hipFree(nn->bias_p[l]);
+  }
+  delete nn;
+}
+
+const char* pf_nn_last_error(const pf_nn* nn) { return nn ? nn->err : g_nn_err; }
+
+pf_status pf_nn_params(pf_nn* nn, int dir, float* host, size_t count) {
+  if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
+  if (!host) return nn_fail(nn, PF_ERR_INVALID_ARG, "host is NULL");
+  if (count != nn->np) return nn_fail(nn, PF_ERR_INVALID_ARG, "%zu parameters expected, got %zu", nn->np, count);
+  if (dir == 1) {
+    NNCHK(nn, hipMemcpyAsync(nn->P, host, nn->np * 4, hipMemcpyHostToDevice, nn->stream));
+    pf_status s = nn_repack(nn, nn->stream);
+    if (s != PF_OK) return s;
+  } else if (dir == 0) {
+    NNCHK(nn, hipMemcpyAsync(host, nn->P, nn->np * 4, hipMemcpyDeviceToHost, nn->stream));
+  } else if (dir == 2) {
+    NNCHK(nn, hipMemcpyAsync(host, nn->G, nn->np * 4, hipMemcpyDeviceToHost, nn->stream));
+  } else {
+    return nn_fail(nn, PF_ERR_INVALID_ARG, "dir must be 0 (get), 1 (set) or 2 (get gradients)");
+  }
+  NNCHK(nn, hipStreamSynchronize(nn->stream));
+  return PF_OK;
+}
+
+pf_status pf_nn_copy(pf_nn* nn, int which, int dir, void* dev, size_t bytes) {
+  if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
+  if (!dev) return nn_fail(nn, PF_ERR_INVALID_ARG, "dev is NULL");
+  if (dir != 0 && dir != 1) return nn_fail(nn, PF_ERR_INVALID_ARG, "dir must be 0 or 1");
+  const size_t cap = (size_t)nn->cap;
+  void* buf = nullptr;
+  size_t size = cap * 16;
+  switch (which) {
+    case PF_NN_BUF_INPUT: buf = nn->x0; break;
+    case PF_NN_BUF_OUTPUT: buf = nn->out; break;
+    case PF_NN_BUF_TARGET: buf = nn->target; break;
+    case PF_NN_BUF_LOSS_GRAD: buf = nn->dpred; break;
+    default: return nn_fail(nn, PF_ERR_INVALID_ARG, "unknown buffer %d", which);
+  }
+  if (!buf) return nn_fail(nn, PF_ERR_INVALID_ARG, "buffer %d needs a network created for training", which);
+  if (bytes > size) return nn_fail(nn, PF_ERR_INVALID_ARG, "%zu bytes exceed the buffer's %zu", bytes, size);
+  NNCHK(nn, hipMemcpyAsync(dir == 0 ? dev : buf, dir == 0 ? buf : dev, bytes, hipMemcpyDeviceToDevice, nn->stream));
+  return PF_OK;
+}
+
+pf_status pf_nn_forward(pf_nn* nn, const void* x, float* y, int n, int D, int H, int W) {
+  if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
+  const Vol v{n, D, H, W};
+  return nn_forward(nn, x ? reinterpret_cast<const uint16_t*>(x) : nn->x0, y ? y : nn->out, v, nn->stream);
+}
+
+pf_status pf_nn_loss(pf_nn* nn, const float* target, double* mean_loss) {
+  if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
+  if (!nn->cfg.training) return nn_fail(nn, PF_ERR_INVALID_ARG, "created without training buffers");
+  if (!nn->have_fwd) return nn_fail(nn, PF_ERR_INVALID_ARG, "no forward pass to take the loss of");
+  const Vol& v = nn->last_v;
+  const long V = (long)v.D * v.H * v.W;
+  if (v.n > 1000) return nn_fail(nn, PF_ERR_INVALID_ARG, "at most 1000 samples per loss");
+  const int nblk = (int)std::max(1L, std::min(64L, (V + pfn::CNT - 1) / pfn::CNT));
+  const float* q = target ? target : nn->target;
+  hipLaunchKernelGGL(pfn::k_loss_part, dim3(nblk, v.n), dim3(pfn::CNT), 0, nn->stream, (const float*)nn->last_y, q, V,
+                     nn->dpart);
+  hipLaunchKernelGGL(pfn::k_loss_grad, dim3(nblk, v.n), dim3(pfn::CNT), 0, nn->stream, (const float*)nn->last_y, q, V,
+                     (const double*)nn->dpart, nblk, v.n, nn->dpred, nn->dscal + 1);
+  NNLAUNCH(nn);
+  if (mean_loss) {
+    std::vector<double> ls(v.n);
+    NNCHK(nn, hipMemcpyAsync(ls.data(), nn->dscal + 1, v.n * sizeof(double), hipMemcpyDeviceToHost, nn->stream));
+    NNCHK(nn, hipStreamSynchronize(nn->stream));
+    double s = 0.0;
+    for (double q2 : ls) s += q2;
+    *mean_loss = s / v.n;
+  }
+  return PF_OK;
+}
+
+pf_status pf_nn_backward(pf_nn* nn, const void* dy) {
+  if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
+  if (!nn->cfg.training) return nn_fail(nn, PF_ERR_INVALID_ARG, "created without training buffers");
+  if (!nn->have_fwd) return nn_fail(nn, PF_ERR_INVALID_ARG, "backward needs the activations of a forward pass");
+  const Vol& v = nn->last_v;
+  hipStream_t st = nn->stream;
+  const uint16_t* gout = dy ? reinterpret_cast<const uint16_t*>(dy) : nn->dpred;
+  pf_status s;
+  if ((s = nn_conv_wgrad(nn, 3, nn->act[2], gout, nn->G + nn->off_w[3], nn->G + nn->off_b[3], v, st)) != PF_OK) return s;
+  if ((s = nn_conv_bwd(nn, 3, gout, nn->act[2], nn->g[0], v, st)) != PF_OK) return s;
+  if ((s = nn_conv_wgrad(nn, 2, nn->act[1], nn->g[0], nn->G + nn->off_w[2], nn->G + nn->off_b[2], v, st)) != PF_OK) return s;
+  if ((s = nn_conv_bwd(nn, 2, nn->g[0], nn->act[1], nn->g[1], v, st)) != PF_OK) return s;
+  if ((s = nn_conv_wgrad(nn, 1, nn->act[0], nn->g[1], nn->G + nn->off_w[1], nn->G + nn->off_b[1], v, st)) != PF_OK) return s;
+  if ((s = nn_conv_bwd(nn, 1, nn->g[1], nn->act[0], nn->g[0], v, st)) != PF_OK) return s;
+  if ((s = nn_conv_wgrad(nn, 0, nn->last_x, nn->g[0], nn->G + nn->off_w[0], nn->G + nn->off_b[0], v, st)) != PF_OK) return s;
+  return PF_OK;
+}
+
+pf_status pf_nn_adam(pf_nn* nn, double lr, double b1, double b2, double eps) {
+  if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
+  if (!(lr > 0.0) || !(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0) || !(eps >= 0.0))
+    return nn_fail(nn, PF_ERR_INVALID_ARG, "need lr > 0, 0 <= b1, b2 < 1 and eps >= 0");
+  nn->adam_t += 1;
+  const double c1 = lr / (1.0 - std::pow(b1, nn->adam_t));
+  const double c2 = 1.0 / (1.0 - std::pow(b2, nn->adam_t));
+  const int n = (int)nn->np;
+  hipLaunchKernelGGL(pfn::k_adam, dim3((n + pfn::CNT - 1) / pfn::CNT), dim3(pfn::CNT), 0, nn->stream, nn->P,
+                     (const float*)nn->G, nn->M, nn->V, n, (float)b1, (float)b2, (float)eps, (float)c1, (float)c2);
+  NNLAUNCH(nn);
+  return nn_repack(nn, nn->stream);
+}
+
+pf_status pf_nn_layer(pf_nn* nn, int op, int layer, const void* in, const void* aux, void* out, int n, int D, int H, int W) {
+  if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
+  if (layer < 0 || layer >= kLayers) return nn_fail(nn, PF_ERR_INVALID_ARG, "layer must be 0..3");
+  if (!in || !out) return nn_fail(nn, PF_ERR_INVALID_ARG, "in and out are required");
+  const Vol v{n, D, H, W};
+  pf_status s = nn_check_vol(nn, v);
+  if (s != PF_OK) return s;
+  const uint16_t* x = reinterpret_cast<const uint16_t*>(in);
+  switch (op) {
+    case PF_NN_OP_FORWARD:
+      return nn_conv_fwd(nn, layer, x, out, v, nn->stream);
+    case PF_NN_OP_BACKWARD_DATA:
+      if (layer == 0) return nn_fail(nn, PF_ERR_INVALID_ARG, "the input gradient of layer 0 is not computed");
+      if (!aux) return nn_fail(nn, PF_ERR_INVALID_ARG, "backward-data needs the layer input as mask");
+      return nn_conv_bwd(nn, layer, x, reinterpret_cast<const uint16_t*>(aux), reinterpret_cast<uint16_t*>(out), v, nn->stream);
+    case PF_NN_OP_BACKWARD_WEIGHT: {
+      if (!nn->cfg.training) return nn_fail(nn, PF_ERR_INVALID_ARG, "created without training buffers");
+      if (!aux) return nn_fail(nn, PF_ERR_INVALID_ARG, "backward-weight needs the output gradient");
+      float* gw = reinterpret_cast<float*>(out);
+      return nn_conv_wgrad(nn, layer, x, reinterpret_cast<const uint16_t*>(aux), gw,
+                           gw + (size_t)pfn::kTaps * kDef[layer].cout * kDef[layer].cin, v, nn->stream);
+    }
+    default:
+      return nn_fail(nn, PF_ERR_INVALID_ARG, "unknown op %d", op);
+  }
+}
+
+pf_status pf_nn_increment_scale(pf_nn* nn, const double* const* u1, const double* const* u0, int nx, int ny, int nz,
+                                double* s_out) {
+  if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
+  if (!u1 || !u1[0] || !u1[1] || !u1[2]) return nn_fail(nn, PF_ERR_INVALID_ARG, "u1 needs three device arrays");
+  if (nx < 1 || ny < 1 || nz < 1) return nn_fail(nn, PF_ERR_INVALID_ARG, "grid sizes must be >= 1");
+  pfn::PackArgs<double> a{};
+  for (int d = 0; d < 3; ++d) {
+    a.u1[d] = xview_face(u1[d], d, nx, ny);
+    a.u0[d] = xview_face(u0 ? u0[d] : nullptr, d, nx, ny);
+  }
+  a.nx = nx; a.ny = ny; a.nz = nz;
+  const int nblk = 1024;
+  hipLaunchKernelGGL((pfn::k_incr_sumsq<double>), dim3(nblk), dim3(pfn::CNT), 0, nn->stream, a, nn->dpart);
+  hipLaunchKernelGGL(pfn::k_incr_scale, dim3(1), dim3(pfn::CNT), 0, nn->stream, (const double*)nn->dpart, nblk,
+                     3.0 * nx * (double)ny * nz, nn->dscal);
+  NNLAUNCH(nn);
+  if (s_out) {
+    NNCHK(nn, hipMemcpyAsync(s_out, nn->dscal, sizeof(double), hipMemcpyDeviceToHost, nn->stream));
+    NNCHK(nn, hipStreamSynchronize(nn->stream));
+  }
+  return PF_OK;
+}
+
+pf_status pf_nn_pack(pf_nn* nn, const double* phi_f, const double* phi_w, const double* phi_prev,
+                     const double* const* u1, const double* const* u0, const double* const* u2, int nx, int ny, int nz,
+                     int x0, int y0, int z0, int cx, int cy, int cz, int slot, double Omega, double h) {
+  if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
+  if (!phi_f || !phi_w || !phi_prev || !u1 || !u1[0] || !u1[1] || !u1[2])
+    return nn_fail(nn, PF_ERR_INVALID_ARG, "phi_f, phi_w, phi_prev and u1 are required");
+  if (u2 && (!u2[0] || !u2[1] || !u2[2])) return nn_fail(nn, PF_ERR_INVALID_ARG, "u2 needs three arrays");
+  if (u2 && !nn->target) return nn_fail(nn, PF_ERR_INVALID_ARG, "targets need a network created for training");
+  if (nx < 1 || ny < 1 || nz < 1 || cx < 1 || cy < 1 || cz < 1 || x0 < 0 || y0 < 0 || z0 < 0 || slot < 0)
+    return nn_fail(nn, PF_ERR_INVALID_ARG, "bad grid, crop or slot");
+  const long long cv = (long long)cx * cy * cz;
+  if ((long long)(slot + 1) * cv > nn->cap) return nn_fail(nn, PF_ERR_INVALID_ARG, "slot %d exceeds the capacity", slot);
+  pfn::PackArgs<double> a{};
+  a.phi_f = xview_cell(phi_f, nx, ny);
+  a.phi_w = xview_cell(phi_w, nx, ny);
+  a.phi_prev = xview_cell(phi_prev, nx, ny);
+  for (int d = 0; d < 3; ++d) {
+    a.u1[d] = xview_face(u1[d], d, nx, ny);
+    a.u0[d] = xview_face(u0 ? u0[d] : nullptr, d, nx, ny);
+    a.u2[d] = xview_face(u2 ? u2[d] : nullptr, d, nx, ny);
+  }
+  a.nx = nx; a.ny = ny; a.nz = nz;
+  a.x0 = x0; a.y0 = y0; a.z0 = z0;
+  a.cx = cx; a.cy = cy; a.cz = cz;
+  a.Omega = Omega;
+  a.h = h;
+  a.s = nn->dscal;
+  a.x = nn->x0 + (size_t)slot * cv * 8;
+  a.target = u2 ? nn->target + (size_t)slot * cv * 4 : nullptr;
+  const int nblk = (int)std::max(1LL, std::min(4096LL, (cv + pfn::CNT - 1) / pfn::CNT));
+  hipLaunchKernelGGL((pfn::k_pack_inputs<double>), dim3(nblk), dim3(pfn::CNT), 0, nn->stream, a);
+  NNLAUNCH(nn);
+  return PF_OK;
+}
+
+pf_status pf_nn_attach(pf_ctx* c, pf_nn* nn) {
+  if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  if (nn && c->cfg.dim != 3) return fail(c, PF_ERR_UNSUPPORTED, "the learned warm start is 3D only");
+  if (nn && c->cfg.warm != PF_WARM_LEARNED)
+    return fail(c, PF_ERR_INVALID_ARG, "the context was not created with the learned warm start");
+  if (nn && (long long)c->cfg.nx * c->cfg.ny * c->cfg.nz > nn->cap)
+    return fail(c, PF_ERR_INVALID_ARG, "the grid exceeds the network's capacity");
+  c->net = nn;
+  return PF_OK;
+}
+
+}  // extern "C"

@@ -18,7 +18,10 @@ LIB_PATH = os.path.join(HERE, "libpf.so")
 PF_OK, PF_ERR_INVALID_ARG, PF_ERR_HIP, PF_ERR_OOM, PF_ERR_CG_NOT_CONVERGED = 0, 1, 2, 3, 4
 PF_ERR_NONFINITE, PF_ERR_LEDGER, PF_ERR_BAD_STATE, PF_ERR_UNSUPPORTED = 5, 6, 7, 8
 PF_FP64, PF_MIXED = 0, 1
-PF_WARM_ZERO, PF_WARM_PREV = 0, 1
+PF_WARM_ZERO, PF_WARM_PREV, PF_WARM_LEARNED = 0, 1, 2
+WARM = {"zero": PF_WARM_ZERO, "prev": PF_WARM_PREV, "learned": PF_WARM_LEARNED}
+PF_NN_OP_FORWARD, PF_NN_OP_BACKWARD_DATA, PF_NN_OP_BACKWARD_WEIGHT = 0, 1, 2
+PF_NN_BUF_INPUT, PF_NN_BUF_OUTPUT, PF_NN_BUF_TARGET, PF_NN_BUF_LOSS_GRAD = 0, 1, 2, 3
 FIELDS = {"phi_f": 0, "phi_w": 1, "xO": 2, "xH": 3, "xW": 4, "ux": 5, "uy": 6, "uz": 7, "epsp": 8, "epsP": 9}
 
 
@@ -50,13 +53,17 @@ class pf_batch_tiles(C.Structure):
                 ("spin_limit", C.c_longlong)]
 
 
+class pf_nn_config(C.Structure):
+    _fields_ = [("max_voxels", C.c_longlong), ("training", C.c_int), ("pad_", C.c_int), ("seed", C.c_ulonglong)]
+
+
 class pf_step_stats(C.Structure):
     _fields_ = [("cg_iters", C.c_int), ("warm_used", C.c_int), ("cg_rel_resid", C.c_double),
                 ("O_tot", C.c_double), ("O_out", C.c_double), ("O_drift", C.c_double),
                 ("H_tot", C.c_double), ("H_out", C.c_double), ("H_drift", C.c_double),
                 ("red_degree", C.c_double), ("max_vm", C.c_double), ("max_epsP", C.c_double),
                 ("step", C.c_longlong), ("nonfinite", C.c_int), ("pad_", C.c_int),
-                ("cg_iters_total", C.c_longlong)]
+                ("cg_iters_total", C.c_longlong), ("r0_learned", C.c_double), ("r0_prev", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
@@ -65,7 +72,10 @@ class pf_step_stats(C.Structure):
 EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_fields", "pf_ledger_reset",
            "pf_timing", "pf_timing_get", "pf_last_error", "pf_destroy",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_set_tiles", "pf_batch_get_tiles",
-           "pf_batch_fields", "pf_batch_step", "pf_batch_last_error", "pf_batch_destroy")
+           "pf_batch_fields", "pf_batch_step", "pf_batch_last_error", "pf_batch_destroy",
+           "pf_nn_param_count", "pf_nn_create", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_params", "pf_nn_copy",
+           "pf_nn_forward", "pf_nn_loss", "pf_nn_backward", "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale",
+           "pf_nn_pack", "pf_nn_attach")
 KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other")
 
 _lib = None
@@ -116,6 +126,27 @@ def lib():
         L.pf_last_error.restype = C.c_char_p
         L.pf_destroy.argtypes = [C.c_void_p]
         L.pf_destroy.restype = None
+        P3 = C.POINTER(C.c_void_p)
+        L.pf_nn_param_count.argtypes = []
+        L.pf_nn_param_count.restype = C.c_size_t
+        L.pf_nn_create.argtypes = [C.POINTER(pf_nn_config), C.c_void_p, C.POINTER(C.c_void_p)]
+        L.pf_nn_destroy.argtypes = [C.c_void_p]
+        L.pf_nn_destroy.restype = None
+        L.pf_nn_last_error.argtypes = [C.c_void_p]
+        L.pf_nn_last_error.restype = C.c_char_p
+        L.pf_nn_params.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.c_size_t]
+        L.pf_nn_copy.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_size_t]
+        L.pf_nn_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p] + [C.c_int] * 4
+        L.pf_nn_loss.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
+        L.pf_nn_backward.argtypes = [C.c_void_p, C.c_void_p]
+        L.pf_nn_adam.argtypes = [C.c_void_p] + [C.c_double] * 4
+        L.pf_nn_layer.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p] + [C.c_int] * 4
+        L.pf_nn_increment_scale.argtypes = [C.c_void_p, P3, P3] + [C.c_int] * 3 + [C.POINTER(C.c_double)]
+        L.pf_nn_pack.argtypes = [C.c_void_p] + [C.c_void_p] * 3 + [P3] * 3 + [C.c_int] * 10 + [C.c_double] * 2
+        L.pf_nn_attach.argtypes = [C.c_void_p, C.c_void_p]
+        for f in ("pf_nn_create", "pf_nn_params", "pf_nn_copy", "pf_nn_forward", "pf_nn_loss", "pf_nn_backward",
+                  "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale", "pf_nn_pack", "pf_nn_attach"):
+            getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
 
@@ -151,7 +182,7 @@ def make_config(dim, shape, h, dt, precision="fp64", mechanics=True, plasticity=
     c.precision = {"fp64": PF_FP64, "mixed": PF_MIXED}[precision]
     c.mechanics, c.plasticity, c.dirichlet, c.chem_phase = int(mechanics), int(plasticity), int(dirichlet), int(chem_phase)
     c.cg_rtol, c.cg_max_iter = cg_rtol, cg_max_iter
-    c.warm = {"zero": PF_WARM_ZERO, "prev": PF_WARM_PREV}[warm]
+    c.warm = WARM[warm]
     c.ledger_tol = ledger_tol
     return c
 
@@ -246,7 +277,7 @@ class Context:
 
     def mech_solve(self, warm="zero"):
         st = pf_step_stats()
-        self._check(lib().pf_mech_solve(self.ctx, {"zero": PF_WARM_ZERO, "prev": PF_WARM_PREV}[warm], C.byref(st)))
+        self._check(lib().pf_mech_solve(self.ctx, WARM[warm], C.byref(st)))
         return st.as_dict()
 
     def timing(self, enable=True):
@@ -348,6 +379,107 @@ class Batch:
         if getattr(self, "ctx", None) and self.ctx.value:
             lib().pf_batch_destroy(self.ctx)
             self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr3(arrs):
+    """Three device tensors (or None) as a C array of pointers."""
+    if arrs is None:
+        return None
+    a = (C.c_void_p * 3)(*[C.c_void_p(t.data_ptr()) for t in arrs])
+    return C.cast(a, C.POINTER(C.c_void_p))
+
+
+class Net:
+    """The learned warm start's network (``pf_nn``): parameters, training
+    buffers and the MFMA convolution kernels live in the library."""
+
+    N_PARAMS = None
+
+    def __init__(self, max_voxels, training=False, seed=2111_11538, device=0, stream=None):
+        import torch
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        cfg = pf_nn_config()
+        cfg.max_voxels, cfg.training, cfg.seed = int(max_voxels), int(training), int(seed)
+        self.nn = C.c_void_p()
+        L = lib()
+        rc = L.pf_nn_create(C.byref(cfg), C.c_void_p(self.stream.cuda_stream), C.byref(self.nn))
+        if rc != PF_OK:
+            raise PFError(rc, L.pf_nn_last_error(None).decode())
+        self.n_params = L.pf_nn_param_count()
+
+    def _check(self, rc):
+        if rc != PF_OK:
+            raise PFError(rc, lib().pf_nn_last_error(self.nn).decode())
+
+    @staticmethod
+    def _p(t):
+        return None if t is None else C.c_void_p(t.data_ptr())
+
+    def params(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        self._check(lib().pf_nn_params(self.nn, 0, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def set_params(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        self._check(lib().pf_nn_params(self.nn, 1, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+    def grads(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        self._check(lib().pf_nn_params(self.nn, 2, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def copy(self, which, t, to_buffer=False):
+        """Copy an internal buffer (``PF_NN_BUF_*``) into the device tensor t,
+        or t into the buffer; the first t.nbytes bytes."""
+        self._check(lib().pf_nn_copy(self.nn, which, int(to_buffer), C.c_void_p(t.data_ptr()), t.numel() * t.element_size()))
+
+    def forward(self, x=None, y=None, n=1, D=1, H=1, W=1):
+        self._check(lib().pf_nn_forward(self.nn, self._p(x), self._p(y), n, D, H, W))
+
+    def loss(self, target=None):
+        out = C.c_double()
+        self._check(lib().pf_nn_loss(self.nn, self._p(target), C.byref(out)))
+        return out.value
+
+    def backward(self, dy=None):
+        self._check(lib().pf_nn_backward(self.nn, self._p(dy)))
+
+    def adam(self, lr, b1=0.9, b2=0.999, eps=1e-8):
+        self._check(lib().pf_nn_adam(self.nn, lr, b1, b2, eps))
+
+    def layer(self, op, layer, x, aux, out, n, D, H, W):
+        self._check(lib().pf_nn_layer(self.nn, op, layer, self._p(x), self._p(aux), self._p(out), n, D, H, W))
+
+    def increment_scale(self, u1, u0=None):
+        nz, ny, nx = u1[2].shape[0] - 1, u1[2].shape[1], u1[2].shape[2]
+        s = C.c_double()
+        self._check(lib().pf_nn_increment_scale(self.nn, _ptr3(u1), _ptr3(u0), nx, ny, nz, C.byref(s)))
+        return s.value
+
+    def pack(self, phi_f, phi_w, phi_prev, u1, u0=None, u2=None, origin=(0, 0, 0), size=None, slot=0, Omega=0.4, h=1.0):
+        nz, ny, nx = phi_f.shape
+        cz, cy, cx = size if size is not None else (nz, ny, nx)
+        z0, y0, x0 = origin
+        self._check(lib().pf_nn_pack(self.nn, self._p(phi_f), self._p(phi_w), self._p(phi_prev), _ptr3(u1), _ptr3(u0),
+                                     _ptr3(u2), nx, ny, nz, x0, y0, z0, cx, cy, cz, slot, float(Omega), float(h)))
+
+    def attach(self, ctx):
+        rc = lib().pf_nn_attach(ctx.ctx, self.nn)
+        if rc != PF_OK:
+            raise PFError(rc, lib().pf_last_error(ctx.ctx).decode())
+
+    def close(self):
+        if getattr(self, "nn", None) and self.nn.value:
+            lib().pf_nn_destroy(self.nn)
+            self.nn = C.c_void_p()
 
     def __del__(self):
         try:
