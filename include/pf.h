@@ -169,7 +169,8 @@ typedef enum {
   PF_K_MU = 4,        /* oxygen chemical potential (one per step) */
   PF_K_OTHER = 5,     /* moduli, convergence checks, ledger (small kernels), and the
                          CG launches queued past convergence, which exit at once */
-  PF_K_COUNT = 6
+  PF_K_NN = 6,        /* the four convolutions of a learned-start inference (one group per solve) */
+  PF_K_COUNT = 7
 } pf_kernel_kind;
 
 /* Per-kernel timing with HIP events recorded on the context's stream around

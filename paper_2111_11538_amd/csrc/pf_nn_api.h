@@ -293,7 +293,9 @@ static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
                        3.0 * (double)vol_voxels(v), nn->dscal);
     hipLaunchKernelGGL((pfn::k_pack_inputs<T>), dim3(2048), dim3(pfn::CNT), 0, st, a);
     LAUNCHCHK(c);
-    if (nn_forward(nn, nn->x0, nn->out, v, st) != PF_OK) return fail(c, PF_ERR_HIP, "network: %s", nn->err);
+    pf_status fs = PF_OK;
+    timed(c, PF_K_NN, [&] { fs = nn_forward(nn, nn->x0, nn->out, v, st); });
+    if (fs != PF_OK) return fail(c, PF_ERR_HIP, "network: %s", nn->err);
     nn->have_fwd = false;    // the activations now belong to this inference, not to a training step
     T* u[3] = {c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2])};
     const T* uo[3] = {c->arr<T>(L.o_uo[0]), c->arr<T>(L.o_uo[1]), c->arr<T>(L.o_uo[2])};

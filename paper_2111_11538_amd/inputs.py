@@ -191,7 +191,8 @@ def ic_core_shell(shape, r_core: float, r_shell: float | None = None, frame: int
 
 
 def ic_porous(shape, porosity: float, n_grains: int, seed: int, semi_min: float = 4.0,
-              semi_max: float = 20.0, x_w: float = X_W_EQ, xH_gas: float = 0.01):
+              semi_max: float = 20.0, x_w: float = X_W_EQ, xH_gas: float = 0.01, rim: float = 0.0,
+              x_f: float = X_F_EQ):
     """Porous wuestite microstructure (stand-in for the SEM-derived section of
     Section 4.3, whose image is not available).
 
@@ -199,7 +200,8 @@ def ic_porous(shape, porosity: float, n_grains: int, seed: int, semi_min: float 
     single isotropic wuestite field, so they do not enter the step); gas pores
     are ellipses (2D) or ellipsoids (3D) with semi-axes U(semi_min, semi_max)
     cells and random orientation, added until the gas fraction reaches
-    ``porosity``.
+    ``porosity``.  With ``rim`` > 0 the solid within that distance (in cells,
+    centre to centre) of a pore is already reduced: ferrite at x_O = x_f.
     """
     dim = len(shape)
     st = Stream(seed)
@@ -244,6 +246,12 @@ def ic_porous(shape, porosity: float, n_grains: int, seed: int, semi_min: float 
     f["phi_w"][solid] = 1.0
     f["xO"][solid] = x_w
     f["xH"][gas] = xH_gas
+    if rim > 0.0:
+        from scipy.ndimage import distance_transform_edt
+        ferrite = solid & (distance_transform_edt(solid) <= rim)
+        f["phi_w"][ferrite] = 0.0
+        f["phi_f"][ferrite] = 1.0
+        f["xO"][ferrite] = x_f
     f["grain"] = _voronoi_ids(shape, seeds)
     return f
 
@@ -297,10 +305,10 @@ def workload(name: str, n: int | None = None, steps: int | None = None) -> Workl
         f = ic_porous((n, n), 0.15, ng, SEED_BASE + 3)
         pp = p.replace(Omega_f=0.2)
         return Workload(name, 2, (n, n), f, pp, h, stable_dt(pp, h, 2), steps or 5000, "mixed", True, 1e-6)
-    if name == "porous_3d":              # 256^3 porous, plastic, Omega_f 0.2
+    if name == "porous_3d":              # 256^3 porous, plastic, Omega_f 0.2, iron rims on the pores
         n = n or 256
         ng = max(4, int(round(64 * (n / 256) ** 3)))
-        f = ic_porous((n, n, n), 0.20, ng, SEED_BASE + 5)
+        f = ic_porous((n, n, n), 0.20, ng, SEED_BASE + 5, rim=2.0)
         pp = p.replace(Omega_f=0.2)
         return Workload(name, 3, (n, n, n), f, pp, h, stable_dt(pp, h, 3), steps or 500, "mixed", True, 1e-6)
     raise ValueError(f"unknown workload {name}")

@@ -76,7 +76,7 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_fiel
            "pf_nn_param_count", "pf_nn_create", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_params", "pf_nn_copy",
            "pf_nn_forward", "pf_nn_loss", "pf_nn_backward", "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale",
            "pf_nn_pack", "pf_nn_attach")
-KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other")
+KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn")
 
 _lib = None
 

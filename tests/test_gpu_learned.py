@@ -1,0 +1,105 @@
+"""The learned warm start inside the solve: the residual judge, the fallback,
+and what a network trained on the plain method's trajectory gains.
+
+A 48^3 instance of the core-shell recipe (mixed precision, plasticity on, CG
+to 1e-6) runs 20 steps with the previous-step start; the network, started
+from weights that reproduce linear extrapolation, is trained on random 24^3
+crops of solves 5..15 (16..19 held out); both starts then continue from
+the same state.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2111_11538_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+N_SIDE = 48
+KW = dict(precision="mixed", plasticity=True, cg_rtol=1e-6)
+NAMES = ("phi_f", "phi_w", "xO", "xH", "xW", "ux", "uy", "uz")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def trajectory():
+    from paper_2111_11538_amd import pf, learned as LR
+    wl = I.workload("core_shell_3d", n=N_SIDE)
+    say(f"recording 20 steps of core_shell_3d at {N_SIDE}^3")
+    c = pf.Context(3, wl.shape, wl.h, wl.dt, wl.params, warm="prev", **KW)
+    c.set_fields(wl.fields)
+    recs = LR.record_trajectory(c, 20)
+    state = c.fields()
+    c.close()
+    return wl, recs, state
+
+
+def _continue(wl, state, warm, net, steps):
+    from paper_2111_11538_amd import pf
+    c = pf.Context(3, wl.shape, wl.h, wl.dt, wl.params, warm=warm, **KW)
+    c.set_fields(state)
+    if net is not None:
+        net.attach(c)
+    stats = [c.step() for _ in range(steps)]
+    out = c.fields(list(NAMES))
+    c.close()
+    return stats, out
+
+
+def test_judge_falls_back_to_the_previous_start(trajectory):
+    """A network with random weights proposes a start far worse than the
+    previous displacement: the judge must reject it every time, and the run
+    must then be bitwise the plain previous-step run."""
+    from paper_2111_11538_amd import pf
+    wl, _, state = trajectory
+    net = pf.Net(max_voxels=N_SIDE ** 3, seed=11)
+    say("random network vs previous-step start, 4 steps")
+    st_l, out_l = _continue(wl, state, "learned", net, 4)
+    st_p, out_p = _continue(wl, state, "prev", None, 4)
+    net.close()
+    for s in st_l[1:]:
+        assert s["r0_learned"] > 0 and s["r0_prev"] > 0
+        assert (s["warm_used"] == pf.PF_WARM_LEARNED) == (s["r0_learned"] < s["r0_prev"])
+    if all(s["warm_used"] == pf.PF_WARM_PREV for s in st_l):
+        for k in NAMES:
+            np.testing.assert_array_equal(out_l[k], out_p[k])
+        assert [s["cg_iters"] for s in st_l] == [s["cg_iters"] for s in st_p]
+
+
+def test_trained_network_saves_cg_iterations(trajectory):
+    from paper_2111_11538_amd import pf, learned as LR
+    wl, recs, state = trajectory
+    net = pf.Net(max_voxels=8 * 24 ** 3, training=True, seed=1)
+    LR.init_extrapolation(net)
+    held = recs[14:]                 # solves 16..19 are not trained on
+    val0 = float(np.mean(LR.evaluate_crops(net, held, wl.params.Omega_f, wl.h, crop=(24, 24, 24))))
+    losses = LR.train(net, recs[:16], 200, wl.params.Omega_f, wl.h, crop=(24, 24, 24), batch=8, lr=1e-4, t_min=5)
+    val1 = float(np.mean(LR.evaluate_crops(net, held, wl.params.Omega_f, wl.h, crop=(24, 24, 24))))
+    say(f"training: loss {np.mean(losses[:20]):.4e} -> {np.mean(losses[-20:]):.4e}; "
+        f"held-out crops {val0:.4e} -> {val1:.4e}")
+    assert val1 < val0
+    inf = pf.Net(max_voxels=N_SIDE ** 3, seed=1)
+    inf.set_params(net.params())
+    net.close()
+    steps = 6
+    st_l, out_l = _continue(wl, state, "learned", inf, steps)
+    st_p, out_p = _continue(wl, state, "prev", None, steps)
+    inf.close()
+    it_l = [s["cg_iters"] for s in st_l]
+    it_p = [s["cg_iters"] for s in st_p]
+    ratio = [s["r0_learned"] / s["r0_prev"] for s in st_l[1:]]
+    say(f"CG iterations, previous-step start: {it_p}")
+    say(f"CG iterations, learned start:       {it_l}  (r0 learned / previous: {np.round(ratio, 3).tolist()})")
+    # from the second solve on the learned start is offered; it must win and save work
+    assert all(s["warm_used"] == pf.PF_WARM_LEARNED for s in st_l[1:])
+    assert all(r < 0.5 for r in ratio)
+    assert sum(it_l[1:]) < 0.8 * sum(it_p[1:])
+    # both runs solve to the same tolerance: the fields agree to the accuracy gate
+    for k in ("phi_f", "phi_w", "xO", "xH"):
+        e = np.linalg.norm(out_l[k] - out_p[k]) / np.linalg.norm(out_p[k])
+        assert e < 1e-4, (k, e)
