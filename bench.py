@@ -45,19 +45,26 @@ def algorithmic_bytes_per_cell(kind, dim, es):
     return 0.0
 
 
-def run_gpu(wl, precision, steps, warmup, timing, rtol):
+NN_FLOP_PER_VOXEL = 2 * 27 * (6 * 32 + 32 * 32 + 32 * 32 + 32 * 3)   # one inference, algorithmic
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak, vendor figure
+
+
+def run_gpu(wl, precision, steps, warmup, timing, rtol, fields=None, net=None):
     import torch
     from paper_2111_11538_amd import pf
     ctx = pf.Context(wl.dim, wl.shape, wl.h, wl.dt, wl.params, device=0, precision=precision,
-                     plasticity=wl.plasticity, cg_rtol=rtol, warm="prev")
-    ctx.set_fields(wl.fields)
-    print(f"[bench] {precision}: warmup {warmup} steps", file=sys.stderr, flush=True)
+                     plasticity=wl.plasticity, cg_rtol=rtol, warm="learned" if net is not None else "prev")
+    ctx.set_fields(fields if fields is not None else wl.fields)
+    if net is not None:
+        net.attach(ctx)
+    tag = precision + (" learned" if net is not None else "")
+    print(f"[bench] {tag}: warmup {warmup} steps", file=sys.stderr, flush=True)
     st0 = ctx.step(warmup) if warmup > 0 else ctx.step(0)
     it0 = st0["cg_iters_total"]
     if timing:
         ctx.timing(True)
     torch.cuda.synchronize()
-    print(f"[bench] {precision}: timing {steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] {tag}: timing {steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     st = ctx.step(steps)
     torch.cuda.synchronize()
@@ -69,21 +76,30 @@ def run_gpu(wl, precision, steps, warmup, timing, rtol):
     return {"seconds": t1 - t0, "stats": st, "cg_iters": st["cg_iters_total"] - it0, "kernels": rep}
 
 
-def accuracy_sample(n=32, steps=10):
-    """Mixed GPU path against the FP64 oracle on an n^3 instance of the recipe."""
+def accuracy_sample(n=32, steps=10, params=None):
+    """Mixed GPU path (with the learned start when trained parameters are
+    given) against the FP64 oracle on an n^3 instance of the recipe."""
     import numpy as np
     from paper_2111_11538_amd import inputs as I
     from paper_2111_11538_amd import pf
     from oracle import oracle as O
     wl = I.workload("core_shell_3d", n=n)
-    g = pf.Context(3, wl.shape, wl.h, wl.dt, wl.params, precision="mixed", plasticity=True, cg_rtol=wl.cg_rtol)
+    g = pf.Context(3, wl.shape, wl.h, wl.dt, wl.params, precision="mixed", plasticity=True, cg_rtol=wl.cg_rtol,
+                   warm="learned" if params is not None else "prev")
     g.set_fields(wl.fields)
+    net = None
+    if params is not None:
+        net = pf.Net(max_voxels=n ** 3)
+        net.set_params(params)
+        net.attach(g)
     o = O.OracleSim(3, wl.shape, wl.h, wl.dt, wl.params, wl.fields, plasticity=True, cg_rtol=wl.cg_rtol)
     for _ in range(steps):
         g.step()
         o.step()
     out = g.fields()
     g.close()
+    if net is not None:
+        net.close()
     fe, ie = {}, {}
     for k in ("phi_f", "phi_w", "xO", "xH", "xW"):
         b, a, b0 = o.f[k], out[k], wl.fields[k]
@@ -92,7 +108,8 @@ def accuracy_sample(n=32, steps=10):
         db = b - b0
         ie[k] = float(np.linalg.norm((a - b0) - db) / np.linalg.norm(db)) if np.linalg.norm(db) > 0 else 0.0
     ue = float(np.linalg.norm(out["uz"] - o.uz) / np.linalg.norm(o.uz))
-    return {"sample": f"{n}^3 core-shell recipe, {steps} steps, mixed GPU vs FP64 oracle",
+    return {"sample": f"{n}^3 core-shell recipe, {steps} steps, mixed GPU"
+                      f"{' with the learned start' if params is not None else ''} vs FP64 oracle",
             "max_field_rel_err": max(fe.values()), "field_err": fe, "incr_rel_err": ie, "u_rel_err": ue}
 
 
@@ -165,6 +182,45 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def train_learned(wl, args):
+    """Record the plain method's first solves of the recipe, train the network
+    on random 32^3 crops of them (offline, untimed) and return the state at the
+    end of the recording, an inference network holding the trained weights,
+    a summary and the weights."""
+    import numpy as np
+    import torch
+    from paper_2111_11538_amd import pf, learned as LR
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    c = pf.Context(wl.dim, wl.shape, wl.h, wl.dt, wl.params, precision=wl.precision, plasticity=wl.plasticity,
+                   cg_rtol=wl.cg_rtol, warm="prev")
+    c.set_fields(wl.fields)
+    t0 = time.perf_counter()
+    recs = LR.record_trajectory(c, args.train_steps)
+    state = c.fields()
+    c.close()
+    t1 = time.perf_counter()
+    tn = pf.Net(max_voxels=8 * 32 ** 3, training=True, seed=1)
+    LR.init_extrapolation(tn)
+    held = recs[-4:]
+    v0 = float(np.mean(LR.evaluate_crops(tn, held, wl.params.Omega_f, wl.h)))
+    losses = LR.train(tn, recs[:-2], args.train_iters, wl.params.Omega_f, wl.h, crop=(32, 32, 32), batch=8,
+                      lr=1e-4, t_min=5, log=log, log_every=100)
+    v1 = float(np.mean(LR.evaluate_crops(tn, held, wl.params.Omega_f, wl.h)))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    params = tn.params()
+    tn.close()
+    ncell = int(np.prod(wl.shape))
+    net = pf.Net(max_voxels=ncell)
+    net.set_params(params)
+    info = {"recorded_solves": args.train_steps, "record_s": round(t1 - t0, 2), "iters": args.train_iters,
+            "batch": "8 crops of 32^3", "train_s": round(t2 - t1, 2),
+            "loss_first_last_50": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
+            "held_out_loss_extrapolation_init": v0, "held_out_loss_trained": v1,
+            "cg_iters_per_step_recorded": [r["cg_iters"] for r in recs]}
+    return state, net, info, params
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +231,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--warm", default="learned", choices=("learned", "prev"),
+                    help="CG start of the timed run (learned: network trained first on the recipe's own trajectory)")
+    ap.add_argument("--train-steps", type=int, default=24, help="recorded solves for training")
+    ap.add_argument("--train-iters", type=int, default=300)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy this many MiB with a plain device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -204,17 +264,23 @@ def main():
         ncell *= s
     es = 4 if wl.precision == "mixed" else 8
 
-    res = run_gpu(wl, wl.precision, args.steps, args.warmup, True, wl.cg_rtol)
+    learned = args.warm == "learned" and wl.dim == 3
+    start, net, train_info, params = None, None, None, None
+    if learned:
+        start, net, train_info, params = train_learned(wl, args)
+    res = run_gpu(wl, wl.precision, args.steps, args.warmup, True, wl.cg_rtol, fields=start, net=net)
     ms = 1e3 * res["seconds"] / args.steps
     value = ncell * args.steps / res["seconds"]
 
     # dominant kernel and its roofline
     kern = res["kernels"]
-    dom = max((k for k in ("apply", "update", "step", "mu", "solve_setup")), key=lambda k: kern[k][0])
+    dom = max((k for k in ("apply", "update", "step", "mu", "solve_setup", "nn")), key=lambda k: kern[k][0])
     tot_ms, nl = kern[dom]
     avg_s = tot_ms / 1e3 / max(nl, 1)
     bytes_per_launch = algorithmic_bytes_per_cell(dom, wl.dim, es) * ncell
     achieved = bytes_per_launch / avg_s / 1e9
+    if dom == "nn":
+        bytes_per_launch = 0.0
     kernels = {k: {"total_ms": round(v[0], 3), "launches": v[1],
                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None,
                    "GBps_algorithmic": (round(algorithmic_bytes_per_cell(k, wl.dim, es) * ncell / (v[0] / 1e3 / v[1]) / 1e9, 1)
@@ -228,7 +294,9 @@ def main():
         "dtype": "f32 state + f64 reductions" if wl.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{wl.name} {'x'.join(str(s) for s in reversed(wl.shape))}, plasticity on, "
-                               f"CG rtol {wl.cg_rtol:g}, warm start = previous step",
+                               f"CG rtol {wl.cg_rtol:g}, warm start = "
+                               + (f"learned (trained on solves 0-{args.train_steps - 1} of this recipe, timed on the "
+                                  f"following steps; judged against the previous step)" if learned else "previous step"),
                    "cells": ncell, "dt_s": wl.dt, "h_m": wl.h},
         "cg_iters_per_step": res["cg_iters"] / args.steps,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -236,14 +304,32 @@ def main():
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)},
         "kernels": kernels,
     }
+    if learned:
+        nn_ms, nn_n = kern["nn"]
+        if nn_n:
+            avg = nn_ms / 1e3 / nn_n
+            tf = NN_FLOP_PER_VOXEL * ncell / avg / 1e12
+            line["roofline_nn"] = {"bound": "mfma", "kernel": "k_conv x4 (one inference)", "achieved": round(tf, 1),
+                                   "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / BF16_PEAK_TFLOPS, 4),
+                                   "traffic": None, "flop_per_launch": NN_FLOP_PER_VOXEL * ncell,
+                                   "avg_launch_us": round(avg * 1e6, 2)}
+        line["training"] = train_info
+        warm_used = res["stats"].get("warm_used")
+        line["learned_last_step"] = {"warm_used": warm_used, "r0_learned": res["stats"]["r0_learned"],
+                                     "r0_prev": res["stats"]["r0_prev"]}
+        rp = run_gpu(wl, wl.precision, args.steps, args.warmup, False, wl.cg_rtol, fields=start)
+        line["plain_mixed_gpu"] = {"value": ncell * args.steps / rp["seconds"], "ms_per_step": 1e3 * rp["seconds"] / args.steps,
+                                   "cg_iters_per_step": rp["cg_iters"] / args.steps,
+                                   "note": "same state and steps, previous-step start"}
+        net.close()
     if not args.no_fp64:
-        r64 = run_gpu(wl, "fp64", max(4, args.steps // 2), args.warmup, False, wl.cg_rtol)
+        r64 = run_gpu(wl, "fp64", max(4, args.steps // 2), args.warmup, False, wl.cg_rtol, fields=start)
         s64 = max(4, args.steps // 2)
         line["fp64_gpu"] = {"value": ncell * s64 / r64["seconds"], "ms_per_step": 1e3 * r64["seconds"] / s64,
                             "cg_iters_per_step": r64["cg_iters"] / s64}
     if not args.no_accuracy:
         print("[bench] accuracy sample", file=sys.stderr, flush=True)
-        line["accuracy"] = accuracy_sample()
+        line["accuracy"] = accuracy_sample(params=params)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()
