@@ -49,6 +49,37 @@ NN_FLOP_PER_VOXEL = 2 * 27 * (6 * 32 + 32 * 32 + 32 * 32 + 32 * 3)   # one infer
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak, vendor figure
 
 
+KERNEL_NAMES = {("update", 3, 4): "k_cg_update<float, 3>", ("apply", 3, 4): "k_apply3<float, 8>",
+                ("step", 3, 4): "k_step<float, 3>", ("mu", 3, 4): "k_mu<float, 3>",
+                ("update", 3, 8): "k_cg_update<double, 3>", ("apply", 3, 8): "k_apply3<double, 8>"}
+
+
+def source_sha():
+    """sha256[:16] over the kernel sources, as recorded in profiles/*_traffic.json."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2111_11538_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(tag, kind, dim, es):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None if it is missing or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"{tag}_traffic.json")
+    name = KERNEL_NAMES.get((kind, dim, es))
+    if not name or not os.path.exists(path):
+        return None, None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha") != source_sha() or name not in d.get("kernels", {}):
+        return None, None
+    k = d["kernels"][name]
+    return k["fetch_bytes"] + k["write_bytes"], os.path.relpath(path, ROOT)
+
+
 def run_gpu(wl, precision, steps, warmup, timing, rtol, fields=None, net=None):
     import torch
     from paper_2111_11538_amd import pf
@@ -281,6 +312,8 @@ def main():
     achieved = bytes_per_launch / avg_s / 1e9
     if dom == "nn":
         bytes_per_launch = 0.0
+    tag = f"{wl.name}_{wl.shape[0]}_{'learned' if learned else 'prev'}"
+    traffic, traffic_src = profiled_traffic(tag, dom, wl.dim, es)
     kernels = {k: {"total_ms": round(v[0], 3), "launches": v[1],
                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None,
                    "GBps_algorithmic": (round(algorithmic_bytes_per_cell(k, wl.dim, es) * ncell / (v[0] / 1e3 / v[1]) / 1e9, 1)
@@ -300,7 +333,8 @@ def main():
                    "cells": ncell, "dt_s": wl.dt, "h_m": wl.h},
         "cg_iters_per_step": res["cg_iters"] / args.steps,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)},
         "kernels": kernels,
     }
