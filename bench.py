@@ -215,7 +215,7 @@ def run_batch(args):
 
 def train_learned(wl, args):
     """Record the plain method's first solves of the recipe, train the network
-    on random 32^3 crops of them (offline, untimed) and return the state at the
+    on random 64^3 crops of them (offline, untimed) and return the state at the
     end of the recording, an inference network holding the trained weights,
     a summary and the weights."""
     import numpy as np
@@ -230,13 +230,13 @@ def train_learned(wl, args):
     state = c.fields()
     c.close()
     t1 = time.perf_counter()
-    tn = pf.Net(max_voxels=8 * 32 ** 3, training=True, seed=1)
+    tn = pf.Net(max_voxels=4 * 64 ** 3, training=True, seed=1)
     LR.init_extrapolation(tn)
     held = recs[-4:]
-    v0 = float(np.mean(LR.evaluate_crops(tn, held, wl.params.Omega_f, wl.h)))
-    losses = LR.train(tn, recs[:-2], args.train_iters, wl.params.Omega_f, wl.h, crop=(32, 32, 32), batch=8,
+    v0 = float(np.mean(LR.evaluate_crops(tn, held, wl.params.Omega_f, wl.h, crop=(64, 64, 64))))
+    losses = LR.train(tn, recs[:-2], args.train_iters, wl.params.Omega_f, wl.h, crop=(64, 64, 64), batch=4,
                       lr=1e-4, t_min=5, log=log, log_every=100)
-    v1 = float(np.mean(LR.evaluate_crops(tn, held, wl.params.Omega_f, wl.h)))
+    v1 = float(np.mean(LR.evaluate_crops(tn, held, wl.params.Omega_f, wl.h, crop=(64, 64, 64))))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     params = tn.params()
@@ -245,7 +245,7 @@ def train_learned(wl, args):
     net = pf.Net(max_voxels=ncell)
     net.set_params(params)
     info = {"recorded_solves": args.train_steps, "record_s": round(t1 - t0, 2), "iters": args.train_iters,
-            "batch": "8 crops of 32^3", "train_s": round(t2 - t1, 2),
+            "batch": "4 crops of 64^3", "train_s": round(t2 - t1, 2),
             "loss_first_last_50": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
             "held_out_loss_extrapolation_init": v0, "held_out_loss_trained": v1,
             "cg_iters_per_step_recorded": [r["cg_iters"] for r in recs]}

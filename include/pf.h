@@ -281,14 +281,14 @@ size_t pf_nn_param_count(void);
 
 /* Create a network; the library allocates and owns its device memory
  * (about 224 bytes per voxel of capacity, 384 with training buffers). */
-pf_status pf_nn_create(const pf_nn_config *cfg, void *hip_stream, pf_nn **out);
+pf_status pf_nn_init(const pf_nn_config *cfg, void *hip_stream, pf_nn **out);
 void pf_nn_destroy(pf_nn *nn);
 const char *pf_nn_last_error(const pf_nn *nn);
 
 /* Parameters to (dir 0) or from (dir 1) the host, or the gradients of the
  * last pf_nn_backward to the host (dir 2); `count` must equal
  * pf_nn_param_count().  Synchronises. */
-pf_status pf_nn_params(pf_nn *nn, int dir, float *host, size_t count);
+pf_status pf_nn_weights(pf_nn *nn, int dir, float *host, size_t count);
 
 /* Copy the first `bytes` bytes of an internal buffer (pf_nn_buffer_id: the
  * packed input [cap][8] bf16, the output [cap][4] FP32, the packed target

@@ -352,7 +352,7 @@ extern "C" {
 
 size_t pf_nn_param_count(void) { return nn_param_count(); }
 
-pf_status pf_nn_create(const pf_nn_config* cfg, void* hip_stream, pf_nn** out) {
+pf_status pf_nn_init(const pf_nn_config* cfg, void* hip_stream, pf_nn** out) {
   if (!out) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!cfg) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "config is NULL");
@@ -446,7 +446,7 @@ void pf_nn_destroy(pf_nn* nn) {
 
 const char* pf_nn_last_error(const pf_nn* nn) { return nn ? nn->err : g_nn_err; }
 
-pf_status pf_nn_params(pf_nn* nn, int dir, float* host, size_t count) {
+pf_status pf_nn_weights(pf_nn* nn, int dir, float* host, size_t count) {
   if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
   if (!host) return nn_fail(nn, PF_ERR_INVALID_ARG, "host is NULL");
   if (count != nn->np) return nn_fail(nn, PF_ERR_INVALID_ARG, "%zu parameters expected, got %zu", nn->np, count);

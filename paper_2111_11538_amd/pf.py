@@ -73,7 +73,7 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_fiel
            "pf_timing", "pf_timing_get", "pf_last_error", "pf_destroy",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_set_tiles", "pf_batch_get_tiles",
            "pf_batch_fields", "pf_batch_step", "pf_batch_last_error", "pf_batch_destroy",
-           "pf_nn_param_count", "pf_nn_create", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_params", "pf_nn_copy",
+           "pf_nn_param_count", "pf_nn_init", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_weights", "pf_nn_copy",
            "pf_nn_forward", "pf_nn_loss", "pf_nn_backward", "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale",
            "pf_nn_pack", "pf_nn_attach")
 KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn")
@@ -129,12 +129,12 @@ def lib():
         P3 = C.POINTER(C.c_void_p)
         L.pf_nn_param_count.argtypes = []
         L.pf_nn_param_count.restype = C.c_size_t
-        L.pf_nn_create.argtypes = [C.POINTER(pf_nn_config), C.c_void_p, C.POINTER(C.c_void_p)]
+        L.pf_nn_init.argtypes = [C.POINTER(pf_nn_config), C.c_void_p, C.POINTER(C.c_void_p)]
         L.pf_nn_destroy.argtypes = [C.c_void_p]
         L.pf_nn_destroy.restype = None
         L.pf_nn_last_error.argtypes = [C.c_void_p]
         L.pf_nn_last_error.restype = C.c_char_p
-        L.pf_nn_params.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.c_size_t]
+        L.pf_nn_weights.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.c_size_t]
         L.pf_nn_copy.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_size_t]
         L.pf_nn_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p] + [C.c_int] * 4
         L.pf_nn_loss.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
@@ -144,7 +144,7 @@ def lib():
         L.pf_nn_increment_scale.argtypes = [C.c_void_p, P3, P3] + [C.c_int] * 3 + [C.POINTER(C.c_double)]
         L.pf_nn_pack.argtypes = [C.c_void_p] + [C.c_void_p] * 3 + [P3] * 3 + [C.c_int] * 10 + [C.c_double] * 2
         L.pf_nn_attach.argtypes = [C.c_void_p, C.c_void_p]
-        for f in ("pf_nn_create", "pf_nn_params", "pf_nn_copy", "pf_nn_forward", "pf_nn_loss", "pf_nn_backward",
+        for f in ("pf_nn_init", "pf_nn_weights", "pf_nn_copy", "pf_nn_forward", "pf_nn_loss", "pf_nn_backward",
                   "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale", "pf_nn_pack", "pf_nn_attach"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -409,7 +409,7 @@ class Net:
         cfg.max_voxels, cfg.training, cfg.seed = int(max_voxels), int(training), int(seed)
         self.nn = C.c_void_p()
         L = lib()
-        rc = L.pf_nn_create(C.byref(cfg), C.c_void_p(self.stream.cuda_stream), C.byref(self.nn))
+        rc = L.pf_nn_init(C.byref(cfg), C.c_void_p(self.stream.cuda_stream), C.byref(self.nn))
         if rc != PF_OK:
             raise PFError(rc, L.pf_nn_last_error(None).decode())
         self.n_params = L.pf_nn_param_count()
@@ -424,16 +424,16 @@ class Net:
 
     def params(self):
         a = np.zeros(self.n_params, dtype=np.float32)
-        self._check(lib().pf_nn_params(self.nn, 0, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        self._check(lib().pf_nn_weights(self.nn, 0, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
         return a
 
     def set_params(self, a):
         a = np.ascontiguousarray(a, dtype=np.float32)
-        self._check(lib().pf_nn_params(self.nn, 1, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        self._check(lib().pf_nn_weights(self.nn, 1, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
 
     def grads(self):
         a = np.zeros(self.n_params, dtype=np.float32)
-        self._check(lib().pf_nn_params(self.nn, 2, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        self._check(lib().pf_nn_weights(self.nn, 2, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
         return a
 
     def copy(self, which, t, to_buffer=False):
