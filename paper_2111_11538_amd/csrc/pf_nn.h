@@ -55,7 +55,8 @@ __device__ __forceinline__ void tap_offset(int t, int& dz, int& dy, int& dx) {
 // output block mb and 32-wide k chunk kc, lane l holds the 8 values
 // W(co = 16 mb + l % 16, k = 32 kc + 8 (l / 16) + j), j = 0..7; entries past
 // the real channel counts or past tap 26 are zero.  One wave computes 64
-// consecutive voxels of one row for all output channels.
+// consecutive voxels of one row for all output channels; a block of 8 waves
+// takes 8 consecutive rows and shares one LDS copy of the weight image.
 //   EPI_RELU:   out (bf16, 16 MB channels) = max(acc + bias, 0)
 //   EPI_LINEAR: out (fp32, 4 channels)     = acc + bias, channels 0..3 of block 0
 //   EPI_MASK:   out (bf16, 16 MB channels) = acc where mask > 0, else 0
@@ -65,60 +66,84 @@ enum Epi { EPI_RELU = 0, EPI_LINEAR = 1, EPI_MASK = 2 };
 template <int CIN>
 constexpr int k_chunks() { return (kTaps * CIN + 31) / 32; }
 
+constexpr int CONV_WAVES = 8;              // waves (rows of a tile) per convolution block
+constexpr int CONV_NT = CONV_WAVES * 64;
+
+constexpr int kBufferFlags = 0x00020000;     // raw buffer, 32-bit data format (gfx9 family)
+constexpr int kOutOfRange = 0x7FFFFFF0;      // byte offset past any tensor here: the load returns zero
+
+// Input fragment of one 16-voxel column block for k chunk kc: lane (lr, lg)
+// holds the 8 channels ci0..ci0+7 of voxel (x + lr + dx, y + dy, z + dz),
+// loaded through a buffer resource over the whole input so that voxels
+// outside the volume read as zero without branches.
+template <int CIN>
+__device__ __forceinline__ void conv_load_b(__amdgpu_buffer_rsrc_t rs, const Vol& v, int n, int z, int y, int x0,
+                                            int kc, int lr, int lg, uint4 (&b)[NBW]) {
+  const int k0 = kc * 32 + lg * 8;
+  const int tap = k0 / CIN, ci0 = k0 % CIN;
+  int dz, dy, dx;
+  tap_offset(tap, dz, dy, dx);
+  const int zz = z + dz, yy = y + dy;
+  const bool rok = tap < kTaps && zz >= 0 && zz < v.D && yy >= 0 && yy < v.H;
+  const int rowv = ((n * v.D + zz) * v.H + yy) * v.W;
+#pragma unroll
+  for (int nb = 0; nb < NBW; ++nb) {
+    const int xx = x0 + nb * 16 + lr + dx;
+    const int off = (rok && xx >= 0 && xx < v.W) ? ((rowv + xx) * CIN + ci0) * 2 : kOutOfRange;
+    const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    b[nb] = uint4{q[0], q[1], q[2], q[3]};
+  }
+}
+
 template <int CIN, int MB, int EPI>
-__global__ __launch_bounds__(CNT) void k_conv(const uint4* __restrict__ wimg, const float* __restrict__ bias,
-                                              const uint16_t* __restrict__ x, void* __restrict__ out,
-                                              const uint16_t* __restrict__ mask, Vol v) {
+__global__ __launch_bounds__(CONV_NT) void k_conv(const uint4* __restrict__ wimg, const float* __restrict__ bias,
+                                                  const uint16_t* __restrict__ x, void* __restrict__ out,
+                                                  const uint16_t* __restrict__ mask, Vol v) {
   constexpr int KC = k_chunks<CIN>();
   constexpr int COUT = MB * 16;
   extern __shared__ uint4 sW[];
-  for (int i = threadIdx.x; i < MB * KC * 64; i += CNT) sW[i] = wimg[i];
+  for (int i = threadIdx.x; i < MB * KC * 64; i += CONV_NT) sW[i] = wimg[i];
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint16_t*>(x), 0, (int)((long)v.n * v.D * v.H * v.W * CIN * 2), kBufferFlags);
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int lr = lane & 15, lg = lane >> 4;
-  const int nseg = (v.W + SEG - 1) / SEG, nyt = (v.H + 3) / 4;
+  const int nseg = (v.W + SEG - 1) / SEG, nyt = (v.H + CONV_WAVES - 1) / CONV_WAVES;
   const long ntiles = (long)nseg * nyt * v.D * v.n;
   for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int xs = (int)(t % nseg);
     long r = t / nseg;
-    const int y = (int)(r % nyt) * 4 + wv;
+    const int y = (int)(r % nyt) * CONV_WAVES + wv;
     r /= nyt;
     const int z = (int)(r % v.D);
     const int n = (int)(r / v.D);
     if (y >= v.H) continue;                     // whole wave; no block barrier follows
+    const int x0 = xs * SEG;
     f32x4 acc[MB][NBW];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the fragments of chunk kc + 1 are in flight while chunk kc is multiplied
+    uint4 bc[NBW], bn[NBW];
+    conv_load_b<CIN>(rs, v, n, z, y, x0, 0, lr, lg, bc);
     for (int kc = 0; kc < KC; ++kc) {
-      const int k0 = kc * 32 + lg * 8;
-      const int tap = k0 / CIN, ci0 = k0 % CIN;
-      int dz, dy, dx;
-      tap_offset(tap, dz, dy, dx);
-      const int zz = z + dz, yy = y + dy;
-      const bool rok = tap < kTaps && zz >= 0 && zz < v.D && yy >= 0 && yy < v.H;
-      const uint16_t* row = x + ((((long)n * v.D + zz) * v.H + yy) * v.W) * CIN + ci0;
-      bf16x8 b[NBW];
-#pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) {
-        const int xx = xs * SEG + nb * 16 + lr + dx;
-        uint4 q = {0u, 0u, 0u, 0u};
-        if (rok && xx >= 0 && xx < v.W) q = *reinterpret_cast<const uint4*>(row + (long)xx * CIN);
-        b[nb] = as_bf8(q);
-      }
+      if (kc + 1 < KC) conv_load_b<CIN>(rs, v, n, z, y, x0, kc + 1, lr, lg, bn);
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const bf16x8 a = as_bf8(sW[(mb * KC + kc) * 64 + lane]);
 #pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[mb][nb], 0, 0, 0);
+        for (int nb = 0; nb < NBW; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf8(bc[nb]), acc[mb][nb], 0, 0, 0);
       }
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) bc[nb] = bn[nb];
     }
     // lane holds out(co = 16 mb + 4 lg + i, voxel = 16 nb + lr)
     const long vrow = (((long)n * v.D + z) * v.H + y) * v.W;
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) {
-      const int xx = xs * SEG + nb * 16 + lr;
+      const int xx = x0 + nb * 16 + lr;
       if (xx >= v.W) continue;
       const long vox = vrow + xx;
       if constexpr (EPI == EPI_LINEAR) {
@@ -150,6 +175,157 @@ __global__ __launch_bounds__(CNT) void k_conv(const uint4* __restrict__ wimg, co
           uint2 st;
           st.x = pack2(o[0], o[1]);
           st.y = pack2(o[2], o[3]);
+          *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + vox * COUT + co0) = st;
+        }
+      }
+    }
+  }
+}
+
+// Convolution with 32 input channels, reusing each input fragment for the three
+// x taps.  For a fixed (dz, dy) a wave loads the 64 input voxels x0..x0+63 of
+// its output row once and multiplies them by the weights of dx = -1, 0, +1
+// into three accumulators; the output of voxel v is acc0[v] + accp[v+1] +
+// accm[v-1], formed once per tile by shuffles within the 16-lane rows.  The
+// two halo voxels x0-1 and x0+64 ride in one extra fragment (lanes 0 and 1)
+// whose products with the dx = -1 / +1 weights complete the edge outputs.
+
+// Value of the neighbouring voxel (dir = +1: voxel lr + 1, dir = -1: voxel lr - 1)
+// within a 16-voxel block; the edge lane takes lane `edge_src` of `edge`.
+__device__ __forceinline__ f32x4 neighbour(const f32x4& cur, const f32x4& edge, int lr, int dir, int edge_src) {
+  f32x4 r;
+  const int src = (lr + dir) & 15;
+  const bool at_edge = dir > 0 ? lr == 15 : lr == 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float a = __shfl(cur[i], src, 16);
+    const float b = __shfl(edge[i], edge_src, 16);
+    r[i] = at_edge ? b : a;
+  }
+  return r;
+}
+
+template <int MB, int EPI>
+__global__ __launch_bounds__(CONV_NT) void k_conv32(const uint4* __restrict__ wimg, const float* __restrict__ bias,
+                                                    const uint16_t* __restrict__ x, void* __restrict__ out,
+                                                    const uint16_t* __restrict__ mask, Vol v) {
+  constexpr int CIN = 32;
+  constexpr int KC = kTaps;                    // one k chunk per tap
+  constexpr int COUT = MB * 16;
+  extern __shared__ uint4 sW[];
+  for (int i = threadIdx.x; i < MB * KC * 64; i += CONV_NT) sW[i] = wimg[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int lr = lane & 15, lg = lane >> 4;
+  const int nseg = (v.W + SEG - 1) / SEG, nyt = (v.H + CONV_WAVES - 1) / CONV_WAVES;
+  const long ntiles = (long)nseg * nyt * v.D * v.n;
+  // each block walks a contiguous run of tiles, z fastest, so the input planes
+  // shared by consecutive tiles are reused from its XCD's L2
+  const long t0 = ntiles * blockIdx.x / gridDim.x, t1 = ntiles * (blockIdx.x + 1) / gridDim.x;
+  for (long t = t0; t < t1; ++t) {
+    const int z = (int)(t % v.D);
+    long r = t / v.D;
+    const int xs = (int)(r % nseg);
+    r /= nseg;
+    const int y = (int)(r % nyt) * CONV_WAVES + wv;
+    const int n = (int)(r / nyt);
+    if (y >= v.H) continue;                     // whole wave; no block barrier follows
+    const int x0 = xs * SEG;
+    f32x4 am[MB][NBW], a0[MB][NBW], ap[MB][NBW], hm[MB], hp[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      hm[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      hp[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        am[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        a0[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        ap[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+    // Branch-free loads through a buffer resource spanning one input row: the
+    // hardware range check returns zero for voxels outside the row (offset
+    // pushed past the end) and for rows outside the volume (empty range).
+    // b[NBW] is the halo fragment: lane 0 voxel x0 - 1, lane 1 voxel x0 + 64.
+    const int xh = lr == 0 ? x0 - 1 : (lr == 1 ? x0 + SEG : -1);
+    auto load = [&](int c, uint4 (&b)[NBW + 1]) {   // c = 3 (dz + 1) + (dy + 1)
+      const int zz = z + c / 3 - 1, yy = y + c % 3 - 1;
+      const bool rok = zz >= 0 && zz < v.D && yy >= 0 && yy < v.H;
+      const uint16_t* row = rok ? x + ((((long)n * v.D + zz) * v.H + yy) * v.W) * CIN : x;
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(row), 0, rok ? v.W * CIN * 2 : 0, kBufferFlags);
+#pragma unroll
+      for (int nb = 0; nb <= NBW; ++nb) {
+        const int xx = nb < NBW ? x0 + nb * 16 + lr : xh;
+        const int off = (xx >= 0 && xx < v.W) ? (xx * CIN + lg * 8) * 2 : kOutOfRange;
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        b[nb] = uint4{q[0], q[1], q[2], q[3]};
+      }
+    };
+    // the fragments of the next (dz, dy) pair are in flight while one is multiplied
+    uint4 bc[NBW + 1], bn[NBW + 1];
+    load(0, bc);
+    for (int c = 0; c < 9; ++c) {
+      if (c + 1 < 9) load(c + 1, bn);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const bf16x8 wm = as_bf8(sW[(mb * KC + 3 * c + 0) * 64 + lane]);
+        const bf16x8 w0 = as_bf8(sW[(mb * KC + 3 * c + 1) * 64 + lane]);
+        const bf16x8 wp = as_bf8(sW[(mb * KC + 3 * c + 2) * 64 + lane]);
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) {
+          const bf16x8 b = as_bf8(bc[nb]);
+          am[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, b, am[mb][nb], 0, 0, 0);
+          a0[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, b, a0[mb][nb], 0, 0, 0);
+          ap[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp, b, ap[mb][nb], 0, 0, 0);
+        }
+        const bf16x8 h = as_bf8(bc[NBW]);
+        hm[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, h, hm[mb], 0, 0, 0);
+        hp[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp, h, hp[mb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int nb = 0; nb <= NBW; ++nb) bc[nb] = bn[nb];
+    }
+    // out(voxel u) = a0[u] + ap[u + 1] + am[u - 1]; lane holds co = 16 mb + 4 lg + i
+    const long vrow = (((long)n * v.D + z) * v.H + y) * v.W;
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) {
+      f32x4 o[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const f32x4 fp = nb + 1 < NBW ? neighbour(ap[mb][nb], ap[mb][nb + 1], lr, +1, 0)
+                                      : neighbour(ap[mb][nb], hp[mb], lr, +1, 1);
+        const f32x4 fm = nb > 0 ? neighbour(am[mb][nb], am[mb][nb - 1], lr, -1, 15)
+                                : neighbour(am[mb][nb], hm[mb], lr, -1, 0);
+        o[mb] = a0[mb][nb] + fp + fm;
+      }
+      const int xx = x0 + nb * 16 + lr;
+      if (xx >= v.W) continue;
+      const long vox = vrow + xx;
+      if constexpr (EPI == EPI_LINEAR) {
+        if (lg == 0)
+          reinterpret_cast<float4*>(out)[vox] =
+              make_float4(o[0][0] + bias[0], o[0][1] + bias[1], o[0][2] + bias[2], o[0][3] + bias[3]);
+      } else {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const int co0 = mb * 16 + lg * 4;
+          float q[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) q[i] = o[mb][i];
+          if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) q[i] = fmaxf(q[i] + bias[co0 + i], 0.f);
+          } else {
+            const uint2 mk = *reinterpret_cast<const uint2*>(mask + vox * COUT + co0);
+            if (!bf_pos(mk.x & 0xFFFFu)) q[0] = 0.f;
+            if (!bf_pos(mk.x >> 16)) q[1] = 0.f;
+            if (!bf_pos(mk.y & 0xFFFFu)) q[2] = 0.f;
+            if (!bf_pos(mk.y >> 16)) q[3] = 0.f;
+          }
+          uint2 st;
+          st.x = pack2(q[0], q[1]);
+          st.y = pack2(q[2], q[3]);
           *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + vox * COUT + co0) = st;
         }
       }

@@ -95,13 +95,20 @@ static long long vol_voxels(const Vol& v) { return (long long)v.n * v.D * v.H * 
 
 static pf_status nn_check_vol(pf_nn* nn, const Vol& v) {
   if (v.n < 1 || v.D < 1 || v.H < 1 || v.W < 1) return nn_fail(nn, PF_ERR_INVALID_ARG, "volume sizes must be >= 1");
+  // the convolutions address a 32-channel bf16 tensor with 32-bit byte offsets
+  if (vol_voxels(v) * 64 >= (1LL << 31)) return nn_fail(nn, PF_ERR_INVALID_ARG, "at most 2^25 voxels per call");
   if (vol_voxels(v) > nn->cap)
     return nn_fail(nn, PF_ERR_INVALID_ARG, "%lld voxels exceed the capacity %lld", vol_voxels(v), nn->cap);
   return PF_OK;
 }
 
+static int conv32_grid(const Vol& v, int cap) {
+  long long nt = (long long)((v.W + pfn::SEG - 1) / pfn::SEG) * ((v.H + pfn::CONV_WAVES - 1) / pfn::CONV_WAVES) * v.D * v.n;
+  return (int)std::max(1LL, std::min(nt, (long long)cap));
+}
+
 static int conv_grid(const Vol& v, int cap) {
-  long long nt = (long long)((v.W + pfn::SEG - 1) / pfn::SEG) * ((v.H + 3) / 4) * v.D * v.n;
+  long long nt = (long long)((v.W + pfn::SEG - 1) / pfn::SEG) * ((v.H + pfn::CONV_WAVES - 1) / pfn::CONV_WAVES) * v.D * v.n;
   return (int)std::max(1LL, std::min(nt, (long long)cap));
 }
 
@@ -111,13 +118,13 @@ static pf_status nn_conv_fwd(pf_nn* nn, int l, const uint16_t* x, void* y, const
   const size_t smem = (size_t)d.mb * kchunks(d.cinp) * 64 * 16;
   const uint4* w = reinterpret_cast<const uint4*>(nn->img_f[l]);
   if (l == 0)
-    hipLaunchKernelGGL((pfn::k_conv<8, 2, pfn::EPI_RELU>), dim3(conv_grid(v, 4096)), dim3(pfn::CNT), smem, st, w,
+    hipLaunchKernelGGL((pfn::k_conv<8, 2, pfn::EPI_RELU>), dim3(conv_grid(v, 4096)), dim3(pfn::CONV_NT), smem, st, w,
                        (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
   else if (l < 3)
-    hipLaunchKernelGGL((pfn::k_conv<32, 2, pfn::EPI_RELU>), dim3(conv_grid(v, 2048)), dim3(pfn::CNT), smem, st, w,
+    hipLaunchKernelGGL((pfn::k_conv32<2, pfn::EPI_RELU>), dim3(conv32_grid(v, 512)), dim3(pfn::CONV_NT), smem, st, w,
                        (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
   else
-    hipLaunchKernelGGL((pfn::k_conv<32, 1, pfn::EPI_LINEAR>), dim3(conv_grid(v, 4096)), dim3(pfn::CNT), smem, st, w,
+    hipLaunchKernelGGL((pfn::k_conv32<1, pfn::EPI_LINEAR>), dim3(conv32_grid(v, 512)), dim3(pfn::CONV_NT), smem, st, w,
                        (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
   NNLAUNCH(nn);
   return PF_OK;
@@ -130,10 +137,10 @@ static pf_status nn_conv_bwd(pf_nn* nn, int l, const uint16_t* dy, const uint16_
   const size_t smem = (size_t)2 * kchunks(d.kinb) * 64 * 16;
   const uint4* w = reinterpret_cast<const uint4*>(nn->img_b[l]);
   if (d.kinb == 8)
-    hipLaunchKernelGGL((pfn::k_conv<8, 2, pfn::EPI_MASK>), dim3(conv_grid(v, 4096)), dim3(pfn::CNT), smem, st, w,
+    hipLaunchKernelGGL((pfn::k_conv<8, 2, pfn::EPI_MASK>), dim3(conv_grid(v, 4096)), dim3(pfn::CONV_NT), smem, st, w,
                        (const float*)nullptr, dy, (void*)dx, mask, v);
   else
-    hipLaunchKernelGGL((pfn::k_conv<32, 2, pfn::EPI_MASK>), dim3(conv_grid(v, 2048)), dim3(pfn::CNT), smem, st, w,
+    hipLaunchKernelGGL((pfn::k_conv32<2, pfn::EPI_MASK>), dim3(conv32_grid(v, 512)), dim3(pfn::CONV_NT), smem, st, w,
                        (const float*)nullptr, dy, (void*)dx, mask, v);
   NNLAUNCH(nn);
   return PF_OK;
