@@ -17,7 +17,7 @@ import os
 import time
 
 APPLY_ROWS = (8, 16, 32, 64)
-UPDATE_CHUNK = (512, 1024, 4096)
+UPDATE_CHUNK = (1024, 4096, 8192, 16384)
 BLOCKS_PER_CU = (1, 2, 3, 4)
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pfx_batch_tiles.json")

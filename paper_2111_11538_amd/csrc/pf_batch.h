@@ -72,34 +72,92 @@ struct BatchArgs {
   long long spin_limit;
 };
 
-// Grid-wide barrier for a launch whose blocks are all resident.  Thread 0 of
-// each block arrives on a global counter; the last arrival resets it and
-// publishes the next generation.  Waiting is bounded: after `spin_limit`
-// polls the block sets the error word and returns false, and a block that sees
-// the error word set also returns false, so every block leaves the kernel.
+// Barrier words (unsigned, 64 apart so that no two share a cache line).
+constexpr int W_ARR = 0;          // arrivals (blocks, or groups in the grouped barrier)
+constexpr int W_GEN = 64;         // generation, published by the last arrival
+constexpr int W_ERR = 128;        // set when a bounded wait gave up
+constexpr int W_MIS = 192;        // set when a block did not run on the XCD its index predicts
+constexpr int W_GARR = 256;       // + 64 x: arrivals within XCD group x
+constexpr int W_GREL = 768;       // + 64 x: release of XCD group x
+constexpr int kBarWords = 1280;
+
+// Bounded wait until *w == target; false (and the error word set) on timeout
+// or when another block already gave up.
+__device__ __forceinline__ bool bar_wait(unsigned* bar, const unsigned* w, unsigned target, long long spin_limit,
+                                         int sleep) {
+  long long spins = 0;
+  while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+    if (__hip_atomic_load(&bar[W_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+    if (++spins > spin_limit) {
+      __hip_atomic_store(&bar[W_ERR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    if (sleep) __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+// Grid-wide barrier for a launch whose blocks are all resident.
+//
+// Flat form: every block makes its writes visible device-wide (release fence
+// at agent scope: write-back of its XCD's L2), arrives on one counter; the
+// last arrival publishes the next generation; every block then invalidates
+// its caches (acquire at agent scope).
+//
+// Grouped form (when every block runs on XCD blockIdx % 8, checked at launch):
+// the blocks of one XCD share an L2, so only the last arrival of each XCD
+// group writes that L2 back (release at agent scope) before arriving on the
+// global counter, on behalf of the group whose stores it has observed through
+// the group counter; the group leaders wait for the generation and release
+// their groups, and every block then acquires at agent scope.  This replaces
+// one L2 write-back per block by one per XCD and keeps the global counter to
+// eight arrivals.
+//
+// Waits are bounded (spin_limit polls): a block that gives up sets the error
+// word, and every block that sees it leaves, so the grid always drains.
 __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen, long long spin_limit,
-                                             int* flag_sh) {
+                                             int grouped, int* flag_sh) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    int ok = 1;
-    __threadfence();
+    bool ok = true;
     const unsigned target = gen + 1u;
-    const unsigned prev = atomicAdd(&bar[0], 1u);
-    if (prev == nblocks - 1u) {
-      atomicExch(&bar[0], 0u);
-      __threadfence();
-      atomicExch(&bar[1], target);
+    if (!grouped) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned prev = __hip_atomic_fetch_add(&bar[W_ARR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == nblocks - 1u) {
+        __hip_atomic_store(&bar[W_ARR], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);        // the reset lands before anyone can arrive again
+        __hip_atomic_store(&bar[W_GEN], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        ok = bar_wait(bar, &bar[W_GEN], target, spin_limit, 1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     } else {
-      long long spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
-        if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { ok = 0; break; }
-        if (++spins > spin_limit) { atomicExch(&bar[2], 1u); ok = 0; break; }
-        __builtin_amdgcn_s_sleep(4);
+      const unsigned x = blockIdx.x % kXCD;
+      const unsigned ngroups = nblocks < (unsigned)kXCD ? nblocks : (unsigned)kXCD;
+      const unsigned gsize = nblocks / kXCD + (x < nblocks % kXCD ? 1u : 0u);
+      const unsigned prev = __hip_atomic_fetch_add(&bar[W_GARR + 64 * x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == gsize - 1u) {
+        __hip_atomic_store(&bar[W_GARR + 64 * x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // also completes the reset above
+        const unsigned gp = __hip_atomic_fetch_add(&bar[W_ARR], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (gp == ngroups - 1u) {
+          __hip_atomic_store(&bar[W_ARR], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_amdgcn_s_waitcnt(0);      // the reset lands before anyone can arrive again
+          __hip_atomic_store(&bar[W_GEN], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          ok = bar_wait(bar, &bar[W_GEN], target, spin_limit, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);          // the invalidate has completed before the group is released
+        __hip_atomic_store(&bar[W_GREL + 64 * x], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        ok = bar_wait(bar, &bar[W_GREL + 64 * x], target, spin_limit, 1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
     }
-    __threadfence();
     gen = target;
-    *flag_sh = ok;
+    *flag_sh = ok ? 1 : 0;
   }
   __syncthreads();
   return *flag_sh != 0;
@@ -152,9 +210,9 @@ constexpr size_t batch_smem() {
   return a > b ? a : b;
 }
 
-#define PF_BARRIER()                                                           \
-  do {                                                                         \
-    if (!grid_barrier(B.bar, nbk, gen, B.spin_limit, &flag_sh)) return;        \
+#define PF_BARRIER()                                                                   \
+  do {                                                                                 \
+    if (!grid_barrier(B.bar, nbk, gen, B.spin_limit, grouped, &flag_sh)) return;       \
   } while (0)
 
 // One explicit step of every instance (2D): moduli, ||b||, initial residual,
@@ -167,8 +225,15 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
   __shared__ int shC[kMaxBatch];
   __shared__ int flag_sh, all_sh;
   __shared__ double red[NT / 64];
+  __shared__ int grouped_sh;
   unsigned gen = 0u;
-  if (threadIdx.x == 0) gen = __hip_atomic_load(&B.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int grouped = 0;                 // the first barrier is flat; it publishes the XCD check
+  if (threadIdx.x == 0) {
+    gen = __hip_atomic_load(&B.bar[W_GEN], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // XCC_ID hardware register (bits 3:0): the XCD this block runs on
+    const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 0xFu;
+    if (xcc != blockIdx.x % kXCD) __hip_atomic_fetch_or(&B.bar[W_MIS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   const unsigned nbk = gridDim.x;
   const int tid = threadIdx.x;
   const int S = S_COUNT;
@@ -180,6 +245,9 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
     moduli_tile<T, 2>(a, tr.bx, tr.by, tr.bz);
   }
   PF_BARRIER();
+  if (tid == 0) grouped_sh = __hip_atomic_load(&B.bar[W_MIS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+  __syncthreads();
+  grouped = grouped_sh;
   // (2) ||b||^2 partials
   for (int w = blockIdx.x; w < B.n_el; w += nbk) {
     const TileRef tr = B.el[w];

@@ -95,7 +95,7 @@ BatchLayout make_batch_layout(const pf_config* c, const pf_extent* ext, int coun
   L.o_pt = take(L.n_el * sizeof(double));
   L.o_pc = take(NQ_STEP * (size_t)L.n_ce * sizeof(double));
   L.o_iscal = take((size_t)count * S_COUNT * sizeof(double));
-  L.o_bar = take(4 * sizeof(unsigned));
+  L.o_bar = take(kBarWords * sizeof(unsigned));
   L.o_stage = take(L.stage_elems * sizeof(double));
   L.total = pos;
   return L;
@@ -422,10 +422,11 @@ pf_status pf_batch_step(pf_batch* bt, int nsteps, pf_step_stats* stats) {
   }
   BHIP(bt, hipMemcpyAsync(bt->host_iscal, bt->ws + L.o_iscal, (size_t)L.count * S_COUNT * sizeof(double),
                           hipMemcpyDeviceToHost, bt->stream));
-  unsigned barw[4];
-  BHIP(bt, hipMemcpyAsync(barw, bt->ws + L.o_bar, sizeof barw, hipMemcpyDeviceToHost, bt->stream));
+  unsigned barerr = 0u;
+  BHIP(bt, hipMemcpyAsync(&barerr, bt->ws + L.o_bar + W_ERR * sizeof(unsigned), sizeof barerr, hipMemcpyDeviceToHost,
+                          bt->stream));
   BHIP(bt, hipStreamSynchronize(bt->stream));
-  if (barw[2] != 0u) {
+  if (barerr != 0u) {
     bt->bad = true;
     return bfail(bt, PF_ERR_HIP, "a grid barrier of the batch kernel timed out (blocks not co-resident?)");
   }
