@@ -163,10 +163,39 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, un
   return *flag_sh != 0;
 }
 
+// Sum of part[r0 .. r0+n) in a fixed order, eight independent loads in flight.
 __device__ __forceinline__ double range_sum(const double* part, int r0, int n) {
-  double s = 0.0;
-  for (int q = 0; q < n; ++q) s += part[r0 + q];
-  return s;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int q = 0;
+  for (; q + 8 <= n; q += 8)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] += part[r0 + q + k];
+  for (; q < n; ++q) s[0] += part[r0 + q];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+// Inclusive prefix sums over the instances of a per-instance count (zero for
+// converged instances), in shared memory; count <= NT.
+__device__ __forceinline__ void active_scan(int* sh, int v, int count) {
+  const int t = threadIdx.x;
+  if (t < count) sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < count; o <<= 1) {
+    const int add = (t < count && t >= o) ? sh[t - o] : 0;
+    __syncthreads();
+    if (t < count) sh[t] += add;
+    __syncthreads();
+  }
+}
+
+// Instance b holding active work item w: incl[b-1] <= w < incl[b].
+__device__ __forceinline__ int active_owner(const int* incl, int count, int w) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (incl[mid] > w) hi = mid; else lo = mid + 1;
+  }
+  return lo;
 }
 
 template <typename T>
@@ -223,6 +252,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
   __shared__ __align__(16) char smem[batch_smem<T>()];
   __shared__ double shA[kMaxBatch], shB[kMaxBatch], shBB[kMaxBatch];
   __shared__ int shC[kMaxBatch];
+  __shared__ int shAp[kMaxBatch], shUp[kMaxBatch];   // inclusive prefix sums of active apply tiles / update chunks
   __shared__ int flag_sh, all_sh;
   __shared__ double red[NT / 64];
   __shared__ int grouped_sh;
@@ -312,13 +342,25 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
     }
     __syncthreads();
     if (all_sh || L >= B.max_iter) break;
+    // the work items of the instances still iterating, dealt out evenly
+    {
+      int nap = 0, nup = 0;
+      if (tid < B.count && !shC[tid]) {
+        nap = B.inst[tid].apn;
+        nup = B.inst[tid].upn;
+      }
+      active_scan(shAp, nap, B.count);
+      active_scan(shUp, nup, B.count);
+    }
+    const int n_ap_act = shAp[B.count - 1], n_up_act = shUp[B.count - 1];
     // apply: q = A p with p = z + beta p
     T* const pold[2] = {(L & 1) ? B.pb[0] : B.pa[0], (L & 1) ? B.pb[1] : B.pa[1]};
     T* const pnew[2] = {(L & 1) ? B.pa[0] : B.pb[0], (L & 1) ? B.pa[1] : B.pb[1]};
-    for (int w = blockIdx.x; w < B.n_ap; w += nbk) {
+    for (int wa = blockIdx.x; wa < n_ap_act; wa += nbk) {
+      const int ib = active_owner(shAp, B.count, wa);
+      const InstDesc& d = B.inst[ib];
+      const int w = d.ap0 + wa - (ib > 0 ? shAp[ib - 1] : 0);
       const TileRef tr = B.ap[w];
-      if (shC[tr.inst]) continue;
-      const InstDesc& d = B.inst[tr.inst];
       ElastArgs<T> a = elast_view(B, d);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -336,10 +378,11 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
     __syncthreads();
     // update: u += alpha p, r -= alpha q, z = D^-1 r
     double* pu = B.part_u + (L & 1) * 2 * B.n_up;
-    for (int w = blockIdx.x; w < B.n_up; w += nbk) {
+    for (int wu = blockIdx.x; wu < n_up_act; wu += nbk) {
+      const int ib = active_owner(shUp, B.count, wu);
+      const InstDesc& d = B.inst[ib];
+      const int w = d.up0 + wu - (ib > 0 ? shUp[ib - 1] : 0);
       const ChunkRef cr = B.up[w];
-      if (shC[cr.inst]) continue;
-      const InstDesc& d = B.inst[cr.inst];
       UpdArgs<T> a{};
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
