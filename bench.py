@@ -230,24 +230,25 @@ def train_learned(wl, args):
     state = c.fields()
     c.close()
     t1 = time.perf_counter()
-    tn = pf.Net(max_voxels=4 * 64 ** 3, training=True, seed=1)
+    ncell = int(np.prod(wl.shape))
+    tn = pf.Net(max_voxels=max(4 * 64 ** 3, ncell), training=True, seed=1)
     LR.init_extrapolation(tn)
-    held = recs[-4:]
-    v0 = float(np.mean(LR.evaluate_crops(tn, held, wl.params.Omega_f, wl.h, crop=(64, 64, 64))))
+    held = recs[-4:]                 # solves 22 and 23 are held out (2 more give their history)
+    v0 = float(np.mean(LR.evaluate(tn, held, wl.params.Omega_f, wl.h)))
     losses = LR.train(tn, recs[:-2], args.train_iters, wl.params.Omega_f, wl.h, crop=(64, 64, 64), batch=4,
-                      lr=1e-4, t_min=5, log=log, log_every=100)
-    v1 = float(np.mean(LR.evaluate_crops(tn, held, wl.params.Omega_f, wl.h, crop=(64, 64, 64))))
+                      lr=1e-4, t_min=5, log=log, log_every=100, val_recs=held, eval_every=25)
+    v1 = float(np.mean(LR.evaluate(tn, held, wl.params.Omega_f, wl.h)))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     params = tn.params()
     tn.close()
-    ncell = int(np.prod(wl.shape))
     net = pf.Net(max_voxels=ncell)
     net.set_params(params)
     info = {"recorded_solves": args.train_steps, "record_s": round(t1 - t0, 2), "iters": args.train_iters,
             "batch": "4 crops of 64^3", "train_s": round(t2 - t1, 2),
             "loss_first_last_50": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
-            "held_out_loss_extrapolation_init": v0, "held_out_loss_trained": v1,
+            "held_out_full_grid_loss_extrapolation_init": v0, "held_out_full_grid_loss_trained": v1,
+            "early_stopping": "best held-out full-grid loss over checkpoints every 25 iterations",
             "cg_iters_per_step_recorded": [r["cg_iters"] for r in recs]}
     return state, net, info, params
 

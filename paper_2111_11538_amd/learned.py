@@ -78,12 +78,21 @@ def init_extrapolation(net, keep_scale=0.1):
 
 
 def train(net, recs, iters, Omega, h, crop=(32, 32, 32), batch=8, lr=1e-4, seed=0, log=None, log_every=25,
-          t_min=2):
-    """Adam on random crops of the recorded solves t >= t_min; returns the loss history."""
+          t_min=2, val_recs=None, eval_every=25):
+    """Adam on random crops of the recorded solves t >= t_min; returns the
+    loss history.  With ``val_recs`` the whole-grid loss on those solves is
+    evaluated every ``eval_every`` iterations (and before the first) and the
+    network keeps the best parameters seen (early stopping)."""
     rng = np.random.default_rng(seed)
     nz, ny, nx = recs[0]["phi_f"].shape
     cz, cy, cx = (min(crop[0], nz), min(crop[1], ny), min(crop[2], nx))
     losses = []
+    best, best_params = None, None
+    if val_recs is not None:
+        best = float(np.mean(evaluate(net, val_recs, Omega, h)))
+        best_params = net.params()
+        if log:
+            log(f"[train] held-out loss at start: {best:.4e}")
     for it in range(iters):
         for b in range(batch):
             t = int(rng.integers(max(2, t_min), len(recs)))
@@ -100,6 +109,14 @@ def train(net, recs, iters, Omega, h, crop=(32, 32, 32), batch=8, lr=1e-4, seed=
         losses.append(loss)
         if log and (it % log_every == 0 or it == iters - 1):
             log(f"[train] iter {it}: loss {loss:.4e}")
+        if val_recs is not None and ((it + 1) % eval_every == 0 or it == iters - 1):
+            v = float(np.mean(evaluate(net, val_recs, Omega, h)))
+            if v < best:
+                best, best_params = v, net.params()
+            if log:
+                log(f"[train] iter {it + 1}: held-out loss {v:.4e} (best {best:.4e})")
+    if best_params is not None:
+        net.set_params(best_params)
     return losses
 
 
