@@ -171,6 +171,7 @@ struct pf_ctx {
   // learned start
   pf_nn* net;
   bool have_prev_incr;
+  bool judged;             // the last solve evaluated the learned start
   double r0_learned, r0_prev;
   template <typename T> T* arr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   double* scal() const { return arr<double>(L.o_scal); }
@@ -308,10 +309,6 @@ struct Impl {
     // ||b||^2
     e.part = part_b;
     timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_BNORM>), L.gel, dim3(NT), 0, st, e); });
-    if (warm == PF_WARM_LEARNED) {
-      pf_status s = learned_start<T, DIM>(c, e, part_a);
-      if (s != PF_OK) return s;
-    }
     // r = b - A u, D^-1, z, and the partials of r.z and r.r
     ElastArgs<T> r = e;
     for (int d = 0; d < DIM; ++d) {
@@ -325,6 +322,11 @@ struct Impl {
     r.part = part_u;
     timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_RESID>), L.gel, dim3(NT), 0, st, r); });
     LAUNCHCHK(c);
+    c->warm_used = warm == PF_WARM_LEARNED ? PF_WARM_PREV : warm;
+    if (warm == PF_WARM_LEARNED) {
+      pf_status s = learned_start<T, DIM>(c, e, part_a);
+      if (s != PF_OK) return s;
+    }
 
     ElastArgs<T> ap = elast_args(c);
     UpdArgs<T> up{};
@@ -386,6 +388,15 @@ struct Impl {
     }
     c->last_iters = (int)c->host_scal[S_ITERS];
     c->iters_total += c->last_iters;
+    if (c->judged) {
+      const double* hs = c->host_scal;
+      c->r0_learned = hs[S_BB] > 0.0 ? std::sqrt(hs[S_JL] / hs[S_BB]) : 0.0;
+      c->r0_prev = hs[S_BB] > 0.0 ? std::sqrt(hs[S_JP] / hs[S_BB]) : 0.0;
+      if (hs[S_JB] != 0.0) c->warm_used = PF_WARM_LEARNED;
+    } else {
+      c->r0_learned = 0.0;
+      c->r0_prev = 0.0;
+    }
     // launches queued past convergence exit at entry: account them as small kernels
     for (auto& pr : c->pending)
       if (pr.launch >= c->last_iters && (pr.kind == PF_K_APPLY || pr.kind == PF_K_UPDATE)) pr.kind = PF_K_OTHER;
@@ -505,6 +516,7 @@ pf_status pf_init(const pf_config* cfg, const pf_params* params, void* workspace
   c->iters_total = 0;
   c->net = nullptr;
   c->have_prev_incr = false;
+  c->judged = false;
   c->r0_learned = 0.0;
   c->r0_prev = 0.0;
   for (int k = 0; k < PF_K_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }

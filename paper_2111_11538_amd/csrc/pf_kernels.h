@@ -38,6 +38,7 @@ struct ElastArgs {
   double tol2;             // cg_rtol^2
   int parity;              // launch position parity inside the CG loop
   int kz;                  // z planes per block
+  int plain;               // APPLY (3D): q = A z only, outside the CG recurrence (no scalars read or written)
 };
 
 // Local tile coordinates: lx = i - i0 + 1 in [0, TX+1], ly = j - j0 + 1 in [0, TY+1].
@@ -410,28 +411,32 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
   const int pl = g.px * g.ny;
 
   // CG scalars (identical in every block)
-  if (a.scal[S_CONV] != 0.0) return;
-  double rzv = 0.0, rrv = 0.0;
-  {
-    double v0 = 0.0, v1 = 0.0;
-    for (int q = threadIdx.x; q < a.n_in; q += NTB) { v0 += a.part_in[q]; v1 += a.part_in[a.n_in + q]; }
-    v0 = wave_sum(v0);
-    v1 = wave_sum(v1);
-    __shared__ double sh2[2][NTB / 64];
-    if ((threadIdx.x & 63) == 0) { sh2[0][threadIdx.x >> 6] = v0; sh2[1][threadIdx.x >> 6] = v1; }
-    __syncthreads();
+  double beta = 0.0;
+  bool first = true;                 // plain: p_new = z
+  if (!a.plain) {
+    if (a.scal[S_CONV] != 0.0) return;
+    double rzv = 0.0, rrv = 0.0;
+    {
+      double v0 = 0.0, v1 = 0.0;
+      for (int q = threadIdx.x; q < a.n_in; q += NTB) { v0 += a.part_in[q]; v1 += a.part_in[a.n_in + q]; }
+      v0 = wave_sum(v0);
+      v1 = wave_sum(v1);
+      __shared__ double sh2[2][NTB / 64];
+      if ((threadIdx.x & 63) == 0) { sh2[0][threadIdx.x >> 6] = v0; sh2[1][threadIdx.x >> 6] = v1; }
+      __syncthreads();
 #pragma unroll
-    for (int w = 0; w < NTB / 64; ++w) { rzv += sh2[0][w]; rrv += sh2[1][w]; }
-  }
-  if (rrv <= a.tol2 * a.scal[S_BB]) {
-    if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = 1.0;
-    return;
-  }
-  const bool first = a.scal[S_FIRST] != 0.0;
-  const double beta = first ? 0.0 : rzv / a.scal[S_RZ + (a.parity ^ 1)];
-  if (bid == 0 && threadIdx.x == 0) {
-    a.scal[S_RZ + a.parity] = rzv;
-    a.scal[S_RR] = rrv;
+      for (int w = 0; w < NTB / 64; ++w) { rzv += sh2[0][w]; rrv += sh2[1][w]; }
+    }
+    if (rrv <= a.tol2 * a.scal[S_BB]) {
+      if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = 1.0;
+      return;
+    }
+    first = a.scal[S_FIRST] != 0.0;
+    beta = first ? 0.0 : rzv / a.scal[S_RZ + (a.parity ^ 1)];
+    if (bid == 0 && threadIdx.x == 0) {
+      a.scal[S_RZ + a.parity] = rzv;
+      a.scal[S_RR] = rrv;
+    }
   }
   const T tb = (T)beta;
 

@@ -222,20 +222,90 @@ static pfn::View<double> xview_face(const double* p, int c, int nx, int ny) {
 // increment of the previous solve (du) and the ferrite phase of the previous
 // solve (phi_prev).
 // ---------------------------------------------------------------------------
+// Learned increment on the low faces of every cell: d = s * y, zero on the
+// low boundary faces (fixed by the rollers) and in the padding.
 template <typename T>
-__global__ __launch_bounds__(pfn::CNT) void k_learned_start(T* __restrict__ u0, T* __restrict__ u1, T* __restrict__ u2,
-                                                           const T* __restrict__ o0, const T* __restrict__ o1,
-                                                           const T* __restrict__ o2, const float* __restrict__ y,
-                                                           const double* __restrict__ s, Grid g) {
+__global__ __launch_bounds__(pfn::CNT) void k_learned_delta(T* __restrict__ d0, T* __restrict__ d1, T* __restrict__ d2,
+                                                           const float* __restrict__ y, const double* __restrict__ s,
+                                                           Grid g) {
   const double sc = *s;
-  const long nv = (long)g.nx * g.ny * g.nz;
-  for (long v = blockIdx.x * (long)pfn::CNT + threadIdx.x; v < nv; v += (long)gridDim.x * pfn::CNT) {
-    const int i = (int)(v % g.nx), j = (int)((v / g.nx) % g.ny), k = (int)(v / ((long)g.nx * g.ny));
-    const long e = ((long)k * g.ny + j) * g.px + i;
-    const float4 o = reinterpret_cast<const float4*>(y)[v];
-    u0[e] = i > 0 ? (T)((double)o0[e] + sc * o.x) : o0[e];
-    u1[e] = j > 0 ? (T)((double)o1[e] + sc * o.y) : o1[e];
-    u2[e] = k > 0 ? (T)((double)o2[e] + sc * o.z) : o2[e];
+  for (long e = blockIdx.x * (long)pfn::CNT + threadIdx.x; e < g.n; e += (long)gridDim.x * pfn::CNT) {
+    const int i = (int)(e % g.px), j = (int)((e / g.px) % g.ny), k = (int)(e / ((long)g.px * g.ny));
+    T a = T(0), b = T(0), c = T(0);
+    if (i < g.nx) {
+      const float4 o = reinterpret_cast<const float4*>(y)[((long)k * g.ny + j) * g.nx + i];
+      if (i > 0) a = (T)(sc * o.x);
+      if (j > 0) b = (T)(sc * o.y);
+      if (k > 0) c = (T)(sc * o.z);
+    }
+    d0[e] = a;
+    d1[e] = b;
+    d2[e] = c;
+  }
+}
+
+// Judge, step 1: partials of ||r - q||^2 with r = b - A u_prev (from the
+// residual pass) and q = A d: the residual of the learned start u_prev + d.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_judge_norm(const T* __restrict__ r0, const T* __restrict__ r1,
+                                                  const T* __restrict__ r2, const T* __restrict__ q0,
+                                                  const T* __restrict__ q1, const T* __restrict__ q2, long n,
+                                                  double* __restrict__ part) {
+  __shared__ double red[NT / 64];
+  double acc = 0.0;
+  for (long e = blockIdx.x * (long)NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
+    const double a = (double)r0[e] - (double)q0[e], b = (double)r1[e] - (double)q1[e], c = (double)r2[e] - (double)q2[e];
+    acc += a * a + b * b + c * c;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// Judge, step 2 (one block): compare the two residual norms; the decision and
+// both norms go to the device scalars.  Nothing is decided when the solve has
+// already converged (b = 0).
+__global__ __launch_bounds__(NT) void k_judge_decide(const double* __restrict__ part_l, const double* __restrict__ part_p,
+                                                    int nb, double* __restrict__ scal) {
+  __shared__ double red[NT / 64];
+  const double rl = sum_partials(part_l, nb, red);
+  const double rp = sum_partials(part_p, nb, red);
+  if (threadIdx.x == 0) {
+    scal[S_JL] = rl;
+    scal[S_JP] = rp;
+    scal[S_JB] = (scal[S_CONV] == 0.0 && rl < rp) ? 1.0 : 0.0;
+  }
+}
+
+// Judge, step 3: if the learned start won, move to it: u += d, r -= q,
+// z = D^-1 r, and replace the partials of r.z and r.r that CG starts from.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_judge_apply(T* __restrict__ u0, T* __restrict__ u1, T* __restrict__ u2,
+                                                   const T* __restrict__ d0, const T* __restrict__ d1,
+                                                   const T* __restrict__ d2, T* __restrict__ r0, T* __restrict__ r1,
+                                                   T* __restrict__ r2, const T* __restrict__ q0, const T* __restrict__ q1,
+                                                   const T* __restrict__ q2, const T* __restrict__ di0,
+                                                   const T* __restrict__ di1, const T* __restrict__ di2,
+                                                   T* __restrict__ z0, T* __restrict__ z1, T* __restrict__ z2, long n,
+                                                   const double* __restrict__ scal, double* __restrict__ part) {
+  __shared__ double red[NT / 64];
+  if (scal[S_JB] == 0.0) return;
+  double rz = 0.0, rr = 0.0;
+  for (long e = blockIdx.x * (long)NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
+    u0[e] += d0[e];
+    u1[e] += d1[e];
+    u2[e] += d2[e];
+    const T a = r0[e] - q0[e], b = r1[e] - q1[e], c = r2[e] - q2[e];
+    const T za = di0[e] * a, zb = di1[e] * b, zc = di2[e] * c;
+    r0[e] = a; r1[e] = b; r2[e] = c;
+    z0[e] = za; z1[e] = zb; z2[e] = zc;
+    rz += (double)a * (double)za + (double)b * (double)zb + (double)c * (double)zc;
+    rr += (double)a * (double)a + (double)b * (double)b + (double)c * (double)c;
+  }
+  rz = block_sum(rz, red);
+  rr = block_sum(rr, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = rz;
+    part[gridDim.x + blockIdx.x] = rr;
   }
 }
 
@@ -274,17 +344,19 @@ static pfn::PackArgs<T> ctx_pack_args(pf_ctx* c) {
   return a;
 }
 
-// Evaluate the learned start and keep it if its residual beats the previous
-// displacement's.  `part` holds 2 * nb_el doubles of scratch.
+// Offer the learned start after the residual pass of the previous
+// displacement: d = s * NN(state), q = A d on the apply kernel, and the
+// residual of u_prev + d is r - q.  The comparison and the switch happen on
+// the device (no host synchronisation); the solve reports the choice.
+// `part` holds 2 * nb_el doubles of scratch; r, z, D^-1 and their partials
+// come from the residual pass.
 template <typename T, int DIM>
 static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
   const Layout& L = c->L;
   hipStream_t st = c->stream;
-  c->r0_learned = 0.0;
-  c->r0_prev = 0.0;
   for (int d = 0; d < DIM; ++d)
     HIPCHK(c, hipMemcpyAsync(c->ws + L.o_uo[d], c->ws + L.o_u[d], (size_t)L.g.n * sizeof(T), hipMemcpyDeviceToDevice, st));
-  c->warm_used = PF_WARM_PREV;
+  c->judged = false;
   if constexpr (DIM == 3) {
     pf_nn* nn = c->net;
     if (!nn || !c->have_prev_incr) return PF_OK;
@@ -304,35 +376,40 @@ static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
     timed(c, PF_K_NN, [&] { fs = nn_forward(nn, nn->x0, nn->out, v, st); });
     if (fs != PF_OK) return fail(c, PF_ERR_HIP, "network: %s", nn->err);
     nn->have_fwd = false;    // the activations now belong to this inference, not to a training step
+    // d into the second direction buffer, q = A d into q (both free before CG starts)
+    T* dl[3] = {c->arr<T>(L.o_pb[0]), c->arr<T>(L.o_pb[1]), c->arr<T>(L.o_pb[2])};
+    T* q[3] = {c->arr<T>(L.o_q[0]), c->arr<T>(L.o_q[1]), c->arr<T>(L.o_q[2])};
+    T* r[3] = {c->arr<T>(L.o_r[0]), c->arr<T>(L.o_r[1]), c->arr<T>(L.o_r[2])};
+    T* z[3] = {c->arr<T>(L.o_z[0]), c->arr<T>(L.o_z[1]), c->arr<T>(L.o_z[2])};
+    T* di[3] = {c->arr<T>(L.o_di[0]), c->arr<T>(L.o_di[1]), c->arr<T>(L.o_di[2])};
     T* u[3] = {c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2])};
-    const T* uo[3] = {c->arr<T>(L.o_uo[0]), c->arr<T>(L.o_uo[1]), c->arr<T>(L.o_uo[2])};
-    hipLaunchKernelGGL((k_learned_start<T>), dim3(2048), dim3(pfn::CNT), 0, st, u[0], u[1], u[2], uo[0], uo[1], uo[2],
+    hipLaunchKernelGGL((k_learned_delta<T>), dim3(2048), dim3(pfn::CNT), 0, st, dl[0], dl[1], dl[2],
                        (const float*)nn->out, (const double*)nn->dscal, L.g);
-    // judge: ||b - A u||^2 for both starts
-    ElastArgs<T> t = e;
-    t.part = part;
-    for (int d = 0; d < 3; ++d) t.u[d] = u[d];
-    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_TRUE>), L.gel, dim3(NT), 0, st, t); });
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part, L.nb_el, c->scal(), (int)S_JL);
-    for (int d = 0; d < 3; ++d) t.u[d] = const_cast<T*>(uo[d]);
-    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_TRUE>), L.gel, dim3(NT), 0, st, t); });
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part, L.nb_el, c->scal(), (int)S_JP);
-    // ||b||^2 from the partials of the b-norm pass
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)c->arr<double>(L.o_part_b), L.nb_el,
-                       c->scal(), (int)S_JB);
-    LAUNCHCHK(c);
-    double js[3];
-    HIPCHK(c, hipMemcpyAsync(js, c->scal() + S_JL, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-    const double bb = js[2];
-    c->r0_learned = bb > 0.0 ? std::sqrt(js[0] / bb) : 0.0;
-    c->r0_prev = bb > 0.0 ? std::sqrt(js[1] / bb) : 0.0;
-    if (js[0] < js[1]) {
-      c->warm_used = PF_WARM_LEARNED;
-    } else {
-      for (int d = 0; d < 3; ++d)
-        HIPCHK(c, hipMemcpyAsync(u[d], uo[d], (size_t)L.g.n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    ElastArgs<T> ap = e;
+    ap.plain = 1;
+    ap.kz = L.kz_ap;
+    ap.part = part;
+    for (int d = 0; d < 3; ++d) {
+      ap.z[d] = dl[d];
+      ap.u[d] = c->arr<T>(L.o_pa[d]);      // previous direction: multiplied by 0
+      ap.o1[d] = c->arr<T>(L.o_pa[d]);     // receives a copy of d
+      ap.o2[d] = q[d];
     }
+    timed(c, PF_K_OTHER, [&] {
+      hipLaunchKernelGGL((k_apply3<T, kApplyBY>), L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
+    });
+    const long n = L.g.n;
+    double* part_u = c->arr<double>(L.o_part_u);
+    hipLaunchKernelGGL((k_judge_norm<T>), dim3(L.nb_el), dim3(NT), 0, st, (const T*)r[0], (const T*)r[1], (const T*)r[2],
+                       (const T*)q[0], (const T*)q[1], (const T*)q[2], n, part);
+    hipLaunchKernelGGL(k_judge_decide, dim3(1), dim3(NT), 0, st, (const double*)part, (const double*)(part_u + L.nb_el),
+                       L.nb_el, c->scal());
+    hipLaunchKernelGGL((k_judge_apply<T>), dim3(L.nb_el), dim3(NT), 0, st, u[0], u[1], u[2], (const T*)dl[0],
+                       (const T*)dl[1], (const T*)dl[2], r[0], r[1], r[2], (const T*)q[0], (const T*)q[1],
+                       (const T*)q[2], (const T*)di[0], (const T*)di[1], (const T*)di[2], z[0], z[1], z[2], n,
+                       (const double*)c->scal(), part_u);
+    LAUNCHCHK(c);
+    c->judged = true;
   }
   return PF_OK;
 }
