@@ -213,6 +213,28 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def measure_copy_peak(mib=1024, reps=20):
+    """Device-to-device copy bandwidth (read + write bytes per second) of a
+    plain 1 GiB copy: the practical HBM ceiling on this machine."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / sec / 1e9
+
+
 def train_learned(wl, args):
     """Record the plain method's first solves of the recipe, train the network
     on random 64^3 crops of them (offline, untimed) and return the state at the
@@ -288,6 +310,7 @@ def main():
     if args.workload == "batch":
         run_batch(args)
         return
+    copy_peak = measure_copy_peak()
 
     from paper_2111_11538_amd import inputs as I
     wl = I.workload(args.workload, n=args.n)
@@ -336,6 +359,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_source": traffic_src,
+                     "torch_copy_GBps": round(copy_peak, 1),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)},
         "kernels": kernels,
     }

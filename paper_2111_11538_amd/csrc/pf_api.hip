@@ -39,6 +39,7 @@ struct Layout {
   size_t o_r[3], o_z[3], o_pa[3], o_pb[3], o_q[3], o_di[3];
   size_t o_scal, o_part_u, o_part_a, o_part_b, o_part_c, o_stage;
   size_t o_uo[3], o_du[3], o_phiprev;   // learned start only
+  size_t o_b[3];                        // 3D: right-hand side b of the equilibrium solve
   size_t total;
 };
 
@@ -109,6 +110,8 @@ Layout make_layout(const pf_config* c) {
     L.o_r[d] = take(arr); L.o_z[d] = take(arr); L.o_pa[d] = take(arr);
     L.o_pb[d] = take(arr); L.o_q[d] = take(arr); L.o_di[d] = take(arr);
   }
+  if (c->dim == 3)
+    for (int d = 0; d < 3; ++d) L.o_b[d] = take(arr);
   L.o_scal = take(S_COUNT * sizeof(double));
   int nbmax = std::max(std::max(L.nb_el, (int)(L.gap.x * L.gap.y * L.gap.z)), std::max(L.nb_cell, L.nb_upd));
   L.o_part_u = take(2 * (size_t)nbmax * sizeof(double));
@@ -288,6 +291,28 @@ struct Impl {
     return PF_OK;
   }
 
+  // q = A x on the 3D apply kernel outside the CG recurrence (x into z's
+  // place; the direction buffer pa receives a copy of x).
+  static void apply_plain(pf_ctx* c, const ElastArgs<T>& e, T* x0, T* x1, T* x2, double* part) {
+    if constexpr (DIM == 3) {
+      const Layout& L = c->L;
+      ElastArgs<T> ap = e;
+      ap.plain = 1;
+      ap.kz = L.kz_ap;
+      ap.part = part;
+      T* x[3] = {x0, x1, x2};
+      for (int d = 0; d < 3; ++d) {
+        ap.z[d] = x[d];
+        ap.u[d] = c->arr<T>(L.o_pa[d]);
+        ap.o1[d] = c->arr<T>(L.o_pa[d]);
+        ap.o2[d] = c->arr<T>(L.o_q[d]);
+      }
+      timed(c, PF_K_SOLVE_SETUP, [&] {
+        hipLaunchKernelGGL((k_apply3<T, kApplyBY>), L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, c->stream, ap);
+      });
+    }
+  }
+
   // Solve A u = b for the current phase fields and plastic strain.
   static pf_status solve(pf_ctx* c, int warm) {
     const Layout& L = c->L;
@@ -306,22 +331,51 @@ struct Impl {
     double* part_u = c->arr<double>(L.o_part_u);
     double* part_a = c->arr<double>(L.o_part_a);
     double* part_b = c->arr<double>(L.o_part_b);
-    // ||b||^2
-    e.part = part_b;
-    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_BNORM>), L.gel, dim3(NT), 0, st, e); });
-    // r = b - A u, D^-1, z, and the partials of r.z and r.r
-    ElastArgs<T> r = e;
-    for (int d = 0; d < DIM; ++d) {
-      r.u[d] = c->arr<T>(L.o_u[d]);
-      r.o1[d] = c->arr<T>(L.o_r[d]);
-      r.o2[d] = c->arr<T>(L.o_z[d]);
-      r.dinv[d] = c->arr<T>(L.o_di[d]);
+    if constexpr (DIM == 3) {
+      // b, D^-1 and the partials of ||b||^2 in one pass; then r = b - A u from
+      // the apply kernel, z = D^-1 r and the partials CG starts from
+      ElastArgs<T> sa = e;
+      sa.part = part_b;
+      for (int d = 0; d < 3; ++d) {
+        sa.o1[d] = c->arr<T>(L.o_b[d]);
+        sa.dinv[d] = c->arr<T>(L.o_di[d]);
+      }
+      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, 3, M_SETUP>), L.gel, dim3(NT), 0, st, sa); });
+      apply_plain(c, e, c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2]), part_a);
+      ResidQArgs<T> rq{};
+      for (int d = 0; d < 3; ++d) {
+        rq.u[d] = c->arr<T>(L.o_u[d]);
+        rq.q[d] = c->arr<T>(L.o_q[d]);
+        rq.b[d] = c->arr<T>(L.o_b[d]);
+        rq.dinv[d] = c->arr<T>(L.o_di[d]);
+        rq.r[d] = c->arr<T>(L.o_r[d]);
+        rq.z[d] = c->arr<T>(L.o_z[d]);
+      }
+      rq.part_in = part_b;
+      rq.n_in = L.nb_el;
+      rq.part = part_u;
+      rq.scal = c->scal();
+      rq.n = L.g.n;
+      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_resid_q<T>), dim3(L.nb_el), dim3(NT), 0, st, rq); });
+      LAUNCHCHK(c);
+    } else {
+      // ||b||^2
+      e.part = part_b;
+      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_BNORM>), L.gel, dim3(NT), 0, st, e); });
+      // r = b - A u, D^-1, z, and the partials of r.z and r.r
+      ElastArgs<T> r = e;
+      for (int d = 0; d < DIM; ++d) {
+        r.u[d] = c->arr<T>(L.o_u[d]);
+        r.o1[d] = c->arr<T>(L.o_r[d]);
+        r.o2[d] = c->arr<T>(L.o_z[d]);
+        r.dinv[d] = c->arr<T>(L.o_di[d]);
+      }
+      r.part_in = part_b;
+      r.n_in = L.nb_el;
+      r.part = part_u;
+      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_RESID>), L.gel, dim3(NT), 0, st, r); });
+      LAUNCHCHK(c);
     }
-    r.part_in = part_b;
-    r.n_in = L.nb_el;
-    r.part = part_u;
-    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_RESID>), L.gel, dim3(NT), 0, st, r); });
-    LAUNCHCHK(c);
     c->warm_used = warm == PF_WARM_LEARNED ? PF_WARM_PREV : warm;
     if (warm == PF_WARM_LEARNED) {
       pf_status s = learned_start<T, DIM>(c, e, part_a);
@@ -401,10 +455,19 @@ struct Impl {
     for (auto& pr : c->pending)
       if (pr.launch >= c->last_iters && (pr.kind == PF_K_APPLY || pr.kind == PF_K_UPDATE)) pr.kind = PF_K_OTHER;
     // true residual ||b - A u||
-    ElastArgs<T> t = e;
-    for (int d = 0; d < DIM; ++d) t.u[d] = c->arr<T>(L.o_u[d]);
-    t.part = part_b;
-    timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_TRUE>), L.gel, dim3(NT), 0, st, t); });
+    if constexpr (DIM == 3) {
+      apply_plain(c, e, c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2]), part_a);
+      timed(c, PF_K_SOLVE_SETUP, [&] {
+        hipLaunchKernelGGL((k_true_q<T>), dim3(L.nb_el), dim3(NT), 0, st, (const T*)c->arr<T>(L.o_b[0]),
+                           (const T*)c->arr<T>(L.o_b[1]), (const T*)c->arr<T>(L.o_b[2]), (const T*)c->arr<T>(L.o_q[0]),
+                           (const T*)c->arr<T>(L.o_q[1]), (const T*)c->arr<T>(L.o_q[2]), (long)L.g.n, part_b);
+      });
+    } else {
+      ElastArgs<T> t = e;
+      for (int d = 0; d < DIM; ++d) t.u[d] = c->arr<T>(L.o_u[d]);
+      t.part = part_b;
+      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_TRUE>), L.gel, dim3(NT), 0, st, t); });
+    }
     timed(c, PF_K_OTHER, [&] {
       hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part_b, L.nb_el, c->scal(), (int)S_TRUE);
     });

@@ -16,7 +16,10 @@
 
 namespace pfk {
 
-enum ElastMode { M_APPLY = 0, M_RESID = 1, M_BNORM = 2, M_TRUE = 3 };
+enum ElastMode { M_APPLY = 0, M_RESID = 1, M_BNORM = 2, M_TRUE = 3, M_SETUP = 4 };
+// M_SETUP: like M_BNORM (u taken as zero) but also stores b (in o1) and the
+// inverse diagonal of A (in dinv); the residual of any u then follows from
+// q = A u on the apply kernel.
 
 template <typename T>
 struct ElastArgs {
@@ -54,7 +57,7 @@ __device__ __forceinline__ int L(int ly, int lx) { return ly * LW + lx; }
 template <typename T, int DIM, int MODE>
 struct ElastSmem {
   static constexpr int D3 = (DIM == 3) ? LS : 1;
-  static constexpr int R3 = (MODE == M_RESID && DIM == 3) ? LS : 1;
+  static constexpr int R3 = ((MODE == M_RESID || MODE == M_SETUP) && DIM == 3) ? LS : 1;
   double red[NT / 64];
   T sP[2][DIM][LS];
   T sK[LS];
@@ -114,7 +117,7 @@ __device__ __forceinline__ void elast_tile(const ElastArgs<T>& a, int bx, int by
       for (int c = 0; c < DIM; ++c) {
         T v = T(0);
         if (in) {
-          if (MODE == M_BNORM) v = T(0);
+          if (MODE == M_BNORM || MODE == M_SETUP) v = T(0);
           else v = zero_u ? T(0) : a.u[c][e];
         }
         sP[slot][c][t] = v;
@@ -217,7 +220,7 @@ __device__ __forceinline__ void elast_tile(const ElastArgs<T>& a, int bx, int by
         }
         sSxz[out][c] = sxz;
         sSyz[out][c] = syz;
-        if constexpr (MODE == M_RESID) {
+        if constexpr (MODE == M_RESID || MODE == M_SETUP) {
           sGxz[out][c] = gxz;
           sGyz[out][c] = gyz;
         }
@@ -297,7 +300,7 @@ __device__ __forceinline__ void elast_tile(const ElastArgs<T>& a, int bx, int by
       if constexpr (DIM == 3) {
         if (k > 0) q[2] = szz_prev - sSzz[c] + sSxz[sk][c] - sSxz[sk][c + 1] + sSyz[sk][c] - sSyz[sk][c + LW];
       }
-      if constexpr (MODE == M_RESID) {
+      if constexpr (MODE == M_RESID || MODE == M_SETUP) {
         // inverse diagonal: (M_left + M_right + adjacent interior edge G_e) / h
         T Mc = sK[c] + T(4.0 / 3.0) * sG[sk][c];
         T d[3] = {T(0), T(0), T(0)};
@@ -322,13 +325,18 @@ __device__ __forceinline__ void elast_tile(const ElastArgs<T>& a, int bx, int by
         for (int cc = 0; cc < DIM; ++cc) {
           T di = d[cc] > T(0) ? T(1) / (d[cc] * ih) : T(0);
           T r = -q[cc];
-          T zz = di * r;
-          a.o1[cc][e] = r;
-          a.o2[cc][e] = zz;
           a.dinv[cc][e] = di;
-          if (zero_u) a.u[cc][e] = T(0);
-          acc0 += (double)r * (double)zz;
-          acc1 += (double)r * (double)r;
+          if constexpr (MODE == M_SETUP) {       // u = 0: r is b
+            a.o1[cc][e] = r;
+            acc0 += (double)r * (double)r;
+          } else {
+            T zz = di * r;
+            a.o1[cc][e] = r;
+            a.o2[cc][e] = zz;
+            if (zero_u) a.u[cc][e] = T(0);
+            acc0 += (double)r * (double)zz;
+            acc1 += (double)r * (double)r;
+          }
         }
       } else {
 #pragma unroll
@@ -363,6 +371,72 @@ __global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
   }
   __shared__ __align__(16) char smem[sizeof(ElastSmem<T, DIM, MODE>)];
   elast_tile<T, DIM, MODE>(a, blockIdx.x, blockIdx.y, blockIdx.z, zero_u, bid, nblk, smem);
+}
+
+// Residual of u from q = A u and the stored b (3D): r = b - q, z = D^-1 r,
+// partials of r.z and r.r (one pair per block, as the residual pass writes
+// them); also opens the solve's device scalars (||b||^2 from the b-norm
+// partials).  With b = 0 the solution is u = 0.
+template <typename T>
+struct ResidQArgs {
+  T* u[3];
+  const T* q[3];           // A u
+  const T* b[3];
+  const T* dinv[3];
+  T* r[3];
+  T* z[3];
+  const double* part_in;   // ||b||^2 partials
+  int n_in;
+  double* part;            // out: r.z and r.r partials, [2][gridDim.x]
+  double* scal;
+  long n;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_resid_q(ResidQArgs<T> a) {
+  __shared__ double red[NT / 64];
+  const double bb = sum_partials(a.part_in, a.n_in, red);
+  const bool zero_u = bb == 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal[S_BB] = bb;
+    a.scal[S_FIRST] = 1.0;
+    a.scal[S_CONV] = 0.0;
+    a.scal[S_ITERS] = 0.0;
+  }
+  double rz = 0.0, rr = 0.0;
+  for (long e = blockIdx.x * (long)NT + threadIdx.x; e < a.n; e += (long)gridDim.x * NT) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T r = zero_u ? T(0) : a.b[c][e] - a.q[c][e];
+      const T z = a.dinv[c][e] * r;
+      a.r[c][e] = r;
+      a.z[c][e] = z;
+      if (zero_u) a.u[c][e] = T(0);
+      rz += (double)r * (double)z;
+      rr += (double)r * (double)r;
+    }
+  }
+  rz = block_sum(rz, red);
+  rr = block_sum(rr, red);
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = rz;
+    a.part[gridDim.x + blockIdx.x] = rr;
+  }
+}
+
+// Partials of ||b - q||^2 (the true residual when q = A u).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_true_q(const T* __restrict__ b0, const T* __restrict__ b1, const T* __restrict__ b2,
+                                              const T* __restrict__ q0, const T* __restrict__ q1, const T* __restrict__ q2,
+                                              long n, double* __restrict__ part) {
+  __shared__ double red[NT / 64];
+  double acc = 0.0;
+  for (long e = blockIdx.x * (long)NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
+    const double x = (double)b0[e] - (double)q0[e], y = (double)b1[e] - (double)q1[e], w = (double)b2[e] - (double)q2[e];
+    acc += x * x + y * y + w * w;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1275,16 +1349,27 @@ __global__ __launch_bounds__(NT) void k_ledger(const double* part, int n, double
     }
     return;
   }
-  double O = sum_partials(part, n, red), H = sum_partials(part + n, n, red), X = sum_partials(part + 2 * n, n, red);
-  double bo = sum_partials(part + 3 * n, n, red), bh = sum_partials(part + 4 * n, n, red);
-  double vm = 0.0, ep = 0.0;
+  // one pass over the eight partial arrays (the same per-thread order as
+  // sum_partials, so the sums are unchanged), all loads of an index in flight together
+  double O = 0.0, H = 0.0, X = 0.0, bo = 0.0, bh = 0.0, vm = 0.0, ep = 0.0, nf = 0.0;
   for (int q = threadIdx.x; q < n; q += NT) {
+    O += part[q];
+    H += part[n + q];
+    X += part[2 * n + q];
+    bo += part[3 * n + q];
+    bh += part[4 * n + q];
     vm = fmax(vm, part[5 * n + q]);
     ep = fmax(ep, part[6 * n + q]);
+    nf += part[7 * n + q];
   }
+  O = block_sum(O, red);
+  H = block_sum(H, red);
+  X = block_sum(X, red);
+  bo = block_sum(bo, red);
+  bh = block_sum(bh, red);
   vm = block_max(vm, red);
   ep = block_max(ep, red);
-  double nf = sum_partials(part + 7 * n, n, red);
+  nf = block_sum(nf, red);
   if (threadIdx.x == 0) {
     scal[S_OOUT] += area_dt * bo;
     scal[S_HOUT] += area_dt * bh;
