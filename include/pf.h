@@ -174,10 +174,14 @@ typedef enum {
 } pf_kernel_kind;
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch.  enable = 1 clears the accumulators and starts recording,
- * 0 stops.  Recording adds a few microseconds per launch; leave it off for
- * throughput runs. */
-pf_status pf_timing(pf_ctx *ctx, int enable);
+ * the launches of the selected kinds.  kinds is a bit mask of
+ * (1 << pf_kernel_kind) values (PF_TIMING_ALL selects every kind); a nonzero
+ * mask clears the accumulators and starts recording, 0 stops.  Each recorded
+ * launch costs a few microseconds of stream time and the stream is
+ * synchronised once per solve while recording; leave it off, or restrict it
+ * to one kind, for throughput runs. */
+#define PF_TIMING_ALL ((1 << PF_K_COUNT) - 1)
+pf_status pf_timing(pf_ctx *ctx, int kinds);
 
 /* Accumulated device time (ms) and launch count of one pf_kernel_kind since
  * timing was enabled.  Synchronises the stream. */

@@ -163,12 +163,13 @@ struct pf_ctx {
   int last_iters;
   int warm_used;
   // per-kernel event timing
-  bool timing;
+  unsigned timing;         // bit mask of the kernel kinds being recorded (0: off)
   std::vector<hipEvent_t> ev_pool;
   struct Rec { int kind, ev, launch; };
   std::vector<Rec> pending;   // start event index ev, stop ev + 1; launch = CG launch index or -1
   long long iters_total;
   int ev_next;
+  long long n_flush;       // timing flushes so far (a flush empties `pending`)
   double t_ms[PF_K_COUNT];
   long long t_n[PF_K_COUNT];
   // learned start
@@ -214,12 +215,13 @@ static void timing_flush(pf_ctx* c) {
   }
   c->pending.clear();
   c->ev_next = 0;
+  ++c->n_flush;
 }
 
 // Launch helper: brackets the launch with events when timing is on.
 template <typename F>
 static void timed(pf_ctx* c, int kind, F&& launch, int cg_launch = -1) {
-  if (!c->timing) {
+  if (!((c->timing >> kind) & 1u)) {
     launch();
     return;
   }
@@ -317,10 +319,18 @@ struct Impl {
   static pf_status solve(pf_ctx* c, int warm) {
     const Layout& L = c->L;
     hipStream_t st = c->stream;
-    if (c->timing) {   // keep every launch of this solve in the pending list until it is retagged below
-      HIPCHK(c, hipStreamSynchronize(st));
-      timing_flush(c);
+    // Every launch of this solve stays in the pending list until it is
+    // retagged below: flush (which waits for the stream) only when the event
+    // pool might not hold a whole solve.
+    if (c->timing) {
+      const long long need = 4LL * (2LL * c->cfg.cg_max_iter + 256);
+      if (c->ev_next + need > (long long)c->ev_pool.size()) {
+        HIPCHK(c, hipStreamSynchronize(st));
+        timing_flush(c);
+      }
     }
+    const size_t pend0 = c->pending.size();
+    const long long flush0 = c->n_flush;
     if (warm == PF_WARM_ZERO)
       for (int d = 0; d < DIM; ++d) HIPCHK(c, hipMemsetAsync(c->ws + L.o_u[d], 0, (size_t)L.g.n * sizeof(T), st));
     c->warm_used = warm;
@@ -451,9 +461,13 @@ struct Impl {
       c->r0_learned = 0.0;
       c->r0_prev = 0.0;
     }
-    // launches queued past convergence exit at entry: account them as small kernels
-    for (auto& pr : c->pending)
+    // launches queued past convergence exit at entry: account them as small
+    // kernels (only this solve's entries; after a flush inside a very long
+    // solve, the ones still pending)
+    for (size_t q = c->n_flush == flush0 ? pend0 : 0; q < c->pending.size(); ++q) {
+      auto& pr = c->pending[q];
       if (pr.launch >= c->last_iters && (pr.kind == PF_K_APPLY || pr.kind == PF_K_UPDATE)) pr.kind = PF_K_OTHER;
+    }
     // true residual ||b - A u||
     if constexpr (DIM == 3) {
       apply_plain(c, e, c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2]), part_a);
@@ -574,8 +588,9 @@ pf_status pf_init(const pf_config* cfg, const pf_params* params, void* workspace
   c->steps = 0;
   c->last_iters = 0;
   c->warm_used = cfg->warm;
-  c->timing = false;
+  c->timing = 0u;
   c->ev_next = 0;
+  c->n_flush = 0;
   c->iters_total = 0;
   c->net = nullptr;
   c->have_prev_incr = false;
@@ -702,18 +717,19 @@ pf_status pf_fields(pf_ctx* c, int field_id, int dir, void* ptr, size_t nbytes, 
   return PF_OK;
 }
 
-pf_status pf_timing(pf_ctx* c, int enable) {
+pf_status pf_timing(pf_ctx* c, int kinds) {
   if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  if (kinds & ~PF_TIMING_ALL) return fail(c, PF_ERR_INVALID_ARG, "timing mask 0x%x has bits beyond the kernel kinds", kinds);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   timing_flush(c);
-  if (enable) {
+  if (kinds) {
     if (c->ev_pool.empty()) {
       c->ev_pool.resize(32768);
       for (auto& e : c->ev_pool) HIPCHK(c, hipEventCreate(&e));
     }
     for (int k = 0; k < PF_K_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
   }
-  c->timing = enable != 0;
+  c->timing = (unsigned)kinds;
   return PF_OK;
 }
 

@@ -21,6 +21,8 @@ struct InstDesc {
   int ap0, apn;    // range in the apply tile table
   int ce0, cen;    // range in the cell tile table
   int up0, upn;    // range in the update chunk table
+  int apf0, apfn;  // range of the fine apply tiles (fewer rows per tile)
+  int upf0, upfn;  // range of the fine update chunks
 };
 struct TileRef {
   int inst, bx, by, bz;
@@ -66,7 +68,8 @@ struct BatchArgs {
   unsigned* bar;           // {arrivals, generation, error}
   double tol2;
   int max_iter;
-  int kz_ap;
+  int kz_ap;                  // rows per coarse apply tile
+  int kz_apf;                 // rows per fine apply tile
   double area_dt;
   double vol;
   long long spin_limit;
@@ -174,18 +177,56 @@ __device__ __forceinline__ double range_sum(const double* part, int r0, int n) {
   return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
-// Inclusive prefix sums over the instances of a per-instance count (zero for
-// converged instances), in shared memory; count <= NT.
-__device__ __forceinline__ void active_scan(int* sh, int v, int count) {
-  const int t = threadIdx.x;
-  if (t < count) sh[t] = v;
-  __syncthreads();
-  for (int o = 1; o < count; o <<= 1) {
-    const int add = (t < count && t >= o) ? sh[t - o] : 0;
-    __syncthreads();
-    if (t < count) sh[t] += add;
-    __syncthreads();
+// Inclusive prefix sums over the instances of two per-instance counts (zero
+// for converged instances) into shared memory; count <= NT.  Wave-level
+// shuffle scans, then the wave totals; two block synchronisations.
+__device__ __forceinline__ void active_scan2(int* sha, int* shb, int va, int vb, int count) {
+  __shared__ int tot[2][NT / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t >= count) va = vb = 0;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int xa = __shfl_up(va, o, 64), xb = __shfl_up(vb, o, 64);
+    if (lane >= o) { va += xa; vb += xb; }
   }
+  if (lane == 63) { tot[0][w] = va; tot[1][w] = vb; }
+  __syncthreads();
+  for (int q = 0; q < w; ++q) { va += tot[0][q]; vb += tot[1][q]; }
+  if (t < count) { sha[t] = va; shb[t] = vb; }
+  __syncthreads();
+}
+
+// Per-instance sums of the partial ranges [r0(b), r0(b) + rn(b)) of two
+// partial arrays, eight lanes per instance with a fixed split and combination
+// order, so every block obtains the same values.  Instances with skip[b] set
+// are not summed and keep their outputs.  Ends with a block synchronisation.
+template <typename R0, typename RN>
+__device__ __forceinline__ void instance_sums2(const double* pa, const double* pb, int count, R0 r0, RN rn,
+                                               const int* skip, double* oa, double* ob) {
+  constexpr int kL = 8;
+  const int t = threadIdx.x, q = t & (kL - 1);
+  for (int base = 0; base < count; base += NT / kL) {
+    const int b = base + t / kL;
+    const bool on = b < count && !(skip && skip[b]);
+    double sa = 0.0, sb = 0.0;
+    if (on) {
+      const int a0 = r0(b), n = rn(b);
+      for (int k = q; k < n; k += kL) {
+        sa += pa[a0 + k];
+        if (pb) sb += pb[a0 + k];
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < kL; o <<= 1) {
+      sa += __shfl_xor(sa, o, 64);
+      sb += __shfl_xor(sb, o, 64);
+    }
+    if (on && q == 0) {
+      oa[b] = sa;
+      if (ob) ob[b] = sb;
+    }
+  }
+  __syncthreads();
 }
 
 // Instance b holding active work item w: incl[b-1] <= w < incl[b].
@@ -253,6 +294,9 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
   __shared__ double shA[kMaxBatch], shB[kMaxBatch], shBB[kMaxBatch];
   __shared__ int shC[kMaxBatch];
   __shared__ int shAp[kMaxBatch], shUp[kMaxBatch];   // inclusive prefix sums of active apply tiles / update chunks
+  __shared__ double shRzPrev[kMaxBatch];              // r.z of the previous pass
+  __shared__ double shRR[kMaxBatch], shPQ[kMaxBatch];  // r.r of this pass, p.q
+  __shared__ int up_fine_sh;                          // the last update pass used the fine chunks
   __shared__ int flag_sh, all_sh;
   __shared__ double red[NT / 64];
   __shared__ int grouped_sh;
@@ -286,8 +330,8 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
     elast_tile<T, 2, M_BNORM>(a, tr.bx, tr.by, tr.bz, false, w, B.n_el, smem);
   }
   PF_BARRIER();
-  for (int b = tid; b < B.count; b += NT) shBB[b] = range_sum(B.part_bn, B.inst[b].el0, B.inst[b].eln);
-  __syncthreads();
+  instance_sums2(B.part_bn, nullptr, B.count, [&](int b) { return B.inst[b].el0; },
+                 [&](int b) { return B.inst[b].eln; }, nullptr, shBB, nullptr);
   // (3) initial residual r = b - A u, D^-1, z
   for (int w = blockIdx.x; w < B.n_el; w += nbk) {
     const TileRef tr = B.el[w];
@@ -312,23 +356,28 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
   PF_BARRIER();
 
   // (4) CG, one recurrence per instance
+  if (tid == 0) up_fine_sh = 0;
   for (int L = 0;; ++L) {
+    // r.z and r.r of every instance from the residual / last update partials;
+    // an instance that has converged keeps its flag and its last values
+    if (L == 0) {
+      instance_sums2(B.part_r, B.part_r + B.n_el, B.count, [&](int b) { return B.inst[b].el0; },
+                     [&](int b) { return B.inst[b].eln; }, nullptr, shA, shRR);
+    } else {
+      const double* pu = B.part_u + ((L - 1) & 1) * 2 * B.n_up;
+      if (up_fine_sh)
+        instance_sums2(pu, pu + B.n_up, B.count, [&](int b) { return B.inst[b].upf0; },
+                       [&](int b) { return B.inst[b].upfn; }, shC, shA, shRR);
+      else
+        instance_sums2(pu, pu + B.n_up, B.count, [&](int b) { return B.inst[b].up0; },
+                       [&](int b) { return B.inst[b].upn; }, shC, shA, shRR);
+    }
     for (int b = tid; b < B.count; b += NT) {
-      const InstDesc& d = B.inst[b];
-      double rz, rr, rzp = 1.0;
-      if (L == 0) {
-        rz = range_sum(B.part_r, d.el0, d.eln);
-        rr = range_sum(B.part_r + B.n_el, d.el0, d.eln);
-      } else {
-        const double* pu = B.part_u + ((L - 1) & 1) * 2 * B.n_up;
-        rz = range_sum(pu, d.up0, d.upn);
-        rr = range_sum(pu + B.n_up, d.up0, d.upn);
-        rzp = (L == 1) ? range_sum(B.part_r, d.el0, d.eln) : range_sum(B.part_u + (L & 1) * 2 * B.n_up, d.up0, d.upn);
-      }
-      const int conv = (B.iscal[b * S + S_CONV] != 0.0) || (rr <= B.tol2 * shBB[b]);
+      const double rz = shA[b];
+      const int conv = (L > 0 && shC[b]) || (shRR[b] <= B.tol2 * shBB[b]);
+      shB[b] = (L == 0 || conv) ? 0.0 : rz / shRzPrev[b];
+      if (!conv || L == 0) shRzPrev[b] = rz;
       shC[b] = conv;
-      shA[b] = rz;
-      shB[b] = (L == 0) ? 0.0 : rz / rzp;
     }
     __syncthreads();
     if (tid == 0) {
@@ -337,20 +386,26 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
       all_sh = all;
       for (int b = blockIdx.x; b < B.count; b += nbk) {
         B.iscal[b * S + S_CONV] = (double)shC[b];
-        B.iscal[b * S + S_RR] = shA[b];
+        B.iscal[b * S + S_RR] = shRR[b];
       }
     }
     __syncthreads();
     if (all_sh || L >= B.max_iter) break;
-    // the work items of the instances still iterating, dealt out evenly
+    // the work items of the instances still iterating, dealt out evenly; when
+    // the coarse tiles or chunks of those instances would leave blocks idle,
+    // the fine ones (a quarter of the size) are dealt instead
+    bool ap_fine, up_fine;
     {
-      int nap = 0, nup = 0;
-      if (tid < B.count && !shC[tid]) {
-        nap = B.inst[tid].apn;
-        nup = B.inst[tid].upn;
+      const bool act = tid < B.count && !shC[tid];
+      int ca = 0, cu = 0, fa = 0, fu = 0;
+      if (act) {
+        const InstDesc& d = B.inst[tid];
+        ca = d.apn; cu = d.upn; fa = d.apfn; fu = d.upfn;
       }
-      active_scan(shAp, nap, B.count);
-      active_scan(shUp, nup, B.count);
+      active_scan2(shAp, shUp, ca, cu, B.count);
+      ap_fine = shAp[B.count - 1] < (int)nbk;
+      up_fine = shUp[B.count - 1] < (int)nbk;
+      if (ap_fine || up_fine) active_scan2(shAp, shUp, ap_fine ? fa : ca, up_fine ? fu : cu, B.count);
     }
     const int n_ap_act = shAp[B.count - 1], n_up_act = shUp[B.count - 1];
     // apply: q = A p with p = z + beta p
@@ -359,7 +414,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
     for (int wa = blockIdx.x; wa < n_ap_act; wa += nbk) {
       const int ib = active_owner(shAp, B.count, wa);
       const InstDesc& d = B.inst[ib];
-      const int w = d.ap0 + wa - (ib > 0 ? shAp[ib - 1] : 0);
+      const int w = (ap_fine ? d.apf0 : d.ap0) + wa - (ib > 0 ? shAp[ib - 1] : 0);
       const TileRef tr = B.ap[w];
       ElastArgs<T> a = elast_view(B, d);
 #pragma unroll
@@ -370,18 +425,26 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
         a.o2[c] = B.q[c] + d.off;
       }
       a.part = B.part_a;
+      a.kz = ap_fine ? B.kz_apf : B.kz_ap;
       apply2_tile(a, tr.bx, tr.by, shB[tr.inst], L == 0, w, smem);
     }
     PF_BARRIER();
+    // alpha = r.z / p.q of every instance still iterating
+    if (ap_fine)
+      instance_sums2(B.part_a, nullptr, B.count, [&](int b) { return B.inst[b].apf0; },
+                     [&](int b) { return B.inst[b].apfn; }, shC, shPQ, nullptr);
+    else
+      instance_sums2(B.part_a, nullptr, B.count, [&](int b) { return B.inst[b].ap0; },
+                     [&](int b) { return B.inst[b].apn; }, shC, shPQ, nullptr);
     for (int b = tid; b < B.count; b += NT)
-      if (!shC[b]) shB[b] = shA[b] / range_sum(B.part_a, B.inst[b].ap0, B.inst[b].apn);
+      if (!shC[b]) shB[b] = shA[b] / shPQ[b];
     __syncthreads();
     // update: u += alpha p, r -= alpha q, z = D^-1 r
     double* pu = B.part_u + (L & 1) * 2 * B.n_up;
     for (int wu = blockIdx.x; wu < n_up_act; wu += nbk) {
       const int ib = active_owner(shUp, B.count, wu);
       const InstDesc& d = B.inst[ib];
-      const int w = d.up0 + wu - (ib > 0 ? shUp[ib - 1] : 0);
+      const int w = (up_fine ? d.upf0 : d.up0) + wu - (ib > 0 ? shUp[ib - 1] : 0);
       const ChunkRef cr = B.up[w];
       UpdArgs<T> a{};
 #pragma unroll
@@ -405,6 +468,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
     if (tid == 0)
       for (int b = blockIdx.x; b < B.count; b += nbk)
         if (!shC[b]) B.iscal[b * S + S_ITERS] += 1.0;
+    if (tid == 0) up_fine_sh = up_fine ? 1 : 0;       // read by the next pass after the barrier's block sync
     PF_BARRIER();
   }
 

@@ -8,6 +8,8 @@ namespace {
 
 constexpr int kMinApplyRows = 4;       // smallest tuning choices bound the table sizes
 constexpr int kMinChunk = 256;
+inline int fine_rows(int rows) { return std::max(kMinApplyRows, rows / 4); }
+inline int fine_chunk(int chunk) { return std::max(kMinChunk, chunk / 4); }
 
 struct BatchLayout {
   int count;
@@ -60,8 +62,9 @@ BatchLayout make_batch_layout(const pf_config* c, const pf_extent* ext, int coun
     d.off = off;
     off += (d.g.n + 63) / 64 * 64;
     L.n_el += ((d.g.nx + TX - 1) / TX) * ((d.g.ny + TY - 1) / TY);
-    L.max_ap += ((d.g.nx + A2W - 1) / A2W) * ((d.g.ny + kMinApplyRows - 1) / kMinApplyRows);
-    L.max_up += (d.g.n / vn + kMinChunk - 1) / kMinChunk;
+    // coarse and fine tables together, each at most the finest tiling
+    L.max_ap += 2 * ((d.g.nx + A2W - 1) / A2W) * ((d.g.ny + kMinApplyRows - 1) / kMinApplyRows);
+    L.max_up += 2 * ((d.g.n / vn + kMinChunk - 1) / kMinChunk);
     L.stage_elems = std::max(L.stage_elems, (size_t)(d.g.nx + 1) * (d.g.ny + 1));
     L.inst.push_back(d);
   }
@@ -184,6 +187,7 @@ static BatchArgs<T> batch_args(pf_batch* bt, int cur) {
   B.tol2 = bt->cfg.cg_rtol * bt->cfg.cg_rtol;
   B.max_iter = bt->cfg.cg_max_iter;
   B.kz_ap = bt->tiles.apply_rows;
+  B.kz_apf = fine_rows(bt->tiles.apply_rows);
   B.vol = bt->cfg.h * bt->cfg.h;
   B.area_dt = bt->cfg.h * bt->cfg.dt;
   B.spin_limit = bt->tiles.spin_limit;
@@ -197,6 +201,7 @@ static pf_status build_tables(pf_batch* bt) {
   std::vector<ChunkRef> up;
   const int vn = (int)(16 / L.es);
   const int rows = bt->tiles.apply_rows, chunk = bt->tiles.update_chunk;
+  const int rows_f = fine_rows(rows), chunk_f = fine_chunk(chunk);
   for (int b = 0; b < L.count; ++b) {
     InstDesc& d = L.inst[b];
     d.el0 = (int)el.size();
@@ -213,6 +218,19 @@ static pf_status build_tables(pf_batch* bt) {
     const int nv = d.g.n / vn;
     for (int v = 0; v < nv; v += chunk) up.push_back({b, v, std::min(nv, v + chunk), 0});
     d.upn = (int)up.size() - d.up0;
+  }
+  // the fine tables, used in passes where the coarse work of the instances
+  // still iterating would leave blocks idle
+  for (int b = 0; b < L.count; ++b) {
+    InstDesc& d = L.inst[b];
+    d.apf0 = (int)ap.size();
+    for (int by = 0; by < (d.g.ny + rows_f - 1) / rows_f; ++by)
+      for (int bx = 0; bx < (d.g.nx + A2W - 1) / A2W; ++bx) ap.push_back({b, bx, by, 0});
+    d.apfn = (int)ap.size() - d.apf0;
+    d.upf0 = (int)up.size();
+    const int nv = d.g.n / vn;
+    for (int v = 0; v < nv; v += chunk_f) up.push_back({b, v, std::min(nv, v + chunk_f), 0});
+    d.upfn = (int)up.size() - d.upf0;
   }
   if ((int)ap.size() > L.max_ap || (int)up.size() > L.max_up)
     return bfail(bt, PF_ERR_INVALID_ARG, "tile tables exceed their capacity");

@@ -56,6 +56,25 @@ struct Grid {
 
 __device__ __forceinline__ int gidx(const Grid& g, int i, int j, int k) { return (k * g.ny + j) * g.px + i; }
 
+// Raw buffer resources: a load whose byte offset lies past num_records
+// returns zero without touching memory, so a load that may or may not be
+// needed can be issued unconditionally (no branch, so the compiler's wait
+// counts stay exact across it).
+constexpr int kBufferFlags = 0x00020000;     // raw buffer, 32-bit data format (gfx9 family)
+constexpr int kOutOfRange = 0x7FFFFFF0;      // byte offset past any tensor here: the load returns zero
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const T* p, int nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, nbytes, kBufferFlags);
+}
+template <typename T> __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 // MI355X has 8 XCDs, each with its own L2; workgroups are dispatched to them
 // round robin by linear block id.  Map block id b to tile id so that XCD
 // (b mod 8) owns the contiguous tile range [x * nb/8, (x+1) * nb/8).  Identity

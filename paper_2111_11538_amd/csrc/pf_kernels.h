@@ -447,8 +447,10 @@ __global__ __launch_bounds__(NT) void k_true_q(const T* __restrict__ b0, const T
 // registers (so the z neighbours never touch LDS); the x / y neighbours come
 // from an LDS plane tile with a one-cell ring.  The stresses the tile needs on
 // the ring (cell stresses below / left of it, edge stresses above / right of
-// it) are a separate short work list.  Global loads of plane k+3 are issued
-// as raw values while plane k is computed and only combined when stored.
+// it) are a separate short work list.  Global loads run two planes ahead:
+// two register sets hold raw values in flight (plane k+3 and k+4 while plane
+// k is computed), combined only when stored.  A block reads exactly the
+// planes k0-1 .. k1 its slab needs.
 // ---------------------------------------------------------------------------
 template <int BY>
 struct ApplyTile {
@@ -530,39 +532,52 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
   const int own_e = own ? j * g.px + i : 0;
 
   // raw (in-flight) loads of one plane: own column and ring position
-  T oz[3], op[3], og, ok, hz[3], hp[3], hg, hk;
-  bool oin = false, hin = false;
-  auto fetch = [&](int kk) {
-    const bool zin = kk >= 0 && kk < g.nz;
-    oin = own && zin;
-    hin = rg_in && zin;
-    const int eo = oin ? own_e + kk * pl : 0;
-    const int eh = hin ? rg_e + kk * pl : 0;
+  struct Raw {
+    T oz[3], op[3], og, ok, hz[3], hp[3], hg, hk;
+    bool oin, hin;
+  };
+  Raw ra, rb;
+  // loads of cells outside the grid, and of planes the slab does not need
+  // (want == false), are range-checked to zero and fetch nothing
+  const int nbytes = g.n * (int)sizeof(T);
+  __amdgpu_buffer_rsrc_t rz_[3], ru_[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    rz_[d] = buf_rsrc(a.z[d], nbytes);
+    ru_[d] = buf_rsrc(a.u[d], nbytes);
+  }
+  const __amdgpu_buffer_rsrc_t rG = buf_rsrc(a.G, nbytes), rK = buf_rsrc(a.K, nbytes);
+  auto fetch = [&](Raw& R, int kk, bool want) {
+    const bool zin = want && kk >= 0 && kk < g.nz;
+    R.oin = own && zin;
+    R.hin = rg_in && zin;
+    const int eo = R.oin ? (own_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
+    const int eh = R.hin ? (rg_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      oz[d] = a.z[d][eo];
-      op[d] = a.u[d][eo];
-      hz[d] = a.z[d][eh];
-      hp[d] = a.u[d][eh];
+      R.oz[d] = buf_ld<T>(rz_[d], eo);
+      R.op[d] = buf_ld<T>(ru_[d], eo);
+      R.hz[d] = buf_ld<T>(rz_[d], eh);
+      R.hp[d] = buf_ld<T>(ru_[d], eh);
     }
-    og = a.G[eo]; ok = a.K[eo];
-    hg = a.G[eh]; hk = a.K[eh];
+    R.og = buf_ld<T>(rG, eo); R.ok = buf_ld<T>(rK, eo);
+    R.hg = buf_ld<T>(rG, eh); R.hk = buf_ld<T>(rK, eh);
   };
   // combine, store the plane into LDS slot `slot`, and return the own values
-  auto stash = [&](int slot, T (&vp)[3], T& vg, T& vk) {
+  auto stash = [&](const Raw& R, int slot, T (&vp)[3], T& vg, T& vk) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) vp[d] = oin ? (first ? oz[d] : oz[d] + tb * op[d]) : T(0);
-    vg = oin ? og : T(0);
-    vk = oin ? ok : T(0);
+    for (int d = 0; d < 3; ++d) vp[d] = R.oin ? (first ? R.oz[d] : R.oz[d] + tb * R.op[d]) : T(0);
+    vg = R.oin ? R.og : T(0);
+    vk = R.oin ? R.ok : T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) sP[slot][d][c] = vp[d];
     sG[slot][c] = vg;
     sK[slot][c] = vk;
     if (rg_t < S) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) sP[slot][d][rg_t] = hin ? (first ? hz[d] : hz[d] + tb * hp[d]) : T(0);
-      sG[slot][rg_t] = hin ? hg : T(0);
-      sK[slot][rg_t] = hin ? hk : T(0);
+      for (int d = 0; d < 3; ++d) sP[slot][d][rg_t] = R.hin ? (first ? R.hz[d] : R.hz[d] + tb * R.hp[d]) : T(0);
+      sG[slot][rg_t] = R.hin ? R.hg : T(0);
+      sK[slot][rg_t] = R.hin ? R.hk : T(0);
     }
   };
   // stresses from LDS at tile position q (all neighbours from LDS)
@@ -627,13 +642,16 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
   T pc[3], gc, kc, pn[3], gn, kn;     // own values of planes k (c) and k+1 (n)
   T szz_prev = T(0), sxz_c = T(0), syz_c = T(0);
 
-  // prologue: planes k0-1, k0; sigma_zz of the own cell below; z edges at level k0
+  // prologue: planes k0-1, k0; sigma_zz of the own cell below; z edges at
+  // level k0.  Plane m travels in register set ra when m - k0 is odd.
   {
     T pb[3], gb, kb;
-    fetch(k0 - 1);
-    stash((k0 - 1) & 1, pb, gb, kb);
-    fetch(k0);
-    stash(k0 & 1, pc, gc, kc);
+    fetch(ra, k0 - 1, true);
+    fetch(rb, k0, true);
+    stash(ra, (k0 - 1) & 1, pb, gb, kb);
+    stash(rb, k0 & 1, pc, gc, kc);
+    fetch(ra, k0 + 1, true);
+    fetch(rb, k0 + 2, k0 + 1 < k1);
     __syncthreads();
     const int sa = (k0 - 1) & 1, sb = k0 & 1;
     if (k0 > 0) {
@@ -650,14 +668,14 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
     sSyz[sb][c] = syz_c;
     ring_items(sa, sb, k0, sa, sb, sb, false);
     __syncthreads();
-    fetch(k0 + 1);
-    stash((k0 + 1) & 1, pn, gn, kn);
-    fetch(k0 + 2);
+    stash(ra, (k0 + 1) & 1, pn, gn, kn);
+    fetch(ra, k0 + 3, k0 + 2 < k1);
     __syncthreads();
   }
 
   double acc = 0.0;
-  for (int k = k0; k < k1; ++k) {
+  // one plane; R carries plane k+2 in and is refilled with plane k+4
+  auto plane = [&](int k, Raw& R) {
     const int sk = k & 1, sk1 = (k + 1) & 1;
     // (A) own stresses of plane k and own z edges at level k+1
     const T exx = (sP[sk][0][c + 1] - pc[0]) * ih;
@@ -710,11 +728,19 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
       for (int d = 0; d < 3; ++d) pc[d] = pn[d];
       gc = gn;
       kc = kn;
-      stash(sk, pn, gn, kn);   // plane k+2 into the slot of plane k
-      fetch(k + 3);
+      stash(R, sk, pn, gn, kn);   // plane k+2 into the slot of plane k
     }
+    fetch(R, k + 4, k + 3 < k1);
     __syncthreads();
+  };
+  // pairs of planes, so that every path into a plane has the same loads in
+  // flight (the wait counts then let the newer set stay outstanding)
+  int k = k0;
+  for (; k + 1 < k1; k += 2) {
+    plane(k, rb);
+    plane(k + 1, ra);
   }
+  if (k < k1) plane(k, rb);
   const double s0 = block_sum_n<NTB>(acc, red);
   if (threadIdx.x == 0) a.part[bid] = s0;
 }

@@ -69,8 +69,6 @@ constexpr int k_chunks() { return (kTaps * CIN + 31) / 32; }
 constexpr int CONV_WAVES = 8;              // waves (rows of a tile) per convolution block
 constexpr int CONV_NT = CONV_WAVES * 64;
 
-constexpr int kBufferFlags = 0x00020000;     // raw buffer, 32-bit data format (gfx9 family)
-constexpr int kOutOfRange = 0x7FFFFFF0;      // byte offset past any tensor here: the load returns zero
 
 // Input fragment of one 16-voxel column block for k chunk kc: lane (lr, lg)
 // holds the 8 channels ci0..ci0+7 of voxel (x + lr + dx, y + dy, z + dz),

@@ -280,8 +280,15 @@ class Context:
         self._check(lib().pf_mech_solve(self.ctx, WARM[warm], C.byref(st)))
         return st.as_dict()
 
-    def timing(self, enable=True):
-        self._check(lib().pf_timing(self.ctx, int(enable)))
+    def timing(self, enable=True, kinds=None):
+        """Start (or with enable False stop) event timing of the named kernel
+        kinds (all of them by default)."""
+        mask = 0
+        if enable:
+            names = KERNEL_KINDS if kinds is None else kinds
+            for n in names:
+                mask |= 1 << KERNEL_KINDS.index(n)
+        self._check(lib().pf_timing(self.ctx, mask))
 
     def timing_report(self):
         out = {}
