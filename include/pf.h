@@ -183,6 +183,15 @@ typedef enum {
 #define PF_TIMING_ALL ((1 << PF_K_COUNT) - 1)
 pf_status pf_timing(pf_ctx *ctx, int kinds);
 
+/* Sampling of the CG kernels (PF_K_APPLY, PF_K_UPDATE) while timing: only
+ * the launches of every `every`-th CG iteration are timed, with the phase
+ * advancing by one per solve (solve s times iterations i with (i + s) a
+ * multiple of every), so that over many solves every iteration index is
+ * sampled alike; the reported totals and launch counts cover that sample.
+ * every >= 1 (1, the default, times all).  Other kinds are always timed in
+ * full. */
+pf_status pf_timing_every(pf_ctx *ctx, int every);
+
 /* Accumulated device time (ms) and launch count of one pf_kernel_kind since
  * timing was enabled.  Synchronises the stream. */
 pf_status pf_timing_get(pf_ctx *ctx, int kind, double *total_ms, long long *launches);

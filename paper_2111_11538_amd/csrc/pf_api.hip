@@ -2,6 +2,7 @@
 // device-side CG control and field exchange.  Every numerical step runs in the
 // kernels of pf_kernels.h.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -161,9 +162,12 @@ struct pf_ctx {
   int cur;                 // which field buffer holds the current state
   long long steps;
   int last_iters;
+  int prev_iters;          // iteration count of the solve before the last one
   int warm_used;
   // per-kernel event timing
   unsigned timing;         // bit mask of the kernel kinds being recorded (0: off)
+  int timing_every;        // CG kernels: record every n-th iteration only
+  long long solves;        // solves started (rotates the sampled iterations)
   std::vector<hipEvent_t> ev_pool;
   struct Rec { int kind, ev, launch; };
   std::vector<Rec> pending;   // start event index ev, stop ev + 1; launch = CG launch index or -1
@@ -221,7 +225,7 @@ static void timing_flush(pf_ctx* c) {
 // Launch helper: brackets the launch with events when timing is on.
 template <typename F>
 static void timed(pf_ctx* c, int kind, F&& launch, int cg_launch = -1) {
-  if (!((c->timing >> kind) & 1u)) {
+  if (!((c->timing >> kind) & 1u) || (cg_launch >= 0 && (cg_launch + c->solves) % c->timing_every != 0)) {
     launch();
     return;
   }
@@ -235,6 +239,27 @@ static void timed(pf_ctx* c, int kind, F&& launch, int cg_launch = -1) {
   launch();
   (void)hipEventRecord(c->ev_pool[i + 1], c->stream);
   c->pending.push_back({kind, i, cg_launch});
+}
+
+// Launch of one kernel, timed when its kind is being recorded: the events
+// are attached to the dispatch itself (hipExtLaunchKernel), so they measure
+// the kernel's execution without extra marker packets in the stream.
+template <typename K, typename... Args>
+static void timed_launch(pf_ctx* c, int kind, int cg_launch, K kernel, dim3 grid, dim3 block, uint32_t smem,
+                         hipStream_t st, Args... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (((c->timing >> kind) & 1u) && !(cg_launch >= 0 && (cg_launch + c->solves) % c->timing_every != 0)) {
+    if (c->ev_next + 2 > (int)c->ev_pool.size()) {
+      (void)hipStreamSynchronize(c->stream);
+      timing_flush(c);
+    }
+    const int i = c->ev_next;
+    c->ev_next += 2;
+    e0 = c->ev_pool[i];
+    e1 = c->ev_pool[i + 1];
+    c->pending.push_back({kind, i, cg_launch});
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, smem, st, e0, e1, 0u, args...);
 }
 
 // learned start (defined with the network code at the end of this file)
@@ -285,7 +310,7 @@ struct Impl {
     const Layout& L = c->L;
     CellArgs<T> a = cell_args(c);
     a.part = c->arr<double>(L.o_part_c);
-    timed(c, PF_K_OTHER, [&] { hipLaunchKernelGGL((k_totals<T, DIM>), L.gcell, dim3(NT), 0, c->stream, a); });
+    timed_launch(c, PF_K_OTHER, -1, k_totals<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
     double vol = std::pow(c->cfg.h, DIM);
     hipLaunchKernelGGL(k_ledger, dim3(1), dim3(NT), 0, c->stream, (const double*)a.part, L.nb_cell, c->scal(), vol, 0.0, 0);
     LAUNCHCHK(c);
@@ -309,9 +334,7 @@ struct Impl {
         ap.o1[d] = c->arr<T>(L.o_pa[d]);
         ap.o2[d] = c->arr<T>(L.o_q[d]);
       }
-      timed(c, PF_K_SOLVE_SETUP, [&] {
-        hipLaunchKernelGGL((k_apply3<T, kApplyBY>), L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, c->stream, ap);
-      });
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_apply3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, c->stream, ap);
     }
   }
 
@@ -329,13 +352,14 @@ struct Impl {
         timing_flush(c);
       }
     }
+    ++c->solves;
     const size_t pend0 = c->pending.size();
     const long long flush0 = c->n_flush;
     if (warm == PF_WARM_ZERO)
       for (int d = 0; d < DIM; ++d) HIPCHK(c, hipMemsetAsync(c->ws + L.o_u[d], 0, (size_t)L.g.n * sizeof(T), st));
     c->warm_used = warm;
     CellArgs<T> ca = cell_args(c);
-    timed(c, PF_K_OTHER, [&] { hipLaunchKernelGGL((k_moduli<T, DIM>), L.gcell, dim3(NT), 0, st, ca); });
+    timed_launch(c, PF_K_OTHER, -1, k_moduli<T, DIM>, L.gcell, dim3(NT), 0, st, ca);
 
     ElastArgs<T> e = elast_args(c);
     double* part_u = c->arr<double>(L.o_part_u);
@@ -350,7 +374,7 @@ struct Impl {
         sa.o1[d] = c->arr<T>(L.o_b[d]);
         sa.dinv[d] = c->arr<T>(L.o_di[d]);
       }
-      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, 3, M_SETUP>), L.gel, dim3(NT), 0, st, sa); });
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_elast<T, 3, M_SETUP>, L.gel, dim3(NT), 0, st, sa);
       apply_plain(c, e, c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2]), part_a);
       ResidQArgs<T> rq{};
       for (int d = 0; d < 3; ++d) {
@@ -366,12 +390,12 @@ struct Impl {
       rq.part = part_u;
       rq.scal = c->scal();
       rq.n = L.g.n;
-      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_resid_q<T>), dim3(L.nb_el), dim3(NT), 0, st, rq); });
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_resid_q<T>, dim3(L.nb_el), dim3(NT), 0, st, rq);
       LAUNCHCHK(c);
     } else {
       // ||b||^2
       e.part = part_b;
-      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_BNORM>), L.gel, dim3(NT), 0, st, e); });
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_elast<T, DIM, M_BNORM>, L.gel, dim3(NT), 0, st, e);
       // r = b - A u, D^-1, z, and the partials of r.z and r.r
       ElastArgs<T> r = e;
       for (int d = 0; d < DIM; ++d) {
@@ -383,7 +407,7 @@ struct Impl {
       r.part_in = part_b;
       r.n_in = L.nb_el;
       r.part = part_u;
-      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_RESID>), L.gel, dim3(NT), 0, st, r); });
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_elast<T, DIM, M_RESID>, L.gel, dim3(NT), 0, st, r);
       LAUNCHCHK(c);
     }
     c->warm_used = warm == PF_WARM_LEARNED ? PF_WARM_PREV : warm;
@@ -415,7 +439,14 @@ struct Impl {
     const int maxit = c->cfg.cg_max_iter;
     int launched = 0;
     bool conv = false;
-    int chunk = std::max(2, c->last_iters + 2);
+    // Launches queued past convergence cost a few microseconds each, a check
+    // (with its host synchronisation) some tens: the first chunk covers the
+    // smaller of the last two counts, the second reaches the larger one, and
+    // later chunks grow with what has been launched.
+    const int p2 = c->prev_iters > 0 ? c->prev_iters : c->last_iters;
+    const int lo = std::min(c->last_iters, p2), hi = std::max(c->last_iters, p2);
+    int chunk = std::max(2, lo + 2);
+    int nchunk = 0;
     while (true) {
       int n = std::min(chunk, maxit - launched);
       for (int q = 0; q < n; ++q) {
@@ -431,25 +462,23 @@ struct Impl {
         ap.n_in = launched == 0 ? L.nb_el : L.nb_upd;
         up.parity = par;
         if constexpr (DIM == 3)
-          timed(c, PF_K_APPLY, [&] {
-            hipLaunchKernelGGL((k_apply3<T, kApplyBY>), L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
-          }, launched);
+          timed_launch(c, PF_K_APPLY, launched, k_apply3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
         else
-          timed(c, PF_K_APPLY, [&] { hipLaunchKernelGGL((k_apply2<T>), L.gap, dim3(A2W), 0, st, ap); }, launched);
-        timed(c, PF_K_UPDATE, [&] { hipLaunchKernelGGL((k_cg_update<T, DIM>), dim3(L.nb_upd), dim3(NT), 0, st, up); }, launched);
+          timed_launch(c, PF_K_APPLY, launched, k_apply2<T>, L.gap, dim3(A2W), 0, st, ap);
+        timed_launch(c, PF_K_UPDATE, launched, k_cg_update<T, DIM>, dim3(L.nb_upd), dim3(NT), 0, st, up);
         ++launched;
       }
-      timed(c, PF_K_OTHER, [&] {
-        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(NT), 0, st, (const double*)part_u,
+      timed_launch(c, PF_K_OTHER, -1, k_cg_check, dim3(1), dim3(NT), 0, st, (const double*)part_u,
                            launched == 0 ? L.nb_el : L.nb_upd, c->scal(), c->cfg.cg_rtol * c->cfg.cg_rtol);
-      });
       LAUNCHCHK(c);
       HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal(), S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(c, hipStreamSynchronize(st));
       if (c->host_scal[S_CONV] != 0.0) { conv = true; break; }
       if (launched >= maxit) break;
-      chunk = std::max(4, std::min(64, launched / 4));
+      ++nchunk;
+      chunk = nchunk == 1 && hi + 2 > launched ? hi + 2 - launched : std::max(4, std::min(64, launched / 4));
     }
+    c->prev_iters = c->last_iters;
     c->last_iters = (int)c->host_scal[S_ITERS];
     c->iters_total += c->last_iters;
     if (c->judged) {
@@ -471,20 +500,16 @@ struct Impl {
     // true residual ||b - A u||
     if constexpr (DIM == 3) {
       apply_plain(c, e, c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2]), part_a);
-      timed(c, PF_K_SOLVE_SETUP, [&] {
-        hipLaunchKernelGGL((k_true_q<T>), dim3(L.nb_el), dim3(NT), 0, st, (const T*)c->arr<T>(L.o_b[0]),
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_true_q<T>, dim3(L.nb_el), dim3(NT), 0, st, (const T*)c->arr<T>(L.o_b[0]),
                            (const T*)c->arr<T>(L.o_b[1]), (const T*)c->arr<T>(L.o_b[2]), (const T*)c->arr<T>(L.o_q[0]),
                            (const T*)c->arr<T>(L.o_q[1]), (const T*)c->arr<T>(L.o_q[2]), (long)L.g.n, part_b);
-      });
     } else {
       ElastArgs<T> t = e;
       for (int d = 0; d < DIM; ++d) t.u[d] = c->arr<T>(L.o_u[d]);
       t.part = part_b;
-      timed(c, PF_K_SOLVE_SETUP, [&] { hipLaunchKernelGGL((k_elast<T, DIM, M_TRUE>), L.gel, dim3(NT), 0, st, t); });
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_elast<T, DIM, M_TRUE>, L.gel, dim3(NT), 0, st, t);
     }
-    timed(c, PF_K_OTHER, [&] {
-      hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part_b, L.nb_el, c->scal(), (int)S_TRUE);
-    });
+    timed_launch(c, PF_K_OTHER, -1, k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part_b, L.nb_el, c->scal(), (int)S_TRUE);
     LAUNCHCHK(c);
     if (!conv)
       return fail(c, PF_ERR_CG_NOT_CONVERGED, "CG did not reach rtol %.3g in %d iterations", c->cfg.cg_rtol, maxit);
@@ -504,13 +529,11 @@ struct Impl {
     }
     CellArgs<T> a = cell_args(c);
     a.part = c->arr<double>(L.o_part_c);
-    timed(c, PF_K_MU, [&] { hipLaunchKernelGGL((k_mu<T, DIM>), L.gcell, dim3(NT), 0, c->stream, a); });
-    timed(c, PF_K_STEP, [&] { hipLaunchKernelGGL((k_step<T, DIM>), L.gcell, dim3(NT), 0, c->stream, a); });
+    timed_launch(c, PF_K_MU, -1, k_mu<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
+    timed_launch(c, PF_K_STEP, -1, k_step<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
     double vol = std::pow(c->cfg.h, DIM), area = std::pow(c->cfg.h, DIM - 1);
-    timed(c, PF_K_OTHER, [&] {
-      hipLaunchKernelGGL(k_ledger, dim3(1), dim3(NT), 0, c->stream, (const double*)a.part, L.nb_cell, c->scal(), vol,
+    timed_launch(c, PF_K_OTHER, -1, k_ledger, dim3(1), dim3(NT), 0, c->stream, (const double*)a.part, L.nb_cell, c->scal(), vol,
                          area * c->cfg.dt, 1);
-    });
     LAUNCHCHK(c);
     c->cur ^= 1;
     c->steps += 1;
@@ -587,8 +610,11 @@ pf_status pf_init(const pf_config* cfg, const pf_params* params, void* workspace
   c->cur = 0;
   c->steps = 0;
   c->last_iters = 0;
+  c->prev_iters = 0;
   c->warm_used = cfg->warm;
   c->timing = 0u;
+  c->timing_every = 1;
+  c->solves = 0;
   c->ev_next = 0;
   c->n_flush = 0;
   c->iters_total = 0;
@@ -730,6 +756,13 @@ pf_status pf_timing(pf_ctx* c, int kinds) {
     for (int k = 0; k < PF_K_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
   }
   c->timing = (unsigned)kinds;
+  return PF_OK;
+}
+
+pf_status pf_timing_every(pf_ctx* c, int every) {
+  if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  if (every < 1) return fail(c, PF_ERR_INVALID_ARG, "every must be >= 1");
+  c->timing_every = every;
   return PF_OK;
 }
 

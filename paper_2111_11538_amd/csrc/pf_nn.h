@@ -122,11 +122,10 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const uint4* __restrict__ wimg
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // the fragments of chunk kc + 1 are in flight while chunk kc is multiplied
-    uint4 bc[NBW], bn[NBW];
-    conv_load_b<CIN>(rs, v, n, z, y, x0, 0, lr, lg, bc);
-    for (int kc = 0; kc < KC; ++kc) {
-      if (kc + 1 < KC) conv_load_b<CIN>(rs, v, n, z, y, x0, kc + 1, lr, lg, bn);
+    // the fragments of chunk kc + 1 are in flight while chunk kc is
+    // multiplied; the two fragment sets alternate roles, and the scheduling
+    // barriers keep the compiler from sinking the loads below the multiplies
+    auto mul = [&](int kc, const uint4 (&bc)[NBW]) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const bf16x8 a = as_bf8(sW[(mb * KC + kc) * 64 + lane]);
@@ -134,8 +133,25 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const uint4* __restrict__ wimg
         for (int nb = 0; nb < NBW; ++nb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf8(bc[nb]), acc[mb][nb], 0, 0, 0);
       }
-#pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) bc[nb] = bn[nb];
+    };
+    uint4 fa[NBW], fb[NBW];
+    conv_load_b<CIN>(rs, v, n, z, y, x0, 0, lr, lg, fa);
+    int kc = 0;
+    for (; kc + 2 < KC; kc += 2) {
+      conv_load_b<CIN>(rs, v, n, z, y, x0, kc + 1, lr, lg, fb);
+      __builtin_amdgcn_sched_barrier(0);
+      mul(kc, fa);
+      conv_load_b<CIN>(rs, v, n, z, y, x0, kc + 2, lr, lg, fa);
+      __builtin_amdgcn_sched_barrier(0);
+      mul(kc + 1, fb);
+    }
+    if (kc + 1 < KC) {
+      conv_load_b<CIN>(rs, v, n, z, y, x0, kc + 1, lr, lg, fb);
+      __builtin_amdgcn_sched_barrier(0);
+      mul(kc, fa);
+      mul(kc + 1, fb);
+    } else {
+      mul(kc, fa);
     }
     // lane holds out(co = 16 mb + 4 lg + i, voxel = 16 nb + lr)
     const long vrow = (((long)n * v.D + z) * v.H + y) * v.W;
@@ -182,25 +198,33 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const uint4* __restrict__ wimg
 
 // Convolution with 32 input channels, reusing each input fragment for the three
 // x taps.  For a fixed (dz, dy) a wave loads the 64 input voxels x0..x0+63 of
-// its output row once and multiplies them by the weights of dx = -1, 0, +1
-// into three accumulators; the output of voxel v is acc0[v] + accp[v+1] +
-// accm[v-1], formed once per tile by shuffles within the 16-lane rows.  The
-// two halo voxels x0-1 and x0+64 ride in one extra fragment (lanes 0 and 1)
-// whose products with the dx = -1 / +1 weights complete the edge outputs.
+// its output row once (four 16-voxel fragments, one per 16-lane row of the
+// wave: lane (lr, lg) holds channels 8 lg..8 lg+7 of voxel lr) plus one halo
+// fragment (lanes lr = 0 / 1: voxels x0 - 1 / x0 + 64).  The fragments of the
+// dx = -1 and dx = +1 taps are the same data moved by one lane within each
+// 16-lane row (DPP row shifts), the lane that leaves the row being filled from
+// the neighbouring fragment; all three taps accumulate into one accumulator.
 
-// Value of the neighbouring voxel (dir = +1: voxel lr + 1, dir = -1: voxel lr - 1)
-// within a 16-voxel block; the edge lane takes lane `edge_src` of `edge`.
-__device__ __forceinline__ f32x4 neighbour(const f32x4& cur, const f32x4& edge, int lr, int dir, int edge_src) {
-  f32x4 r;
-  const int src = (lr + dir) & 15;
-  const bool at_edge = dir > 0 ? lr == 15 : lr == 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float a = __shfl(cur[i], src, 16);
-    const float b = __shfl(edge[i], edge_src, 16);
-    r[i] = at_edge ? b : a;
-  }
-  return r;
+// Move of one 32-bit lane value within 16-lane rows (DPP).  Lanes whose
+// source lies outside the row keep `old`.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xF, 0xF, false);
+}
+constexpr int kRowShl1 = 0x101;   // lane i <- lane i + 1 (lane 15 keeps old)
+constexpr int kRowShr1 = 0x111;   // lane i <- lane i - 1 (lane 0 keeps old)
+constexpr int kRowRor1 = 0x121;   // lane i <- lane (i - 1) mod 16
+constexpr int kRowRor14 = 0x12E;  // lane i <- lane (i + 2) mod 16
+constexpr int kRowRor15 = 0x12F;  // lane i <- lane (i + 1) mod 16
+
+template <int CTRL>
+__device__ __forceinline__ uint4 dpp4(uint4 old, uint4 src) {
+  return uint4{dpp_mov<CTRL>(old.x, src.x), dpp_mov<CTRL>(old.y, src.y), dpp_mov<CTRL>(old.z, src.z),
+               dpp_mov<CTRL>(old.w, src.w)};
+}
+template <int CTRL>
+__device__ __forceinline__ uint4 dpp4(uint4 src) {
+  return dpp4<CTRL>(src, src);
 }
 
 template <int MB, int EPI>
@@ -229,18 +253,11 @@ __global__ __launch_bounds__(CONV_NT) void k_conv32(const uint4* __restrict__ wi
     const int n = (int)(r / nyt);
     if (y >= v.H) continue;                     // whole wave; no block barrier follows
     const int x0 = xs * SEG;
-    f32x4 am[MB][NBW], a0[MB][NBW], ap[MB][NBW], hm[MB], hp[MB];
+    f32x4 acc[MB][NBW];
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      hm[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      hp[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) {
-        am[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        a0[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        ap[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      }
-    }
+      for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     // Branch-free loads through a buffer resource spanning one input row: the
     // hardware range check returns zero for voxels outside the row (offset
     // pushed past the end) and for rows outside the volume (empty range).
@@ -260,43 +277,53 @@ __global__ __launch_bounds__(CONV_NT) void k_conv32(const uint4* __restrict__ wi
         b[nb] = uint4{q[0], q[1], q[2], q[3]};
       }
     };
-    // the fragments of the next (dz, dy) pair are in flight while one is multiplied
-    uint4 bc[NBW + 1], bn[NBW + 1];
-    load(0, bc);
-    for (int c = 0; c < 9; ++c) {
-      if (c + 1 < 9) load(c + 1, bn);
+    // the fragments of the next (dz, dy) pair are in flight while one is
+    // multiplied; the two fragment sets alternate roles (no copies, so the
+    // wait before a multiply leaves the newer loads outstanding)
+    auto pair = [&](int c, const uint4 (&bc)[NBW + 1]) {
+      bf16x8 wm[MB], w0[MB], wp[MB];
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        const bf16x8 wm = as_bf8(sW[(mb * KC + 3 * c + 0) * 64 + lane]);
-        const bf16x8 w0 = as_bf8(sW[(mb * KC + 3 * c + 1) * 64 + lane]);
-        const bf16x8 wp = as_bf8(sW[(mb * KC + 3 * c + 2) * 64 + lane]);
-#pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) {
-          const bf16x8 b = as_bf8(bc[nb]);
-          am[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, b, am[mb][nb], 0, 0, 0);
-          a0[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, b, a0[mb][nb], 0, 0, 0);
-          ap[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp, b, ap[mb][nb], 0, 0, 0);
-        }
-        const bf16x8 h = as_bf8(bc[NBW]);
-        hm[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, h, hm[mb], 0, 0, 0);
-        hp[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp, h, hp[mb], 0, 0, 0);
+        wm[mb] = as_bf8(sW[(mb * KC + 3 * c + 0) * 64 + lane]);
+        w0[mb] = as_bf8(sW[(mb * KC + 3 * c + 1) * 64 + lane]);
+        wp[mb] = as_bf8(sW[(mb * KC + 3 * c + 2) * 64 + lane]);
       }
 #pragma unroll
-      for (int nb = 0; nb <= NBW; ++nb) bc[nb] = bn[nb];
+      for (int nb = 0; nb < NBW; ++nb) {
+        // dx = -1: voxel lr - 1; lane 0 takes lane 15 of the previous fragment
+        // (for the first, the halo's lane 0, voxel x0 - 1)
+        const uint4 bm = dpp4<kRowShr1>(nb > 0 ? dpp4<kRowRor1>(bc[nb - 1]) : bc[NBW], bc[nb]);
+        // dx = +1: voxel lr + 1; lane 15 takes lane 0 of the next fragment
+        // (for the last, the halo's lane 1, voxel x0 + 64)
+        const uint4 bp = dpp4<kRowShl1>(nb + 1 < NBW ? dpp4<kRowRor15>(bc[nb + 1]) : dpp4<kRowRor14>(bc[NBW]), bc[nb]);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm[mb], as_bf8(bm), acc[mb][nb], 0, 0, 0);
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0[mb], as_bf8(bc[nb]), acc[mb][nb], 0, 0, 0);
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp[mb], as_bf8(bp), acc[mb][nb], 0, 0, 0);
+        }
+      }
+    };
+    // (the scheduling barriers keep the compiler from sinking the loads of
+    // the next pair below the multiplies of this one)
+    uint4 fa[NBW + 1], fb[NBW + 1];
+    load(0, fa);
+    for (int c = 0; c < 8; c += 2) {
+      load(c + 1, fb);
+      __builtin_amdgcn_sched_barrier(0);
+      pair(c, fa);
+      load(c + 2, fa);
+      __builtin_amdgcn_sched_barrier(0);
+      pair(c + 1, fb);
     }
-    // out(voxel u) = a0[u] + ap[u + 1] + am[u - 1]; lane holds co = 16 mb + 4 lg + i
+    pair(8, fa);
+    // lane holds out(co = 16 mb + 4 lg + i, voxel = 16 nb + lr)
     const long vrow = (((long)n * v.D + z) * v.H + y) * v.W;
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) {
       f32x4 o[MB];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const f32x4 fp = nb + 1 < NBW ? neighbour(ap[mb][nb], ap[mb][nb + 1], lr, +1, 0)
-                                      : neighbour(ap[mb][nb], hp[mb], lr, +1, 1);
-        const f32x4 fm = nb > 0 ? neighbour(am[mb][nb], am[mb][nb - 1], lr, -1, 15)
-                                : neighbour(am[mb][nb], hm[mb], lr, -1, 0);
-        o[mb] = a0[mb][nb] + fp + fm;
-      }
+      for (int mb = 0; mb < MB; ++mb) o[mb] = acc[mb][nb];
       const int xx = x0 + nb * 16 + lr;
       if (xx >= v.W) continue;
       const long vox = vrow + xx;

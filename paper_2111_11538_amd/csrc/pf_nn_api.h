@@ -395,9 +395,7 @@ static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
       ap.o1[d] = c->arr<T>(L.o_pa[d]);     // receives a copy of d
       ap.o2[d] = q[d];
     }
-    timed(c, PF_K_OTHER, [&] {
-      hipLaunchKernelGGL((k_apply3<T, kApplyBY>), L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
-    });
+    timed_launch(c, PF_K_OTHER, -1, k_apply3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
     const long n = L.g.n;
     double* part_u = c->arr<double>(L.o_part_u);
     hipLaunchKernelGGL((k_judge_norm<T>), dim3(L.nb_el), dim3(NT), 0, st, (const T*)r[0], (const T*)r[1], (const T*)r[2],

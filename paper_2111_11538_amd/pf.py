@@ -70,7 +70,7 @@ class pf_step_stats(C.Structure):
 
 
 EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_fields", "pf_ledger_reset",
-           "pf_timing", "pf_timing_get", "pf_last_error", "pf_destroy",
+           "pf_timing", "pf_timing_every", "pf_timing_get", "pf_last_error", "pf_destroy",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_set_tiles", "pf_batch_get_tiles",
            "pf_batch_fields", "pf_batch_step", "pf_batch_last_error", "pf_batch_destroy",
            "pf_nn_param_count", "pf_nn_init", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_weights", "pf_nn_copy",
@@ -103,6 +103,8 @@ def lib():
         L.pf_ledger_reset.restype = C.c_int
         L.pf_timing.argtypes = [C.c_void_p, C.c_int]
         L.pf_timing.restype = C.c_int
+        L.pf_timing_every.argtypes = [C.c_void_p, C.c_int]
+        L.pf_timing_every.restype = C.c_int
         L.pf_timing_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
         L.pf_timing_get.restype = C.c_int
         L.pf_batch_workspace_bytes.argtypes = [C.POINTER(pf_config), C.POINTER(pf_extent), C.c_int]
@@ -280,9 +282,11 @@ class Context:
         self._check(lib().pf_mech_solve(self.ctx, WARM[warm], C.byref(st)))
         return st.as_dict()
 
-    def timing(self, enable=True, kinds=None):
+    def timing(self, enable=True, kinds=None, every=1):
         """Start (or with enable False stop) event timing of the named kernel
-        kinds (all of them by default)."""
+        kinds (all of them by default); the CG kernels only on every
+        `every`-th iteration."""
+        self._check(lib().pf_timing_every(self.ctx, int(every)))
         mask = 0
         if enable:
             names = KERNEL_KINDS if kinds is None else kinds
