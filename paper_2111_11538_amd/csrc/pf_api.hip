@@ -25,6 +25,8 @@ constexpr int kApplyBY = 8;          // tile height of the 3D apply kernel (bloc
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+constexpr int kAfterBlocks = 2048;   // blocks of the learned start's after-solve pass
+
 struct Layout {
   Grid g;
   int nc;                  // plastic strain components
@@ -40,6 +42,7 @@ struct Layout {
   size_t o_r[3], o_z[3], o_pa[3], o_pb[3], o_q[3], o_di[3];
   size_t o_scal, o_part_u, o_part_a, o_part_b, o_part_c, o_stage;
   size_t o_uo[3], o_du[3], o_phiprev;   // learned start only
+  size_t o_dsq;                          // learned start: partials of the increment's sum of squares
   size_t o_b[3];                        // 3D: right-hand side b of the equilibrium solve
   size_t total;
 };
@@ -123,6 +126,7 @@ Layout make_layout(const pf_config* c) {
   if (c->warm == PF_WARM_LEARNED) {
     for (int d = 0; d < 3; ++d) { L.o_uo[d] = take(arr); L.o_du[d] = take(arr); }
     L.o_phiprev = take(arr);
+    L.o_dsq = take(kAfterBlocks * sizeof(double));
   }
   L.total = off;
   return L;

@@ -41,7 +41,9 @@ struct ElastArgs {
   double tol2;             // cg_rtol^2
   int parity;              // launch position parity inside the CG loop
   int kz;                  // z planes per block
-  int plain;               // APPLY (3D): q = A z only, outside the CG recurrence (no scalars read or written)
+  int plain;               // APPLY (3D): q = A z only, outside the CG recurrence (no scalars read or
+                           // written, u not read, o1 not written)
+  const T* jr[3];          // APPLY (3D, plain): if set, the partials are ||jr - q||^2 instead of p.q
 };
 
 // Local tile coordinates: lx = i - i0 + 1 in [0, TX+1], ly = j - j0 + 1 in [0, TY+1].
@@ -547,6 +549,9 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
     ru_[d] = buf_rsrc(a.u[d], nbytes);
   }
   const __amdgpu_buffer_rsrc_t rG = buf_rsrc(a.G, nbytes), rK = buf_rsrc(a.K, nbytes);
+  if (a.plain)        // p = z: the previous direction is never read
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ru_[d] = buf_rsrc(a.u[d], 0);
   auto fetch = [&](Raw& R, int kk, bool want) {
     const bool zin = want && kk >= 0 && kk < g.nz;
     R.oin = own && zin;
@@ -716,9 +721,15 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
       if (i > 0) q0 = sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n;
       if (j > 0) q1 = sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n;
       if (k > 0) q2 = szz_prev - szz + sxz_c - sSxz[sk][c + 1] + syz_c - sSyz[sk][c + W];
-      a.o1[0][e] = pc[0]; a.o1[1][e] = pc[1]; a.o1[2][e] = pc[2];
+      if (!a.plain) { a.o1[0][e] = pc[0]; a.o1[1][e] = pc[1]; a.o1[2][e] = pc[2]; }
       a.o2[0][e] = q0; a.o2[1][e] = q1; a.o2[2][e] = q2;
-      acc += (double)pc[0] * (double)q0 + (double)pc[1] * (double)q1 + (double)pc[2] * (double)q2;
+      if (a.jr[0]) {
+        const double d0 = (double)a.jr[0][e] - (double)q0, d1 = (double)a.jr[1][e] - (double)q1,
+                     d2 = (double)a.jr[2][e] - (double)q2;
+        acc += d0 * d0 + d1 * d1 + d2 * d2;
+      } else {
+        acc += (double)pc[0] * (double)q0 + (double)pc[1] * (double)q1 + (double)pc[2] * (double)q2;
+      }
     }
     szz_prev = szz;
     sxz_c = sxz_n;

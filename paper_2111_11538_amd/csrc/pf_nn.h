@@ -358,6 +358,157 @@ __global__ __launch_bounds__(CONV_NT) void k_conv32(const uint4* __restrict__ wi
   }
 }
 
+// The output layer (one 16-channel block of which 3 are used) is too light on
+// multiplies for the row shifts to pay: there the three x taps go to three
+// accumulators instead, and the outputs are combined once per tile, by
+// shuffles within the 16-lane rows (acc0[v] + accp[v + 1] + accm[v - 1]; the
+// halo fragment's products complete the edge voxels).
+
+// Value of the neighbouring voxel (dir = +1: voxel lr + 1, dir = -1: voxel lr - 1)
+// within a 16-voxel block; the edge lane takes lane `edge_src` of `edge`.
+__device__ __forceinline__ f32x4 neighbour(const f32x4& cur, const f32x4& edge, int lr, int dir, int edge_src) {
+  f32x4 r;
+  const int src = (lr + dir) & 15;
+  const bool at_edge = dir > 0 ? lr == 15 : lr == 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float a = __shfl(cur[i], src, 16);
+    const float b = __shfl(edge[i], edge_src, 16);
+    r[i] = at_edge ? b : a;
+  }
+  return r;
+}
+
+template <int MB, int EPI>
+__global__ __launch_bounds__(CONV_NT) void k_conv32_acc3(const uint4* __restrict__ wimg, const float* __restrict__ bias,
+                                                    const uint16_t* __restrict__ x, void* __restrict__ out,
+                                                    const uint16_t* __restrict__ mask, Vol v) {
+  constexpr int CIN = 32;
+  constexpr int KC = kTaps;                    // one k chunk per tap
+  constexpr int COUT = MB * 16;
+  extern __shared__ uint4 sW[];
+  for (int i = threadIdx.x; i < MB * KC * 64; i += CONV_NT) sW[i] = wimg[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int lr = lane & 15, lg = lane >> 4;
+  const int nseg = (v.W + SEG - 1) / SEG, nyt = (v.H + CONV_WAVES - 1) / CONV_WAVES;
+  const long ntiles = (long)nseg * nyt * v.D * v.n;
+  // each block walks a contiguous run of tiles, z fastest, so the input planes
+  // shared by consecutive tiles are reused from its XCD's L2
+  const long t0 = ntiles * blockIdx.x / gridDim.x, t1 = ntiles * (blockIdx.x + 1) / gridDim.x;
+  for (long t = t0; t < t1; ++t) {
+    const int z = (int)(t % v.D);
+    long r = t / v.D;
+    const int xs = (int)(r % nseg);
+    r /= nseg;
+    const int y = (int)(r % nyt) * CONV_WAVES + wv;
+    const int n = (int)(r / nyt);
+    if (y >= v.H) continue;                     // whole wave; no block barrier follows
+    const int x0 = xs * SEG;
+    f32x4 am[MB][NBW], a0[MB][NBW], ap[MB][NBW], hm[MB], hp[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      hm[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      hp[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        am[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        a0[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        ap[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+    // Branch-free loads through a buffer resource spanning one input row: the
+    // hardware range check returns zero for voxels outside the row (offset
+    // pushed past the end) and for rows outside the volume (empty range).
+    // b[NBW] is the halo fragment: lane 0 voxel x0 - 1, lane 1 voxel x0 + 64.
+    const int xh = lr == 0 ? x0 - 1 : (lr == 1 ? x0 + SEG : -1);
+    auto load = [&](int c, uint4 (&b)[NBW + 1]) {   // c = 3 (dz + 1) + (dy + 1)
+      const int zz = z + c / 3 - 1, yy = y + c % 3 - 1;
+      const bool rok = zz >= 0 && zz < v.D && yy >= 0 && yy < v.H;
+      const uint16_t* row = rok ? x + ((((long)n * v.D + zz) * v.H + yy) * v.W) * CIN : x;
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(row), 0, rok ? v.W * CIN * 2 : 0, kBufferFlags);
+#pragma unroll
+      for (int nb = 0; nb <= NBW; ++nb) {
+        const int xx = nb < NBW ? x0 + nb * 16 + lr : xh;
+        const int off = (xx >= 0 && xx < v.W) ? (xx * CIN + lg * 8) * 2 : kOutOfRange;
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        b[nb] = uint4{q[0], q[1], q[2], q[3]};
+      }
+    };
+    // the fragments of the next (dz, dy) pair are loaded while one is
+    // multiplied (one set plus a copy; a deeper prefetch costs occupancy
+    // here, which this kernel needs more)
+    uint4 bc[NBW + 1], bn[NBW + 1];
+    load(0, bc);
+    for (int c = 0; c < 9; ++c) {
+      if (c + 1 < 9) load(c + 1, bn);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const bf16x8 wm = as_bf8(sW[(mb * KC + 3 * c + 0) * 64 + lane]);
+        const bf16x8 w0 = as_bf8(sW[(mb * KC + 3 * c + 1) * 64 + lane]);
+        const bf16x8 wp = as_bf8(sW[(mb * KC + 3 * c + 2) * 64 + lane]);
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) {
+          const bf16x8 b = as_bf8(bc[nb]);
+          am[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, b, am[mb][nb], 0, 0, 0);
+          a0[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, b, a0[mb][nb], 0, 0, 0);
+          ap[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp, b, ap[mb][nb], 0, 0, 0);
+        }
+        const bf16x8 h = as_bf8(bc[NBW]);
+        hm[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, h, hm[mb], 0, 0, 0);
+        hp[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp, h, hp[mb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int nb = 0; nb <= NBW; ++nb) bc[nb] = bn[nb];
+    }
+    // out(voxel u) = a0[u] + ap[u + 1] + am[u - 1]; lane holds co = 16 mb + 4 lg + i
+    const long vrow = (((long)n * v.D + z) * v.H + y) * v.W;
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) {
+      f32x4 o[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const f32x4 fp = nb + 1 < NBW ? neighbour(ap[mb][nb], ap[mb][nb + 1], lr, +1, 0)
+                                      : neighbour(ap[mb][nb], hp[mb], lr, +1, 1);
+        const f32x4 fm = nb > 0 ? neighbour(am[mb][nb], am[mb][nb - 1], lr, -1, 15)
+                                : neighbour(am[mb][nb], hm[mb], lr, -1, 0);
+        o[mb] = a0[mb][nb] + fp + fm;
+      }
+      const int xx = x0 + nb * 16 + lr;
+      if (xx >= v.W) continue;
+      const long vox = vrow + xx;
+      if constexpr (EPI == EPI_LINEAR) {
+        if (lg == 0)
+          reinterpret_cast<float4*>(out)[vox] =
+              make_float4(o[0][0] + bias[0], o[0][1] + bias[1], o[0][2] + bias[2], o[0][3] + bias[3]);
+      } else {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const int co0 = mb * 16 + lg * 4;
+          float q[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) q[i] = o[mb][i];
+          if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) q[i] = fmaxf(q[i] + bias[co0 + i], 0.f);
+          } else {
+            const uint2 mk = *reinterpret_cast<const uint2*>(mask + vox * COUT + co0);
+            if (!bf_pos(mk.x & 0xFFFFu)) q[0] = 0.f;
+            if (!bf_pos(mk.x >> 16)) q[1] = 0.f;
+            if (!bf_pos(mk.y & 0xFFFFu)) q[2] = 0.f;
+            if (!bf_pos(mk.y >> 16)) q[3] = 0.f;
+          }
+          uint2 st;
+          st.x = pack2(q[0], q[1]);
+          st.y = pack2(q[2], q[3]);
+          *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + vox * COUT + co0) = st;
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Weight gradient: dW[t][co][ci] = sum_v dy(v, co) x(v + d(t), ci).  Grid
 // (nsplit, 27): block (s, t) contracts its share of voxel rows for tap t on

@@ -124,7 +124,7 @@ static pf_status nn_conv_fwd(pf_nn* nn, int l, const uint16_t* x, void* y, const
     hipLaunchKernelGGL((pfn::k_conv32<2, pfn::EPI_RELU>), dim3(conv32_grid(v, 512)), dim3(pfn::CONV_NT), smem, st, w,
                        (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
   else
-    hipLaunchKernelGGL((pfn::k_conv32<1, pfn::EPI_LINEAR>), dim3(conv32_grid(v, 512)), dim3(pfn::CONV_NT), smem, st, w,
+    hipLaunchKernelGGL((pfn::k_conv32_acc3<1, pfn::EPI_LINEAR>), dim3(conv32_grid(v, 512)), dim3(pfn::CONV_NT), smem, st, w,
                        (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
   NNLAUNCH(nn);
   return PF_OK;
@@ -244,31 +244,16 @@ __global__ __launch_bounds__(pfn::CNT) void k_learned_delta(T* __restrict__ d0, 
   }
 }
 
-// Judge, step 1: partials of ||r - q||^2 with r = b - A u_prev (from the
-// residual pass) and q = A d: the residual of the learned start u_prev + d.
-template <typename T>
-__global__ __launch_bounds__(NT) void k_judge_norm(const T* __restrict__ r0, const T* __restrict__ r1,
-                                                  const T* __restrict__ r2, const T* __restrict__ q0,
-                                                  const T* __restrict__ q1, const T* __restrict__ q2, long n,
-                                                  double* __restrict__ part) {
+// Judge (one block): compare the residual norm of the learned start, whose
+// partials the apply kernel computed with q = A d (||r - q||^2, r = b - A u_prev
+// from the residual pass), with that of the previous displacement; the
+// decision and both norms go to the device scalars.  Nothing is decided when
+// the solve has already converged (b = 0).
+__global__ __launch_bounds__(NT) void k_judge_decide(const double* __restrict__ part_l, int nl,
+                                                    const double* __restrict__ part_p, int np, double* __restrict__ scal) {
   __shared__ double red[NT / 64];
-  double acc = 0.0;
-  for (long e = blockIdx.x * (long)NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
-    const double a = (double)r0[e] - (double)q0[e], b = (double)r1[e] - (double)q1[e], c = (double)r2[e] - (double)q2[e];
-    acc += a * a + b * b + c * c;
-  }
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
-}
-
-// Judge, step 2 (one block): compare the two residual norms; the decision and
-// both norms go to the device scalars.  Nothing is decided when the solve has
-// already converged (b = 0).
-__global__ __launch_bounds__(NT) void k_judge_decide(const double* __restrict__ part_l, const double* __restrict__ part_p,
-                                                    int nb, double* __restrict__ scal) {
-  __shared__ double red[NT / 64];
-  const double rl = sum_partials(part_l, nb, red);
-  const double rp = sum_partials(part_p, nb, red);
+  const double rl = sum_partials(part_l, nl, red);
+  const double rp = sum_partials(part_p, np, red);
   if (threadIdx.x == 0) {
     scal[S_JL] = rl;
     scal[S_JP] = rp;
@@ -276,7 +261,7 @@ __global__ __launch_bounds__(NT) void k_judge_decide(const double* __restrict__ 
   }
 }
 
-// Judge, step 3: if the learned start won, move to it: u += d, r -= q,
+// Judge, second step: if the learned start won, move to it: u += d, r -= q,
 // z = D^-1 r, and replace the partials of r.z and r.r that CG starts from.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_judge_apply(T* __restrict__ u0, T* __restrict__ u1, T* __restrict__ u2,
@@ -309,18 +294,33 @@ __global__ __launch_bounds__(NT) void k_judge_apply(T* __restrict__ u0, T* __res
   }
 }
 
+// After a solve: the increment d = u - u_o of this step (the network's input
+// at the next), u_o = u (the next solve's previous displacement), the phase
+// field it was taken at, and partials of sum d^2 (the increment's scale; the
+// padding holds zeros in u and u_o).
 template <typename T>
 __global__ __launch_bounds__(pfn::CNT) void k_after_solve(const T* __restrict__ u0, const T* __restrict__ u1,
-                                                         const T* __restrict__ u2, const T* __restrict__ o0,
-                                                         const T* __restrict__ o1, const T* __restrict__ o2,
+                                                         const T* __restrict__ u2, T* __restrict__ o0,
+                                                         T* __restrict__ o1, T* __restrict__ o2,
                                                          T* __restrict__ d0, T* __restrict__ d1, T* __restrict__ d2,
-                                                         const T* __restrict__ phi, T* __restrict__ phi_prev, long n) {
+                                                         const T* __restrict__ phi, T* __restrict__ phi_prev, long n,
+                                                         double* __restrict__ part) {
+  __shared__ double red[pfn::CNT / 64];
+  double s = 0.0;
   for (long e = blockIdx.x * (long)pfn::CNT + threadIdx.x; e < n; e += (long)gridDim.x * pfn::CNT) {
-    d0[e] = u0[e] - o0[e];
-    d1[e] = u1[e] - o1[e];
-    d2[e] = u2[e] - o2[e];
+    const T a = u0[e], b = u1[e], c = u2[e];
+    const T da = a - o0[e], db = b - o1[e], dc = c - o2[e];
+    d0[e] = da;
+    d1[e] = db;
+    d2[e] = dc;
+    o0[e] = a;
+    o1[e] = b;
+    o2[e] = c;
     phi_prev[e] = phi[e];
+    s += (double)da * (double)da + (double)db * (double)db + (double)dc * (double)dc;
   }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 template <typename T>
@@ -354,9 +354,13 @@ template <typename T, int DIM>
 static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
   const Layout& L = c->L;
   hipStream_t st = c->stream;
-  for (int d = 0; d < DIM; ++d)
-    HIPCHK(c, hipMemcpyAsync(c->ws + L.o_uo[d], c->ws + L.o_u[d], (size_t)L.g.n * sizeof(T), hipMemcpyDeviceToDevice, st));
   c->judged = false;
+  // u_o (the displacement this solve starts from) was left equal to u by the
+  // previous solve's after-solve pass, unless there was none since the state
+  // was set
+  if (!c->have_prev_incr)
+    for (int d = 0; d < DIM; ++d)
+      HIPCHK(c, hipMemcpyAsync(c->ws + L.o_uo[d], c->ws + L.o_u[d], (size_t)L.g.n * sizeof(T), hipMemcpyDeviceToDevice, st));
   if constexpr (DIM == 3) {
     pf_nn* nn = c->net;
     if (!nn || !c->have_prev_incr) return PF_OK;
@@ -366,10 +370,9 @@ static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
     a.s = nn->dscal;
     a.x = nn->x0;
     a.target = nullptr;
-    const int nblk = 1024;
-    hipLaunchKernelGGL((pfn::k_incr_sumsq<T>), dim3(nblk), dim3(pfn::CNT), 0, st, a, nn->dpart);
-    hipLaunchKernelGGL(pfn::k_incr_scale, dim3(1), dim3(pfn::CNT), 0, st, (const double*)nn->dpart, nblk,
-                       3.0 * (double)vol_voxels(v), nn->dscal);
+    // the increment's scale from the partials the previous after-solve pass left
+    hipLaunchKernelGGL(pfn::k_incr_scale, dim3(1), dim3(pfn::CNT), 0, st, (const double*)c->arr<double>(L.o_dsq),
+                       kAfterBlocks, 3.0 * (double)vol_voxels(v), nn->dscal);
     hipLaunchKernelGGL((pfn::k_pack_inputs<T>), dim3(2048), dim3(pfn::CNT), 0, st, a);
     LAUNCHCHK(c);
     pf_status fs = PF_OK;
@@ -389,19 +392,19 @@ static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
     ap.plain = 1;
     ap.kz = L.kz_ap;
     ap.part = part;
+    // q = A d, with the partials of ||r - q||^2 (the learned start's residual)
     for (int d = 0; d < 3; ++d) {
       ap.z[d] = dl[d];
-      ap.u[d] = c->arr<T>(L.o_pa[d]);      // previous direction: multiplied by 0
-      ap.o1[d] = c->arr<T>(L.o_pa[d]);     // receives a copy of d
+      ap.u[d] = c->arr<T>(L.o_pa[d]);      // not read (plain)
+      ap.o1[d] = c->arr<T>(L.o_pa[d]);     // not written (plain)
       ap.o2[d] = q[d];
+      ap.jr[d] = r[d];
     }
     timed_launch(c, PF_K_OTHER, -1, k_apply3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
     const long n = L.g.n;
     double* part_u = c->arr<double>(L.o_part_u);
-    hipLaunchKernelGGL((k_judge_norm<T>), dim3(L.nb_el), dim3(NT), 0, st, (const T*)r[0], (const T*)r[1], (const T*)r[2],
-                       (const T*)q[0], (const T*)q[1], (const T*)q[2], n, part);
-    hipLaunchKernelGGL(k_judge_decide, dim3(1), dim3(NT), 0, st, (const double*)part, (const double*)(part_u + L.nb_el),
-                       L.nb_el, c->scal());
+    hipLaunchKernelGGL(k_judge_decide, dim3(1), dim3(NT), 0, st, (const double*)part, (int)(L.gap.x * L.gap.y * L.gap.z),
+                       (const double*)(part_u + L.nb_el), L.nb_el, c->scal());
     hipLaunchKernelGGL((k_judge_apply<T>), dim3(L.nb_el), dim3(NT), 0, st, u[0], u[1], u[2], (const T*)dl[0],
                        (const T*)dl[1], (const T*)dl[2], r[0], r[1], r[2], (const T*)q[0], (const T*)q[1],
                        (const T*)q[2], (const T*)di[0], (const T*)di[1], (const T*)di[2], z[0], z[1], z[2], n,
@@ -416,11 +419,11 @@ template <typename T, int DIM>
 static pf_status learned_after_solve(pf_ctx* c) {
   const Layout& L = c->L;
   if constexpr (DIM == 3) {
-    hipLaunchKernelGGL((k_after_solve<T>), dim3(2048), dim3(pfn::CNT), 0, c->stream, (const T*)c->arr<T>(L.o_u[0]),
-                       (const T*)c->arr<T>(L.o_u[1]), (const T*)c->arr<T>(L.o_u[2]), (const T*)c->arr<T>(L.o_uo[0]),
-                       (const T*)c->arr<T>(L.o_uo[1]), (const T*)c->arr<T>(L.o_uo[2]), c->arr<T>(L.o_du[0]),
+    hipLaunchKernelGGL((k_after_solve<T>), dim3(kAfterBlocks), dim3(pfn::CNT), 0, c->stream,
+                       (const T*)c->arr<T>(L.o_u[0]), (const T*)c->arr<T>(L.o_u[1]), (const T*)c->arr<T>(L.o_u[2]),
+                       c->arr<T>(L.o_uo[0]), c->arr<T>(L.o_uo[1]), c->arr<T>(L.o_uo[2]), c->arr<T>(L.o_du[0]),
                        c->arr<T>(L.o_du[1]), c->arr<T>(L.o_du[2]), (const T*)c->arr<T>(L.o_fld[c->cur][0]),
-                       c->arr<T>(L.o_phiprev), (long)L.g.n);
+                       c->arr<T>(L.o_phiprev), (long)L.g.n, c->arr<double>(L.o_dsq));
     LAUNCHCHK(c);
     c->have_prev_incr = true;
   }
