@@ -613,9 +613,14 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
   };
   // ring stress items: cells left / below the tile, xy edges above / right,
   // z edges right (xz) / above (yz) at level kk
+  // With at least 3 x 128 threads each group starts on a wave boundary
+  // (group g on threads 128 g ..), so no wave runs two groups' code.
+  constexpr bool kAligned = NTB >= 3 * 128 && TX + BY <= 128;
   auto ring_items = [&](int sk, int sk1, int kk_edge, int s0, int s1, int zout, bool cells_and_xy) {
-    for (int w = threadIdx.x; w < TL::NHALO; w += NTB) {
-      const int grp = w / (TX + BY), r = w - grp * (TX + BY);
+    for (int w = threadIdx.x; kAligned ? (w < 3 * 128) : (w < TL::NHALO); w += NTB) {
+      const int grp = kAligned ? (w >> 7) : w / (TX + BY);
+      const int r = kAligned ? (w & 127) : w - grp * (TX + BY);
+      if (kAligned && r >= TX + BY) continue;
       if (grp == 0) {
         if (!cells_and_xy) continue;
         const int yy = r < TX ? 0 : 1 + (r - TX), xx = r < TX ? 1 + r : 0;

@@ -486,6 +486,7 @@ pf_status pf_nn_init(const pf_nn_config* cfg, void* hip_stream, pf_nn** out) {
     pf_nn_destroy(nn);
     return nn_fail(nullptr, PF_ERR_OOM, "device allocation failed");
   }
+
   // He-uniform initialisation from SplitMix64; the output layer is scaled by 0.1
   std::vector<float> P(nn->np, 0.f);
   uint64_t s = cfg->seed;
