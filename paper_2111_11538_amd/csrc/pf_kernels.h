@@ -463,7 +463,7 @@ struct ApplyTile {
 };
 
 template <typename T, int BY>
-__global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
+__global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 ? 4 : 1) void k_apply3(ElastArgs<T> a) {
   using TL = ApplyTile<BY>;
   constexpr int W = TL::W, S = TL::S, NTB = TL::NTB;
   __shared__ T sP[2][3][S];
@@ -649,68 +649,73 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
 
   const int k0 = bz * a.kz;
   const int k1 = min(k0 + a.kz, g.nz);
-  T pc[3], gc, kc, pn[3], gn, kn;     // own values of planes k (c) and k+1 (n)
+  // LDS slots are numbered relative to k0 (plane m in slot (m - k0) & 1), so
+  // inside the plane pairs below every slot index is a constant
+  struct Own { T p[3], g, k; };       // own column's values of one plane
+  Own oA, oB;                         // planes k (current) and k+1, roles alternating
   T szz_prev = T(0), sxz_c = T(0), syz_c = T(0);
+  // boundary factors (0 / 1) of the own column: edges on the domain boundary
+  // carry no shear stress, the low boundary faces no force; all the LDS
+  // values they multiply are finite (zeros outside the domain)
+  const T f_xy = (i > 0 && i < g.nx && j > 0 && j < g.ny) ? T(1) : T(0);
+  const T f_xz = (i > 0 && i < g.nx) ? T(1) : T(0);
+  const T f_yz = (j > 0 && j < g.ny) ? T(1) : T(0);
+  const T f_i = i > 0 ? T(1) : T(0), f_j = j > 0 ? T(1) : T(0);
 
-  // prologue: planes k0-1, k0; sigma_zz of the own cell below; z edges at
-  // level k0.  Plane m travels in register set ra when m - k0 is odd.
+  // prologue: planes k0-1 (slot 1), k0 (slot 0); sigma_zz of the own cell
+  // below; z edges at level k0.  Plane m travels in register set ra when
+  // m - k0 is odd.
   {
-    T pb[3], gb, kb;
+    Own ob;
     fetch(ra, k0 - 1, true);
     fetch(rb, k0, true);
-    stash(ra, (k0 - 1) & 1, pb, gb, kb);
-    stash(rb, k0 & 1, pc, gc, kc);
+    stash(ra, 1, ob.p, ob.g, ob.k);
+    stash(rb, 0, oA.p, oA.g, oA.k);
     fetch(ra, k0 + 1, true);
     fetch(rb, k0 + 2, k0 + 1 < k1);
     __syncthreads();
-    const int sa = (k0 - 1) & 1, sb = k0 & 1;
     if (k0 > 0) {
-      const T exx = (sP[sa][0][c + 1] - pb[0]) * ih;
-      const T eyy = (sP[sa][1][c + W] - pb[1]) * ih;
-      const T ezz = (pc[2] - pb[2]) * ih;
+      const T exx = (sP[1][0][c + 1] - ob.p[0]) * ih;
+      const T eyy = (sP[1][1][c + W] - ob.p[1]) * ih;
+      const T ezz = (oA.p[2] - ob.p[2]) * ih;
       const T tr = exx + eyy + ezz;
-      const T G2 = T(2) * gb;
-      szz_prev = kb * tr - G2 * tr * T(1.0 / 3.0) + G2 * ezz;
+      const T G2 = T(2) * ob.g;
+      szz_prev = ob.k * tr - G2 * tr * T(1.0 / 3.0) + G2 * ezz;
     }
-    sxz_c = xz_lds(c, i, j, k0, sa, sb);
-    syz_c = yz_lds(c, i, j, k0, sa, sb);
-    sSxz[sb][c] = sxz_c;
-    sSyz[sb][c] = syz_c;
-    ring_items(sa, sb, k0, sa, sb, sb, false);
+    sxz_c = xz_lds(c, i, j, k0, 1, 0);
+    syz_c = yz_lds(c, i, j, k0, 1, 0);
+    sSxz[0][c] = sxz_c;
+    sSyz[0][c] = syz_c;
+    ring_items(1, 0, k0, 1, 0, 0, false);
     __syncthreads();
-    stash(ra, (k0 + 1) & 1, pn, gn, kn);
+    stash(ra, 1, oB.p, oB.g, oB.k);
     fetch(ra, k0 + 3, k0 + 2 < k1);
     __syncthreads();
   }
 
   double acc = 0.0;
-  // one plane; R carries plane k+2 in and is refilled with plane k+4
-  auto plane = [&](int k, Raw& R) {
-    const int sk = k & 1, sk1 = (k + 1) & 1;
+  // one plane k in slot sk (plane k+1 in slot sk1); C holds its own values,
+  // N those of plane k+1.  R carries plane k+2 in (stashed into slot sk and
+  // into C, which then holds the plane after N) and is refilled with plane k+4.
+  auto plane = [&](int k, Raw& R, const int sk, Own& C, const Own& N) {
+    const int sk1 = sk ^ 1;
     // (A) own stresses of plane k and own z edges at level k+1
-    const T exx = (sP[sk][0][c + 1] - pc[0]) * ih;
-    const T eyy = (sP[sk][1][c + W] - pc[1]) * ih;
-    const T ezz = (pn[2] - pc[2]) * ih;
+    const T exx = (sP[sk][0][c + 1] - C.p[0]) * ih;
+    const T eyy = (sP[sk][1][c + W] - C.p[1]) * ih;
+    const T ezz = (N.p[2] - C.p[2]) * ih;
     const T tr = exx + eyy + ezz;
-    const T G2 = T(2) * gc;
-    const T lam = kc * tr - G2 * tr * T(1.0 / 3.0);
+    const T G2 = T(2) * C.g;
+    const T lam = C.k * tr - G2 * tr * T(1.0 / 3.0);
     const T sxx = lam + G2 * exx, syy = lam + G2 * eyy, szz = lam + G2 * ezz;
-    T sxy = T(0);
-    if (i > 0 && i < g.nx && j > 0 && j < g.ny) {
-      const T ge = T(0.25) * (sG[sk][c - W - 1] + sG[sk][c - W] + sG[sk][c - 1] + gc);
-      sxy = ge * ((pc[0] - sP[sk][0][c - W]) + (pc[1] - sP[sk][1][c - 1])) * ih;
-    }
+    const T gxy = T(0.25) * (sG[sk][c - W - 1] + sG[sk][c - W] + sG[sk][c - 1] + C.g);
+    const T sxy = f_xy * gxy * ((C.p[0] - sP[sk][0][c - W]) + (C.p[1] - sP[sk][1][c - 1])) * ih;
     const int kn1 = k + 1;
     T sxz_n = T(0), syz_n = T(0);
-    if (kn1 < g.nz) {
-      if (i > 0 && i < g.nx) {
-        const T ge = T(0.25) * (sG[sk][c - 1] + gc + sG[sk1][c - 1] + gn);
-        sxz_n = ge * ((pn[0] - pc[0]) + (pn[2] - sP[sk1][2][c - 1])) * ih;
-      }
-      if (j > 0 && j < g.ny) {
-        const T ge = T(0.25) * (sG[sk][c - W] + gc + sG[sk1][c - W] + gn);
-        syz_n = ge * ((pn[1] - pc[1]) + (pn[2] - sP[sk1][2][c - W])) * ih;
-      }
+    if (kn1 < g.nz) {                 // block-uniform
+      const T gxz = T(0.25) * (sG[sk][c - 1] + C.g + sG[sk1][c - 1] + N.g);
+      sxz_n = f_xz * gxz * ((N.p[0] - C.p[0]) + (N.p[2] - sP[sk1][2][c - 1])) * ih;
+      const T gyz = T(0.25) * (sG[sk][c - W] + C.g + sG[sk1][c - W] + N.g);
+      syz_n = f_yz * gyz * ((N.p[1] - C.p[1]) + (N.p[2] - sP[sk1][2][c - W])) * ih;
     }
     sSxx[c] = sxx;
     sSyy[c] = syy;
@@ -722,30 +727,23 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
     // (C) divergence onto the own faces of plane k
     if (own) {
       const int e = own_e + k * pl;
-      T q0 = T(0), q1 = T(0), q2 = T(0);
-      if (i > 0) q0 = sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n;
-      if (j > 0) q1 = sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n;
-      if (k > 0) q2 = szz_prev - szz + sxz_c - sSxz[sk][c + 1] + syz_c - sSyz[sk][c + W];
-      if (!a.plain) { a.o1[0][e] = pc[0]; a.o1[1][e] = pc[1]; a.o1[2][e] = pc[2]; }
+      const T q0 = f_i * (sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n);
+      const T q1 = f_j * (sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n);
+      const T q2 = k > 0 ? szz_prev - szz + sxz_c - sSxz[sk][c + 1] + syz_c - sSyz[sk][c + W] : T(0);
+      if (!a.plain) { a.o1[0][e] = C.p[0]; a.o1[1][e] = C.p[1]; a.o1[2][e] = C.p[2]; }
       a.o2[0][e] = q0; a.o2[1][e] = q1; a.o2[2][e] = q2;
       if (a.jr[0]) {
         const double d0 = (double)a.jr[0][e] - (double)q0, d1 = (double)a.jr[1][e] - (double)q1,
                      d2 = (double)a.jr[2][e] - (double)q2;
         acc += d0 * d0 + d1 * d1 + d2 * d2;
       } else {
-        acc += (double)pc[0] * (double)q0 + (double)pc[1] * (double)q1 + (double)pc[2] * (double)q2;
+        acc += (double)C.p[0] * (double)q0 + (double)C.p[1] * (double)q1 + (double)C.p[2] * (double)q2;
       }
     }
     szz_prev = szz;
     sxz_c = sxz_n;
     syz_c = syz_n;
-    if (k + 1 < k1) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) pc[d] = pn[d];
-      gc = gn;
-      kc = kn;
-      stash(R, sk, pn, gn, kn);   // plane k+2 into the slot of plane k
-    }
+    if (k + 1 < k1) stash(R, sk, C.p, C.g, C.k);   // plane k+2 into the slot of plane k
     fetch(R, k + 4, k + 3 < k1);
     __syncthreads();
   };
@@ -753,10 +751,10 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_apply3(ElastArgs<T> a) {
   // flight (the wait counts then let the newer set stay outstanding)
   int k = k0;
   for (; k + 1 < k1; k += 2) {
-    plane(k, rb);
-    plane(k + 1, ra);
+    plane(k, rb, 0, oA, oB);
+    plane(k + 1, ra, 1, oB, oA);
   }
-  if (k < k1) plane(k, rb);
+  if (k < k1) plane(k, rb, 0, oA, oB);
   const double s0 = block_sum_n<NTB>(acc, red);
   if (threadIdx.x == 0) a.part[bid] = s0;
 }
