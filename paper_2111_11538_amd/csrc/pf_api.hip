@@ -378,7 +378,8 @@ struct Impl {
         sa.o1[d] = c->arr<T>(L.o_b[d]);
         sa.dinv[d] = c->arr<T>(L.o_di[d]);
       }
-      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_elast<T, 3, M_SETUP>, L.gel, dim3(NT), 0, st, sa);
+      sa.kz = L.kz_ap;
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_setup3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, sa);
       apply_plain(c, e, c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2]), part_a);
       ResidQArgs<T> rq{};
       for (int d = 0; d < 3; ++d) {
@@ -390,7 +391,7 @@ struct Impl {
         rq.z[d] = c->arr<T>(L.o_z[d]);
       }
       rq.part_in = part_b;
-      rq.n_in = L.nb_el;
+      rq.n_in = (int)(L.gap.x * L.gap.y * L.gap.z);   // the set-up pass's ||b||^2 partials
       rq.part = part_u;
       rq.scal = c->scal();
       rq.n = L.g.n;

@@ -16,10 +16,7 @@
 
 namespace pfk {
 
-enum ElastMode { M_APPLY = 0, M_RESID = 1, M_BNORM = 2, M_TRUE = 3, M_SETUP = 4 };
-// M_SETUP: like M_BNORM (u taken as zero) but also stores b (in o1) and the
-// inverse diagonal of A (in dinv); the residual of any u then follows from
-// q = A u on the apply kernel.
+enum ElastMode { M_APPLY = 0, M_RESID = 1, M_BNORM = 2, M_TRUE = 3 };
 
 template <typename T>
 struct ElastArgs {
@@ -59,7 +56,7 @@ __device__ __forceinline__ int L(int ly, int lx) { return ly * LW + lx; }
 template <typename T, int DIM, int MODE>
 struct ElastSmem {
   static constexpr int D3 = (DIM == 3) ? LS : 1;
-  static constexpr int R3 = ((MODE == M_RESID || MODE == M_SETUP) && DIM == 3) ? LS : 1;
+  static constexpr int R3 = (MODE == M_RESID && DIM == 3) ? LS : 1;
   double red[NT / 64];
   T sP[2][DIM][LS];
   T sK[LS];
@@ -119,7 +116,7 @@ __device__ __forceinline__ void elast_tile(const ElastArgs<T>& a, int bx, int by
       for (int c = 0; c < DIM; ++c) {
         T v = T(0);
         if (in) {
-          if (MODE == M_BNORM || MODE == M_SETUP) v = T(0);
+          if (MODE == M_BNORM) v = T(0);
           else v = zero_u ? T(0) : a.u[c][e];
         }
         sP[slot][c][t] = v;
@@ -222,7 +219,7 @@ __device__ __forceinline__ void elast_tile(const ElastArgs<T>& a, int bx, int by
         }
         sSxz[out][c] = sxz;
         sSyz[out][c] = syz;
-        if constexpr (MODE == M_RESID || MODE == M_SETUP) {
+        if constexpr (MODE == M_RESID) {
           sGxz[out][c] = gxz;
           sGyz[out][c] = gyz;
         }
@@ -302,7 +299,7 @@ __device__ __forceinline__ void elast_tile(const ElastArgs<T>& a, int bx, int by
       if constexpr (DIM == 3) {
         if (k > 0) q[2] = szz_prev - sSzz[c] + sSxz[sk][c] - sSxz[sk][c + 1] + sSyz[sk][c] - sSyz[sk][c + LW];
       }
-      if constexpr (MODE == M_RESID || MODE == M_SETUP) {
+      if constexpr (MODE == M_RESID) {
         // inverse diagonal: (M_left + M_right + adjacent interior edge G_e) / h
         T Mc = sK[c] + T(4.0 / 3.0) * sG[sk][c];
         T d[3] = {T(0), T(0), T(0)};
@@ -328,17 +325,12 @@ __device__ __forceinline__ void elast_tile(const ElastArgs<T>& a, int bx, int by
           T di = d[cc] > T(0) ? T(1) / (d[cc] * ih) : T(0);
           T r = -q[cc];
           a.dinv[cc][e] = di;
-          if constexpr (MODE == M_SETUP) {       // u = 0: r is b
-            a.o1[cc][e] = r;
-            acc0 += (double)r * (double)r;
-          } else {
-            T zz = di * r;
-            a.o1[cc][e] = r;
-            a.o2[cc][e] = zz;
-            if (zero_u) a.u[cc][e] = T(0);
-            acc0 += (double)r * (double)zz;
-            acc1 += (double)r * (double)r;
-          }
+          T zz = di * r;
+          a.o1[cc][e] = r;
+          a.o2[cc][e] = zz;
+          if (zero_u) a.u[cc][e] = T(0);
+          acc0 += (double)r * (double)zz;
+          acc1 += (double)r * (double)r;
         }
       } else {
 #pragma unroll
@@ -749,6 +741,278 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 ? 4 : 1) void k_
   };
   // pairs of planes, so that every path into a plane has the same loads in
   // flight (the wait counts then let the newer set stay outstanding)
+  int k = k0;
+  for (; k + 1 < k1; k += 2) {
+    plane(k, rb, 0, oA, oB);
+    plane(k + 1, ra, 1, oB, oA);
+  }
+  if (k < k1) plane(k, rb, 0, oA, oB);
+  const double s0 = block_sum_n<NTB>(acc, red);
+  if (threadIdx.x == 0) a.part[bid] = s0;
+}
+
+// ---------------------------------------------------------------------------
+// 3D solve set-up: b = div(C : eps*) of the eigenstrain and plastic strain
+// (the right-hand side; u = 0), the Jacobi inverse diagonal D^-1 and the
+// block partials of ||b||^2, in the 2.5D layout of k_apply3: block = 64 x BY
+// threads over a column tile marching along z, own column values in
+// registers, x / y neighbours from a one-cell-ring LDS plane tile, ring
+// stresses from a short work list, loads two planes ahead.  Per plane it
+// reads K, G, phi_f (for the eigenstrain) and the six plastic strain
+// components, and writes b and D^-1.
+// ---------------------------------------------------------------------------
+template <typename T, int BY>
+__global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
+  using TL = ApplyTile<BY>;
+  constexpr int W = TL::W, S = TL::S, NTB = TL::NTB;
+  __shared__ T sK[2][S], sG[2][S], sN[2][3][S], sExy[2][S], sExz[2][S], sEyz[2][S];
+  __shared__ T sSxx[S], sSyy[S], sSxy[S], sGxy[S];
+  __shared__ T sSxz[2][S], sSyz[2][S], sGxz[2][S], sGyz[2][S];
+  __shared__ double red[NTB / 64];
+
+  const Grid& g = a.g;
+  const KP<T>& p = a.p;
+  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int tile = xcd_tile(bid, gridDim.x * gridDim.y * gridDim.z);
+  const int bx = tile % gridDim.x, by = (tile / gridDim.x) % gridDim.y, bz = tile / (gridDim.x * gridDim.y);
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
+  const int i0 = bx * TX, j0 = by * BY;
+  const int i = i0 + tx, j = j0 + ty;
+  const int c = (ty + 1) * W + tx + 1;
+  const bool own = (i < g.nx) && (j < g.ny);
+  const T ih = p.ih;
+  const int pl = g.px * g.ny;
+
+  int rg_t = S, rg_e = 0;
+  bool rg_in = false;
+  if (threadIdx.x < TL::NRING) {
+    int t = threadIdx.x, yy, xx;
+    if (t < W) { yy = 0; xx = t; }
+    else if (t < 2 * W) { yy = BY + 1; xx = t - W; }
+    else { t -= 2 * W; yy = 1 + (t >> 1); xx = (t & 1) ? TX + 1 : 0; }
+    const int ii = i0 + xx - 1, jj = j0 + yy - 1;
+    rg_t = yy * W + xx;
+    rg_in = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny;
+    rg_e = rg_in ? jj * g.px + ii : 0;
+  }
+  const int own_e = own ? j * g.px + i : 0;
+
+  // raw loads of one plane (own column and ring position), two sets in flight
+  struct Raw {
+    T oK, oG, of, op[6], hK, hG, hf, hp[6];
+    bool oin, hin;
+  };
+  struct Own { T K, G, n[3], xy, xz, yz; };    // own cell: moduli, eps*_nn (eigen + plastic), plastic shears
+  Raw ra, rb;
+  const int nbytes = g.n * (int)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rK = buf_rsrc(a.K, nbytes), rG = buf_rsrc(a.G, nbytes), rF = buf_rsrc(a.phi_f, nbytes);
+  const __amdgpu_buffer_rsrc_t rE = buf_rsrc(a.epsp, 6 * g.ns * (int)sizeof(T));
+  const int cstride = g.ns * (int)sizeof(T);
+  auto fetch = [&](Raw& R, int kk, bool want) {
+    const bool zin = want && kk >= 0 && kk < g.nz;
+    R.oin = own && zin;
+    R.hin = rg_in && zin;
+    const int eo = R.oin ? (own_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
+    const int eh = R.hin ? (rg_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
+    R.oK = buf_ld<T>(rK, eo); R.oG = buf_ld<T>(rG, eo); R.of = buf_ld<T>(rF, eo);
+    R.hK = buf_ld<T>(rK, eh); R.hG = buf_ld<T>(rG, eh); R.hf = buf_ld<T>(rF, eh);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      R.op[q] = buf_ld<T>(rE, R.oin ? eo + q * cstride : kOutOfRange);
+      R.hp[q] = buf_ld<T>(rE, R.hin ? eh + q * cstride : kOutOfRange);
+    }
+  };
+  auto stash = [&](const Raw& R, int slot, Own& O) {
+    const T et = R.oin ? eigen_strain(p, R.of) : T(0);
+    O.K = R.oin ? R.oK : T(0);
+    O.G = R.oin ? R.oG : T(0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) O.n[q] = R.oin ? et + R.op[q] : T(0);
+    O.xy = R.oin ? R.op[3] : T(0);
+    O.xz = R.oin ? R.op[4] : T(0);
+    O.yz = R.oin ? R.op[5] : T(0);
+    sK[slot][c] = O.K;
+    sG[slot][c] = O.G;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) sN[slot][q][c] = O.n[q];
+    sExy[slot][c] = O.xy;
+    sExz[slot][c] = O.xz;
+    sEyz[slot][c] = O.yz;
+    if (rg_t < S) {
+      const T hu = R.hin ? eigen_strain(p, R.hf) : T(0);
+      sK[slot][rg_t] = R.hin ? R.hK : T(0);
+      sG[slot][rg_t] = R.hin ? R.hG : T(0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sN[slot][q][rg_t] = R.hin ? hu + R.hp[q] : T(0);
+      sExy[slot][rg_t] = R.hin ? R.hp[3] : T(0);
+      sExz[slot][rg_t] = R.hin ? R.hp[4] : T(0);
+      sEyz[slot][rg_t] = R.hin ? R.hp[5] : T(0);
+    }
+  };
+  // normal stresses of the cell at tile position q (slot sk), u = 0
+  auto cell_sn = [&](int q, int sk, T& sxx, T& syy) {
+    const T n0 = sN[sk][0][q], n1 = sN[sk][1][q], n2 = sN[sk][2][q];
+    const T tr = -(n0 + n1 + n2);
+    const T G2 = T(2) * sG[sk][q];
+    const T lam = sK[sk][q] * tr - G2 * tr * T(1.0 / 3.0);
+    sxx = lam - G2 * n0;
+    syy = lam - G2 * n1;
+  };
+  // xz / yz edge stresses and moduli at level kk (planes in slots s0 below, s1 above)
+  auto xz_edge = [&](int q, int ii, int jj, int kk, int s0, int s1, T& gv) -> T {
+    gv = T(0);
+    if (!(kk > 0 && kk < g.nz && ii > 0 && ii < g.nx && jj < g.ny)) return T(0);
+    gv = T(0.25) * (sG[s0][q - 1] + sG[s0][q] + sG[s1][q - 1] + sG[s1][q]);
+    return T(-0.5) * gv * (sExz[s0][q - 1] + sExz[s0][q] + sExz[s1][q - 1] + sExz[s1][q]);
+  };
+  auto yz_edge = [&](int q, int ii, int jj, int kk, int s0, int s1, T& gv) -> T {
+    gv = T(0);
+    if (!(kk > 0 && kk < g.nz && jj > 0 && jj < g.ny && ii < g.nx)) return T(0);
+    gv = T(0.25) * (sG[s0][q - W] + sG[s0][q] + sG[s1][q - W] + sG[s1][q]);
+    return T(-0.5) * gv * (sEyz[s0][q - W] + sEyz[s0][q] + sEyz[s1][q - W] + sEyz[s1][q]);
+  };
+  // ring work: cells left / below the tile (normal stresses), xy nodes above /
+  // right, z edges at level kk above (yz) and right (xz); group g on threads
+  // 128 g .. so that no wave runs two groups' code
+  constexpr bool kAligned = NTB >= 3 * 128 && TX + BY <= 128;
+  auto ring_items = [&](int sk, int kk_edge, int s0, int s1, int zout, bool cells_and_xy) {
+    for (int w = threadIdx.x; kAligned ? (w < 3 * 128) : (w < TL::NHALO); w += NTB) {
+      const int grp = kAligned ? (w >> 7) : w / (TX + BY);
+      const int r = kAligned ? (w & 127) : w - grp * (TX + BY);
+      if (kAligned && r >= TX + BY) continue;
+      if (grp == 0) {
+        if (!cells_and_xy) continue;
+        const int yy = r < TX ? 0 : 1 + (r - TX), xx = r < TX ? 1 + r : 0;
+        const int q = yy * W + xx;
+        T sxx, syy;
+        cell_sn(q, sk, sxx, syy);
+        sSxx[q] = sxx;
+        sSyy[q] = syy;
+      } else if (grp == 1) {
+        if (!cells_and_xy) continue;
+        const int yy = r < TX ? BY + 1 : 1 + (r - TX), xx = r < TX ? 1 + r : TX + 1;
+        const int q = yy * W + xx;
+        const int ii = i0 + xx - 1, jj = j0 + yy - 1;
+        T sxy = T(0), gv = T(0);
+        if (ii > 0 && ii < g.nx && jj > 0 && jj < g.ny) {
+          gv = T(0.25) * (sG[sk][q - W - 1] + sG[sk][q - W] + sG[sk][q - 1] + sG[sk][q]);
+          sxy = T(-0.5) * gv * (sExy[sk][q - W - 1] + sExy[sk][q - W] + sExy[sk][q - 1] + sExy[sk][q]);
+        }
+        sSxy[q] = sxy;
+        sGxy[q] = gv;
+      } else {
+        T gv;
+        if (r < TX) {    // yz edge above the tile
+          const int q = (BY + 1) * W + 1 + r;
+          sSyz[zout][q] = yz_edge(q, i0 + r, j0 + BY, kk_edge, s0, s1, gv);
+          sGyz[zout][q] = gv;
+        } else {         // xz edge right of the tile
+          const int yy = 1 + (r - TX);
+          const int q = yy * W + TX + 1;
+          sSxz[zout][q] = xz_edge(q, i0 + TX, j0 + yy - 1, kk_edge, s0, s1, gv);
+          sGxz[zout][q] = gv;
+        }
+      }
+    }
+  };
+
+  const int k0 = bz * a.kz;
+  const int k1 = min(k0 + a.kz, g.nz);
+  Own oA, oB;                         // own values of planes k and k+1, roles alternating
+  T szz_prev = T(0), m_prev = T(0);
+  T sxz_c = T(0), syz_c = T(0), gxz_c = T(0), gyz_c = T(0);   // own z edges at level k
+  const T f_xy = (i > 0 && i < g.nx && j > 0 && j < g.ny) ? T(1) : T(0);
+  const T f_xz = (i > 0 && i < g.nx && j < g.ny) ? T(1) : T(0);
+  const T f_yz = (j > 0 && j < g.ny && i < g.nx) ? T(1) : T(0);
+  const T f_i = i > 0 ? T(1) : T(0), f_j = j > 0 ? T(1) : T(0);
+
+  // prologue: planes k0-1 (slot 1) and k0 (slot 0); the own cell below; z edges at level k0
+  {
+    Own ob;
+    fetch(ra, k0 - 1, true);
+    fetch(rb, k0, true);
+    stash(ra, 1, ob);
+    stash(rb, 0, oA);
+    fetch(ra, k0 + 1, true);
+    fetch(rb, k0 + 2, k0 + 1 < k1);
+    __syncthreads();
+    if (k0 > 0) {
+      const T tr = -(ob.n[0] + ob.n[1] + ob.n[2]);
+      const T G2 = T(2) * ob.G;
+      szz_prev = ob.K * tr - G2 * tr * T(1.0 / 3.0) - G2 * ob.n[2];
+      m_prev = ob.K + T(4.0 / 3.0) * ob.G;
+    }
+    sxz_c = xz_edge(c, i, j, k0, 1, 0, gxz_c);
+    syz_c = yz_edge(c, i, j, k0, 1, 0, gyz_c);
+    sSxz[0][c] = sxz_c;
+    sSyz[0][c] = syz_c;
+    sGxz[0][c] = gxz_c;
+    sGyz[0][c] = gyz_c;
+    ring_items(1, k0, 1, 0, 0, false);
+    __syncthreads();
+    stash(ra, 1, oB);
+    fetch(ra, k0 + 3, k0 + 2 < k1);
+    __syncthreads();
+  }
+
+  double acc = 0.0;
+  auto plane = [&](int k, Raw& R, const int sk, Own& C, const Own& N) {
+    const int sk1 = sk ^ 1;
+    // own cell normal stresses and diagonal term
+    const T tr = -(C.n[0] + C.n[1] + C.n[2]);
+    const T G2 = T(2) * C.G;
+    const T lam = C.K * tr - G2 * tr * T(1.0 / 3.0);
+    const T sxx = lam - G2 * C.n[0], syy = lam - G2 * C.n[1], szz = lam - G2 * C.n[2];
+    const T Mc = C.K + T(4.0 / 3.0) * C.G;
+    // own xy node (i, j)
+    const T gxy = f_xy * T(0.25) * (sG[sk][c - W - 1] + sG[sk][c - W] + sG[sk][c - 1] + C.G);
+    const T sxy = T(-0.5) * gxy * (sExy[sk][c - W - 1] + sExy[sk][c - W] + sExy[sk][c - 1] + C.xy);
+    // own z edges at level k+1
+    const int kn1 = k + 1;
+    T sxz_n = T(0), syz_n = T(0), gxz_n = T(0), gyz_n = T(0);
+    if (kn1 < g.nz) {                 // block-uniform
+      gxz_n = f_xz * T(0.25) * (sG[sk][c - 1] + C.G + sG[sk1][c - 1] + N.G);
+      sxz_n = T(-0.5) * gxz_n * (sExz[sk][c - 1] + C.xz + sExz[sk1][c - 1] + N.xz);
+      gyz_n = f_yz * T(0.25) * (sG[sk][c - W] + C.G + sG[sk1][c - W] + N.G);
+      syz_n = T(-0.5) * gyz_n * (sEyz[sk][c - W] + C.yz + sEyz[sk1][c - W] + N.yz);
+    }
+    sSxx[c] = sxx;
+    sSyy[c] = syy;
+    sSxy[c] = sxy;
+    sGxy[c] = gxy;
+    sSxz[sk1][c] = sxz_n;
+    sSyz[sk1][c] = syz_n;
+    sGxz[sk1][c] = gxz_n;
+    sGyz[sk1][c] = gyz_n;
+    ring_items(sk, kn1, sk, sk1, sk1, true);
+    __syncthreads();
+    if (own) {
+      const int e = own_e + k * pl;
+      const T q0 = f_i * (sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n);
+      const T q1 = f_j * (sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n);
+      const T q2 = k > 0 ? szz_prev - szz + sxz_c - sSxz[sk][c + 1] + syz_c - sSyz[sk][c + W] : T(0);
+      const T d0 = f_i * (sK[sk][c - 1] + T(4.0 / 3.0) * sG[sk][c - 1] + Mc + gxy + sGxy[c + W] + gxz_c + gxz_n);
+      const T d1 = f_j * (sK[sk][c - W] + T(4.0 / 3.0) * sG[sk][c - W] + Mc + gxy + sGxy[c + 1] + gyz_c + gyz_n);
+      const T d2 = k > 0 ? m_prev + Mc + gxz_c + sGxz[sk][c + 1] + gyz_c + sGyz[sk][c + W] : T(0);
+      const T q[3] = {q0, q1, q2}, d[3] = {d0, d1, d2};
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const T r = -q[cc];
+        a.o1[cc][e] = r;
+        a.dinv[cc][e] = d[cc] > T(0) ? T(1) / (d[cc] * ih) : T(0);
+        acc += (double)r * (double)r;
+      }
+    }
+    szz_prev = szz;
+    m_prev = Mc;
+    sxz_c = sxz_n;
+    syz_c = syz_n;
+    gxz_c = gxz_n;
+    gyz_c = gyz_n;
+    if (k + 1 < k1) stash(R, sk, C);   // plane k+2 into the slot of plane k
+    fetch(R, k + 4, k + 3 < k1);
+    __syncthreads();
+  };
   int k = k0;
   for (; k + 1 < k1; k += 2) {
     plane(k, rb, 0, oA, oB);
