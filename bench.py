@@ -49,9 +49,9 @@ NN_FLOP_PER_VOXEL = 2 * 27 * (6 * 32 + 32 * 32 + 32 * 32 + 32 * 3)   # one infer
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak, vendor figure
 
 
-KERNEL_NAMES = {("update", 3, 4): "k_cg_update<float, 3>", ("apply", 3, 4): "k_apply3<float, 8>",
+KERNEL_NAMES = {("update", 3, 4): "k_cg_update<float, 3>", ("apply", 3, 4): "k_apply3<float, 8, 0>",
                 ("step", 3, 4): "k_step<float, 3>", ("mu", 3, 4): "k_mu<float, 3>",
-                ("update", 3, 8): "k_cg_update<double, 3>", ("apply", 3, 8): "k_apply3<double, 8>"}
+                ("update", 3, 8): "k_cg_update<double, 3>", ("apply", 3, 8): "k_apply3<double, 8, 0>"}
 
 
 def source_sha():

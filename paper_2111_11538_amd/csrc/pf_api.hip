@@ -36,6 +36,7 @@ struct Layout {
   int kz_ap;               // z planes per block of the 3D apply kernel
   dim3 gap;                // its grid (64 x kApplyBY tiles)
   int nb_el, nb_cell, nb_upd;
+  int nb_res;              // blocks (partial pairs) of the residual pass CG starts from: the apply grid (3D), the elast grid (2D)
   size_t stage_elems;
   // byte offsets into the workspace
   size_t o_fld[2][5], o_u[3], o_epsp, o_epsP, o_mu, o_K, o_G;
@@ -117,6 +118,7 @@ Layout make_layout(const pf_config* c) {
   if (c->dim == 3)
     for (int d = 0; d < 3; ++d) L.o_b[d] = take(arr);
   L.o_scal = take(S_COUNT * sizeof(double));
+  L.nb_res = c->dim == 3 ? (int)(L.gap.x * L.gap.y * L.gap.z) : L.nb_el;
   int nbmax = std::max(std::max(L.nb_el, (int)(L.gap.x * L.gap.y * L.gap.z)), std::max(L.nb_cell, L.nb_upd));
   L.o_part_u = take(2 * (size_t)nbmax * sizeof(double));
   L.o_part_a = take(2 * (size_t)nbmax * sizeof(double));
@@ -324,11 +326,13 @@ struct Impl {
 
   // q = A x on the 3D apply kernel outside the CG recurrence (x into z's
   // place; the direction buffer pa receives a copy of x).
-  static void apply_plain(pf_ctx* c, const ElastArgs<T>& e, T* x0, T* x1, T* x2, double* part) {
+  // q = A x on the apply kernel; with jr set, the block partials are
+  // ||jr - q||^2 instead of x.q
+  static void apply_plain(pf_ctx* c, const ElastArgs<T>& e, T* x0, T* x1, T* x2, double* part,
+                          const T* const* jr = nullptr) {
     if constexpr (DIM == 3) {
       const Layout& L = c->L;
       ElastArgs<T> ap = e;
-      ap.plain = 1;
       ap.kz = L.kz_ap;
       ap.part = part;
       T* x[3] = {x0, x1, x2};
@@ -337,8 +341,9 @@ struct Impl {
         ap.u[d] = c->arr<T>(L.o_pa[d]);
         ap.o1[d] = c->arr<T>(L.o_pa[d]);
         ap.o2[d] = c->arr<T>(L.o_q[d]);
+        ap.jr[d] = jr ? jr[d] : nullptr;
       }
-      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_apply3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, c->stream, ap);
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_apply3<T, kApplyBY, APPLY_PLAIN>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, c->stream, ap);
     }
   }
 
@@ -370,8 +375,9 @@ struct Impl {
     double* part_a = c->arr<double>(L.o_part_a);
     double* part_b = c->arr<double>(L.o_part_b);
     if constexpr (DIM == 3) {
-      // b, D^-1 and the partials of ||b||^2 in one pass; then r = b - A u from
-      // the apply kernel, z = D^-1 r and the partials CG starts from
+      // b, D^-1 and the partials of ||b||^2 in one pass; then, on the apply
+      // kernel, q = A u with r = b - q, z = D^-1 r and the partials CG starts
+      // from formed in its epilogue (q itself is not stored)
       ElastArgs<T> sa = e;
       sa.part = part_b;
       for (int d = 0; d < 3; ++d) {
@@ -380,22 +386,21 @@ struct Impl {
       }
       sa.kz = L.kz_ap;
       timed_launch(c, PF_K_SOLVE_SETUP, -1, k_setup3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, sa);
-      apply_plain(c, e, c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2]), part_a);
-      ResidQArgs<T> rq{};
+      ElastArgs<T> ra = e;
+      ra.kz = L.kz_ap;
       for (int d = 0; d < 3; ++d) {
-        rq.u[d] = c->arr<T>(L.o_u[d]);
-        rq.q[d] = c->arr<T>(L.o_q[d]);
-        rq.b[d] = c->arr<T>(L.o_b[d]);
-        rq.dinv[d] = c->arr<T>(L.o_di[d]);
-        rq.r[d] = c->arr<T>(L.o_r[d]);
-        rq.z[d] = c->arr<T>(L.o_z[d]);
+        ra.z[d] = c->arr<T>(L.o_u[d]);      // the vector applied
+        ra.u[d] = c->arr<T>(L.o_u[d]);      // not read; zeroed when b = 0
+        ra.jr[d] = c->arr<T>(L.o_b[d]);
+        ra.dinv[d] = c->arr<T>(L.o_di[d]);
+        ra.o1[d] = c->arr<T>(L.o_r[d]);
+        ra.o2[d] = c->arr<T>(L.o_z[d]);
       }
-      rq.part_in = part_b;
-      rq.n_in = (int)(L.gap.x * L.gap.y * L.gap.z);   // the set-up pass's ||b||^2 partials
-      rq.part = part_u;
-      rq.scal = c->scal();
-      rq.n = L.g.n;
-      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_resid_q<T>, dim3(L.nb_el), dim3(NT), 0, st, rq);
+      ra.part_in = part_b;
+      ra.n_in = L.nb_res;                   // the set-up pass's ||b||^2 partials
+      ra.part = part_u;
+      ra.scal = c->scal();
+      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_apply3<T, kApplyBY, APPLY_RESID>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ra);
       LAUNCHCHK(c);
     } else {
       // ||b||^2
@@ -464,17 +469,17 @@ struct Impl {
           up.p[d] = c->arr<T>(pnew[d]);
         }
         ap.parity = par;
-        ap.n_in = launched == 0 ? L.nb_el : L.nb_upd;
+        ap.n_in = launched == 0 ? L.nb_res : L.nb_upd;
         up.parity = par;
         if constexpr (DIM == 3)
-          timed_launch(c, PF_K_APPLY, launched, k_apply3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
+          timed_launch(c, PF_K_APPLY, launched, k_apply3<T, kApplyBY, APPLY_CG>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
         else
           timed_launch(c, PF_K_APPLY, launched, k_apply2<T>, L.gap, dim3(A2W), 0, st, ap);
         timed_launch(c, PF_K_UPDATE, launched, k_cg_update<T, DIM>, dim3(L.nb_upd), dim3(NT), 0, st, up);
         ++launched;
       }
       timed_launch(c, PF_K_OTHER, -1, k_cg_check, dim3(1), dim3(NT), 0, st, (const double*)part_u,
-                           launched == 0 ? L.nb_el : L.nb_upd, c->scal(), c->cfg.cg_rtol * c->cfg.cg_rtol);
+                           launched == 0 ? L.nb_res : L.nb_upd, c->scal(), c->cfg.cg_rtol * c->cfg.cg_rtol);
       LAUNCHCHK(c);
       HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal(), S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(c, hipStreamSynchronize(st));
@@ -502,19 +507,19 @@ struct Impl {
       auto& pr = c->pending[q];
       if (pr.launch >= c->last_iters && (pr.kind == PF_K_APPLY || pr.kind == PF_K_UPDATE)) pr.kind = PF_K_OTHER;
     }
-    // true residual ||b - A u||
+    // true residual ||b - A u|| (3D: the apply kernel's ||b - q||^2 partials)
+    int n_true = L.nb_el;
     if constexpr (DIM == 3) {
-      apply_plain(c, e, c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2]), part_a);
-      timed_launch(c, PF_K_SOLVE_SETUP, -1, k_true_q<T>, dim3(L.nb_el), dim3(NT), 0, st, (const T*)c->arr<T>(L.o_b[0]),
-                           (const T*)c->arr<T>(L.o_b[1]), (const T*)c->arr<T>(L.o_b[2]), (const T*)c->arr<T>(L.o_q[0]),
-                           (const T*)c->arr<T>(L.o_q[1]), (const T*)c->arr<T>(L.o_q[2]), (long)L.g.n, part_b);
+      const T* bvec[3] = {c->arr<T>(L.o_b[0]), c->arr<T>(L.o_b[1]), c->arr<T>(L.o_b[2])};
+      apply_plain(c, e, c->arr<T>(L.o_u[0]), c->arr<T>(L.o_u[1]), c->arr<T>(L.o_u[2]), part_b, bvec);
+      n_true = (int)(L.gap.x * L.gap.y * L.gap.z);
     } else {
       ElastArgs<T> t = e;
       for (int d = 0; d < DIM; ++d) t.u[d] = c->arr<T>(L.o_u[d]);
       t.part = part_b;
       timed_launch(c, PF_K_SOLVE_SETUP, -1, k_elast<T, DIM, M_TRUE>, L.gel, dim3(NT), 0, st, t);
     }
-    timed_launch(c, PF_K_OTHER, -1, k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part_b, L.nb_el, c->scal(), (int)S_TRUE);
+    timed_launch(c, PF_K_OTHER, -1, k_sum_to, dim3(1), dim3(NT), 0, st, (const double*)part_b, n_true, c->scal(), (int)S_TRUE);
     LAUNCHCHK(c);
     if (!conv)
       return fail(c, PF_ERR_CG_NOT_CONVERGED, "CG did not reach rtol %.3g in %d iterations", c->cfg.cg_rtol, maxit);

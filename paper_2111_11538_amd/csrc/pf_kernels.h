@@ -38,9 +38,11 @@ struct ElastArgs {
   double tol2;             // cg_rtol^2
   int parity;              // launch position parity inside the CG loop
   int kz;                  // z planes per block
-  int plain;               // APPLY (3D): q = A z only, outside the CG recurrence (no scalars read or
-                           // written, u not read, o1 not written)
-  const T* jr[3];          // APPLY (3D, plain): if set, the partials are ||jr - q||^2 instead of p.q
+  const T* jr[3];          // APPLY_PLAIN (3D): if set, the partials are ||jr - q||^2 instead of z.q;
+                           // APPLY_RESID: b.  The residual pass writes r = b - q into o1, z = D^-1 r
+                           // into o2 (q not stored) and partials r.z, r.r; it opens the solve's scalars
+                           // from the ||b||^2 partials part_in[0..n_in), and with b = 0 sets the
+                           // vector (u[]) and r, z to zero
 };
 
 // Local tile coordinates: lx = i - i0 + 1 in [0, TX+1], ly = j - j0 + 1 in [0, TY+1].
@@ -367,71 +369,7 @@ __global__ __launch_bounds__(NT) void k_elast(ElastArgs<T> a) {
   elast_tile<T, DIM, MODE>(a, blockIdx.x, blockIdx.y, blockIdx.z, zero_u, bid, nblk, smem);
 }
 
-// Residual of u from q = A u and the stored b (3D): r = b - q, z = D^-1 r,
-// partials of r.z and r.r (one pair per block, as the residual pass writes
-// them); also opens the solve's device scalars (||b||^2 from the b-norm
-// partials).  With b = 0 the solution is u = 0.
-template <typename T>
-struct ResidQArgs {
-  T* u[3];
-  const T* q[3];           // A u
-  const T* b[3];
-  const T* dinv[3];
-  T* r[3];
-  T* z[3];
-  const double* part_in;   // ||b||^2 partials
-  int n_in;
-  double* part;            // out: r.z and r.r partials, [2][gridDim.x]
-  double* scal;
-  long n;
-};
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_resid_q(ResidQArgs<T> a) {
-  __shared__ double red[NT / 64];
-  const double bb = sum_partials(a.part_in, a.n_in, red);
-  const bool zero_u = bb == 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.scal[S_BB] = bb;
-    a.scal[S_FIRST] = 1.0;
-    a.scal[S_CONV] = 0.0;
-    a.scal[S_ITERS] = 0.0;
-  }
-  double rz = 0.0, rr = 0.0;
-  for (long e = blockIdx.x * (long)NT + threadIdx.x; e < a.n; e += (long)gridDim.x * NT) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T r = zero_u ? T(0) : a.b[c][e] - a.q[c][e];
-      const T z = a.dinv[c][e] * r;
-      a.r[c][e] = r;
-      a.z[c][e] = z;
-      if (zero_u) a.u[c][e] = T(0);
-      rz += (double)r * (double)z;
-      rr += (double)r * (double)r;
-    }
-  }
-  rz = block_sum(rz, red);
-  rr = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    a.part[blockIdx.x] = rz;
-    a.part[gridDim.x + blockIdx.x] = rr;
-  }
-}
-
-// Partials of ||b - q||^2 (the true residual when q = A u).
-template <typename T>
-__global__ __launch_bounds__(NT) void k_true_q(const T* __restrict__ b0, const T* __restrict__ b1, const T* __restrict__ b2,
-                                              const T* __restrict__ q0, const T* __restrict__ q1, const T* __restrict__ q2,
-                                              long n, double* __restrict__ part) {
-  __shared__ double red[NT / 64];
-  double acc = 0.0;
-  for (long e = blockIdx.x * (long)NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
-    const double x = (double)b0[e] - (double)q0[e], y = (double)b1[e] - (double)q1[e], w = (double)b2[e] - (double)q2[e];
-    acc += x * x + y * y + w * w;
-  }
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
-}
 
 // ---------------------------------------------------------------------------
 // 3D q = A p with the direction update p = z + beta p fused in.
@@ -454,8 +392,16 @@ struct ApplyTile {
   static constexpr int NHALO = 3 * (TX + BY);        // ring stress items per plane
 };
 
-template <typename T, int BY>
-__global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 ? 4 : 1) void k_apply3(ElastArgs<T> a) {
+// Modes (compile time, so that the CG instance carries no other code):
+// APPLY_CG inside the CG recurrence; APPLY_PLAIN q = A z outside it (the
+// previous direction not read, the new one not written; with ElastArgs::jr
+// set, ||jr - q||^2 partials); APPLY_RESID the residual pass r = b - A z
+// (ElastArgs::resid).
+enum ApplyMode { APPLY_CG = 0, APPLY_PLAIN = 1, APPLY_RESID = 2 };
+
+template <typename T, int BY, int AM>
+__global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_RESID ? 4 : 1) void k_apply3(ElastArgs<T> a) {
+  constexpr bool kPlain = AM != APPLY_CG, kResid = AM == APPLY_RESID;
   using TL = ApplyTile<BY>;
   constexpr int W = TL::W, S = TL::S, NTB = TL::NTB;
   __shared__ T sP[2][3][S];
@@ -483,7 +429,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 ? 4 : 1) void k_
   // CG scalars (identical in every block)
   double beta = 0.0;
   bool first = true;                 // plain: p_new = z
-  if (!a.plain) {
+  if constexpr (!kPlain) {
     if (a.scal[S_CONV] != 0.0) return;
     double rzv = 0.0, rrv = 0.0;
     {
@@ -509,6 +455,25 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 ? 4 : 1) void k_
     }
   }
   const T tb = (T)beta;
+  bool zero_u = false;
+  if constexpr (kResid) {            // residual of the set-up: ||b||^2 from the set-up partials
+    double v = 0.0;
+    for (int q = threadIdx.x; q < a.n_in; q += NTB) v += a.part_in[q];
+    v = wave_sum(v);
+    __shared__ double shb[NTB / 64];
+    if ((threadIdx.x & 63) == 0) shb[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double bb = 0.0;
+#pragma unroll
+    for (int w = 0; w < NTB / 64; ++w) bb += shb[w];
+    zero_u = bb == 0.0;
+    if (bid == 0 && threadIdx.x == 0) {
+      a.scal[S_BB] = bb;
+      a.scal[S_FIRST] = 1.0;
+      a.scal[S_CONV] = 0.0;
+      a.scal[S_ITERS] = 0.0;
+    }
+  }
 
   // ring position handled by this thread (threads >= NRING have none)
   int rg_t = S, rg_e = 0;
@@ -541,7 +506,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 ? 4 : 1) void k_
     ru_[d] = buf_rsrc(a.u[d], nbytes);
   }
   const __amdgpu_buffer_rsrc_t rG = buf_rsrc(a.G, nbytes), rK = buf_rsrc(a.K, nbytes);
-  if (a.plain)        // p = z: the previous direction is never read
+  if constexpr (kPlain)        // p = z: the previous direction is never read
 #pragma unroll
     for (int d = 0; d < 3; ++d) ru_[d] = buf_rsrc(a.u[d], 0);
   auto fetch = [&](Raw& R, int kk, bool want) {
@@ -685,7 +650,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 ? 4 : 1) void k_
     __syncthreads();
   }
 
-  double acc = 0.0;
+  double acc = 0.0, acc1 = 0.0;
   // one plane k in slot sk (plane k+1 in slot sk1); C holds its own values,
   // N those of plane k+1.  R carries plane k+2 in (stashed into slot sk and
   // into C, which then holds the plane after N) and is refilled with plane k+4.
@@ -722,14 +687,28 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 ? 4 : 1) void k_
       const T q0 = f_i * (sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n);
       const T q1 = f_j * (sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n);
       const T q2 = k > 0 ? szz_prev - szz + sxz_c - sSxz[sk][c + 1] + syz_c - sSyz[sk][c + W] : T(0);
-      if (!a.plain) { a.o1[0][e] = C.p[0]; a.o1[1][e] = C.p[1]; a.o1[2][e] = C.p[2]; }
+      if constexpr (kResid) {
+        const T qv[3] = {q0, q1, q2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const T r = zero_u ? T(0) : a.jr[d][e] - qv[d];
+          const T z = a.dinv[d][e] * r;
+          a.o1[d][e] = r;
+          a.o2[d][e] = z;
+          if (zero_u) a.u[d][e] = T(0);
+          acc += (double)r * (double)z;
+          acc1 += (double)r * (double)r;
+        }
+      } else {
+      if constexpr (!kPlain) { a.o1[0][e] = C.p[0]; a.o1[1][e] = C.p[1]; a.o1[2][e] = C.p[2]; }
       a.o2[0][e] = q0; a.o2[1][e] = q1; a.o2[2][e] = q2;
-      if (a.jr[0]) {
+      if (kPlain && a.jr[0]) {
         const double d0 = (double)a.jr[0][e] - (double)q0, d1 = (double)a.jr[1][e] - (double)q1,
                      d2 = (double)a.jr[2][e] - (double)q2;
         acc += d0 * d0 + d1 * d1 + d2 * d2;
       } else {
         acc += (double)C.p[0] * (double)q0 + (double)C.p[1] * (double)q1 + (double)C.p[2] * (double)q2;
+      }
       }
     }
     szz_prev = szz;
@@ -749,6 +728,10 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 ? 4 : 1) void k_
   if (k < k1) plane(k, rb, 0, oA, oB);
   const double s0 = block_sum_n<NTB>(acc, red);
   if (threadIdx.x == 0) a.part[bid] = s0;
+  if constexpr (kResid) {
+    const double s1 = block_sum_n<NTB>(acc1, red);
+    if (threadIdx.x == 0) a.part[gridDim.x * gridDim.y * gridDim.z + bid] = s1;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -389,7 +389,6 @@ static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
     hipLaunchKernelGGL((k_learned_delta<T>), dim3(2048), dim3(pfn::CNT), 0, st, dl[0], dl[1], dl[2],
                        (const float*)nn->out, (const double*)nn->dscal, L.g);
     ElastArgs<T> ap = e;
-    ap.plain = 1;
     ap.kz = L.kz_ap;
     ap.part = part;
     // q = A d, with the partials of ||r - q||^2 (the learned start's residual)
@@ -400,12 +399,13 @@ static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part) {
       ap.o2[d] = q[d];
       ap.jr[d] = r[d];
     }
-    timed_launch(c, PF_K_OTHER, -1, k_apply3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
+    timed_launch(c, PF_K_OTHER, -1, k_apply3<T, kApplyBY, APPLY_PLAIN>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
     const long n = L.g.n;
     double* part_u = c->arr<double>(L.o_part_u);
     hipLaunchKernelGGL(k_judge_decide, dim3(1), dim3(NT), 0, st, (const double*)part, (int)(L.gap.x * L.gap.y * L.gap.z),
-                       (const double*)(part_u + L.nb_el), L.nb_el, c->scal());
-    hipLaunchKernelGGL((k_judge_apply<T>), dim3(L.nb_el), dim3(NT), 0, st, u[0], u[1], u[2], (const T*)dl[0],
+                       (const double*)(part_u + L.nb_res), L.nb_res, c->scal());
+    // (its grid is the residual pass's, so CG reads the same number of partials either way)
+    hipLaunchKernelGGL((k_judge_apply<T>), dim3(L.nb_res), dim3(NT), 0, st, u[0], u[1], u[2], (const T*)dl[0],
                        (const T*)dl[1], (const T*)dl[2], r[0], r[1], r[2], (const T*)q[0], (const T*)q[1],
                        (const T*)q[2], (const T*)di[0], (const T*)di[1], (const T*)di[2], z[0], z[1], z[2], n,
                        (const double*)c->scal(), part_u);
