@@ -1405,7 +1405,6 @@ __device__ __forceinline__ T shear_yz(const Grid& g, const T* uy, const T* uz, i
 
 template <typename T, int DIM>
 __device__ __forceinline__ void step_tile(const CellArgs<T>& a, int bx, int by, int bz, int pidx, int pstride) {
-  __shared__ double red[NT / 64];
   const Grid& g = a.g;
   const KP<T>& p = a.p;
   const int i = bx * TX + (threadIdx.x & (TX - 1));
@@ -1575,10 +1574,29 @@ __device__ __forceinline__ void step_tile(const CellArgs<T>& a, int bx, int by, 
     bool fin = isfinite(nf) && isfinite(nw) && isfinite(nO) && isfinite(nH) && isfinite(nW) && isfinite(vm);
     acc[7] = fin ? 0.0 : 1.0;
   }
+  // the eight partials together: the wave trees of all quantities interleaved,
+  // then one exchange across the waves (the same operations in the same
+  // order as eight separate block reductions, with two barriers instead of 16)
+  __shared__ double red8[NQ_STEP][NT / 64];
 #pragma unroll
-  for (int qn = 0; qn < NQ_STEP; ++qn) {
-    double s = (qn == 5 || qn == 6) ? block_max(acc[qn], red) : block_sum(acc[qn], red);
-    if (threadIdx.x == 0) a.part[qn * pstride + pidx] = s;
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int qn = 0; qn < NQ_STEP; ++qn) {
+      const double v = __shfl_xor(acc[qn], o, 64);
+      acc[qn] = (qn == 5 || qn == 6) ? fmax(acc[qn], v) : acc[qn] + v;
+    }
+  __syncthreads();                  // the previous tile's exchange has been read
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int qn = 0; qn < NQ_STEP; ++qn) red8[qn][threadIdx.x >> 6] = acc[qn];
+  __syncthreads();
+  if (threadIdx.x < NQ_STEP) {
+    const int qn = threadIdx.x;
+    const bool mx = qn == 5 || qn == 6;
+    double s = mx ? red8[qn][0] : 0.0 + red8[qn][0];
+#pragma unroll
+    for (int q = 1; q < NT / 64; ++q) s = mx ? fmax(s, red8[qn][q]) : s + red8[qn][q];
+    a.part[qn * pstride + pidx] = s;
   }
 }
 
