@@ -298,7 +298,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
   __shared__ double shRR[kMaxBatch], shPQ[kMaxBatch];  // r.r of this pass, p.q
   __shared__ int up_fine_sh;                          // the last update pass used the fine chunks
   __shared__ int flag_sh, all_sh;
-  __shared__ double red[NT / 64];
+  __shared__ double red[2 * (NT / 64)];
   __shared__ int grouped_sh;
   unsigned gen = 0u;
   int grouped = 0;                 // the first barrier is flat; it publishes the XCD check
@@ -458,8 +458,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
       }
       double rz = 0.0, rr = 0.0;
       cg_update_range<T, 2>(a, cr.v0 + tid, cr.v1, NT, shB[cr.inst], rz, rr);
-      rz = block_sum(rz, red);
-      rr = block_sum(rr, red);
+      block_sum2(rz, rr, red);
       if (tid == 0) {
         pu[w] = rz;
         pu[B.n_up + w] = rr;

@@ -214,6 +214,24 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int q = 0; q < NT / 64; ++q) s += sh[q];
   return s;
 }
+// Two sums over the block at once (the same operations and order as two
+// block_sum calls, with two barriers instead of four); sh holds 2 * NT / 64.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) { sh[w] = a; sh[NT / 64 + w] = b; }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) { sa += sh[q]; sb += sh[NT / 64 + q]; }
+  a = sa;
+  b = sb;
+}
 __device__ __forceinline__ double block_max(double v, double* sh) {
   v = wave_max(v);
   int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -243,6 +261,7 @@ __device__ __forceinline__ double block_sum_n(double v, double* sh) {
 // Sum of part[0..n) in a fixed order; identical in every block.
 __device__ __forceinline__ double sum_partials(const double* part, int n, double* sh) {
   double v = 0.0;
+#pragma unroll 8
   for (int q = threadIdx.x; q < n; q += NT) v += part[q];
   return block_sum(v, sh);
 }

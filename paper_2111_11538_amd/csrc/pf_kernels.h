@@ -1277,7 +1277,7 @@ __device__ __forceinline__ void cg_update_range(const UpdArgs<T>& a, int v0, int
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
-  __shared__ double red[NT / 64];
+  __shared__ double red[2 * (NT / 64)];
   if (a.scal[S_CONV] != 0.0) return;
   const double pq = sum_partials(a.part_in, a.n_in, red);
   const double alpha = a.scal[S_RZ + a.parity] / pq;
@@ -1285,8 +1285,8 @@ __global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
   constexpr int VN = sizeof(V) / sizeof(T);
   double rz = 0.0, rr = 0.0;
   cg_update_range<T, DIM>(a, blockIdx.x * NT + threadIdx.x, a.n / VN, gridDim.x * NT, alpha, rz, rr);
-  const double s0 = block_sum(rz, red);
-  const double s1 = block_sum(rr, red);
+  double s0 = rz, s1 = rr;
+  block_sum2(s0, s1, red);
   if (threadIdx.x == 0) {
     a.part[blockIdx.x] = s0;
     a.part[gridDim.x + blockIdx.x] = s1;
@@ -1657,6 +1657,7 @@ __global__ __launch_bounds__(NT) void k_ledger(const double* part, int n, double
   // one pass over the eight partial arrays (the same per-thread order as
   // sum_partials, so the sums are unchanged), all loads of an index in flight together
   double O = 0.0, H = 0.0, X = 0.0, bo = 0.0, bh = 0.0, vm = 0.0, ep = 0.0, nf = 0.0;
+#pragma unroll 8
   for (int q = threadIdx.x; q < n; q += NT) {
     O += part[q];
     H += part[n + q];

@@ -272,7 +272,7 @@ __global__ __launch_bounds__(NT) void k_judge_apply(T* __restrict__ u0, T* __res
                                                    const T* __restrict__ di1, const T* __restrict__ di2,
                                                    T* __restrict__ z0, T* __restrict__ z1, T* __restrict__ z2, long n,
                                                    const double* __restrict__ scal, double* __restrict__ part) {
-  __shared__ double red[NT / 64];
+  __shared__ double red[2 * (NT / 64)];
   if (scal[S_JB] == 0.0) return;
   double rz = 0.0, rr = 0.0;
   for (long e = blockIdx.x * (long)NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
@@ -286,8 +286,7 @@ __global__ __launch_bounds__(NT) void k_judge_apply(T* __restrict__ u0, T* __res
     rz += (double)a * (double)za + (double)b * (double)zb + (double)c * (double)zc;
     rr += (double)a * (double)a + (double)b * (double)b + (double)c * (double)c;
   }
-  rz = block_sum(rz, red);
-  rr = block_sum(rr, red);
+  block_sum2(rz, rr, red);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = rz;
     part[gridDim.x + blockIdx.x] = rr;
