@@ -34,8 +34,10 @@ def algorithmic_bytes_per_cell(kind, dim, es):
     nc = 4 if dim == 2 else 6
     if kind == "apply":        # read z, p_old (dim each), K, G; write p_new, q (dim each)
         return (4 * dim + 2) * es
-    if kind == "update":       # read u, p, r, q, D^-1; write u, r, z (dim each)
-        return 8 * dim * es
+    if kind == "update":
+        if dim == 3:           # read r, q, D^-1, write r, z; after odd iterations also read u, p, p_prev, write u
+            return 7 * dim * es
+        return 8 * dim * es    # read u, p, r, q, D^-1; write u, r, z (dim each)
     if kind == "step":         # read 5 fields, mu, u, eps_p, eps_P; write 5 fields, eps_p, eps_P
         return (5 + 1 + dim + nc + 1 + 5 + nc + 1) * es
     if kind == "mu":           # read phi_f, phi_w, x_O; write mu

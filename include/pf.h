@@ -145,6 +145,12 @@ pf_status pf_step(pf_ctx *ctx, int nsteps, pf_step_stats *last);
  * cg_rel_resid of `stats` (nullable). */
 pf_status pf_mech_solve(pf_ctx *ctx, int warm, pf_step_stats *stats);
 
+/* CG launches queued between two convergence checks (each check synchronises
+ * the stream).  n = 0 (the default) adapts the chunk to the iteration counts
+ * of the last two solves; n >= 1 fixes it.  The results do not depend on it:
+ * iterations queued past convergence exit at entry.  Errors: n < 0. */
+pf_status pf_cg_chunk(pf_ctx *ctx, int n);
+
 /* Copy one field between the context and caller memory.  dir 0: get (context
  * -> ptr), 1: set (ptr -> context).  ptr holds FP64 compact data (layouts
  * above) of exactly nbytes; ptr_is_device selects a device or host pointer.

@@ -22,6 +22,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kUpdBlocksMax = 512;
 constexpr int kApplyBY = 8;          // tile height of the 3D apply kernel (block = 64 x 8 threads)
+constexpr int kCgBY = 8;             // tile height of its CG instance
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -35,6 +36,9 @@ struct Layout {
   dim3 gel, gcell;
   int kz_ap;               // z planes per block of the 3D apply kernel
   dim3 gap;                // its grid (64 x kApplyBY tiles)
+  int kz_cg;               // the same for the CG instance (64 x kCgBY tiles); 2D: the apply grid
+  dim3 gcg;
+  int nb_cg;
   int nb_el, nb_cell, nb_upd;
   int nb_res;              // blocks (partial pairs) of the residual pass CG starts from: the apply grid (3D), the elast grid (2D)
   size_t stage_elems;
@@ -85,13 +89,20 @@ Layout make_layout(const pf_config* c) {
     L.kz_ap = 8;
     while (L.kz_ap > 1 && (long long)nbx * nby8 * ((g.nz + L.kz_ap - 1) / L.kz_ap) < 512) L.kz_ap /= 2;
     L.gap = dim3(nbx, nby8, (g.nz + L.kz_ap - 1) / L.kz_ap);
+    int nbyc = (g.ny + kCgBY - 1) / kCgBY;
+    L.kz_cg = 8;
+    while (L.kz_cg > 1 && (long long)nbx * nbyc * ((g.nz + L.kz_cg - 1) / L.kz_cg) < 512) L.kz_cg /= 2;
+    L.gcg = dim3(nbx, nbyc, (g.nz + L.kz_cg - 1) / L.kz_cg);
   } else {
     // rows of A2W columns marching along y over kz_ap rows; keep >= 512 blocks
     int nbx2 = (g.nx + A2W - 1) / A2W;
     L.kz_ap = 32;
     while (L.kz_ap > 1 && (long long)nbx2 * ((g.ny + L.kz_ap - 1) / L.kz_ap) < 512) L.kz_ap /= 2;
     L.gap = dim3(nbx2, (g.ny + L.kz_ap - 1) / L.kz_ap, 1);
+    L.kz_cg = L.kz_ap;
+    L.gcg = L.gap;
   }
+  L.nb_cg = (int)(L.gcg.x * L.gcg.y * L.gcg.z);
   L.nb_el = nbx * nby * (int)L.gel.z;
   L.gcell = dim3(nbx, nby, g.nz);
   L.nb_cell = nbx * nby * g.nz;
@@ -120,6 +131,7 @@ Layout make_layout(const pf_config* c) {
   L.o_scal = take(S_COUNT * sizeof(double));
   L.nb_res = c->dim == 3 ? (int)(L.gap.x * L.gap.y * L.gap.z) : L.nb_el;
   int nbmax = std::max(std::max(L.nb_el, (int)(L.gap.x * L.gap.y * L.gap.z)), std::max(L.nb_cell, L.nb_upd));
+  nbmax = std::max(nbmax, L.nb_cg);
   L.o_part_u = take(2 * (size_t)nbmax * sizeof(double));
   L.o_part_a = take(2 * (size_t)nbmax * sizeof(double));
   L.o_part_b = take(2 * (size_t)nbmax * sizeof(double));
@@ -169,6 +181,7 @@ struct pf_ctx {
   long long steps;
   int last_iters;
   int prev_iters;          // iteration count of the solve before the last one
+  int cg_chunk;            // CG launches between convergence checks (0: adaptive)
   int warm_used;
   // per-kernel event timing
   unsigned timing;         // bit mask of the kernel kinds being recorded (0: off)
@@ -432,7 +445,7 @@ struct Impl {
     up.scal = c->scal();
     up.part = part_u;
     up.part_in = part_a;
-    up.n_in = (int)(L.gap.x * L.gap.y * L.gap.z);
+    up.n_in = L.nb_cg;
     for (int d = 0; d < DIM; ++d) {
       ap.z[d] = c->arr<T>(L.o_z[d]);
       ap.o2[d] = c->arr<T>(L.o_q[d]);
@@ -444,7 +457,9 @@ struct Impl {
     }
     ap.part = part_a;
     ap.part_in = part_u;
-    ap.kz = L.kz_ap;
+    ap.kz = L.kz_cg;
+    if constexpr (DIM == 3)   // the apply launch that stops the solve completes u
+      for (int d = 0; d < 3; ++d) ap.xs[d] = c->arr<T>(L.o_u[d]);
 
     const int maxit = c->cfg.cg_max_iter;
     int launched = 0;
@@ -455,37 +470,61 @@ struct Impl {
     // later chunks grow with what has been launched.
     const int p2 = c->prev_iters > 0 ? c->prev_iters : c->last_iters;
     const int lo = std::min(c->last_iters, p2), hi = std::max(c->last_iters, p2);
-    int chunk = std::max(2, lo + 2);
+    int chunk = c->cg_chunk > 0 ? c->cg_chunk : std::max(2, lo + 2);
     int nchunk = 0;
+    auto apply_cg = [&](int j) {       // the apply launch of CG iteration j
+      const int par = j & 1;
+      const size_t* pold = par ? L.o_pb : L.o_pa;
+      const size_t* pnew = par ? L.o_pa : L.o_pb;
+      for (int d = 0; d < DIM; ++d) {
+        ap.u[d] = c->arr<T>(pold[d]);
+        ap.o1[d] = c->arr<T>(pnew[d]);
+        up.p[d] = c->arr<T>(pnew[d]);
+        up.pp[d] = c->arr<T>(pold[d]);
+      }
+      ap.parity = par;
+      ap.it = j;
+      ap.n_in = j == 0 ? L.nb_res : L.nb_upd;
+      up.parity = par;
+      if constexpr (DIM == 3)
+        timed_launch(c, PF_K_APPLY, j, k_apply3<T, kCgBY, APPLY_CG>, L.gcg, dim3(ApplyTile<kCgBY>::NTB), 0, st, ap);
+      else
+        timed_launch(c, PF_K_APPLY, j, k_apply2<T>, L.gap, dim3(A2W), 0, st, ap);
+    };
     while (true) {
       int n = std::min(chunk, maxit - launched);
       for (int q = 0; q < n; ++q) {
-        const int par = launched & 1;
-        const size_t* pold = par ? L.o_pb : L.o_pa;
-        const size_t* pnew = par ? L.o_pa : L.o_pb;
-        for (int d = 0; d < DIM; ++d) {
-          ap.u[d] = c->arr<T>(pold[d]);
-          ap.o1[d] = c->arr<T>(pnew[d]);
-          up.p[d] = c->arr<T>(pnew[d]);
-        }
-        ap.parity = par;
-        ap.n_in = launched == 0 ? L.nb_res : L.nb_upd;
-        up.parity = par;
-        if constexpr (DIM == 3)
-          timed_launch(c, PF_K_APPLY, launched, k_apply3<T, kApplyBY, APPLY_CG>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, ap);
-        else
-          timed_launch(c, PF_K_APPLY, launched, k_apply2<T>, L.gap, dim3(A2W), 0, st, ap);
+        apply_cg(launched);
         timed_launch(c, PF_K_UPDATE, launched, k_cg_update<T, DIM>, dim3(L.nb_upd), dim3(NT), 0, st, up);
         ++launched;
       }
       timed_launch(c, PF_K_OTHER, -1, k_cg_check, dim3(1), dim3(NT), 0, st, (const double*)part_u,
-                           launched == 0 ? L.nb_res : L.nb_upd, c->scal(), c->cfg.cg_rtol * c->cfg.cg_rtol);
+                   launched == 0 ? L.nb_res : L.nb_upd, c->scal(), c->cfg.cg_rtol * c->cfg.cg_rtol,
+                   DIM == 3 ? (double)(launched + 1) : 1.0);
       LAUNCHCHK(c);
       HIPCHK(c, hipMemcpyAsync(c->host_scal, c->scal(), S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(c, hipStreamSynchronize(st));
-      if (c->host_scal[S_CONV] != 0.0) { conv = true; break; }
-      if (launched >= maxit) break;
+      if (c->host_scal[S_CONV] != 0.0) {
+        conv = true;
+        // 3D: the check found the last update converged; the apply launch
+        // it marked adds that update's alpha p to u and stops
+        if (DIM == 3 && c->host_scal[S_CONV] == (double)(launched + 1)) {
+          apply_cg(launched);
+          LAUNCHCHK(c);
+        }
+        break;
+      }
+      if (launched >= maxit) {
+        if constexpr (DIM == 3) {   // not converged: u still gets the last update's alpha p
+          timed_launch(c, PF_K_OTHER, -1, k_cg_check, dim3(1), dim3(NT), 0, st, (const double*)part_u, L.nb_upd,
+                       c->scal(), -1.0, (double)(launched + 1));
+          apply_cg(launched);
+          LAUNCHCHK(c);
+        }
+        break;
+      }
       ++nchunk;
+      if (c->cg_chunk > 0) continue;
       chunk = nchunk == 1 && hi + 2 > launched ? hi + 2 - launched : std::max(4, std::min(64, launched / 4));
     }
     c->prev_iters = c->last_iters;
@@ -621,6 +660,7 @@ pf_status pf_init(const pf_config* cfg, const pf_params* params, void* workspace
   c->steps = 0;
   c->last_iters = 0;
   c->prev_iters = 0;
+  c->cg_chunk = 0;
   c->warm_used = cfg->warm;
   c->timing = 0u;
   c->timing_every = 1;
@@ -773,6 +813,13 @@ pf_status pf_timing_every(pf_ctx* c, int every) {
   if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
   if (every < 1) return fail(c, PF_ERR_INVALID_ARG, "every must be >= 1");
   c->timing_every = every;
+  return PF_OK;
+}
+
+pf_status pf_cg_chunk(pf_ctx* c, int n) {
+  if (!c) return fail(nullptr, PF_ERR_INVALID_ARG, "ctx is NULL");
+  if (n < 0) return fail(c, PF_ERR_INVALID_ARG, "chunk must be >= 0");
+  c->cg_chunk = n;
   return PF_OK;
 }
 

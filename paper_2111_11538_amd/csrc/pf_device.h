@@ -14,13 +14,15 @@ constexpr int NT = TX * TY;
 
 // Device scalars shared by the solver kernels (FP64 slots).
 enum Scal {
-  S_CONV = 0,      // 1 once the current solve has converged
+  S_CONV = 0,      // nonzero once the current solve has converged (3D CG: the index + 1
+                   // of the apply launch that completes the solution)
   S_FIRST = 1,     // 1 before the first CG update of a solve
   S_ITERS = 2,     // CG updates performed in the current solve
   S_BB = 3,        // ||b||^2
   S_RZ = 4,        // r.z of the two most recent iterations (slots 4, 5)
   S_RR = 6,        // ||r||^2 of the last check
   S_TRUE = 7,      // true ||b - A u||^2 after the solve
+  S_ALPHA = 8,     // alpha of the last CG update of even (slot 8) and odd (slot 9) index
   // ledger (persistent across steps)
   S_O0 = 10, S_H0 = 11, S_XO0 = 12, S_OOUT = 13, S_HOUT = 14,
   // last-step statistics

@@ -43,6 +43,8 @@ struct ElastArgs {
                            // into o2 (q not stored) and partials r.z, r.r; it opens the solve's scalars
                            // from the ||b||^2 partials part_in[0..n_in), and with b = 0 sets the
                            // vector (u[]) and r, z to zero
+  T* xs[3];                // APPLY_CG (3D): the solution (completed by the launch that stops the solve)
+  int it;                  // APPLY_CG (3D): index of this launch in the solve
 };
 
 // Local tile coordinates: lx = i - i0 + 1 in [0, TX+1], ly = j - j0 + 1 in [0, TY+1].
@@ -401,7 +403,7 @@ enum ApplyMode { APPLY_CG = 0, APPLY_PLAIN = 1, APPLY_RESID = 2 };
 
 template <typename T, int BY, int AM>
 __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_RESID ? 4 : 1) void k_apply3(ElastArgs<T> a) {
-  constexpr bool kPlain = AM != APPLY_CG, kResid = AM == APPLY_RESID;
+  constexpr bool kPlain = AM != APPLY_CG, kResid = AM == APPLY_RESID, kCG = AM == APPLY_CG;
   using TL = ApplyTile<BY>;
   constexpr int W = TL::W, S = TL::S, NTB = TL::NTB;
   __shared__ T sP[2][3][S];
@@ -426,11 +428,17 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   const T ih = a.p.ih;
   const int pl = g.px * g.ny;
 
+  const int k0 = bz * a.kz;
+  const int k1 = min(k0 + a.kz, g.nz);
+  const int own_e = own ? j * g.px + i : 0;
+
   // CG scalars (identical in every block)
   double beta = 0.0;
   bool first = true;                 // plain: p_new = z
-  if constexpr (!kPlain) {
-    if (a.scal[S_CONV] != 0.0) return;
+  if constexpr (kCG) {
+    const double cv = a.scal[S_CONV];
+    const double mine = (double)(a.it + 1);
+    if (cv != 0.0 && cv != mine) return;
     double rzv = 0.0, rrv = 0.0;
     {
       double v0 = 0.0, v1 = 0.0;
@@ -443,11 +451,23 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
 #pragma unroll
       for (int w = 0; w < NTB / 64; ++w) { rzv += sh2[0][w]; rrv += sh2[1][w]; }
     }
-    if (rrv <= a.tol2 * a.scal[S_BB]) {
-      if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = 1.0;
+    first = a.scal[S_FIRST] != 0.0;
+    // converged by the last update (found here, or by the check after a
+    // chunk of launches, which marks this launch): stop, after adding the
+    // last update's alpha p to x if that update left it pending (the updates
+    // add the steps of two iterations at a time, after odd iterations)
+    if (cv == mine || rrv <= a.tol2 * a.scal[S_BB]) {
+      if (bid == 0 && threadIdx.x == 0) a.scal[S_CONV] = mine;
+      if ((a.it & 1) && own) {
+        const T al = (T)a.scal[S_ALPHA];
+        for (int kk = k0; kk < k1; ++kk) {
+          const int e = own_e + kk * pl;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) a.xs[d][e] += al * a.u[d][e];
+        }
+      }
       return;
     }
-    first = a.scal[S_FIRST] != 0.0;
     beta = first ? 0.0 : rzv / a.scal[S_RZ + (a.parity ^ 1)];
     if (bid == 0 && threadIdx.x == 0) {
       a.scal[S_RZ + a.parity] = rzv;
@@ -488,7 +508,6 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     rg_in = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny;
     rg_e = rg_in ? jj * g.px + ii : 0;
   }
-  const int own_e = own ? j * g.px + i : 0;
 
   // raw (in-flight) loads of one plane: own column and ring position
   struct Raw {
@@ -604,8 +623,6 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     }
   };
 
-  const int k0 = bz * a.kz;
-  const int k1 = min(k0 + a.kz, g.nz);
   // LDS slots are numbered relative to k0 (plane m in slot (m - k0) & 1), so
   // inside the plane pairs below every slot index is a constant
   struct Own { T p[3], g, k; };       // own column's values of one plane
@@ -614,10 +631,10 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   // boundary factors (0 / 1) of the own column: edges on the domain boundary
   // carry no shear stress, the low boundary faces no force; all the LDS
   // values they multiply are finite (zeros outside the domain)
-  const T f_xy = (i > 0 && i < g.nx && j > 0 && j < g.ny) ? T(1) : T(0);
+  // (interior in x, interior in y; for the own column, whose q is stored,
+  // these are also the low boundary faces)
   const T f_xz = (i > 0 && i < g.nx) ? T(1) : T(0);
   const T f_yz = (j > 0 && j < g.ny) ? T(1) : T(0);
-  const T f_i = i > 0 ? T(1) : T(0), f_j = j > 0 ? T(1) : T(0);
 
   // prologue: planes k0-1 (slot 1), k0 (slot 0); sigma_zz of the own cell
   // below; z edges at level k0.  Plane m travels in register set ra when
@@ -665,7 +682,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     const T lam = C.k * tr - G2 * tr * T(1.0 / 3.0);
     const T sxx = lam + G2 * exx, syy = lam + G2 * eyy, szz = lam + G2 * ezz;
     const T gxy = T(0.25) * (sG[sk][c - W - 1] + sG[sk][c - W] + sG[sk][c - 1] + C.g);
-    const T sxy = f_xy * gxy * ((C.p[0] - sP[sk][0][c - W]) + (C.p[1] - sP[sk][1][c - 1])) * ih;
+    const T sxy = f_xz * f_yz * gxy * ((C.p[0] - sP[sk][0][c - W]) + (C.p[1] - sP[sk][1][c - 1])) * ih;
     const int kn1 = k + 1;
     T sxz_n = T(0), syz_n = T(0);
     if (kn1 < g.nz) {                 // block-uniform
@@ -684,8 +701,8 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     // (C) divergence onto the own faces of plane k
     if (own) {
       const int e = own_e + k * pl;
-      const T q0 = f_i * (sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n);
-      const T q1 = f_j * (sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n);
+      const T q0 = f_xz * (sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n);
+      const T q1 = f_yz * (sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n);
       const T q2 = k > 0 ? szz_prev - szz + sxz_c - sSxz[sk][c + 1] + syz_c - sSyz[sk][c + W] : T(0);
       if constexpr (kResid) {
         const T qv[3] = {q0, q1, q2};
@@ -971,8 +988,8 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
     __syncthreads();
     if (own) {
       const int e = own_e + k * pl;
-      const T q0 = f_i * (sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n);
-      const T q1 = f_j * (sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n);
+      const T q0 = f_xz * (sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n);
+      const T q1 = f_yz * (sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n);
       const T q2 = k > 0 ? szz_prev - szz + sxz_c - sSxz[sk][c + 1] + syz_c - sSyz[sk][c + W] : T(0);
       const T d0 = f_i * (sK[sk][c - 1] + T(4.0 / 3.0) * sG[sk][c - 1] + Mc + gxy + sGxy[c + W] + gxz_c + gxz_n);
       const T d1 = f_j * (sK[sk][c - W] + T(4.0 / 3.0) * sG[sk][c - W] + Mc + gxy + sGxy[c + 1] + gyz_c + gyz_n);
@@ -1221,6 +1238,7 @@ struct UpdArgs {
   int n;                   // elements per component array (multiple of 16)
   T* u[3];
   const T* p[3];
+  const T* pp[3];          // 3D: the previous direction (read after odd iterations)
   T* r[3];
   const T* q[3];
   const T* dinv[3];
@@ -1237,46 +1255,69 @@ template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double2; };
 
 // u += alpha p, r -= alpha q, z = D^-1 r over the vector range [v0, v1) of
-// every component (vectors of 16 bytes); accumulates r.z and r.r.
-template <typename T, int DIM>
+// every component (vectors of 16 bytes); accumulates r.z and r.r.  Without
+// XU, u is updated only when xstep is set, with the steps of this iteration
+// and the previous one (alpha_prev along pp), in the order of two single
+// updates.
+template <typename T, int DIM, bool XU = true>
 __device__ __forceinline__ void cg_update_range(const UpdArgs<T>& a, int v0, int v1, int vstride, double alpha,
-                                                double& rz, double& rr) {
-  const T al = (T)alpha;
+                                                double& rz, double& rr, bool xstep = false,
+                                                double alpha_prev = 0.0) {
+  const T al = (T)alpha, alp = (T)alpha_prev;
+  const bool ux = XU || xstep;
   using V = typename Vec4<T>::type;
   constexpr int VN = sizeof(V) / sizeof(T);
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
     V* uu = reinterpret_cast<V*>(a.u[c]);
     const V* pp = reinterpret_cast<const V*>(a.p[c]);
+    const V* ppp = reinterpret_cast<const V*>(XU ? a.p[c] : a.pp[c]);
     V* rrp = reinterpret_cast<V*>(a.r[c]);
     const V* qq = reinterpret_cast<const V*>(a.q[c]);
     const V* dd = reinterpret_cast<const V*>(a.dinv[c]);
     V* zz = reinterpret_cast<V*>(a.z[c]);
     for (int v = v0; v < v1; v += vstride) {
-      V uv = uu[v], pv = pp[v], rv = rrp[v], qv = qq[v], dv = dd[v], zv;
+      V uv, pv, ppv, rv = rrp[v], qv = qq[v], dv = dd[v], zv;
+      if (ux) {
+        uv = uu[v];
+        pv = pp[v];
+      }
+      if (!XU && xstep) ppv = ppp[v];
       T* ue = reinterpret_cast<T*>(&uv);
       const T* pe = reinterpret_cast<const T*>(&pv);
+      const T* ppe = reinterpret_cast<const T*>(&ppv);
       T* re = reinterpret_cast<T*>(&rv);
       const T* qe = reinterpret_cast<const T*>(&qv);
       const T* de = reinterpret_cast<const T*>(&dv);
       T* ze = reinterpret_cast<T*>(&zv);
 #pragma unroll
       for (int l = 0; l < VN; ++l) {
-        ue[l] += al * pe[l];
+        if constexpr (XU) {
+          ue[l] += al * pe[l];
+        } else if (xstep) {
+          const T t = ue[l] + alp * ppe[l];
+          ue[l] = t + al * pe[l];
+        }
         re[l] -= al * qe[l];
         ze[l] = de[l] * re[l];
         rz += (double)re[l] * (double)ze[l];
         rr += (double)re[l] * (double)re[l];
       }
-      uu[v] = uv;
+      if (ux) uu[v] = uv;
       rrp[v] = rv;
       zz[v] = zv;
     }
   }
 }
 
+// 3D: u is updated after odd iterations only, with the steps of the last two
+// (the previous direction is still held in the other direction buffer); the
+// alpha of every update goes to the device scalars (slot S_ALPHA + parity),
+// and the apply launch that stops the solve after an even iteration adds its
+// step.
 template <typename T, int DIM>
 __global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
+  constexpr bool XU = DIM != 3;
   __shared__ double red[2 * (NT / 64)];
   if (a.scal[S_CONV] != 0.0) return;
   const double pq = sum_partials(a.part_in, a.n_in, red);
@@ -1284,7 +1325,10 @@ __global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
   using V = typename Vec4<T>::type;
   constexpr int VN = sizeof(V) / sizeof(T);
   double rz = 0.0, rr = 0.0;
-  cg_update_range<T, DIM>(a, blockIdx.x * NT + threadIdx.x, a.n / VN, gridDim.x * NT, alpha, rz, rr);
+  const bool xstep = !XU && a.parity == 1;
+  const double alpha_prev = xstep ? a.scal[S_ALPHA] : 0.0;
+  cg_update_range<T, DIM, XU>(a, blockIdx.x * NT + threadIdx.x, a.n / VN, gridDim.x * NT, alpha, rz, rr, xstep,
+                              alpha_prev);
   double s0 = rz, s1 = rr;
   block_sum2(s0, s1, red);
   if (threadIdx.x == 0) {
@@ -1294,17 +1338,22 @@ __global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.scal[S_FIRST] = 0.0;
     a.scal[S_ITERS] += 1.0;
+    a.scal[S_ALPHA + a.parity] = alpha;
   }
 }
 
-// After a chunk of CG launches: mark convergence from the latest residual.
-__global__ __launch_bounds__(NT) void k_cg_check(const double* part_in, int n_in, double* scal, double tol2) {
+// After a chunk of CG launches: mark convergence from the latest residual
+// with `mark` (3D: the index + 1 of the apply launch that completes u);
+// tol2 < 0 marks without testing (3D, iteration limit reached: u is still
+// completed).
+__global__ __launch_bounds__(NT) void k_cg_check(const double* part_in, int n_in, double* scal, double tol2,
+                                                 double mark) {
   __shared__ double red[NT / 64];
   if (scal[S_CONV] != 0.0) return;
   double rr = sum_partials(part_in + n_in, n_in, red);
   if (threadIdx.x == 0) {
     scal[S_RR] = rr;
-    if (rr <= tol2 * scal[S_BB]) scal[S_CONV] = 1.0;
+    if (tol2 < 0.0 || rr <= tol2 * scal[S_BB]) scal[S_CONV] = mark;
   }
 }
 

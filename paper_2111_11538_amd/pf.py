@@ -69,7 +69,7 @@ class pf_step_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
-EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_fields", "pf_ledger_reset",
+EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_chunk", "pf_fields", "pf_ledger_reset",
            "pf_timing", "pf_timing_every", "pf_timing_get", "pf_last_error", "pf_destroy",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_set_tiles", "pf_batch_get_tiles",
            "pf_batch_fields", "pf_batch_step", "pf_batch_last_error", "pf_batch_destroy",
@@ -105,6 +105,8 @@ def lib():
         L.pf_timing.restype = C.c_int
         L.pf_timing_every.argtypes = [C.c_void_p, C.c_int]
         L.pf_timing_every.restype = C.c_int
+        L.pf_cg_chunk.argtypes = [C.c_void_p, C.c_int]
+        L.pf_cg_chunk.restype = C.c_int
         L.pf_timing_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
         L.pf_timing_get.restype = C.c_int
         L.pf_batch_workspace_bytes.argtypes = [C.POINTER(pf_config), C.POINTER(pf_extent), C.c_int]
@@ -281,6 +283,10 @@ class Context:
         st = pf_step_stats()
         self._check(lib().pf_mech_solve(self.ctx, WARM[warm], C.byref(st)))
         return st.as_dict()
+
+    def cg_chunk(self, n=0):
+        """CG launches between convergence checks (0: adaptive)."""
+        self._check(lib().pf_cg_chunk(self.ctx, int(n)))
 
     def timing(self, enable=True, kinds=None, every=1):
         """Start (or with enable False stop) event timing of the named kernel
