@@ -23,6 +23,9 @@ constexpr size_t kAlign = 256;
 constexpr int kUpdBlocksMax = 512;
 constexpr int kApplyBY = 8;          // tile height of the 3D apply kernel (block = 64 x 8 threads)
 constexpr int kCgBY = 8;             // tile height of its CG instance
+// deepest z slab per block of the 3D apply kernels (halved while the grid
+// has fewer than 512 blocks): the slab re-reads one plane at each end
+constexpr int kSlabMax = 32;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -86,11 +89,11 @@ Layout make_layout(const pf_config* c) {
   if (c->dim == 3) {
     // deeper z chunks and taller tiles cut the re-fetched halo; keep >= 512 blocks
     int nby8 = (g.ny + kApplyBY - 1) / kApplyBY;
-    L.kz_ap = 8;
+    L.kz_ap = kSlabMax;
     while (L.kz_ap > 1 && (long long)nbx * nby8 * ((g.nz + L.kz_ap - 1) / L.kz_ap) < 512) L.kz_ap /= 2;
     L.gap = dim3(nbx, nby8, (g.nz + L.kz_ap - 1) / L.kz_ap);
     int nbyc = (g.ny + kCgBY - 1) / kCgBY;
-    L.kz_cg = 8;
+    L.kz_cg = kSlabMax;
     while (L.kz_cg > 1 && (long long)nbx * nbyc * ((g.nz + L.kz_cg - 1) / L.kz_cg) < 512) L.kz_cg /= 2;
     L.gcg = dim3(nbx, nbyc, (g.nz + L.kz_cg - 1) / L.kz_cg);
   } else {
@@ -188,7 +191,7 @@ struct pf_ctx {
   int timing_every;        // CG kernels: record every n-th iteration only
   long long solves;        // solves started (rotates the sampled iterations)
   std::vector<hipEvent_t> ev_pool;
-  struct Rec { int kind, ev, launch; };
+  struct Rec { int kind, ev, launch; bool count; };
   std::vector<Rec> pending;   // start event index ev, stop ev + 1; launch = CG launch index or -1
   long long iters_total;
   int ev_next;
@@ -231,7 +234,7 @@ static pf_status fail(pf_ctx* c, pf_status s, const char* fmt, ...) {
 static void timing_flush(pf_ctx* c) {
   for (auto& pr : c->pending) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->ev_pool[pr.ev], c->ev_pool[pr.ev + 1]) == hipSuccess) {
+    if (pr.count && hipEventElapsedTime(&ms, c->ev_pool[pr.ev], c->ev_pool[pr.ev + 1]) == hipSuccess) {
       c->t_ms[pr.kind] += ms;
       c->t_n[pr.kind] += 1;
     }
@@ -257,17 +260,32 @@ static void timed(pf_ctx* c, int kind, F&& launch, int cg_launch = -1) {
   (void)hipEventRecord(c->ev_pool[i], c->stream);
   launch();
   (void)hipEventRecord(c->ev_pool[i + 1], c->stream);
-  c->pending.push_back({kind, i, cg_launch});
+  c->pending.push_back({kind, i, cg_launch, true});
 }
 
 // Launch of one kernel, timed when its kind is being recorded: the events
-// are attached to the dispatch itself (hipExtLaunchKernel), so they measure
-// the kernel's execution without extra marker packets in the stream.
+// are attached to the dispatch itself (hipExtLaunchKernel).  A dispatch
+// with events that follows one without them reads a few microseconds long,
+// so in a sampled CG iteration every launch carries events, and so does the
+// update before it; only the selected kinds of the sampled iteration count.
 template <typename K, typename... Args>
 static void timed_launch(pf_ctx* c, int kind, int cg_launch, K kernel, dim3 grid, dim3 block, uint32_t smem,
                          hipStream_t st, Args... args) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (((c->timing >> kind) & 1u) && !(cg_launch >= 0 && (cg_launch + c->solves) % c->timing_every != 0)) {
+  bool rec = false, count = false;
+  if (c->timing) {
+    const bool on = (c->timing >> kind) & 1u;
+    if (cg_launch < 0) {
+      rec = count = on;
+    } else {
+      const bool sampled = (cg_launch + c->solves) % c->timing_every == 0;
+      const bool guard = kind == PF_K_UPDATE && (cg_launch + 1 + c->solves) % c->timing_every == 0;
+      const bool cg_on = ((c->timing >> PF_K_APPLY) & 1u) || ((c->timing >> PF_K_UPDATE) & 1u);
+      rec = cg_on && (sampled || guard);
+      count = on && sampled;
+    }
+  }
+  if (rec) {
     if (c->ev_next + 2 > (int)c->ev_pool.size()) {
       (void)hipStreamSynchronize(c->stream);
       timing_flush(c);
@@ -276,7 +294,7 @@ static void timed_launch(pf_ctx* c, int kind, int cg_launch, K kernel, dim3 grid
     c->ev_next += 2;
     e0 = c->ev_pool[i];
     e1 = c->ev_pool[i + 1];
-    c->pending.push_back({kind, i, cg_launch});
+    c->pending.push_back({kind, i, cg_launch, count});
   }
   hipExtLaunchKernelGGL(kernel, grid, block, smem, st, e0, e1, 0u, args...);
 }
@@ -365,10 +383,13 @@ struct Impl {
     const Layout& L = c->L;
     hipStream_t st = c->stream;
     // Every launch of this solve stays in the pending list until it is
-    // retagged below: flush (which waits for the stream) only when the event
-    // pool might not hold a whole solve.
+    // retagged below: flush (which waits for the stream) when the event pool
+    // might not hold a solve of twice the recent iteration counts (a longer
+    // one flushes when the pool is full; only its launches still pending are
+    // then retagged).
     if (c->timing) {
-      const long long need = 4LL * (2LL * c->cfg.cg_max_iter + 256);
+      const long long expect = 2LL * std::max(c->last_iters, c->prev_iters) + 64;
+      const long long need = 4LL * (2LL * std::min<long long>(c->cfg.cg_max_iter, expect) + 256);
       if (c->ev_next + need > (long long)c->ev_pool.size()) {
         HIPCHK(c, hipStreamSynchronize(st));
         timing_flush(c);

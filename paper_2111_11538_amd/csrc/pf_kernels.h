@@ -12,6 +12,8 @@
 // writes one partial, and consumers reduce the partials in a fixed order.
 #pragma once
 
+#include <type_traits>
+
 #include "pf_device.h"
 
 namespace pfk {
@@ -1264,50 +1266,56 @@ __device__ __forceinline__ void cg_update_range(const UpdArgs<T>& a, int v0, int
                                                 double& rz, double& rr, bool xstep = false,
                                                 double alpha_prev = 0.0) {
   const T al = (T)alpha, alp = (T)alpha_prev;
-  const bool ux = XU || xstep;
   using V = typename Vec4<T>::type;
   constexpr int VN = sizeof(V) / sizeof(T);
+  // XM: 0 u untouched, 1 u += alpha p, 2 u += alpha_prev pp + alpha p
+  auto run = [&](auto xm_tag) {
+    constexpr int XM = decltype(xm_tag)::value;
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) {
-    V* uu = reinterpret_cast<V*>(a.u[c]);
-    const V* pp = reinterpret_cast<const V*>(a.p[c]);
-    const V* ppp = reinterpret_cast<const V*>(XU ? a.p[c] : a.pp[c]);
-    V* rrp = reinterpret_cast<V*>(a.r[c]);
-    const V* qq = reinterpret_cast<const V*>(a.q[c]);
-    const V* dd = reinterpret_cast<const V*>(a.dinv[c]);
-    V* zz = reinterpret_cast<V*>(a.z[c]);
-    for (int v = v0; v < v1; v += vstride) {
-      V uv, pv, ppv, rv = rrp[v], qv = qq[v], dv = dd[v], zv;
-      if (ux) {
-        uv = uu[v];
-        pv = pp[v];
-      }
-      if (!XU && xstep) ppv = ppp[v];
-      T* ue = reinterpret_cast<T*>(&uv);
-      const T* pe = reinterpret_cast<const T*>(&pv);
-      const T* ppe = reinterpret_cast<const T*>(&ppv);
-      T* re = reinterpret_cast<T*>(&rv);
-      const T* qe = reinterpret_cast<const T*>(&qv);
-      const T* de = reinterpret_cast<const T*>(&dv);
-      T* ze = reinterpret_cast<T*>(&zv);
-#pragma unroll
-      for (int l = 0; l < VN; ++l) {
-        if constexpr (XU) {
-          ue[l] += al * pe[l];
-        } else if (xstep) {
-          const T t = ue[l] + alp * ppe[l];
-          ue[l] = t + al * pe[l];
+    for (int c = 0; c < DIM; ++c) {
+      V* uu = reinterpret_cast<V*>(a.u[c]);
+      const V* pp = reinterpret_cast<const V*>(a.p[c]);
+      const V* ppp = reinterpret_cast<const V*>(XM == 2 ? a.pp[c] : a.p[c]);
+      V* rrp = reinterpret_cast<V*>(a.r[c]);
+      const V* qq = reinterpret_cast<const V*>(a.q[c]);
+      const V* dd = reinterpret_cast<const V*>(a.dinv[c]);
+      V* zz = reinterpret_cast<V*>(a.z[c]);
+      for (int v = v0; v < v1; v += vstride) {
+        V uv, pv, ppv, rv = rrp[v], qv = qq[v], dv = dd[v], zv;
+        if constexpr (XM >= 1) {
+          uv = uu[v];
+          pv = pp[v];
         }
-        re[l] -= al * qe[l];
-        ze[l] = de[l] * re[l];
-        rz += (double)re[l] * (double)ze[l];
-        rr += (double)re[l] * (double)re[l];
+        if constexpr (XM == 2) ppv = ppp[v];
+        T* ue = reinterpret_cast<T*>(&uv);
+        const T* pe = reinterpret_cast<const T*>(&pv);
+        const T* ppe = reinterpret_cast<const T*>(&ppv);
+        T* re = reinterpret_cast<T*>(&rv);
+        const T* qe = reinterpret_cast<const T*>(&qv);
+        const T* de = reinterpret_cast<const T*>(&dv);
+        T* ze = reinterpret_cast<T*>(&zv);
+#pragma unroll
+        for (int l = 0; l < VN; ++l) {
+          if constexpr (XM == 1) {
+            ue[l] += al * pe[l];
+          } else if constexpr (XM == 2) {
+            const T t = ue[l] + alp * ppe[l];
+            ue[l] = t + al * pe[l];
+          }
+          re[l] -= al * qe[l];
+          ze[l] = de[l] * re[l];
+          rz += (double)re[l] * (double)ze[l];
+          rr += (double)re[l] * (double)re[l];
+        }
+        if constexpr (XM >= 1) uu[v] = uv;
+        rrp[v] = rv;
+        zz[v] = zv;
       }
-      if (ux) uu[v] = uv;
-      rrp[v] = rv;
-      zz[v] = zv;
     }
-  }
+  };
+  if constexpr (XU) run(std::integral_constant<int, 1>());
+  else if (xstep) run(std::integral_constant<int, 2>());
+  else run(std::integral_constant<int, 0>());
 }
 
 // 3D: u is updated after odd iterations only, with the steps of the last two

@@ -761,10 +761,63 @@ __device__ __forceinline__ double eigen_strain_d(double pf, double Omega) {
   return cbrt(1.0 - Omega * hf) - 1.0;
 }
 
+// FP32 difference of the small-strain eigenstrain of two ferrite phases,
+// eps_T(x) - eps_T(y) with eps_T = cbrt(1 - Omega h) - 1, accurate to about
+// 1e-6 relative everywhere (the difference of the two cube roots in FP64
+// loses all digits near x = y = 1, where h' vanishes):
+//   h(x) - h(y) = (x - y) * mean of h'(t) = 30 t^2 (1 - t)^2 over [y, x],
+// the mean by 3-point Gauss-Legendre (exact for this quartic; a sum of
+// non-negative terms, with 1 - t formed from 1 - x and 1 - y), and
+//   cbrt(a) - cbrt(b) = (a - b) / (ca^2 + ca cb + cb^2).
+__device__ __forceinline__ float eigen_strain_diff_f(float x, float y, float Omega) {
+  const float m = 0.5f * (x + y), mc = 0.5f * ((1.f - x) + (1.f - y));
+  const float r = 0.7745966692414834f * (0.5f * (x - y));     // sqrt(3/5) times the half width
+  const float u0 = m * mc, u1 = (m - r) * (mc + r), u2 = (m + r) * (mc - r);
+  const float mean = (5.f * (u1 * u1 + u2 * u2) + 8.f * (u0 * u0)) * (1.f / 18.f);
+  const float dh = (x - y) * 30.f * mean;
+  const float hx = x * x * x * (x * (6.f * x - 15.f) + 10.f), hy = y * y * y * (y * (6.f * y - 15.f) + 10.f);
+  const float ca = cbrtf(1.f - Omega * hx), cb = cbrtf(1.f - Omega * hy);
+  return -Omega * dh / (ca * ca + ca * cb + cb * cb);
+}
+
 template <typename T>
 __global__ __launch_bounds__(CNT) void k_pack_inputs(PackArgs<T> a) {
   const double s = *a.s;
   const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  if constexpr (sizeof(T) == 4) {
+    // FP32 state: FP32 arithmetic (the inputs are rounded to bf16), 32-bit
+    // indices (a crop of a grid with fewer than 2^31 cells)
+    const float invf = (float)inv, es = (float)(32.0 * a.h * inv), Om = (float)a.Omega;
+    const int nv = a.cx * a.cy * a.cz, cxy = a.cx * a.cy;
+    for (int v = blockIdx.x * CNT + threadIdx.x; v < nv; v += gridDim.x * CNT) {
+      const int lk = v / cxy, r = v - lk * cxy, lj = r / a.cx, li = r - lj * a.cx;
+      const int i = a.x0 + li, j = a.y0 + lj, k = a.z0 + lk;
+      float c[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float tg[4] = {0.f, 0.f, 0.f, 0.f};
+      if (i < a.nx && j < a.ny && k < a.nz) {
+        const int e = k * (int)a.phi_f.ps + j * (int)a.phi_f.rs + i;   // every view shares the cell layout
+        const float pf = a.phi_f.p[e];
+        c[0] = pf;
+        c[1] = a.phi_w.p[e];
+        c[2] = eigen_strain_diff_f(pf, a.phi_prev.p[e], Om) * es;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const float u1 = a.u1[d].p[e];
+          const float u0 = a.u0[d].p ? a.u0[d].p[e] : 0.f;
+          c[3 + d] = (u1 - u0) * invf;
+          if (a.target) tg[d] = (a.u2[d].p[e] - u1) * invf;
+        }
+      }
+      uint4 o;
+      o.x = pack2(c[0], c[1]);
+      o.y = pack2(c[2], c[3]);
+      o.z = pack2(c[4], c[5]);
+      o.w = pack2(c[6], c[7]);
+      reinterpret_cast<uint4*>(a.x)[v] = o;
+      if (a.target) reinterpret_cast<float4*>(a.target)[v] = make_float4(tg[0], tg[1], tg[2], 0.f);
+    }
+    return;
+  }
   const long nv = (long)a.cx * a.cy * a.cz;
   for (long v = blockIdx.x * (long)CNT + threadIdx.x; v < nv; v += (long)gridDim.x * CNT) {
     const int li = (int)(v % a.cx), lj = (int)((v / a.cx) % a.cy), lk = (int)(v / ((long)a.cx * a.cy));

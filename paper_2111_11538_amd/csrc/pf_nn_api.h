@@ -229,11 +229,11 @@ __global__ __launch_bounds__(pfn::CNT) void k_learned_delta(T* __restrict__ d0, 
                                                            const float* __restrict__ y, const double* __restrict__ s,
                                                            Grid g) {
   const double sc = *s;
-  for (long e = blockIdx.x * (long)pfn::CNT + threadIdx.x; e < g.n; e += (long)gridDim.x * pfn::CNT) {
-    const int i = (int)(e % g.px), j = (int)((e / g.px) % g.ny), k = (int)(e / ((long)g.px * g.ny));
+  for (int e = blockIdx.x * pfn::CNT + threadIdx.x; e < g.n; e += gridDim.x * pfn::CNT) {
+    const int row = e / g.px, i = e - row * g.px, k = row / g.ny, j = row - k * g.ny;
     T a = T(0), b = T(0), c = T(0);
     if (i < g.nx) {
-      const float4 o = reinterpret_cast<const float4*>(y)[((long)k * g.ny + j) * g.nx + i];
+      const float4 o = reinterpret_cast<const float4*>(y)[row * g.nx + i];
       if (i > 0) a = (T)(sc * o.x);
       if (j > 0) b = (T)(sc * o.y);
       if (k > 0) c = (T)(sc * o.z);

@@ -262,6 +262,64 @@ def test_adam_matches_oracle():
         net.close()
 
 
+def test_context_pack_matches_oracle():
+    """The FP32 packing inside a mixed-precision context's learned start
+    (phi_f, phi_w, the eigenstrain change since the previous solve and the
+    previous increment, scaled) against the oracle's packing of the same
+    state: bit for bit after the bf16 rounding in > 99.9 % of the entries of
+    every channel but the eigenstrain change, which the kernel forms without
+    the cancellation of two cube roots (the oracle's plain difference of cube
+    roots in FP64 loses every digit where the phase barely moves near 1): that
+    channel is held to one bf16 ulp of the exact difference, evaluated
+    at 40 digits from the same FP32 phases."""
+    torch = _torch()
+    from paper_2111_11538_amd import inputs as I, pf
+    n = 16
+    wl = I.workload("core_shell_3d", n=n)
+    say(f"context packing, core_shell_3d {n}^3 mixed")
+    c = pf.Context(3, wl.shape, wl.h, wl.dt, wl.params, warm="learned", precision="mixed", plasticity=True,
+                   cg_rtol=1e-6)
+    c.set_fields(wl.fields)
+    net = pf.Net(max_voxels=n ** 3, seed=3)
+    try:
+        net.attach(c)
+        f0 = c.fields(["phi_f", "ux", "uy", "uz"])
+        c.step()                       # no previous increment yet: records it
+        f1 = c.fields(["phi_f", "phi_w", "ux", "uy", "uz"])
+        c.step()                       # packs the state after the first step
+        xb = torch.zeros(n ** 3 * 8, dtype=torch.bfloat16, device="cuda")
+        net.copy(pf.PF_NN_BUF_INPUT, xb)
+        torch.cuda.synchronize()
+        got = from_dev(xb).reshape((n, n, n, 8))
+    finally:
+        c.close()
+        net.close()
+    low = [(f1[k] - f0[k])[:n, :n, :n] for k in ("ux", "uy", "uz")]
+    Om = wl.params.Omega_f
+    x, _ = N.pack_inputs(f1["phi_f"], f1["phi_w"], N.eigenstrain(f0["phi_f"], Om), low, Om, wl.h)
+    want = np.zeros((n, n, n, 8))
+    want[..., :6] = x
+    want = N.bf16_round(want)
+    assert np.max(np.abs(want[..., 2])) > 0 and np.max(np.abs(want[..., 3:6])) > 0
+    plain = [0, 1, 3, 4, 5, 6, 7]
+    exact = np.mean(got[..., plain] == want[..., plain])
+    assert exact > 0.999, exact
+    np.testing.assert_allclose(got[..., plain], want[..., plain], rtol=2.0 ** -7, atol=0)
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    s_o = N.increment_scale(low)
+
+    def eps_t(p):
+        p = mpmath.mpf(float(p))
+        return mpmath.cbrt(1 - mpmath.mpf(Om) * p ** 3 * (p * (6 * p - 15) + 10)) - 1
+
+    gain = mpmath.mpf(N.EPS_GAIN) * mpmath.mpf(wl.h) / mpmath.mpf(s_o)
+    w2 = np.array([float((eps_t(a) - eps_t(b)) * gain) for a, b in zip(f1["phi_f"].ravel(), f0["phi_f"].ravel())])
+    g2 = got[..., 2].ravel()
+    assert np.max(np.abs(w2)) > 0
+    np.testing.assert_allclose(g2, w2, rtol=2.0 ** -7, atol=0)
+
+
 def test_pack_matches_oracle(net):
     torch = _torch()
     say("pack inputs and targets, ragged crop past the grid")
