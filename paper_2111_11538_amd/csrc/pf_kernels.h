@@ -986,6 +986,10 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
     sSyz[sk1][c] = syz_n;
     sGxz[sk1][c] = gxz_n;
     sGyz[sk1][c] = gyz_n;
+    // the moduli of the cells left of and below the own cell, read before the
+    // barrier: after it, other waves stash plane k+2 into slot sk
+    const T m_l = sK[sk][c - 1] + T(4.0 / 3.0) * sG[sk][c - 1];
+    const T m_b = sK[sk][c - W] + T(4.0 / 3.0) * sG[sk][c - W];
     ring_items(sk, kn1, sk, sk1, sk1, true);
     __syncthreads();
     if (own) {
@@ -993,8 +997,8 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
       const T q0 = f_xz * (sSxx[c - 1] - sxx + sxy - sSxy[c + W] + sxz_c - sxz_n);
       const T q1 = f_yz * (sSyy[c - W] - syy + sxy - sSxy[c + 1] + syz_c - syz_n);
       const T q2 = k > 0 ? szz_prev - szz + sxz_c - sSxz[sk][c + 1] + syz_c - sSyz[sk][c + W] : T(0);
-      const T d0 = f_i * (sK[sk][c - 1] + T(4.0 / 3.0) * sG[sk][c - 1] + Mc + gxy + sGxy[c + W] + gxz_c + gxz_n);
-      const T d1 = f_j * (sK[sk][c - W] + T(4.0 / 3.0) * sG[sk][c - W] + Mc + gxy + sGxy[c + 1] + gyz_c + gyz_n);
+      const T d0 = f_i * (m_l + Mc + gxy + sGxy[c + W] + gxz_c + gxz_n);
+      const T d1 = f_j * (m_b + Mc + gxy + sGxy[c + 1] + gyz_c + gyz_n);
       const T d2 = k > 0 ? m_prev + Mc + gxz_c + sGxz[sk][c + 1] + gyz_c + sGyz[sk][c + W] : T(0);
       const T q[3] = {q0, q1, q2}, d[3] = {d0, d1, d2};
 #pragma unroll

@@ -83,3 +83,53 @@ def test_iteration_limit_iterate_matches_oracle(oracle, iters, chunk):
         err = np.max(np.abs(a - b)) / np.max(np.abs(b))
         assert np.max(np.abs(b)) > 0 and err <= 1e-10, (k, err)
     g.close()
+
+
+def test_preconditioner_after_few_iterations_matches_oracle(oracle):
+    """The iterate after three Jacobi-preconditioned iterations depends on
+    every entry of D^-1: on a grid of many tiles and slabs, repeated solves
+    from zero must all match the oracle's (the set-up pass once read the
+    moduli of its neighbours after other waves had started to overwrite
+    them with the next plane's)."""
+    from paper_2111_11538_amd import pf
+    wl = I.workload("core_shell_3d", n=48)
+    o = oracle.OracleSim(3, wl.shape, wl.h, wl.dt, wl.params, wl.fields, plasticity=True, cg_rtol=1e-14,
+                         cg_max_iter=3)
+    with pytest.raises(RuntimeError):
+        o.mech_solve()
+    of = o.fields()
+    g = _ctx(3, wl, precision="fp64", plasticity=True, cg_rtol=1e-14, cg_max_iter=3)
+    for rep in range(4):
+        say(f"case 48^3 fp64, 3 iterations, repeat {rep}")
+        with pytest.raises(pf.PFError):
+            g.mech_solve("zero")
+        for k in ("ux", "uy", "uz"):
+            a, b = g.get(k), of[k]
+            err = np.max(np.abs(a - b)) / np.max(np.abs(b))
+            assert err <= 1e-10, (rep, k, err)
+    g.close()
+
+
+def test_learned_steps_are_bitwise_repeatable():
+    """Identical runs with the learned start (network weights that
+    reproduce linear extrapolation) give bitwise-equal states."""
+    from paper_2111_11538_amd import pf, learned as LR
+    n = 64
+    wl = I.workload("core_shell_3d", n=n)
+    net = pf.Net(max_voxels=n ** 3, seed=5)
+    LR.init_extrapolation(net)
+    outs = []
+    try:
+        for rep in range(3):
+            say(f"case learned 64^3 mixed, run {rep}")
+            c = _ctx(3, wl, precision="mixed", plasticity=True, cg_rtol=1e-6, warm="learned")
+            net.attach(c)
+            st = c.step(10)
+            outs.append((c.fields(["phi_f", "phi_w", "xO", "ux", "uy", "uz", "epsp"]), st["cg_iters_total"]))
+            c.close()
+    finally:
+        net.close()
+    for f, it in outs[1:]:
+        assert it == outs[0][1]
+        for k in f:
+            np.testing.assert_array_equal(f[k], outs[0][0][k], err_msg=k)
