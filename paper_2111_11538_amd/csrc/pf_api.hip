@@ -28,8 +28,10 @@ constexpr int kCgBY = 8;             // tile height of its CG instance
 constexpr int kSlabMax = 32;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t kStagger = 17 * kAlign;
 
 constexpr int kAfterBlocks = 2048;   // blocks of the learned start's after-solve pass
+constexpr int kFoldBlocks = 128;     // blocks folding the field update's partials before the ledger
 
 struct Layout {
   Grid g;
@@ -48,7 +50,7 @@ struct Layout {
   // byte offsets into the workspace
   size_t o_fld[2][5], o_u[3], o_epsp, o_epsP, o_mu, o_K, o_G;
   size_t o_r[3], o_z[3], o_pa[3], o_pb[3], o_q[3], o_di[3];
-  size_t o_scal, o_part_u, o_part_a, o_part_b, o_part_c, o_stage;
+  size_t o_scal, o_part_u, o_part_a, o_part_b, o_part_c, o_part_f, o_stage;
   size_t o_uo[3], o_du[3], o_phiprev;   // learned start only
   size_t o_dsq;                          // learned start: partials of the increment's sum of squares
   size_t o_b[3];                        // 3D: right-hand side b of the equilibrium solve
@@ -116,7 +118,10 @@ Layout make_layout(const pf_config* c) {
   L.stage_elems = std::max(fx, std::max(fy, fz));
   size_t off = 0;
   size_t arr = align_up((size_t)g.n * L.es);
-  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+  // consecutive arrays start 17 x 256 bytes apart beyond their size (with
+  // power-of-two sizes, the arrays a kernel streams together would otherwise
+  // start at the same offset of the memory channel interleave)
+  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes) + kStagger; return o; };
   for (int s = 0; s < 2; ++s)
     for (int f = 0; f < 5; ++f) L.o_fld[s][f] = take(arr);
   for (int d = 0; d < 3; ++d) L.o_u[d] = d < c->dim ? take(arr) : 0;
@@ -139,6 +144,7 @@ Layout make_layout(const pf_config* c) {
   L.o_part_a = take(2 * (size_t)nbmax * sizeof(double));
   L.o_part_b = take(2 * (size_t)nbmax * sizeof(double));
   L.o_part_c = take(NQ_STEP * (size_t)nbmax * sizeof(double));
+  L.o_part_f = take(NQ_STEP * (size_t)kFoldBlocks * sizeof(double));
   L.o_stage = take(L.stage_elems * sizeof(double));
   if (c->warm == PF_WARM_LEARNED) {
     for (int d = 0; d < 3; ++d) { L.o_uo[d] = take(arr); L.o_du[d] = take(arr); }
@@ -602,8 +608,17 @@ struct Impl {
     timed_launch(c, PF_K_MU, -1, k_mu<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
     timed_launch(c, PF_K_STEP, -1, k_step<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
     double vol = std::pow(c->cfg.h, DIM), area = std::pow(c->cfg.h, DIM - 1);
-    timed_launch(c, PF_K_OTHER, -1, k_ledger, dim3(1), dim3(NT), 0, c->stream, (const double*)a.part, L.nb_cell, c->scal(), vol,
-                         area * c->cfg.dt, 1);
+    const double* lp = a.part;
+    int ln = L.nb_cell;
+    if (ln > 8 * kFoldBlocks) {         // many partials: fold them on kFoldBlocks blocks first
+      double* fold = c->arr<double>(L.o_part_f);
+      timed_launch(c, PF_K_OTHER, -1, k_fold_step, dim3(kFoldBlocks), dim3(NT), 0, c->stream, (const double*)a.part, ln,
+                   fold, kFoldBlocks);
+      lp = fold;
+      ln = kFoldBlocks;
+    }
+    timed_launch(c, PF_K_OTHER, -1, k_ledger, dim3(1), dim3(NT), 0, c->stream, lp, ln, c->scal(), vol,
+                 area * c->cfg.dt, 1);
     LAUNCHCHK(c);
     c->cur ^= 1;
     c->steps += 1;

@@ -530,6 +530,13 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   if constexpr (kPlain)        // p = z: the previous direction is never read
 #pragma unroll
     for (int d = 0; d < 3; ++d) ru_[d] = buf_rsrc(a.u[d], 0);
+  __amdgpu_buffer_rsrc_t rjb_[3], rjd_[3];
+  if constexpr (kResid)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      rjb_[d] = buf_rsrc(a.jr[d], nbytes);
+      rjd_[d] = buf_rsrc(a.dinv[d], nbytes);
+    }
   auto fetch = [&](Raw& R, int kk, bool want) {
     const bool zin = want && kk >= 0 && kk < g.nz;
     R.oin = own && zin;
@@ -675,6 +682,17 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   // into C, which then holds the plane after N) and is refilled with plane k+4.
   auto plane = [&](int k, Raw& R, const int sk, Own& C, const Own& N) {
     const int sk1 = sk ^ 1;
+    // residual pass: b and D^-1 of the own cell, issued before the stencil so
+    // that their latency hides behind it
+    T jb[3], jd[3];
+    if constexpr (kResid) {
+      const int eo = own ? (own_e + k * pl) * (int)sizeof(T) : kOutOfRange;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        jb[d] = buf_ld<T>(rjb_[d], eo);
+        jd[d] = buf_ld<T>(rjd_[d], eo);
+      }
+    }
     // (A) own stresses of plane k and own z edges at level k+1
     const T exx = (sP[sk][0][c + 1] - C.p[0]) * ih;
     const T eyy = (sP[sk][1][c + W] - C.p[1]) * ih;
@@ -710,8 +728,8 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
         const T qv[3] = {q0, q1, q2};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          const T r = zero_u ? T(0) : a.jr[d][e] - qv[d];
-          const T z = a.dinv[d][e] * r;
+          const T r = zero_u ? T(0) : jb[d] - qv[d];
+          const T z = jd[d] * r;
           a.o1[d][e] = r;
           a.o2[d][e] = z;
           if (zero_u) a.u[d][e] = T(0);
@@ -1695,6 +1713,43 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(NT) void k_totals(CellArgs<T> a) {
   const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   totals_tile<T, DIM>(a, blockIdx.x, blockIdx.y, blockIdx.z, bid, gridDim.x * gridDim.y * gridDim.z);
+}
+
+// Fold the eight partial arrays of k_step ([NQ_STEP][n]) into [NQ_STEP][m]:
+// block b reduces entries [b len, (b+1) len) of each, in a fixed order (sums,
+// and maxima for the two maximum slots), so that the one-block ledger pass
+// reads m instead of n partials per quantity.
+__global__ __launch_bounds__(NT) void k_fold_step(const double* part, int n, double* out, int m) {
+  const int len = (n + m - 1) / m, lo = blockIdx.x * len, hi = min(n, lo + len);
+  double acc[NQ_STEP];
+#pragma unroll
+  for (int qn = 0; qn < NQ_STEP; ++qn) acc[qn] = 0.0;
+  for (int t = lo + threadIdx.x; t < hi; t += NT)
+#pragma unroll
+    for (int qn = 0; qn < NQ_STEP; ++qn) {
+      const double v = part[qn * n + t];
+      acc[qn] = (qn == 5 || qn == 6) ? fmax(acc[qn], v) : acc[qn] + v;
+    }
+  __shared__ double red8[NQ_STEP][NT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int qn = 0; qn < NQ_STEP; ++qn) {
+      const double v = __shfl_xor(acc[qn], o, 64);
+      acc[qn] = (qn == 5 || qn == 6) ? fmax(acc[qn], v) : acc[qn] + v;
+    }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int qn = 0; qn < NQ_STEP; ++qn) red8[qn][threadIdx.x >> 6] = acc[qn];
+  __syncthreads();
+  if (threadIdx.x < NQ_STEP) {
+    const int qn = threadIdx.x;
+    const bool mx = qn == 5 || qn == 6;
+    double s = red8[qn][0];
+#pragma unroll
+    for (int q = 1; q < NT / 64; ++q) s = mx ? fmax(s, red8[qn][q]) : s + red8[qn][q];
+    out[qn * m + blockIdx.x] = s;
+  }
 }
 
 // mode 0: ledger reset from k_totals partials; mode 1: end of step from k_step partials
