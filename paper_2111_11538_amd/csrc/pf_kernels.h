@@ -1482,6 +1482,107 @@ __device__ __forceinline__ T shear_yz(const Grid& g, const T* uy, const T* uz, i
   return T(0.5) * ((uy[e] - uy[e - pl]) + (uz[e] - uz[e - g.px])) * ih;
 }
 
+// The explicit update of one cell given its transport terms (Laplacians of
+// the phases, flux divergences, outward boundary fluxes) and its total
+// strain: phase quantities and driving forces (Eq. 33), return map (Eq. 25,
+// 34), reaction (Eq. 27, 28), explicit Euler update, and the cell's
+// contributions to the step's partial sums.
+template <typename T, int DIM>
+__device__ __forceinline__ void cell_update(const CellArgs<T>& a, int e, T pf, T pw, T xO, T xH, T xW, T lf, T lw,
+                                            T divO, T divH, T divW, T bO, T bH, const T (&eb)[6],
+                                            double (&acc)[NQ_STEP]) {
+  const Grid& g = a.g;
+  const KP<T>& p = a.p;
+  lf *= p.ih2;
+  lw *= p.ih2;
+
+  // phase quantities and the chemical / barrier driving forces (Eq. 33)
+  Phase<T> q;
+  phase_eval(p, pf, pw, q);
+  const T pg = T(1) - pf - pw;
+  T gf = p.w[0] * interp_dm(pf, p.mform) - p.w[1] * interp_dm(pg, p.mform);
+  T gw = p.w[2] * interp_dm(pw, p.mform) - p.w[1] * interp_dm(pg, p.mform);
+  if (p.chem) {
+    T f0, f1, f2, g0, g1, g2, w0, w1, w2;
+    fe_ferrite(xO, f0, f1, f2);
+    fe_gas(xO, g0, g1, g2);
+    fe_wuestite(xO, w0, w1, w2);
+    gf += p.scale * (q.dhf * f0 - q.dhg * g0);
+    gw += p.scale * (q.dhw * w0 - q.dhg * g0);
+  }
+  T vm = T(0), epsPn = T(0);
+  if (p.mech) {
+    constexpr int NC = (DIM == 2) ? 4 : 6;
+    T ep[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int c = 0; c < NC; ++c) ep[c] = a.epsp[c * g.ns + e];
+    const T epsP0 = a.epsP[e];
+    epsPn = epsP0;
+    // elastic strain and its deviator
+    T ee[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ee[c] = eb[c] - ep[c];
+    ee[0] -= q.eT; ee[1] -= q.eT; ee[2] -= q.eT;
+    T tr = ee[0] + ee[1] + ee[2];
+    T dv[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dv[c] = ee[c];
+    dv[0] -= tr * T(1.0 / 3.0); dv[1] -= tr * T(1.0 / 3.0); dv[2] -= tr * T(1.0 / 3.0);
+    T nd2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2] + T(2) * (dv[3] * dv[3] + dv[4] * dv[4] + dv[5] * dv[5]);
+    T nd = tsqrt(nd2);
+    if (p.plastic) {
+      // J2 radial return, backward Euler (Eq. 25, Eq. 34)
+      const T r23 = T(0.816496580927726032732428024902);   // sqrt(2/3)
+      T ftr = T(2) * q.G * nd - r23 * (p.sigY + p.Hh * epsP0);
+      if (ftr > T(0)) {
+        T dl = ftr / (T(2) * q.G + r23 * p.Hh);
+        T sc = dl / nd;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ep[c] += sc * dv[c];
+        epsPn = epsP0 + dl;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a.epsp[c * g.ns + e] = ep[c];
+        a.epsP[e] = epsPn;
+        // the return keeps tr and scales the deviator
+        T f = T(1) - T(2) * q.G * dl / (T(2) * q.G * nd);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) dv[c] *= f;
+        nd2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2] + T(2) * (dv[3] * dv[3] + dv[4] * dv[4] + dv[5] * dv[5]);
+        nd = tsqrt(nd2);
+      }
+    }
+    // elastic driving force: derivative of d_T sum h(phi_a) (K_a tr^2/2 + G_a |dev|^2)
+    T pe_f = T(0.5) * p.K[0] * tr * tr + p.G[0] * nd2;
+    T pe_g = T(0.5) * p.K[1] * tr * tr + p.G[1] * nd2;
+    T pe_w = T(0.5) * p.K[2] * tr * tr + p.G[2] * nd2;
+    T phi_el = q.hf * pe_f + q.hg * pe_g + q.hw * pe_w;
+    gf += q.dTp * phi_el + q.dT * (q.dhf * pe_f - q.dhg * pe_g) - q.eTp * T(3) * q.K * tr;
+    gw += q.dT * (q.dhw * pe_w - q.dhg * pe_g);
+    vm = T(1.2247448713915890491) * T(2) * q.G * nd;   // sqrt(3/2) |dev sigma|
+  }
+  // reaction (Eq. 27, 28): zero once the cell is full of water
+  const T r = xW < T(1) ? interp_m(pg, p.mform) * p.kfor * xO * xH : T(0);
+  const T nf = pf + p.dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf);
+  const T nw = pw + p.dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw);
+  const T nO = xO + p.dt * (-divO - r);
+  const T nH = xH + p.dt * (-divH - T(2) * r);
+  const T nW = xW + p.dt * (-divW + r);
+  a.npf[e] = nf;
+  a.npw[e] = nw;
+  a.nxO[e] = nO;
+  a.nxH[e] = nH;
+  a.nxW[e] = nW;
+  acc[0] = (double)nO + (double)nW;
+  acc[1] = (double)nH + 2.0 * (double)nW;
+  acc[2] = (double)nO;
+  acc[3] = (double)bO;
+  acc[4] = (double)bH + 2.0 * (double)bO;
+  acc[5] = (double)vm;
+  acc[6] = (double)epsPn;
+  bool fin = isfinite(nf) && isfinite(nw) && isfinite(nO) && isfinite(nH) && isfinite(nW) && isfinite(vm);
+  acc[7] = fin ? 0.0 : 1.0;
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void step_tile(const CellArgs<T>& a, int bx, int by, int bz, int pidx, int pstride) {
   const Grid& g = a.g;
@@ -1545,29 +1646,11 @@ __device__ __forceinline__ void step_tile(const CellArgs<T>& a, int bx, int by, 
       divH += (JHp - JHm) * ih;
       divW += (JWp - JWm) * ih;
     }
-    lf *= p.ih2;
-    lw *= p.ih2;
-
-    // phase quantities and the chemical / barrier driving forces (Eq. 33)
-    Phase<T> q;
-    phase_eval(p, pf, pw, q);
-    const T pg = T(1) - pf - pw;
-    T gf = p.w[0] * interp_dm(pf, p.mform) - p.w[1] * interp_dm(pg, p.mform);
-    T gw = p.w[2] * interp_dm(pw, p.mform) - p.w[1] * interp_dm(pg, p.mform);
-    if (p.chem) {
-      T f0, f1, f2, g0, g1, g2, w0, w1, w2;
-      fe_ferrite(xO, f0, f1, f2);
-      fe_gas(xO, g0, g1, g2);
-      fe_wuestite(xO, w0, w1, w2);
-      gf += p.scale * (q.dhf * f0 - q.dhg * g0);
-      gw += p.scale * (q.dhw * w0 - q.dhg * g0);
-    }
-    T vm = T(0), epsPn = T(0);
+    T eb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if (p.mech) {
       // cell strain: normal from faces, shear as the mean of four edges
       const T* ux = a.u[0];
       const T* uy = a.u[1];
-      T eb[6];
       eb[0] = ((i + 1 < g.nx ? ux[e + 1] : T(0)) - ux[e]) * ih;
       eb[1] = ((j + 1 < g.ny ? uy[e + g.px] : T(0)) - uy[e]) * ih;
       eb[2] = T(0);
@@ -1583,75 +1666,8 @@ __device__ __forceinline__ void step_tile(const CellArgs<T>& a, int bx, int by, 
         eb[5] = T(0.25) * (shear_yz(g, uy, uz, i, j, k, ih) + shear_yz(g, uy, uz, i, j + 1, k, ih) +
                            shear_yz(g, uy, uz, i, j, k + 1, ih) + shear_yz(g, uy, uz, i, j + 1, k + 1, ih));
       }
-      constexpr int NC = (DIM == 2) ? 4 : 6;
-      T ep[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-      for (int c = 0; c < NC; ++c) ep[c] = a.epsp[c * g.ns + e];
-      const T epsP0 = a.epsP[e];
-      epsPn = epsP0;
-      // elastic strain and its deviator
-      T ee[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) ee[c] = eb[c] - ep[c];
-      ee[0] -= q.eT; ee[1] -= q.eT; ee[2] -= q.eT;
-      T tr = ee[0] + ee[1] + ee[2];
-      T dv[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) dv[c] = ee[c];
-      dv[0] -= tr * T(1.0 / 3.0); dv[1] -= tr * T(1.0 / 3.0); dv[2] -= tr * T(1.0 / 3.0);
-      T nd2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2] + T(2) * (dv[3] * dv[3] + dv[4] * dv[4] + dv[5] * dv[5]);
-      T nd = tsqrt(nd2);
-      if (p.plastic) {
-        // J2 radial return, backward Euler (Eq. 25, Eq. 34)
-        const T r23 = T(0.816496580927726032732428024902);   // sqrt(2/3)
-        T ftr = T(2) * q.G * nd - r23 * (p.sigY + p.Hh * epsP0);
-        if (ftr > T(0)) {
-          T dl = ftr / (T(2) * q.G + r23 * p.Hh);
-          T sc = dl / nd;
-#pragma unroll
-          for (int c = 0; c < 6; ++c) ep[c] += sc * dv[c];
-          epsPn = epsP0 + dl;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) a.epsp[c * g.ns + e] = ep[c];
-          a.epsP[e] = epsPn;
-          // the return keeps tr and scales the deviator
-          T f = T(1) - T(2) * q.G * dl / (T(2) * q.G * nd);
-#pragma unroll
-          for (int c = 0; c < 6; ++c) dv[c] *= f;
-          nd2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2] + T(2) * (dv[3] * dv[3] + dv[4] * dv[4] + dv[5] * dv[5]);
-          nd = tsqrt(nd2);
-        }
-      }
-      // elastic driving force: derivative of d_T sum h(phi_a) (K_a tr^2/2 + G_a |dev|^2)
-      T pe_f = T(0.5) * p.K[0] * tr * tr + p.G[0] * nd2;
-      T pe_g = T(0.5) * p.K[1] * tr * tr + p.G[1] * nd2;
-      T pe_w = T(0.5) * p.K[2] * tr * tr + p.G[2] * nd2;
-      T phi_el = q.hf * pe_f + q.hg * pe_g + q.hw * pe_w;
-      gf += q.dTp * phi_el + q.dT * (q.dhf * pe_f - q.dhg * pe_g) - q.eTp * T(3) * q.K * tr;
-      gw += q.dT * (q.dhw * pe_w - q.dhg * pe_g);
-      vm = T(1.2247448713915890491) * T(2) * q.G * nd;   // sqrt(3/2) |dev sigma|
     }
-    // reaction (Eq. 27, 28): zero once the cell is full of water
-    const T r = xW < T(1) ? interp_m(pg, p.mform) * p.kfor * xO * xH : T(0);
-    const T nf = pf + p.dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf);
-    const T nw = pw + p.dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw);
-    const T nO = xO + p.dt * (-divO - r);
-    const T nH = xH + p.dt * (-divH - T(2) * r);
-    const T nW = xW + p.dt * (-divW + r);
-    a.npf[e] = nf;
-    a.npw[e] = nw;
-    a.nxO[e] = nO;
-    a.nxH[e] = nH;
-    a.nxW[e] = nW;
-    acc[0] = (double)nO + (double)nW;
-    acc[1] = (double)nH + 2.0 * (double)nW;
-    acc[2] = (double)nO;
-    acc[3] = (double)bO;
-    acc[4] = (double)bH + 2.0 * (double)bO;
-    acc[5] = (double)vm;
-    acc[6] = (double)epsPn;
-    bool fin = isfinite(nf) && isfinite(nw) && isfinite(nO) && isfinite(nH) && isfinite(nW) && isfinite(vm);
-    acc[7] = fin ? 0.0 : 1.0;
+    cell_update<T, DIM>(a, e, pf, pw, xO, xH, xW, lf, lw, divO, divH, divW, bO, bH, eb, acc);
   }
   // the eight partials together: the wave trees of all quantities interleaved,
   // then one exchange across the waves (the same operations in the same
