@@ -269,7 +269,7 @@ def train_learned(wl, args):
     held = recs[-4:]                 # solves 22 and 23 are held out (2 more give their history)
     v0 = float(np.mean(LR.evaluate(tn, held, wl.params.Omega_f, wl.h)))
     losses = LR.train(tn, recs[:-2], args.train_iters, wl.params.Omega_f, wl.h, crop=(64, 64, 64), batch=4,
-                      lr=1e-4, t_min=5, log=log, log_every=100, val_recs=held, eval_every=25)
+                      lr=args.train_lr, t_min=5, log=log, log_every=100, val_recs=held, eval_every=25)
     v1 = float(np.mean(LR.evaluate(tn, held, wl.params.Omega_f, wl.h)))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -299,7 +299,9 @@ def main():
     ap.add_argument("--warm", default="learned", choices=("learned", "prev"),
                     help="CG start of the timed run (learned: network trained first on the recipe's own trajectory)")
     ap.add_argument("--train-steps", type=int, default=24, help="recorded solves for training")
-    ap.add_argument("--train-iters", type=int, default=300)
+    ap.add_argument("--train-iters", type=int, default=3000,
+                    help="Adam iterations of the network's training (early stopping keeps the best held-out checkpoint)")
+    ap.add_argument("--train-lr", type=float, default=1e-4, help="Adam learning rate of the network's training")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy this many MiB with a plain device copy (counter calibration under a profiler)")
     args = ap.parse_args()
