@@ -408,7 +408,8 @@ struct Impl {
       for (int d = 0; d < DIM; ++d) HIPCHK(c, hipMemsetAsync(c->ws + L.o_u[d], 0, (size_t)L.g.n * sizeof(T), st));
     c->warm_used = warm;
     CellArgs<T> ca = cell_args(c);
-    timed_launch(c, PF_K_OTHER, -1, k_moduli<T, DIM>, L.gcell, dim3(NT), 0, st, ca);
+    if constexpr (DIM != 3)           // 3D: the set-up pass evaluates the moduli itself
+      timed_launch(c, PF_K_OTHER, -1, k_moduli<T, DIM>, L.gcell, dim3(NT), 0, st, ca);
 
     ElastArgs<T> e = elast_args(c);
     double* part_u = c->arr<double>(L.o_part_u);
@@ -420,6 +421,9 @@ struct Impl {
       // from formed in its epilogue (q itself is not stored)
       ElastArgs<T> sa = e;
       sa.part = part_b;
+      sa.phi_w = c->arr<T>(L.o_fld[c->cur][1]);
+      sa.Kw = c->arr<T>(L.o_K);
+      sa.Gw = c->arr<T>(L.o_G);
       for (int d = 0; d < 3; ++d) {
         sa.o1[d] = c->arr<T>(L.o_b[d]);
         sa.dinv[d] = c->arr<T>(L.o_di[d]);

@@ -45,6 +45,9 @@ struct ElastArgs {
                            // into o2 (q not stored) and partials r.z, r.r; it opens the solve's scalars
                            // from the ||b||^2 partials part_in[0..n_in), and with b = 0 sets the
                            // vector (u[]) and r, z to zero
+  const T* phi_w;          // k_setup3: water phase (with phi_f, the moduli it computes)
+  T* Kw;                   // k_setup3: the moduli K, G it writes for the apply kernels
+  T* Gw;
   T* xs[3];                // APPLY_CG (3D): the solution (completed by the launch that stops the solve)
   int it;                  // APPLY_CG (3D): index of this launch in the solve
 };
@@ -778,8 +781,9 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
 // threads over a column tile marching along z, own column values in
 // registers, x / y neighbours from a one-cell-ring LDS plane tile, ring
 // stresses from a short work list, loads two planes ahead.  Per plane it
-// reads K, G, phi_f (for the eigenstrain) and the six plastic strain
-// components, and writes b and D^-1.
+// reads phi_f, phi_w and the six plastic strain components, evaluates the
+// moduli (Eq. 32) and the eigenstrain from the phases, and writes b, D^-1 and
+// the moduli of the cells it owns (the apply kernels read them).
 // ---------------------------------------------------------------------------
 template <typename T, int BY>
 __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
@@ -816,16 +820,18 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
     rg_e = rg_in ? jj * g.px + ii : 0;
   }
   const int own_e = own ? j * g.px + i : 0;
+  const int k0 = bz * a.kz;
+  const int k1 = min(k0 + a.kz, g.nz);
 
   // raw loads of one plane (own column and ring position), two sets in flight
   struct Raw {
-    T oK, oG, of, op[6], hK, hG, hf, hp[6];
+    T ow, of, op[6], hw, hf, hp[6];
     bool oin, hin;
   };
   struct Own { T K, G, n[3], xy, xz, yz; };    // own cell: moduli, eps*_nn (eigen + plastic), plastic shears
   Raw ra, rb;
   const int nbytes = g.n * (int)sizeof(T);
-  const __amdgpu_buffer_rsrc_t rK = buf_rsrc(a.K, nbytes), rG = buf_rsrc(a.G, nbytes), rF = buf_rsrc(a.phi_f, nbytes);
+  const __amdgpu_buffer_rsrc_t rW = buf_rsrc(a.phi_w, nbytes), rF = buf_rsrc(a.phi_f, nbytes);
   const __amdgpu_buffer_rsrc_t rE = buf_rsrc(a.epsp, 6 * g.ns * (int)sizeof(T));
   const int cstride = g.ns * (int)sizeof(T);
   auto fetch = [&](Raw& R, int kk, bool want) {
@@ -834,18 +840,27 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
     R.hin = rg_in && zin;
     const int eo = R.oin ? (own_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
     const int eh = R.hin ? (rg_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
-    R.oK = buf_ld<T>(rK, eo); R.oG = buf_ld<T>(rG, eo); R.of = buf_ld<T>(rF, eo);
-    R.hK = buf_ld<T>(rK, eh); R.hG = buf_ld<T>(rG, eh); R.hf = buf_ld<T>(rF, eh);
+    R.ow = buf_ld<T>(rW, eo); R.of = buf_ld<T>(rF, eo);
+    R.hw = buf_ld<T>(rW, eh); R.hf = buf_ld<T>(rF, eh);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       R.op[q] = buf_ld<T>(rE, R.oin ? eo + q * cstride : kOutOfRange);
       R.hp[q] = buf_ld<T>(rE, R.hin ? eh + q * cstride : kOutOfRange);
     }
   };
-  auto stash = [&](const Raw& R, int slot, Own& O) {
+  // combine plane kk into LDS slot `slot`: the moduli from the phases (written
+  // out for the planes the block owns), the eigenstrain, the plastic strain
+  auto stash = [&](const Raw& R, int kk, int slot, Own& O) {
     const T et = R.oin ? eigen_strain(p, R.of) : T(0);
-    O.K = R.oin ? R.oK : T(0);
-    O.G = R.oin ? R.oG : T(0);
+    T mK, mG;
+    moduli(p, R.of, R.ow, mK, mG);
+    O.K = R.oin ? mK : T(0);
+    O.G = R.oin ? mG : T(0);
+    if (R.oin && kk >= k0 && kk < k1) {
+      const int e = own_e + kk * pl;
+      a.Kw[e] = mK;
+      a.Gw[e] = mG;
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q) O.n[q] = R.oin ? et + R.op[q] : T(0);
     O.xy = R.oin ? R.op[3] : T(0);
@@ -860,8 +875,10 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
     sEyz[slot][c] = O.yz;
     if (rg_t < S) {
       const T hu = R.hin ? eigen_strain(p, R.hf) : T(0);
-      sK[slot][rg_t] = R.hin ? R.hK : T(0);
-      sG[slot][rg_t] = R.hin ? R.hG : T(0);
+      T hK, hG;
+      moduli(p, R.hf, R.hw, hK, hG);
+      sK[slot][rg_t] = R.hin ? hK : T(0);
+      sG[slot][rg_t] = R.hin ? hG : T(0);
 #pragma unroll
       for (int q = 0; q < 3; ++q) sN[slot][q][rg_t] = R.hin ? hu + R.hp[q] : T(0);
       sExy[slot][rg_t] = R.hin ? R.hp[3] : T(0);
@@ -936,8 +953,6 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
     }
   };
 
-  const int k0 = bz * a.kz;
-  const int k1 = min(k0 + a.kz, g.nz);
   Own oA, oB;                         // own values of planes k and k+1, roles alternating
   T szz_prev = T(0), m_prev = T(0);
   T sxz_c = T(0), syz_c = T(0), gxz_c = T(0), gyz_c = T(0);   // own z edges at level k
@@ -951,8 +966,8 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
     Own ob;
     fetch(ra, k0 - 1, true);
     fetch(rb, k0, true);
-    stash(ra, 1, ob);
-    stash(rb, 0, oA);
+    stash(ra, k0 - 1, 1, ob);
+    stash(rb, k0, 0, oA);
     fetch(ra, k0 + 1, true);
     fetch(rb, k0 + 2, k0 + 1 < k1);
     __syncthreads();
@@ -970,7 +985,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
     sGyz[0][c] = gyz_c;
     ring_items(1, k0, 1, 0, 0, false);
     __syncthreads();
-    stash(ra, 1, oB);
+    stash(ra, k0 + 1, 1, oB);
     fetch(ra, k0 + 3, k0 + 2 < k1);
     __syncthreads();
   }
@@ -1033,7 +1048,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
     syz_c = syz_n;
     gxz_c = gxz_n;
     gyz_c = gyz_n;
-    if (k + 1 < k1) stash(R, sk, C);   // plane k+2 into the slot of plane k
+    if (k + 1 < k1) stash(R, k + 2, sk, C);   // plane k+2 into the slot of plane k
     fetch(R, k + 4, k + 3 < k1);
     __syncthreads();
   };
