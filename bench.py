@@ -42,7 +42,11 @@ def algorithmic_bytes_per_cell(kind, dim, es):
         return (5 + 1 + dim + nc + 1 + 5 + nc + 1) * es
     if kind == "mu":           # read phi_f, phi_w, x_O; write mu
         return 4 * es
-    if kind == "solve_setup":  # average of ||b|| (K, G, phi_f, eps_p), residual (+u, r, z, D^-1), true residual
+    if kind == "solve_setup":
+        if dim == 3:           # average of the set-up pass (phi_f, phi_w, eps_p -> K, G, b, D^-1), the residual
+            # pass (u, K, G, b, D^-1 -> r, z) and the true residual (u, K, G, b -> q)
+            return ((2 + nc + 2 + 2 * dim) + (dim + 2 + 2 * dim + 2 * dim) + (dim + 2 + dim + dim)) * es / 3.0
+        # 2D: average of ||b|| (K, G, phi_f, eps_p), residual (+u, r, z, D^-1), true residual
         return ((2 + 1 + nc) + (dim + 2 + 1 + nc + 3 * dim) + (dim + 2 + 1 + nc)) * es / 3.0
     return 0.0
 
