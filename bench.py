@@ -268,11 +268,11 @@ def train_learned(wl, args):
     c.close()
     t1 = time.perf_counter()
     ncell = int(np.prod(wl.shape))
-    tn = pf.Net(max_voxels=max(4 * 64 ** 3, ncell), training=True, seed=1)
+    tn = pf.Net(max_voxels=max(args.train_batch * 64 ** 3, ncell), training=True, seed=1)
     LR.init_extrapolation(tn)
     held = recs[-4:]                 # solves 22 and 23 are held out (2 more give their history)
     v0 = float(np.mean(LR.evaluate(tn, held, wl.params.Omega_f, wl.h)))
-    losses = LR.train(tn, recs[:-2], args.train_iters, wl.params.Omega_f, wl.h, crop=(64, 64, 64), batch=4,
+    losses = LR.train(tn, recs[:-2], args.train_iters, wl.params.Omega_f, wl.h, crop=(64, 64, 64), batch=args.train_batch,
                       lr=args.train_lr, t_min=5, log=log, log_every=100, val_recs=held, eval_every=25)
     v1 = float(np.mean(LR.evaluate(tn, held, wl.params.Omega_f, wl.h)))
     torch.cuda.synchronize()
@@ -282,7 +282,7 @@ def train_learned(wl, args):
     net = pf.Net(max_voxels=ncell)
     net.set_params(params)
     info = {"recorded_solves": args.train_steps, "record_s": round(t1 - t0, 2), "iters": args.train_iters,
-            "batch": "4 crops of 64^3", "train_s": round(t2 - t1, 2),
+            "batch": f"{args.train_batch} crops of 64^3", "train_s": round(t2 - t1, 2),
             "loss_first_last_50": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
             "held_out_full_grid_loss_extrapolation_init": v0, "held_out_full_grid_loss_trained": v1,
             "early_stopping": "best held-out full-grid loss over checkpoints every 25 iterations",
@@ -306,6 +306,7 @@ def main():
     ap.add_argument("--train-iters", type=int, default=3000,
                     help="Adam iterations of the network's training (early stopping keeps the best held-out checkpoint)")
     ap.add_argument("--train-lr", type=float, default=1e-4, help="Adam learning rate of the network's training")
+    ap.add_argument("--train-batch", type=int, default=4, help="64^3 crops per training minibatch")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy this many MiB with a plain device copy (counter calibration under a profiler)")
     args = ap.parse_args()
