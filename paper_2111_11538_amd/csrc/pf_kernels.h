@@ -540,24 +540,37 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
       rjb_[d] = buf_rsrc(a.jr[d], nbytes);
       rjd_[d] = buf_rsrc(a.dinv[d], nbytes);
     }
-  auto fetch = [&](Raw& R, int kk, bool want) {
+  // only the first waves hold ring positions (threads < NRING); the others
+  // run a copy of the plane loop without ring loads and stores (RW = false),
+  // so that in both copies every load's wait count is exact
+  const bool ring_wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) < (TL::NRING + 63) / 64;
+  auto fetch = [&](Raw& R, int kk, bool want, auto RW) {
     const bool zin = want && kk >= 0 && kk < g.nz;
     R.oin = own && zin;
     R.hin = rg_in && zin;
     const int eo = R.oin ? (own_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
-    const int eh = R.hin ? (rg_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       R.oz[d] = buf_ld<T>(rz_[d], eo);
       R.op[d] = buf_ld<T>(ru_[d], eo);
-      R.hz[d] = buf_ld<T>(rz_[d], eh);
-      R.hp[d] = buf_ld<T>(ru_[d], eh);
     }
     R.og = buf_ld<T>(rG, eo); R.ok = buf_ld<T>(rK, eo);
-    R.hg = buf_ld<T>(rG, eh); R.hk = buf_ld<T>(rK, eh);
+    if constexpr (decltype(RW)::value) {
+      const int eh = R.hin ? (rg_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        R.hz[d] = buf_ld<T>(rz_[d], eh);
+        R.hp[d] = buf_ld<T>(ru_[d], eh);
+      }
+      R.hg = buf_ld<T>(rG, eh); R.hk = buf_ld<T>(rK, eh);
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) R.hz[d] = R.hp[d] = T(0);
+      R.hg = R.hk = T(0);
+    }
   };
   // combine, store the plane into LDS slot `slot`, and return the own values
-  auto stash = [&](const Raw& R, int slot, T (&vp)[3], T& vg, T& vk) {
+  auto stash = [&](const Raw& R, int slot, T (&vp)[3], T& vg, T& vk, auto RW) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) vp[d] = R.oin ? (first ? R.oz[d] : R.oz[d] + tb * R.op[d]) : T(0);
     vg = R.oin ? R.og : T(0);
@@ -566,7 +579,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     for (int d = 0; d < 3; ++d) sP[slot][d][c] = vp[d];
     sG[slot][c] = vg;
     sK[slot][c] = vk;
-    if (rg_t < S) {
+    if (decltype(RW)::value && rg_t < S) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) sP[slot][d][rg_t] = R.hin ? (first ? R.hz[d] : R.hz[d] + tb * R.hp[d]) : T(0);
       sG[slot][rg_t] = R.hin ? R.hg : T(0);
@@ -648,17 +661,18 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   const T f_xz = (i > 0 && i < g.nx) ? T(1) : T(0);
   const T f_yz = (j > 0 && j < g.ny) ? T(1) : T(0);
 
+  double acc = 0.0, acc1 = 0.0;
   // prologue: planes k0-1 (slot 1), k0 (slot 0); sigma_zz of the own cell
   // below; z edges at level k0.  Plane m travels in register set ra when
   // m - k0 is odd.
-  {
+  auto prologue = [&](auto RW) {
     Own ob;
-    fetch(ra, k0 - 1, true);
-    fetch(rb, k0, true);
-    stash(ra, 1, ob.p, ob.g, ob.k);
-    stash(rb, 0, oA.p, oA.g, oA.k);
-    fetch(ra, k0 + 1, true);
-    fetch(rb, k0 + 2, k0 + 1 < k1);
+    fetch(ra, k0 - 1, true, RW);
+    fetch(rb, k0, true, RW);
+    stash(ra, 1, ob.p, ob.g, ob.k, RW);
+    stash(rb, 0, oA.p, oA.g, oA.k, RW);
+    fetch(ra, k0 + 1, true, RW);
+    fetch(rb, k0 + 2, k0 + 1 < k1, RW);
     __syncthreads();
     if (k0 > 0) {
       const T exx = (sP[1][0][c + 1] - ob.p[0]) * ih;
@@ -674,16 +688,15 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     sSyz[0][c] = syz_c;
     ring_items(1, 0, k0, 1, 0, 0, false);
     __syncthreads();
-    stash(ra, 1, oB.p, oB.g, oB.k);
-    fetch(ra, k0 + 3, k0 + 2 < k1);
+    stash(ra, 1, oB.p, oB.g, oB.k, RW);
+    fetch(ra, k0 + 3, k0 + 2 < k1, RW);
     __syncthreads();
-  }
+  };
 
-  double acc = 0.0, acc1 = 0.0;
   // one plane k in slot sk (plane k+1 in slot sk1); C holds its own values,
   // N those of plane k+1.  R carries plane k+2 in (stashed into slot sk and
   // into C, which then holds the plane after N) and is refilled with plane k+4.
-  auto plane = [&](int k, Raw& R, const int sk, Own& C, const Own& N) {
+  auto plane = [&](int k, Raw& R, const int sk, Own& C, const Own& N, auto RW) {
     const int sk1 = sk ^ 1;
     // residual pass: b and D^-1 of the own cell, issued before the stencil so
     // that their latency hides behind it
@@ -754,18 +767,22 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     szz_prev = szz;
     sxz_c = sxz_n;
     syz_c = syz_n;
-    if (k + 1 < k1) stash(R, sk, C.p, C.g, C.k);   // plane k+2 into the slot of plane k
-    fetch(R, k + 4, k + 3 < k1);
+    if (k + 1 < k1) stash(R, sk, C.p, C.g, C.k, RW);   // plane k+2 into the slot of plane k
+    fetch(R, k + 4, k + 3 < k1, RW);
     __syncthreads();
   };
   // pairs of planes, so that every path into a plane has the same loads in
   // flight (the wait counts then let the newer set stay outstanding)
-  int k = k0;
-  for (; k + 1 < k1; k += 2) {
-    plane(k, rb, 0, oA, oB);
-    plane(k + 1, ra, 1, oB, oA);
-  }
-  if (k < k1) plane(k, rb, 0, oA, oB);
+  auto march = [&](auto RW) {
+    prologue(RW);
+    int k = k0;
+    for (; k + 1 < k1; k += 2) {
+      plane(k, rb, 0, oA, oB, RW);
+      plane(k + 1, ra, 1, oB, oA, RW);
+    }
+    if (k < k1) plane(k, rb, 0, oA, oB, RW);
+  };
+  if (ring_wave) march(std::true_type{}); else march(std::false_type{});
   const double s0 = block_sum_n<NTB>(acc, red);
   if (threadIdx.x == 0) a.part[bid] = s0;
   if constexpr (kResid) {
