@@ -216,7 +216,7 @@ typedef struct pf_batch pf_batch;
 typedef struct { int nx, ny, nz; } pf_extent;   /* one instance's cells (2D: nz = 1) */
 
 /* Work decomposition of a batch step (chosen by an autotuner):
- *  apply_rows     rows per block of the 256-column elasticity apply tiles (4..256)
+ *  apply_rows     rows per CG apply strip (62 columns, one wave each) (4..256)
  *  update_chunk   16-byte vectors per CG-update work item (256..65536)
  *  blocks_per_cu  persistent blocks per compute unit (1..occupancy limit)
  *  spin_limit     polls before a grid barrier gives up and reports an error */

@@ -2,7 +2,7 @@
 
 It times whole batch steps for candidate tile shapes and keeps the fastest, by
 coordinate descent over the three parameters of ``pf_batch_tiles``: rows per
-apply tile, vectors per CG-update work item and persistent blocks per compute
+apply strip, vectors per CG-update work item and persistent blocks per compute
 unit.  Because the state advances while it is timed and the number of CG
 iterations changes from step to step, a candidate is scored by time per pass
 of the persistent CG loop (the step time divided by one plus the largest
@@ -16,7 +16,7 @@ import math
 import os
 import time
 
-APPLY_ROWS = (8, 16, 32, 64)
+APPLY_ROWS = (16, 32, 64, 128)
 UPDATE_CHUNK = (1024, 4096, 8192, 16384)
 BLOCKS_PER_CU = (1, 2, 3, 4)
 

@@ -2,8 +2,9 @@
 //
 // Every instance keeps its own grid, CG recurrence and ledger; their arrays
 // are packed one after another in shared buffers.  Work is described by tile
-// tables (elasticity 64x4 tiles, apply row tiles, cell tiles, CG update
-// chunks) that the persistent blocks walk with a fixed stride; phases are
+// tables (elasticity 64x4 tiles, CG apply strips of 62 columns taken one per
+// wave, cell tiles, CG update chunks) that the persistent blocks walk with a
+// fixed stride; phases are
 // separated by a grid barrier whose wait is bounded (a timeout raises an error
 // flag and every block leaves), so the launch always drains.
 #pragma once
@@ -18,10 +19,10 @@ struct InstDesc {
   Grid g;          // the instance's own grid; g.ns = packed component stride of eps_p
   int off;         // element offset of the instance in every packed array (multiple of 64)
   int el0, eln;    // range in the elasticity tile table
-  int ap0, apn;    // range in the apply tile table
+  int ap0, apn;    // range in the apply strip table (A2S columns x kz_ap rows, one per wave)
   int ce0, cen;    // range in the cell tile table
   int up0, upn;    // range in the update chunk table
-  int apf0, apfn;  // range of the fine apply tiles (fewer rows per tile)
+  int apf0, apfn;  // range of the fine apply strips (fewer rows per strip)
   int upf0, upfn;  // range of the fine update chunks
 };
 struct TileRef {
@@ -68,8 +69,8 @@ struct BatchArgs {
   unsigned* bar;           // {arrivals, generation, error}
   double tol2;
   int max_iter;
-  int kz_ap;                  // rows per coarse apply tile
-  int kz_apf;                 // rows per fine apply tile
+  int kz_ap;                  // rows per coarse apply strip
+  int kz_apf;                 // rows per fine apply strip
   double area_dt;
   double vol;
   long long spin_limit;
@@ -275,9 +276,7 @@ __device__ __forceinline__ CellArgs<T> cell_view(const BatchArgs<T>& B, const In
 
 template <typename T>
 constexpr size_t batch_smem() {
-  size_t a = sizeof(ElastSmem<T, 2, M_RESID>);
-  size_t b = sizeof(Apply2Smem<T>);
-  return a > b ? a : b;
+  return sizeof(ElastSmem<T, 2, M_RESID>);
 }
 
 #define PF_BARRIER()                                                                   \
@@ -403,15 +402,16 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
         ca = d.apn; cu = d.upn; fa = d.apfn; fu = d.upfn;
       }
       active_scan2(shAp, shUp, ca, cu, B.count);
-      ap_fine = shAp[B.count - 1] < (int)nbk;
+      ap_fine = shAp[B.count - 1] < (int)nbk * (NT / 64);   // apply strips go one per wave
       up_fine = shUp[B.count - 1] < (int)nbk;
       if (ap_fine || up_fine) active_scan2(shAp, shUp, ap_fine ? fa : ca, up_fine ? fu : cu, B.count);
     }
     const int n_ap_act = shAp[B.count - 1], n_up_act = shUp[B.count - 1];
-    // apply: q = A p with p = z + beta p
+    // apply: q = A p with p = z + beta p, one strip per wave
     T* const pold[2] = {(L & 1) ? B.pb[0] : B.pa[0], (L & 1) ? B.pb[1] : B.pa[1]};
     T* const pnew[2] = {(L & 1) ? B.pa[0] : B.pb[0], (L & 1) ? B.pa[1] : B.pb[1]};
-    for (int wa = blockIdx.x; wa < n_ap_act; wa += nbk) {
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int wa = blockIdx.x * (NT / 64) + wv; wa < n_ap_act; wa += nbk * (NT / 64)) {
       const int ib = active_owner(shAp, B.count, wa);
       const InstDesc& d = B.inst[ib];
       const int w = (ap_fine ? d.apf0 : d.ap0) + wa - (ib > 0 ? shAp[ib - 1] : 0);
@@ -424,9 +424,10 @@ __global__ __launch_bounds__(NT) void k_batch_step(BatchArgs<T> B) {
         a.o1[c] = pnew[c] + d.off;
         a.o2[c] = B.q[c] + d.off;
       }
-      a.part = B.part_a;
-      a.kz = ap_fine ? B.kz_apf : B.kz_ap;
-      apply2_tile(a, tr.bx, tr.by, shB[tr.inst], L == 0, w, smem);
+      const int kz = ap_fine ? B.kz_apf : B.kz_ap;
+      const int j0 = tr.by * kz, j1 = min(j0 + kz, d.g.ny);
+      const double s = wave_sum(apply2_strip(a, tr.bx, j0, j1, shB[tr.inst], L == 0));
+      if ((tid & 63) == 0) B.part_a[w] = s;
     }
     PF_BARRIER();
     // alpha = r.z / p.q of every instance still iterating

@@ -63,7 +63,7 @@ BatchLayout make_batch_layout(const pf_config* c, const pf_extent* ext, int coun
     off += (d.g.n + 63) / 64 * 64;
     L.n_el += ((d.g.nx + TX - 1) / TX) * ((d.g.ny + TY - 1) / TY);
     // coarse and fine tables together, each at most the finest tiling
-    L.max_ap += 2 * ((d.g.nx + A2W - 1) / A2W) * ((d.g.ny + kMinApplyRows - 1) / kMinApplyRows);
+    L.max_ap += 2 * ((d.g.nx + A2S - 1) / A2S) * ((d.g.ny + kMinApplyRows - 1) / kMinApplyRows);
     L.max_up += 2 * ((d.g.n / vn + kMinChunk - 1) / kMinChunk);
     L.stage_elems = std::max(L.stage_elems, (size_t)(d.g.nx + 1) * (d.g.ny + 1));
     L.inst.push_back(d);
@@ -212,7 +212,7 @@ static pf_status build_tables(pf_batch* bt) {
     d.cen = d.eln;
     d.ap0 = (int)ap.size();
     for (int by = 0; by < (d.g.ny + rows - 1) / rows; ++by)
-      for (int bx = 0; bx < (d.g.nx + A2W - 1) / A2W; ++bx) ap.push_back({b, bx, by, 0});
+      for (int bx = 0; bx < (d.g.nx + A2S - 1) / A2S; ++bx) ap.push_back({b, bx, by, 0});
     d.apn = (int)ap.size() - d.ap0;
     d.up0 = (int)up.size();
     const int nv = d.g.n / vn;
@@ -225,7 +225,7 @@ static pf_status build_tables(pf_batch* bt) {
     InstDesc& d = L.inst[b];
     d.apf0 = (int)ap.size();
     for (int by = 0; by < (d.g.ny + rows_f - 1) / rows_f; ++by)
-      for (int bx = 0; bx < (d.g.nx + A2W - 1) / A2W; ++bx) ap.push_back({b, bx, by, 0});
+      for (int bx = 0; bx < (d.g.nx + A2S - 1) / A2S; ++bx) ap.push_back({b, bx, by, 0});
     d.apfn = (int)ap.size() - d.apf0;
     d.upf0 = (int)up.size();
     const int nv = d.g.n / vn;

@@ -1247,6 +1247,130 @@ __device__ __forceinline__ void apply2_tile(const ElastArgs<T>& a, int bx, int b
   if (threadIdx.x == 0) a.part[pidx] = s0;
 }
 
+// ---------------------------------------------------------------------------
+// 2D q = A p with p = z + beta p, by one wave over a strip of A2S columns,
+// marching along y over rows [j0, j1).  Lane l holds column sx*A2S - 1 + l:
+// lanes 1..A2S are the strip's own columns, lanes 0 and A2S+1 its left and
+// right neighbour columns, so every x neighbour a stencil term needs is one
+// lane away (shuffles: no LDS tile and no block barrier).  The two edge lanes
+// only supply what their inner neighbours read from them (the cell stress
+// left of the strip, the xy edge stress right of it) and store nothing.  The
+// arithmetic is the same, term by term, as the block tile's above.  Returns
+// the lane's share of p.q.
+// ---------------------------------------------------------------------------
+constexpr int A2S = 62;                  // columns per strip
+constexpr int A2PF = 8;                  // rows of loads in flight per strip
+
+template <typename T>
+__device__ __forceinline__ double apply2_strip(const ElastArgs<T>& a, int sx, int j0, int j1, double beta,
+                                               bool first) {
+  const Grid& g = a.g;
+  const int lane = threadIdx.x & 63;
+  const int i = sx * A2S - 1 + lane;
+  const bool col = i >= 0 && i < g.nx;
+  const bool store = col && lane >= 1 && lane <= A2S;
+  const T ih = a.p.ih;
+  const T tb = (T)beta;
+
+  // raw loads of A2PF rows in flight: row j0 + 2 + m travels in set m % A2PF
+  // (every set index below is a compile-time constant, so the sets stay in
+  // registers and each wait leaves the newer sets outstanding)
+  struct Raw { T z[2], p[2], g, k; bool in; };
+  Raw rw[A2PF];
+  // rows past j1 (the last one the strip reads) load element 0 instead
+  auto fetch = [&](Raw& R, int jj) {
+    R.in = col && jj >= 0 && jj <= j1 && jj < g.ny;
+    const int e = R.in ? jj * g.px + i : 0;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      R.z[d] = a.z[d][e];
+      R.p[d] = a.u[d][e];
+    }
+    R.g = a.G[e];
+    R.k = a.K[e];
+  };
+  auto take = [&](const Raw& R, T (&vp)[2], T& vg, T& vk) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) vp[d] = R.in ? (first ? R.z[d] : R.z[d] + tb * R.p[d]) : T(0);
+    vg = R.in ? R.g : T(0);
+    vk = R.in ? R.k : T(0);
+  };
+  auto left = [](T v) { return __shfl_up(v, 1, 64); };      // value of column i - 1
+  auto right = [](T v) { return __shfl_down(v, 1, 64); };   // value of column i + 1
+
+  T pc[2], gc, kc, pn[2], gn, kn;
+  T syy_prev = T(0), sxy_c = T(0);
+  // prologue: rows j0-1 .. j0+1; sigma_yy of the own cell below; xy edge at level j0
+  {
+    T pb[2], gb, kb;
+    fetch(rw[0], j0 - 1);
+    fetch(rw[1], j0);
+    fetch(rw[2], j0 + 1);
+    take(rw[0], pb, gb, kb);
+    take(rw[1], pc, gc, kc);
+    take(rw[2], pn, gn, kn);
+#pragma unroll
+    for (int m = 0; m < A2PF; ++m) fetch(rw[m], j0 + 2 + m);
+    const T pb0r = right(pb[0]);
+    const T gbl = left(gb), gcl = left(gc), pc1l = left(pc[1]);
+    if (j0 > 0) {
+      const T exx = (pb0r - pb[0]) * ih;
+      const T eyy = (pc[1] - pb[1]) * ih;
+      const T tr = exx + eyy;
+      const T G2 = T(2) * gb;
+      syy_prev = kb * tr - G2 * tr * T(1.0 / 3.0) + G2 * eyy;
+    }
+    if (i > 0 && i < g.nx && j0 > 0 && j0 < g.ny) {
+      const T ge = T(0.25) * (gbl + gb + gcl + gc);
+      sxy_c = ge * ((pc[0] - pb[0]) + (pc[1] - pc1l)) * ih;
+    }
+  }
+
+  double acc = 0.0;
+  // row j (m = j - j0): own cell stresses of row j (plane strain), own xy edge
+  // at level j+1, the forces of row j; then row j+2 moves in from set m % A2PF
+  // and row j+2+A2PF is fetched into it
+  auto row = [&](int j, Raw& R) {
+    const T pc0r = right(pc[0]);
+    const T gcl = left(gc), gnl = left(gn), pn1l = left(pn[1]);
+    const T exx = (pc0r - pc[0]) * ih;
+    const T eyy = (pn[1] - pc[1]) * ih;
+    const T tr = exx + eyy;
+    const T G2 = T(2) * gc;
+    const T lam = kc * tr - G2 * tr * T(1.0 / 3.0);
+    const T sxx = lam + G2 * exx, syy = lam + G2 * eyy;
+    T sxy_n = T(0);
+    if (i > 0 && i < g.nx && j + 1 < g.ny) {
+      const T ge = T(0.25) * (gcl + gc + gnl + gn);
+      sxy_n = ge * ((pn[0] - pc[0]) + (pn[1] - pn1l)) * ih;
+    }
+    const T sxx_l = left(sxx);           // cell stress of column i - 1
+    const T sxy_r = right(sxy_c);        // xy edge of node (i + 1, j)
+    if (store) {
+      const int e = j * g.px + i;
+      T q0 = T(0), q1 = T(0);
+      if (i > 0) q0 = sxx_l - sxx + sxy_c - sxy_n;
+      if (j > 0) q1 = syy_prev - syy + sxy_c - sxy_r;
+      a.o1[0][e] = pc[0]; a.o1[1][e] = pc[1];
+      a.o2[0][e] = q0; a.o2[1][e] = q1;
+      acc += (double)pc[0] * (double)q0 + (double)pc[1] * (double)q1;
+    }
+    syy_prev = syy;
+    sxy_c = sxy_n;
+    pc[0] = pn[0]; pc[1] = pn[1];
+    gc = gn;
+    kc = kn;
+    take(R, pn, gn, kn);                 // row j+2
+    fetch(R, j + 2 + A2PF);
+  };
+  for (int j = j0; j < j1; j += A2PF) {
+#pragma unroll
+    for (int m = 0; m < A2PF; ++m)
+      if (j + m < j1) row(j + m, rw[m]);
+  }
+  return acc;
+}
+
 // CG scalars at the start of an apply: r.z and r.r of the latest residual
 // (partials part_in[0..n) and part_in[n..2n)); identical in every block.
 template <int NTB>
