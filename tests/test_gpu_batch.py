@@ -30,7 +30,8 @@ def _instances(shapes, seed0=7):
 
 def test_fp64_batch_matches_oracle(oracle):
     from paper_2111_11538_amd import pf
-    shapes = [(24, 24), (31, 40), (64, 57)]
+    # the widest instance spans three CG apply strips (62 columns each)
+    shapes = [(24, 24), (31, 40), (64, 57), (21, 130)]
     p = I.Params()
     h = I.H_DEFAULT
     dt = I.stable_dt(p, h, 2)
@@ -84,14 +85,18 @@ def test_mixed_batch_matches_single_contexts():
 
 def test_tile_choice_does_not_change_results():
     from paper_2111_11538_amd import pf
-    shapes = [(40, 72), (90, 33)]
+    # widths one past a strip (63) and exactly two strips (124); strips of 4
+    # rows (fewer than the rows of loads in flight) and of 128 (taller than
+    # every instance)
+    shapes = [(40, 72), (90, 33), (20, 124), (25, 63)]
     p = I.Params()
     h = I.H_DEFAULT
     dt = I.stable_dt(p, h, 2)
     fields = _instances(shapes, 40)
     outs = []
     for tiles in ({"apply_rows": 4, "update_chunk": 256, "blocks_per_cu": 1},
-                  {"apply_rows": 64, "update_chunk": 4096, "blocks_per_cu": 2}):
+                  {"apply_rows": 64, "update_chunk": 4096, "blocks_per_cu": 2},
+                  {"apply_rows": 128, "update_chunk": 8192, "blocks_per_cu": 2}):
         b = pf.Batch(shapes, h, dt, p, precision="fp64", plasticity=True, cg_rtol=1e-12)
         b.set_tiles(**tiles)
         for k, f in enumerate(fields):
@@ -99,10 +104,11 @@ def test_tile_choice_does_not_change_results():
         b.step(3)
         outs.append([b.fields(k) for k in range(len(shapes))])
         b.close()
-    for k in range(len(shapes)):
-        for n in NAMES:
-            assert rel(outs[0][k][n], outs[1][k][n]) < 1e-12
-        assert rel(outs[0][k]["ux"], outs[1][k]["ux"]) < 1e-7
+    for o in outs[1:]:
+        for k in range(len(shapes)):
+            for n in NAMES:
+                assert rel(outs[0][k][n], o[k][n]) < 1e-12
+            assert rel(outs[0][k]["ux"], o[k]["ux"]) < 1e-7
 
 
 def test_batch_is_deterministic():
