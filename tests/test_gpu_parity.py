@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-Tolerances (derived in the design doc):
+Tolerances (derived from the arithmetic of each path):
   * FP64 path: both sides stop CG at ||b - A u|| <= rtol ||b||; with rtol =
     1e-12 the displacements may differ by the conditioning times rtol, so u is
     compared at 1e-7 relative; the per-step increments of the five fields
