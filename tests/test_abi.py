@@ -76,3 +76,35 @@ def test_workspace_size_and_validation(lib):
     rc = lib.pf_init(C.byref(cfg), C.byref(prm), C.c_void_p(256), 16, None, C.byref(ctx))
     assert rc == pf.PF_ERR_OOM
     assert lib.pf_step(None, 1, None) == pf.PF_ERR_INVALID_ARG
+
+
+def test_batch_workspace_validation(lib):
+    """Batch sizing on the host: 1..256 instances, 2D only, mechanics on, the
+    previous-step start, non-empty extents; the workspace grows with the
+    instances and is 0 for every invalid request."""
+    def ext_of(shapes):
+        e = (pf.pf_extent * max(1, len(shapes)))()
+        for k, (ny, nx) in enumerate(shapes):
+            e[k].nx, e[k].ny, e[k].nz = nx, ny, 1
+        return e
+
+    cfg = pf.make_config(2, (8, 8), I.H_DEFAULT, 1e-8, precision="mixed", plasticity=True)
+    one = lib.pf_batch_workspace_bytes(C.byref(cfg), ext_of([(8, 8)]), 1)
+    full = lib.pf_batch_workspace_bytes(C.byref(cfg), ext_of([(8, 8)] * 256), 256)
+    assert 0 < one < full
+    wide = lib.pf_batch_workspace_bytes(C.byref(cfg), ext_of([(8, 8), (40, 130)]), 2)
+    assert lib.pf_batch_workspace_bytes(C.byref(cfg), ext_of([(8, 8)] * 2), 2) < wide
+    assert lib.pf_batch_workspace_bytes(C.byref(cfg), ext_of([(8, 8)] * 257), 257) == 0
+    assert lib.pf_batch_workspace_bytes(C.byref(cfg), ext_of([]), 0) == 0
+    assert lib.pf_batch_workspace_bytes(C.byref(cfg), ext_of([(0, 8)]), 1) == 0
+    assert lib.pf_batch_workspace_bytes(C.byref(cfg), ext_of([(8, 0)]), 1) == 0
+    for kw in ({"mechanics": False}, {"warm": "learned"}):
+        bad = pf.make_config(2, (8, 8), I.H_DEFAULT, 1e-8, precision="mixed", **kw)
+        assert lib.pf_batch_workspace_bytes(C.byref(bad), ext_of([(8, 8)]), 1) == 0, kw
+    bad3 = pf.make_config(3, (8, 8, 8), I.H_DEFAULT, 1e-8, precision="mixed")
+    assert lib.pf_batch_workspace_bytes(C.byref(bad3), ext_of([(8, 8)]), 1) == 0
+    b = C.c_void_p()
+    prm = pf.make_params(I.Params())
+    rc = lib.pf_batch_init(C.byref(cfg), C.byref(prm), ext_of([(8, 8)] * 257), 257, None, 0, None, C.byref(b))
+    assert rc == pf.PF_ERR_INVALID_ARG and not b.value
+    assert b"count" in lib.pf_batch_last_error(None)
