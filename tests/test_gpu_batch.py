@@ -142,3 +142,30 @@ def test_barrier_timeout_is_reported_not_hung():
         b.step()
     assert e.value.status == pf.PF_ERR_HIP
     b.close()
+
+
+def test_largest_batch_matches_oracle_on_sampled_instances(oracle):
+    """256 instances (the most one batch takes) of uneven small shapes in one
+    launch; the first, a middle and the last instance against the oracle."""
+    from paper_2111_11538_amd import pf
+    rng = np.random.default_rng(I.SEED_BASE + 256)
+    shapes = [(int(rng.integers(8, 41)), int(rng.integers(8, 70))) for _ in range(256)]
+    p = I.Params()
+    h = I.H_DEFAULT
+    dt = I.stable_dt(p, h, 2)
+    fields = _instances(shapes, 300)
+    say("batch of 256, fp64")
+    b = pf.Batch(shapes, h, dt, p, precision="fp64", plasticity=True, cg_rtol=1e-12)
+    for k, f in enumerate(fields):
+        b.set_fields(k, f)
+    bst = b.step(2)
+    for k in (0, 1, 128, 255):
+        s = oracle.OracleSim(2, shapes[k], h, dt, p, fields[k], plasticity=True, cg_rtol=1e-12)
+        s.step()
+        ost = s.step()
+        out = b.fields(k)
+        for n in NAMES:
+            assert rel(out[n], s.f[n]) < 1e-12, (k, n)
+        assert rel(out["ux"], s.ux) < 1e-7 and rel(out["uy"], s.uy) < 1e-7, k
+        assert abs(bst[k]["cg_iters"] - ost["cg_iters"]) <= max(2, 0.1 * ost["cg_iters"]), k
+    b.close()
