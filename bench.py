@@ -250,6 +250,40 @@ def measure_copy_peak(mib=1024, reps=20):
     return 2 * n * 4 / sec / 1e9
 
 
+def time_train_iters(tn, recs, wl, args, n=20):
+    """Device time of one training iteration (forward, loss, backward-data,
+    backward-weight, Adam) on one packed batch of crops, averaged over `n`
+    iterations between HIP events on the network's stream; priced in the
+    algorithmic MFMA flops of the three convolution passes."""
+    import torch
+    from paper_2111_11538_amd import learned as LR
+    LR.train(tn, recs, 1, wl.params.Omega_f, wl.h, crop=(64, 64, 64), batch=args.train_batch, lr=args.train_lr,
+             t_min=5)                       # packs one batch of crops into the network's input slots
+    cz, cy, cx = (min(64, d) for d in recs[0]["phi_f"].shape)
+    vox = args.train_batch * cz * cy * cx
+    fwd = NN_FLOP_PER_VOXEL * vox
+    bwd_data = 2 * 27 * (32 * 32 + 32 * 32 + 32 * 3) * vox     # input gradients of layers 2-4
+    flop = 2 * fwd + bwd_data                                  # forward, backward-weight, backward-data
+    total = 0.0
+    for _ in range(n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(tn.stream)
+        tn.forward(None, None, args.train_batch, cz, cy, cx)
+        tn.loss()
+        tn.backward()
+        tn.adam(args.train_lr)
+        e1.record(tn.stream)
+        e1.synchronize()
+        total += e0.elapsed_time(e1) / 1e3
+    avg = total / n
+    tf = flop / avg / 1e12
+    return {"bound": "mfma", "kernel": f"one training iteration on {args.train_batch} crops of {cz}x{cy}x{cx} "
+            "(4 forward, 3 backward-data and 4 backward-weight convolutions, loss, Adam)",
+            "achieved": round(tf, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / BF16_PEAK_TFLOPS, 4),
+            "traffic": None, "flop_per_iter": flop, "avg_iter_us": round(avg * 1e6, 1),
+            "timed_with": f"HIP events on the network's stream around {n} iterations after training"}
+
+
 def train_learned(wl, args):
     """Record the plain method's first solves of the recipe, train the network
     on random 64^3 crops of them (offline, untimed) and return the state at the
@@ -278,6 +312,7 @@ def train_learned(wl, args):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     params = tn.params()
+    train_roof = time_train_iters(tn, recs[:-2], wl, args)   # the training net's weights are not used after this
     tn.close()
     net = pf.Net(max_voxels=ncell)
     net.set_params(params)
@@ -286,7 +321,7 @@ def train_learned(wl, args):
             "loss_first_last_50": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
             "held_out_full_grid_loss_extrapolation_init": v0, "held_out_full_grid_loss_trained": v1,
             "early_stopping": "best held-out full-grid loss over checkpoints every 25 iterations",
-            "cg_iters_per_step_recorded": [r["cg_iters"] for r in recs]}
+            "cg_iters_per_step_recorded": [r["cg_iters"] for r in recs], "roofline": train_roof}
     return state, net, info, params
 
 

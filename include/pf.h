@@ -343,7 +343,9 @@ pf_status pf_nn_adam(pf_nn *nn, double lr, double b1, double b2, double eps);
  *                    out = input gradient where aux > 0, else 0 (32 bf16);
  *  BACKWARD_WEIGHT:  in = layer input, aux = output gradient ->
  *                    out = FP32 dW[27][cout][cin] followed by db[cout]
- *                    (needs training buffers). */
+ *                    (needs training buffers).
+ * in, aux and out are device pointers aligned to 16 bytes
+ * (PF_ERR_INVALID_ARG otherwise). */
 pf_status pf_nn_layer(pf_nn *nn, int op, int layer, const void *in, const void *aux, void *out, int n, int D, int H,
                       int W);
 

@@ -605,30 +605,69 @@ __global__ __launch_bounds__(CNT) void k_wgrad_reduce(const float* __restrict__ 
   }
 }
 
-// Bias gradient: db[c] = sum_v dy(v, c); block s sums its voxel range per
-// channel (FP64), the reduction over blocks is done by k_bgrad_reduce.
+// Bias gradient: db[c] = sum_v dy(v, c), dy holding cg bf16 channels per voxel
+// (cg = 8 or 32).  Block s sums its voxel range: a thread reads 8 channels of
+// a voxel at once (16 bytes), keeps their FP64 sums and has four such loads
+// in flight; the block's threads are then combined per channel in a fixed
+// order.  k_bgrad_reduce sums over the blocks.
+__device__ __forceinline__ void bgrad_add8(double (&s)[8], const uint4 w) {
+  const uint32_t x[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    s[2 * m] += (double)bf2f((uint16_t)(x[m] & 0xFFFFu));
+    s[2 * m + 1] += (double)bf2f((uint16_t)(x[m] >> 16));
+  }
+}
 __global__ __launch_bounds__(CNT) void k_bgrad_part(const uint16_t* __restrict__ dy, int cg, long nvox, double* __restrict__ part) {
-  __shared__ double sh[CNT];
+  __shared__ double sh[8][CNT];
   const long v0 = nvox * blockIdx.x / gridDim.x, v1 = nvox * (blockIdx.x + 1) / gridDim.x;
-  const int per = CNT / cg;                    // threads per channel (cg divides 256)
-  const int c = threadIdx.x % cg, sub = threadIdx.x / cg;
-  double s = 0.0;
-  if (sub < per)
-    for (long vv = v0 + sub; vv < v1; vv += per) s += (double)bf2f(dy[vv * cg + c]);
-  sh[threadIdx.x] = s;
+  const int tpv = cg / 8;                      // threads per voxel
+  const int vpb = CNT / tpv;                   // voxels per pass of the block
+  const int q = threadIdx.x % tpv, sub = threadIdx.x / tpv;
+  const uint4* rows = reinterpret_cast<const uint4*>(dy);
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  long vv = v0 + sub;
+  for (; vv + 3L * vpb < v1; vv += 4L * vpb) {
+    uint4 w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = rows[(vv + (long)k * vpb) * tpv + q];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bgrad_add8(s, w[k]);
+  }
+  for (; vv < v1; vv += vpb) bgrad_add8(s, rows[vv * tpv + q]);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) sh[i][threadIdx.x] = s[i];
   __syncthreads();
   if (threadIdx.x < cg) {
+    const int qq = threadIdx.x / 8, i = threadIdx.x % 8;   // channel 8 qq + i
     double t = 0.0;
-    for (int q = 0; q < per; ++q) t += sh[q * cg + threadIdx.x];
+    for (int u = 0; u < vpb; ++u) t += sh[i][u * tpv + qq];
     part[(long)blockIdx.x * cg + threadIdx.x] = t;
   }
 }
-__global__ void k_bgrad_reduce(const double* __restrict__ part, int nblk, int cg, int cout, float* __restrict__ grad) {
-  const int c = threadIdx.x;
-  if (c >= cout) return;
-  double s = 0.0;
-  for (int q = 0; q < nblk; ++q) s += part[(long)q * cg + c];
-  grad[c] = (float)s;
+// Sum over the blocks' partials: one block, channel c = t % cg taken by
+// CNT / cg interleaved splits of the partials (four loads in flight each),
+// the splits combined in a fixed order.
+__global__ __launch_bounds__(CNT) void k_bgrad_reduce(const double* __restrict__ part, int nblk, int cg, int cout,
+                                                      float* __restrict__ grad) {
+  __shared__ double sh[CNT];
+  const int c = threadIdx.x % cg, sp = threadIdx.x / cg, nsp = CNT / cg;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int q = sp;
+  for (; q + 3 * nsp < nblk; q += 4 * nsp) {
+    a0 += part[(long)q * cg + c];
+    a1 += part[(long)(q + nsp) * cg + c];
+    a2 += part[(long)(q + 2 * nsp) * cg + c];
+    a3 += part[(long)(q + 3 * nsp) * cg + c];
+  }
+  for (; q < nblk; q += nsp) a0 += part[(long)q * cg + c];
+  sh[threadIdx.x] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (threadIdx.x < cout) {
+    double t = 0.0;
+    for (int u = 0; u < nsp; ++u) t += sh[u * cg + threadIdx.x];
+    grad[threadIdx.x] = (float)t;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -169,7 +169,7 @@ static pf_status nn_conv_wgrad(pf_nn* nn, int l, const uint16_t* x, const uint16
                      (const float*)nn->wpart, nsplit, coutp, cinp, d.cout, d.cin, gw);
   const long long nvox = vol_voxels(v);
   hipLaunchKernelGGL(pfn::k_bgrad_part, dim3(kBgradBlocks), dim3(pfn::CNT), 0, st, dy, cg, (long)nvox, nn->dpart);
-  hipLaunchKernelGGL(pfn::k_bgrad_reduce, dim3(1), dim3(64), 0, st, (const double*)nn->dpart, kBgradBlocks, cg, d.cout, gb);
+  hipLaunchKernelGGL(pfn::k_bgrad_reduce, dim3(1), dim3(pfn::CNT), 0, st, (const double*)nn->dpart, kBgradBlocks, cg, d.cout, gb);
   NNLAUNCH(nn);
   return PF_OK;
 }
@@ -637,6 +637,9 @@ pf_status pf_nn_layer(pf_nn* nn, int op, int layer, const void* in, const void* 
   if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
   if (layer < 0 || layer >= kLayers) return nn_fail(nn, PF_ERR_INVALID_ARG, "layer must be 0..3");
   if (!in || !out) return nn_fail(nn, PF_ERR_INVALID_ARG, "in and out are required");
+  // the kernels read and write 16-byte channel groups
+  if (((uintptr_t)in | (uintptr_t)aux | (uintptr_t)out) & 15u)
+    return nn_fail(nn, PF_ERR_INVALID_ARG, "in, aux and out must be 16-byte aligned");
   const Vol v{n, D, H, W};
   pf_status s = nn_check_vol(nn, v);
   if (s != PF_OK) return s;
