@@ -599,9 +599,18 @@ __global__ __launch_bounds__(CNT) void k_wgrad_reduce(const float* __restrict__ 
   for (int e = blockIdx.x * CNT + threadIdx.x; e < n; e += gridDim.x * CNT) {
     const int t = e / (cout * cin), co = (e / cin) % cout, ci = e % cin;
     const long off = ((long)t * coutp + co) * cinp + ci;
-    double s = 0.0;
-    for (int q = 0; q < nsplit; ++q) s += (double)part[(long)q * kTaps * coutp * cinp + off];
-    grad[e] = (float)s;
+    // four interleaved partial sums (four loads in flight), combined in a fixed order
+    const long st = (long)kTaps * coutp * cinp;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = 0;
+    for (; q + 3 < nsplit; q += 4) {
+      s0 += (double)part[(long)q * st + off];
+      s1 += (double)part[(long)(q + 1) * st + off];
+      s2 += (double)part[(long)(q + 2) * st + off];
+      s3 += (double)part[(long)(q + 3) * st + off];
+    }
+    for (; q < nsplit; ++q) s0 += (double)part[(long)q * st + off];
+    grad[e] = (float)((s0 + s1) + (s2 + s3));
   }
 }
 
