@@ -178,6 +178,9 @@ def cpu_baseline(n=64, steps=4):
                       f"(warm-started, {iters / steps:.0f} CG iterations/step), {dt:.1f} s"}
 
 
+BATCH_TRANSIENT_STEPS = 24
+
+
 def run_batch(args):
     """The 64-instance batch (2D core-shell template, sides U{64..512}),
     autotuned, one persistent graph launch per step."""
@@ -195,8 +198,18 @@ def run_batch(args):
         b.set_fields(k, f)
     cells = sum(ny * nx for ny, nx in shapes)
     print(f"[bench] batch of {len(shapes)}, {cells} cells: warmup {args.warmup}", file=sys.stderr, flush=True)
-    b.step(args.warmup)
+    # the first steps of the recipe are a start-up transient (their solves
+    # take about twice the CG iterations of later ones): like the 3D learned
+    # runs, which follow 24 recorded solves, the timed steps follow 24 steps
+    b.step(args.warmup + BATCH_TRANSIENT_STEPS)
+    # the whole state after the warm-up (fields, displacements, plastic
+    # strains), restored after tuning: the timed steps then do the same work
+    # whatever number of trial steps the tuner took
+    saved = [b.fields(k) for k in range(len(shapes))]
     tuned = autotune.tune(b, prec, cache_path=None, log=lambda m: print(m, file=sys.stderr, flush=True))
+    for k, f in enumerate(saved):
+        b.set_fields(k, f)
+    del saved
     b.step(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -217,7 +230,8 @@ def run_batch(args):
         "warmup": args.warmup, "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 state + f64 reductions", "data": "synthetic",
         "config": {"workload": f"batch of {len(shapes)} 2D core-shell instances, sides U{{64..512}}, plasticity on, "
-                               f"CG rtol 1e-06, one persistent graph launch per step", "cells": cells},
+                               f"CG rtol 1e-06, one persistent graph launch per step, timed after "
+                               f"{BATCH_TRANSIENT_STEPS + args.warmup + 1} untimed steps", "cells": cells},
         "cg_iters_per_step": {"mean": sum(iters) / len(iters), "max": max(iters)},
         "roofline": {"bound": "hbm", "kernel": "k_batch_step (whole step, algorithmic bytes of apply+update per "
                      "iteration per instance + step)", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
