@@ -94,6 +94,7 @@ def lib():
         L.or_elastic_energy.restype = C.c_double
         L.or_common_tangent.argtypes = [_P, _P, _P]
         L.or_fe.argtypes = [C.c_int, C.c_double, _P]
+        L.or_simplex_project.argtypes = [_P, _P]
         _lib = L
     return _lib
 
@@ -243,6 +244,12 @@ def fe(phase: int, x: float):
     out = np.zeros(3)
     lib().or_fe(phase, x, _ptr(out))
     return out
+
+
+def simplex_project(phi_f, phi_w):
+    a, b = np.array([float(phi_f)]), np.array([float(phi_w)])
+    lib().or_simplex_project(_ptr(a), _ptr(b))
+    return a[0], b[0]
 
 
 def common_tangent():

@@ -757,6 +757,33 @@ static double face_flux(double ca, double cb, double va, double vb, double h) {
   return -0.5 * (ca + cb) * (vb - va) / h;
 }
 
+/* The order parameters lie in [0, 1] (Sec. 2.2) and phi_g = 1 - phi_f - phi_w.
+ * After the explicit update the triple (phi_f, phi_g, phi_w) is replaced by its
+ * Euclidean projection onto {phi_a >= 0, sum_a phi_a = 1}, by the sort-based
+ * algorithm of Held, Wolfe and Crowder (1974): sort descending, find the
+ * largest rho with s_rho > (s_1 + ... + s_rho - 1) / rho, shift every entry by
+ * that threshold and clip at zero.  A triple already inside is left as is. */
+void or_simplex_project(double *phi_f, double *phi_w) {
+  double u[3] = {*phi_f, 1.0 - *phi_f - *phi_w, *phi_w};
+  if (u[0] >= 0.0 && u[1] >= 0.0 && u[2] >= 0.0) return;
+  double srt[3] = {u[0], u[1], u[2]};
+  for (int a = 0; a < 3; ++a)
+    for (int b = a + 1; b < 3; ++b)
+      if (srt[b] > srt[a]) {
+        double t = srt[a];
+        srt[a] = srt[b];
+        srt[b] = t;
+      }
+  double cum = 0.0, theta = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    cum += srt[j];
+    double t = (cum - 1.0) / (double)(j + 1);
+    if (srt[j] - t > 0.0) theta = t;
+  }
+  *phi_f = fmax(u[0] - theta, 0.0);
+  *phi_w = fmax(u[2] - theta, 0.0);
+}
+
 int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, or_stats *st) {
   if (c->dim != 2 && c->dim != 3) return OR_INVALID;
   if (c->nx < 1 || c->ny < 1 || c->nz < 1 || (c->dim == 2 && c->nz != 1)) return OR_INVALID;
@@ -880,6 +907,7 @@ int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, 
         double r = s->xW[q] < 1.0 ? L.m[1] * p->kfor * s->xO[q] * s->xH[q] : 0.0;   /* Eq. 27, 28 */
         nf_[q] = s->phi_f[q] + dt * p->L[0] * ((p->eps[0] + p->eps[1]) * lf + p->eps[1] * lw - gf[q]);
         nw_[q] = s->phi_w[q] + dt * p->L[2] * ((p->eps[2] + p->eps[1]) * lw + p->eps[1] * lf - gw[q]);
+        or_simplex_project(&nf_[q], &nw_[q]);
         nO[q] = s->xO[q] + dt * (-divO - r);
         nH[q] = s->xH[q] + dt * (-divH - 2.0 * r);
         nW[q] = s->xW[q] + dt * (-divW + r);

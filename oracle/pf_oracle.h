@@ -96,6 +96,7 @@ void or_point_energy(const or_config *c, const or_params *p, double phi_f, doubl
 double or_energy(const or_config *c, const or_params *p, const or_state *s);
 double or_elastic_energy(const or_config *c, const or_params *p, const or_state *s);
 int  or_common_tangent(double *xf, double *xw, double *resid);
+void or_simplex_project(double *phi_f, double *phi_w);
 void or_fe(int phase, double x, double out[3]);
 
 #ifdef __cplusplus

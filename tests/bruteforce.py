@@ -35,6 +35,24 @@ def _dm(x, form):
     return 16 * v if form == 0 else v
 
 
+def simplex(pf, pw):
+    """Order parameters bounded to [0, 1] with phi_g = 1 - phi_f - phi_w: the
+    nearest point of {phi >= 0, sum = 1} is max(u - theta, 0), with theta the
+    root of sum_a max(u_a - theta, 0) = 1 (found here by bisection; cells
+    already inside are returned unchanged)."""
+    u = np.stack([pf, 1 - pf - pw, pw])
+    inside = np.all(u >= 0, axis=0)
+    lo = u.min(0) - 1.0                       # sum_a max(u_a - lo, 0) >= 1
+    hi = u.max(0)                             # sum_a max(u_a - hi, 0) = 0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        big = np.maximum(u - mid[None], 0).sum(0) > 1
+        lo = np.where(big, mid, lo)
+        hi = np.where(big, hi, mid)
+    v = np.maximum(u - (0.5 * (lo + hi))[None], 0)
+    return np.where(inside, pf, v[0]), np.where(inside, pw, v[2])
+
+
 # ---------------------------------------------------------------------------
 # Mechanics by explicit energy assembly
 # ---------------------------------------------------------------------------
@@ -254,9 +272,11 @@ def step(dim, shape, h, dt, p, f, u, epsp, epsP, plasticity=True, dirichlet=True
     divW = div_flux(DWw, xW, p.xW_bc if dirichlet else None)
     r = np.where(xW < 1, Mm[1] * p.kfor * xO * xH, 0.0)
     lf, lw = lap(pf), lap(pw)
+    nf, nw = simplex(pf + dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf),
+                     pw + dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw))
     out = {
-        "phi_f": pf + dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf),
-        "phi_w": pw + dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw),
+        "phi_f": nf,
+        "phi_w": nw,
         "xO": xO + dt * (-divO - r),
         "xH": xH + dt * (-divH - 2 * r),
         "xW": xW + dt * (-divW + r),

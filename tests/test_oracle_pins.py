@@ -380,3 +380,273 @@ def test_driving_force_is_energy_derivative(oracle):
         gw = (E(pf, pw + d) - E(pf, pw - d)) / (2 * d)
         assert abs(gf - g[0]) < 1e-6 * (abs(g[0]) + 1e4 * p.w[0] * 1e-4)
         assert abs(gw - g[1]) < 1e-6 * (abs(g[1]) + 1e4 * p.w[0] * 1e-4)
+
+
+# ---------------------------------------------------------------------------
+# Order parameters bounded to [0, 1] (Sec. 2.2): projection onto the simplex
+# ---------------------------------------------------------------------------
+def test_phase_bound_is_nearest_simplex_point(oracle):
+    rng = np.random.default_rng(11)
+    # a dense sample of the simplex {phi >= 0, sum = 1} for a brute-force nearest point
+    t = np.linspace(0.0, 1.0, 801)
+    A, B = np.meshgrid(t, t, indexing="ij")
+    ok = A + B <= 1.0 + 1e-15
+    cand = np.stack([A[ok], 1.0 - A[ok] - B[ok], B[ok]], axis=1)
+    for _ in range(200):
+        pf, pw = rng.uniform(-0.6, 1.6, 2)
+        qf, qw = oracle.simplex_project(pf, pw)
+        q = np.array([qf, 1.0 - qf - qw, qw])
+        assert np.all(q >= -1e-15) and abs(q.sum() - 1.0) < 1e-15
+        u = np.array([pf, 1.0 - pf - pw, pw])
+        d_best = np.min(np.sum((cand - u) ** 2, axis=1))
+        # no sampled point of the simplex is nearer (grid spacing 1/800)
+        assert np.sum((q - u) ** 2) <= d_best + 1e-12
+        assert oracle.simplex_project(qf, qw) == (qf, qw)          # idempotent
+        if np.all(u >= 0):
+            assert (qf, qw) == (pf, pw)                             # inside: unchanged
+    # the projection moves along the simplex's normal when one entry is slightly negative
+    qf, qw = oracle.simplex_project(0.6, 0.5)                     # phi_g = -0.1
+    assert abs(qf - 0.55) < 1e-15 and abs(qw - 0.45) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Largest von Mises stress: closed form of the laminate
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_max_von_mises_of_the_laminate(oracle, dim):
+    """Layers stacked along x under rollers: u_y = u_z = 0, uniform sigma_xx,
+    strain eps_xx_i = (sigma_xx + 3 K_i e_i) / M_i in layer i, and the cell von
+    Mises stress sqrt(3/2) |dev sigma| reduces to 2 G_i |eps_xx_i|."""
+    p = I.Params()
+    n = 12
+    shape = (4, n) if dim == 2 else (3, 4, n)
+    f = _uniform_fields(shape)
+    layer = np.array([0, 0, 1, 1, 1, 2, 2, 0, 0, 1, 2, 2])
+    f["phi_f"][...] = (layer == 0)
+    f["phi_w"][...] = (layer == 2)
+    h = I.H_DEFAULT
+    s = _sim(oracle, dim, shape, h, 1e-12, p, f, mechanics=True, plasticity=False, dirichlet=False, cg_rtol=1e-13)
+    st = s.step()
+    dT = np.where(layer == 0, 1 - p.Omega_f, 1.0)
+    Kl = dT * np.array([p.K[a] for a in layer])
+    Gl = dT * np.array([p.G[a] for a in layer])
+    el = np.where(layer == 0, (1 - p.Omega_f) ** (1 / 3) - 1, 0.0)
+    Ml = Kl + 4 * Gl / 3
+    sig = -np.sum(3 * Kl * el / Ml) / np.sum(1 / Ml)
+    exx = (sig + 3 * Kl * el) / Ml
+    vm = np.max(2 * Gl * np.abs(exx))
+    assert abs(st["max_vm"] - vm) < 1e-8 * vm, (st["max_vm"], vm)
+
+
+# ---------------------------------------------------------------------------
+# Reduction degree f = 1 - sum x_O / sum x_O(0) (Eq. 39), closed form
+# ---------------------------------------------------------------------------
+def test_reduction_degree_closed_form(oracle):
+    """Half of a closed box reacts (phi_g = 1/2 there, so m(phi_g) = 1), the
+    other half is pure wuestite (m = 0); no transport (every diffusivity 0) and
+    frozen phases (L = 0).  In the reacting half a = x_O follows
+    a' = -k a (2 a + c), c = x_H - 2 x_O (constant), whose solution is
+    a(t) = c a0 / ((2 a0 + c) exp(c k t) - 2 a0); Eq. 39 then gives f(t) in
+    closed form.  Explicit Euler converges to it at first order in dt."""
+    shape = (6, 8)
+    a0, xH0, xb = 0.02, 0.08, 0.5
+    k = 4.5e4
+    T = 2.0e-4
+    errs = []
+    for nsteps in (200, 400, 800):
+        p = I.Params(L=(0.0, 0.0, 0.0), DO=(0.0, 0.0, 0.0), DH=(0.0, 0.0, 0.0), DW=(0.0, 0.0, 0.0), kappaO=0.0,
+                     kfor=k)
+        f = _uniform_fields(shape)
+        f["phi_w"][:, :4] = 1.0
+        f["xO"][:, :4] = xb
+        f["phi_f"][:, 4:] = 0.25
+        f["phi_w"][:, 4:] = 0.25
+        f["xO"][:, 4:] = a0
+        f["xH"][:, 4:] = xH0
+        s = _sim(oracle, 2, shape, I.H_DEFAULT, T / nsteps, p, f, mechanics=False, dirichlet=False)
+        st = s.step(nsteps)
+        c = xH0 - 2 * a0
+        a = c * a0 / ((2 * a0 + c) * math.exp(c * k * T) - 2 * a0)
+        f_exact = 1.0 - (a + xb) / (a0 + xb)
+        errs.append(abs(st["red_degree"] - f_exact))
+        assert f_exact > 0.01
+    assert errs[-1] < 2e-3 * f_exact
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3     # first order
+
+
+# ---------------------------------------------------------------------------
+# The discrete elastic energy's gradient is the residual A u - b
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_elastic_energy_gradient_is_the_residual(oracle, dim):
+    """Pi(u) is quadratic, so central differences of the discrete elastic
+    energy give its gradient exactly (up to rounding); it must equal
+    h^(d-1) (A u - b) of the operator and right-hand side the solve uses (the
+    net force on a face divided by the face's area), with a plastic strain
+    present so that every term of b enters."""
+    rng = np.random.default_rng(5 + dim)
+    shape = (5, 6) if dim == 2 else (4, 5, 6)
+    f = _uniform_fields(shape)
+    f["phi_f"] = rng.uniform(0.0, 0.7, shape)
+    f["phi_w"] = rng.uniform(0.0, 0.3, shape)
+    nc = 4 if dim == 2 else 6
+    epsp = rng.normal(0, 2e-3, (nc,) + shape)
+    h = I.H_DEFAULT
+    p = I.Params()
+    s = _sim(oracle, dim, shape, h, 1e-9, p, f, epsp=epsp)
+    fs = oracle.face_shapes(dim, shape)[:dim]
+    u = [rng.normal(0, 1e-9, fsh) for fsh in fs]
+    u[0][..., 0] = 0; u[0][..., -1] = 0
+    u[1][..., 0, :] = 0; u[1][..., -1, :] = 0
+    if dim == 3:
+        u[2][0] = 0; u[2][-1] = 0
+    s.ux[...] = u[0]
+    s.uy[...] = u[1]
+    if dim == 3:
+        s.uz[...] = u[2]
+    K, G = s.moduli()
+    Au = s.apply(K, G, u)
+    b = s.rhs()
+    arrs = [s.ux, s.uy] + ([s.uz] if dim == 3 else [])
+    d = 1e-12
+    checked = [0, 0, 0]
+    for comp in range(dim):
+        a = arrs[comp]
+        for idx in list(np.ndindex(a.shape))[::3]:
+            # interior faces only (the roller faces are fixed at zero)
+            ax = {0: -1, 1: -2, 2: -3}[comp]
+            if idx[ax] == 0 or idx[ax] == a.shape[ax] - 1:
+                continue
+            v = a[idx]
+            a[idx] = v + d
+            Ep = s.elastic_energy()
+            a[idx] = v - d
+            Em = s.elastic_energy()
+            a[idx] = v
+            g = (Ep - Em) / (2 * d)
+            want = h ** (dim - 1) * (Au[comp][idx] - b[comp][idx])
+            scale = h ** (dim - 1) * (np.max(np.abs(Au[comp])) + np.max(np.abs(b[comp])))
+            assert abs(g - want) < 1e-6 * scale, (comp, idx, g, want)
+            checked[comp] += 1
+    assert min(checked[:dim]) > 5, checked
+
+
+# ---------------------------------------------------------------------------
+# P11 with mechanics: the elastic energy at equilibrium joins the descent
+# ---------------------------------------------------------------------------
+def test_energy_decreases_with_mechanics(oracle):
+    """Without reaction and Dirichlet faces the total free energy -- barrier,
+    gradient and the elastic energy at mechanical equilibrium (Eq. 26) --
+    never increases.  The chemical energy is switched off and the species are
+    frozen (no diffusion), so that the phases move under the elastic driving
+    force and the elastic energy is about half of the drop."""
+    p = I.Params(kfor=0.0, DO=(0.0, 0.0, 0.0), DH=(0.0, 0.0, 0.0), DW=(0.0, 0.0, 0.0))
+    n = 24
+    f = I.ic_core_shell((n, n), r_core=7.0, frame=0, noise_seed=5)
+    f["xO"] = np.where(f["phi_w"] > 0.5, 0.45, 0.05)
+    s = _sim(oracle, 2, (n, n), I.H_DEFAULT, 1e-2, p, f, mechanics=True, plasticity=False, dirichlet=False,
+             chem_phase=False, cg_rtol=1e-12)
+    s.mech_solve()
+    E, Eel = [s.energy()], [s.elastic_energy()]
+    for _ in range(30):
+        s.step()
+        s.mech_solve()                 # the elastic energy at equilibrium with the new phases
+        E.append(s.energy())
+        Eel.append(s.elastic_energy())
+    dE = np.diff(E)
+    assert np.all(dE <= 1e-12 * abs(E[0]))
+    assert E[-1] < E[0]
+    assert Eel[-1] - Eel[0] < 0.25 * (E[-1] - E[0]) < 0
+
+
+# ---------------------------------------------------------------------------
+# P8 in 3D: Lame solution of a misfitting core-shell sphere
+# ---------------------------------------------------------------------------
+def _lame_3d(layers, R):
+    """u_r = A_k r + B_k / r^2 per layer, eigenstrain e_k:
+    sigma_rr = 3 K (A - e) - 4 G B / r^3; B_core = 0, u_r and sigma_rr
+    continuous, u_r(R) = 0."""
+    nl = len(layers)
+    M = np.zeros((2 * nl, 2 * nl))
+    rhs = np.zeros(2 * nl)
+    row = 0
+    M[row, 1] = 1.0; row += 1
+    for k in range(nl - 1):
+        r = layers[k][0]
+        Kk, Gk, ek = layers[k][1:]
+        Kn, Gn, en = layers[k + 1][1:]
+        M[row, 2 * k] = r; M[row, 2 * k + 1] = 1 / r ** 2
+        M[row, 2 * k + 2] = -r; M[row, 2 * k + 3] = -1 / r ** 2; row += 1
+        M[row, 2 * k] = 3 * Kk; M[row, 2 * k + 1] = -4 * Gk / r ** 3
+        M[row, 2 * k + 2] = -3 * Kn; M[row, 2 * k + 3] = 4 * Gn / r ** 3
+        rhs[row] = 3 * Kk * ek - 3 * Kn * en; row += 1
+    M[row, 2 * nl - 2] = R; M[row, 2 * nl - 1] = 1 / R ** 2
+    return np.linalg.solve(M, rhs)
+
+
+def test_lame_core_shell_sphere_converges(oracle):
+    p = I.Params()
+    errs = []
+    for n in (16, 32, 48):
+        a, b = 0.25 * n, 0.375 * n
+        f = I.ic_core_shell((n, n, n), r_core=a, r_shell=b)
+        h = 1e-7
+        s = _sim(oracle, 3, (n, n, n), h, 1e-9, p, f, cg_rtol=1e-10)
+        s.mech_solve()
+        dT = 1 - p.Omega_f
+        layers = [(a * h, p.K[2], p.G[2], 0.0),
+                  (b * h, dT * p.K[0], dT * p.G[0], dT ** (1 / 3) - 1),
+                  (n / 2 * h, p.K[1], p.G[1], 0.0)]
+        A_core = _lame_3d(layers, n / 2 * h)[0]
+        c = np.arange(n) + 0.5 - n / 2
+        zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
+        inner = xx ** 2 + yy ** 2 + zz ** 2 < (0.5 * a) ** 2
+        e = [np.diff(s.ux, axis=2)[inner].mean() / h, np.diff(s.uy, axis=1)[inner].mean() / h,
+             np.diff(s.uz, axis=0)[inner].mean() / h]
+        assert max(e) - min(e) < 1e-8 * abs(A_core)          # the core's strain is isotropic
+        errs.append(abs(e[0] - A_core) / abs(A_core))
+    assert errs[-1] < 0.015, errs
+    assert errs[-1] < errs[0]
+
+
+# ---------------------------------------------------------------------------
+# P10: lever rule of the ferrite / wuestite benchmark (Sec. 4.1, Eq. 38)
+# ---------------------------------------------------------------------------
+@pytest.mark.slow
+def test_lever_rule(oracle):
+    """Sec. 4.1: a box half ferrite, half wuestite with a uniform initial x_O
+    (no reaction, no mechanics, closed) equilibrates to a wuestite fraction
+    (Eq. 38) given by the lever rule (x_O - x_f) / (x_w - x_f).  Equilibrium
+    depends on the energy only, so the mobilities L_a are raised tenfold and
+    the gradient coefficients eps_a thirtyfold (a flat interface has no
+    curvature, so eps moves no bulk composition) so that the interface is
+    resolved on the 78 nm grid and moves within seconds of model time.  The
+    diffuse interface holds an oxygen excess, so phi_bar = lever + c / length:
+    two box lengths (5 and 10 um) extrapolate it away.  The bulk compositions
+    reach the common tangent of Eq. 35, and the fraction discriminates the
+    tangent value x_w = 0.517 from the 0.571 printed in the caption of Fig. 1."""
+    base = I.Params()
+    p = I.Params(kfor=0.0, eps=tuple(30 * e for e in base.eps), L=tuple(10 * l for l in base.L))
+    h = 5e-6 / 64
+    dt, T = 3.5e-5, 4.0
+    xf, xw = oracle.common_tangent()[:2]
+    for xbar in (0.3, 0.45):
+        res = {}
+        for nx in (64, 128):
+            f = _uniform_fields((1, nx))
+            f["phi_f"][:, :nx // 2] = 1.0
+            f["phi_w"][:, nx // 2:] = 1.0
+            f["xO"][...] = xbar
+            s = _sim(oracle, 2, (1, nx), h, dt, p, f, mechanics=False, plasticity=False, dirichlet=False)
+            n = int(T / dt)
+            s.step(int(0.9 * n))
+            a = s.f["phi_w"].mean()
+            s.step(n - int(0.9 * n))
+            res[nx] = s.f["phi_w"].mean()
+            assert abs(res[nx] - a) < 2e-4                          # equilibrated
+            assert abs(s.f["xO"][0, 0] - xf) < 0.005 and abs(s.f["xO"][0, -1] - xw) < 0.005
+        ext = 2 * res[128] - res[64]
+        lever = (xbar - xf) / (xw - xf)
+        printed = (xbar - I.X_F_PRINTED) / (I.X_W_PRINTED - I.X_F_PRINTED)
+        assert abs(ext - lever) < 0.01, (xbar, ext, lever)
+        assert abs(ext - printed) > 0.05, (xbar, ext, printed)
