@@ -49,9 +49,11 @@ struct Layout {
   size_t stage_elems;
   // byte offsets into the workspace
   size_t o_fld[2][5], o_u[3], o_epsp, o_epsP, o_mu, o_K, o_G;
+  size_t o_lo[2][5];       // FP32 state: low parts of the five fields (0 in FP64)
   size_t o_r[3], o_z[3], o_pa[3], o_pb[3], o_q[3], o_di[3];
   size_t o_scal, o_part_u, o_part_a, o_part_b, o_part_c, o_part_f, o_stage;
   size_t o_uo[3], o_du[3], o_phiprev;   // learned start only
+  size_t o_phiprev_lo;                  // learned start, FP32 state: low part of phi_prev
   size_t o_dsq;                          // learned start: partials of the increment's sum of squares
   size_t o_b[3];                        // 3D: right-hand side b of the equilibrium solve
   size_t total;
@@ -124,6 +126,8 @@ Layout make_layout(const pf_config* c) {
   auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes) + kStagger; return o; };
   for (int s = 0; s < 2; ++s)
     for (int f = 0; f < 5; ++f) L.o_fld[s][f] = take(arr);
+  for (int s = 0; s < 2; ++s)
+    for (int f = 0; f < 5; ++f) L.o_lo[s][f] = L.es == 4 ? take(arr) : 0;
   for (int d = 0; d < 3; ++d) L.o_u[d] = d < c->dim ? take(arr) : 0;
   L.o_epsp = take(arr * L.nc);
   L.o_epsP = take(arr);
@@ -149,6 +153,7 @@ Layout make_layout(const pf_config* c) {
   if (c->warm == PF_WARM_LEARNED) {
     for (int d = 0; d < 3; ++d) { L.o_uo[d] = take(arr); L.o_du[d] = take(arr); }
     L.o_phiprev = take(arr);
+    L.o_phiprev_lo = L.es == 4 ? take(arr) : 0;
     L.o_dsq = take(kAfterBlocks * sizeof(double));
   }
   L.total = off;
@@ -324,6 +329,11 @@ struct Impl {
     a.xH = c->arr<T>(L.o_fld[s][3]); a.xW = c->arr<T>(L.o_fld[s][4]);
     a.npf = c->arr<T>(L.o_fld[s ^ 1][0]); a.npw = c->arr<T>(L.o_fld[s ^ 1][1]); a.nxO = c->arr<T>(L.o_fld[s ^ 1][2]);
     a.nxH = c->arr<T>(L.o_fld[s ^ 1][3]); a.nxW = c->arr<T>(L.o_fld[s ^ 1][4]);
+    if (L.es == 4)
+      for (int f = 0; f < 5; ++f) {
+        a.lo[f] = c->arr<T>(L.o_lo[s][f]);
+        a.nlo[f] = c->arr<T>(L.o_lo[s ^ 1][f]);
+      }
     a.mu = c->arr<T>(L.o_mu);
     a.mu_out = c->arr<T>(L.o_mu);
     for (int d = 0; d < DIM; ++d) a.u[d] = c->arr<T>(L.o_u[d]);
@@ -785,10 +795,12 @@ pf_status pf_fields(pf_ctx* c, int field_id, int dir, void* ptr, size_t nbytes, 
   const Grid& g = L.g;
   const int dim = c->cfg.dim;
   int cx = g.nx, cy = g.ny, cz = g.nz, zaxis = -1, ncomp = 1;
-  size_t base = 0;
+  size_t base = 0, base_lo = 0;
   switch (field_id) {
     case PF_FIELD_PHI_F: case PF_FIELD_PHI_W: case PF_FIELD_XO: case PF_FIELD_XH: case PF_FIELD_XW:
-      base = L.o_fld[c->cur][field_id]; break;
+      base = L.o_fld[c->cur][field_id];
+      base_lo = L.o_lo[c->cur][field_id];
+      break;
     case PF_FIELD_UX: base = L.o_u[0]; cx += 1; zaxis = 0; break;
     case PF_FIELD_UY: base = L.o_u[1]; cy += 1; zaxis = 1; break;
     case PF_FIELD_UZ:
@@ -812,12 +824,18 @@ pf_status pf_fields(pf_ctx* c, int field_id, int dir, void* ptr, size_t nbytes, 
       if (!ptr_is_device) HIPCHK(c, hipMemcpyAsync(stage, user, per * sizeof(double), hipMemcpyHostToDevice, c->stream));
       if (L.es == 8)
         hipLaunchKernelGGL(k_unpack<double>, dim3(nblk), dim3(nthr), 0, c->stream, (const double*)buf, c->arr<double>(dev_off), g, cx, cy, cz, zaxis);
+      else if (base_lo)
+        hipLaunchKernelGGL(k_unpack_pair, dim3(nblk), dim3(nthr), 0, c->stream, (const double*)buf, c->arr<float>(dev_off),
+                           c->arr<float>(base_lo), g, cx, cy, cz);
       else
         hipLaunchKernelGGL(k_unpack<float>, dim3(nblk), dim3(nthr), 0, c->stream, (const double*)buf, c->arr<float>(dev_off), g, cx, cy, cz, zaxis);
       LAUNCHCHK(c);
     } else {
       if (L.es == 8)
         hipLaunchKernelGGL(k_pack<double>, dim3(nblk), dim3(nthr), 0, c->stream, (const double*)c->arr<double>(dev_off), buf, g, cx, cy, cz);
+      else if (base_lo)
+        hipLaunchKernelGGL(k_pack_pair, dim3(nblk), dim3(nthr), 0, c->stream, (const float*)c->arr<float>(dev_off),
+                           (const float*)c->arr<float>(base_lo), buf, g, cx, cy, cz);
       else
         hipLaunchKernelGGL(k_pack<float>, dim3(nblk), dim3(nthr), 0, c->stream, (const float*)c->arr<float>(dev_off), buf, g, cx, cy, cz);
       LAUNCHCHK(c);

@@ -47,6 +47,8 @@ struct BatchArgs {
   KP<T> p;
   T* f_old[5];             // current fields phi_f, phi_w, x_O, x_H, x_H2O
   T* f_new[5];             // where the step writes the next ones
+  T* lo_old[5];            // FP32 state: low parts of the current fields (null in FP64)
+  T* lo_new[5];
   T* u[2];
   T* epsp;
   T* epsP;
@@ -262,6 +264,11 @@ __device__ __forceinline__ CellArgs<T> cell_view(const BatchArgs<T>& B, const In
   a.xH = B.f_old[3] + d.off; a.xW = B.f_old[4] + d.off;
   a.npf = B.f_new[0] + d.off; a.npw = B.f_new[1] + d.off; a.nxO = B.f_new[2] + d.off;
   a.nxH = B.f_new[3] + d.off; a.nxW = B.f_new[4] + d.off;
+  if constexpr (sizeof(T) == 4)
+    for (int f = 0; f < 5; ++f) {
+      a.lo[f] = B.lo_old[f] + d.off;
+      a.nlo[f] = B.lo_new[f] + d.off;
+    }
   a.mu = B.mu + d.off;
   a.mu_out = B.mu + d.off;
   a.u[0] = B.u[0] + d.off;

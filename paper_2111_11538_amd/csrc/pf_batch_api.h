@@ -19,6 +19,7 @@ struct BatchLayout {
   int n_el, n_ce;
   int max_ap, max_up;                  // table capacities
   size_t o_fld[2][5], o_u[2], o_epsp, o_epsP, o_mu, o_K, o_G;
+  size_t o_lo[2][5];       // FP32 state: low parts of the five fields (0 in FP64)
   size_t o_r[2], o_z[2], o_pa[2], o_pb[2], o_q[2], o_di[2];
   size_t o_inst, o_el, o_ap, o_ce, o_up;
   size_t o_bn, o_pr, o_pa_part, o_pu, o_pt, o_pc, o_iscal, o_bar, o_stage;
@@ -76,6 +77,8 @@ BatchLayout make_batch_layout(const pf_config* c, const pf_extent* ext, int coun
   const size_t arr = align_up((size_t)L.N * L.es);
   for (int s = 0; s < 2; ++s)
     for (int f = 0; f < 5; ++f) L.o_fld[s][f] = take(arr);
+  for (int s = 0; s < 2; ++s)
+    for (int f = 0; f < 5; ++f) L.o_lo[s][f] = L.es == 4 ? take(arr) : 0;
   for (int d = 0; d < 2; ++d) L.o_u[d] = take(arr);
   L.o_epsp = take((size_t)L.N * L.es * 4);
   L.o_epsP = take(arr);
@@ -161,6 +164,8 @@ static BatchArgs<T> batch_args(pf_batch* bt, int cur) {
   for (int f = 0; f < 5; ++f) {
     B.f_old[f] = bt->arr<T>(L.o_fld[cur][f]);
     B.f_new[f] = bt->arr<T>(L.o_fld[cur ^ 1][f]);
+    B.lo_old[f] = L.es == 4 ? bt->arr<T>(L.o_lo[cur][f]) : nullptr;
+    B.lo_new[f] = L.es == 4 ? bt->arr<T>(L.o_lo[cur ^ 1][f]) : nullptr;
   }
   for (int d = 0; d < 2; ++d) {
     B.u[d] = bt->arr<T>(L.o_u[d]);
@@ -376,10 +381,12 @@ pf_status pf_batch_fields(pf_batch* bt, int instance, int field_id, int dir, voi
   const InstDesc& d = L.inst[instance];
   Grid g = d.g;
   int cx = g.nx, cy = g.ny, cz = 1, zaxis = -1, ncomp = 1;
-  size_t base;
+  size_t base, base_lo = 0;
   switch (field_id) {
     case PF_FIELD_PHI_F: case PF_FIELD_PHI_W: case PF_FIELD_XO: case PF_FIELD_XH: case PF_FIELD_XW:
-      base = L.o_fld[bt->cur][field_id]; break;
+      base = L.o_fld[bt->cur][field_id];
+      base_lo = L.o_lo[bt->cur][field_id];
+      break;
     case PF_FIELD_UX: base = L.o_u[0]; cx += 1; zaxis = 0; break;
     case PF_FIELD_UY: base = L.o_u[1]; cy += 1; zaxis = 1; break;
     case PF_FIELD_EPSP: base = L.o_epsp; ncomp = 4; break;
@@ -393,17 +400,24 @@ pf_status pf_batch_fields(pf_batch* bt, int instance, int field_id, int dir, voi
   const int nthr = 256, nblk = (int)((per + nthr - 1) / nthr);
   for (int comp = 0; comp < ncomp; ++comp) {
     const size_t dev_off = base + ((size_t)comp * L.N + d.off) * L.es;
+    const size_t lo_off = base_lo ? base_lo + (size_t)d.off * L.es : 0;
     char* user = reinterpret_cast<char*>(ptr) + comp * per * sizeof(double);
     double* buf = ptr_is_device ? reinterpret_cast<double*>(user) : stage;
     if (dir == 1) {
       if (!ptr_is_device) BHIP(bt, hipMemcpyAsync(stage, user, per * sizeof(double), hipMemcpyHostToDevice, bt->stream));
       if (L.es == 8)
         hipLaunchKernelGGL(k_unpack<double>, dim3(nblk), dim3(nthr), 0, bt->stream, (const double*)buf, bt->arr<double>(dev_off), g, cx, cy, cz, zaxis);
+      else if (lo_off)
+        hipLaunchKernelGGL(k_unpack_pair, dim3(nblk), dim3(nthr), 0, bt->stream, (const double*)buf, bt->arr<float>(dev_off),
+                           bt->arr<float>(lo_off), g, cx, cy, cz);
       else
         hipLaunchKernelGGL(k_unpack<float>, dim3(nblk), dim3(nthr), 0, bt->stream, (const double*)buf, bt->arr<float>(dev_off), g, cx, cy, cz, zaxis);
     } else {
       if (L.es == 8)
         hipLaunchKernelGGL(k_pack<double>, dim3(nblk), dim3(nthr), 0, bt->stream, (const double*)bt->arr<double>(dev_off), buf, g, cx, cy, cz);
+      else if (lo_off)
+        hipLaunchKernelGGL(k_pack_pair, dim3(nblk), dim3(nthr), 0, bt->stream, (const float*)bt->arr<float>(dev_off),
+                           (const float*)bt->arr<float>(lo_off), buf, g, cx, cy, cz);
       else
         hipLaunchKernelGGL(k_pack<float>, dim3(nblk), dim3(nthr), 0, bt->stream, (const float*)bt->arr<float>(dev_off), buf, g, cx, cy, cz);
       if (!ptr_is_device) BHIP(bt, hipMemcpyAsync(user, stage, per * sizeof(double), hipMemcpyDeviceToHost, bt->stream));

@@ -1559,6 +1559,10 @@ struct CellArgs {
   KP<T> p;
   const T *pf, *pw, *xO, *xH, *xW, *mu;
   T *npf, *npw, *nxO, *nxH, *nxW;
+  // FP32 state only: low parts of the five fields (value = hi + lo, the hi
+  // arrays above), read and written by the field update; null in FP64
+  const T* lo[5];
+  T* nlo[5];
   const T* u[3];
   T* epsp;
   T* epsP;
@@ -1643,10 +1647,60 @@ __device__ __forceinline__ T shear_yz(const Grid& g, const T* uy, const T* uz, i
 // strain: phase quantities and driving forces (Eq. 33), return map (Eq. 25,
 // 34), reaction (Eq. 27, 28), explicit Euler update, and the cell's
 // contributions to the step's partial sums.
+// New value of a field given its old value and increment d.  FP64 state:
+// old + d.  FP32 state: the value is the pair (hi, lo) with value hi + lo; the
+// FP32 increment is added in FP64 (and the sum later split again into an FP32
+// pair, about 48 significant bits), so that increments far below half an
+// FP32 ulp of the field accumulate instead of being rounded away.
+template <typename T>
+__device__ __forceinline__ double field_new(T hi, T lo, T d) {
+  if constexpr (sizeof(T) == 4)
+    return ((double)hi + (double)lo) + (double)d;   // hi + lo is exact in FP64
+  else
+    return hi + d;
+}
+template <typename T>
+__device__ __forceinline__ void field_store(double v, T* out_hi, T* out_lo, int e) {
+  if constexpr (sizeof(T) == 4) {
+    const float h = (float)v;
+    out_hi[e] = h;
+    out_lo[e] = (float)(v - (double)h);
+  } else {
+    (void)out_lo;
+    out_hi[e] = v;
+  }
+}
+
+// The order parameters lie in [0, 1] with phi_g = 1 - phi_f - phi_w (Sec.
+// 2.2): after the explicit update (phi_f, phi_g, phi_w) is replaced by its
+// Euclidean projection onto {phi_a >= 0, sum = 1}.  Michelot's active-set
+// iteration (1986): shift the active entries by (sum - 1) / count, drop the
+// ones that become negative, repeat; with three entries two passes suffice.
+// A triple already inside is left unchanged.
+__device__ __forceinline__ void phase_bound(double& pf, double& pw) {
+  double a0 = pf, a1 = 1.0 - pf - pw, a2 = pw;
+  if (a0 >= 0.0 && a1 >= 0.0 && a2 >= 0.0) return;
+  bool k0 = true, k1 = true, k2 = true;
+  double th = 0.0;
+#pragma unroll
+  for (int pass = 0; pass < 3; ++pass) {
+    const double sum = (k0 ? a0 : 0.0) + (k1 ? a1 : 0.0) + (k2 ? a2 : 0.0);
+    const int cnt = (int)k0 + (int)k1 + (int)k2;
+    th = (sum - 1.0) / (double)cnt;
+    const bool d0 = k0 && a0 - th < 0.0, d1 = k1 && a1 - th < 0.0, d2 = k2 && a2 - th < 0.0;
+    if (!(d0 || d1 || d2)) break;
+    k0 = k0 && !d0;
+    k1 = k1 && !d1;
+    k2 = k2 && !d2;
+  }
+  pf = k0 ? a0 - th : 0.0;
+  pw = k2 ? a2 - th : 0.0;
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void cell_update(const CellArgs<T>& a, int e, T pf, T pw, T xO, T xH, T xW, T lf, T lw,
                                             T divO, T divH, T divW, T bO, T bH, const T (&eb)[6],
-                                            double (&acc)[NQ_STEP]) {
+                                            const T (&lo)[5], double (&acc)[NQ_STEP]) {
   const Grid& g = a.g;
   const KP<T>& p = a.p;
   lf *= p.ih2;
@@ -1717,20 +1771,23 @@ __device__ __forceinline__ void cell_update(const CellArgs<T>& a, int e, T pf, T
     vm = T(1.2247448713915890491) * T(2) * q.G * nd;   // sqrt(3/2) |dev sigma|
   }
   // reaction (Eq. 27, 28): zero once the cell is full of water
-  const T r = xW < T(1) ? interp_m(pg, p.mform) * p.kfor * xO * xH : T(0);
-  const T nf = pf + p.dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf);
-  const T nw = pw + p.dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw);
-  const T nO = xO + p.dt * (-divO - r);
-  const T nH = xH + p.dt * (-divH - T(2) * r);
-  const T nW = xW + p.dt * (-divW + r);
-  a.npf[e] = nf;
-  a.npw[e] = nw;
-  a.nxO[e] = nO;
-  a.nxH[e] = nH;
-  a.nxW[e] = nW;
-  acc[0] = (double)nO + (double)nW;
-  acc[1] = (double)nH + 2.0 * (double)nW;
-  acc[2] = (double)nO;
+  const T r = (double)xW + (double)lo[4] < 1.0 ? interp_m(pg, p.mform) * p.kfor * xO * xH : T(0);
+  const T df = p.dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf);
+  const T dw = p.dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw);
+  const T dO = p.dt * (-divO - r);
+  const T dH = p.dt * (-divH - T(2) * r);
+  const T dW = p.dt * (-divW + r);
+  double nf = field_new(pf, lo[0], df), nw = field_new(pw, lo[1], dw);
+  phase_bound(nf, nw);
+  const double nO = field_new(xO, lo[2], dO), nH = field_new(xH, lo[3], dH), nW = field_new(xW, lo[4], dW);
+  field_store(nf, a.npf, a.nlo[0], e);
+  field_store(nw, a.npw, a.nlo[1], e);
+  field_store(nO, a.nxO, a.nlo[2], e);
+  field_store(nH, a.nxH, a.nlo[3], e);
+  field_store(nW, a.nxW, a.nlo[4], e);
+  acc[0] = nO + nW;
+  acc[1] = nH + 2.0 * nW;
+  acc[2] = nO;
   acc[3] = (double)bO;
   acc[4] = (double)bH + 2.0 * (double)bO;
   acc[5] = (double)vm;
@@ -1752,6 +1809,10 @@ __device__ __forceinline__ void step_tile(const CellArgs<T>& a, int bx, int by, 
     const int pl = g.px * g.ny;
     const T ih = p.ih;
     const T pf = a.pf[e], pw = a.pw[e], xO = a.xO[e], xH = a.xH[e], xW = a.xW[e], muc = a.mu[e];
+    T lo[5] = {T(0), T(0), T(0), T(0), T(0)};
+    if constexpr (sizeof(T) == 4)
+#pragma unroll
+      for (int f = 0; f < 5; ++f) lo[f] = a.lo[f][e];
     T mu_l, MOc, DHc, DWc;
     transport(p, pf, pw, xO, mu_l, MOc, DHc, DWc);
     (void)mu_l;
@@ -1823,7 +1884,7 @@ __device__ __forceinline__ void step_tile(const CellArgs<T>& a, int bx, int by, 
                            shear_yz(g, uy, uz, i, j, k + 1, ih) + shear_yz(g, uy, uz, i, j + 1, k + 1, ih));
       }
     }
-    cell_update<T, DIM>(a, e, pf, pw, xO, xH, xW, lf, lw, divO, divH, divW, bO, bH, eb, acc);
+    cell_update<T, DIM>(a, e, pf, pw, xO, xH, xW, lf, lw, divO, divH, divW, bO, bH, eb, lo, acc);
   }
   // the eight partials together: the wave trees of all quantities interleaved,
   // then one exchange across the waves (the same operations in the same
@@ -1867,9 +1928,15 @@ __device__ __forceinline__ void totals_tile(const CellArgs<T>& a, int bx, int by
   double s0 = 0, s1 = 0, s2 = 0;
   if (i < a.g.nx && j < a.g.ny) {
     const int e = gidx(a.g, i, j, k);
-    s0 = (double)a.xO[e] + (double)a.xW[e];
-    s1 = (double)a.xH[e] + 2.0 * (double)a.xW[e];
-    s2 = (double)a.xO[e];
+    double O = (double)a.xO[e], H = (double)a.xH[e], W = (double)a.xW[e];
+    if constexpr (sizeof(T) == 4) {
+      O += (double)a.lo[2][e];
+      H += (double)a.lo[3][e];
+      W += (double)a.lo[4][e];
+    }
+    s0 = O + W;
+    s1 = H + 2.0 * W;
+    s2 = O;
   }
   s0 = block_sum(s0, red);
   s1 = block_sum(s1, red);
@@ -1995,6 +2062,40 @@ __global__ void k_unpack(const double* src, T* dst, Grid g, int cx, int cy, int 
   double v = src[t];
   if ((zero_axis == 0 && ii == 0) || (zero_axis == 1 && jj == 0) || (zero_axis == 2 && kk == 0)) v = 0.0;
   dst[gidx(g, ii, jj, kk)] = (T)v;
+}
+
+// FP32 pair form of the five fields: hi = the FP32 rounding of the value,
+// lo = the FP32 rounding of the remainder (set), value = hi + lo (get).
+__global__ void k_unpack_pair(const double* src, float* hi, float* lo, Grid g, int cx, int cy, int cz) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long total = (long long)cx * cy * cz;
+  if (t >= total) return;
+  int ii = (int)(t % cx);
+  long long rest = t / cx;
+  int jj = (int)(rest % cy);
+  int kk = (int)(rest / cy);
+  if (ii >= g.nx || jj >= g.ny || kk >= g.nz) return;
+  const double v = src[t];
+  const float h = (float)v;
+  const int e = gidx(g, ii, jj, kk);
+  hi[e] = h;
+  lo[e] = (float)(v - (double)h);
+}
+
+__global__ void k_pack_pair(const float* hi, const float* lo, double* dst, Grid g, int cx, int cy, int cz) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long total = (long long)cx * cy * cz;
+  if (t >= total) return;
+  int ii = (int)(t % cx);
+  long long rest = t / cx;
+  int jj = (int)(rest % cy);
+  int kk = (int)(rest / cy);
+  double v = 0.0;
+  if (ii < g.nx && jj < g.ny && kk < g.nz) {
+    const int e = gidx(g, ii, jj, kk);
+    v = (double)hi[e] + (double)lo[e];
+  }
+  dst[t] = v;
 }
 
 template <typename T>

@@ -793,6 +793,8 @@ struct View {
 template <typename T>
 struct PackArgs {
   View<T> phi_f, phi_w, phi_prev;
+  const T* phi_f_lo;           // FP32 state: low parts of phi_f and of phi_prev (null: none)
+  const T* phi_prev_lo;
   View<T> u1[3], u0[3];        // previous increment = u1 - u0 (u0 may be null: zero)
   View<T> u2[3];               // current state for targets (u2 - u1), null when no target is wanted
   int nx, ny, nz;              // full grid
@@ -817,12 +819,14 @@ __device__ __forceinline__ double eigen_strain_d(double pf, double Omega) {
 // the mean by 3-point Gauss-Legendre (exact for this quartic; a sum of
 // non-negative terms, with 1 - t formed from 1 - x and 1 - y), and
 //   cbrt(a) - cbrt(b) = (a - b) / (ca^2 + ca cb + cb^2).
-__device__ __forceinline__ float eigen_strain_diff_f(float x, float y, float Omega) {
+// dxy is x - y, passed separately so that a state held as FP32 pairs can give
+// it from both parts.
+__device__ __forceinline__ float eigen_strain_diff_f(float x, float y, float dxy, float Omega) {
   const float m = 0.5f * (x + y), mc = 0.5f * ((1.f - x) + (1.f - y));
-  const float r = 0.7745966692414834f * (0.5f * (x - y));     // sqrt(3/5) times the half width
+  const float r = 0.7745966692414834f * (0.5f * dxy);         // sqrt(3/5) times the half width
   const float u0 = m * mc, u1 = (m - r) * (mc + r), u2 = (m + r) * (mc - r);
   const float mean = (5.f * (u1 * u1 + u2 * u2) + 8.f * (u0 * u0)) * (1.f / 18.f);
-  const float dh = (x - y) * 30.f * mean;
+  const float dh = dxy * 30.f * mean;
   const float hx = x * x * x * (x * (6.f * x - 15.f) + 10.f), hy = y * y * y * (y * (6.f * y - 15.f) + 10.f);
   const float ca = cbrtf(1.f - Omega * hx), cb = cbrtf(1.f - Omega * hy);
   return -Omega * dh / (ca * ca + ca * cb + cb * cb);
@@ -847,7 +851,10 @@ __global__ __launch_bounds__(CNT) void k_pack_inputs(PackArgs<T> a) {
         const float pf = a.phi_f.p[e];
         c[0] = pf;
         c[1] = a.phi_w.p[e];
-        c[2] = eigen_strain_diff_f(pf, a.phi_prev.p[e], Om) * es;
+        const float pp = a.phi_prev.p[e];
+        float dxy = pf - pp;
+        if (a.phi_f_lo) dxy += a.phi_f_lo[e] - a.phi_prev_lo[e];
+        c[2] = eigen_strain_diff_f(pf, pp, dxy, Om) * es;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           const float u1 = a.u1[d].p[e];

@@ -302,8 +302,9 @@ __global__ __launch_bounds__(pfn::CNT) void k_after_solve(const T* __restrict__ 
                                                          const T* __restrict__ u2, T* __restrict__ o0,
                                                          T* __restrict__ o1, T* __restrict__ o2,
                                                          T* __restrict__ d0, T* __restrict__ d1, T* __restrict__ d2,
-                                                         const T* __restrict__ phi, T* __restrict__ phi_prev, long n,
-                                                         double* __restrict__ part) {
+                                                         const T* __restrict__ phi, T* __restrict__ phi_prev,
+                                                         const T* __restrict__ phi_lo, T* __restrict__ phi_prev_lo,
+                                                         long n, double* __restrict__ part) {
   __shared__ double red[pfn::CNT / 64];
   double s = 0.0;
   for (long e = blockIdx.x * (long)pfn::CNT + threadIdx.x; e < n; e += (long)gridDim.x * pfn::CNT) {
@@ -316,6 +317,7 @@ __global__ __launch_bounds__(pfn::CNT) void k_after_solve(const T* __restrict__ 
     o1[e] = b;
     o2[e] = c;
     phi_prev[e] = phi[e];
+    if (phi_lo) phi_prev_lo[e] = phi_lo[e];
     s += (double)da * (double)da + (double)db * (double)db + (double)dc * (double)dc;
   }
   s = block_sum(s, red);
@@ -331,6 +333,10 @@ static pfn::PackArgs<T> ctx_pack_args(pf_ctx* c) {
   a.phi_f = {c->arr<T>(L.o_fld[c->cur][0]), rs, ps};
   a.phi_w = {c->arr<T>(L.o_fld[c->cur][1]), rs, ps};
   a.phi_prev = {c->arr<T>(L.o_phiprev), rs, ps};
+  if (L.es == 4) {
+    a.phi_f_lo = c->arr<T>(L.o_lo[c->cur][0]);
+    a.phi_prev_lo = c->arr<T>(L.o_phiprev_lo);
+  }
   for (int d = 0; d < 3; ++d) {
     a.u1[d] = {c->arr<T>(L.o_du[d]), rs, ps};
     a.u0[d] = {nullptr, rs, ps};
@@ -422,7 +428,8 @@ static pf_status learned_after_solve(pf_ctx* c) {
                        (const T*)c->arr<T>(L.o_u[0]), (const T*)c->arr<T>(L.o_u[1]), (const T*)c->arr<T>(L.o_u[2]),
                        c->arr<T>(L.o_uo[0]), c->arr<T>(L.o_uo[1]), c->arr<T>(L.o_uo[2]), c->arr<T>(L.o_du[0]),
                        c->arr<T>(L.o_du[1]), c->arr<T>(L.o_du[2]), (const T*)c->arr<T>(L.o_fld[c->cur][0]),
-                       c->arr<T>(L.o_phiprev), (long)L.g.n, c->arr<double>(L.o_dsq));
+                       c->arr<T>(L.o_phiprev), L.es == 4 ? (const T*)c->arr<T>(L.o_lo[c->cur][0]) : nullptr,
+                       L.es == 4 ? c->arr<T>(L.o_phiprev_lo) : nullptr, (long)L.g.n, c->arr<double>(L.o_dsq));
     LAUNCHCHK(c);
     c->have_prev_incr = true;
   }

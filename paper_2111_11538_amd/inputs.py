@@ -299,10 +299,10 @@ def workload(name: str, n: int | None = None, steps: int | None = None) -> Workl
         n = n or 128
         f = ic_core_shell((n, n, n), r_core=48.0 * n / 128, r_shell=52.0 * n / 128, noise_seed=SEED_BASE + 2)
         return Workload(name, 3, (n, n, n), f, p, h, stable_dt(p, h, 3), steps or 1000, "mixed", True, 1e-6)
-    if name == "porous_2d":              # 2048^2 porous, plastic, Omega_f 0.2
+    if name == "porous_2d":              # 2048^2 porous, plastic, Omega_f 0.2, iron rims on the pores
         n = n or 2048
         ng = max(4, int(round(400 * (n / 2048) ** 2)))
-        f = ic_porous((n, n), 0.15, ng, SEED_BASE + 3)
+        f = ic_porous((n, n), 0.15, ng, SEED_BASE + 3, rim=2.0)
         pp = p.replace(Omega_f=0.2)
         return Workload(name, 2, (n, n), f, pp, h, stable_dt(pp, h, 2), steps or 5000, "mixed", True, 1e-6)
     if name == "porous_3d":              # 256^3 porous, plastic, Omega_f 0.2, iron rims on the pores

@@ -58,6 +58,38 @@ def test_fp64_batch_matches_oracle(oracle):
     b.close()
 
 
+def test_mixed_batch_matches_oracle(oracle):
+    """A mixed batch holding an instance of side 512 (the largest side of the
+    batch recipe) and two smaller ones, against the oracle: field error 1e-4,
+    increment error 1e-3 for phi_f, phi_w, x_H2O and 1e-4 for x_O, x_H (an
+    increment at rounding level, RMS below 1e-12, to 1e-15 absolute)."""
+    from paper_2111_11538_amd import pf
+    shapes = [(512, 512), (64, 96), (130, 77)]
+    p = I.Params()
+    h = I.H_DEFAULT
+    dt = I.stable_dt(p, h, 2)
+    fields = _instances(shapes, 80)
+    say("mixed batch vs oracle", shapes)
+    b = pf.Batch(shapes, h, dt, p, precision="mixed", plasticity=True, cg_rtol=1e-6)
+    for k, f in enumerate(fields):
+        b.set_fields(k, f)
+    b.step(2)
+    tol = {"phi_f": 1e-3, "phi_w": 1e-3, "xO": 1e-4, "xH": 1e-4, "xW": 1e-3}
+    for k, shp in enumerate(shapes):
+        s = oracle.OracleSim(2, shp, h, dt, p, fields[k], plasticity=True, cg_rtol=1e-8)
+        s.step(2)
+        out = b.fields(k)
+        for n in NAMES:
+            assert rel(out[n], s.f[n]) < 1e-4, (k, n)
+            da, db = out[n] - fields[k][n], s.f[n] - fields[k][n]
+            if np.sqrt(np.mean(db * db)) < 1e-12:
+                assert np.sqrt(np.mean((da - db) ** 2)) < 1e-15, (k, n)
+            else:
+                assert rel(da, db) < tol[n], (k, n, rel(da, db))
+        assert rel(out["ux"], s.ux) < 1e-3
+    b.close()
+
+
 def test_mixed_batch_matches_single_contexts():
     from paper_2111_11538_amd import pf
     shapes = [(64, 64), (80, 112), (96, 70), (130, 130), (64, 200), (150, 90)]
