@@ -355,6 +355,25 @@ pf_status pf_nn_layer(pf_nn *nn, int op, int layer, const void *in, const void *
 pf_status pf_nn_increment_scale(pf_nn *nn, const double *const *u1, const double *const *u0, int nx, int ny, int nz,
                                 double *s_out);
 
+/* The increment scale of pf_nn_increment_scale for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): no network, no allocation of any kind.
+ * s = root mean square of u1 - u0 over the low faces of every cell (u0 may be
+ * NULL: zero), written to the caller's device scalar `s_dev` on `hip_stream`
+ * (NULL = default stream); u1, u0 are 3 device FP64 arrays in the exchange
+ * layout of pf_fields.  Stream-ordered, returns without waiting.  The result
+ * is bitwise that of pf_nn_increment_scale (same kernels, same reduction
+ * order).
+ * Scratch: the 1024 FP64 block partials live in a static device array of the
+ * library (8 KiB per GPU, held until the process ends); each call overwrites
+ * all of it before reading it.  Calls that overlap on one GPU (other streams
+ * or threads) share that array and race: serialise them.
+ * Errors: PF_ERR_INVALID_ARG for NULL arrays or s_dev, sizes < 1, or
+ * (nx+1)(ny+1)(nz+1) above 2^31 - 1; PF_ERR_HIP if there is no current device
+ * or a launch fails.  Messages via pf_nn_last_error(NULL). */
+pf_status pf_increment_scale_static(const double *const *u1, const double *const *u0, int nx, int ny, int nz,
+                                    double *s_dev, void *hip_stream);
+
 /* Pack the crop [x0, x0+cx) x [y0, y0+cy) x [z0, z0+cz) of a state into volume
  * `slot` of the input buffer (voxels outside the grid get zero), with the
  * scale of the last pf_nn_increment_scale: previous increment u1 - u0; when u2

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "pf_nn.h"
 
@@ -670,6 +671,10 @@ pf_status pf_nn_layer(pf_nn* nn, int op, int layer, const void* in, const void* 
   }
 }
 
+// The increment scale's reduction: kStaticScaleBlocks FP64 partials, then one block.
+constexpr int kStaticScaleBlocks = 1024;
+constexpr long long kStaticScaleMaxCells = (1LL << 31) - 1;   // largest (nx+1)(ny+1)(nz+1) of the static variant
+
 pf_status pf_nn_increment_scale(pf_nn* nn, const double* const* u1, const double* const* u0, int nx, int ny, int nz,
                                 double* s_out) {
   if (!nn) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "nn is NULL");
@@ -681,7 +686,7 @@ pf_status pf_nn_increment_scale(pf_nn* nn, const double* const* u1, const double
     a.u0[d] = xview_face(u0 ? u0[d] : nullptr, d, nx, ny);
   }
   a.nx = nx; a.ny = ny; a.nz = nz;
-  const int nblk = 1024;
+  const int nblk = kStaticScaleBlocks;
   hipLaunchKernelGGL((pfn::k_incr_sumsq<double>), dim3(nblk), dim3(pfn::CNT), 0, nn->stream, a, nn->dpart);
   hipLaunchKernelGGL(pfn::k_incr_scale, dim3(1), dim3(pfn::CNT), 0, nn->stream, (const double*)nn->dpart, nblk,
                      3.0 * nx * (double)ny * nz, nn->dscal);
@@ -690,6 +695,62 @@ pf_status pf_nn_increment_scale(pf_nn* nn, const double* const* u1, const double
     NNCHK(nn, hipMemcpyAsync(s_out, nn->dscal, sizeof(double), hipMemcpyDeviceToHost, nn->stream));
     NNCHK(nn, hipStreamSynchronize(nn->stream));
   }
+  return PF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Increment scale without any allocation: the block partials and nothing else
+// live in this file-scope device array (one copy per GPU, held until the
+// process ends).  Host code never passes the array's name to a kernel: the
+// device address of each GPU's copy is looked up once, with that GPU
+// current, and kept per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kStaticScaleBlocks];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+static pf_status static_scratch(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return nn_fail(nullptr, PF_ERR_HIP, "no current HIP device (or device index >= %d)", kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return nn_fail(nullptr, PF_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = reinterpret_cast<double*>(g_scratch_ptr[dev]);
+  return PF_OK;
+}
+
+pf_status pf_increment_scale_static(const double* const* u1, const double* const* u0, int nx, int ny, int nz,
+                                    double* s_dev, void* hip_stream) {
+  if (!u1 || !u1[0] || !u1[1] || !u1[2]) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "u1 needs three device arrays");
+  if (u0 && (!u0[0] || !u0[1] || !u0[2])) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "u0 needs three device arrays or NULL");
+  if (!s_dev) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "s_dev is NULL");
+  if (nx < 1 || ny < 1 || nz < 1) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "grid sizes must be >= 1");
+  if (((long long)nx + 1) * ((long long)ny + 1) * ((long long)nz + 1) > kStaticScaleMaxCells)
+    return nn_fail(nullptr, PF_ERR_INVALID_ARG, "grid %dx%dx%d exceeds the %lld cells this entry point takes", nx, ny, nz,
+                   (long long)kStaticScaleMaxCells);
+  double* part = nullptr;
+  pf_status st = static_scratch(&part);
+  if (st != PF_OK) return st;
+  pfn::PackArgs<double> a{};
+  for (int d = 0; d < 3; ++d) {
+    a.u1[d] = xview_face(u1[d], d, nx, ny);
+    a.u0[d] = xview_face(u0 ? u0[d] : nullptr, d, nx, ny);
+  }
+  a.nx = nx; a.ny = ny; a.nz = nz;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // every block writes its partial, so nothing left by an earlier call is read
+  hipLaunchKernelGGL((pfn::k_incr_sumsq<double>), dim3(kStaticScaleBlocks), dim3(pfn::CNT), 0, stream, a, part);
+  hipLaunchKernelGGL(pfn::k_incr_scale, dim3(1), dim3(pfn::CNT), 0, stream, (const double*)part, kStaticScaleBlocks,
+                     3.0 * nx * (double)ny * nz, s_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return nn_fail(nullptr, PF_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
   return PF_OK;
 }
 

@@ -75,7 +75,7 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_c
            "pf_batch_fields", "pf_batch_step", "pf_batch_last_error", "pf_batch_destroy",
            "pf_nn_param_count", "pf_nn_init", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_weights", "pf_nn_copy",
            "pf_nn_forward", "pf_nn_loss", "pf_nn_backward", "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale",
-           "pf_nn_pack", "pf_nn_attach")
+           "pf_nn_pack", "pf_nn_attach", "pf_increment_scale_static")
 KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn")
 
 _lib = None
@@ -148,6 +148,8 @@ def lib():
         L.pf_nn_increment_scale.argtypes = [C.c_void_p, P3, P3] + [C.c_int] * 3 + [C.POINTER(C.c_double)]
         L.pf_nn_pack.argtypes = [C.c_void_p] + [C.c_void_p] * 3 + [P3] * 3 + [C.c_int] * 10 + [C.c_double] * 2
         L.pf_nn_attach.argtypes = [C.c_void_p, C.c_void_p]
+        L.pf_increment_scale_static.argtypes = [P3, P3] + [C.c_int] * 3 + [C.c_void_p, C.c_void_p]
+        L.pf_increment_scale_static.restype = C.c_int
         for f in ("pf_nn_init", "pf_nn_weights", "pf_nn_copy", "pf_nn_forward", "pf_nn_loss", "pf_nn_backward",
                   "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale", "pf_nn_pack", "pf_nn_attach"):
             getattr(L, f).restype = C.c_int
@@ -410,6 +412,19 @@ def _ptr3(arrs):
         return None
     a = (C.c_void_p * 3)(*[C.c_void_p(t.data_ptr()) for t in arrs])
     return C.cast(a, C.POINTER(C.c_void_p))
+
+
+def increment_scale_static(u1, u0, s_dev, stream=None):
+    """``pf_increment_scale_static``: RMS of u1 - u0 over the low faces into the
+    one-element FP64 device tensor ``s_dev``, without any allocation.  u1, u0:
+    three FP64 device tensors each (u0 may be None)."""
+    import torch
+    nz, ny, nx = u1[2].shape[0] - 1, u1[2].shape[1], u1[2].shape[2]
+    st = stream if stream is not None else torch.cuda.current_stream(s_dev.device)
+    rc = lib().pf_increment_scale_static(_ptr3(u1), _ptr3(u0), nx, ny, nz, C.c_void_p(s_dev.data_ptr()),
+                                         C.c_void_p(st.cuda_stream))
+    if rc != PF_OK:
+        raise PFError(rc, lib().pf_nn_last_error(None).decode())
 
 
 class Net:
