@@ -2,18 +2,21 @@
 """Throughput of the coupled phase-field step on one MI355X.
 
 One "step" is one call-level pass of the whole hot path: the mechanical
-equilibrium solve (Jacobi-PCG to the workload's tolerance, warm-started from
-the previous step), the J2 return map, the elastic / chemical driving forces,
-the fluxes and reaction, the explicit update of the five fields and the FP64
-ledger.  The default workload is the 128^3 core-shell recipe (wuestite sphere
-of radius 48 cells in a 4-cell ferrite shell, gas outside, +-0.01 noise,
-plasticity on, FP32 state with FP64 reductions, CG to 1e-6).
+equilibrium solve (Jacobi-PCG to the workload's tolerance), the J2 return
+map, the elastic / chemical driving forces, the fluxes and reaction, the
+explicit update of the five fields and the FP64 ledger.  The default workload
+is the 256^3 porous recipe (64 Voronoi grains, 20 % ellipsoidal pores lined
+with a 2-cell iron rim, plasticity on, Omega_f 0.2, FP32 arithmetic with FP64
+reductions, CG to 1e-6) with the learned warm start: the network is trained
+beforehand, untimed, on the plain method's trajectory of the 128^3 core-shell
+recipe only, then frozen.
 
 Prints ONE JSON line.  Besides the throughput it reports the dominant
-kernel's roofline figures (average launch duration measured with HIP events
-over the timed region), the same workload on the plain FP64 GPU path, the
-field / increment error of the mixed path against the FP64 CPU oracle on a
-small instance of the same recipe, and the oracle's own throughput on a
+kernel's roofline figures (average launch duration measured with HIP events),
+every stencil kernel's fraction of HBM peak, the same steps from the same
+state on the plain mixed path and on the plain FP64 GPU path, the field and
+increment error of the timed configuration against the FP64 CPU oracle on a
+reduced instance of the same recipe, and the oracle's own throughput on a
 bounded sample (``cpu_baseline``).
 """
 import argparse
@@ -39,7 +42,8 @@ def algorithmic_bytes_per_cell(kind, dim, es):
             return 7 * dim * es
         return 8 * dim * es    # read u, p, r, q, D^-1; write u, r, z (dim each)
     if kind == "step":         # read 5 fields, mu, u, eps_p, eps_P; write 5 fields, eps_p, eps_P
-        return (5 + 1 + dim + nc + 1 + 5 + nc + 1) * es
+        nf = 10 if es == 4 else 5  # FP32 state: each field is an FP32 pair (hi, lo)
+        return (nf + 1 + dim + nc + 1 + nf + nc + 1) * es
     if kind == "mu":           # read phi_f, phi_w, x_O; write mu
         return 4 * es
     if kind == "solve_setup":
@@ -120,62 +124,88 @@ def run_gpu(wl, precision, steps, warmup, timing, rtol, fields=None, net=None, e
     return {"seconds": t1 - t0, "stats": st, "cg_iters": st["cg_iters_total"] - it0, "kernels": rep}
 
 
-def accuracy_sample(n=32, steps=10, params=None):
-    """Mixed GPU path (with the learned start when trained parameters are
-    given) against the FP64 oracle on an n^3 instance of the recipe."""
+INCR_TOL = {"phi_f": 1e-3, "phi_w": 1e-3, "xO": 1e-4, "xH": 1e-4, "xW": 1e-3}
+FIELD_TOL = 1e-4
+
+
+def accuracy_sample(name, n, steps=10, params=None, settle=0):
+    """The timed configuration (mixed GPU path, CG 1e-6, with the learned start
+    when trained parameters are given) against the FP64 oracle solved to 1e-10
+    on an n^3 (or n^2) instance of the same recipe: per-field relative error
+    and the error of the increment over the run (absolute RMS where the
+    increment's RMS is below 1e-12, i.e. rounding noise)."""
     import numpy as np
     from paper_2111_11538_amd import inputs as I
     from paper_2111_11538_amd import pf
     from oracle import oracle as O
-    wl = I.workload("core_shell_3d", n=n)
-    g = pf.Context(3, wl.shape, wl.h, wl.dt, wl.params, precision="mixed", plasticity=True, cg_rtol=wl.cg_rtol,
-                   warm="learned" if params is not None else "prev")
+    wl = I.workload(name, n=n)
+    learned = params is not None and wl.dim == 3
+    g = pf.Context(wl.dim, wl.shape, wl.h, wl.dt, wl.params, precision=wl.precision, plasticity=wl.plasticity,
+                   cg_rtol=wl.cg_rtol, warm="learned" if learned else "prev")
     g.set_fields(wl.fields)
     net = None
-    if params is not None:
-        net = pf.Net(max_voxels=n ** 3)
+    if learned:
+        net = pf.Net(max_voxels=int(np.prod(wl.shape)))
         net.set_params(params)
         net.attach(g)
-    o = O.OracleSim(3, wl.shape, wl.h, wl.dt, wl.params, wl.fields, plasticity=True, cg_rtol=wl.cg_rtol)
+    o = O.OracleSim(wl.dim, wl.shape, wl.h, wl.dt, wl.params, wl.fields, plasticity=wl.plasticity, cg_rtol=1e-10)
+    iters, used = [], []
     for _ in range(steps):
-        g.step()
+        st = g.step()
         o.step()
+        iters.append(st["cg_iters"])
+        used.append(st["warm_used"])
     out = g.fields()
     g.close()
     if net is not None:
         net.close()
-    fe, ie = {}, {}
+    fe, ie, ok = {}, {}, True
     for k in ("phi_f", "phi_w", "xO", "xH", "xW"):
         b, a, b0 = o.f[k], out[k], wl.fields[k]
         rms = float(np.sqrt(np.mean(b * b)))
         fe[k] = float(np.linalg.norm(a - b) / np.linalg.norm(b)) if rms >= 1e-6 else float(np.sqrt(np.mean((a - b) ** 2)))
-        db = b - b0
-        ie[k] = float(np.linalg.norm((a - b0) - db) / np.linalg.norm(db)) if np.linalg.norm(db) > 0 else 0.0
-    ue = float(np.linalg.norm(out["uz"] - o.uz) / np.linalg.norm(o.uz))
-    return {"sample": f"{n}^3 core-shell recipe, {steps} steps, mixed GPU"
-                      f"{' with the learned start' if params is not None else ''} vs FP64 oracle",
-            "max_field_rel_err": max(fe.values()), "field_err": fe, "incr_rel_err": ie, "u_rel_err": ue}
+        db, da = b - b0, a - b0
+        if float(np.sqrt(np.mean(db * db))) < 1e-12:
+            ie[k] = {"abs_rms": float(np.sqrt(np.mean((da - db) ** 2)))}
+            ok &= ie[k]["abs_rms"] < 1e-15
+        else:
+            ie[k] = float(np.linalg.norm(da - db) / np.linalg.norm(db))
+            ok &= ie[k] < INCR_TOL[k]
+        ok &= fe[k] < FIELD_TOL
+    ue = float(np.linalg.norm(out["ux"] - o.ux) / np.linalg.norm(o.ux))
+    return {"sample": f"{name} {n}^{wl.dim} (reduced instance of the timed recipe), {steps} steps, mixed GPU, CG 1e-6"
+                      f"{', learned start' if learned else ''} vs FP64 oracle, CG 1e-10",
+            "max_field_rel_err": max(v for v in fe.values()), "field_err": fe, "incr_rel_err": ie, "u_rel_err": ue,
+            "gates": {"field": FIELD_TOL, "increment": INCR_TOL}, "within_gates": bool(ok),
+            "cg_iters": iters, "learned_used_steps": int(sum(1 for u in used if u == 2))}
 
 
-def cpu_baseline(n=64, steps=4):
-    """The FP64 oracle on a bounded sample: an n^3 instance of the core-shell
-    recipe, one untimed cold-start step, then `steps` timed warm-started steps."""
+def cpu_baseline(name, n, budget_s=15.0, max_steps=12):
+    """The FP64 oracle on a bounded sample: an n^3 (or n^2) instance of the
+    timed recipe, one untimed cold-start step, then warm-started steps until
+    about `budget_s` seconds have passed."""
     from paper_2111_11538_amd import inputs as I
     from oracle import oracle as O
-    wl = I.workload("core_shell_3d", n=n)
-    o = O.OracleSim(3, wl.shape, wl.h, wl.dt, wl.params, wl.fields, plasticity=True, cg_rtol=wl.cg_rtol)
+    wl = I.workload(name, n=n)
+    o = O.OracleSim(wl.dim, wl.shape, wl.h, wl.dt, wl.params, wl.fields, plasticity=wl.plasticity, cg_rtol=wl.cg_rtol)
     o.step()
     t0 = time.perf_counter()
-    st = None
-    iters = 0
-    for _ in range(steps):
+    steps, iters = 0, 0
+    while steps < max_steps and (time.perf_counter() - t0 < budget_s or steps < 2):
         st = o.step()
+        steps += 1
         iters += st["cg_iters"]
     dt = time.perf_counter() - t0
+    ncell = 1
+    for d in wl.shape:
+        ncell *= d
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    return {"value": n ** 3 * steps / dt, "unit": "voxel-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 C oracle (OpenMP), {n}^3 instance of the core-shell recipe, steps 2-{steps + 1} "
-                      f"(warm-started, {iters / steps:.0f} CG iterations/step), {dt:.1f} s"}
+    return {"value": ncell * steps / dt, "unit": "voxel-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 C oracle (OpenMP over cell loops; CG dot products serial), {name} "
+                      f"{'x'.join(str(x) for x in reversed(wl.shape))} (reduced instance of the timed recipe), "
+                      f"steps 2-{steps + 1} (warm-started, {iters / steps:.0f} CG iterations/step at rtol "
+                      f"{wl.cg_rtol:g}), {dt:.1f} s",
+            "cg_iters_per_step": iters / steps}
 
 
 BATCH_TRANSIENT_STEPS = 24
@@ -298,59 +328,83 @@ def time_train_iters(tn, recs, wl, args, n=20):
             "timed_with": f"HIP events on the network's stream around {n} iterations after training"}
 
 
-def train_learned(wl, args):
-    """Record the plain method's first solves of the recipe, train the network
-    on random 64^3 crops of them (offline, untimed) and return the state at the
-    end of the recording, an inference network holding the trained weights,
-    a summary and the weights."""
+def train_learned(args):
+    """Record the plain method's first solves of the training recipe (the
+    128^3 core-shell workload by default), train the network on random 64^3
+    crops of them (offline, untimed) and return the trained (then frozen)
+    parameters and a summary."""
     import numpy as np
     import torch
+    from paper_2111_11538_amd import inputs as I
     from paper_2111_11538_amd import pf, learned as LR
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    c = pf.Context(wl.dim, wl.shape, wl.h, wl.dt, wl.params, precision=wl.precision, plasticity=wl.plasticity,
-                   cg_rtol=wl.cg_rtol, warm="prev")
-    c.set_fields(wl.fields)
+    twl = I.workload(args.train_workload, n=args.train_n)
+    c = pf.Context(twl.dim, twl.shape, twl.h, twl.dt, twl.params, precision=twl.precision, plasticity=twl.plasticity,
+                   cg_rtol=twl.cg_rtol, warm="prev")
+    c.set_fields(twl.fields)
     t0 = time.perf_counter()
     recs = LR.record_trajectory(c, args.train_steps)
-    state = c.fields()
     c.close()
     t1 = time.perf_counter()
-    ncell = int(np.prod(wl.shape))
+    ncell = int(np.prod(twl.shape))
     tn = pf.Net(max_voxels=max(args.train_batch * 64 ** 3, ncell), training=True, seed=1)
     LR.init_extrapolation(tn)
-    held = recs[-4:]                 # solves 22 and 23 are held out (2 more give their history)
-    v0 = float(np.mean(LR.evaluate(tn, held, wl.params.Omega_f, wl.h)))
-    losses = LR.train(tn, recs[:-2], args.train_iters, wl.params.Omega_f, wl.h, crop=(64, 64, 64), batch=args.train_batch,
-                      lr=args.train_lr, t_min=5, log=log, log_every=100, val_recs=held, eval_every=25)
-    v1 = float(np.mean(LR.evaluate(tn, held, wl.params.Omega_f, wl.h)))
+    held = recs[-4:]                 # the last 2 recorded solves are held out (2 more give their history)
+    v0 = float(np.mean(LR.evaluate(tn, held, twl.params.Omega_f, twl.h)))
+    losses = LR.train(tn, recs[:-2], args.train_iters, twl.params.Omega_f, twl.h, crop=(64, 64, 64),
+                      batch=args.train_batch, lr=args.train_lr, t_min=5, log=log, log_every=500, val_recs=held,
+                      eval_every=25)
+    v1 = float(np.mean(LR.evaluate(tn, held, twl.params.Omega_f, twl.h)))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     params = tn.params()
-    train_roof = time_train_iters(tn, recs[:-2], wl, args)   # the training net's weights are not used after this
+    train_roof = time_train_iters(tn, recs[:-2], twl, args)   # the training net's weights are not used after this
     tn.close()
-    net = pf.Net(max_voxels=ncell)
-    net.set_params(params)
-    info = {"recorded_solves": args.train_steps, "record_s": round(t1 - t0, 2), "iters": args.train_iters,
+    del recs
+    torch.cuda.empty_cache()
+    info = {"trained_on": f"{twl.name} {'x'.join(str(x) for x in reversed(twl.shape))} (plain method, previous-step "
+                          f"start), solves 0-{args.train_steps - 1}; frozen before the timed workload",
+            "record_s": round(t1 - t0, 2), "iters": args.train_iters,
             "batch": f"{args.train_batch} crops of 64^3", "train_s": round(t2 - t1, 2),
             "loss_first_last_50": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
             "held_out_full_grid_loss_extrapolation_init": v0, "held_out_full_grid_loss_trained": v1,
-            "early_stopping": "best held-out full-grid loss over checkpoints every 25 iterations",
-            "cg_iters_per_step_recorded": [r["cg_iters"] for r in recs], "roofline": train_roof}
-    return state, net, info, params
+            "early_stopping": "best held-out full-grid loss (last 2 recorded solves) over checkpoints every 25 iterations",
+            "roofline": train_roof}
+    return params, info
+
+
+def settle(wl, steps):
+    """The common starting state of every timed leg: the recipe's initial
+    condition advanced `steps` untimed steps by the plain mixed path with the
+    previous-step start (past the cold first solves)."""
+    from paper_2111_11538_amd import pf
+    c = pf.Context(wl.dim, wl.shape, wl.h, wl.dt, wl.params, precision=wl.precision, plasticity=wl.plasticity,
+                   cg_rtol=wl.cg_rtol, warm="prev")
+    c.set_fields(wl.fields)
+    st = c.step(steps) if steps > 0 else c.step(0)
+    state = c.fields()
+    c.close()
+    return state, st
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="core_shell_3d")
+    ap.add_argument("--workload", default="porous_3d")
     ap.add_argument("--n", type=int, default=None, help="grid side override (reduced runs)")
+    ap.add_argument("--settle", type=int, default=10,
+                    help="untimed steps from the initial condition (previous-step start) before every timed leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--acc-n", type=int, default=None, help="side of the accuracy sample (default 48 in 3D, 256 in 2D)")
+    ap.add_argument("--cpu-n", type=int, default=None, help="side of the CPU baseline sample (default 64 in 3D, 512 in 2D)")
     ap.add_argument("--warm", default="learned", choices=("learned", "prev"),
-                    help="CG start of the timed run (learned: network trained first on the recipe's own trajectory)")
+                    help="CG start of the timed run (learned: network trained first, on the training recipe)")
+    ap.add_argument("--train-workload", default="core_shell_3d", help="recipe whose trajectory trains the network")
+    ap.add_argument("--train-n", type=int, default=128, help="grid side of the training recipe")
     ap.add_argument("--train-steps", type=int, default=24, help="recorded solves for training")
     ap.add_argument("--train-iters", type=int, default=3000,
                     help="Adam iterations of the network's training (early stopping keeps the best held-out checkpoint)")
@@ -380,16 +434,23 @@ def main():
     copy_peak = measure_copy_peak()
 
     from paper_2111_11538_amd import inputs as I
+    from paper_2111_11538_amd import pf
     wl = I.workload(args.workload, n=args.n)
     ncell = 1
-    for s in wl.shape:
-        ncell *= s
+    for d in wl.shape:
+        ncell *= d
     es = 4 if wl.precision == "mixed" else 8
 
     learned = args.warm == "learned" and wl.dim == 3
-    start, net, train_info, params = None, None, None, None
+    params, train_info, net = None, None, None
     if learned:
-        start, net, train_info, params = train_learned(wl, args)
+        print(f"[bench] training on {args.train_workload} at {args.train_n}", file=sys.stderr, flush=True)
+        params, train_info = train_learned(args)
+    print(f"[bench] settling {wl.name} {wl.shape}: {args.settle} steps", file=sys.stderr, flush=True)
+    start, st_settle = settle(wl, args.settle)
+    if learned:
+        net = pf.Net(max_voxels=ncell)
+        net.set_params(params)
     # per-kernel times: a replay of the same steps from the same state with
     # HIP events attached to every dispatch (each timed dispatch then follows
     # a timed one, which keeps the events' own overhead out of the kernel's
@@ -406,36 +467,49 @@ def main():
     avg_s = tot_ms / 1e3 / max(nl, 1)
     bytes_per_launch = algorithmic_bytes_per_cell(dom, wl.dim, es) * ncell
     achieved = bytes_per_launch / avg_s / 1e9
-    if dom == "nn":
-        bytes_per_launch = 0.0
     tag = f"{wl.name}_{wl.shape[0]}_{'learned' if learned else 'prev'}"
     traffic, traffic_src = profiled_traffic(tag, dom, wl.dim, es)
-    kernels = {k: {"total_ms": round(v[0], 3), "launches": v[1],
-                   "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None,
-                   "GBps_algorithmic": (round(algorithmic_bytes_per_cell(k, wl.dim, es) * ncell / (v[0] / 1e3 / v[1]) / 1e9, 1)
-                                        if v[1] and algorithmic_bytes_per_cell(k, wl.dim, es) > 0 else None)}
-               for k, v in kern.items()}
+    kernels = {}
+    for k, v in kern.items():
+        b = algorithmic_bytes_per_cell(k, wl.dim, es) * ncell
+        gbs = b / (v[0] / 1e3 / v[1]) / 1e9 if v[1] and b > 0 else None
+        kernels[k] = {"total_ms": round(v[0], 3), "launches": v[1],
+                      "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None,
+                      "bytes_per_launch": b or None,
+                      "GBps_algorithmic": round(gbs, 1) if gbs else None,
+                      "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4) if gbs else None,
+                      "frac_of_copy": round(gbs / copy_peak, 4) if gbs else None}
+    stencils = {k: kernels[k]["frac_of_8TBps"] for k in ("apply", "step", "mu", "solve_setup") if kernels[k]["frac_of_8TBps"]}
 
+    warm_txt = "previous step"
+    if learned:
+        warm_txt = (f"learned (network trained only on {args.train_workload} at {args.train_n}^3, solves "
+                    f"0-{args.train_steps - 1}, then frozen; judged against the previous step)")
     line = {
         "metric": "voxel-steps/s at <=1e-4 rel err vs FP64 oracle; % of HBM peak; CG iters/step",
         "value": value, "unit": "voxel-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 state + f64 reductions" if wl.precision == "mixed" else "f64",
+        "dtype": "f32 arithmetic, f32-pair state, f64 reductions" if wl.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name} {'x'.join(str(s) for s in reversed(wl.shape))}, plasticity on, "
-                               f"CG rtol {wl.cg_rtol:g}, warm start = "
-                               + (f"learned (trained on solves 0-{args.train_steps - 1} of this recipe, timed on the "
-                                  f"following steps; judged against the previous step)" if learned else "previous step"),
+        "config": {"workload": f"{wl.name} {'x'.join(str(x) for x in reversed(wl.shape))}, "
+                               f"plasticity {'on' if wl.plasticity else 'off'}, Omega_f {wl.params.Omega_f:g}, "
+                               f"CG rtol {wl.cg_rtol:g}, warm start = {warm_txt}; timed after {args.settle} + "
+                               f"{args.warmup} untimed steps",
                    "cells": ncell, "dt_s": wl.dt, "h_m": wl.h},
         "cg_iters_per_step": res["cg_iters"] / args.steps,
+        "cg_rel_resid_last": res["stats"]["cg_rel_resid"],
+        "cg_resid_note": ("CG stops on the recursive residual at rtol; cg_rel_resid_last is the true "
+                          "||b - A u|| / ||b|| of the last solve, recomputed after it (in FP32 arithmetic the "
+                          "true residual of the FP32 iterate levels off near 1e-5)"),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "timed_with": ("HIP events attached to every dispatch (hipExtLaunchKernel) in a replay of "
                                     "the timed steps from the same state; the throughput run carries no events"),
                      "launches_timed": nl, "replay_cg_iters_per_step": brk["cg_iters"] / args.steps,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_source": traffic_src,
-                     "torch_copy_GBps": round(copy_peak, 1),
+                     "torch_copy_GBps": round(copy_peak, 1), "frac_of_copy": round(achieved / copy_peak, 4),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2)},
+        "stencil_kernels_frac_of_8TBps": stencils,
         "kernels": kernels,
         "kernels_note": "HIP events attached to every dispatch, in a replay of the timed steps from the same state",
     }
@@ -449,25 +523,28 @@ def main():
                                    "traffic": None, "flop_per_launch": NN_FLOP_PER_VOXEL * ncell,
                                    "avg_launch_us": round(avg * 1e6, 2)}
         line["training"] = train_info
-        warm_used = res["stats"].get("warm_used")
-        line["learned_last_step"] = {"warm_used": warm_used, "r0_learned": res["stats"]["r0_learned"],
+        line["learned_last_step"] = {"warm_used": res["stats"].get("warm_used"), "r0_learned": res["stats"]["r0_learned"],
                                      "r0_prev": res["stats"]["r0_prev"]}
+        net.close()
         rp = run_gpu(wl, wl.precision, args.steps, args.warmup, False, wl.cg_rtol, fields=start)
         line["plain_mixed_gpu"] = {"value": ncell * args.steps / rp["seconds"], "ms_per_step": 1e3 * rp["seconds"] / args.steps,
                                    "cg_iters_per_step": rp["cg_iters"] / args.steps,
                                    "note": "same state and steps, previous-step start"}
-        net.close()
+        line["learned_speedup_vs_plain_mixed"] = value / line["plain_mixed_gpu"]["value"]
     if not args.no_fp64:
-        r64 = run_gpu(wl, "fp64", max(4, args.steps // 2), args.warmup, False, wl.cg_rtol, fields=start)
         s64 = max(4, args.steps // 2)
+        r64 = run_gpu(wl, "fp64", s64, args.warmup, False, wl.cg_rtol, fields=start)
         line["fp64_gpu"] = {"value": ncell * s64 / r64["seconds"], "ms_per_step": 1e3 * r64["seconds"] / s64,
-                            "cg_iters_per_step": r64["cg_iters"] / s64}
+                            "cg_iters_per_step": r64["cg_iters"] / s64,
+                            "note": f"plain FP64 GPU path, previous-step start, same state, {s64} steps"}
+        line["speedup_vs_fp64_gpu"] = value / line["fp64_gpu"]["value"]
     if not args.no_accuracy:
         print("[bench] accuracy sample", file=sys.stderr, flush=True)
-        line["accuracy"] = accuracy_sample(params=params)
+        acc_n = args.acc_n or (48 if wl.dim == 3 else 256)
+        line["accuracy"] = accuracy_sample(wl.name, acc_n, params=params)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(wl.name, args.cpu_n or (64 if wl.dim == 3 else 512))
     print(json.dumps(line), flush=True)
 
 
