@@ -258,7 +258,7 @@ def run_batch(args):
         "metric": "voxel-steps/s at <=1e-4 rel err vs FP64 oracle; % of HBM peak; CG iters/step",
         "value": cells * args.steps / sec, "unit": "voxel-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 state + f64 reductions", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32 arithmetic, f32-pair state, f64 reductions", "data": "synthetic",
         "config": {"workload": f"batch of {len(shapes)} 2D core-shell instances, sides U{{64..512}}, plasticity on, "
                                f"CG rtol 1e-06, one persistent graph launch per step, timed after "
                                f"{BATCH_TRANSIENT_STEPS + args.warmup + 1} untimed steps", "cells": cells},

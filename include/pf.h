@@ -133,9 +133,15 @@ pf_status pf_init(const pf_config *cfg, const pf_params *params, void *workspace
 
 /* Advance `nsteps` explicit steps (Section 2.4 field relations; each step:
  * equilibrium solve with phi^n and eps_p^n, return map, driving forces,
- * fluxes and reaction, explicit Euler update, FP64 ledger).  Synchronises the
- * stream once at the end; `last` (nullable) receives the stats of the last
- * step.  After an error the context is in BAD_STATE until fields are set. */
+ * fluxes and reaction, explicit Euler update, FP64 ledger).  The CG
+ * recurrence scalars and the convergence test live on the device; the host
+ * reads the convergence flag once per chunk of queued CG launches (a stream
+ * synchronisation per chunk, see pf_cg_chunk: launches queued past
+ * convergence exit at entry) and once at the end; `last` (nullable)
+ * receives the stats of the last step.  In PF_MIXED the solve stops when the
+ * recursive residual reaches cg_rtol; cg_rel_resid reports the true residual
+ * recomputed afterwards, which for an FP32 iterate levels off near 1e-5.
+ * After an error the context is in BAD_STATE until fields are set. */
 pf_status pf_step(pf_ctx *ctx, int nsteps, pf_step_stats *last);
 
 /* Solve only the mechanical equilibrium (Eq. 29 line 4) for the current phase
@@ -298,10 +304,21 @@ typedef enum { PF_NN_BUF_INPUT = 0, PF_NN_BUF_OUTPUT = 1, PF_NN_BUF_TARGET = 2, 
 /* Number of FP32 parameters (63 171). */
 size_t pf_nn_param_count(void);
 
-/* Create a network; the library allocates and owns its device memory
- * (about 224 bytes per voxel of capacity, 384 with training buffers). */
-pf_status pf_nn_init(const pf_nn_config *cfg, void *hip_stream, pf_nn **out);
-void pf_nn_destroy(pf_nn *nn);
+/* Bytes of device workspace a network with this configuration needs (about
+ * 224 bytes per voxel of capacity, 384 with training buffers, plus the
+ * parameters, their gradients, Adam moments and operand images); 0 if the
+ * configuration is invalid. */
+size_t pf_nn_workspace_bytes(const pf_nn_config *cfg);
+
+/* Create a network.  `workspace` is a caller-owned device pointer (256-byte
+ * aligned) to at least pf_nn_workspace_bytes(cfg) bytes, kept alive until
+ * pf_nn_destroy; the library carves every device buffer of the network out of
+ * it and allocates no device memory.  `hip_stream` is a hipStream_t (NULL =
+ * default stream).  Errors: PF_ERR_INVALID_ARG (NULL or misaligned pointers,
+ * max_voxels < 1), PF_ERR_OOM (workspace too small), PF_ERR_HIP. */
+pf_status pf_nn_init(const pf_nn_config *cfg, void *workspace, size_t workspace_bytes, void *hip_stream,
+                     pf_nn **out);
+void pf_nn_destroy(pf_nn *nn);            /* frees the host object only, never the workspace */
 const char *pf_nn_last_error(const pf_nn *nn);
 
 /* Parameters to (dir 0) or from (dir 1) the host, or the gradients of the

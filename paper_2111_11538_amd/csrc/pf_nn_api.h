@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 
 #include "pf_nn.h"
 
@@ -444,11 +445,61 @@ extern "C" {
 
 size_t pf_nn_param_count(void) { return nn_param_count(); }
 
-pf_status pf_nn_init(const pf_nn_config* cfg, void* hip_stream, pf_nn** out) {
+// Carve every device buffer of a network out of one caller-owned workspace
+// (256-byte aligned pieces).  With base == nullptr only the size is computed.
+static size_t nn_layout(pf_nn* nn, const pf_nn_config* cfg, char* base) {
+  const size_t cap = (size_t)cfg->max_voxels;
+  size_t off = 0;
+  auto take = [&](auto*& p, size_t bytes) {
+    using P = std::remove_reference_t<decltype(p)>;
+    if (base) p = reinterpret_cast<P>(base + off);
+    off += (std::max<size_t>(bytes, 256) + 255) / 256 * 256;
+  };
+  const size_t np = nn_param_count();
+  pf_nn tmp{};
+  pf_nn* t = nn ? nn : &tmp;
+  take(t->P, np * 4);
+  take(t->G, np * 4);
+  take(t->M, np * 4);
+  take(t->V, np * 4);
+  for (int l = 0; l < kLayers; ++l) {
+    take(t->img_f[l], (size_t)kDef[l].mb * kchunks(kDef[l].cinp) * 1024);
+    if (kDef[l].kinb) take(t->img_b[l], (size_t)2 * kchunks(kDef[l].kinb) * 1024);
+    take(t->bias_p[l], 32 * 4);
+  }
+  take(t->x0, cap * 8 * 2);
+  for (int q = 0; q < 3; ++q) take(t->act[q], cap * 32 * 2);
+  take(t->out, cap * 4 * 4);
+  take(t->dscal, 1024 * 8);
+  take(t->dpart, (size_t)std::max(kBgradBlocks * 32, 4096) * 8 * 2);
+  if (cfg->training) {
+    take(t->target, cap * 4 * 4);
+    take(t->dpred, cap * 8 * 2);
+    take(t->g[0], cap * 32 * 2);
+    take(t->g[1], cap * 32 * 2);
+    take(t->wpart, (size_t)kWgradSplitMax * pfn::kTaps * 32 * 32 * 4);
+  }
+  return off;
+}
+
+static bool nn_carve(pf_nn* nn, const pf_nn_config* cfg, char* base, size_t bytes) {
+  if (!base || nn_layout(nullptr, cfg, nullptr) > bytes) return false;
+  nn_layout(nn, cfg, base);
+  return true;
+}
+
+size_t pf_nn_workspace_bytes(const pf_nn_config* cfg) {
+  if (!cfg || cfg->max_voxels < 1) return 0;
+  return nn_layout(nullptr, cfg, nullptr);
+}
+
+pf_status pf_nn_init(const pf_nn_config* cfg, void* workspace, size_t workspace_bytes, void* hip_stream, pf_nn** out) {
   if (!out) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!cfg) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "config is NULL");
   if (cfg->max_voxels < 1) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "max_voxels must be >= 1");
+  if (!workspace) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return nn_fail(nullptr, PF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   pf_nn* nn = new (std::nothrow) pf_nn();
   if (!nn) return nn_fail(nullptr, PF_ERR_OOM, "host allocation failed");
   nn->cfg = *cfg;
@@ -462,36 +513,10 @@ pf_status pf_nn_init(const pf_nn_config* cfg, void* hip_stream, pf_nn** out) {
     nn->off_b[l] = off;
     off += kDef[l].cout;
   }
-  const size_t cap = (size_t)nn->cap;
-  bool ok = true;
-  auto alloc = [&](auto*& p, size_t bytes) {
-    if (!ok) return;
-    if (hipMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(bytes, 256)) != hipSuccess) { ok = false; p = nullptr; }
-  };
-  alloc(nn->P, nn->np * 4);
-  alloc(nn->G, nn->np * 4);
-  alloc(nn->M, nn->np * 4);
-  alloc(nn->V, nn->np * 4);
-  for (int l = 0; l < kLayers; ++l) {
-    alloc(nn->img_f[l], (size_t)kDef[l].mb * kchunks(kDef[l].cinp) * 1024);
-    if (kDef[l].kinb) alloc(nn->img_b[l], (size_t)2 * kchunks(kDef[l].kinb) * 1024);
-    alloc(nn->bias_p[l], 32 * 4);
-  }
-  alloc(nn->x0, cap * 8 * 2);
-  for (int q = 0; q < 3; ++q) alloc(nn->act[q], cap * 32 * 2);
-  alloc(nn->out, cap * 4 * 4);
-  alloc(nn->dscal, 1024 * 8);
-  alloc(nn->dpart, (size_t)std::max(kBgradBlocks * 32, 4096) * 8 * 2);
-  if (cfg->training) {
-    alloc(nn->target, cap * 4 * 4);
-    alloc(nn->dpred, cap * 8 * 2);
-    alloc(nn->g[0], cap * 32 * 2);
-    alloc(nn->g[1], cap * 32 * 2);
-    alloc(nn->wpart, (size_t)kWgradSplitMax * pfn::kTaps * 32 * 32 * 4);
-  }
-  if (!ok) {
-    pf_nn_destroy(nn);
-    return nn_fail(nullptr, PF_ERR_OOM, "device allocation failed");
+  if (!nn_carve(nn, cfg, reinterpret_cast<char*>(workspace), workspace_bytes)) {
+    const size_t need = pf_nn_workspace_bytes(cfg);
+    delete nn;
+    return nn_fail(nullptr, PF_ERR_OOM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
   }
 
   // He-uniform initialisation from SplitMix64; the output layer is scaled by 0.1
@@ -525,16 +550,7 @@ pf_status pf_nn_init(const pf_nn_config* cfg, void* hip_stream, pf_nn** out) {
 void pf_nn_destroy(pf_nn* nn) {
   if (!nn) return;
   (void)hipStreamSynchronize(nn->stream);
-  void* ptrs[] = {nn->P, nn->G, nn->M, nn->V, nn->x0, nn->act[0], nn->act[1], nn->act[2], nn->out, nn->target,
-                  nn->dpred, nn->g[0], nn->g[1], nn->wpart, nn->dpart, nn->dscal};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  for (int l = 0; l < kLayers; ++l) {
-    if (nn->img_f[l]) (void)hipFree(nn->img_f[l]);
-    if (nn->img_b[l]) (void)hipFree(nn->img_b[l]);
-    if (nn->bias_p[l]) (void)hipFree(nn->bias_p[l]);
-  }
-  delete nn;
+  delete nn;                       // the device workspace belongs to the caller
 }
 
 const char* pf_nn_last_error(const pf_nn* nn) { return nn ? nn->err : g_nn_err; }

@@ -73,7 +73,7 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_c
            "pf_timing", "pf_timing_every", "pf_timing_get", "pf_last_error", "pf_destroy",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_set_tiles", "pf_batch_get_tiles",
            "pf_batch_fields", "pf_batch_step", "pf_batch_last_error", "pf_batch_destroy",
-           "pf_nn_param_count", "pf_nn_init", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_weights", "pf_nn_copy",
+           "pf_nn_param_count", "pf_nn_workspace_bytes", "pf_nn_init", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_weights", "pf_nn_copy",
            "pf_nn_forward", "pf_nn_loss", "pf_nn_backward", "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale",
            "pf_nn_pack", "pf_nn_attach", "pf_increment_scale_static")
 KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn")
@@ -133,7 +133,9 @@ def lib():
         P3 = C.POINTER(C.c_void_p)
         L.pf_nn_param_count.argtypes = []
         L.pf_nn_param_count.restype = C.c_size_t
-        L.pf_nn_init.argtypes = [C.POINTER(pf_nn_config), C.c_void_p, C.POINTER(C.c_void_p)]
+        L.pf_nn_workspace_bytes.argtypes = [C.POINTER(pf_nn_config)]
+        L.pf_nn_workspace_bytes.restype = C.c_size_t
+        L.pf_nn_init.argtypes = [C.POINTER(pf_nn_config), C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
         L.pf_nn_destroy.argtypes = [C.c_void_p]
         L.pf_nn_destroy.restype = None
         L.pf_nn_last_error.argtypes = [C.c_void_p]
@@ -441,7 +443,12 @@ class Net:
         cfg.max_voxels, cfg.training, cfg.seed = int(max_voxels), int(training), int(seed)
         self.nn = C.c_void_p()
         L = lib()
-        rc = L.pf_nn_init(C.byref(cfg), C.c_void_p(self.stream.cuda_stream), C.byref(self.nn))
+        nbytes = L.pf_nn_workspace_bytes(C.byref(cfg))
+        if nbytes == 0:
+            raise PFError(PF_ERR_INVALID_ARG, "invalid network configuration")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        rc = L.pf_nn_init(C.byref(cfg), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                          C.c_void_p(self.stream.cuda_stream), C.byref(self.nn))
         if rc != PF_OK:
             raise PFError(rc, L.pf_nn_last_error(None).decode())
         self.n_params = L.pf_nn_param_count()

@@ -108,3 +108,21 @@ def test_batch_workspace_validation(lib):
     rc = lib.pf_batch_init(C.byref(cfg), C.byref(prm), ext_of([(8, 8)] * 257), 257, None, 0, None, C.byref(b))
     assert rc == pf.PF_ERR_INVALID_ARG and not b.value
     assert b"count" in lib.pf_batch_last_error(None)
+
+
+def test_network_workspace_size(lib):
+    """pf_nn_workspace_bytes is host arithmetic: it grows with the capacity
+    (about 224 bytes per voxel, 384 with training buffers) and is 0 for an
+    invalid configuration."""
+    from paper_2111_11538_amd import pf
+    c = pf.pf_nn_config()
+    c.max_voxels, c.training = 0, 0
+    assert lib.pf_nn_workspace_bytes(C.byref(c)) == 0
+    sizes = {}
+    for tr in (0, 1):
+        for cap in (4096, 8192):
+            c.max_voxels, c.training = cap, tr
+            sizes[tr, cap] = lib.pf_nn_workspace_bytes(C.byref(c))
+    assert 220 * 4096 <= sizes[0, 8192] - sizes[0, 4096] <= 230 * 4096
+    assert 380 * 4096 <= sizes[1, 8192] - sizes[1, 4096] <= 390 * 4096
+    assert all(v % 256 == 0 for v in sizes.values())

@@ -364,3 +364,26 @@ def test_pack_matches_oracle(net):
     assert exact > 0.999, exact
     np.testing.assert_allclose(got, want, rtol=2.0 ** -7, atol=0)
     np.testing.assert_allclose(gt, wt.astype(np.float32).astype(np.float64), rtol=1e-6, atol=1e-7)
+
+
+def test_network_lives_in_the_callers_workspace():
+    """pf_nn_init carves the network out of the caller's workspace: a workspace
+    one byte short or misaligned is refused, an exact one works."""
+    import ctypes
+    torch = _torch()
+    from paper_2111_11538_amd import pf
+    L = pf.lib()
+    cfg = pf.pf_nn_config()
+    cfg.max_voxels, cfg.training, cfg.seed = 4096, 1, 3
+    nb = L.pf_nn_workspace_bytes(ctypes.byref(cfg))
+    ws = torch.empty(nb + 512, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    base = ws.data_ptr()
+    assert L.pf_nn_init(ctypes.byref(cfg), ctypes.c_void_p(base), nb - 1, st, ctypes.byref(h)) == pf.PF_ERR_OOM
+    assert L.pf_nn_init(ctypes.byref(cfg), ctypes.c_void_p(base + 16), nb, st, ctypes.byref(h)) == pf.PF_ERR_INVALID_ARG
+    assert L.pf_nn_init(ctypes.byref(cfg), ctypes.c_void_p(base), nb, st, ctypes.byref(h)) == pf.PF_OK
+    w = np.zeros(L.pf_nn_param_count(), dtype=np.float32)
+    assert L.pf_nn_weights(h, 0, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size) == pf.PF_OK
+    assert np.any(w != 0)
+    L.pf_nn_destroy(h)
