@@ -39,7 +39,7 @@ class OrConfig(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("h", C.c_double), ("dt", C.c_double),
                 ("mechanics", C.c_int), ("plasticity", C.c_int), ("dirichlet", C.c_int), ("chem_phase", C.c_int),
-                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("pad_", C.c_int)]
+                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("species_implicit", C.c_int)]
 
 
 _P = C.POINTER(C.c_double)
@@ -135,7 +135,8 @@ class OracleSim:
     """One simulation held in numpy FP64 arrays and advanced by the C oracle."""
 
     def __init__(self, dim, shape, h, dt, params, fields, mechanics=True, plasticity=False, dirichlet=True,
-                 chem_phase=True, cg_rtol=1e-10, cg_max_iter=200000, u=None, epsp=None, epsP=None):
+                 chem_phase=True, cg_rtol=1e-10, cg_max_iter=200000, u=None, epsp=None, epsP=None,
+                 implicit=False):
         self.dim = dim
         self.shape = tuple(shape)
         cfg = OrConfig()
@@ -148,6 +149,7 @@ class OracleSim:
         cfg.h, cfg.dt = h, dt
         cfg.mechanics, cfg.plasticity, cfg.dirichlet, cfg.chem_phase = int(mechanics), int(plasticity), int(dirichlet), int(chem_phase)
         cfg.cg_rtol, cfg.cg_max_iter = cg_rtol, cg_max_iter
+        cfg.species_implicit = int(implicit)
         self.cfg = cfg
         self.params = params
         self.cp = make_params(params)

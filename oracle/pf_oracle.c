@@ -784,6 +784,94 @@ void or_simplex_project(double *phi_f, double *phi_w) {
   *phi_w = fmax(u[2] - theta, 0.0);
 }
 
+/* Linearly implicit Euler for one species.  The increment d of a step
+ * solves (I + dt A) d = t, where t = dt T(x^n) is the explicit increment (the
+ * full fluxes and reaction at x^n) and A = -div(D grad .) is the linear part
+ * of the species' diffusion with the two-cell mean D at interior faces and,
+ * where `dirichlet` is set, the half-cell boundary faces (D of the cell,
+ * distance h/2).  Backward Euler for the stiff diffusion (Sec. 2.4 uses
+ * backward Euler for the species), explicit for the rest.  Plain
+ * Jacobi-preconditioned CG from d = 0 to ||t - (I + dt A) d|| <= 1e-13 ||t||,
+ * sums in lexicographic order. */
+static void species_op(const or_config *c, const double *D, int dirichlet, const double *v, double *out) {
+  int nx = c->nx, ny = c->ny, nz = c->nz;
+  double ih2 = 1.0 / (c->h * c->h), dt = c->dt;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        long q = CI(c, i, j, k);
+        int cc[3] = {i, j, k}, lim[3] = {nx, ny, nz};
+        double a = 0.0;
+        for (int d = 0; d < c->dim; ++d)
+          for (int side = -1; side <= 1; side += 2) {
+            int nb[3] = {i, j, k};
+            nb[d] += side;
+            if (nb[d] < 0 || nb[d] >= lim[d]) {
+              if (dirichlet) a += 2.0 * D[q] * v[q] * ih2;
+              continue;
+            }
+            long r = CI(c, nb[0], nb[1], nb[2]);
+            a -= 0.5 * (D[q] + D[r]) * (v[r] - v[q]) * ih2;
+          }
+        (void)cc;
+        out[q] = v[q] + dt * a;
+      }
+}
+
+static int species_solve(const or_config *c, const double *D, int dirichlet, const double *t, double *d) {
+  long n = ncell(c);
+  int nx = c->nx, ny = c->ny, nz = c->nz;
+  double ih2 = 1.0 / (c->h * c->h), dt = c->dt;
+  double *dg = malloc(n * sizeof(double)), *r = malloc(n * sizeof(double)), *z = malloc(n * sizeof(double));
+  double *pv = malloc(n * sizeof(double)), *qv = malloc(n * sizeof(double));
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        long q = CI(c, i, j, k);
+        int lim[3] = {nx, ny, nz};
+        double a = 0.0;
+        for (int dd = 0; dd < c->dim; ++dd)
+          for (int side = -1; side <= 1; side += 2) {
+            int nb[3] = {i, j, k};
+            nb[dd] += side;
+            if (nb[dd] < 0 || nb[dd] >= lim[dd]) {
+              if (dirichlet) a += 2.0 * D[q] * ih2;
+              continue;
+            }
+            a += 0.5 * (D[q] + D[CI(c, nb[0], nb[1], nb[2])]) * ih2;
+          }
+        dg[q] = 1.0 / (1.0 + dt * a);
+      }
+  double tt = dot3(t, t, n);
+  for (long q = 0; q < n; ++q) {
+    d[q] = 0.0;
+    r[q] = t[q];
+    z[q] = dg[q] * r[q];
+    pv[q] = z[q];
+  }
+  int status = OR_OK;
+  if (tt > 0.0) {
+    double rz = dot3(r, z, n);
+    int it = 0;
+    while (dot3(r, r, n) > 1e-26 * tt) {
+      if (++it > 100000) { status = OR_CG_NOT_CONVERGED; break; }
+      species_op(c, D, dirichlet, pv, qv);
+      double alpha = rz / dot3(pv, qv, n);
+      for (long q = 0; q < n; ++q) {
+        d[q] += alpha * pv[q];
+        r[q] -= alpha * qv[q];
+        z[q] = dg[q] * r[q];
+      }
+      double rz1 = dot3(r, z, n);
+      double beta = rz1 / rz;
+      rz = rz1;
+      for (long q = 0; q < n; ++q) pv[q] = z[q] + beta * pv[q];
+    }
+  }
+  free(dg); free(r); free(z); free(pv); free(qv);
+  return status;
+}
+
 int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, or_stats *st) {
   if (c->dim != 2 && c->dim != 3) return OR_INVALID;
   if (c->nx < 1 || c->ny < 1 || c->nz < 1 || (c->dim == 2 && c->nz != 1)) return OR_INVALID;
@@ -908,10 +996,37 @@ int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, 
         nf_[q] = s->phi_f[q] + dt * p->L[0] * ((p->eps[0] + p->eps[1]) * lf + p->eps[1] * lw - gf[q]);
         nw_[q] = s->phi_w[q] + dt * p->L[2] * ((p->eps[2] + p->eps[1]) * lw + p->eps[1] * lf - gw[q]);
         or_simplex_project(&nf_[q], &nw_[q]);
-        nO[q] = s->xO[q] + dt * (-divO - r);
-        nH[q] = s->xH[q] + dt * (-divH - 2.0 * r);
-        nW[q] = s->xW[q] + dt * (-divW + r);
+        /* the explicit increments of the species; added below (explicit) or
+         * taken as the right-hand sides of the implicit solves */
+        nO[q] = dt * (-divO - r);
+        nH[q] = dt * (-divH - 2.0 * r);
+        nW[q] = dt * (-divW + r);
       }
+
+  if (c->species_implicit) {
+    double *DO = malloc(n * sizeof(double)), *dx = malloc(n * sizeof(double));
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          long q = CI(c, i, j, k);
+          local_t L;
+          local_eval(p, s->phi_f[q], s->phi_w[q], s->xO[q], &L);
+          DO[q] = L.DO;
+        }
+    double *tx[3] = {nO, nH, nW};
+    const double *Dc[3] = {DO, DH, DW};
+    for (int sp = 0; sp < 3; ++sp) {
+      int rc = species_solve(c, Dc[sp], sp > 0 && c->dirichlet, tx[sp], dx);
+      if (rc != OR_OK) status = rc;
+      memcpy(tx[sp], dx, n * sizeof(double));
+    }
+    free(DO); free(dx);
+  }
+  for (long q = 0; q < n; ++q) {
+    nO[q] += s->xO[q];
+    nH[q] += s->xH[q];
+    nW[q] += s->xW[q];
+  }
 
   /* (4) boundary outflux for the ledger (lexicographic over faces) */
   double outO = 0.0, outH = 0.0;
@@ -924,8 +1039,11 @@ int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, 
           for (int d = 0; d < c->dim; ++d) {
             int nb = (cc[d] == 0) + (cc[d] == lim[d] - 1);   /* boundary faces of this cell on axis d */
             if (!nb) continue;
-            double jw = 2.0 * DW[q] * (s->xW[q] - p->xW_bc) / h;   /* outward flux */
-            double jh = 2.0 * DH[q] * (s->xH[q] - p->xH_bc) / h;
+            /* outward flux, with the values the update used at the face: x^n
+             * (explicit) or x^(n+1) (implicit) */
+            double xw = c->species_implicit ? nW[q] : s->xW[q], xh = c->species_implicit ? nH[q] : s->xH[q];
+            double jw = 2.0 * DW[q] * (xw - p->xW_bc) / h;
+            double jh = 2.0 * DH[q] * (xh - p->xH_bc) / h;
             outO += nb * jw;
             outH += nb * (jh + 2.0 * jw);
           }

@@ -43,7 +43,7 @@ typedef struct {
   int chem_phase;      /* chemical energy drives the phase fields (1, the model) */
   double cg_rtol;
   int cg_max_iter;
-  int pad_;
+  int species_implicit; /* 0: explicit Euler for the species; 1: linearly implicit Euler (or_step) */
 } or_config;
 
 typedef struct {

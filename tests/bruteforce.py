@@ -180,7 +180,36 @@ class Mech:
 # ---------------------------------------------------------------------------
 # One full step (2D or 3D) on whole arrays
 # ---------------------------------------------------------------------------
-def step(dim, shape, h, dt, p, f, u, epsp, epsP, plasticity=True, dirichlet=True):
+def implicit_matrix(coef, dt, h, dirichlet):
+    """Dense I + dt A for one species on the (nz, ny, nx) grid, assembled face
+    by face: every interior face between cells a and b with the mean
+    diffusivity couples them with weight D_face / h^2; a Dirichlet boundary
+    face adds 2 D_cell / h^2 to its cell."""
+    shp = coef.shape
+    n = coef.size
+    A = np.zeros((n, n))
+    idx = np.arange(n).reshape(shp)
+    for ax in range(3):
+        m = shp[ax]
+        if m == 1:
+            continue
+        for c in np.ndindex(*shp):
+            a = idx[c]
+            if c[ax] + 1 < m:
+                nb = list(c)
+                nb[ax] += 1
+                b = idx[tuple(nb)]
+                w = 0.5 * (coef[c] + coef[tuple(nb)]) / h ** 2
+                A[a, a] += w
+                A[b, b] += w
+                A[a, b] -= w
+                A[b, a] -= w
+            if dirichlet and (c[ax] == 0 or c[ax] == m - 1):
+                A[a, a] += 2 * coef[c] / h ** 2 * ((c[ax] == 0) + (c[ax] == m - 1))
+    return np.eye(n) + dt * A
+
+
+def step(dim, shape, h, dt, p, f, u, epsp, epsP, plasticity=True, dirichlet=True, implicit=False):
     """Returns new (fields, u, epsp, epsP).  Arrays use (nz, ny, nx) shapes
     (2D: nz = 1); epsp is (6, nz, ny, nx)."""
     pf, pw, xO, xH, xW = (f[k] for k in ("phi_f", "phi_w", "xO", "xH", "xW"))
@@ -274,11 +303,17 @@ def step(dim, shape, h, dt, p, f, u, epsp, epsP, plasticity=True, dirichlet=True
     lf, lw = lap(pf), lap(pw)
     nf, nw = simplex(pf + dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf),
                      pw + dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw))
+    inc = {"xO": dt * (-divO - r), "xH": dt * (-divH - 2 * r), "xW": dt * (-divW + r)}
+    if implicit:
+        # linearly implicit Euler: (I + dt A) d = dt T(x^n), A the species' diffusion
+        for key, coef, bc in (("xO", DO, False), ("xH", DHh, dirichlet), ("xW", DWw, dirichlet)):
+            M = implicit_matrix(coef, dt, h, bc)
+            inc[key] = np.linalg.solve(M, inc[key].ravel()).reshape(inc[key].shape)
     out = {
         "phi_f": nf,
         "phi_w": nw,
-        "xO": xO + dt * (-divO - r),
-        "xH": xH + dt * (-divH - 2 * r),
-        "xW": xW + dt * (-divW + r),
+        "xO": xO + inc["xO"],
+        "xH": xH + inc["xH"],
+        "xW": xW + inc["xW"],
     }
     return out, (ux, uy, uz), new_epsp, new_epsP

@@ -21,14 +21,17 @@ def _random_fields(shape, seed):
             "xW": rng.uniform(0.0, 0.05, shape)}
 
 
-@pytest.mark.parametrize("dim,n,nsteps,kind", [(2, 8, 4, "core_shell"), (2, 8, 3, "random"),
-                                               (3, 4, 2, "core_shell"), (3, 4, 2, "random")])
-def test_oracle_matches_bruteforce(oracle, dim, n, nsteps, kind):
+@pytest.mark.parametrize("dim,n,nsteps,kind,implicit", [(2, 8, 4, "core_shell", False), (2, 8, 3, "random", False),
+                                                        (3, 4, 2, "core_shell", False), (3, 4, 2, "random", False),
+                                                        (2, 8, 3, "core_shell", True), (2, 8, 3, "random", True),
+                                                        (3, 4, 2, "random", True)])
+def test_oracle_matches_bruteforce(oracle, dim, n, nsteps, kind, implicit):
     p = I.Params()
     h = I.H_DEFAULT
     # a larger time step than the explicit bound of the gas is fine for a
-    # handful of steps and makes every term visible above rounding
-    dt = 2 * I.stable_dt(p, h, dim)
+    # handful of steps and makes every term visible above rounding; the
+    # implicit species update takes 50 times that
+    dt = (100 if implicit else 2) * I.stable_dt(p, h, dim)
     shape = (n,) * dim
     if kind == "random":
         f = _random_fields(shape, 100 + dim)
@@ -38,7 +41,8 @@ def test_oracle_matches_bruteforce(oracle, dim, n, nsteps, kind):
     else:
         f = I.ic_core_shell(shape, r_core=1.2, r_shell=1.8, noise_seed=12)
         f["xW"] = 0.05 * f["xH"]
-    sim = oracle.OracleSim(dim, shape, h, dt, p, f, mechanics=True, plasticity=True, dirichlet=True, cg_rtol=1e-14)
+    sim = oracle.OracleSim(dim, shape, h, dt, p, f, mechanics=True, plasticity=True, dirichlet=True, cg_rtol=1e-14,
+                           implicit=implicit)
     # brute-force state with a leading z axis in 2D
     bshape = (1, n, n) if dim == 2 else shape
     bf = {k: f[k].reshape(bshape).copy() for k in ("phi_f", "phi_w", "xO", "xH", "xW")}
@@ -49,7 +53,7 @@ def test_oracle_matches_bruteforce(oracle, dim, n, nsteps, kind):
         before = {k: sim.f[k].reshape(bshape).copy() for k in bf}
         st = sim.step()
         assert st["cg_rel_resid"] < 1e-12
-        bf, (ux, uy, uz), epsp, epsP = BF.step(dim, shape, h, dt, p, bf, None, epsp, epsP)
+        bf, (ux, uy, uz), epsp, epsP = BF.step(dim, shape, h, dt, p, bf, None, epsp, epsP, implicit=implicit)
         scale_u = np.max(np.abs(ux))
         assert np.max(np.abs(sim.ux.reshape(ux.shape) - ux)) < 1e-10 * scale_u
         assert np.max(np.abs(sim.uy.reshape(uy.shape) - uy)) < 1e-10 * scale_u

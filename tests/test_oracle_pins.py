@@ -650,3 +650,122 @@ def test_lever_rule(oracle):
         printed = (xbar - I.X_F_PRINTED) / (I.X_W_PRINTED - I.X_F_PRINTED)
         assert abs(ext - lever) < 0.01, (xbar, ext, lever)
         assert abs(ext - printed) > 0.05, (xbar, ext, printed)
+
+
+# ---------------------------------------------------------------------------
+# Linearly implicit species update (backward Euler for the diffusion)
+# ---------------------------------------------------------------------------
+def _mode_fields(shape, k, key, base, amp, **vals):
+    f = _uniform_fields(shape, **vals)
+    nx = shape[-1]
+    i = np.arange(nx) + 0.5
+    f[key] = base + amp * np.cos(np.pi * k * i / nx) * np.ones(shape)
+    return f
+
+
+def test_implicit_hydrogen_mode_decays_by_the_backward_euler_factor(oracle):
+    """Pure gas, closed box, no reaction: a cosine mode of x_H (an exact
+    eigenvector of the no-flux Laplacian, eigenvalue lambda = (4/h^2)
+    sin^2(pi k / 2N)) is multiplied per step by exactly 1 / (1 + dt D lambda),
+    at a time step 200 times the explicit limit."""
+    p = I.Params(kfor=0.0)
+    h = I.H_DEFAULT
+    shape = (4, 32)
+    D = p.DH[1]
+    dt = 200 * h * h / (4 * D)
+    for k in (1, 5):
+        f = _mode_fields(shape, k, "xH", 0.01, 0.002, phi_f=0.0, phi_w=0.0)
+        s = _sim(oracle, 2, shape, h, dt, p, f, mechanics=False, dirichlet=False, implicit=True)
+        lam = 4 / h ** 2 * math.sin(math.pi * k / (2 * shape[-1])) ** 2
+        for _ in range(3):
+            a0 = s.f["xH"] - 0.01
+            s.step()
+            a1 = s.f["xH"] - 0.01
+            fac = np.sum(a1 * a0) / np.sum(a0 * a0)
+            assert abs(fac - 1 / (1 + dt * D * lam)) < 1e-10, (k, fac)
+            assert np.max(np.abs(a1 - fac * a0)) < 1e-12 * np.max(np.abs(a0))
+
+
+def test_implicit_oxygen_mode_factor(oracle):
+    """Pure wuestite (quadratic free energy, constant M_O = D_O / psi_xx): a
+    cosine mode of x_O has explicit tendency -(D lambda + M kappa lambda^2) a;
+    with the diffusion implicit the factor per step is exactly
+    1 - dt (D lambda + M kappa lambda^2) / (1 + dt D lambda)."""
+    p = I.Params(kfor=0.0)
+    h = I.H_DEFAULT
+    shape = (3, 40)
+    k = 3
+    D = p.DO[2]
+    psi_xx = p.R * p.theta / p.Vmol * 2 * 173.263
+    M = D / psi_xx
+    lam = 4 / h ** 2 * math.sin(math.pi * k / (2 * shape[-1])) ** 2
+    dt = 50 * h * h / (4 * D)
+    f = _mode_fields(shape, k, "xO", 0.5, 0.01, phi_w=1.0)
+    s = _sim(oracle, 2, shape, h, dt, p, f, mechanics=False, dirichlet=False, implicit=True)
+    want = 1 - dt * (D * lam + M * p.kappaO * lam ** 2) / (1 + dt * D * lam)
+    for _ in range(3):
+        a0 = s.f["xO"] - 0.5
+        s.step()
+        a1 = s.f["xO"] - 0.5
+        fac = np.sum(a1 * a0) / np.sum(a0 * a0)
+        assert abs(fac - want) < 1e-10 * abs(want), (fac, want)
+
+
+@pytest.mark.parametrize("dirichlet", [False, True])
+def test_implicit_species_conserve_oxygen_and_hydrogen(oracle, dirichlet):
+    """The implicit solve only redistributes (no-flux faces) or exchanges
+    through the boundary faces the ledger accounts for, at 100 times the
+    explicit time step."""
+    wl = I.workload("core_shell_2d", n=24)
+    s = _sim(oracle, 2, wl.shape, wl.h, 100 * wl.dt, wl.params, wl.fields, mechanics=True, plasticity=True,
+             dirichlet=dirichlet, cg_rtol=1e-10, implicit=True)
+    O0 = (s.f["xO"] + s.f["xW"]).sum()
+    for _ in range(10):
+        st = s.step()
+        assert abs(st["O_drift"]) < 1e-12
+        assert abs(st["H_drift"]) < 1e-12
+    if not dirichlet:
+        assert abs((s.f["xO"] + s.f["xW"]).sum() - O0) < 1e-12 * O0
+    else:
+        assert st["H_out"] < 0
+
+
+def test_implicit_matches_explicit_to_first_order(oracle):
+    """Over a fixed time the implicit and explicit updates differ by O(dt):
+    halving the step halves the difference."""
+    wl = I.workload("core_shell_2d", n=24)
+    T = 32 * wl.dt
+    diffs = []
+    for m in (8, 4, 2):
+        dt = wl.dt * m / 8                      # at most the explicit step
+        runs = []
+        for implicit in (False, True):
+            s = _sim(oracle, 2, wl.shape, wl.h, dt, wl.params, wl.fields, mechanics=False, dirichlet=True,
+                     implicit=implicit)
+            s.step(int(round(T / dt)))
+            runs.append(s.f["xH"] - wl.fields["xH"])
+        diffs.append(np.linalg.norm(runs[1] - runs[0]) / np.linalg.norm(runs[0]))
+    assert diffs[0] < 0.2
+    assert 1.7 < diffs[0] / diffs[1] < 2.3 and 1.7 < diffs[1] / diffs[2] < 2.3, diffs
+
+
+def test_implicit_is_stable_far_beyond_the_explicit_limit(oracle):
+    """At 1000 times the explicit gas-diffusion limit the implicit update of a
+    Gaussian of x_H in gas stays bounded and positive and conserves it; the
+    explicit update at the same step diverges."""
+    p = I.Params(kfor=0.0)
+    h = I.H_DEFAULT
+    n = 32
+    shape = (n, n)
+    yy, xx = np.meshgrid(np.arange(n) - n / 2 + 0.5, np.arange(n) - n / 2 + 0.5, indexing="ij")
+    f = _uniform_fields(shape, phi_f=0.0, phi_w=0.0)
+    f["xH"] = 0.01 * np.exp(-(xx ** 2 + yy ** 2) / 8)
+    dt = 1000 * h * h / (4 * p.DH[1])
+    s = _sim(oracle, 2, shape, h, dt, p, f, mechanics=False, dirichlet=False, implicit=True)
+    m0 = s.f["xH"].sum()
+    s.step(5)
+    assert np.all(np.isfinite(s.f["xH"])) and s.f["xH"].min() > 0 and s.f["xH"].max() <= 0.01
+    assert abs(s.f["xH"].sum() - m0) < 1e-12 * m0
+    e = _sim(oracle, 2, shape, h, dt, p, f, mechanics=False, dirichlet=False, implicit=False)
+    e.step(5)
+    assert not np.all(np.abs(e.f["xH"]) < 1.0)
