@@ -81,6 +81,9 @@ typedef struct {
   int cg_max_iter;        /* reaching it is an error */
   int warm;               /* pf_warm: start of each step's solve */
   double ledger_tol;      /* |O drift| above this raises PF_ERR_LEDGER; <= 0 disables */
+  int species_implicit;   /* 0: explicit Euler for x_O, x_H, x_H2O; 1: linearly implicit Euler (see pf_step) */
+  int species_max_iter;   /* implicit species: CG iteration limit per step (reaching it is an error) */
+  double species_rtol;    /* implicit species: stop each species' CG at ||r|| <= species_rtol ||b|| */
 } pf_config;
 
 /* Material and model parameters, Table 1 of the paper; phase index 0 ferrite,
@@ -116,6 +119,8 @@ typedef struct {
   long long cg_iters_total;   /* CG iterations summed over every solve since pf_init */
   double r0_learned;      /* learned start: ||b - A u0|| / ||b|| of the network's start, 0 if not evaluated */
   double r0_prev;         /* learned start: the same for the previous displacement, 0 if not evaluated */
+  int species_iters;      /* implicit species: the most CG iterations any species took in the last step */
+  int pad2_;
 } pf_step_stats;
 
 /* Bytes of device workspace pf_init needs for this configuration (0 if the
@@ -131,9 +136,17 @@ size_t pf_workspace_bytes(const pf_config *cfg);
 pf_status pf_init(const pf_config *cfg, const pf_params *params, void *workspace, size_t workspace_bytes,
                   void *hip_stream, pf_ctx **out);
 
-/* Advance `nsteps` explicit steps (Section 2.4 field relations; each step:
+/* Advance `nsteps` steps (Section 2.4 field relations; each step:
  * equilibrium solve with phi^n and eps_p^n, return map, driving forces,
- * fluxes and reaction, explicit Euler update, FP64 ledger).  The CG
+ * fluxes and reaction, explicit Euler update, FP64 ledger).  With
+ * species_implicit the species take a linearly implicit Euler step instead
+ * (Sec. 2.4 uses backward Euler for them): the increment d of x_O, x_H and
+ * x_H2O solves (I + dt A) d = dt T(x^n), T the explicit tendency (every flux
+ * and the reaction at x^n), A = -div(D grad .) the species' diffusion with
+ * the two-cell mean D at interior faces and, for x_H and x_H2O, the half-cell
+ * Dirichlet faces; each species is solved by Jacobi-PCG to species_rtol.
+ * This removes the gas-diffusion limit on dt; the phase fields stay
+ * explicit.  The CG
  * recurrence scalars and the convergence test live on the device; the host
  * reads the convergence flag once per chunk of queued CG launches (a stream
  * synchronisation per chunk, see pf_cg_chunk: launches queued past
@@ -182,7 +195,8 @@ typedef enum {
   PF_K_OTHER = 5,     /* moduli, convergence checks, ledger (small kernels), and the
                          CG launches queued past convergence, which exit at once */
   PF_K_NN = 6,        /* the four convolutions of a learned-start inference (one group per solve) */
-  PF_K_COUNT = 7
+  PF_K_SPECIES = 7,   /* implicit species: set-up, apply, update and final update of their CG */
+  PF_K_COUNT = 8
 } pf_kernel_kind;
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
@@ -239,8 +253,9 @@ typedef struct {
 size_t pf_batch_workspace_bytes(const pf_config *cfg, const pf_extent *ext, int count);
 
 /* Create a batch.  Same ownership rules as pf_init; every instance starts at
- * zero.  Requires dim == 2, mechanics == 1 and warm == PF_WARM_PREV (the
- * first step of an instance starts its solve from u = 0). */
+ * zero.  Requires dim == 2, mechanics == 1, warm == PF_WARM_PREV (the
+ * first step of an instance starts its solve from u = 0) and explicit
+ * species (species_implicit == 0; PF_ERR_UNSUPPORTED otherwise). */
 pf_status pf_batch_init(const pf_config *cfg, const pf_params *params, const pf_extent *ext, int count,
                         void *workspace, size_t workspace_bytes, void *hip_stream, pf_batch **out);
 

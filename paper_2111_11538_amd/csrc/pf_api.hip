@@ -14,6 +14,7 @@
 
 #include "../../include/pf.h"
 #include "pf_kernels.h"
+#include "pf_species.h"
 
 using namespace pfk;
 
@@ -56,6 +57,10 @@ struct Layout {
   size_t o_phiprev_lo;                  // learned start, FP32 state: low part of phi_prev
   size_t o_dsq;                          // learned start: partials of the increment's sum of squares
   size_t o_b[3];                        // 3D: right-hand side b of the equilibrium solve
+  // implicit species: per species D, D^-1, r, z, two directions, q and the increment
+  size_t o_sp[8][3];
+  size_t o_sp_part, o_sp_scal;
+  int nb_sp;
   size_t total;
 };
 
@@ -69,6 +74,8 @@ bool valid_cfg(const pf_config* c, char* msg, size_t len) {
   if (c->mechanics && (!(c->cg_rtol > 0.0) || c->cg_max_iter < 1)) { snprintf(msg, len, "cg_rtol > 0 and cg_max_iter >= 1 required"); return false; }
   if (c->warm != PF_WARM_ZERO && c->warm != PF_WARM_PREV && c->warm != PF_WARM_LEARNED) { snprintf(msg, len, "unknown warm start %d", c->warm); return false; }
   if (c->warm == PF_WARM_LEARNED && (c->dim != 3 || !c->mechanics)) { snprintf(msg, len, "the learned warm start needs dim 3 and mechanics"); return false; }
+  if (c->species_implicit != 0 && c->species_implicit != 1) { snprintf(msg, len, "species_implicit must be 0 or 1"); return false; }
+  if (c->species_implicit && (!(c->species_rtol > 0.0) || c->species_max_iter < 1)) { snprintf(msg, len, "species_rtol > 0 and species_max_iter >= 1 required"); return false; }
   long long px = (c->nx + 15) / 16 * 16;
   if (px * c->ny * (long long)c->nz >= (1LL << 31) / 8) { snprintf(msg, len, "grid too large for 32-bit indexing"); return false; }
   return true;
@@ -150,6 +157,13 @@ Layout make_layout(const pf_config* c) {
   L.o_part_c = take(NQ_STEP * (size_t)nbmax * sizeof(double));
   L.o_part_f = take(NQ_STEP * (size_t)kFoldBlocks * sizeof(double));
   L.o_stage = take(L.stage_elems * sizeof(double));
+  L.nb_sp = std::max(1, std::min(kSpBlocksMax, (g.n + NT - 1) / NT));
+  if (c->species_implicit) {
+    for (int a = 0; a < 8; ++a)
+      for (int q = 0; q < 3; ++q) L.o_sp[a][q] = take(arr);
+    L.o_sp_part = take(9 * (size_t)L.nb_sp * sizeof(double));
+    L.o_sp_scal = take(SP_COUNT * sizeof(double));
+  }
   if (c->warm == PF_WARM_LEARNED) {
     for (int d = 0; d < 3; ++d) { L.o_uo[d] = take(arr); L.o_du[d] = take(arr); }
     L.o_phiprev = take(arr);
@@ -214,6 +228,8 @@ struct pf_ctx {
   bool have_prev_incr;
   bool judged;             // the last solve evaluated the learned start
   double r0_learned, r0_prev;
+  int sp_last_iters;       // implicit species: the most CG iterations of a species in the last step
+  double* host_sp;         // pinned copy of the species scalars
   template <typename T> T* arr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   double* scal() const { return arr<double>(L.o_scal); }
 };
@@ -333,6 +349,11 @@ struct Impl {
       for (int f = 0; f < 5; ++f) {
         a.lo[f] = c->arr<T>(L.o_lo[s][f]);
         a.nlo[f] = c->arr<T>(L.o_lo[s ^ 1][f]);
+      }
+    if (c->cfg.species_implicit)
+      for (int q = 0; q < 3; ++q) {
+        a.sp_r[q] = c->arr<T>(L.o_sp[2][q]);
+        a.sp_D[q] = c->arr<T>(L.o_sp[0][q]);
       }
     a.mu = c->arr<T>(L.o_mu);
     a.mu_out = c->arr<T>(L.o_mu);
@@ -607,6 +628,64 @@ struct Impl {
     return PF_OK;
   }
 
+  static SpArgs<T> sp_args(pf_ctx* c) {
+    const Layout& L = c->L;
+    SpArgs<T> a{};
+    a.g = L.g;
+    a.dt_ih2 = (T)(c->cfg.dt / (c->cfg.h * c->cfg.h));
+    a.dirichlet = c->cfg.dirichlet;
+    for (int q = 0; q < 3; ++q) {
+      a.D[q] = c->arr<T>(L.o_sp[0][q]);
+      a.dinv[q] = c->arr<T>(L.o_sp[1][q]);
+      a.r[q] = c->arr<T>(L.o_sp[2][q]);
+      a.z[q] = c->arr<T>(L.o_sp[3][q]);
+      a.pa[q] = c->arr<T>(L.o_sp[4][q]);
+      a.pb[q] = c->arr<T>(L.o_sp[5][q]);
+      a.q[q] = c->arr<T>(L.o_sp[6][q]);
+      a.d[q] = c->arr<T>(L.o_sp[7][q]);
+    }
+    a.nb = L.nb_sp;
+    a.part_rr = c->arr<double>(L.o_sp_part);
+    a.part_pq = a.part_rr + 6 * (size_t)L.nb_sp;
+    a.sc = c->arr<double>(L.o_sp_scal);
+    a.tol2 = c->cfg.species_rtol * c->cfg.species_rtol;
+    return a;
+  }
+
+  // The three species' CG solves (I + dt A_s) d_s = b_s, side by side: every
+  // chunk of apply / update launches is followed by a convergence test the
+  // host reads (a synchronisation per chunk).
+  static pf_status species_solve(pf_ctx* c) {
+    const Layout& L = c->L;
+    hipStream_t st = c->stream;
+    SpArgs<T> a = sp_args(c);
+    timed_launch(c, PF_K_SPECIES, -1, k_sp_init<T, DIM>, dim3(L.nb_sp), dim3(NT), 0, st, a);
+    const int maxit = c->cfg.species_max_iter;
+    int it = 0;
+    int chunk = std::max(4, c->sp_last_iters + 1);
+    while (true) {
+      const int n = std::min(chunk, maxit - it);
+      for (int q = 0; q < n; ++q, ++it) {
+        a.it = it;
+        timed_launch(c, PF_K_SPECIES, -1, k_sp_apply<T, DIM>, dim3(L.nb_sp), dim3(NT), 0, st, a);
+        timed_launch(c, PF_K_SPECIES, -1, k_sp_update<T, DIM>, dim3(L.nb_sp), dim3(NT), 0, st, a);
+      }
+      hipLaunchKernelGGL(k_sp_check, dim3(1), dim3(NT), 0, st, (const double*)a.part_rr, L.nb_sp, a.sc, a.tol2, 0);
+      LAUNCHCHK(c);
+      HIPCHK(c, hipMemcpyAsync(c->host_sp, a.sc, SP_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipStreamSynchronize(st));
+      const double* h = c->host_sp;
+      if (h[SP_CONV] != 0.0 && h[SP_CONV + 1] != 0.0 && h[SP_CONV + 2] != 0.0) break;
+      if (it >= maxit)
+        return fail(c, PF_ERR_CG_NOT_CONVERGED, "implicit species CG did not reach rtol %.3g in %d iterations",
+                    c->cfg.species_rtol, maxit);
+      chunk = std::max(4, std::min(64, it / 4));
+    }
+    const double* h = c->host_sp;
+    c->sp_last_iters = (int)std::max(h[SP_ITERS], std::max(h[SP_ITERS + 1], h[SP_ITERS + 2]));
+    return PF_OK;
+  }
+
   static pf_status step_once(pf_ctx* c) {
     const Layout& L = c->L;
     if (!c->ledger_valid) {
@@ -621,6 +700,11 @@ struct Impl {
     a.part = c->arr<double>(L.o_part_c);
     timed_launch(c, PF_K_MU, -1, k_mu<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
     timed_launch(c, PF_K_STEP, -1, k_step<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
+    if (c->cfg.species_implicit) {
+      pf_status s = species_solve(c);
+      if (s != PF_OK) return s;
+      timed_launch(c, PF_K_SPECIES, -1, k_sp_finish<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a, sp_args(c));
+    }
     double vol = std::pow(c->cfg.h, DIM), area = std::pow(c->cfg.h, DIM - 1);
     const double* lp = a.part;
     int ln = L.nb_cell;
@@ -670,6 +754,7 @@ static void fill_stats(pf_ctx* c, pf_step_stats* s) {
   s->cg_iters_total = c->iters_total;
   s->r0_learned = c->r0_learned;
   s->r0_prev = c->r0_prev;
+  s->species_iters = c->sp_last_iters;
 }
 
 // ---------------------------------------------------------------------------
@@ -723,12 +808,14 @@ pf_status pf_init(const pf_config* cfg, const pf_params* params, void* workspace
   c->judged = false;
   c->r0_learned = 0.0;
   c->r0_prev = 0.0;
+  c->sp_last_iters = 0;
   for (int k = 0; k < PF_K_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_scal), S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_scal), (S_COUNT + SP_COUNT) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(nullptr, PF_ERR_HIP, "hipHostMalloc of the stats block failed");
   }
-  memset(c->host_scal, 0, S_COUNT * sizeof(double));
+  memset(c->host_scal, 0, (S_COUNT + SP_COUNT) * sizeof(double));
+  c->host_sp = c->host_scal + S_COUNT;
   hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {

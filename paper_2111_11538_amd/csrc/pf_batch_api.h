@@ -311,6 +311,7 @@ pf_status pf_batch_init(const pf_config* cfg, const pf_params* params, const pf_
   *out = nullptr;
   char msg[256];
   if (!valid_batch(cfg, ext, count, msg, sizeof msg)) return bfail(nullptr, PF_ERR_INVALID_ARG, "%s", msg);
+  if (cfg->species_implicit) return bfail(nullptr, PF_ERR_UNSUPPORTED, "batches step the species explicitly");
   if (!params) return bfail(nullptr, PF_ERR_INVALID_ARG, "params is NULL");
   if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign)
     return bfail(nullptr, PF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");

@@ -181,6 +181,14 @@ __device__ __forceinline__ void transport(const KP<T>& p, T pf, T pw, T x, T& mu
   DW = (hf * p.DW[0] + hg * p.DW[1] + hw * p.DW[2]) * ihs;
 }
 
+// Phase-weighted oxygen diffusivity (the D_O inside M_O = D_O / psi_xx).
+template <typename T>
+__device__ __forceinline__ T diffusivity_O(const KP<T>& p, T pf, T pw) {
+  T pg = T(1) - pf - pw;
+  T hf = interp_h(pf), hg = interp_h(pg), hw = interp_h(pw);
+  return (hf * p.DO[0] + hg * p.DO[1] + hw * p.DO[2]) / (hf + hg + hw);
+}
+
 template <typename T>
 __device__ __forceinline__ void transport_D(const KP<T>& p, T pf, T pw, T& DH, T& DW) {
   T pg = T(1) - pf - pw;

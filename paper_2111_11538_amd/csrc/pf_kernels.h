@@ -1563,6 +1563,12 @@ struct CellArgs {
   // arrays above), read and written by the field update; null in FP64
   const T* lo[5];
   T* nlo[5];
+  // linearly implicit species (null: explicit): the step writes the explicit
+  // increments dt T of x_O, x_H, x_H2O into sp_r and the cell diffusivities
+  // D_O, D_H, D_H2O of the implicit operator into sp_D; the species
+  // themselves are updated after the solve
+  T* sp_r[3];
+  T* sp_D[3];
   const T* u[3];
   T* epsp;
   T* epsP;
@@ -1700,7 +1706,7 @@ __device__ __forceinline__ void phase_bound(double& pf, double& pw) {
 template <typename T, int DIM>
 __device__ __forceinline__ void cell_update(const CellArgs<T>& a, int e, T pf, T pw, T xO, T xH, T xW, T lf, T lw,
                                             T divO, T divH, T divW, T bO, T bH, const T (&eb)[6],
-                                            const T (&lo)[5], double (&acc)[NQ_STEP]) {
+                                            const T (&lo)[5], T DHc, T DWc, double (&acc)[NQ_STEP]) {
   const Grid& g = a.g;
   const KP<T>& p = a.p;
   lf *= p.ih2;
@@ -1779,9 +1785,25 @@ __device__ __forceinline__ void cell_update(const CellArgs<T>& a, int e, T pf, T
   const T dW = p.dt * (-divW + r);
   double nf = field_new(pf, lo[0], df), nw = field_new(pw, lo[1], dw);
   phase_bound(nf, nw);
-  const double nO = field_new(xO, lo[2], dO), nH = field_new(xH, lo[3], dH), nW = field_new(xW, lo[4], dW);
   field_store(nf, a.npf, a.nlo[0], e);
   field_store(nw, a.npw, a.nlo[1], e);
+  acc[5] = (double)vm;
+  acc[6] = (double)epsPn;
+  if (a.sp_r[0]) {
+    // implicit species: right-hand sides and coefficients of the solve; the
+    // species' ledger terms come from the update that follows it
+    a.sp_r[0][e] = dO;
+    a.sp_r[1][e] = dH;
+    a.sp_r[2][e] = dW;
+    a.sp_D[0][e] = diffusivity_O(p, pf, pw);
+    a.sp_D[1][e] = DHc;
+    a.sp_D[2][e] = DWc;
+    acc[0] = acc[1] = acc[2] = acc[3] = acc[4] = 0.0;
+    const bool fin = isfinite(nf) && isfinite(nw) && isfinite(dO) && isfinite(dH) && isfinite(dW) && isfinite(vm);
+    acc[7] = fin ? 0.0 : 1.0;
+    return;
+  }
+  const double nO = field_new(xO, lo[2], dO), nH = field_new(xH, lo[3], dH), nW = field_new(xW, lo[4], dW);
   field_store(nO, a.nxO, a.nlo[2], e);
   field_store(nH, a.nxH, a.nlo[3], e);
   field_store(nW, a.nxW, a.nlo[4], e);
@@ -1790,8 +1812,6 @@ __device__ __forceinline__ void cell_update(const CellArgs<T>& a, int e, T pf, T
   acc[2] = nO;
   acc[3] = (double)bO;
   acc[4] = (double)bH + 2.0 * (double)bO;
-  acc[5] = (double)vm;
-  acc[6] = (double)epsPn;
   bool fin = isfinite(nf) && isfinite(nw) && isfinite(nO) && isfinite(nH) && isfinite(nW) && isfinite(vm);
   acc[7] = fin ? 0.0 : 1.0;
 }
@@ -1884,7 +1904,7 @@ __device__ __forceinline__ void step_tile(const CellArgs<T>& a, int bx, int by, 
                            shear_yz(g, uy, uz, i, j, k + 1, ih) + shear_yz(g, uy, uz, i, j + 1, k + 1, ih));
       }
     }
-    cell_update<T, DIM>(a, e, pf, pw, xO, xH, xW, lf, lw, divO, divH, divW, bO, bH, eb, lo, acc);
+    cell_update<T, DIM>(a, e, pf, pw, xO, xH, xW, lf, lw, divO, divH, divW, bO, bH, eb, lo, DHc, DWc, acc);
   }
   // the eight partials together: the wave trees of all quantities interleaved,
   // then one exchange across the waves (the same operations in the same

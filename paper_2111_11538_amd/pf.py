@@ -31,7 +31,8 @@ class pf_config(C.Structure):
                 ("precision", C.c_int), ("mechanics", C.c_int), ("plasticity", C.c_int),
                 ("dirichlet", C.c_int), ("chem_phase", C.c_int),
                 ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("warm", C.c_int),
-                ("ledger_tol", C.c_double)]
+                ("ledger_tol", C.c_double), ("species_implicit", C.c_int), ("species_max_iter", C.c_int),
+                ("species_rtol", C.c_double)]
 
 
 class pf_params(C.Structure):
@@ -63,10 +64,11 @@ class pf_step_stats(C.Structure):
                 ("H_tot", C.c_double), ("H_out", C.c_double), ("H_drift", C.c_double),
                 ("red_degree", C.c_double), ("max_vm", C.c_double), ("max_epsP", C.c_double),
                 ("step", C.c_longlong), ("nonfinite", C.c_int), ("pad_", C.c_int),
-                ("cg_iters_total", C.c_longlong), ("r0_learned", C.c_double), ("r0_prev", C.c_double)]
+                ("cg_iters_total", C.c_longlong), ("r0_learned", C.c_double), ("r0_prev", C.c_double),
+                ("species_iters", C.c_int), ("pad2_", C.c_int)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("pad")}
 
 
 EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_chunk", "pf_fields", "pf_ledger_reset",
@@ -76,7 +78,7 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_c
            "pf_nn_param_count", "pf_nn_workspace_bytes", "pf_nn_init", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_weights", "pf_nn_copy",
            "pf_nn_forward", "pf_nn_loss", "pf_nn_backward", "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale",
            "pf_nn_pack", "pf_nn_attach", "pf_increment_scale_static")
-KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn")
+KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn", "species")
 
 _lib = None
 
@@ -178,7 +180,8 @@ def make_params(p) -> pf_params:
 
 
 def make_config(dim, shape, h, dt, precision="fp64", mechanics=True, plasticity=False, dirichlet=True,
-                chem_phase=True, cg_rtol=1e-10, cg_max_iter=200000, warm="prev", ledger_tol=0.0) -> pf_config:
+                chem_phase=True, cg_rtol=1e-10, cg_max_iter=200000, warm="prev", ledger_tol=0.0,
+                species_implicit=False, species_rtol=None, species_max_iter=100000) -> pf_config:
     c = pf_config()
     c.dim = dim
     if dim == 2:
@@ -192,6 +195,9 @@ def make_config(dim, shape, h, dt, precision="fp64", mechanics=True, plasticity=
     c.cg_rtol, c.cg_max_iter = cg_rtol, cg_max_iter
     c.warm = WARM[warm]
     c.ledger_tol = ledger_tol
+    c.species_implicit = int(species_implicit)
+    c.species_max_iter = int(species_max_iter)
+    c.species_rtol = species_rtol if species_rtol is not None else (1e-12 if precision == "fp64" else 1e-6)
     return c
 
 
