@@ -992,7 +992,10 @@ int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, 
         lw *= ih2;
         local_t L;
         local_eval(p, s->phi_f[q], s->phi_w[q], s->xO[q], &L);
-        double r = s->xW[q] < 1.0 ? L.m[1] * p->kfor * s->xO[q] * s->xH[q] : 0.0;   /* Eq. 27, 28 */
+        /* Eq. 27, 28: forward rate k_for m(phi_g) x_O x_H, zero where the cell
+         * is full of water; mole fractions below zero (the variational O flux
+         * leaves the gas slightly below x_O = 0) take no part in it */
+        double r = s->xW[q] < 1.0 ? L.m[1] * p->kfor * fmax(s->xO[q], 0.0) * fmax(s->xH[q], 0.0) : 0.0;
         nf_[q] = s->phi_f[q] + dt * p->L[0] * ((p->eps[0] + p->eps[1]) * lf + p->eps[1] * lw - gf[q]);
         nw_[q] = s->phi_w[q] + dt * p->L[2] * ((p->eps[2] + p->eps[1]) * lw + p->eps[1] * lf - gw[q]);
         or_simplex_project(&nf_[q], &nw_[q]);

@@ -256,6 +256,33 @@ def ic_porous(shape, porosity: float, n_grains: int, seed: int, semi_min: float 
     return f
 
 
+def ic_pores(shape=(32, 48), radius: float = 3.0, iso_x: float = 6.0, open_x: float = 34.0,
+             channel_half: float = 1.0, prefill=None, prefill_rings: float = 1.0, x_w: float = X_W_EQ,
+             xH_gas: float = 0.01):
+    """Two pores in wuestite (the isolated and open pores of Sec. 4.3 on a
+    synthetic section): gas disks of `radius` cells centred at mid-height and
+    x = iso_x and x = open_x; the open one is joined to the right edge by a gas
+    channel of half-width `channel_half` cells (every outer face carries the
+    H-rich gas of the Dirichlet boundary), the isolated one is closed.  With
+    `prefill` = value, the isolated pore and `prefill_rings` rings of solid
+    around it start with x_H2O = value.  Returns the fields and the masks
+    "iso", "open" and "wet" (the prefilled cells)."""
+    ny, nx = shape
+    yy, xx = np.meshgrid(np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    yc = ny / 2
+    iso = (xx - iso_x) ** 2 + (yy - yc) ** 2 <= radius ** 2
+    opn = ((xx - open_x) ** 2 + (yy - yc) ** 2 <= radius ** 2) | ((xx >= open_x) & (np.abs(yy - yc) <= channel_half))
+    gas = iso | opn
+    f = _empty(shape)
+    f["phi_w"][~gas] = 1.0
+    f["xO"][~gas] = x_w
+    f["xH"][gas] = xH_gas
+    wet = (xx - iso_x) ** 2 + (yy - yc) ** 2 <= (radius + prefill_rings) ** 2
+    if prefill is not None:
+        f["xW"][wet] = prefill
+    return f, {"iso": iso, "open": opn, "wet": wet}
+
+
 def _voronoi_ids(shape, seeds):
     from scipy.spatial import cKDTree
     coords = _centres(shape)

@@ -299,7 +299,7 @@ def step(dim, shape, h, dt, p, f, u, epsp, epsP, plasticity=True, dirichlet=True
     divO = div_flux(MO, mu, None)
     divH = div_flux(DHh, xH, p.xH_bc if dirichlet else None)
     divW = div_flux(DWw, xW, p.xW_bc if dirichlet else None)
-    r = np.where(xW < 1, Mm[1] * p.kfor * xO * xH, 0.0)
+    r = np.where(xW < 1, Mm[1] * p.kfor * np.clip(xO, 0, None) * np.clip(xH, 0, None), 0.0)
     lf, lw = lap(pf), lap(pw)
     nf, nw = simplex(pf + dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf),
                      pw + dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw))

@@ -6,9 +6,8 @@ Tolerances: FP64 (both species solves to 1e-12 / 1e-13, the equilibrium solve
 to 1e-12) as the explicit FP64 parity: fields 1e-12 relative, increments 1e-6
 (they inherit the equilibrium solve's tolerance through the elastic driving
 force); mixed (species and equilibrium solves to 1e-6, oracle to 1e-10 / 1e-13):
-fields 1e-4, increments 1e-3 for phi_f, phi_w and x_H2O and 1e-4 for x_O, x_H,
-except that the species increments are held to 1e-4 through the implicit
-solve's own tolerance (1e-6) times its conditioning.
+fields 1e-4, increments 1e-3 for phi_f, phi_w and x_H2O and 1e-4 for x_O, x_H
+(the gates of the explicit mixed path); element by element 1e-4.
 """
 import sys
 

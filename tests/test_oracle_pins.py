@@ -769,3 +769,20 @@ def test_implicit_is_stable_far_beyond_the_explicit_limit(oracle):
     e = _sim(oracle, 2, shape, h, dt, p, f, mechanics=False, dirichlet=False, implicit=False)
     e.step(5)
     assert not np.all(np.abs(e.f["xH"]) < 1.0)
+
+
+def test_reaction_is_forward_only(oracle):
+    """The rate of Eq. 27 is a forward rate: a cell whose x_O or x_H is below
+    zero (the variational O flux leaves gas slightly below x_O = 0) does not
+    react, in either direction."""
+    p = I.Params(L=(0.0, 0.0, 0.0), DO=(0.0, 0.0, 0.0), DH=(0.0, 0.0, 0.0), DW=(0.0, 0.0, 0.0), kappaO=0.0)
+    for xO, xH in ((-0.01, 0.01), (0.3, -0.002), (-0.01, -0.01)):
+        f = _uniform_fields((4, 4), phi_f=0.25, phi_w=0.25, xO=xO, xH=xH, xW=0.1)
+        s = _sim(oracle, 2, (4, 4), I.H_DEFAULT, 1e-6, p, f, mechanics=False, dirichlet=False)
+        s.step(5)
+        for k in ("xO", "xH", "xW"):
+            assert np.array_equal(s.f[k], f[k]), (xO, xH, k)
+    f = _uniform_fields((4, 4), phi_f=0.25, phi_w=0.25, xO=0.3, xH=0.01, xW=0.1)
+    s = _sim(oracle, 2, (4, 4), I.H_DEFAULT, 1e-6, p, f, mechanics=False, dirichlet=False)
+    s.step()
+    assert np.all(s.f["xW"] > 0.1)                     # positive fractions do react
