@@ -272,6 +272,55 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def run_trends(args):
+    """The core-shell study of Sec. 4.2 over minutes of model time: a 2D
+    wuestite core (radius 24 cells, 1.9 um) in a 4-cell ferrite shell inside a
+    5 um gas box, advanced with the implicit species update and the reaction
+    solved exactly per cell (dt = 10 ms), for Omega_f in 0 ... 0.4 (elastic)
+    and 0.1, 0.4 (elasto-plastic); records the reduction degree (Eq. 39), the
+    largest von Mises stress and plastic strain over time."""
+    import torch
+    from paper_2111_11538_amd import inputs as I
+    from paper_2111_11538_amd import pf
+    n, dt = 64, 1e-2
+    T = args.trend_seconds
+    every = max(1, int(round(T / dt / 24)))
+    steps = every * 24
+    f0 = I.ic_core_shell((n, n), r_core=24.0, r_shell=28.0, noise_seed=I.SEED_BASE + 6)
+    cases = [(om, False) for om in (0.0, 0.1, 0.2, 0.25, 0.3, 0.4)] + [(0.1, True), (0.4, True)]
+    out = {}
+    t0 = time.perf_counter()
+    for om, plastic in cases:
+        p = I.Params(Omega_f=om)
+        c = pf.Context(2, (n, n), I.H_DEFAULT, dt, p, precision="fp64", plasticity=plastic, cg_rtol=1e-8,
+                       species_implicit=2, species_rtol=1e-10)
+        c.set_fields(f0)
+        rec = {"t_s": [], "red_degree": [], "max_vm_GPa": [], "max_epsP": [], "mean_phi_f": []}
+        vm_max = 0.0
+        for k in range(steps // every):
+            st = c.step(every)
+            vm_max = max(vm_max, st["max_vm"])
+            rec["t_s"].append(round((k + 1) * every * dt, 3))
+            rec["red_degree"].append(round(st["red_degree"], 5))
+            rec["max_vm_GPa"].append(round(st["max_vm"] / 1e9, 4))
+            rec["max_epsP"].append(round(st["max_epsP"], 5))
+            rec["mean_phi_f"].append(round(float(c.get("phi_f").mean()), 5))
+        rec["peak_vm_GPa_sampled"] = round(vm_max / 1e9, 4)
+        rec["O_drift"] = st["O_drift"]
+        c.close()
+        key = f"Omega_f={om:g} {'elasto-plastic' if plastic else 'elastic'}"
+        out[key] = rec
+        print(f"[trends] {key}: reduction degree {rec['red_degree'][-1]:.4f} at {T:g} s, largest sampled "
+              f"sigma_vm {rec['peak_vm_GPa_sampled']:.3f} GPa ({time.perf_counter() - t0:.0f} s)", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    line = {"metric": "core-shell trends (Sec. 4.2): reduction degree and largest von Mises stress over time",
+            "workload": f"2D core-shell {n}x{n}, h {I.H_DEFAULT:g} m, core r 24, shell to r 28, gas box; "
+                        f"dt {dt:g} s, {steps} steps, species implicit with the reaction solved exactly",
+            "cases": out}
+    print(json.dumps(line), flush=True)
+
+
 def measure_copy_peak(mib=1024, reps=20):
     """Device-to-device copy bandwidth (read + write bytes per second) of a
     plain 1 GiB copy: the practical HBM ceiling on this machine."""
@@ -410,6 +459,7 @@ def main():
                     help="Adam iterations of the network's training (early stopping keeps the best held-out checkpoint)")
     ap.add_argument("--train-lr", type=float, default=1e-4, help="Adam learning rate of the network's training")
     ap.add_argument("--train-batch", type=int, default=4, help="64^3 crops per training minibatch")
+    ap.add_argument("--trend-seconds", type=float, default=120.0, help="model time of the core-shell trend runs")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first copy this many MiB with a plain device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -430,6 +480,9 @@ def main():
 
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "trends":
+        run_trends(args)
         return
     copy_peak = measure_copy_peak()
 

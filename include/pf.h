@@ -81,7 +81,8 @@ typedef struct {
   int cg_max_iter;        /* reaching it is an error */
   int warm;               /* pf_warm: start of each step's solve */
   double ledger_tol;      /* |O drift| above this raises PF_ERR_LEDGER; <= 0 disables */
-  int species_implicit;   /* 0: explicit Euler for x_O, x_H, x_H2O; 1: linearly implicit Euler (see pf_step) */
+  int species_implicit;   /* 0: explicit Euler for x_O, x_H, x_H2O; 1: linearly implicit Euler (see pf_step);
+                             2: as 1 without the reaction, then the reaction over dt solved exactly per cell */
   int species_max_iter;   /* implicit species: CG iteration limit per step (reaching it is an error) */
   double species_rtol;    /* implicit species: stop each species' CG at ||r|| <= species_rtol ||b|| */
 } pf_config;
@@ -146,7 +147,11 @@ pf_status pf_init(const pf_config *cfg, const pf_params *params, void *workspace
  * the two-cell mean D at interior faces and, for x_H and x_H2O, the half-cell
  * Dirichlet faces; each species is solved by Jacobi-PCG to species_rtol.
  * This removes the gas-diffusion limit on dt; the phase fields stay
- * explicit.  The CG
+ * explicit.  With species_implicit == 2 the tendency leaves the reaction out
+ * and, after the solve, each cell's reaction over dt (Eq. 27, 28 with
+ * m(phi_g^n) frozen) is applied from the exact solution of its rate law,
+ * which removes the reaction's limit on dt as well and keeps x_O + x_H2O and
+ * x_H + 2 x_H2O of every cell unchanged.  The CG
  * recurrence scalars and the convergence test live on the device; the host
  * reads the convergence flag once per chunk of queued CG launches (a stream
  * synchronisation per chunk, see pf_cg_chunk: launches queued past

@@ -95,6 +95,8 @@ def lib():
         L.or_common_tangent.argtypes = [_P, _P, _P]
         L.or_fe.argtypes = [C.c_int, C.c_double, _P]
         L.or_simplex_project.argtypes = [_P, _P]
+        L.or_reaction_exact.argtypes = [C.POINTER(OrParams)] + [C.c_double] * 5
+        L.or_reaction_exact.restype = C.c_double
         _lib = L
     return _lib
 
@@ -252,6 +254,10 @@ def simplex_project(phi_f, phi_w):
     a, b = np.array([float(phi_f)]), np.array([float(phi_w)])
     lib().or_simplex_project(_ptr(a), _ptr(b))
     return a[0], b[0]
+
+
+def reaction_exact(params, m, xO, xH, xW, t):
+    return lib().or_reaction_exact(C.byref(make_params(params)), m, xO, xH, xW, t)
 
 
 def common_tangent():

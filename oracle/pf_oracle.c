@@ -872,6 +872,24 @@ static int species_solve(const or_config *c, const double *D, int dirichlet, con
   return status;
 }
 
+/* The reaction of Eq. 27, 28 alone over a time t in one cell, with m(phi_g)
+ * frozen: a = x_O obeys a' = -k m a (2a + c) with c = x_H - 2 x_O constant,
+ * solved exactly:  a(t) = c a0 / ((2 a0 + c) e^(c k m t) - 2 a0) = a0 / D with
+ * D = e^x + 2 a0 k m t g(x), x = c k m t, g(x) = (e^x - 1)/x, which holds for
+ * every sign of c (and c = 0).  Since D - 1 = k m t x_H g(x), the amount
+ * reacted is a0 - a = a0 k m t x_H g(x) / D, formed without cancellation.
+ * None when x_O or x_H is not positive or the cell is full of water. */
+double or_reaction_exact(const or_params *p, double m, double xO, double xH, double xW, double t) {
+  if (!(xW < 1.0) || !(xO > 0.0) || !(xH > 0.0) || !(m > 0.0)) return 0.0;
+  double kmt = p->kfor * m * t;
+  double c = xH - 2.0 * xO;
+  double x = c * kmt;
+  double g = fabs(x) < 1e-8 ? 1.0 + x * (0.5 + x / 6.0) : expm1(x) / x;
+  if (x > 700.0) return xO;                       /* e^x overflows: everything reacted to double precision */
+  double dm1 = kmt * xH * g;
+  return xO * dm1 / (1.0 + dm1);
+}
+
 int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, or_stats *st) {
   if (c->dim != 2 && c->dim != 3) return OR_INVALID;
   if (c->nx < 1 || c->ny < 1 || c->nz < 1 || (c->dim == 2 && c->nz != 1)) return OR_INVALID;
@@ -996,6 +1014,7 @@ int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, 
          * is full of water; mole fractions below zero (the variational O flux
          * leaves the gas slightly below x_O = 0) take no part in it */
         double r = s->xW[q] < 1.0 ? L.m[1] * p->kfor * fmax(s->xO[q], 0.0) * fmax(s->xH[q], 0.0) : 0.0;
+        if (c->species_implicit == 2) r = 0.0;        /* the reaction follows the transport below */
         nf_[q] = s->phi_f[q] + dt * p->L[0] * ((p->eps[0] + p->eps[1]) * lf + p->eps[1] * lw - gf[q]);
         nw_[q] = s->phi_w[q] + dt * p->L[2] * ((p->eps[2] + p->eps[1]) * lw + p->eps[1] * lf - gw[q]);
         or_simplex_project(&nf_[q], &nw_[q]);
@@ -1029,6 +1048,16 @@ int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, 
     nO[q] += s->xO[q];
     nH[q] += s->xH[q];
     nW[q] += s->xW[q];
+  }
+  if (c->species_implicit == 2) {
+    /* the reaction over dt after the transport, exactly per cell, m at phi^n */
+    for (long q = 0; q < n; ++q) {
+      double g = 1.0 - s->phi_f[q] - s->phi_w[q];
+      double R = or_reaction_exact(p, mfun(p, g), nO[q], nH[q], nW[q], dt);
+      nO[q] -= R;
+      nH[q] -= 2.0 * R;
+      nW[q] += R;
+    }
   }
 
   /* (4) boundary outflux for the ledger (lexicographic over faces) */

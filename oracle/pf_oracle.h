@@ -43,7 +43,8 @@ typedef struct {
   int chem_phase;      /* chemical energy drives the phase fields (1, the model) */
   double cg_rtol;
   int cg_max_iter;
-  int species_implicit; /* 0: explicit Euler for the species; 1: linearly implicit Euler (or_step) */
+  int species_implicit; /* 0: explicit Euler for the species; 1: linearly implicit Euler (or_step);
+                           2: as 1 for the transport, then the reaction over dt solved exactly per cell */
 } or_config;
 
 typedef struct {
@@ -97,6 +98,7 @@ double or_energy(const or_config *c, const or_params *p, const or_state *s);
 double or_elastic_energy(const or_config *c, const or_params *p, const or_state *s);
 int  or_common_tangent(double *xf, double *xw, double *resid);
 void or_simplex_project(double *phi_f, double *phi_w);
+double or_reaction_exact(const or_params *p, double m, double xO, double xH, double xW, double t);
 void or_fe(int phase, double x, double out[3]);
 
 #ifdef __cplusplus

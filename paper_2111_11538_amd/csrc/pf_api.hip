@@ -74,7 +74,7 @@ bool valid_cfg(const pf_config* c, char* msg, size_t len) {
   if (c->mechanics && (!(c->cg_rtol > 0.0) || c->cg_max_iter < 1)) { snprintf(msg, len, "cg_rtol > 0 and cg_max_iter >= 1 required"); return false; }
   if (c->warm != PF_WARM_ZERO && c->warm != PF_WARM_PREV && c->warm != PF_WARM_LEARNED) { snprintf(msg, len, "unknown warm start %d", c->warm); return false; }
   if (c->warm == PF_WARM_LEARNED && (c->dim != 3 || !c->mechanics)) { snprintf(msg, len, "the learned warm start needs dim 3 and mechanics"); return false; }
-  if (c->species_implicit != 0 && c->species_implicit != 1) { snprintf(msg, len, "species_implicit must be 0 or 1"); return false; }
+  if (c->species_implicit < 0 || c->species_implicit > 2) { snprintf(msg, len, "species_implicit must be 0, 1 or 2"); return false; }
   if (c->species_implicit && (!(c->species_rtol > 0.0) || c->species_max_iter < 1)) { snprintf(msg, len, "species_rtol > 0 and species_max_iter >= 1 required"); return false; }
   long long px = (c->nx + 15) / 16 * 16;
   if (px * c->ny * (long long)c->nz >= (1LL << 31) / 8) { snprintf(msg, len, "grid too large for 32-bit indexing"); return false; }
@@ -190,6 +190,7 @@ KP<T> make_kp(const pf_config* c, const pf_params* p) {
   k.h = (T)c->h; k.ih = (T)(1.0 / c->h); k.ih2 = (T)(1.0 / (c->h * c->h)); k.dt = (T)c->dt;
   k.mform = p->m_form; k.dirichlet = c->dirichlet; k.chem = c->chem_phase;
   k.plastic = c->plasticity; k.mech = c->mechanics;
+  k.rsplit = c->species_implicit == 2;
   return k;
 }
 

@@ -43,7 +43,8 @@ struct KP {
   T kfor, Omega;
   T xHbc, xWbc;
   T h, ih, ih2, dt;
-  int mform, dirichlet, chem, plastic, mech, pad;
+  int mform, dirichlet, chem, plastic, mech;
+  int rsplit;              // 1: the reaction is left out of the tendencies and solved exactly after the transport
 };
 
 // Padded SoA layout shared by every cell and face array: element (i, j, k) at

@@ -1778,7 +1778,7 @@ __device__ __forceinline__ void cell_update(const CellArgs<T>& a, int e, T pf, T
   }
   // reaction (Eq. 27, 28): forward rate, zero once the cell is full of water;
   // mole fractions below zero take no part in it
-  const T r = (double)xW + (double)lo[4] < 1.0 ? interp_m(pg, p.mform) * p.kfor * fmax(xO, T(0)) * fmax(xH, T(0)) : T(0);
+  const T r = !p.rsplit && (double)xW + (double)lo[4] < 1.0 ? interp_m(pg, p.mform) * p.kfor * fmax(xO, T(0)) * fmax(xH, T(0)) : T(0);
   const T df = p.dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf);
   const T dw = p.dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw);
   const T dO = p.dt * (-divO - r);

@@ -1,7 +1,8 @@
 // Linearly implicit Euler for the three species (x_O, x_H, x_H2O).
 //
 // The field update writes, per species s, the explicit increment
-// b_s = dt T_s(x^n) (every flux and the reaction at x^n) and the cell
+// b_s = dt T_s(x^n) (every flux, and the reaction at x^n unless the reaction
+// is split off and solved exactly afterwards, see k_sp_finish) and the cell
 // diffusivity D_s of the species.  The increment d_s of the step then solves
 //   (I + dt A_s) d_s = b_s,   A_s v = -div(D_s grad v),
 // with the two-cell mean of D_s at interior faces and, for x_H and x_H2O when
@@ -265,6 +266,23 @@ __global__ __launch_bounds__(NT) void k_sp_update(SpArgs<T> a) {
   sp_partials<6>(v, a.part_rr, a.nb);
 }
 
+// The reaction of Eq. 27, 28 alone over a time t in one cell (m(phi_g)
+// frozen), from its exact solution: with b = x_H, c = b - 2a constant and
+// x = c k m t, the amount of O reacted is
+//   R = a b k m t E / (1 + s k m t E),  E = (1 - e^-|x|) / |x|,
+// s = 2a when c >= 0 (hydrogen in excess) and s = b when c < 0 (E -> 1 as
+// x -> 0; every term non-negative, no cancellation).  Zero where a or b is not
+// positive or the cell is full of water.  FP64.
+__device__ __forceinline__ double reaction_exact(double a, double b, double w, double m, double k, double t) {
+  if (!(w < 1.0) || !(a > 0.0) || !(b > 0.0) || !(m > 0.0)) return 0.0;
+  const double kmt = k * m * t;
+  const double c = b - 2.0 * a;
+  const double ax = fabs(c) * kmt;
+  const double E = ax < 1e-8 ? 1.0 - 0.5 * ax : -expm1(-ax) / ax;
+  const double s = c >= 0.0 ? 2.0 * a : b;
+  return a * b * kmt * E / (1.0 + s * kmt * E);
+}
+
 // After the solve: x^(n+1) = x^n + d for the three species (FP32 state: the
 // pair sum in FP64, split again), and the ledger partials of the step (the
 // same tiles and slots as the field update, whose slots for the species it
@@ -288,8 +306,23 @@ __global__ __launch_bounds__(NT) void k_sp_finish(CellArgs<T> a, SpArgs<T> s) {
       T lo = T(0);
       if constexpr (sizeof(T) == 4) lo = a.lo[2 + q][e];
       x[q] = field_new(old[q][e], lo, s.d[q][e]);
-      field_store(x[q], nhi[q], a.nlo[2 + q], e);
     }
+    if (a.p.rsplit) {
+      // the reaction over dt after the transport, with m(phi_g) of phi^n
+      double pf = (double)a.pf[e], pw = (double)a.pw[e];
+      if constexpr (sizeof(T) == 4) {
+        pf += (double)a.lo[0][e];
+        pw += (double)a.lo[1][e];
+      }
+      const double g = 1.0 - pf - pw, y = g * (1.0 - g);
+      const double m = (a.p.mform == 0 ? 16.0 : 1.0) * y * y;
+      const double R = reaction_exact(x[0], x[1], x[2], m, (double)a.p.kfor, (double)a.p.dt);
+      x[0] -= R;
+      x[1] -= 2.0 * R;
+      x[2] += R;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) field_store(x[q], nhi[q], a.nlo[2 + q], e);
     v[0] = x[0] + x[2];
     v[1] = x[1] + 2.0 * x[2];
     v[2] = x[0];

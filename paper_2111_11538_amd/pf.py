@@ -195,7 +195,7 @@ def make_config(dim, shape, h, dt, precision="fp64", mechanics=True, plasticity=
     c.cg_rtol, c.cg_max_iter = cg_rtol, cg_max_iter
     c.warm = WARM[warm]
     c.ledger_tol = ledger_tol
-    c.species_implicit = int(species_implicit)
+    c.species_implicit = int(species_implicit)        # 0, 1 (or True) or 2
     c.species_max_iter = int(species_max_iter)
     c.species_rtol = species_rtol if species_rtol is not None else (1e-12 if precision == "fp64" else 1e-6)
     return c

@@ -209,6 +209,21 @@ def implicit_matrix(coef, dt, h, dirichlet):
     return np.eye(n) + dt * A
 
 
+def reacted(a0, b0, xw, m, k, t):
+    """Amount of O reacted in time t by a' = -k m a b, b' = -2 k m a b (the
+    textbook solution a(t) = c a0 / ((2 a0 + c) e^(c k m t) - 2 a0),
+    c = b0 - 2 a0; a0 / (1 + 2 a0 k m t) when c = 0), zero where a0 or b0 is
+    not positive or the cell is full of water."""
+    ok = (a0 > 0) & (b0 > 0) & (xw < 1) & (m > 0)
+    a0s, b0s, ms = np.where(ok, a0, 1.0), np.where(ok, b0, 3.0), np.where(ok, m, 1.0)
+    c = b0s - 2 * a0s
+    with np.errstate(over="ignore", divide="ignore", invalid="ignore"):
+        e = np.exp(c * k * ms * t)
+        a = np.where(np.abs(c) > 1e-13, c * a0s / ((2 * a0s + c) * e - 2 * a0s), a0s / (1 + 2 * a0s * k * ms * t))
+    a = np.where(np.isfinite(a), a, 0.0)
+    return np.where(ok, a0s - a, 0.0)
+
+
 def step(dim, shape, h, dt, p, f, u, epsp, epsP, plasticity=True, dirichlet=True, implicit=False):
     """Returns new (fields, u, epsp, epsP).  Arrays use (nz, ny, nx) shapes
     (2D: nz = 1); epsp is (6, nz, ny, nx)."""
@@ -300,6 +315,8 @@ def step(dim, shape, h, dt, p, f, u, epsp, epsP, plasticity=True, dirichlet=True
     divH = div_flux(DHh, xH, p.xH_bc if dirichlet else None)
     divW = div_flux(DWw, xW, p.xW_bc if dirichlet else None)
     r = np.where(xW < 1, Mm[1] * p.kfor * np.clip(xO, 0, None) * np.clip(xH, 0, None), 0.0)
+    if implicit == 2:
+        r = np.zeros_like(r)                  # the reaction follows the transport, exactly
     lf, lw = lap(pf), lap(pw)
     nf, nw = simplex(pf + dt * p.L[0] * ((p.eps[0] + p.eps[1]) * lf + p.eps[1] * lw - gf),
                      pw + dt * p.L[2] * ((p.eps[2] + p.eps[1]) * lw + p.eps[1] * lf - gw))
@@ -316,4 +333,9 @@ def step(dim, shape, h, dt, p, f, u, epsp, epsP, plasticity=True, dirichlet=True
         "xH": xH + inc["xH"],
         "xW": xW + inc["xW"],
     }
+    if implicit == 2:
+        R = reacted(out["xO"], out["xH"], out["xW"], Mm[1], p.kfor, dt)
+        out["xO"] = out["xO"] - R
+        out["xH"] = out["xH"] - 2 * R
+        out["xW"] = out["xW"] + R
     return out, (ux, uy, uz), new_epsp, new_epsP

@@ -24,14 +24,15 @@ def _random_fields(shape, seed):
 @pytest.mark.parametrize("dim,n,nsteps,kind,implicit", [(2, 8, 4, "core_shell", False), (2, 8, 3, "random", False),
                                                         (3, 4, 2, "core_shell", False), (3, 4, 2, "random", False),
                                                         (2, 8, 3, "core_shell", True), (2, 8, 3, "random", True),
-                                                        (3, 4, 2, "random", True)])
+                                                        (3, 4, 2, "random", True), (2, 8, 3, "core_shell", 2),
+                                                        (2, 8, 3, "random", 2), (3, 4, 2, "random", 2)])
 def test_oracle_matches_bruteforce(oracle, dim, n, nsteps, kind, implicit):
     p = I.Params()
     h = I.H_DEFAULT
     # a larger time step than the explicit bound of the gas is fine for a
     # handful of steps and makes every term visible above rounding; the
     # implicit species update takes 50 times that
-    dt = (100 if implicit else 2) * I.stable_dt(p, h, dim)
+    dt = (100 if implicit == 1 else 1000 if implicit == 2 else 2) * I.stable_dt(p, h, dim)
     shape = (n,) * dim
     if kind == "random":
         f = _random_fields(shape, 100 + dim)

@@ -786,3 +786,57 @@ def test_reaction_is_forward_only(oracle):
     s = _sim(oracle, 2, (4, 4), I.H_DEFAULT, 1e-6, p, f, mechanics=False, dirichlet=False)
     s.step()
     assert np.all(s.f["xW"] > 0.1)                     # positive fractions do react
+
+
+# ---------------------------------------------------------------------------
+# Reaction solved exactly over a step (species_implicit = 2)
+# ---------------------------------------------------------------------------
+def test_exact_reaction_matches_the_closed_form(oracle):
+    """Against a 40-digit evaluation of a(t) = c a0 / ((2 a0 + c) e^(c k m t)
+    - 2 a0) (and a0 / (1 + 2 a0 k m t) at c = 0), for hydrogen-rich (c > 0),
+    oxygen-rich (c < 0) and balanced cells, short and long times."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    p = I.Params()
+    for a0, b0 in ((0.02, 0.08), (0.5, 0.01), (0.01, 0.02), (0.01, 0.02 + 1e-14), (0.3, 0.3)):
+        for m in (1.0, 0.3):
+            for t in (1e-7, 1e-4, 1e-2, 10.0):
+                R = oracle.reaction_exact(p, m, a0, b0, 0.1, t)
+                A, B, K = mpmath.mpf(a0), mpmath.mpf(b0), mpmath.mpf(p.kfor) * m * mpmath.mpf(t)
+                cc = B - 2 * A
+                a = A / (1 + 2 * A * K) if cc == 0 else cc * A / ((2 * A + cc) * mpmath.exp(cc * K) - 2 * A)
+                want = float(A - a)
+                assert abs(R - want) <= 1e-12 * max(want, 1e-300) + 1e-300, (a0, b0, m, t, R, want)
+                assert 0.0 <= R <= min(a0, b0 / 2) * (1 + 1e-14)
+
+
+def test_exact_reaction_composes_and_halts(oracle):
+    p = I.Params()
+    a0, b0 = 0.2, 0.05
+    R1 = oracle.reaction_exact(p, 1.0, a0, b0, 0.0, 2e-4)
+    R2 = oracle.reaction_exact(p, 1.0, a0 - R1, b0 - 2 * R1, R1, 3e-4)
+    R = oracle.reaction_exact(p, 1.0, a0, b0, 0.0, 5e-4)
+    assert abs((R1 + R2) - R) < 1e-14 * R                    # reacting t1 then t2 is reacting t1 + t2
+    assert oracle.reaction_exact(p, 1.0, a0, b0, 1.0, 1.0) == 0.0     # full of water
+    assert oracle.reaction_exact(p, 1.0, -1e-3, b0, 0.0, 1.0) == 0.0  # forward only
+    assert oracle.reaction_exact(p, 0.0, a0, b0, 0.0, 1.0) == 0.0     # no gas, no reaction
+
+
+@pytest.mark.parametrize("dt", [1e-6, 1e-3, 1.0])
+def test_exact_reaction_step_follows_the_ode_at_any_step(oracle, dt):
+    """Uniform closed box (no transport, frozen phases, m(phi_g) = 1): with the
+    reaction solved exactly the state after n steps is the ODE's at n dt, for
+    any dt (the explicit update diverges or overshoots at the larger ones),
+    and O + H2O, H + 2 H2O are unchanged."""
+    shape = (4, 5)
+    a0, b0, n = 0.02, 0.08, 7
+    p = I.Params(L=(0.0, 0.0, 0.0), DO=(0.0, 0.0, 0.0), DH=(0.0, 0.0, 0.0), DW=(0.0, 0.0, 0.0), kappaO=0.0)
+    f = _uniform_fields(shape, phi_f=0.25, phi_w=0.25, xO=a0, xH=b0)
+    s = _sim(oracle, 2, shape, I.H_DEFAULT, dt, p, f, mechanics=False, dirichlet=False, implicit=2)
+    s.step(n)
+    c = b0 - 2 * a0
+    e = math.exp(-c * p.kfor * n * dt)                  # c > 0: the decaying form
+    a = c * a0 * e / ((2 * a0 + c) - 2 * a0 * e)
+    assert np.max(np.abs(s.f["xO"] - a)) <= 1e-12 * a0 + 1e-300
+    assert np.max(np.abs(s.f["xO"] + s.f["xW"] - a0)) <= 1e-15
+    assert np.max(np.abs(s.f["xH"] + 2 * s.f["xW"] - b0)) <= 1e-15
