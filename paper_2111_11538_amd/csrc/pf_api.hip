@@ -15,6 +15,7 @@
 #include "../../include/pf.h"
 #include "pf_kernels.h"
 #include "pf_species.h"
+#include "pf_step3.h"
 
 using namespace pfk;
 
@@ -700,7 +701,15 @@ struct Impl {
     CellArgs<T> a = cell_args(c);
     a.part = c->arr<double>(L.o_part_c);
     timed_launch(c, PF_K_MU, -1, k_mu<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
-    timed_launch(c, PF_K_STEP, -1, k_step<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
+    int ln = L.nb_cell;                // partials of the field update
+    if (DIM == 3 && !c->cfg.species_implicit) {
+      // 3D: the LDS plane-tile kernel (64 x 8 tiles)
+      const dim3 g3((L.g.nx + TX - 1) / TX, (L.g.ny + S3_BY - 1) / S3_BY, L.g.nz);
+      ln = (int)(g3.x * g3.y * g3.z);
+      timed_launch(c, PF_K_STEP, -1, k_step3<T>, g3, dim3(S3_NT), 0, c->stream, a);
+    } else {
+      timed_launch(c, PF_K_STEP, -1, k_step<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
+    }
     if (c->cfg.species_implicit) {
       pf_status s = species_solve(c);
       if (s != PF_OK) return s;
@@ -708,7 +717,6 @@ struct Impl {
     }
     double vol = std::pow(c->cfg.h, DIM), area = std::pow(c->cfg.h, DIM - 1);
     const double* lp = a.part;
-    int ln = L.nb_cell;
     if (ln > 8 * kFoldBlocks) {         // many partials: fold them on kFoldBlocks blocks first
       double* fold = c->arr<double>(L.o_part_f);
       timed_launch(c, PF_K_OTHER, -1, k_fold_step, dim3(kFoldBlocks), dim3(NT), 0, c->stream, (const double*)a.part, ln,
