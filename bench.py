@@ -60,7 +60,7 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak, vendor figure
 
 
 KERNEL_NAMES = {("update", 3, 4): "k_cg_update<float, 3>", ("apply", 3, 4): "k_apply3<float, 8, 0>",
-                ("step", 3, 4): "k_step<float, 3>", ("mu", 3, 4): "k_mu<float, 3>",
+                ("step", 3, 4): "k_step3<float>", ("mu", 3, 4): "k_mu<float, 3>",
                 ("update", 3, 8): "k_cg_update<double, 3>", ("apply", 3, 8): "k_apply3<double, 8, 0>"}
 
 
@@ -436,6 +436,22 @@ def settle(wl, steps):
     return state, st
 
 
+def copy_probe(mib, times):
+    """A plain device copy of `mib` MiB, `times` times (counter calibration
+    under a profiler, and a marker that brackets the dispatches of the timed
+    legs in its trace); nothing when mib is 0."""
+    if mib <= 0:
+        return
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(times):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -461,22 +477,15 @@ def main():
     ap.add_argument("--train-batch", type=int, default=4, help="64^3 crops per training minibatch")
     ap.add_argument("--trend-seconds", type=float, default=120.0, help="model time of the core-shell trend runs")
     ap.add_argument("--copy-probe", type=int, default=0,
-                    help="first copy this many MiB with a plain device copy (counter calibration under a profiler)")
+                    help="copy this many MiB with a plain device copy first (counter calibration under a profiler) "
+                         "and once before and after the timed legs (markers in the trace)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    if args.copy_probe > 0:
-        import torch
-        n = args.copy_probe * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_probe(args.copy_probe, 3)
 
     if args.workload == "batch":
         run_batch(args)
@@ -508,10 +517,12 @@ def main():
     # HIP events attached to every dispatch (each timed dispatch then follows
     # a timed one, which keeps the events' own overhead out of the kernel's
     # interval); the throughput run below carries no events
+    copy_probe(args.copy_probe, 1)
     brk = run_gpu(wl, wl.precision, args.steps, args.warmup, pf_kinds(), wl.cg_rtol, fields=start, net=net)
     kern = brk["kernels"]
     dom = max((k for k in ("apply", "update", "step", "mu", "solve_setup", "nn")), key=lambda k: kern[k][0])
     res = run_gpu(wl, wl.precision, args.steps, args.warmup, None, wl.cg_rtol, fields=start, net=net)
+    copy_probe(args.copy_probe, 1)
     ms = 1e3 * res["seconds"] / args.steps
     value = ncell * args.steps / res["seconds"]
 
