@@ -99,8 +99,12 @@ def return_map(F, phi_f, phi_w, Fp_n, epsP_n, p, tol=1e-13):
     F_P^n), y_tr = |dev M_tr| - sqrt(2/3)(sigma_Y + H eps_P^n).  If y_tr > 0,
     the step is F_P = exp(dl N) F_P^n with N = dev M_tr / |dev M_tr| (the flow
     direction of an isotropic material is coaxial with the trial state) and dl
-    the root of |dev M(F_P)| = sqrt(2/3)(sigma_Y + H (eps_P^n + dl)), found by
-    bisection.  Returns F_P, eps_P, dl."""
+    the root of g(dl) = |dev M(F_P)| - sqrt(2/3)(sigma_Y + H (eps_P^n + dl)).
+    g falls while the stress's projection s(dl) = dev M : N is positive and
+    rises once it has turned negative, so a plain growing bracket can step
+    over the root: the bracket end hi is first grown (doubling from 1e-3)
+    until s(hi) <= 0, then bisected on s until g(hi) <= 0; dl is the root of g
+    on [0, hi] by bisection to hi - lo <= tol hi.  Returns F_P, eps_P, dl."""
     r23 = math.sqrt(2.0 / 3.0)
     M = mandel(F, phi_f, phi_w, Fp_n, p)
     s = dev(M)
@@ -110,14 +114,30 @@ def return_map(F, phi_f, phi_w, Fp_n, epsP_n, p, tol=1e-13):
         return Fp_n.copy(), epsP_n, 0.0
     N = s / ns
 
+    def dev_at(dl):
+        return dev(mandel(F, phi_f, phi_w, expm_sym_traceless(dl * N) @ Fp_n, p))
+
     def g(dl):
-        Fp = expm_sym_traceless(dl * N) @ Fp_n
-        sd = dev(mandel(F, phi_f, phi_w, Fp, p))
+        sd = dev_at(dl)
         return math.sqrt(np.sum(sd * sd)) - r23 * (p.sigY + p.Hhard * (epsP_n + dl))
 
-    lo, hi = 0.0, 1e-3
-    while g(hi) > 0.0:
-        hi *= 2.0
+    def proj(dl):
+        return float(np.sum(dev_at(dl) * N))
+
+    lo_s, hi = 0.0, 1e-3
+    while proj(hi) > 0.0:
+        lo_s, hi = hi, 2.0 * hi
+    for _ in range(200):
+        if g(hi) <= 0.0:
+            break
+        mid = 0.5 * (lo_s + hi)
+        if proj(mid) > 0.0:
+            lo_s = mid
+        else:
+            hi = mid
+    else:
+        raise ArithmeticError("return map: no root of the yield function along the trial direction")
+    lo = 0.0
     for _ in range(200):
         mid = 0.5 * (lo + hi)
         if g(mid) > 0.0:
