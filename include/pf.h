@@ -430,6 +430,102 @@ pf_status pf_nn_attach(pf_ctx *ctx, pf_nn *nn);
 /* Free the host-side context (never the caller's workspace). */
 void pf_destroy(pf_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Finite-strain mechanics (Sec. 2.2, Eq. 9-14, 19, 25, 31, 34)
+ *
+ * The paper's kinematics F = F_E F_T F_P with F_T = d_T^(1/3) I (Eq. 9-12),
+ * the phase-weighted neo-Hooke energy psi = d_T sum_a h(phi_a) phi_a(F_E)
+ * (Eq. 13, 14) and the first Piola-Kirchhoff stress taken as its derivative
+ * d psi / d F (Eq. 31; the printed form is twice that derivative), on a voxel
+ * grid of bilinear (2D, plane strain) or trilinear (3D) cells with the
+ * displacement at the cell corners and 2^d Gauss points per cell, each with
+ * its own plastic deformation gradient F_P and accumulated plastic strain.
+ * One solve: equilibrium Div P = 0 (Eq. 29, momentum line) under rollers on
+ * every outer face (u . n = 0 there) by Newton's method, each Newton step
+ * solved by Jacobi-preconditioned CG with the Jacobian applied matrix-free
+ * (exact directional derivatives of the nodal forces), with a halving line
+ * search on ||R||; then, with plasticity, the J2 return in the Mandel stress
+ * at every Gauss point (Eq. 25, 34: backward Euler along the trial direction,
+ * F_P = exp(dl N) F_P^n); then the cell means of d psi / d phi_f and
+ * d psi / d phi_w at fixed F, F_P (the elastic driving forces of Eq. 33 in
+ * this kinematics) and the largest von Mises stress of the Cauchy stress.
+ * FP64 throughout.
+ *
+ * Exchange layouts (FP64, compact, x fastest): cells [nz][ny][nx]; nodal
+ * displacement [d][nz+1][ny+1][nx+1] (2D: [2][ny+1][nx+1]); plastic
+ * deformation gradient [nz][ny][nx][2^d][3][3] (Gauss point g: bit 0 the x
+ * side, bit 1 y, bit 2 z of the cell, at 1/2 -+ 1/(2 sqrt 3)); accumulated
+ * plastic strain [nz][ny][nx][2^d]; driving forces [2][nz][ny][nx].
+ * ------------------------------------------------------------------------- */
+typedef struct pf_fs pf_fs;
+
+typedef struct {
+  int dim;                /* 2 (plane strain) or 3 */
+  int nx, ny, nz;         /* cells; nz == 1 when dim == 2; each >= 1 */
+  double h;               /* cell size (m) */
+  int plasticity;         /* 1: return map after the equilibrium solve */
+  int newton_max_iter;    /* reaching it without convergence is an error */
+  double newton_rtol;     /* stop when ||R(u)|| <= newton_rtol ||R(0)|| (free components) */
+  double cg_rtol;         /* each Newton step: stop CG at ||J d + R|| <= cg_rtol ||R|| */
+  int cg_max_iter;        /* per Newton step; reaching it ends that step's CG (not an error) */
+  int pad_;
+} pf_fs_config;
+
+typedef struct {
+  int newton_iters;       /* Newton steps of the last solve */
+  int cg_iters;           /* CG iterations summed over its Newton steps */
+  double rel_resid;       /* ||R(u)|| / ||R(0)|| at its end (0 when R(0) = 0) */
+  double max_vm;          /* largest von Mises stress over the Gauss points (Pa) */
+  double max_epsP;        /* largest accumulated plastic strain */
+  int yielded;            /* Gauss points the return map moved */
+  int line_search_cuts;   /* halvings of Newton steps */
+} pf_fs_stats;
+
+typedef enum {
+  PF_FS_PHI_F = 0, PF_FS_PHI_W = 1,   /* cells, set/get */
+  PF_FS_U = 2,                        /* nodes, d components, set/get (roller components forced to 0 on set) */
+  PF_FS_FP = 3,                       /* Gauss points, 9 components, set/get */
+  PF_FS_EPSP = 4,                     /* Gauss points, set/get */
+  PF_FS_DRIVE = 5                     /* cells, 2 components, get only (from the last solve) */
+} pf_fs_field;
+
+/* Bytes of device workspace for this configuration (about 9 d + 2^d (d + 10)
+ * + 4 doubles per cell); 0 if the configuration is invalid. */
+size_t pf_fs_workspace_bytes(const pf_fs_config *cfg);
+
+/* Create a finite-strain mechanics context on the caller's device workspace
+ * (256-byte aligned, at least pf_fs_workspace_bytes bytes, kept alive until
+ * pf_fs_destroy) and HIP stream (NULL = default).  Material parameters from
+ * `params` (K, G, Omega_f, sigY, Hhard).  Starts with phi_f = phi_w = 0 (gas),
+ * u = 0, F_P = I, eps_P = 0.  Allocates no device memory.  Errors:
+ * PF_ERR_INVALID_ARG (bad configuration, NULL or misaligned pointers),
+ * PF_ERR_OOM (workspace too small), PF_ERR_HIP. */
+pf_status pf_fs_init(const pf_fs_config *cfg, const pf_params *params, void *workspace, size_t workspace_bytes,
+                     void *hip_stream, pf_fs **out);
+
+/* Copy one field (pf_fs_field) between the context and caller memory; dir 0
+ * get, 1 set; ptr holds exactly nbytes of FP64 in the exchange layout;
+ * ptr_is_device selects a device or host pointer.  Stream-ordered; a get to
+ * host memory synchronises the stream.  Errors: PF_ERR_INVALID_ARG (unknown
+ * field, wrong size, set of PF_FS_DRIVE), PF_ERR_HIP. */
+pf_status pf_fs_fields(pf_fs *fs, int field, int dir, void *ptr, size_t nbytes, int ptr_is_device);
+
+/* Solve for the displacement from the current one, then (plasticity) update
+ * F_P and eps_P, then the driving forces and max_vm; `stats` nullable.
+ * Synchronises the stream once per Newton step (for ||R||) and once per chunk
+ * of CG launches.  Errors: PF_ERR_CG_NOT_CONVERGED when Newton reaches
+ * newton_max_iter above newton_rtol or the tangent is not positive along a CG
+ * direction; PF_ERR_NONFINITE when no step of the line search keeps the
+ * residual finite (a cell turned inside out); PF_ERR_HIP. */
+pf_status pf_fs_solve(pf_fs *fs, pf_fs_stats *stats);
+
+/* Message of the last error on this context (fs NULL: errors raised before a
+ * context existed). */
+const char *pf_fs_last_error(const pf_fs *fs);
+
+/* Free the host side (never the caller's workspace). */
+void pf_fs_destroy(pf_fs *fs);
+
 #ifdef __cplusplus
 }
 #endif

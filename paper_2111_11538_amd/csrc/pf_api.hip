@@ -1001,3 +1001,4 @@ void pf_destroy(pf_ctx* c) {
 
 #include "pf_batch_api.h"
 #include "pf_nn_api.h"
+#include "pf_fs_api.h"

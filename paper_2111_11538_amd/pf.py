@@ -71,13 +71,31 @@ class pf_step_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("pad")}
 
 
+class pf_fs_config(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double),
+                ("plasticity", C.c_int), ("newton_max_iter", C.c_int), ("newton_rtol", C.c_double),
+                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("pad_", C.c_int)]
+
+
+class pf_fs_stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int), ("cg_iters", C.c_int), ("rel_resid", C.c_double), ("max_vm", C.c_double),
+                ("max_epsP", C.c_double), ("yielded", C.c_int), ("line_search_cuts", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+FS_FIELDS = {"phi_f": 0, "phi_w": 1, "u": 2, "Fp": 3, "epsP": 4, "drive": 5}
+
+
 EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_chunk", "pf_fields", "pf_ledger_reset",
            "pf_timing", "pf_timing_every", "pf_timing_get", "pf_last_error", "pf_destroy",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_set_tiles", "pf_batch_get_tiles",
            "pf_batch_fields", "pf_batch_step", "pf_batch_last_error", "pf_batch_destroy",
            "pf_nn_param_count", "pf_nn_workspace_bytes", "pf_nn_init", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_weights", "pf_nn_copy",
            "pf_nn_forward", "pf_nn_loss", "pf_nn_backward", "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale",
-           "pf_nn_pack", "pf_nn_attach", "pf_increment_scale_static")
+           "pf_nn_pack", "pf_nn_attach", "pf_increment_scale_static",
+           "pf_fs_workspace_bytes", "pf_fs_init", "pf_fs_fields", "pf_fs_solve", "pf_fs_last_error", "pf_fs_destroy")
 KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn", "species")
 
 _lib = None
@@ -157,6 +175,19 @@ def lib():
         for f in ("pf_nn_init", "pf_nn_weights", "pf_nn_copy", "pf_nn_forward", "pf_nn_loss", "pf_nn_backward",
                   "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale", "pf_nn_pack", "pf_nn_attach"):
             getattr(L, f).restype = C.c_int
+        L.pf_fs_workspace_bytes.argtypes = [C.POINTER(pf_fs_config)]
+        L.pf_fs_workspace_bytes.restype = C.c_size_t
+        L.pf_fs_init.argtypes = [C.POINTER(pf_fs_config), C.POINTER(pf_params), C.c_void_p, C.c_size_t, C.c_void_p,
+                                 C.POINTER(C.c_void_p)]
+        L.pf_fs_init.restype = C.c_int
+        L.pf_fs_fields.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_int]
+        L.pf_fs_fields.restype = C.c_int
+        L.pf_fs_solve.argtypes = [C.c_void_p, C.POINTER(pf_fs_stats)]
+        L.pf_fs_solve.restype = C.c_int
+        L.pf_fs_last_error.argtypes = [C.c_void_p]
+        L.pf_fs_last_error.restype = C.c_char_p
+        L.pf_fs_destroy.argtypes = [C.c_void_p]
+        L.pf_fs_destroy.restype = None
         _lib = L
     return _lib
 
@@ -525,6 +556,85 @@ class Net:
         if getattr(self, "nn", None) and self.nn.value:
             lib().pf_nn_destroy(self.nn)
             self.nn = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_fs_config(dim, shape, h, plasticity=False, newton_rtol=1e-10, newton_max_iter=50, cg_rtol=1e-3,
+                   cg_max_iter=20000) -> pf_fs_config:
+    c = pf_fs_config()
+    c.dim = dim
+    if dim == 2:
+        c.ny, c.nx = shape
+        c.nz = 1
+    else:
+        c.nz, c.ny, c.nx = shape
+    c.h = h
+    c.plasticity = int(plasticity)
+    c.newton_rtol, c.newton_max_iter = newton_rtol, newton_max_iter
+    c.cg_rtol, c.cg_max_iter = cg_rtol, cg_max_iter
+    return c
+
+
+class FiniteStrain:
+    """Finite-strain mechanics on one GPU: owner of a ``pf_fs`` and of the
+    torch-allocated device workspace it lives in.  Arrays use the exchange
+    layouts of ``include/pf.h`` (cells ``shape``; nodal displacement
+    ``(dim,) + nodes``; F_P ``shape + (2^dim, 3, 3)``; eps_P ``shape +
+    (2^dim,)``; driving forces ``(2,) + shape``)."""
+
+    def __init__(self, dim, shape, h, params, device=0, stream=None, **cfg_kw):
+        import torch
+        self.dim, self.shape = dim, tuple(shape)
+        self.nodes = tuple(n + 1 for n in self.shape)
+        self.cfg = make_fs_config(dim, shape, h, **cfg_kw)
+        self.params = make_params(params)
+        L = lib()
+        nbytes = L.pf_fs_workspace_bytes(C.byref(self.cfg))
+        if nbytes == 0:
+            raise PFError(PF_ERR_INVALID_ARG, "invalid finite-strain configuration")
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        rc = L.pf_fs_init(C.byref(self.cfg), C.byref(self.params), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                          C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx))
+        if rc != PF_OK:
+            raise PFError(rc, L.pf_fs_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != PF_OK:
+            raise PFError(rc, lib().pf_fs_last_error(self.ctx).decode())
+
+    def field_shape(self, name):
+        ngp = 1 << self.dim
+        return {"phi_f": self.shape, "phi_w": self.shape, "u": (self.dim,) + self.nodes,
+                "Fp": self.shape + (ngp, 3, 3), "epsP": self.shape + (ngp,), "drive": (2,) + self.shape}[name]
+
+    def set(self, name, value):
+        a = np.ascontiguousarray(value, dtype=np.float64)
+        assert a.shape == self.field_shape(name), (name, a.shape, self.field_shape(name))
+        self._check(lib().pf_fs_fields(self.ctx, FS_FIELDS[name], 1, a.ctypes.data_as(C.c_void_p), a.nbytes, 0))
+
+    def get(self, name):
+        a = np.zeros(self.field_shape(name), dtype=np.float64)
+        self._check(lib().pf_fs_fields(self.ctx, FS_FIELDS[name], 0, a.ctypes.data_as(C.c_void_p), a.nbytes, 0))
+        return a
+
+    def solve(self):
+        st = pf_fs_stats()
+        self._check(lib().pf_fs_solve(self.ctx, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.ctx:
+            lib().pf_fs_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+            self.workspace = None
 
     def __del__(self):
         try:

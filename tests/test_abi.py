@@ -42,8 +42,9 @@ def test_struct_layouts_match_the_header(lib):
 #include <stddef.h>
 #include "pf.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pf_config), sizeof(pf_params), sizeof(pf_step_stats),
-         offsetof(pf_config, ledger_tol), offsetof(pf_params, m_form), offsetof(pf_step_stats, nonfinite));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pf_config), sizeof(pf_params), sizeof(pf_step_stats),
+         offsetof(pf_config, ledger_tol), offsetof(pf_params, m_form), offsetof(pf_step_stats, nonfinite),
+         sizeof(pf_fs_config), offsetof(pf_fs_config, cg_rtol), sizeof(pf_fs_stats), offsetof(pf_fs_stats, yielded));
   return 0;
 }
 '''
@@ -54,7 +55,9 @@ int main(void) {
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, c])
         out = [int(v) for v in subprocess.check_output([exe]).split()]
     assert out == [C.sizeof(pf.pf_config), C.sizeof(pf.pf_params), C.sizeof(pf.pf_step_stats),
-                   pf.pf_config.ledger_tol.offset, pf.pf_params.m_form.offset, pf.pf_step_stats.nonfinite.offset]
+                   pf.pf_config.ledger_tol.offset, pf.pf_params.m_form.offset, pf.pf_step_stats.nonfinite.offset,
+                   C.sizeof(pf.pf_fs_config), pf.pf_fs_config.cg_rtol.offset, C.sizeof(pf.pf_fs_stats),
+                   pf.pf_fs_stats.yielded.offset]
 
 
 def test_workspace_size_and_validation(lib):
@@ -126,3 +129,26 @@ def test_network_workspace_size(lib):
     assert 220 * 4096 <= sizes[0, 8192] - sizes[0, 4096] <= 230 * 4096
     assert 380 * 4096 <= sizes[1, 8192] - sizes[1, 4096] <= 390 * 4096
     assert all(v % 256 == 0 for v in sizes.values())
+
+
+def test_finite_strain_workspace_and_validation(lib):
+    cfg = pf.make_fs_config(2, (8, 10), 1e-7)
+    n2 = lib.pf_fs_workspace_bytes(C.byref(cfg))
+    assert n2 > 0 and n2 % 256 == 0
+    cfg3 = pf.make_fs_config(3, (8, 8, 10), 1e-7)
+    assert lib.pf_fs_workspace_bytes(C.byref(cfg3)) > n2
+    for field, value in (("nz", 2), ("h", 0.0), ("newton_rtol", -1.0), ("cg_max_iter", 0), ("dim", 4)):
+        bad = pf.make_fs_config(2, (8, 10), 1e-7)
+        setattr(bad, field, value)
+        assert lib.pf_fs_workspace_bytes(C.byref(bad)) == 0, field
+    fs = C.c_void_p()
+    prm = pf.make_params(I.Params())
+    assert lib.pf_fs_init(C.byref(cfg), C.byref(prm), None, n2, None, C.byref(fs)) == pf.PF_ERR_INVALID_ARG
+    assert b"workspace" in lib.pf_fs_last_error(None)
+    # a misaligned workspace is rejected before any HIP call
+    assert lib.pf_fs_init(C.byref(cfg), C.byref(prm), C.c_void_p(257 * 256 + 8), n2, None,
+                          C.byref(fs)) == pf.PF_ERR_INVALID_ARG
+    assert lib.pf_fs_init(C.byref(cfg), C.byref(prm), C.c_void_p(256), 16, None, C.byref(fs)) == pf.PF_ERR_OOM
+    assert not fs.value
+    assert lib.pf_fs_solve(None, None) == pf.PF_ERR_INVALID_ARG
+    assert lib.pf_fs_fields(None, 0, 0, None, 0, 0) == pf.PF_ERR_INVALID_ARG

@@ -270,6 +270,37 @@ def test_determinism_bitwise():
     assert outs[0][1]["O_tot"] == outs[1][1]["O_tot"]
 
 
+@pytest.mark.parametrize("precision,implicit", [("fp64", 0), ("mixed", 0), ("mixed", 2)])
+def test_checkpoint_restart_is_bitwise(precision, implicit):
+    """N steps, every field copied out, a new context set from the copies, N
+    more steps: bitwise the state of 2N steps in one context.  The exchange is
+    FP64, which holds an FP32 pair exactly; the displacement is part of the
+    state, so the restarted solve starts where the other one would."""
+    wl = I.workload("core_shell_3d", n=20)
+    kw = dict(precision=precision, plasticity=True, cg_rtol=1e-6 if precision == "mixed" else 1e-10,
+              species_implicit=implicit)
+    dt = wl.dt * (50 if implicit else 1)
+    say("checkpoint", precision, implicit)
+    g = _ctx(3, wl.shape, wl.h, dt, wl.params, **kw)
+    g.set_fields(wl.fields)
+    g.step(3)
+    g.step(3)
+    want = g.fields()
+    g.close()
+    a = _ctx(3, wl.shape, wl.h, dt, wl.params, **kw)
+    a.set_fields(wl.fields)
+    a.step(3)
+    saved = a.fields()
+    a.close()
+    b = _ctx(3, wl.shape, wl.h, dt, wl.params, **kw)
+    b.set_fields(saved)
+    b.step(3)
+    got = b.fields()
+    b.close()
+    for k in want:
+        assert np.array_equal(got[k], want[k]), k
+
+
 def test_field_roundtrip_and_roller_faces():
     shape = (9, 7)
     rng = np.random.default_rng(1)
