@@ -90,71 +90,79 @@ def dev_b(A):
 
 
 def expm_sym_b(A):
+    """exp of symmetric matrices by their eigen-decomposition."""
     lam, Q = np.linalg.eigh(0.5 * (A + np.swapaxes(A, -1, -2)))
     return (Q * np.exp(lam)[..., None, :]) @ np.swapaxes(Q, -1, -2)
 
 
 def return_map_b(F, phi_f, phi_w, Fp_n, epsP_n, p, tol=1e-13):
     """The pointwise return map of `fs_oracle.return_map` on every point at
-    once, each point taking the same steps: trial Mandel stress, yield test,
-    flow direction N = dev M_tr / |dev M_tr|, the bracket end grown until the
-    projection dev M : N is no longer positive and bisected on it until the
-    yield function is no longer positive, then the bisection of the yield
-    function on [0, hi].  Returns F_P, eps_P, dl."""
+    once, each point taking the same steps: the principal frame of the trial
+    elastic state, the deviatoric log stretches, the yield test, then for each
+    trial dl the Newton solve of e + dl s(e) / Y(dl) = e_tr (to 1e-15) and the
+    bracket-and-bisection on |s(e(dl))| - Y(dl).  Returns F_P, eps_P, dl."""
     r23 = math.sqrt(2.0 / 3.0)
-    s = dev_b(mandel_b(F, phi_f, phi_w, Fp_n, p))
-    ns = np.sqrt(np.sum(s * s, axis=(-2, -1)))
-    ytr = ns - r23 * (p.sigY + p.Hhard * epsP_n)
+    dT, _, FE = _elastic_part(F, phi_f, Fp_n, p)
+    c, Q = np.linalg.eigh(np.swapaxes(FE, -1, -2) @ FE)
+    lnJ = 0.5 * np.sum(np.log(c), axis=-1)
+    etr = 0.5 * np.log(c) - (lnJ / 3.0)[..., None]
+    _, Gb = _moduli(phi_f, phi_w, p)
+    k = dT * Gb
+
+    def s_of(e, kk):
+        x = np.exp(2.0 * e)
+        return kk[..., None] * (x - x.mean(axis=-1, keepdims=True))
+
+    def Y(dl, e0):
+        return r23 * (p.sigY + p.Hhard * (e0 + dl))
+
+    ytr = np.sqrt(np.sum(s_of(etr, k) ** 2, axis=-1)) - Y(0.0, epsP_n)
     Fp = Fp_n.copy()
     epsP = epsP_n.copy()
     dl = np.zeros_like(epsP_n)
     idx = np.nonzero(ytr > 0.0)
     if len(idx[0]) == 0:
         return Fp, epsP, dl
-    Fy, Fpy, ey = F[idx], Fp_n[idx], epsP_n[idx]
-    pfy, pwy = phi_f[idx], phi_w[idx]
-    N = s[idx] / ns[idx][..., None, None]
+    et, ky, ey, Qy, Fpy = etr[idx], k[idx], epsP_n[idx], Q[idx], Fp_n[idx]
 
-    def dev_at(d):
-        return dev_b(mandel_b(Fy, pfy, pwy, expm_sym_b(d[..., None, None] * N) @ Fpy, p))
+    def e_of(d):
+        a = d / Y(d, ey)
+        e = et.copy()
+        todo = np.ones(len(d), bool)
+        for _ in range(60):
+            x = np.exp(2.0 * e)
+            G = e + (a * ky)[:, None] * (x - x.mean(axis=-1, keepdims=True)) - et
+            todo = np.max(np.abs(G), axis=-1) > 1e-15
+            if not np.any(todo):
+                break
+            Jm = np.eye(3) + (a * ky)[:, None, None] * (2.0 * x[:, :, None] * np.eye(3) - (2.0 / 3.0) * x[:, None, :])
+            step = np.linalg.solve(Jm, G[..., None])[..., 0]
+            e = np.where(todo[:, None], e - step, e)
+        return e
 
-    def g(d):
-        sd = dev_at(d)
-        return np.sqrt(np.sum(sd * sd, axis=(-2, -1))) - r23 * (p.sigY + p.Hhard * (ey + d))
-
-    def proj(d):
-        return np.sum(dev_at(d) * N, axis=(-2, -1))
+    def phi(d):
+        return np.sqrt(np.sum(s_of(e_of(d), ky) ** 2, axis=-1)) - Y(d, ey)
 
     n = len(idx[0])
-    lo_s, hi = np.zeros(n), np.full(n, 1e-3)
-    grow = proj(hi) > 0.0
+    lo, hi = np.zeros(n), np.full(n, 1e-3)
+    grow = phi(hi) > 0.0
     while np.any(grow):
-        lo_s = np.where(grow, hi, lo_s)
+        lo = np.where(grow, hi, lo)
         hi = np.where(grow, 2.0 * hi, hi)
-        grow = grow & (proj(hi) > 0.0)
-    todo = g(hi) > 0.0
-    for _ in range(200):
-        if not np.any(todo):
-            break
-        mid = 0.5 * (lo_s + hi)
-        pos = proj(mid) > 0.0
-        lo_s = np.where(todo & pos, mid, lo_s)
-        hi = np.where(todo & ~pos, mid, hi)
-        todo = todo & (g(hi) > 0.0)
-    if np.any(todo):
-        raise ArithmeticError("return map: no root of the yield function along the trial direction")
-    lo = np.zeros(n)
+        grow = grow & (phi(hi) > 0.0)
     active = np.ones(n, bool)
     for _ in range(200):
         mid = 0.5 * (lo + hi)
-        pos = g(mid) > 0.0
+        pos = phi(mid) > 0.0
         lo = np.where(active & pos, mid, lo)
         hi = np.where(active & ~pos, mid, hi)
         active &= ~(hi - lo <= tol * np.maximum(hi, 1e-300))
         if not np.any(active):
             break
     d = 0.5 * (lo + hi)
-    Fp[idx] = expm_sym_b(d[..., None, None] * N) @ Fpy
+    sv = s_of(e_of(d), ky)
+    nv = sv / np.sqrt(np.sum(sv * sv, axis=-1, keepdims=True))
+    Fp[idx] = ((Qy * np.exp(d[:, None] * nv)[:, None, :]) @ np.swapaxes(Qy, -1, -2)) @ Fpy
     epsP[idx] = ey + d
     dl[idx] = d
     return Fp, epsP, dl

@@ -95,59 +95,69 @@ def expm_sym_traceless(A):
 
 
 def return_map(F, phi_f, phi_w, Fp_n, epsP_n, p, tol=1e-13):
-    """Eq. 25, 34 by backward Euler: with the trial Mandel stress M_tr (F_P =
-    F_P^n), y_tr = |dev M_tr| - sqrt(2/3)(sigma_Y + H eps_P^n).  If y_tr > 0,
-    the step is F_P = exp(dl N) F_P^n with N = dev M_tr / |dev M_tr| (the flow
-    direction of an isotropic material is coaxial with the trial state) and dl
-    the root of g(dl) = |dev M(F_P)| - sqrt(2/3)(sigma_Y + H (eps_P^n + dl)).
-    g falls while the stress's projection s(dl) = dev M : N is positive and
-    rises once it has turned negative, so a plain growing bracket can step
-    over the root: the bracket end hi is first grown (doubling from 1e-3)
-    until s(hi) <= 0, then bisected on s until g(hi) <= 0; dl is the root of g
-    on [0, hi] by bisection to hi - lo <= tol hi.  Returns F_P, eps_P, dl."""
+    """Eq. 25, 34 by backward Euler with the exponential map: F_P = exp(dl N)
+    F_P^n with N = dev M / |dev M| of the END state and
+    |dev M| = sqrt(2/3)(sigma_Y + H (eps_P^n + dl)).
+
+    For an isotropic energy the end state is coaxial with the trial elastic
+    state C_tr = F_E,tr^T F_E,tr (F_P = F_P^n): with C_tr = Q diag(c) Q^T,
+    J = sqrt(prod c) (plastic flow keeps it) and the deviatoric log stretches
+    e_tr = ln(c) / 2 - ln(J) / 3, the neo-Hooke energy gives
+    dev M = k dev(exp(2 e)) in that frame, k = d_T sum_a h_a G_a, and the flow
+    moves e to e = e_tr - dl n, n = s(e) / |s(e)|.  With |s| = Y(dl) at the end
+    this is e + dl s(e) / Y(dl) = e_tr, solved by Newton for each dl; dl is the
+    root of |s(e(dl))| - Y(dl), which falls with dl (bracket doubled from
+    1e-3, then bisection to hi - lo <= tol hi).  Returns F_P, eps_P, dl."""
     r23 = math.sqrt(2.0 / 3.0)
-    M = mandel(F, phi_f, phi_w, Fp_n, p)
-    s = dev(M)
-    ns = math.sqrt(np.sum(s * s))
-    ytr = ns - r23 * (p.sigY + p.Hhard * epsP_n)
+    dT = d_T(phi_f, p.Omega_f)
+    FE = elastic_deformation(F, phi_f, Fp_n, p.Omega_f)
+    c, Q = np.linalg.eigh(FE.T @ FE)
+    lnJ = 0.5 * float(np.sum(np.log(c)))
+    etr = 0.5 * np.log(c) - lnJ / 3.0
+    w = phase_weights(phi_f, phi_w)
+    k = dT * sum(w[a] * p.G[a] for a in range(3))
+
+    def s_of(e):
+        x = np.exp(2.0 * e)
+        return k * (x - x.mean())
+
+    def Y(dl):
+        return r23 * (p.sigY + p.Hhard * (epsP_n + dl))
+
+    ytr = math.sqrt(float(np.sum(s_of(etr) ** 2))) - Y(0.0)
     if ytr <= 0.0:
         return Fp_n.copy(), epsP_n, 0.0
-    N = s / ns
 
-    def dev_at(dl):
-        return dev(mandel(F, phi_f, phi_w, expm_sym_traceless(dl * N) @ Fp_n, p))
+    def e_of(dl):
+        a = dl / Y(dl)
+        e = etr.copy()
+        for _ in range(60):
+            x = np.exp(2.0 * e)
+            G = e + a * k * (x - x.mean()) - etr
+            if np.max(np.abs(G)) <= 1e-15:
+                break
+            Jm = np.eye(3) + a * k * (2.0 * np.diag(x) - (2.0 / 3.0) * np.outer(np.ones(3), x))
+            e = e - np.linalg.solve(Jm, G)
+        return e
 
-    def g(dl):
-        sd = dev_at(dl)
-        return math.sqrt(np.sum(sd * sd)) - r23 * (p.sigY + p.Hhard * (epsP_n + dl))
+    def phi(dl):
+        return math.sqrt(float(np.sum(s_of(e_of(dl)) ** 2))) - Y(dl)
 
-    def proj(dl):
-        return float(np.sum(dev_at(dl) * N))
-
-    lo_s, hi = 0.0, 1e-3
-    while proj(hi) > 0.0:
-        lo_s, hi = hi, 2.0 * hi
-    for _ in range(200):
-        if g(hi) <= 0.0:
-            break
-        mid = 0.5 * (lo_s + hi)
-        if proj(mid) > 0.0:
-            lo_s = mid
-        else:
-            hi = mid
-    else:
-        raise ArithmeticError("return map: no root of the yield function along the trial direction")
-    lo = 0.0
+    lo, hi = 0.0, 1e-3
+    while phi(hi) > 0.0:
+        lo, hi = hi, 2.0 * hi
     for _ in range(200):
         mid = 0.5 * (lo + hi)
-        if g(mid) > 0.0:
+        if phi(mid) > 0.0:
             lo = mid
         else:
             hi = mid
         if hi - lo <= tol * max(hi, 1e-300):
             break
     dl = 0.5 * (lo + hi)
-    return expm_sym_traceless(dl * N) @ Fp_n, epsP_n + dl, dl
+    sv = s_of(e_of(dl))
+    n = sv / math.sqrt(float(np.sum(sv * sv)))
+    return (Q * np.exp(dl * n)) @ Q.T @ Fp_n, epsP_n + dl, dl
 
 
 def laminate(phi_f, phi_w, p, h_cell=1.0, tol=1e-13):

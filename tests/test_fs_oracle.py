@@ -162,3 +162,32 @@ def test_laminate_equilibrium_and_small_strain_limit():
             Ml = Kl + 4 * Gl / 3
             sig = -np.sum(3 * Kl * el / Ml) / np.sum(1 / Ml)
             assert abs(P - sig) < 0.02 * abs(sig), (P, sig)
+
+
+def test_return_map_is_backward_euler_in_the_end_state():
+    """One large step (no yield in between): the returned state satisfies the
+    backward-Euler equations checked with the stress routine itself: F_P =
+    exp(dl N) F_P^n with N = dev M / |dev M| of the END state, and |dev M| =
+    sqrt(2/3)(sigma_Y + H (eps_P^n + dl))."""
+    rng = np.random.default_rng(11)
+    p = I.Params()
+    r23 = math.sqrt(2 / 3)
+    cases = []
+    F = np.eye(3)
+    F[0, 1] = 0.12
+    cases.append((F, 0.1, 0.8, np.eye(3), 0.02))
+    for _ in range(4):
+        F = np.eye(3) + rng.normal(0, 0.1, (3, 3))
+        cases.append((F, rng.uniform(0, 0.6), rng.uniform(0, 0.4), _unimodular(rng, 0.05), rng.uniform(0, 0.05)))
+    moved = 0
+    for F, pf, pw, Fp0, e0 in cases:
+        Fp, eP, dl = FS.return_map(F, pf, pw, Fp0, e0, p)
+        if dl == 0.0:
+            continue
+        moved += 1
+        s = FS.dev(FS.mandel(F, pf, pw, Fp, p))
+        ns = math.sqrt(np.sum(s * s))
+        assert abs(ns - r23 * (p.sigY + p.Hhard * eP)) < 1e-9 * ns
+        assert np.max(np.abs(FS.expm_sym_traceless(dl * s / ns) @ Fp0 - Fp)) < 1e-10
+        assert abs(np.linalg.det(Fp) - np.linalg.det(Fp0)) < 1e-12
+    assert moved >= 4
