@@ -519,6 +519,26 @@ pf_status pf_fs_fields(pf_fs *fs, int field, int dir, void *ptr, size_t nbytes, 
  * residual finite (a cell turned inside out); PF_ERR_HIP. */
 pf_status pf_fs_solve(pf_fs *fs, pf_fs_stats *stats);
 
+/* Kernel classes of the finite-strain timing interface. */
+typedef enum {
+  PF_FS_K_TANGENT = 0,    /* element kernel on dual numbers: J v (one per CG iteration) */
+  PF_FS_K_GATHER = 1,     /* nodal gather of element forces, with a dot-product partial */
+  PF_FS_K_RESIDUAL = 2,   /* element kernel on FP64: nodal forces R(u) */
+  PF_FS_K_VECTOR = 3,     /* CG vector updates and reductions */
+  PF_FS_K_RETURN = 4,     /* return map at the Gauss points */
+  PF_FS_K_POST = 5,       /* driving forces and von Mises stress */
+  PF_FS_K_COUNT = 6
+} pf_fs_kernel;
+
+/* Switch per-kernel timing on (1) or off (0): HIP events around every launch
+ * of the classes above, read back at the solve's synchronisations; turning it
+ * on clears the accumulators.  Errors: PF_ERR_INVALID_ARG, PF_ERR_HIP. */
+pf_status pf_fs_timing(pf_fs *fs, int on);
+
+/* Accumulated device time (ms) and launch count of one kernel class since
+ * timing was switched on.  Errors: PF_ERR_INVALID_ARG (NULL, unknown kind). */
+pf_status pf_fs_timing_get(pf_fs *fs, int kind, double *ms, long long *launches);
+
 /* Message of the last error on this context (fs NULL: errors raised before a
  * context existed). */
 const char *pf_fs_last_error(const pf_fs *fs);

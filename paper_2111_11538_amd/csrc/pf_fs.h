@@ -15,7 +15,8 @@
 //    block partial of a dot product.
 //  * PCG kernels on the nodal vectors with device-side scalars.
 //  * k_fs_return: the J2 return in the Mandel stress at each Gauss point
-//    (backward Euler along the trial direction, exponential map).
+//    (backward Euler with the exponential map and the flow direction of the
+//    end state, solved in the principal frame of the trial elastic stretch).
 //  * k_fs_post: the cell-mean driving forces d psi / d phi_f, d psi / d phi_w
 //    at fixed F, F_P (dual numbers in phi), and the largest von Mises stress.
 #pragma once
@@ -191,57 +192,6 @@ __device__ __forceinline__ void neo_hooke(const M3<S>& F, S pf, S pw, const M3<d
   }
 }
 
-// Mandel stress M = d_T [Kb/2 (J^2 - 1) I + Gb J^(-2/3) (C_E - tr C_E / 3 I)].
-__device__ __forceinline__ M3<double> mandel(const M3<double>& F, double pf, double pw, const M3<double>& Fpi,
-                                             const FSP& p) {
-  const double hf = hpoly(pf), hg = hpoly(1.0 - pf - pw), hw = hpoly(pw);
-  const double Kb = hf * p.K[0] + hg * p.K[1] + hw * p.K[2];
-  const double Gb = hf * p.G[0] + hg * p.G[1] + hw * p.G[2];
-  const double dT = 1.0 - hf * p.Omega;
-  const double c = exp(log(dT) * (-1.0 / 3.0));
-  M3<double> FE = mul3(F, Fpi);
-#pragma unroll
-  for (int q = 0; q < 9; ++q) FE.a[q] *= c;
-  const double J = det3(FE);
-  M3<double> C = mul3t(FE, FE);
-  const double trC = C.a[0] + C.a[4] + C.a[8];
-  const double b = Gb * exp(log(J) * (-2.0 / 3.0));
-  const double a = 0.5 * Kb * (J * J - 1.0);
-  M3<double> M;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) M.a[q] = dT * (b * C.a[q] + ((q % 4 == 0) ? a - b * trC / 3.0 : 0.0));
-  return M;
-}
-
-// exp of a symmetric matrix A by scaling and squaring: A / 2^s with
-// |A / 2^s|_F <= 1/4, Taylor series to 14 terms (truncation below 1e-17),
-// then s squarings.
-__device__ __forceinline__ M3<double> expm3(const M3<double>& A) {
-  double nf = 0.0;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) nf += A.a[q] * A.a[q];
-  nf = sqrt(nf);
-  int s = 0;
-  double sc = 1.0;
-  while (nf * sc > 0.25 && s < 60) {
-    sc *= 0.5;
-    ++s;
-  }
-  M3<double> X;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) X.a[q] = A.a[q] * sc;
-  M3<double> E = eye3(), T = eye3();
-  for (int k = 1; k <= 14; ++k) {
-    T = mul3(T, X);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) T.a[q] /= (double)k;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) E.a[q] += T.a[q];
-  }
-  for (int r = 0; r < s; ++r) E = mul3(E, E);
-  return E;
-}
-
 // ---------------------------------------------------------------------------
 // grid, shape functions
 // ---------------------------------------------------------------------------
@@ -313,12 +263,14 @@ struct FSElemArgs {
   const double* pw;
   const double* u;         // [DIM][nn]
   const double* v;         // direction of the tangent mode [DIM][nn]
-  const double* Fp;        // [ne][ngp][9]
+  const double* Fp;        // [ne][ngp][9]; nullptr when every F_P is the identity
   double* ef;              // [2^DIM * DIM][ne] element forces
   const double* sc;        // device scalars (the tangent mode exits once CG has stopped)
 };
 
+// F_P^-1 at Gauss point gq of cell e (Fp == nullptr: every F_P is the identity)
 __device__ __forceinline__ M3<double> load_Fpi(const double* Fp, long long e, int gq, int ngp) {
+  if (!Fp) return eye3();
   M3<double> m;
   const double* s = Fp + (e * ngp + gq) * 9;
 #pragma unroll
@@ -708,14 +660,57 @@ struct FSRetArgs {
   double tol;
 };
 
-// J2 return in the Mandel stress at each Gauss point (Eq. 25, 34): trial
-// M_tr with F_P^n; if |dev M_tr| exceeds sqrt(2/3)(sigma_Y + H eps_P^n), F_P =
-// exp(dl N) F_P^n with N = dev M_tr / |dev M_tr| and dl the root of
-// g(dl) = |dev M(dl)| - sqrt(2/3)(sigma_Y + H (eps_P^n + dl)) on the branch
-// where g falls: the bracket end hi is doubled from 1e-3 until the
-// projection dev M(hi) : N is no longer positive, then bisected on that
-// projection until g(hi) <= 0, and dl is found by bisection on [0, hi] to
-// hi - lo <= tol hi.
+// Eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi rotations:
+// A = Q diag(c) Q^T (columns of Q are the eigenvectors).
+__device__ __forceinline__ void eig_sym3(M3<double> A, double c[3], M3<double>& Q) {
+  Q = eye3();
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    const double off = A.a[1] * A.a[1] + A.a[2] * A.a[2] + A.a[5] * A.a[5];
+    const double dia = A.a[0] * A.a[0] + A.a[4] * A.a[4] + A.a[8] * A.a[8];
+    if (off <= 1e-36 * dia || off == 0.0) break;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int pi = r == 2 ? 1 : 0, qi = r == 0 ? 1 : 2;
+      const double apq = A.a[3 * pi + qi];
+      if (apq == 0.0) continue;
+      const double th = (A.a[3 * qi + qi] - A.a[3 * pi + pi]) / (2.0 * apq);
+      const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+      const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+      // A <- R^T A R with the rotation in the (pi, qi) plane
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {           // columns pi, qi
+        const double akp = A.a[3 * k + pi], akq = A.a[3 * k + qi];
+        A.a[3 * k + pi] = cs * akp - sn * akq;
+        A.a[3 * k + qi] = sn * akp + cs * akq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {           // rows pi, qi
+        const double apk = A.a[3 * pi + k], aqk = A.a[3 * qi + k];
+        A.a[3 * pi + k] = cs * apk - sn * aqk;
+        A.a[3 * qi + k] = sn * apk + cs * aqk;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double qkp = Q.a[3 * k + pi], qkq = Q.a[3 * k + qi];
+        Q.a[3 * k + pi] = cs * qkp - sn * qkq;
+        Q.a[3 * k + qi] = sn * qkp + cs * qkq;
+      }
+    }
+  }
+  c[0] = A.a[0];
+  c[1] = A.a[4];
+  c[2] = A.a[8];
+}
+
+// J2 return in the Mandel stress at each Gauss point (Eq. 25, 34), backward
+// Euler with the exponential map and the flow direction of the end state:
+// in the principal frame Q of the trial elastic stretch C_tr (F_P = F_P^n),
+// with the deviatoric log stretches e_tr = ln(c)/2 - ln(J)/3, the neo-Hooke
+// energy gives dev M = k dev(exp(2 e)), k = d_T sum h_a G_a; the return
+// solves e + dl s(e) / Y(dl) = e_tr (Newton in e) with |s(e(dl))| = Y(dl) =
+// sqrt(2/3)(sigma_Y + H (eps_P^n + dl)) (bracket doubled from 1e-3, then
+// bisection to hi - lo <= tol hi) and sets F_P = Q diag(exp(dl n)) Q^T F_P^n,
+// n = s / |s|.
 template <int DIM>
 __global__ __launch_bounds__(kFsThreads) void k_fs_return(FSRetArgs a) {
   constexpr int NA = 1 << DIM;
@@ -726,6 +721,10 @@ __global__ __launch_bounds__(kFsThreads) void k_fs_return(FSRetArgs a) {
     int i, j, k;
     cell_ijk(g, e, i, j, k);
     const double pf = a.pf[e], pw = a.pw[e];
+    const double hf = hpoly(pf), hg = hpoly(1.0 - pf - pw), hw = hpoly(pw);
+    const double dT = 1.0 - hf * a.p.Omega;
+    const double kk = dT * (hf * a.p.G[0] + hg * a.p.G[1] + hw * a.p.G[2]);
+    const double cT = exp(log(dT) * (-1.0 / 3.0));
     for (int gq = 0; gq < NA; ++gq) {
       const long long pt = e * NA + gq;
       M3<double> Fpn;
@@ -733,56 +732,87 @@ __global__ __launch_bounds__(kFsThreads) void k_fs_return(FSRetArgs a) {
       for (int q = 0; q < 9; ++q) Fpn.a[q] = a.Fp[pt * 9 + q];
       const double e0 = a.epsP[pt];
       const M3<double> F = grad_F<DIM>(g, a.u, i, j, k, gq);
-      M3<double> s = mandel(F, pf, pw, inv3(Fpn), a.p);
-      dev3(s);
-      const double ns = sqrt(dot3(s, s));
-      const double ytr = ns - r23 * (a.p.sigY + a.p.Hh * e0);
+      M3<double> FE = mul3(F, inv3(Fpn));
+#pragma unroll
+      for (int q = 0; q < 9; ++q) FE.a[q] *= cT;
+      double c[3];
+      M3<double> Q;
+      eig_sym3(mul3t(FE, FE), c, Q);
+      const double lnJ = 0.5 * (log(c[0]) + log(c[1]) + log(c[2]));
+      double et[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) et[q] = 0.5 * log(c[q]) - lnJ / 3.0;
+      auto s_of = [&](const double* ev, double* sv) {
+        const double x0 = exp(2.0 * ev[0]), x1 = exp(2.0 * ev[1]), x2 = exp(2.0 * ev[2]);
+        const double m = (x0 + x1 + x2) / 3.0;
+        sv[0] = kk * (x0 - m);
+        sv[1] = kk * (x1 - m);
+        sv[2] = kk * (x2 - m);
+      };
+      auto Yf = [&](double dl) { return r23 * (a.p.sigY + a.p.Hh * (e0 + dl)); };
+      double st[3];
+      s_of(et, st);
+      const double ytr = sqrt(st[0] * st[0] + st[1] * st[1] + st[2] * st[2]) - Yf(0.0);
       if (ytr > 0.0) {
-        M3<double> N;
+        // e(dl): Newton on G(e) = e + (dl / Y) s(e) - e_tr from e_tr
+        auto e_of = [&](double dl, double* ev) {
+          const double al = dl / Yf(dl) * kk;
+          ev[0] = et[0];
+          ev[1] = et[1];
+          ev[2] = et[2];
+          for (int t = 0; t < 60; ++t) {
+            const double x[3] = {exp(2.0 * ev[0]), exp(2.0 * ev[1]), exp(2.0 * ev[2])};
+            const double m = (x[0] + x[1] + x[2]) / 3.0;
+            double G[3];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) N.a[q] = s.a[q] / ns;
-        auto dev_at = [&](double dl) {
-          M3<double> A;
+            for (int q = 0; q < 3; ++q) G[q] = ev[q] + al * (x[q] - m) - et[q];
+            if (fmax(fabs(G[0]), fmax(fabs(G[1]), fabs(G[2]))) <= 1e-15) break;
+            M3<double> Jm;
 #pragma unroll
-          for (int q = 0; q < 9; ++q) A.a[q] = dl * N.a[q];
-          M3<double> m = mandel(F, pf, pw, inv3(mul3(expm3(A), Fpn)), a.p);
-          dev3(m);
-          return m;
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int q = 0; q < 3; ++q)
+                Jm.a[3 * r + q] = (r == q ? 1.0 + 2.0 * al * x[q] : 0.0) - al * (2.0 / 3.0) * x[q];
+            const M3<double> Ji = inv3(Jm);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) ev[r] -= Ji.a[3 * r] * G[0] + Ji.a[3 * r + 1] * G[1] + Ji.a[3 * r + 2] * G[2];
+          }
         };
-        auto gfun = [&](double dl) {
-          const M3<double> m = dev_at(dl);
-          return sqrt(dot3(m, m)) - r23 * (a.p.sigY + a.p.Hh * (e0 + dl));
+        auto phi = [&](double dl) {
+          double ev[3], sv[3];
+          e_of(dl, ev);
+          s_of(ev, sv);
+          return sqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]) - Yf(dl);
         };
-        auto proj = [&](double dl) {
-          const M3<double> m = dev_at(dl);
-          return dot3(m, N);
-        };
-        double lo_s = 0.0, hi = 1e-3;
-        for (int t = 0; t < 64 && proj(hi) > 0.0; ++t) {
-          lo_s = hi;
+        double lo = 0.0, hi = 1e-3;
+        for (int t = 0; t < 64 && phi(hi) > 0.0; ++t) {
+          lo = hi;
           hi *= 2.0;
         }
-        for (int t = 0; t < 200 && gfun(hi) > 0.0; ++t) {
-          const double mid = 0.5 * (lo_s + hi);
-          if (proj(mid) > 0.0)
-            lo_s = mid;
-          else
-            hi = mid;
-        }
-        double lo = 0.0;
         for (int t = 0; t < 200; ++t) {
           const double mid = 0.5 * (lo + hi);
-          if (gfun(mid) > 0.0)
+          if (phi(mid) > 0.0)
             lo = mid;
           else
             hi = mid;
           if (hi - lo <= a.tol * fmax(hi, 1e-300)) break;
         }
         const double dl = 0.5 * (lo + hi);
-        M3<double> A;
+        double ev[3], sv[3];
+        e_of(dl, ev);
+        s_of(ev, sv);
+        const double ns = sqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+        double ex[3];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) A.a[q] = dl * N.a[q];
-        const M3<double> Fpnew = mul3(expm3(A), Fpn);
+        for (int q = 0; q < 3; ++q) ex[q] = exp(dl * sv[q] / ns);
+        M3<double> Ex;                          // Q diag(ex) Q^T
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            Ex.a[3 * r + q] = Q.a[3 * r] * ex[0] * Q.a[3 * q] + Q.a[3 * r + 1] * ex[1] * Q.a[3 * q + 1] +
+                              Q.a[3 * r + 2] * ex[2] * Q.a[3 * q + 2];
+        const M3<double> Fpnew = mul3(Ex, Fpn);
 #pragma unroll
         for (int q = 0; q < 9; ++q) a.Fp[pt * 9 + q] = Fpnew.a[q];
         a.epsP[pt] = e0 + dl;
@@ -802,7 +832,7 @@ struct FSPostArgs {
   const double* pf;
   const double* pw;
   const double* u;
-  const double* Fp;
+  const double* Fp;        // nullptr when every F_P is the identity
   double* drive;           // [2][ne]: cell means of d psi / d phi_f, d psi / d phi_w
   double* part;            // [3][nb]: (unused), max von Mises, (unused)
 };

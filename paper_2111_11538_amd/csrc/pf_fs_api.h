@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <vector>
 
 #include "pf_fs.h"
 
@@ -19,8 +20,47 @@ struct pf_fs {
   long long nd;            // d * nodes
   double *pf, *pw, *u, *uold, *R, *x, *r, *z, *pd, *q, *dinv, *Fp, *epsP, *drive, *ef, *part, *sc;
   double* host;            // pinned copy of the scalars
+  bool fp_identity;        // every F_P is the identity (the element kernels skip loading it)
+  // timing: event pairs around launches, resolved at the next synchronisation
+  bool timing;
+  std::vector<hipEvent_t> ev;
+  std::vector<std::pair<int, int>> pend;   // (kind, first event)
+  int ev_used;
+  double t_ms[PF_FS_K_COUNT];
+  long long t_n[PF_FS_K_COUNT];
   char err[512];
 };
+
+static void fs_flush(pf_fs* f) {
+  for (auto& pr : f->pend) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, f->ev[pr.second], f->ev[pr.second + 1]) == hipSuccess) {
+      f->t_ms[pr.first] += ms;
+      f->t_n[pr.first] += 1;
+    }
+  }
+  f->pend.clear();
+  f->ev_used = 0;
+}
+
+// Launch through `launch`, bracketed by events of class `kind` when timing is on.
+template <typename L>
+static void fs_timed(pf_fs* f, int kind, L&& launch) {
+  if (!f->timing) {
+    launch();
+    return;
+  }
+  if (f->ev_used + 2 > (int)f->ev.size()) {
+    (void)hipStreamSynchronize(f->stream);
+    fs_flush(f);
+  }
+  const int i = f->ev_used;
+  (void)hipEventRecord(f->ev[i], f->stream);
+  launch();
+  (void)hipEventRecord(f->ev[i + 1], f->stream);
+  f->pend.emplace_back(kind, i);
+  f->ev_used += 2;
+}
 
 static char g_fs_err[512] = "";
 
@@ -116,7 +156,7 @@ static pfs::FSElemArgs fs_elem_args(pf_fs* f, const double* u, const double* v) 
   a.pw = f->pw;
   a.u = u;
   a.v = v;
-  a.Fp = f->Fp;
+  a.Fp = f->fp_identity ? nullptr : f->Fp;
   a.ef = f->ef;
   a.sc = f->sc;
   return a;
@@ -126,10 +166,14 @@ static pfs::FSElemArgs fs_elem_args(pf_fs* f, const double* u, const double* v) 
 template <int DIM>
 static pf_status fs_residual(pf_fs* f, const double* u, double* R) {
   const int nbe = fs_blocks(f->g.ne);
-  hipLaunchKernelGGL((pfs::k_fs_elem<DIM, false>), dim3(nbe), dim3(pfs::kFsThreads), 0, f->stream,
-                     fs_elem_args<DIM>(f, u, nullptr));
+  const pfs::FSElemArgs ea = fs_elem_args<DIM>(f, u, nullptr);
+  fs_timed(f, PF_FS_K_RESIDUAL, [&] {
+    hipLaunchKernelGGL((pfs::k_fs_elem<DIM, false>), dim3(nbe), dim3(pfs::kFsThreads), 0, f->stream, ea);
+  });
   pfs::FSGatherArgs ga{f->g, f->ef, R, nullptr, f->part, nullptr};
-  hipLaunchKernelGGL((pfs::k_fs_gather<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, f->stream, ga);
+  fs_timed(f, PF_FS_K_GATHER, [&] {
+    hipLaunchKernelGGL((pfs::k_fs_gather<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, f->stream, ga);
+  });
   hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, f->stream, (const double*)f->part, f->nb, f->sc,
                      (int)pfs::FSR_NORM, 0);
   FSLAUNCH(f);
@@ -139,6 +183,7 @@ static pf_status fs_residual(pf_fs* f, const double* u, double* R) {
 static pf_status fs_read_scalars(pf_fs* f) {
   FSCHK(f, hipMemcpyAsync(f->host, f->sc, pfs::FS_COUNT * sizeof(double), hipMemcpyDeviceToHost, f->stream));
   FSCHK(f, hipStreamSynchronize(f->stream));
+  if (f->timing) fs_flush(f);
   return PF_OK;
 }
 
@@ -160,14 +205,22 @@ static pf_status fs_cg(pf_fs* f, int* iters) {
   for (;;) {
     for (int t = 0; t < chunk; ++t) {
       if (launched > 0)
-        hipLaunchKernelGGL(pfs::k_fs_cg_dir, dim3(nbv), dim3(pfs::kFsThreads), 0, f->stream, v);
-      hipLaunchKernelGGL((pfs::k_fs_elem<DIM, true>), dim3(nbe), dim3(pfs::kFsThreads), 0, f->stream, ea);
-      hipLaunchKernelGGL((pfs::k_fs_gather<DIM>), dim3(nbv), dim3(pfs::kFsThreads), 0, f->stream, ga);
-      hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, f->stream, (const double*)f->part, nbv, f->sc,
-                         (int)pfs::FSR_ALPHA, f->cfg.cg_max_iter);
-      hipLaunchKernelGGL(pfs::k_fs_cg_update, dim3(nbv), dim3(pfs::kFsThreads), 0, f->stream, v);
-      hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, f->stream, (const double*)f->part, nbv, f->sc,
-                         (int)pfs::FSR_BETA, f->cfg.cg_max_iter);
+        fs_timed(f, PF_FS_K_VECTOR, [&] {
+          hipLaunchKernelGGL(pfs::k_fs_cg_dir, dim3(nbv), dim3(pfs::kFsThreads), 0, f->stream, v);
+        });
+      fs_timed(f, PF_FS_K_TANGENT, [&] {
+        hipLaunchKernelGGL((pfs::k_fs_elem<DIM, true>), dim3(nbe), dim3(pfs::kFsThreads), 0, f->stream, ea);
+      });
+      fs_timed(f, PF_FS_K_GATHER, [&] {
+        hipLaunchKernelGGL((pfs::k_fs_gather<DIM>), dim3(nbv), dim3(pfs::kFsThreads), 0, f->stream, ga);
+      });
+      fs_timed(f, PF_FS_K_VECTOR, [&] {
+        hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, f->stream, (const double*)f->part, nbv, f->sc,
+                           (int)pfs::FSR_ALPHA, f->cfg.cg_max_iter);
+        hipLaunchKernelGGL(pfs::k_fs_cg_update, dim3(nbv), dim3(pfs::kFsThreads), 0, f->stream, v);
+        hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, f->stream, (const double*)f->part, nbv, f->sc,
+                           (int)pfs::FSR_BETA, f->cfg.cg_max_iter);
+      });
       ++launched;
     }
     FSLAUNCH(f);
@@ -238,16 +291,21 @@ static pf_status fs_solve_dim(pf_fs* f, pf_fs_stats* out) {
   }
   if (f->cfg.plasticity) {
     pfs::FSRetArgs ra{f->g, f->p, f->pf, f->pw, f->u, f->Fp, f->epsP, f->part, 1e-13};
-    hipLaunchKernelGGL((pfs::k_fs_return<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, s, ra);
+    fs_timed(f, PF_FS_K_RETURN, [&] {
+      hipLaunchKernelGGL((pfs::k_fs_return<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, s, ra);
+    });
     hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, s, (const double*)f->part, f->nb, f->sc,
                        (int)pfs::FSR_MAX2_SUM, 0);
     FSLAUNCH(f);
     if ((rc = fs_read_scalars(f)) != PF_OK) return rc;
     st.max_epsP = f->host[pfs::FS_MAX0];
     st.yielded = (int)f->host[pfs::FS_SUM0];
+    if (st.yielded > 0) f->fp_identity = false;
   }
-  pfs::FSPostArgs pa{f->g, f->p, f->pf, f->pw, f->u, f->Fp, f->drive, f->part};
-  hipLaunchKernelGGL((pfs::k_fs_post<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, s, pa);
+  pfs::FSPostArgs pa{f->g, f->p, f->pf, f->pw, f->u, f->fp_identity ? nullptr : f->Fp, f->drive, f->part};
+  fs_timed(f, PF_FS_K_POST, [&] {
+    hipLaunchKernelGGL((pfs::k_fs_post<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, s, pa);
+  });
   hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, s, (const double*)f->part, f->nb, f->sc,
                      (int)pfs::FSR_MAX2_SUM, 0);
   FSLAUNCH(f);
@@ -303,6 +361,7 @@ pf_status pf_fs_init(const pf_fs_config* cfg, const pf_params* params, void* wor
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  f->fp_identity = true;
   if (e != hipSuccess) {
     (void)hipHostFree(f->host);
     delete f;
@@ -336,6 +395,7 @@ pf_status pf_fs_fields(pf_fs* f, int field, int dir, void* ptr, size_t nbytes, i
     FSCHK(f, hipMemcpyAsync(arr, ptr, nbytes, kind, f->stream));
   else
     FSCHK(f, hipMemcpyAsync(ptr, arr, nbytes, kind, f->stream));
+  if (dir == 1 && field == PF_FS_FP) f->fp_identity = false;
   if (dir == 1 && field == PF_FS_U) {
     if (f->cfg.dim == 2)
       hipLaunchKernelGGL((pfs::k_fs_fix<2>), dim3(f->nb), dim3(pfs::kFsThreads), 0, f->stream, f->g, f->u);
@@ -352,10 +412,36 @@ pf_status pf_fs_solve(pf_fs* f, pf_fs_stats* stats) {
   return f->cfg.dim == 2 ? fs_solve_dim<2>(f, stats) : fs_solve_dim<3>(f, stats);
 }
 
+pf_status pf_fs_timing(pf_fs* f, int on) {
+  if (!f) return fs_fail(nullptr, PF_ERR_INVALID_ARG, "pf_fs_timing: NULL context");
+  FSCHK(f, hipStreamSynchronize(f->stream));
+  fs_flush(f);
+  if (on && f->ev.empty()) {
+    f->ev.resize(4096);
+    for (auto& e : f->ev) FSCHK(f, hipEventCreate(&e));
+  }
+  for (int k = 0; k < PF_FS_K_COUNT; ++k) {
+    f->t_ms[k] = 0.0;
+    f->t_n[k] = 0;
+  }
+  f->timing = on != 0;
+  return PF_OK;
+}
+
+pf_status pf_fs_timing_get(pf_fs* f, int kind, double* ms, long long* launches) {
+  if (!f || !ms || !launches || kind < 0 || kind >= PF_FS_K_COUNT)
+    return fs_fail(f, PF_ERR_INVALID_ARG, "pf_fs_timing_get: bad arguments");
+  *ms = f->t_ms[kind];
+  *launches = f->t_n[kind];
+  return PF_OK;
+}
+
 const char* pf_fs_last_error(const pf_fs* f) { return f ? f->err : g_fs_err; }
 
 void pf_fs_destroy(pf_fs* f) {
   if (!f) return;
+  if (!f->ev.empty()) (void)hipStreamSynchronize(f->stream);
+  for (auto& e : f->ev) (void)hipEventDestroy(e);
   (void)hipHostFree(f->host);
   delete f;
 }

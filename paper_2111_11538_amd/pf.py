@@ -86,6 +86,7 @@ class pf_fs_stats(C.Structure):
 
 
 FS_FIELDS = {"phi_f": 0, "phi_w": 1, "u": 2, "Fp": 3, "epsP": 4, "drive": 5}
+FS_KERNEL_KINDS = ("tangent", "gather", "residual", "vector", "return", "post")
 
 
 EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_chunk", "pf_fields", "pf_ledger_reset",
@@ -95,7 +96,8 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_c
            "pf_nn_param_count", "pf_nn_workspace_bytes", "pf_nn_init", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_weights", "pf_nn_copy",
            "pf_nn_forward", "pf_nn_loss", "pf_nn_backward", "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale",
            "pf_nn_pack", "pf_nn_attach", "pf_increment_scale_static",
-           "pf_fs_workspace_bytes", "pf_fs_init", "pf_fs_fields", "pf_fs_solve", "pf_fs_last_error", "pf_fs_destroy")
+           "pf_fs_workspace_bytes", "pf_fs_init", "pf_fs_fields", "pf_fs_solve", "pf_fs_timing", "pf_fs_timing_get",
+           "pf_fs_last_error", "pf_fs_destroy")
 KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn", "species")
 
 _lib = None
@@ -184,6 +186,10 @@ def lib():
         L.pf_fs_fields.restype = C.c_int
         L.pf_fs_solve.argtypes = [C.c_void_p, C.POINTER(pf_fs_stats)]
         L.pf_fs_solve.restype = C.c_int
+        L.pf_fs_timing.argtypes = [C.c_void_p, C.c_int]
+        L.pf_fs_timing.restype = C.c_int
+        L.pf_fs_timing_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
+        L.pf_fs_timing_get.restype = C.c_int
         L.pf_fs_last_error.argtypes = [C.c_void_p]
         L.pf_fs_last_error.restype = C.c_char_p
         L.pf_fs_destroy.argtypes = [C.c_void_p]
@@ -629,6 +635,18 @@ class FiniteStrain:
         st = pf_fs_stats()
         self._check(lib().pf_fs_solve(self.ctx, C.byref(st)))
         return st.as_dict()
+
+    def timing(self, on=True):
+        self._check(lib().pf_fs_timing(self.ctx, int(on)))
+
+    def timing_report(self):
+        """{kind: (total ms, launches)} since timing was switched on."""
+        out = {}
+        for k, name in enumerate(FS_KERNEL_KINDS):
+            ms, n = C.c_double(), C.c_longlong()
+            self._check(lib().pf_fs_timing_get(self.ctx, k, C.byref(ms), C.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def close(self):
         if self.ctx:

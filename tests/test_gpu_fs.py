@@ -72,12 +72,13 @@ def test_elastic_core_shell_matches_oracle(dim, n):
     assert st["yielded"] == 0 and st["max_epsP"] == 0.0
 
 
-@pytest.mark.parametrize("dim,n", [(2, 20), (3, 6)])
-def test_plastic_core_shell_matches_oracle_over_two_solves(dim, n):
+@pytest.mark.parametrize("dim,n,omega", [(2, 20, 0.2), (3, 6, 0.2), (3, 8, 0.4)])
+def test_plastic_core_shell_matches_oracle_over_two_solves(dim, n, omega):
     """Two solves with the return map in between (the second starts from the
     first's F_P and displacement and from phases moved by hand), against the
-    oracle taking the same steps."""
-    p = I.Params(Omega_f=0.2)
+    oracle taking the same steps; at Omega_f = 0.4 the first return is a
+    large one-step flow (tens of percent of plastic strain)."""
+    p = I.Params(Omega_f=omega)
     h = 1e-7
     pf, pw = _core_shell(dim, n, rng_seed=I.SEED_BASE + 8)
     shape = (n,) * dim
