@@ -321,6 +321,11 @@ def run_trends(args):
     print(json.dumps(line), flush=True)
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (non-matrix) peak, vendor figure
+# FP64 operations per cell of the 3D tangent kernel (dual numbers, 8 Gauss
+# points, F_P = I): SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes per launch at 128^3,
+# divided by the cells (24.48 GFLOP / 2097152)
+FS_TANGENT_FLOP_PER_CELL = 11672
 FS_KERNEL_BYTES_PER_CELL = {
     # tangent J v and residual R(u), per cell: nodal u (and v) 8 B per component
     # per node (one node per cell), phi_f, phi_w, the element forces written
@@ -376,7 +381,8 @@ def run_finite_strain(args):
     tan_ms = rep["tangent"][0]
     tan_us = 1e3 * tan_ms / max(st["cg_iters"], 1)
     bpc = FS_KERNEL_BYTES_PER_CELL["tangent"](3, True)
-    achieved = bpc * cells / (tan_us * 1e-6) / 1e9
+    gbs = bpc * cells / (tan_us * 1e-6) / 1e9
+    tflops = FS_TANGENT_FLOP_PER_CELL * cells / (tan_us * 1e-6) / 1e12
     dom = max(rep, key=lambda k: rep[k][0])
     # small vs finite strain, 2D core-shell of the trend study
     sweep = {}
@@ -407,12 +413,14 @@ def run_finite_strain(args):
         "solve_s": sec, "newton_iters": st["newton_iters"], "cg_iters": st["cg_iters"],
         "line_search_cuts": st["line_search_cuts"], "rel_resid": st["rel_resid"], "yielded_gauss_points": st["yielded"],
         "max_vm_GPa": st["max_vm"] / 1e9, "max_epsP": st["max_epsP"],
-        "roofline": {"bound": "hbm", "kernel": "tangent (k_fs_elem on dual numbers, one per CG iteration)",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": bpc * cells, "avg_launch_us": round(tan_us, 2),
-                     "note": ("algorithmic bytes of the first solve (F_P = I is not loaded); the kernel holds 256 "
-                              "VGPRs (one wave per SIMD) and is bound by FP64 latency, not by memory")},
+        "roofline": {"bound": "alu", "kernel": "tangent (k_fs_elem on dual numbers, one per CG iteration)",
+                     "achieved": round(tflops, 2), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "flop_per_launch": FS_TANGENT_FLOP_PER_CELL * cells, "avg_launch_us": round(tan_us, 2),
+                     "hbm_GBps_algorithmic": round(gbs, 1), "hbm_frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
+                     "note": ("FP64 operations of the dual-number stress evaluation per cell (8 Gauss points), "
+                              "counted once with rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 (x 64 lanes); time per CG "
+                              "iteration that did work (launches queued past convergence excluded)")},
         "dominant_kernel": dom,
         "kernels": kernels,
         "small_vs_finite_strain_max_vm": {"workload": "2D core-shell 64x64 (core r 24, shell to 28), first solve",

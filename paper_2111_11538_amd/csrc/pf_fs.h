@@ -551,51 +551,69 @@ __global__ __launch_bounds__(kFsThreads) void k_fs_cg_dir(FSVec v) {
 
 enum FsReduce { FSR_INIT = 0, FSR_ALPHA = 1, FSR_BETA = 2, FSR_NORM = 3, FSR_MAX2_SUM = 4 };
 
-// One block: fixed-order sums of the block partials and the CG scalars.
-__global__ __launch_bounds__(64) void k_fs_reduce(const double* part, int nb, double* sc, int mode, int max_iter) {
-  if (threadIdx.x != 0) return;
-  auto sum = [&](const double* a) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += a[b];
-    return s;
-  };
+// One block of kFsThreads threads: fixed-order sums (and maxima) of the
+// block partials -- thread t takes partials t, t + 256, ... in order, then a
+// fixed tree over the threads -- and the CG scalars from them.
+__device__ __forceinline__ double fs_block_reduce(const double* a, int nb, bool mx) {
+  __shared__ double red[kFsThreads];
+  double v = mx ? -INFINITY : 0.0;
+  for (int b = threadIdx.x; b < nb; b += kFsThreads) v = mx ? fmax(v, a[b]) : v + a[b];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kFsThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = mx ? fmax(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kFsThreads) void k_fs_reduce(const double* part, int nb, double* sc, int mode, int max_iter) {
+  const bool conv = sc[FS_CONV] != 0.0;
   if (mode == FSR_INIT) {
-    const double rz = sum(part), rr = sum(part + nb);
-    sc[FS_RZ] = rz;
-    sc[FS_RR] = rr;
-    sc[FS_RR0] = rr;
-    sc[FS_ITERS] = 0.0;
-    sc[FS_BAD] = 0.0;
-    sc[FS_CONV] = (rr == 0.0) ? 1.0 : 0.0;
+    const double rz = fs_block_reduce(part, nb, false), rr = fs_block_reduce(part + nb, nb, false);
+    if (threadIdx.x == 0) {
+      sc[FS_RZ] = rz;
+      sc[FS_RR] = rr;
+      sc[FS_RR0] = rr;
+      sc[FS_ITERS] = 0.0;
+      sc[FS_BAD] = 0.0;
+      sc[FS_CONV] = (rr == 0.0) ? 1.0 : 0.0;
+    }
   } else if (mode == FSR_ALPHA) {
-    if (sc[FS_CONV] != 0.0) return;
-    const double pq = sum(part);
-    sc[FS_PQ] = pq;
-    if (!(pq > 0.0)) {
-      sc[FS_BAD] = 1.0;
-      sc[FS_CONV] = 1.0;
-      return;
+    if (conv) return;
+    const double pq = fs_block_reduce(part, nb, false);
+    if (threadIdx.x == 0) {
+      sc[FS_PQ] = pq;
+      if (!(pq > 0.0)) {
+        sc[FS_BAD] = 1.0;
+        sc[FS_CONV] = 1.0;
+      } else {
+        sc[FS_ALPHA] = sc[FS_RZ] / pq;
+      }
     }
-    sc[FS_ALPHA] = sc[FS_RZ] / pq;
   } else if (mode == FSR_BETA) {
-    if (sc[FS_CONV] != 0.0) return;
-    const double rz = sum(part), rr = sum(part + nb);
-    sc[FS_BETA] = rz / sc[FS_RZ];
-    sc[FS_RZ] = rz;
-    sc[FS_RR] = rr;
-    sc[FS_ITERS] += 1.0;
-    if (rr <= sc[FS_TOL2] * sc[FS_RR0] || sc[FS_ITERS] >= (double)max_iter) sc[FS_CONV] = 1.0;
-  } else if (mode == FSR_NORM) {
-    sc[FS_NORM] = sum(part);
-  } else {
-    double m0 = part[0], m1 = part[nb];
-    for (int b = 1; b < nb; ++b) {
-      m0 = fmax(m0, part[b]);
-      m1 = fmax(m1, part[nb + b]);
+    if (conv) return;
+    const double rz = fs_block_reduce(part, nb, false), rr = fs_block_reduce(part + nb, nb, false);
+    if (threadIdx.x == 0) {
+      sc[FS_BETA] = rz / sc[FS_RZ];
+      sc[FS_RZ] = rz;
+      sc[FS_RR] = rr;
+      sc[FS_ITERS] += 1.0;
+      if (rr <= sc[FS_TOL2] * sc[FS_RR0] || sc[FS_ITERS] >= (double)max_iter) sc[FS_CONV] = 1.0;
     }
-    sc[FS_MAX0] = m0;
-    sc[FS_MAX1] = m1;
-    sc[FS_SUM0] = sum(part + 2 * nb);
+  } else if (mode == FSR_NORM) {
+    const double v = fs_block_reduce(part, nb, false);
+    if (threadIdx.x == 0) sc[FS_NORM] = v;
+  } else {
+    const double m0 = fs_block_reduce(part, nb, true), m1 = fs_block_reduce(part + nb, nb, true);
+    const double s2 = fs_block_reduce(part + 2 * nb, nb, false);
+    if (threadIdx.x == 0) {
+      sc[FS_MAX0] = m0;
+      sc[FS_MAX1] = m1;
+      sc[FS_SUM0] = s2;
+    }
   }
 }
 
@@ -709,8 +727,9 @@ __device__ __forceinline__ void eig_sym3(M3<double> A, double c[3], M3<double>& 
 // energy gives dev M = k dev(exp(2 e)), k = d_T sum h_a G_a; the return
 // solves e + dl s(e) / Y(dl) = e_tr (Newton in e) with |s(e(dl))| = Y(dl) =
 // sqrt(2/3)(sigma_Y + H (eps_P^n + dl)) (bracket doubled from 1e-3, then
-// bisection to hi - lo <= tol hi) and sets F_P = Q diag(exp(dl n)) Q^T F_P^n,
-// n = s / |s|.
+// Illinois regula falsi to hi - lo <= tol hi: the root the oracle's
+// bisection reaches, in fewer evaluations) and sets F_P = Q diag(exp(dl n))
+// Q^T F_P^n, n = s / |s|.
 template <int DIM>
 __global__ __launch_bounds__(kFsThreads) void k_fs_return(FSRetArgs a) {
   constexpr int NA = 1 << DIM;
@@ -784,20 +803,40 @@ __global__ __launch_bounds__(kFsThreads) void k_fs_return(FSRetArgs a) {
           s_of(ev, sv);
           return sqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]) - Yf(dl);
         };
-        double lo = 0.0, hi = 1e-3;
-        for (int t = 0; t < 64 && phi(hi) > 0.0; ++t) {
+        // bracket [lo, hi] with phi(lo) > 0 >= phi(hi), then the Illinois
+        // variant of regula falsi (the retained end's value halved when the
+        // same end is kept twice), down to hi - lo <= tol hi or |phi| <= 1e-14 Y
+        double lo = 0.0, hi = 1e-3, flo = ytr, fhi = phi(hi);
+        for (int t = 0; t < 64 && fhi > 0.0; ++t) {
           lo = hi;
+          flo = fhi;
           hi *= 2.0;
+          fhi = phi(hi);
         }
+        double dl = hi;
+        int side = 0;
         for (int t = 0; t < 200; ++t) {
-          const double mid = 0.5 * (lo + hi);
-          if (phi(mid) > 0.0)
-            lo = mid;
-          else
-            hi = mid;
-          if (hi - lo <= a.tol * fmax(hi, 1e-300)) break;
+          if (hi - lo <= a.tol * fmax(hi, 1e-300)) {
+            dl = 0.5 * (lo + hi);
+            break;
+          }
+          double x = hi - fhi * (hi - lo) / (fhi - flo);
+          if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+          const double fx = phi(x);
+          dl = x;
+          if (fabs(fx) <= 1e-14 * Yf(x)) break;     // |dl - root| ~ 1e-14 Y / (2 G): far below tol dl
+          if (fx > 0.0) {
+            lo = x;
+            flo = fx;
+            if (side == 1) fhi *= 0.5;
+            side = 1;
+          } else {
+            hi = x;
+            fhi = fx;
+            if (side == -1) flo *= 0.5;
+            side = -1;
+          }
         }
-        const double dl = 0.5 * (lo + hi);
         double ev[3], sv[3];
         e_of(dl, ev);
         s_of(ev, sv);

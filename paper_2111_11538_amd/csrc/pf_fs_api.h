@@ -174,7 +174,7 @@ static pf_status fs_residual(pf_fs* f, const double* u, double* R) {
   fs_timed(f, PF_FS_K_GATHER, [&] {
     hipLaunchKernelGGL((pfs::k_fs_gather<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, f->stream, ga);
   });
-  hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, f->stream, (const double*)f->part, f->nb, f->sc,
+  hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(pfs::kFsThreads), 0, f->stream, (const double*)f->part, f->nb, f->sc,
                      (int)pfs::FSR_NORM, 0);
   FSLAUNCH(f);
   return PF_OK;
@@ -195,7 +195,7 @@ static pf_status fs_cg(pf_fs* f, int* iters) {
   FSCHK(f, hipMemcpyAsync(f->sc + pfs::FS_TOL2, &tol2, sizeof(double), hipMemcpyHostToDevice, f->stream));
   const int nbv = f->nb;
   hipLaunchKernelGGL(pfs::k_fs_cg_init, dim3(nbv), dim3(pfs::kFsThreads), 0, f->stream, v, (const double*)f->R);
-  hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, f->stream, (const double*)f->part, nbv, f->sc,
+  hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(pfs::kFsThreads), 0, f->stream, (const double*)f->part, nbv, f->sc,
                      (int)pfs::FSR_INIT, f->cfg.cg_max_iter);
   FSLAUNCH(f);
   const int nbe = fs_blocks(f->g.ne);
@@ -215,10 +215,10 @@ static pf_status fs_cg(pf_fs* f, int* iters) {
         hipLaunchKernelGGL((pfs::k_fs_gather<DIM>), dim3(nbv), dim3(pfs::kFsThreads), 0, f->stream, ga);
       });
       fs_timed(f, PF_FS_K_VECTOR, [&] {
-        hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, f->stream, (const double*)f->part, nbv, f->sc,
+        hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(pfs::kFsThreads), 0, f->stream, (const double*)f->part, nbv, f->sc,
                            (int)pfs::FSR_ALPHA, f->cfg.cg_max_iter);
         hipLaunchKernelGGL(pfs::k_fs_cg_update, dim3(nbv), dim3(pfs::kFsThreads), 0, f->stream, v);
-        hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, f->stream, (const double*)f->part, nbv, f->sc,
+        hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(pfs::kFsThreads), 0, f->stream, (const double*)f->part, nbv, f->sc,
                            (int)pfs::FSR_BETA, f->cfg.cg_max_iter);
       });
       ++launched;
@@ -228,7 +228,7 @@ static pf_status fs_cg(pf_fs* f, int* iters) {
     if (s != PF_OK) return s;
     if (f->host[pfs::FS_CONV] != 0.0) break;
     if (launched >= f->cfg.cg_max_iter) break;
-    chunk = std::min(2 * chunk, 256);
+    chunk = std::min(2 * chunk, 64);
   }
   *iters = (int)f->host[pfs::FS_ITERS];
   if (f->host[pfs::FS_BAD] != 0.0)
@@ -294,7 +294,7 @@ static pf_status fs_solve_dim(pf_fs* f, pf_fs_stats* out) {
     fs_timed(f, PF_FS_K_RETURN, [&] {
       hipLaunchKernelGGL((pfs::k_fs_return<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, s, ra);
     });
-    hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, s, (const double*)f->part, f->nb, f->sc,
+    hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(pfs::kFsThreads), 0, s, (const double*)f->part, f->nb, f->sc,
                        (int)pfs::FSR_MAX2_SUM, 0);
     FSLAUNCH(f);
     if ((rc = fs_read_scalars(f)) != PF_OK) return rc;
@@ -306,7 +306,7 @@ static pf_status fs_solve_dim(pf_fs* f, pf_fs_stats* out) {
   fs_timed(f, PF_FS_K_POST, [&] {
     hipLaunchKernelGGL((pfs::k_fs_post<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, s, pa);
   });
-  hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(64), 0, s, (const double*)f->part, f->nb, f->sc,
+  hipLaunchKernelGGL(pfs::k_fs_reduce, dim3(1), dim3(pfs::kFsThreads), 0, s, (const double*)f->part, f->nb, f->sc,
                      (int)pfs::FSR_MAX2_SUM, 0);
   FSLAUNCH(f);
   if ((rc = fs_read_scalars(f)) != PF_OK) return rc;
