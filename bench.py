@@ -61,7 +61,9 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak, vendor figure
 
 KERNEL_NAMES = {("update", 3, 4): "k_cg_update<float, 3>", ("apply", 3, 4): "k_apply3<float, 8, 0>",
                 ("step", 3, 4): "k_step3<float>", ("mu", 3, 4): "k_mu<float, 3>",
-                ("update", 3, 8): "k_cg_update<double, 3>", ("apply", 3, 8): "k_apply3<double, 8, 0>"}
+                ("update", 3, 8): "k_cg_update<double, 3>", ("apply", 3, 8): "k_apply3<double, 8, 0>",
+                ("update", 2, 4): "k_cg_update<float, 2>", ("apply", 2, 4): "k_apply2<float>",
+                ("step", 2, 4): "k_step<float, 2>", ("mu", 2, 4): "k_mu<float, 2>"}
 
 
 def source_sha():
@@ -241,11 +243,13 @@ def run_batch(args):
         b.set_fields(k, f)
     del saved
     b.step(1)
+    copy_probe(args.copy_probe, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = b.step(args.steps)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
+    copy_probe(args.copy_probe, 1)
     iters = [s["cg_iters"] for s in st]
     es = 4
     bytes_step = sum((s["cg_iters"] * (algorithmic_bytes_per_cell("apply", 2, es) + algorithmic_bytes_per_cell("update", 2, es))
@@ -365,12 +369,14 @@ def run_finite_strain(args):
     fs.set("phi_f", wl.fields["phi_f"])
     fs.set("phi_w", wl.fields["phi_w"])
     fs.timing(True)
+    copy_probe(args.copy_probe, 1)
     torch.cuda.synchronize()
     print(f"[bench] finite strain {shape}: solve", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     st = fs.solve()
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
+    copy_probe(args.copy_probe, 1)
     rep = fs.timing_report()
     fs.close()
     kernels = {}
@@ -384,6 +390,7 @@ def run_finite_strain(args):
     gbs = bpc * cells / (tan_us * 1e-6) / 1e9
     tflops = FS_TANGENT_FLOP_PER_CELL * cells / (tan_us * 1e-6) / 1e12
     dom = max(rep, key=lambda k: rep[k][0])
+    fs_traffic, fs_traffic_src = profiled_traffic(f"finite_strain_3d_{n}", None, 3, 8, name="k_fs_elem<3, true>")
     # small vs finite strain, 2D core-shell of the trend study
     sweep = {}
     f0 = I.ic_core_shell((64, 64), r_core=24.0, r_shell=28.0, noise_seed=I.SEED_BASE + 6)
@@ -415,7 +422,8 @@ def run_finite_strain(args):
         "max_vm_GPa": st["max_vm"] / 1e9, "max_epsP": st["max_epsP"],
         "roofline": {"bound": "alu", "kernel": "tangent (k_fs_elem on dual numbers, one per CG iteration)",
                      "achieved": round(tflops, 2), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": fs_traffic,
+                     "traffic_source": fs_traffic_src,
                      "flop_per_launch": FS_TANGENT_FLOP_PER_CELL * cells, "avg_launch_us": round(tan_us, 2),
                      "hbm_GBps_algorithmic": round(gbs, 1), "hbm_frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
                      "note": ("FP64 operations of the dual-number stress evaluation per cell (8 Gauss points), "
