@@ -39,7 +39,8 @@ class OrConfig(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("h", C.c_double), ("dt", C.c_double),
                 ("mechanics", C.c_int), ("plasticity", C.c_int), ("dirichlet", C.c_int), ("chem_phase", C.c_int),
-                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("species_implicit", C.c_int)]
+                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("species_implicit", C.c_int),
+                ("gext", C.POINTER(C.c_double))]
 
 
 _P = C.POINTER(C.c_double)
@@ -138,7 +139,11 @@ class OracleSim:
 
     def __init__(self, dim, shape, h, dt, params, fields, mechanics=True, plasticity=False, dirichlet=True,
                  chem_phase=True, cg_rtol=1e-10, cg_max_iter=200000, u=None, epsp=None, epsP=None,
-                 implicit=False):
+                 implicit=False, finite_strain=False, fs_rtol=1e-13):
+        """finite_strain: the mechanics of each step is the finite-strain
+        solve of `fs_fe_oracle` (Newton to fs_rtol, then the return map when
+        `plasticity`), whose cell-mean driving forces enter the phase-field
+        update; the small-strain mechanics is then off."""
         self.dim = dim
         self.shape = tuple(shape)
         cfg = OrConfig()
@@ -149,6 +154,8 @@ class OracleSim:
         else:
             cfg.nz, cfg.ny, cfg.nx = shape
         cfg.h, cfg.dt = h, dt
+        if finite_strain:
+            mechanics = False
         cfg.mechanics, cfg.plasticity, cfg.dirichlet, cfg.chem_phase = int(mechanics), int(plasticity), int(dirichlet), int(chem_phase)
         cfg.cg_rtol, cfg.cg_max_iter = cg_rtol, cg_max_iter
         cfg.species_implicit = int(implicit)
@@ -167,6 +174,17 @@ class OracleSim:
                 self.uz[...] = u[2]
         self.epsp = np.zeros((ncomp(dim),) + self.shape) if epsp is None else np.array(epsp, dtype=np.float64)
         self.epsP = np.zeros(self.shape) if epsP is None else np.array(epsP, dtype=np.float64)
+        self.fs = finite_strain
+        if finite_strain:
+            from oracle import fs_fe_oracle as FE
+            self.FE = FE
+            self.h = h
+            self.fs_rtol = fs_rtol
+            self.fs_plastic = plasticity
+            self.fs_u = np.zeros((dim,) + tuple(n + 1 for n in self.shape))
+            self.fs_Fp, self.fs_eP = FE.identity_plastic(self.shape, dim)
+            self.gext = np.zeros(2 * int(np.prod(self.shape)))
+            cfg.gext = self.gext.ctypes.data_as(C.POINTER(C.c_double))
         self._state()
         self.ledger = OrLedger()
         lib().or_ledger_init(C.byref(self.cfg), C.byref(self.cp), C.byref(self.st), C.byref(self.ledger))
@@ -179,13 +197,40 @@ class OracleSim:
         st.epsp, st.epsP = _ptr(self.epsp), _ptr(self.epsP)
         self.st = st
 
+    def fs_solve(self):
+        """The finite-strain mechanics of the current phases: equilibrium from
+        the previous displacement, the return map, the driving forces (into the
+        array the C step adds); returns (newton iterations, max vm, max eps_P)."""
+        g = self.FE.FEGrid(self.dim, self.shape, self.h, self.params, self.f["phi_f"], self.f["phi_w"])
+        u, it, rr = g.solve(self.fs_u, self.fs_Fp, rtol=self.fs_rtol)
+        if rr > self.fs_rtol:
+            raise RuntimeError(f"oracle finite-strain solve stopped at {rr:.3e}")
+        self.fs_u = u
+        if self.fs_plastic:
+            self.fs_Fp, self.fs_eP, _ = g.return_map(u, self.fs_Fp, self.fs_eP)
+        gf, gw = g.driving_forces(u, self.fs_Fp)
+        n = gf.size
+        self.gext[:n] = gf.ravel()
+        self.gext[n:] = gw.ravel()
+        return it, g.max_von_mises(u, self.fs_Fp), float(self.fs_eP.max())
+
+    def fs_energy(self):
+        """Elastic energy of the finite-strain state (displacement and F_P as they are)."""
+        g = self.FE.FEGrid(self.dim, self.shape, self.h, self.params, self.f["phi_f"], self.f["phi_w"])
+        return g.energy(self.fs_u, self.fs_Fp)
+
     def step(self, n=1):
         stats = OrStats()
         for _ in range(n):
+            if self.fs:
+                _, vm, ep = self.fs_solve()
             rc = lib().or_step(C.byref(self.cfg), C.byref(self.cp), C.byref(self.st), C.byref(self.ledger), C.byref(stats))
             if rc != 0:
                 raise RuntimeError(f"oracle step failed with status {rc}")
-        return stats.as_dict()
+        out = stats.as_dict()
+        if self.fs:
+            out["max_vm"], out["max_epsP"] = vm, ep
+        return out
 
     def mech_solve(self):
         stats = OrStats()

@@ -948,6 +948,10 @@ int or_step(const or_config *c, const or_params *p, or_state *s, or_ledger *lg, 
           g_f += mf;
           g_w += mw;
         }
+        if (c->gext) {
+          g_f += c->gext[q];
+          g_w += c->gext[n + q];
+        }
         gf[q] = g_f;
         gw[q] = g_w;
         MO[q] = L.MO;

@@ -45,6 +45,8 @@ typedef struct {
   int cg_max_iter;
   int species_implicit; /* 0: explicit Euler for the species; 1: linearly implicit Euler (or_step);
                            2: as 1 for the transport, then the reaction over dt solved exactly per cell */
+  const double *gext;   /* nullable: [2][ncell] mechanical driving forces d psi / d phi_f, d psi / d phi_w
+                           from outside (the finite-strain mechanics), added to those of the phase fields */
 } or_config;
 
 typedef struct {

@@ -221,3 +221,53 @@ def test_core_shell_disk_converges_to_the_radial_solution():
     assert errs[-1] < errs[1] < errs[0], errs
     small = _small_strain_core_stretch(p, a * h, b * h, n / 2 * h)
     assert abs(small - lam) > 5 * errs[-1] * abs(lam - 1), (small, lam)
+
+
+# ---------------------------------------------------------------------------
+# the phase-field step driven by the finite-strain mechanics
+# ---------------------------------------------------------------------------
+def test_external_driving_force_enters_allen_cahn(oracle):
+    """A uniform box without chemistry, gradients or mechanics: the step moves
+    phi_f and phi_w by exactly -dt L (barrier terms + the external driving
+    force), so adding g moves them by -dt L g (Eq. 29, phase lines)."""
+    p = I.Params()
+    shape = (3, 4)
+    f = {"phi_f": np.full(shape, 0.3), "phi_w": np.full(shape, 0.5), "xO": np.full(shape, 0.2),
+         "xH": np.zeros(shape), "xW": np.zeros(shape)}
+    dt = 1e-6
+    a = oracle.OracleSim(2, shape, 1e-7, dt, p, f, mechanics=False, chem_phase=False, dirichlet=False)
+    a.step()
+    b = oracle.OracleSim(2, shape, 1e-7, dt, p, f, mechanics=False, chem_phase=False, dirichlet=False)
+    g = np.concatenate([np.full(12, 3.0e6), np.full(12, -2.0e6)])
+    keep = g.copy()
+    b.cfg.gext = keep.ctypes.data_as(oracle.C.POINTER(oracle.C.c_double))
+    b.step()
+    df = b.f["phi_f"] - a.f["phi_f"]
+    dw = b.f["phi_w"] - a.f["phi_w"]
+    # the difference of two fields near 0.3 carries their rounding: 1e-6 of the 4.5e-10 shift
+    assert np.allclose(df, -dt * p.L[0] * 3.0e6, rtol=1e-6, atol=0)
+    assert np.allclose(dw, -dt * p.L[2] * -2.0e6, rtol=1e-6, atol=0)
+
+
+def test_energy_decreases_with_finite_strain_mechanics(oracle):
+    """Eq. 26 with the finite-strain mechanics: without reaction, Dirichlet
+    faces and chemical energy (species frozen), the barrier and gradient
+    energy plus the finite-strain elastic energy at equilibrium never
+    increases, and the elastic part takes a share of the drop."""
+    p = I.Params(kfor=0.0, DO=(0.0, 0.0, 0.0), DH=(0.0, 0.0, 0.0), DW=(0.0, 0.0, 0.0))
+    n = 16
+    f = I.ic_core_shell((n, n), r_core=4.5, frame=0, noise_seed=5)
+    f["xO"] = np.where(f["phi_w"] > 0.5, 0.45, 0.05)
+    s = oracle.OracleSim(2, (n, n), I.H_DEFAULT, 1e-2, p, f, plasticity=False, dirichlet=False, chem_phase=False,
+                         finite_strain=True, fs_rtol=1e-12)
+    s.fs_solve()
+    E, Eel = [s.energy() + s.fs_energy()], [s.fs_energy()]
+    for _ in range(15):
+        s.step()
+        s.fs_solve()                  # the elastic energy at equilibrium with the new phases
+        E.append(s.energy() + s.fs_energy())
+        Eel.append(s.fs_energy())
+    dE = np.diff(E)
+    assert np.all(dE <= 1e-10 * abs(E[0])), dE
+    assert E[-1] < E[0]
+    assert Eel[-1] < Eel[0]
