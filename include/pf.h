@@ -539,6 +539,17 @@ pf_status pf_fs_timing(pf_fs *fs, int on);
  * timing was switched on.  Errors: PF_ERR_INVALID_ARG (NULL, unknown kind). */
 pf_status pf_fs_timing_get(pf_fs *fs, int kind, double *ms, long long *launches);
 
+/* Drive a context's phase-field step with the finite-strain mechanics (NULL
+ * detaches).  Each pf_step then imports the current phases into `fs`, runs
+ * pf_fs_solve (from the previous displacement and plastic state of `fs`) and
+ * adds its cell driving forces d psi / d phi_f, d psi / d phi_w (Eq. 33) to
+ * the Allen-Cahn update of that step; the step's stats report the solve's CG
+ * iterations, residual, largest von Mises stress and plastic strain.  The
+ * context must have been created with mechanics = 0 (its small-strain
+ * mechanics off), on the same grid, h and stream; it does not own `fs`.
+ * Errors: PF_ERR_INVALID_ARG (mismatch; message on the context). */
+pf_status pf_fs_attach(pf_ctx *ctx, pf_fs *fs);
+
 /* Message of the last error on this context (fs NULL: errors raised before a
  * context existed). */
 const char *pf_fs_last_error(const pf_fs *fs);

@@ -232,6 +232,10 @@ struct pf_ctx {
   double r0_learned, r0_prev;
   int sp_last_iters;       // implicit species: the most CG iterations of a species in the last step
   double* host_sp;         // pinned copy of the species scalars
+  // attached finite-strain mechanics (pf_fs_attach): solved for the phases
+  // of each step, its cell driving forces enter the phase-field update
+  pf_fs* fs;
+  pf_fs_stats fs_last;
   template <typename T> T* arr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   double* scal() const { return arr<double>(L.o_scal); }
 };
@@ -327,6 +331,13 @@ static void timed_launch(pf_ctx* c, int kind, int cg_launch, K kernel, dim3 grid
   }
   hipExtLaunchKernelGGL(kernel, grid, block, smem, st, e0, e1, 0u, args...);
 }
+
+// finite-strain mechanics of a step (defined with the finite-strain code at the
+// end of this file): imports the current phases (padded, element size es,
+// FP32 pairs when lo is given) into the attached solver, solves, and returns
+// its cell driving forces
+static pf_status fs_couple(pf_ctx* c, const Grid& g, const void* pf_hi, const void* pw_hi, const void* pf_lo,
+                           const void* pw_lo, int es, const double** drive);
 
 // learned start (defined with the network code at the end of this file)
 template <typename T, int DIM> static pf_status learned_start(pf_ctx* c, ElastArgs<T> e, double* part);
@@ -700,6 +711,11 @@ struct Impl {
     }
     CellArgs<T> a = cell_args(c);
     a.part = c->arr<double>(L.o_part_c);
+    if (c->fs) {
+      pf_status s = fs_couple(c, L.g, a.pf, a.pw, L.es == 4 ? (const void*)a.lo[0] : nullptr,
+                              L.es == 4 ? (const void*)a.lo[1] : nullptr, (int)sizeof(T), &a.gext);
+      if (s != PF_OK) return s;
+    }
     timed_launch(c, PF_K_MU, -1, k_mu<T, DIM>, L.gcell, dim3(NT), 0, c->stream, a);
     int ln = L.nb_cell;                // partials of the field update
     if (DIM == 3 && !c->cfg.species_implicit) {
@@ -764,6 +780,12 @@ static void fill_stats(pf_ctx* c, pf_step_stats* s) {
   s->r0_learned = c->r0_learned;
   s->r0_prev = c->r0_prev;
   s->species_iters = c->sp_last_iters;
+  if (c->fs) {                         // the mechanics of the step was the finite-strain solve
+    s->cg_iters = c->fs_last.cg_iters;
+    s->cg_rel_resid = c->fs_last.rel_resid;
+    s->max_vm = c->fs_last.max_vm;
+    s->max_epsP = c->fs_last.max_epsP;
+  }
 }
 
 // ---------------------------------------------------------------------------

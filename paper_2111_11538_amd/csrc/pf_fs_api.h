@@ -316,7 +316,54 @@ static pf_status fs_solve_dim(pf_fs* f, pf_fs_stats* out) {
   return PF_OK;
 }
 
+// phases of a context (padded layout, T, optional FP32 low parts) -> the
+// solver's compact FP64 cell arrays
+template <typename T>
+__global__ __launch_bounds__(pfs::kFsThreads) void k_fs_import(pfk::Grid g, const T* pfh, const T* pwh, const T* pfl,
+                                                               const T* pwl, double* pf, double* pw) {
+  const long long n = (long long)g.nx * g.ny * g.nz;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    const long long r = c / g.nx;
+    const long long e = r * g.px + (c - r * g.nx);
+    pf[c] = (double)pfh[e] + (pfl ? (double)pfl[e] : 0.0);
+    pw[c] = (double)pwh[e] + (pwl ? (double)pwl[e] : 0.0);
+  }
+}
+
+static pf_status fs_couple(pf_ctx* c, const Grid& g, const void* pf_hi, const void* pw_hi, const void* pf_lo,
+                           const void* pw_lo, int es, const double** drive) {
+  pf_fs* f = c->fs;
+  const int nb = fs_blocks(f->g.ne);
+  if (es == 8)
+    hipLaunchKernelGGL((k_fs_import<double>), dim3(nb), dim3(pfs::kFsThreads), 0, c->stream, g,
+                       (const double*)pf_hi, (const double*)pw_hi, (const double*)pf_lo, (const double*)pw_lo, f->pf,
+                       f->pw);
+  else
+    hipLaunchKernelGGL((k_fs_import<float>), dim3(nb), dim3(pfs::kFsThreads), 0, c->stream, g, (const float*)pf_hi,
+                       (const float*)pw_hi, (const float*)pf_lo, (const float*)pw_lo, f->pf, f->pw);
+  HIPCHK(c, hipGetLastError());
+  const pf_status s = pf_fs_solve(f, &c->fs_last);
+  if (s != PF_OK) return fail(c, s, "finite-strain mechanics: %s", f->err);
+  *drive = f->drive;
+  return PF_OK;
+}
+
 extern "C" {
+
+pf_status pf_fs_attach(pf_ctx* ctx, pf_fs* fs) {
+  if (!ctx) return fs_fail(nullptr, PF_ERR_INVALID_ARG, "pf_fs_attach: NULL context");
+  if (fs) {
+    const pf_config& a = ctx->cfg;
+    const pf_fs_config& b = fs->cfg;
+    if (a.dim != b.dim || a.nx != b.nx || a.ny != b.ny || a.nz != b.nz || a.h != b.h)
+      return fail(ctx, PF_ERR_INVALID_ARG, "pf_fs_attach: the grids differ");
+    if (a.mechanics) return fail(ctx, PF_ERR_INVALID_ARG, "pf_fs_attach: the context's small-strain mechanics must be off");
+    if (ctx->stream != fs->stream) return fail(ctx, PF_ERR_INVALID_ARG, "pf_fs_attach: the streams differ");
+  }
+  ctx->fs = fs;
+  ctx->fs_last = pf_fs_stats{};
+  return PF_OK;
+}
 
 size_t pf_fs_workspace_bytes(const pf_fs_config* cfg) {
   if (!fs_valid(cfg)) return 0;

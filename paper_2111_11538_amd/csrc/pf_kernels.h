@@ -1575,6 +1575,9 @@ struct CellArgs {
   T* K;
   T* G;
   T* mu_out;
+  // finite-strain mechanics: [2][nx ny nz] compact FP64 cell driving forces
+  // d psi / d phi_f, d psi / d phi_w added to those of the phase fields (null: none)
+  const double* gext;
   double* part;            // [NQ][nblocks]
 };
 
@@ -1775,6 +1778,12 @@ __device__ __forceinline__ void cell_update(const CellArgs<T>& a, int e, T pf, T
     gf += q.dTp * phi_el + q.dT * (q.dhf * pe_f - q.dhg * pe_g) - q.eTp * T(3) * q.K * tr;
     gw += q.dT * (q.dhw * pe_w - q.dhg * pe_g);
     vm = T(1.2247448713915890491) * T(2) * q.G * nd;   // sqrt(3/2) |dev sigma|
+  }
+  if (a.gext) {
+    const int ci = e % g.px, cr = e / g.px;
+    const long c = (long)cr * g.nx + ci;      // compact index of (i, j, k): rows of nx cells
+    gf += (T)a.gext[c];
+    gw += (T)a.gext[(long)g.nx * g.ny * g.nz + c];
   }
   // reaction (Eq. 27, 28): forward rate, zero once the cell is full of water;
   // mole fractions below zero take no part in it

@@ -96,7 +96,7 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_c
            "pf_nn_param_count", "pf_nn_workspace_bytes", "pf_nn_init", "pf_nn_destroy", "pf_nn_last_error", "pf_nn_weights", "pf_nn_copy",
            "pf_nn_forward", "pf_nn_loss", "pf_nn_backward", "pf_nn_adam", "pf_nn_layer", "pf_nn_increment_scale",
            "pf_nn_pack", "pf_nn_attach", "pf_increment_scale_static",
-           "pf_fs_workspace_bytes", "pf_fs_init", "pf_fs_fields", "pf_fs_solve", "pf_fs_timing", "pf_fs_timing_get",
+           "pf_fs_workspace_bytes", "pf_fs_init", "pf_fs_fields", "pf_fs_solve", "pf_fs_timing", "pf_fs_timing_get", "pf_fs_attach",
            "pf_fs_last_error", "pf_fs_destroy")
 KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn", "species")
 
@@ -190,6 +190,8 @@ def lib():
         L.pf_fs_timing.restype = C.c_int
         L.pf_fs_timing_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
         L.pf_fs_timing_get.restype = C.c_int
+        L.pf_fs_attach.argtypes = [C.c_void_p, C.c_void_p]
+        L.pf_fs_attach.restype = C.c_int
         L.pf_fs_last_error.argtypes = [C.c_void_p]
         L.pf_fs_last_error.restype = C.c_char_p
         L.pf_fs_destroy.argtypes = [C.c_void_p]
@@ -325,6 +327,13 @@ class Context:
         st = pf_step_stats()
         self._check(lib().pf_step(self.ctx, int(n), C.byref(st)))
         return st.as_dict()
+
+    def attach_fs(self, fs):
+        """Drive this context's steps with the finite-strain mechanics of a
+        ``FiniteStrain`` on the same grid and stream (None detaches); the
+        context must have been created with mechanics=False."""
+        self._fs = fs
+        self._check(lib().pf_fs_attach(self.ctx, fs.ctx if fs is not None else None))
 
     def mech_solve(self, warm="zero"):
         st = pf_step_stats()

@@ -145,3 +145,88 @@ def test_zero_load_and_errors():
     with pytest.raises(P.PFError):
         g._check(P.lib().pf_fs_fields(g.ctx, 0, 0, P.C.c_void_p(g.workspace.data_ptr()), 8, 1))
     g.close()
+
+
+def _coupled_pair(oracle, dim, n, precision, plastic, implicit, dt, steps, p, coupled=True):
+    from paper_2111_11538_amd import pf as P
+    h = I.H_DEFAULT
+    shape = (n,) * dim
+    f = I.ic_core_shell(shape, r_core=0.3 * n, r_shell=0.4 * n, frame=2 if dim == 2 else 0,
+                        noise_seed=I.SEED_BASE + 9)
+    say(f"finite strain coupled={coupled} dim={dim} n={n} {precision} plastic={plastic} implicit={implicit} "
+        f"steps={steps}")
+    kw = dict(species_implicit=implicit, species_rtol=1e-12 if precision == "fp64" else 1e-6) if implicit else {}
+    g = P.Context(dim, shape, h, dt, p, precision=precision, mechanics=False, plasticity=plastic,
+                  cg_rtol=1e-12 if precision == "fp64" else 1e-6, **kw)
+    fs = P.FiniteStrain(dim, shape, h, p, plasticity=plastic, newton_rtol=1e-12)
+    if coupled:
+        g.attach_fs(fs)
+    g.set_fields(f)
+    gst = g.step(steps)
+    out = g.fields(["phi_f", "phi_w", "xO", "xH", "xW"])
+    g.close()
+    fs.close()
+    o = oracle.OracleSim(dim, shape, h, dt, p, f, mechanics=False, plasticity=plastic, finite_strain=coupled,
+                         fs_rtol=1e-13, implicit=implicit)
+    ost = o.step(steps)
+    return f, out, gst, o, ost
+
+
+# 3D case: gas diffusivities set to the solids' so that the explicit step
+# (the LDS-tiled 3D field update) can take dt large enough for the
+# finite-strain driving forces to move the phases well above rounding
+_P_SLOW_GAS = dict(DO=(2.16e-11,) * 3, DH=(2.5e-11,) * 3, DW=(2.5e-20, 2.5e-11, 2.5e-20))
+
+
+@pytest.mark.parametrize("dim,n,precision,plastic,implicit,steps",
+                         [(2, 20, "fp64", False, 2, 3), (2, 20, "fp64", True, 2, 3),
+                          (3, 8, "fp64", True, 0, 2), (2, 20, "mixed", True, 2, 3)])
+def test_coupled_step_matches_oracle(oracle, dim, n, precision, plastic, implicit, steps):
+    """Steps whose mechanics is the finite-strain solve (pf_fs_attach) against
+    the oracle's coupled mode, field increments to 1e-6 relative in FP64 (the
+    driving forces carry the Newton tolerance) and to the mixed gates in
+    mixed precision; in FP64 also the part of the phase increments that the
+    driving forces make (coupled minus uncoupled run, on both sides), to 1e-6."""
+    if dim == 3:
+        p = I.Params(Omega_f=0.4, **_P_SLOW_GAS)
+        dt = I.stable_dt(p, I.H_DEFAULT, dim)
+    else:
+        p = I.Params(Omega_f=0.4)
+        dt = 3e4 * I.stable_dt(p, I.H_DEFAULT, dim)
+    f0, out, gst, o, ost = _coupled_pair(oracle, dim, n, precision, plastic, implicit, dt, steps, p)
+    tol_i = {"phi_f": 1e-6, "phi_w": 1e-6, "xO": 1e-6, "xH": 1e-6, "xW": 1e-6} if precision == "fp64" else \
+        {"phi_f": 1e-3, "phi_w": 1e-3, "xO": 1e-4, "xH": 1e-4, "xW": 1e-3}
+    for k in ("phi_f", "phi_w", "xO", "xH", "xW"):
+        db, da = o.f[k] - f0[k], out[k] - f0[k]
+        if np.sqrt(np.mean(db * db)) < 1e-12:
+            assert np.sqrt(np.mean((da - db) ** 2)) < 1e-14, k
+            continue
+        err = rel(da, db)
+        say(k, f"increment error {err:.2e}")
+        assert err < tol_i[k], (k, err)
+    assert abs(gst["max_vm"] - ost["max_vm"]) < 1e-6 * ost["max_vm"], (gst["max_vm"], ost["max_vm"])
+    if plastic:
+        assert abs(gst["max_epsP"] - ost["max_epsP"]) < 1e-6 * ost["max_epsP"]
+        assert gst["max_epsP"] > 0
+    if precision == "fp64":
+        _, out0, _, o0, _ = _coupled_pair(oracle, dim, n, precision, plastic, implicit, dt, steps, p, coupled=False)
+        for k in ("phi_f", "phi_w"):
+            eo, eg = o.f[k] - o0.f[k], out[k] - out0[k]
+            say(k, f"driving-force effect {np.linalg.norm(eo):.3e}, error {rel(eg, eo):.2e}")
+            assert np.linalg.norm(eo) > 1e-9 * np.sqrt(eo.size)
+            assert rel(eg, eo) < 1e-6, (k, rel(eg, eo))
+
+
+def test_attach_checks_the_grid_and_the_mechanics():
+    from paper_2111_11538_amd import pf as P
+    p = I.Params()
+    fs = P.FiniteStrain(2, (8, 9), I.H_DEFAULT, p)
+    g = P.Context(2, (8, 9), I.H_DEFAULT, 1e-9, p, mechanics=True)
+    with pytest.raises(P.PFError):
+        g.attach_fs(fs)
+    g.close()
+    g = P.Context(2, (8, 10), I.H_DEFAULT, 1e-9, p, mechanics=False)
+    with pytest.raises(P.PFError):
+        g.attach_fs(fs)
+    g.close()
+    fs.close()
