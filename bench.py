@@ -281,8 +281,10 @@ def run_trends(args):
     wuestite core (radius 24 cells, 1.9 um) in a 4-cell ferrite shell inside a
     5 um gas box, advanced with the implicit species update and the reaction
     solved exactly per cell (dt = 10 ms), for Omega_f in 0 ... 0.4 (elastic)
-    and 0.1, 0.4 (elasto-plastic); records the reduction degree (Eq. 39), the
-    largest von Mises stress and plastic strain over time."""
+    and 0.1, 0.4 (elasto-plastic), with the small-strain mechanics of the step
+    or (--kinematics finite) the finite-strain solver attached; records the
+    reduction degree (Eq. 39), the largest von Mises stress and plastic strain
+    over time."""
     import torch
     from paper_2111_11538_amd import inputs as I
     from paper_2111_11538_amd import pf
@@ -294,10 +296,15 @@ def run_trends(args):
     cases = [(om, False) for om in (0.0, 0.1, 0.2, 0.25, 0.3, 0.4)] + [(0.1, True), (0.4, True)]
     out = {}
     t0 = time.perf_counter()
+    finite = args.kinematics == "finite"
     for om, plastic in cases:
         p = I.Params(Omega_f=om)
         c = pf.Context(2, (n, n), I.H_DEFAULT, dt, p, precision="fp64", plasticity=plastic, cg_rtol=1e-8,
-                       species_implicit=2, species_rtol=1e-10)
+                       species_implicit=2, species_rtol=1e-10, mechanics=not finite)
+        fs = None
+        if finite:
+            fs = pf.FiniteStrain(2, (n, n), I.H_DEFAULT, p, plasticity=plastic, newton_rtol=1e-8, cg_rtol=1e-3)
+            c.attach_fs(fs)
         c.set_fields(f0)
         rec = {"t_s": [], "red_degree": [], "max_vm_GPa": [], "max_epsP": [], "mean_phi_f": []}
         vm_max = 0.0
@@ -312,6 +319,8 @@ def run_trends(args):
         rec["peak_vm_GPa_sampled"] = round(vm_max / 1e9, 4)
         rec["O_drift"] = st["O_drift"]
         c.close()
+        if fs is not None:
+            fs.close()
         key = f"Omega_f={om:g} {'elasto-plastic' if plastic else 'elastic'}"
         out[key] = rec
         print(f"[trends] {key}: reduction degree {rec['red_degree'][-1]:.4f} at {T:g} s, largest sampled "
@@ -320,7 +329,8 @@ def run_trends(args):
     torch.cuda.synchronize()
     line = {"metric": "core-shell trends (Sec. 4.2): reduction degree and largest von Mises stress over time",
             "workload": f"2D core-shell {n}x{n}, h {I.H_DEFAULT:g} m, core r 24, shell to r 28, gas box; "
-                        f"dt {dt:g} s, {steps} steps, species implicit with the reaction solved exactly",
+                        f"dt {dt:g} s, {steps} steps, species implicit with the reaction solved exactly; "
+                        f"{'finite-strain' if finite else 'small-strain'} mechanics",
             "cases": out}
     print(json.dumps(line), flush=True)
 
@@ -605,6 +615,8 @@ def main():
     ap.add_argument("--train-lr", type=float, default=1e-4, help="Adam learning rate of the network's training")
     ap.add_argument("--train-batch", type=int, default=4, help="64^3 crops per training minibatch")
     ap.add_argument("--trend-seconds", type=float, default=120.0, help="model time of the core-shell trend runs")
+    ap.add_argument("--kinematics", default="small", choices=("small", "finite"),
+                    help="mechanics of the trend runs: small strain (in the step) or the finite-strain solver")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="copy this many MiB with a plain device copy first (counter calibration under a profiler) "
                          "and once before and after the timed legs (markers in the trace)")

@@ -288,12 +288,16 @@ class FEGrid:
 
     def solve(self, u0, Fp, rtol=1e-13, max_iter=50):
         """Newton on R(u) = 0 (free dofs) from u0, with a halving line search
-        on ||R||; stop at ||R|| <= rtol ||R(0)||.  Returns u, iterations,
-        ||R|| / ||R(0)||."""
+        on ||R||; stop at ||R|| <= rtol ||R(0)||; u = 0 when there is no load.
+        Returns u, iterations, ||R|| / ||R(0)||."""
         u = np.array(u0, float)
         u[self.fixed] = 0.0
         r0 = np.linalg.norm(self.residual(np.zeros_like(u), Fp))
-        if r0 == 0.0:
+        # without transformation misfit P(I) vanishes only up to rounding: a
+        # load below 1e-12 of (K + G)_max h^(d-1) sqrt(dofs) is no load
+        zero_load = 1e-12 * max(self.p.K[a] + self.p.G[a] for a in range(3)) * self.h ** (self.dim - 1) \
+            * math.sqrt(u.size)
+        if r0 <= zero_load:
             return np.zeros_like(u), 0, 0.0
         free = self.free.ravel()
         R = self.residual(u, Fp)

@@ -250,7 +250,12 @@ static pf_status fs_solve_dim(pf_fs* f, pf_fs_stats* out) {
   hipLaunchKernelGGL((pfs::k_fs_diag<DIM>), dim3(f->nb), dim3(pfs::kFsThreads), 0, s, f->g, f->p,
                      (const double*)f->pf, (const double*)f->pw, f->dinv);
   FSLAUNCH(f);
-  if (!(r0 > 0.0)) {
+  // a load at the rounding level of the stress evaluation (no transformation
+  // misfit: P(I) is zero only up to rounding) is no load: u = 0
+  double mod = 0.0;
+  for (int a = 0; a < 3; ++a) mod = std::max(mod, f->p.K[a] + f->p.G[a]);
+  const double zero_load = 1e-12 * mod * std::pow(f->cfg.h, DIM - 1) * std::sqrt((double)f->nd);
+  if (!(r0 > zero_load)) {
     if (!std::isfinite(r0)) return fs_fail(f, PF_ERR_NONFINITE, "finite strain: non-finite load");
     FSCHK(f, hipMemcpyAsync(f->u, f->x, f->nd * sizeof(double), hipMemcpyDeviceToDevice, s));   // u = 0
   } else {
