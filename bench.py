@@ -294,6 +294,8 @@ def run_trends(args):
     steps = every * 24
     f0 = I.ic_core_shell((n, n), r_core=24.0, r_shell=28.0, noise_seed=I.SEED_BASE + 6)
     cases = [(om, False) for om in (0.0, 0.1, 0.2, 0.25, 0.3, 0.4)] + [(0.1, True), (0.4, True)]
+    if args.trend_cases:                 # e.g. "0.1e,0.4p": Omega_f and e(lastic) / p(lastic)
+        cases = [(float(c[:-1]), c[-1] == "p") for c in args.trend_cases.split(",")]
     out = {}
     t0 = time.perf_counter()
     finite = args.kinematics == "finite"
@@ -316,6 +318,9 @@ def run_trends(args):
             rec["max_vm_GPa"].append(round(st["max_vm"] / 1e9, 4))
             rec["max_epsP"].append(round(st["max_epsP"], 5))
             rec["mean_phi_f"].append(round(float(c.get("phi_f").mean()), 5))
+            print(f"[trends]   Omega_f={om:g} {'p' if plastic else 'e'} t={rec['t_s'][-1]:g} s f={rec['red_degree'][-1]:.4f} "
+                  f"vm={rec['max_vm_GPa'][-1]:.3f} GPa cg/step(last)={st['cg_iters']} ({time.perf_counter() - t0:.0f} s)",
+                  file=sys.stderr, flush=True)
         rec["peak_vm_GPa_sampled"] = round(vm_max / 1e9, 4)
         rec["O_drift"] = st["O_drift"]
         c.close()
@@ -615,6 +620,7 @@ def main():
     ap.add_argument("--train-lr", type=float, default=1e-4, help="Adam learning rate of the network's training")
     ap.add_argument("--train-batch", type=int, default=4, help="64^3 crops per training minibatch")
     ap.add_argument("--trend-seconds", type=float, default=120.0, help="model time of the core-shell trend runs")
+    ap.add_argument("--trend-cases", default="", help="comma list of Omega_f with e (elastic) or p (plastic), e.g. 0.1e,0.4p")
     ap.add_argument("--kinematics", default="small", choices=("small", "finite"),
                     help="mechanics of the trend runs: small strain (in the step) or the finite-strain solver")
     ap.add_argument("--copy-probe", type=int, default=0,
