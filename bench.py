@@ -97,13 +97,14 @@ def pf_kinds():
     return pf.KERNEL_KINDS
 
 
-def run_gpu(wl, precision, steps, warmup, timing, rtol, fields=None, net=None, every=1):
+def run_gpu(wl, precision, steps, warmup, timing, rtol, fields=None, net=None, every=1, precond="jacobi"):
     """timing: None (no events), or the kernel kinds to bracket with events
     (the CG kernels on every `every`-th iteration of each solve)."""
     import torch
     from paper_2111_11538_amd import pf
     ctx = pf.Context(wl.dim, wl.shape, wl.h, wl.dt, wl.params, device=0, precision=precision,
-                     plasticity=wl.plasticity, cg_rtol=rtol, warm="learned" if net is not None else "prev")
+                     plasticity=wl.plasticity, cg_rtol=rtol, warm="learned" if net is not None else "prev",
+                     cg_precond=precond)
     ctx.set_fields(fields if fields is not None else wl.fields)
     if net is not None:
         net.attach(ctx)
@@ -243,13 +244,13 @@ def run_batch(args):
         b.set_fields(k, f)
     del saved
     b.step(1)
-    copy_probe(args.copy_probe, 1)
+    trace_marker(args.copy_probe)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = b.step(args.steps)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    copy_probe(args.copy_probe, 1)
+    trace_marker(args.copy_probe)
     iters = [s["cg_iters"] for s in st]
     es = 4
     bytes_step = sum((s["cg_iters"] * (algorithmic_bytes_per_cell("apply", 2, es) + algorithmic_bytes_per_cell("update", 2, es))
@@ -384,14 +385,14 @@ def run_finite_strain(args):
     fs.set("phi_f", wl.fields["phi_f"])
     fs.set("phi_w", wl.fields["phi_w"])
     fs.timing(True)
-    copy_probe(args.copy_probe, 1)
+    trace_marker(args.copy_probe)
     torch.cuda.synchronize()
     print(f"[bench] finite strain {shape}: solve", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     st = fs.solve()
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    copy_probe(args.copy_probe, 1)
+    trace_marker(args.copy_probe)
     rep = fs.timing_report()
     fs.close()
     kernels = {}
@@ -581,19 +582,31 @@ def settle(wl, steps):
 
 
 def copy_probe(mib, times):
-    """A plain device copy of `mib` MiB, `times` times (counter calibration
-    under a profiler, and a marker that brackets the dispatches of the timed
-    legs in its trace); nothing when mib is 0."""
+    """Counter calibration under a profiler: `times` plain device copies of
+    `mib` MiB between two trace markers (nothing when mib is 0)."""
     if mib <= 0:
         return
     import torch
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    trace_marker(mib)
     for _ in range(times):
         dst.copy_(src)
+    trace_marker(mib)
     torch.cuda.synchronize()
     del src, dst
+
+
+def trace_marker(mib):
+    """A kernel no other part of the run launches (a flip of four numbers):
+    brackets the calibration copies and the timed legs in a profiler's trace
+    (nothing when mib is 0)."""
+    if mib <= 0:
+        return
+    import torch
+    torch.flip(torch.arange(4, device="cuda"), dims=(0,))
+    torch.cuda.synchronize()
 
 
 def main():
@@ -625,7 +638,7 @@ def main():
                     help="mechanics of the trend runs: small strain (in the step) or the finite-strain solver")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="copy this many MiB with a plain device copy first (counter calibration under a profiler) "
-                         "and once before and after the timed legs (markers in the trace)")
+                         "and mark the calibration copies and the timed legs with a flip kernel in the trace")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -667,12 +680,12 @@ def main():
     # HIP events attached to every dispatch (each timed dispatch then follows
     # a timed one, which keeps the events' own overhead out of the kernel's
     # interval); the throughput run below carries no events
-    copy_probe(args.copy_probe, 1)
+    trace_marker(args.copy_probe)
     brk = run_gpu(wl, wl.precision, args.steps, args.warmup, pf_kinds(), wl.cg_rtol, fields=start, net=net)
     kern = brk["kernels"]
     dom = max((k for k in ("apply", "update", "step", "mu", "solve_setup", "nn")), key=lambda k: kern[k][0])
     res = run_gpu(wl, wl.precision, args.steps, args.warmup, None, wl.cg_rtol, fields=start, net=net)
-    copy_probe(args.copy_probe, 1)
+    trace_marker(args.copy_probe)
     ms = 1e3 * res["seconds"] / args.steps
     value = ncell * args.steps / res["seconds"]
 

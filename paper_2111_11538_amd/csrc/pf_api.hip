@@ -16,6 +16,7 @@
 #include "pf_kernels.h"
 #include "pf_species.h"
 #include "pf_step3.h"
+#include "pf_mg.h"
 
 using namespace pfk;
 
@@ -62,6 +63,21 @@ struct Layout {
   size_t o_sp[8][3];
   size_t o_sp_part, o_sp_scal;
   int nb_sp;
+  // multigrid preconditioner (3D, cg_precond == 1): level 0 is the grid of
+  // the solve (its K, G, D^-1; b is the CG residual, x the preconditioned z);
+  // levels 1 .. mg_n - 1 own their moduli, diagonal, b, x, a second x and r
+  struct MGLevel {
+    Grid g;
+    int kz;
+    dim3 grid;             // apply-kernel grid of the level
+    double h;
+    size_t oK, oG, odi[3], ob[3], ox[3], oxt[3], orr[3];
+  };
+  static constexpr int kMGMax = 10;
+  int mg_n;
+  MGLevel mg[kMGMax];
+  size_t o_mg_part;
+  int nb_mg;               // partials of the level-0 smoothing (its apply grid)
   size_t total;
 };
 
@@ -76,6 +92,8 @@ bool valid_cfg(const pf_config* c, char* msg, size_t len) {
   if (c->warm != PF_WARM_ZERO && c->warm != PF_WARM_PREV && c->warm != PF_WARM_LEARNED) { snprintf(msg, len, "unknown warm start %d", c->warm); return false; }
   if (c->warm == PF_WARM_LEARNED && (c->dim != 3 || !c->mechanics)) { snprintf(msg, len, "the learned warm start needs dim 3 and mechanics"); return false; }
   if (c->species_implicit < 0 || c->species_implicit > 2) { snprintf(msg, len, "species_implicit must be 0, 1 or 2"); return false; }
+  if (c->cg_precond != 0 && c->cg_precond != 1) { snprintf(msg, len, "cg_precond must be 0 or 1"); return false; }
+  if (c->cg_precond == 1 && c->dim != 3) { snprintf(msg, len, "the multigrid preconditioner needs dim 3"); return false; }
   if (c->species_implicit && (!(c->species_rtol > 0.0) || c->species_max_iter < 1)) { snprintf(msg, len, "species_rtol > 0 and species_max_iter >= 1 required"); return false; }
   long long px = (c->nx + 15) / 16 * 16;
   if (px * c->ny * (long long)c->nz >= (1LL << 31) / 8) { snprintf(msg, len, "grid too large for 32-bit indexing"); return false; }
@@ -164,6 +182,51 @@ Layout make_layout(const pf_config* c) {
       for (int q = 0; q < 3; ++q) L.o_sp[a][q] = take(arr);
     L.o_sp_part = take(9 * (size_t)L.nb_sp * sizeof(double));
     L.o_sp_scal = take(SP_COUNT * sizeof(double));
+  }
+  L.mg_n = 0;
+  if (c->cg_precond == 1 && c->dim == 3) {
+    auto apply_geom = [](Layout::MGLevel& m) {
+      const int nbx = (m.g.nx + TX - 1) / TX, nby8 = (m.g.ny + kApplyBY - 1) / kApplyBY;
+      m.kz = kSlabMax;
+      while (m.kz > 1 && (long long)nbx * nby8 * ((m.g.nz + m.kz - 1) / m.kz) < 512) m.kz /= 2;
+      m.grid = dim3(nbx, nby8, (m.g.nz + m.kz - 1) / m.kz);
+    };
+    Layout::MGLevel& m0 = L.mg[0];
+    m0.g = g;
+    m0.h = c->h;
+    apply_geom(m0);
+    m0.oK = L.o_K;
+    m0.oG = L.o_G;
+    for (int d = 0; d < 3; ++d) {
+      m0.odi[d] = L.o_di[d];
+      m0.ob[d] = L.o_r[d];
+      m0.ox[d] = L.o_z[d];
+      m0.oxt[d] = take(arr);
+      m0.orr[d] = take(arr);
+    }
+    L.mg_n = 1;
+    while (L.mg_n < Layout::kMGMax) {
+      const Grid& f = L.mg[L.mg_n - 1].g;
+      if ((f.nx & 1) || (f.ny & 1) || (f.nz & 1) || std::min(f.nx, std::min(f.ny, f.nz)) <= 8) break;
+      Layout::MGLevel& m = L.mg[L.mg_n];
+      m.g.nx = f.nx / 2; m.g.ny = f.ny / 2; m.g.nz = f.nz / 2;
+      m.g.px = (m.g.nx + 15) / 16 * 16;
+      m.g.n = m.g.px * m.g.ny * m.g.nz;
+      m.g.ns = m.g.n;
+      m.h = 2.0 * L.mg[L.mg_n - 1].h;
+      apply_geom(m);
+      const size_t la = align_up((size_t)m.g.n * L.es);
+      m.oK = take(la);
+      m.oG = take(la);
+      for (int d = 0; d < 3; ++d) {
+        m.odi[d] = take(la); m.ob[d] = take(la); m.ox[d] = take(la); m.oxt[d] = take(la); m.orr[d] = take(la);
+      }
+      ++L.mg_n;
+    }
+    L.nb_mg = (int)(m0.grid.x * m0.grid.y * m0.grid.z);
+    int nb_mg_max = 0;
+    for (int l = 0; l < L.mg_n; ++l) nb_mg_max = std::max(nb_mg_max, (int)(L.mg[l].grid.x * L.mg[l].grid.y * L.mg[l].grid.z));
+    L.o_mg_part = take((size_t)nb_mg_max * sizeof(double));
   }
   if (c->warm == PF_WARM_LEARNED) {
     for (int d = 0; d < 3; ++d) { L.o_uo[d] = take(arr); L.o_du[d] = take(arr); }
@@ -313,7 +376,8 @@ static void timed_launch(pf_ctx* c, int kind, int cg_launch, K kernel, dim3 grid
     } else {
       const bool sampled = (cg_launch + c->solves) % c->timing_every == 0;
       const bool guard = kind == PF_K_UPDATE && (cg_launch + 1 + c->solves) % c->timing_every == 0;
-      const bool cg_on = ((c->timing >> PF_K_APPLY) & 1u) || ((c->timing >> PF_K_UPDATE) & 1u);
+      const bool cg_on = ((c->timing >> PF_K_APPLY) & 1u) || ((c->timing >> PF_K_UPDATE) & 1u) ||
+                         ((c->timing >> PF_K_PRECOND) & 1u);
       rec = cg_on && (sampled || guard);
       count = on && sampled;
     }
@@ -428,6 +492,104 @@ struct Impl {
     }
   }
 
+  // Multigrid preconditioner (3D).  Grid-stride launches over a level.
+  static dim3 mg_blocks(const Grid& g) {
+    const long n = (long)g.nx * g.ny * g.nz;
+    return dim3((unsigned)std::max(1L, std::min(4096L, (n + NT - 1) / NT)));
+  }
+  static Vec3<T> mg_vec(pf_ctx* c, const size_t (&o)[3]) {
+    Vec3<T> v;
+    for (int d = 0; d < 3; ++d) v.a[d] = c->arr<T>(o[d]);
+    return v;
+  }
+  static CVec3<T> mg_cvec(pf_ctx* c, const size_t (&o)[3]) {
+    CVec3<T> v;
+    for (int d = 0; d < 3; ++d) v.a[d] = c->arr<T>(o[d]);
+    return v;
+  }
+  // coarse moduli and Jacobi diagonals of every level from the moduli the
+  // set-up pass wrote (once per solve)
+  static void mg_setup(pf_ctx* c) {
+    const Layout& L = c->L;
+    for (int l = 1; l < L.mg_n; ++l) {
+      const Layout::MGLevel& f = L.mg[l - 1];
+      const Layout::MGLevel& m = L.mg[l];
+      timed_launch(c, PF_K_PRECOND, -1, k_mg_coarsen<T>, mg_blocks(m.g), dim3(NT), 0, c->stream, f.g, m.g,
+                   (const T*)c->arr<T>(f.oK), (const T*)c->arr<T>(f.oG), c->arr<T>(m.oK), c->arr<T>(m.oG));
+      timed_launch(c, PF_K_PRECOND, -1, k_mg_diag<T>, mg_blocks(m.g), dim3(NT), 0, c->stream, m.g, (T)(1.0 / m.h),
+                   (const T*)c->arr<T>(m.oK), (const T*)c->arr<T>(m.oG), mg_vec(c, m.odi));
+    }
+  }
+  // z = M^-1 r: one V-cycle from zero on the CG residual (level 0: b = r,
+  // x = z), then r.z into the r.z partials CG reads (n_rz slots of part_u).
+  // j: the CG launch index the cycle follows (-1: before the first).
+  static void mg_vcycle(pf_ctx* c, const ElastArgs<T>& e, int j, int n_rz) {
+    constexpr double kOmega = 0.4;
+    constexpr int kNu = 2, kCoarseSweeps = 8;
+    static_assert(kNu == 2, "the sweeps below alternate x and xt for two pre- and post-smoothing sweeps");
+    const Layout& L = c->L;
+    hipStream_t st = c->stream;
+    double* part = c->arr<double>(L.o_mg_part);
+    const double* scal = c->scal();
+    const int last = L.mg_n - 1;
+    // one damped Jacobi sweep xout = xin + omega D^-1 (b - A xin) of level l,
+    // or with omega = 0 the residual xout = b - A xin
+    auto sweep = [&](int l, const size_t (&xin)[3], const size_t (&xout)[3], double omega) {
+      const Layout::MGLevel& m = L.mg[l];
+      ElastArgs<T> a = e;
+      a.g = m.g;
+      a.p.ih = (T)(1.0 / m.h);
+      a.K = c->arr<T>(m.oK);
+      a.G = c->arr<T>(m.oG);
+      for (int d = 0; d < 3; ++d) {
+        a.z[d] = c->arr<T>(xin[d]);
+        a.u[d] = c->arr<T>(xin[d]);      // not read
+        a.jr[d] = c->arr<T>(m.ob[d]);
+        a.dinv[d] = c->arr<T>(m.odi[d]);
+        a.o1[d] = c->arr<T>(xout[d]);
+      }
+      a.part = part;
+      a.kz = m.kz;
+      a.omega = omega;
+      a.scal = c->scal();
+      timed_launch(c, PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH>, m.grid, dim3(ApplyTile<kApplyBY>::NTB), 0,
+                   st, a);
+    };
+    auto jacobi0 = [&](int l, const size_t (&xout)[3]) {
+      const Layout::MGLevel& m = L.mg[l];
+      timed_launch(c, PF_K_PRECOND, j, k_mg_jacobi0<T>, mg_blocks(m.g), dim3(NT), 0, st, m.g, (T)kOmega,
+                   mg_cvec(c, m.odi), mg_cvec(c, m.ob), mg_vec(c, xout), scal);
+    };
+    for (int l = 0; l < last; ++l) {             // pre-smoothing and restriction, down to the coarsest
+      const Layout::MGLevel& m = L.mg[l];
+      jacobi0(l, m.oxt);
+      sweep(l, m.oxt, m.ox, kOmega);
+      sweep(l, m.ox, m.orr, 0.0);
+      const Layout::MGLevel& mc = L.mg[l + 1];
+      timed_launch(c, PF_K_PRECOND, j, k_mg_restrict<T>, mg_blocks(mc.g), dim3(NT), 0, st, m.g, mc.g,
+                   mg_cvec(c, m.orr), mg_vec(c, mc.ob), scal);
+    }
+    {                                            // coarsest level: a fixed number of sweeps from zero
+      const Layout::MGLevel& m = L.mg[last];
+      static_assert(kCoarseSweeps % 2 == 0, "the coarsest sweeps end in x");
+      jacobi0(last, m.oxt);
+      for (int s = 1; s < kCoarseSweeps; ++s) {
+        if (s & 1) sweep(last, m.oxt, m.ox, kOmega);
+        else sweep(last, m.ox, m.oxt, kOmega);
+      }
+    }
+    for (int l = last - 1; l >= 0; --l) {        // prolongation and post-smoothing, up to the solve's grid
+      const Layout::MGLevel& m = L.mg[l];
+      const Layout::MGLevel& mc = L.mg[l + 1];
+      timed_launch(c, PF_K_PRECOND, j, k_mg_prolong<T>, mg_blocks(m.g), dim3(NT), 0, st, m.g, mc.g,
+                   mg_cvec(c, mc.ox), mg_vec(c, m.ox), scal);
+      sweep(l, m.ox, m.oxt, kOmega);
+      sweep(l, m.oxt, m.ox, kOmega);             // level 0: z, with the partials of r.z
+    }
+    timed_launch(c, PF_K_PRECOND, j, k_mg_rz, dim3(1), dim3(NT), 0, st, (const double*)part, L.nb_mg,
+                 c->arr<double>(L.o_part_u), n_rz, scal);
+  }
+
   // Solve A u = b for the current phase fields and plastic strain.
   static pf_status solve(pf_ctx* c, int warm) {
     const Layout& L = c->L;
@@ -513,6 +675,12 @@ struct Impl {
       pf_status s = learned_start<T, DIM>(c, e, part_a);
       if (s != PF_OK) return s;
     }
+    const bool mg = DIM == 3 && L.mg_n > 0;
+    if (mg) {                       // z = M^-1 r of the starting residual
+      mg_setup(c);
+      mg_vcycle(c, e, -1, L.nb_res);
+      LAUNCHCHK(c);
+    }
 
     ElastArgs<T> ap = elast_args(c);
     UpdArgs<T> up{};
@@ -571,6 +739,7 @@ struct Impl {
       for (int q = 0; q < n; ++q) {
         apply_cg(launched);
         timed_launch(c, PF_K_UPDATE, launched, k_cg_update<T, DIM>, dim3(L.nb_upd), dim3(NT), 0, st, up);
+        if (mg) mg_vcycle(c, e, launched, L.nb_upd);
         ++launched;
       }
       timed_launch(c, PF_K_OTHER, -1, k_cg_check, dim3(1), dim3(NT), 0, st, (const double*)part_u,
@@ -619,7 +788,8 @@ struct Impl {
     // solve, the ones still pending)
     for (size_t q = c->n_flush == flush0 ? pend0 : 0; q < c->pending.size(); ++q) {
       auto& pr = c->pending[q];
-      if (pr.launch >= c->last_iters && (pr.kind == PF_K_APPLY || pr.kind == PF_K_UPDATE)) pr.kind = PF_K_OTHER;
+      if (pr.launch >= c->last_iters && (pr.kind == PF_K_APPLY || pr.kind == PF_K_UPDATE || pr.kind == PF_K_PRECOND))
+        pr.kind = PF_K_OTHER;
     }
     // true residual ||b - A u|| (3D: the apply kernel's ||b - q||^2 partials)
     int n_true = L.nb_el;

@@ -50,6 +50,7 @@ struct ElastArgs {
   T* Gw;
   T* xs[3];                // APPLY_CG (3D): the solution (completed by the launch that stops the solve)
   int it;                  // APPLY_CG (3D): index of this launch in the solve
+  double omega;            // APPLY_SMOOTH: Jacobi damping (0: write the residual instead)
 };
 
 // Local tile coordinates: lx = i - i0 + 1 in [0, TX+1], ly = j - j0 + 1 in [0, TY+1].
@@ -403,12 +404,15 @@ struct ApplyTile {
 // APPLY_CG inside the CG recurrence; APPLY_PLAIN q = A z outside it (the
 // previous direction not read, the new one not written; with ElastArgs::jr
 // set, ||jr - q||^2 partials); APPLY_RESID the residual pass r = b - A z
-// (ElastArgs::resid).
-enum ApplyMode { APPLY_CG = 0, APPLY_PLAIN = 1, APPLY_RESID = 2 };
+// (ElastArgs::resid); APPLY_SMOOTH one damped Jacobi sweep of a multigrid
+// level, o1 = z + omega D^-1 (b - A z), or with omega = 0 its residual
+// o1 = b - A z (b in jr), with the partials of b . o1.
+enum ApplyMode { APPLY_CG = 0, APPLY_PLAIN = 1, APPLY_RESID = 2, APPLY_SMOOTH = 3 };
 
 template <typename T, int BY, int AM>
-__global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_RESID ? 4 : 1) void k_apply3(ElastArgs<T> a) {
+__global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_RESID && AM != APPLY_SMOOTH ? 4 : 1) void k_apply3(ElastArgs<T> a) {
   constexpr bool kPlain = AM != APPLY_CG, kResid = AM == APPLY_RESID, kCG = AM == APPLY_CG;
+  constexpr bool kSmooth = AM == APPLY_SMOOTH, kRB = kResid || kSmooth;   // kRB: reads b and D^-1
   using TL = ApplyTile<BY>;
   constexpr int W = TL::W, S = TL::S, NTB = TL::NTB;
   __shared__ T sP[2][3][S];
@@ -437,6 +441,8 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   const int k1 = min(k0 + a.kz, g.nz);
   const int own_e = own ? j * g.px + i : 0;
 
+  if constexpr (kSmooth)             // a multigrid sweep queued past the solve's convergence
+    if (a.scal[S_CONV] != 0.0) return;
   // CG scalars (identical in every block)
   double beta = 0.0;
   bool first = true;                 // plain: p_new = z
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
 #pragma unroll
     for (int d = 0; d < 3; ++d) ru_[d] = buf_rsrc(a.u[d], 0);
   __amdgpu_buffer_rsrc_t rjb_[3], rjd_[3];
-  if constexpr (kResid)
+  if constexpr (kRB)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       rjb_[d] = buf_rsrc(a.jr[d], nbytes);
@@ -701,7 +707,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     // residual pass: b and D^-1 of the own cell, issued before the stencil so
     // that their latency hides behind it
     T jb[3], jd[3];
-    if constexpr (kResid) {
+    if constexpr (kRB) {
       const int eo = own ? (own_e + k * pl) * (int)sizeof(T) : kOutOfRange;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -751,6 +757,16 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
           if (zero_u) a.u[d][e] = T(0);
           acc += (double)r * (double)z;
           acc1 += (double)r * (double)r;
+        }
+      } else if constexpr (kSmooth) {
+        const T qv[3] = {q0, q1, q2};
+        const T om = (T)a.omega;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const T r = jb[d] - qv[d];
+          const T o = a.omega != 0.0 ? C.p[d] + om * jd[d] * r : r;
+          a.o1[d][e] = o;
+          acc += (double)jb[d] * (double)o;
         }
       } else {
       if constexpr (!kPlain) { a.o1[0][e] = C.p[0]; a.o1[1][e] = C.p[1]; a.o1[2][e] = C.p[2]; }

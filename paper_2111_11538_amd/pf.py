@@ -32,7 +32,7 @@ class pf_config(C.Structure):
                 ("dirichlet", C.c_int), ("chem_phase", C.c_int),
                 ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("warm", C.c_int),
                 ("ledger_tol", C.c_double), ("species_implicit", C.c_int), ("species_max_iter", C.c_int),
-                ("species_rtol", C.c_double)]
+                ("species_rtol", C.c_double), ("cg_precond", C.c_int)]
 
 
 class pf_params(C.Structure):
@@ -98,7 +98,8 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_c
            "pf_nn_pack", "pf_nn_attach", "pf_increment_scale_static",
            "pf_fs_workspace_bytes", "pf_fs_init", "pf_fs_fields", "pf_fs_solve", "pf_fs_timing", "pf_fs_timing_get", "pf_fs_attach",
            "pf_fs_last_error", "pf_fs_destroy")
-KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn", "species")
+PRECOND = {"jacobi": 0, "mg": 1}
+KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn", "species", "precond")
 
 _lib = None
 
@@ -220,7 +221,8 @@ def make_params(p) -> pf_params:
 
 def make_config(dim, shape, h, dt, precision="fp64", mechanics=True, plasticity=False, dirichlet=True,
                 chem_phase=True, cg_rtol=1e-10, cg_max_iter=200000, warm="prev", ledger_tol=0.0,
-                species_implicit=False, species_rtol=None, species_max_iter=100000) -> pf_config:
+                species_implicit=False, species_rtol=None, species_max_iter=100000,
+                cg_precond="jacobi") -> pf_config:
     c = pf_config()
     c.dim = dim
     if dim == 2:
@@ -237,6 +239,7 @@ def make_config(dim, shape, h, dt, precision="fp64", mechanics=True, plasticity=
     c.species_implicit = int(species_implicit)        # 0, 1 (or True) or 2
     c.species_max_iter = int(species_max_iter)
     c.species_rtol = species_rtol if species_rtol is not None else (1e-12 if precision == "fp64" else 1e-6)
+    c.cg_precond = PRECOND[cg_precond]
     return c
 
 

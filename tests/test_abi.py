@@ -42,9 +42,10 @@ def test_struct_layouts_match_the_header(lib):
 #include <stddef.h>
 #include "pf.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pf_config), sizeof(pf_params), sizeof(pf_step_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pf_config), sizeof(pf_params), sizeof(pf_step_stats),
          offsetof(pf_config, ledger_tol), offsetof(pf_params, m_form), offsetof(pf_step_stats, nonfinite),
-         sizeof(pf_fs_config), offsetof(pf_fs_config, cg_rtol), sizeof(pf_fs_stats), offsetof(pf_fs_stats, yielded));
+         sizeof(pf_fs_config), offsetof(pf_fs_config, cg_rtol), sizeof(pf_fs_stats), offsetof(pf_fs_stats, yielded),
+         offsetof(pf_config, cg_precond));
   return 0;
 }
 '''
@@ -57,7 +58,7 @@ int main(void) {
     assert out == [C.sizeof(pf.pf_config), C.sizeof(pf.pf_params), C.sizeof(pf.pf_step_stats),
                    pf.pf_config.ledger_tol.offset, pf.pf_params.m_form.offset, pf.pf_step_stats.nonfinite.offset,
                    C.sizeof(pf.pf_fs_config), pf.pf_fs_config.cg_rtol.offset, C.sizeof(pf.pf_fs_stats),
-                   pf.pf_fs_stats.yielded.offset]
+                   pf.pf_fs_stats.yielded.offset, pf.pf_config.cg_precond.offset]
 
 
 def test_workspace_size_and_validation(lib):
@@ -79,6 +80,28 @@ def test_workspace_size_and_validation(lib):
     rc = lib.pf_init(C.byref(cfg), C.byref(prm), C.c_void_p(256), 16, None, C.byref(ctx))
     assert rc == pf.PF_ERR_OOM
     assert lib.pf_step(None, 1, None) == pf.PF_ERR_INVALID_ARG
+
+
+def test_multigrid_workspace_and_validation(lib):
+    """The multigrid preconditioner adds its levels to the 3D workspace (two
+    more fine vectors and 17 arrays per coarse level, 1/8 of the cells each);
+    it is refused in 2D and for unknown preconditioner codes."""
+    sz = lambda c: lib.pf_workspace_bytes(C.byref(c))
+    for prec in ("fp64", "mixed"):
+        jac = pf.make_config(3, (32, 32, 32), I.H_DEFAULT, 1e-8, precision=prec)
+        mg = pf.make_config(3, (32, 32, 32), I.H_DEFAULT, 1e-8, precision=prec, cg_precond="mg")
+        es = 8 if prec == "fp64" else 4
+        fine = 32 * 32 * 32 * es
+        extra = sz(mg) - sz(jac)
+        # level 0: 6 vectors; levels 16^3 and 8^3: 17 arrays each; alignment and stagger slack
+        want = 6 * fine + 17 * (fine // 8 + fine // 64)
+        assert want <= extra <= want + 64 * 8192, (prec, extra, want)
+    odd = pf.make_config(3, (9, 12, 16), I.H_DEFAULT, 1e-8, cg_precond="mg")
+    assert sz(odd) > sz(pf.make_config(3, (9, 12, 16), I.H_DEFAULT, 1e-8))   # one level: Jacobi sweeps only
+    assert sz(pf.make_config(2, (32, 32), I.H_DEFAULT, 1e-8, cg_precond="mg")) == 0
+    bad = pf.make_config(3, (32, 32, 32), I.H_DEFAULT, 1e-8)
+    bad.cg_precond = 2
+    assert sz(bad) == 0
 
 
 def test_batch_workspace_validation(lib):
