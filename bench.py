@@ -2,7 +2,8 @@
 """Throughput of the coupled phase-field step on one MI355X.
 
 One "step" is one call-level pass of the whole hot path: the mechanical
-equilibrium solve (Jacobi-PCG to the workload's tolerance), the J2 return
+equilibrium solve (PCG to the workload's tolerance; in 3D preconditioned by
+a multigrid V-cycle unless --precond jacobi), the J2 return
 map, the elastic / chemical driving forces, the fluxes and reaction, the
 explicit update of the five fields and the FP64 ledger.  The default workload
 is the 256^3 porous recipe (64 Voronoi grains, 20 % ellipsoidal pores lined
@@ -46,6 +47,10 @@ def algorithmic_bytes_per_cell(kind, dim, es):
         return (nf + 1 + dim + nc + 1 + nf + nc + 1) * es
     if kind == "mu":           # read phi_f, phi_w, x_O; write mu
         return 4 * es
+    if kind == "smooth" and dim == 3:
+        # multigrid sweeps on the solve's grid, four per cycle: the two-sweep pass from zero (read b, D^-1, K,
+        # G; write x), the residual and two post-smoothing sweeps (read x, b, D^-1, K, G; write x or r)
+        return ((3 + 3 + 2 + 3) + 3 * (3 + 3 + 3 + 2 + 3)) * es / 4.0
     if kind == "solve_setup":
         if dim == 3:           # average of the set-up pass (phi_f, phi_w, eps_p -> K, G, b, D^-1), the residual
             # pass (u, K, G, b, D^-1 -> r, z) and the true residual (u, K, G, b -> q)
@@ -63,7 +68,10 @@ KERNEL_NAMES = {("update", 3, 4): "k_cg_update<float, 3>", ("apply", 3, 4): "k_a
                 ("step", 3, 4): "k_step3<float>", ("mu", 3, 4): "k_mu<float, 3>",
                 ("update", 3, 8): "k_cg_update<double, 3>", ("apply", 3, 8): "k_apply3<double, 8, 0>",
                 ("update", 2, 4): "k_cg_update<float, 2>", ("apply", 2, 4): "k_apply2<float>",
-                ("step", 2, 4): "k_step<float, 2>", ("mu", 2, 4): "k_mu<float, 2>"}
+                ("step", 2, 4): "k_step<float, 2>", ("mu", 2, 4): "k_mu<float, 2>",
+                ("smooth", 3, 4): ("k_apply3<float, 8, 4> @fine", "k_apply3<float, 8, 3> @fine")}
+# launches per cycle of each kernel of a kind made of several (weights of their traffic)
+KERNEL_WEIGHTS = {"smooth": (1, 3)}
 
 
 def source_sha():
@@ -86,10 +94,12 @@ def profiled_traffic(tag, kind, dim, es, name=None):
         return None, None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_sha") != source_sha() or name not in d.get("kernels", {}):
+    names = name if isinstance(name, tuple) else (name,)
+    weights = KERNEL_WEIGHTS.get(kind, (1,)) if isinstance(name, tuple) else (1,)
+    if d.get("kernel_source_sha") != source_sha() or any(n not in d.get("kernels", {}) for n in names):
         return None, None
-    k = d["kernels"][name]
-    return k["fetch_bytes"] + k["write_bytes"], os.path.relpath(path, ROOT)
+    tot = sum(w * (d["kernels"][n]["fetch_bytes"] + d["kernels"][n]["write_bytes"]) for n, w in zip(names, weights))
+    return tot / sum(weights), os.path.relpath(path, ROOT)
 
 
 def pf_kinds():
@@ -131,7 +141,7 @@ INCR_TOL = {"phi_f": 1e-3, "phi_w": 1e-3, "xO": 1e-4, "xH": 1e-4, "xW": 1e-3}
 FIELD_TOL = 1e-4
 
 
-def accuracy_sample(name, n, steps=10, params=None, settle=0):
+def accuracy_sample(name, n, steps=10, params=None, settle=0, precond="jacobi"):
     """The timed configuration (mixed GPU path, CG 1e-6, with the learned start
     when trained parameters are given) against the FP64 oracle solved to 1e-10
     on an n^3 (or n^2) instance of the same recipe: per-field relative error
@@ -144,7 +154,7 @@ def accuracy_sample(name, n, steps=10, params=None, settle=0):
     wl = I.workload(name, n=n)
     learned = params is not None and wl.dim == 3
     g = pf.Context(wl.dim, wl.shape, wl.h, wl.dt, wl.params, precision=wl.precision, plasticity=wl.plasticity,
-                   cg_rtol=wl.cg_rtol, warm="learned" if learned else "prev")
+                   cg_rtol=wl.cg_rtol, warm="learned" if learned else "prev", cg_precond=precond)
     g.set_fields(wl.fields)
     net = None
     if learned:
@@ -176,8 +186,9 @@ def accuracy_sample(name, n, steps=10, params=None, settle=0):
             ok &= ie[k] < INCR_TOL[k]
         ok &= fe[k] < FIELD_TOL
     ue = float(np.linalg.norm(out["ux"] - o.ux) / np.linalg.norm(o.ux))
-    return {"sample": f"{name} {n}^{wl.dim} (reduced instance of the timed recipe), {steps} steps, mixed GPU, CG 1e-6"
-                      f"{', learned start' if learned else ''} vs FP64 oracle, CG 1e-10",
+    return {"sample": f"{name} {n}^{wl.dim} (reduced instance of the timed recipe), {steps} steps, mixed GPU, "
+                      f"{'MG-' if precond == 'mg' else 'Jacobi-'}PCG 1e-6"
+                      f"{', learned start' if learned else ''} vs FP64 oracle, Jacobi-PCG 1e-10",
             "max_field_rel_err": max(v for v in fe.values()), "field_err": fe, "incr_rel_err": ie, "u_rel_err": ue,
             "gates": {"field": FIELD_TOL, "increment": INCR_TOL}, "within_gates": bool(ok),
             "cg_iters": iters, "learned_used_steps": int(sum(1 for u in used if u == 2))}
@@ -567,13 +578,13 @@ def train_learned(args):
     return params, info
 
 
-def settle(wl, steps):
+def settle(wl, steps, precond="jacobi"):
     """The common starting state of every timed leg: the recipe's initial
     condition advanced `steps` untimed steps by the plain mixed path with the
     previous-step start (past the cold first solves)."""
     from paper_2111_11538_amd import pf
     c = pf.Context(wl.dim, wl.shape, wl.h, wl.dt, wl.params, precision=wl.precision, plasticity=wl.plasticity,
-                   cg_rtol=wl.cg_rtol, warm="prev")
+                   cg_rtol=wl.cg_rtol, warm="prev", cg_precond=precond)
     c.set_fields(wl.fields)
     st = c.step(steps) if steps > 0 else c.step(0)
     state = c.fields()
@@ -623,6 +634,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--acc-n", type=int, default=None, help="side of the accuracy sample (default 48 in 3D, 256 in 2D)")
     ap.add_argument("--cpu-n", type=int, default=None, help="side of the CPU baseline sample (default 64 in 3D, 512 in 2D)")
+    ap.add_argument("--precond", default="mg", choices=("mg", "jacobi"),
+                    help="preconditioner of the 3D equilibrium CG (2D workloads use Jacobi)")
     ap.add_argument("--warm", default="learned", choices=("learned", "prev"),
                     help="CG start of the timed run (learned: network trained first, on the training recipe)")
     ap.add_argument("--train-workload", default="core_shell_3d", help="recipe whose trajectory trains the network")
@@ -671,8 +684,9 @@ def main():
     if learned:
         print(f"[bench] training on {args.train_workload} at {args.train_n}", file=sys.stderr, flush=True)
         params, train_info = train_learned(args)
+    precond = args.precond if wl.dim == 3 else "jacobi"
     print(f"[bench] settling {wl.name} {wl.shape}: {args.settle} steps", file=sys.stderr, flush=True)
-    start, st_settle = settle(wl, args.settle)
+    start, st_settle = settle(wl, args.settle, precond)
     if learned:
         net = pf.Net(max_voxels=ncell)
         net.set_params(params)
@@ -681,10 +695,13 @@ def main():
     # a timed one, which keeps the events' own overhead out of the kernel's
     # interval); the throughput run below carries no events
     trace_marker(args.copy_probe)
-    brk = run_gpu(wl, wl.precision, args.steps, args.warmup, pf_kinds(), wl.cg_rtol, fields=start, net=net)
+    brk = run_gpu(wl, wl.precision, args.steps, args.warmup, pf_kinds(), wl.cg_rtol, fields=start, net=net,
+                  precond=precond)
     kern = brk["kernels"]
-    dom = max((k for k in ("apply", "update", "step", "mu", "solve_setup", "nn")), key=lambda k: kern[k][0])
-    res = run_gpu(wl, wl.precision, args.steps, args.warmup, None, wl.cg_rtol, fields=start, net=net)
+    dom = max((k for k in ("apply", "update", "step", "mu", "solve_setup", "nn", "smooth", "precond")),
+              key=lambda k: kern[k][0])
+    res = run_gpu(wl, wl.precision, args.steps, args.warmup, None, wl.cg_rtol, fields=start, net=net,
+                  precond=precond)
     trace_marker(args.copy_probe)
     ms = 1e3 * res["seconds"] / args.steps
     value = ncell * args.steps / res["seconds"]
@@ -706,7 +723,8 @@ def main():
                       "GBps_algorithmic": round(gbs, 1) if gbs else None,
                       "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4) if gbs else None,
                       "frac_of_copy": round(gbs / copy_peak, 4) if gbs else None}
-    stencils = {k: kernels[k]["frac_of_8TBps"] for k in ("apply", "step", "mu", "solve_setup") if kernels[k]["frac_of_8TBps"]}
+    stencils = {k: kernels[k]["frac_of_8TBps"] for k in ("apply", "step", "mu", "solve_setup", "smooth")
+                if kernels[k]["frac_of_8TBps"]}
 
     warm_txt = "previous step"
     if learned:
@@ -720,7 +738,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name} {'x'.join(str(x) for x in reversed(wl.shape))}, "
                                f"plasticity {'on' if wl.plasticity else 'off'}, Omega_f {wl.params.Omega_f:g}, "
-                               f"CG rtol {wl.cg_rtol:g}, warm start = {warm_txt}; timed after {args.settle} + "
+                               f"CG rtol {wl.cg_rtol:g}, preconditioner = "
+                               f"{'multigrid V-cycle' if precond == 'mg' else 'Jacobi'}, warm start = {warm_txt}; "
+                               f"timed after {args.settle} + "
                                f"{args.warmup} untimed steps",
                    "cells": ncell, "dt_s": wl.dt, "h_m": wl.h},
         "cg_iters_per_step": res["cg_iters"] / args.steps,
@@ -753,22 +773,36 @@ def main():
         line["learned_last_step"] = {"warm_used": res["stats"].get("warm_used"), "r0_learned": res["stats"]["r0_learned"],
                                      "r0_prev": res["stats"]["r0_prev"]}
         net.close()
-        rp = run_gpu(wl, wl.precision, args.steps, args.warmup, False, wl.cg_rtol, fields=start)
+        rp = run_gpu(wl, wl.precision, args.steps, args.warmup, False, wl.cg_rtol, fields=start, precond=precond)
         line["plain_mixed_gpu"] = {"value": ncell * args.steps / rp["seconds"], "ms_per_step": 1e3 * rp["seconds"] / args.steps,
                                    "cg_iters_per_step": rp["cg_iters"] / args.steps,
-                                   "note": "same state and steps, previous-step start"}
+                                   "note": "same state, steps and preconditioner, previous-step start"}
         line["learned_speedup_vs_plain_mixed"] = value / line["plain_mixed_gpu"]["value"]
+    if precond == "mg":
+        net_j = None
+        if learned:
+            net_j = pf.Net(max_voxels=ncell)
+            net_j.set_params(params)
+        rj = run_gpu(wl, wl.precision, args.steps, args.warmup, False, wl.cg_rtol, fields=start, net=net_j,
+                     precond="jacobi")
+        if net_j is not None:
+            net_j.close()
+        line["jacobi_pcg_gpu"] = {"value": ncell * args.steps / rj["seconds"], "ms_per_step": 1e3 * rj["seconds"] / args.steps,
+                                  "cg_iters_per_step": rj["cg_iters"] / args.steps,
+                                  "note": "same state, steps and warm start, Jacobi-preconditioned CG"}
+        line["mg_speedup_vs_jacobi"] = value / line["jacobi_pcg_gpu"]["value"]
     if not args.no_fp64:
         s64 = max(4, args.steps // 2)
-        r64 = run_gpu(wl, "fp64", s64, args.warmup, False, wl.cg_rtol, fields=start)
+        r64 = run_gpu(wl, "fp64", s64, args.warmup, False, wl.cg_rtol, fields=start, precond=precond)
         line["fp64_gpu"] = {"value": ncell * s64 / r64["seconds"], "ms_per_step": 1e3 * r64["seconds"] / s64,
                             "cg_iters_per_step": r64["cg_iters"] / s64,
-                            "note": f"plain FP64 GPU path, previous-step start, same state, {s64} steps"}
+                            "note": f"plain FP64 GPU path, previous-step start, same state and preconditioner, "
+                                    f"{s64} steps"}
         line["speedup_vs_fp64_gpu"] = value / line["fp64_gpu"]["value"]
     if not args.no_accuracy:
         print("[bench] accuracy sample", file=sys.stderr, flush=True)
         acc_n = args.acc_n or (48 if wl.dim == 3 else 256)
-        line["accuracy"] = accuracy_sample(wl.name, acc_n, params=params)
+        line["accuracy"] = accuracy_sample(wl.name, acc_n, params=params, precond=precond)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl.name, args.cpu_n or (64 if wl.dim == 3 else 512))

@@ -211,8 +211,11 @@ typedef enum {
                          CG launches queued past convergence, which exit at once */
   PF_K_NN = 6,        /* the four convolutions of a learned-start inference (one group per solve) */
   PF_K_SPECIES = 7,   /* implicit species: set-up, apply, update and final update of their CG */
-  PF_K_PRECOND = 8,   /* multigrid preconditioner: smoothing, transfers, coarse moduli and diagonals */
-  PF_K_COUNT = 9
+  PF_K_PRECOND = 8,   /* multigrid preconditioner: coarse-level smoothing, transfers, coarse moduli and
+                         diagonals */
+  PF_K_SMOOTH = 9,    /* multigrid preconditioner: the smoothing and residual sweeps on the solve's own grid
+                         (four per cycle) */
+  PF_K_COUNT = 10
 } pf_kernel_kind;
 
 /* Per-kernel timing with HIP events recorded on the context's stream around

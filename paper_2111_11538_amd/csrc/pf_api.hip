@@ -377,7 +377,7 @@ static void timed_launch(pf_ctx* c, int kind, int cg_launch, K kernel, dim3 grid
       const bool sampled = (cg_launch + c->solves) % c->timing_every == 0;
       const bool guard = kind == PF_K_UPDATE && (cg_launch + 1 + c->solves) % c->timing_every == 0;
       const bool cg_on = ((c->timing >> PF_K_APPLY) & 1u) || ((c->timing >> PF_K_UPDATE) & 1u) ||
-                         ((c->timing >> PF_K_PRECOND) & 1u);
+                         ((c->timing >> PF_K_PRECOND) & 1u) || ((c->timing >> PF_K_SMOOTH) & 1u);
       rec = cg_on && (sampled || guard);
       count = on && sampled;
     }
@@ -526,7 +526,7 @@ struct Impl {
   static void mg_vcycle(pf_ctx* c, const ElastArgs<T>& e, int j, int n_rz) {
     constexpr double kOmega = 0.4;
     constexpr int kNu = 2, kCoarseSweeps = 8;
-    static_assert(kNu == 2, "the sweeps below alternate x and xt for two pre- and post-smoothing sweeps");
+    static_assert(kNu == 2, "the pre-smoothing is the two-sweep pass from zero; two post-smoothing sweeps");
     const Layout& L = c->L;
     hipStream_t st = c->stream;
     double* part = c->arr<double>(L.o_mg_part);
@@ -552,18 +552,34 @@ struct Impl {
       a.kz = m.kz;
       a.omega = omega;
       a.scal = c->scal();
-      timed_launch(c, PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH>, m.grid, dim3(ApplyTile<kApplyBY>::NTB), 0,
-                   st, a);
+      timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH>, m.grid,
+                   dim3(ApplyTile<kApplyBY>::NTB), 0, st, a);
     };
-    auto jacobi0 = [&](int l, const size_t (&xout)[3]) {
+    // the first two sweeps from zero in one pass
+    auto sweep0 = [&](int l, const size_t (&xout)[3]) {
       const Layout::MGLevel& m = L.mg[l];
-      timed_launch(c, PF_K_PRECOND, j, k_mg_jacobi0<T>, mg_blocks(m.g), dim3(NT), 0, st, m.g, (T)kOmega,
-                   mg_cvec(c, m.odi), mg_cvec(c, m.ob), mg_vec(c, xout), scal);
+      ElastArgs<T> a = e;
+      a.g = m.g;
+      a.p.ih = (T)(1.0 / m.h);
+      a.K = c->arr<T>(m.oK);
+      a.G = c->arr<T>(m.oG);
+      for (int d = 0; d < 3; ++d) {
+        a.z[d] = c->arr<T>(m.ob[d]);        // not read
+        a.u[d] = c->arr<T>(m.odi[d]);       // not read
+        a.jr[d] = c->arr<T>(m.ob[d]);
+        a.dinv[d] = c->arr<T>(m.odi[d]);
+        a.o1[d] = c->arr<T>(xout[d]);
+      }
+      a.part = part;
+      a.kz = m.kz;
+      a.omega = kOmega;
+      a.scal = c->scal();
+      timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH0>, m.grid,
+                   dim3(ApplyTile<kApplyBY>::NTB), 0, st, a);
     };
     for (int l = 0; l < last; ++l) {             // pre-smoothing and restriction, down to the coarsest
       const Layout::MGLevel& m = L.mg[l];
-      jacobi0(l, m.oxt);
-      sweep(l, m.oxt, m.ox, kOmega);
+      sweep0(l, m.ox);
       sweep(l, m.ox, m.orr, 0.0);
       const Layout::MGLevel& mc = L.mg[l + 1];
       timed_launch(c, PF_K_PRECOND, j, k_mg_restrict<T>, mg_blocks(mc.g), dim3(NT), 0, st, m.g, mc.g,
@@ -572,8 +588,8 @@ struct Impl {
     {                                            // coarsest level: a fixed number of sweeps from zero
       const Layout::MGLevel& m = L.mg[last];
       static_assert(kCoarseSweeps % 2 == 0, "the coarsest sweeps end in x");
-      jacobi0(last, m.oxt);
-      for (int s = 1; s < kCoarseSweeps; ++s) {
+      sweep0(last, m.ox);
+      for (int s = 2; s < kCoarseSweeps; ++s) {
         if (s & 1) sweep(last, m.oxt, m.ox, kOmega);
         else sweep(last, m.ox, m.oxt, kOmega);
       }
@@ -738,8 +754,12 @@ struct Impl {
       int n = std::min(chunk, maxit - launched);
       for (int q = 0; q < n; ++q) {
         apply_cg(launched);
-        timed_launch(c, PF_K_UPDATE, launched, k_cg_update<T, DIM>, dim3(L.nb_upd), dim3(NT), 0, st, up);
-        if (mg) mg_vcycle(c, e, launched, L.nb_upd);
+        if (mg) {
+          timed_launch(c, PF_K_UPDATE, launched, k_cg_update<T, DIM, true>, dim3(L.nb_upd), dim3(NT), 0, st, up);
+          mg_vcycle(c, e, launched, L.nb_upd);
+        } else {
+          timed_launch(c, PF_K_UPDATE, launched, k_cg_update<T, DIM>, dim3(L.nb_upd), dim3(NT), 0, st, up);
+        }
         ++launched;
       }
       timed_launch(c, PF_K_OTHER, -1, k_cg_check, dim3(1), dim3(NT), 0, st, (const double*)part_u,
@@ -788,7 +808,8 @@ struct Impl {
     // solve, the ones still pending)
     for (size_t q = c->n_flush == flush0 ? pend0 : 0; q < c->pending.size(); ++q) {
       auto& pr = c->pending[q];
-      if (pr.launch >= c->last_iters && (pr.kind == PF_K_APPLY || pr.kind == PF_K_UPDATE || pr.kind == PF_K_PRECOND))
+      if (pr.launch >= c->last_iters && (pr.kind == PF_K_APPLY || pr.kind == PF_K_UPDATE || pr.kind == PF_K_PRECOND ||
+                                         pr.kind == PF_K_SMOOTH))
         pr.kind = PF_K_OTHER;
     }
     // true residual ||b - A u|| (3D: the apply kernel's ||b - q||^2 partials)

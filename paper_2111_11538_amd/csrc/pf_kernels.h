@@ -406,13 +406,16 @@ struct ApplyTile {
 // set, ||jr - q||^2 partials); APPLY_RESID the residual pass r = b - A z
 // (ElastArgs::resid); APPLY_SMOOTH one damped Jacobi sweep of a multigrid
 // level, o1 = z + omega D^-1 (b - A z), or with omega = 0 its residual
-// o1 = b - A z (b in jr), with the partials of b . o1.
-enum ApplyMode { APPLY_CG = 0, APPLY_PLAIN = 1, APPLY_RESID = 2, APPLY_SMOOTH = 3 };
+// o1 = b - A z (b in jr), with the partials of b . o1; APPLY_SMOOTH0 the
+// first two sweeps from zero in one pass: z = omega D^-1 b formed from b and
+// D^-1 as the tile is loaded (z not read), then o1 as in APPLY_SMOOTH.
+enum ApplyMode { APPLY_CG = 0, APPLY_PLAIN = 1, APPLY_RESID = 2, APPLY_SMOOTH = 3, APPLY_SMOOTH0 = 4 };
 
 template <typename T, int BY, int AM>
-__global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_RESID && AM != APPLY_SMOOTH ? 4 : 1) void k_apply3(ElastArgs<T> a) {
+__global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_RESID && AM != APPLY_SMOOTH && AM != APPLY_SMOOTH0 ? 4 : 1) void k_apply3(ElastArgs<T> a) {
   constexpr bool kPlain = AM != APPLY_CG, kResid = AM == APPLY_RESID, kCG = AM == APPLY_CG;
-  constexpr bool kSmooth = AM == APPLY_SMOOTH, kRB = kResid || kSmooth;   // kRB: reads b and D^-1
+  constexpr bool kSmooth0 = AM == APPLY_SMOOTH0;
+  constexpr bool kSmooth = AM == APPLY_SMOOTH || kSmooth0, kRB = kResid || kSmooth;   // kRB: reads b and D^-1
   using TL = ApplyTile<BY>;
   constexpr int W = TL::W, S = TL::S, NTB = TL::NTB;
   __shared__ T sP[2][3][S];
@@ -539,6 +542,13 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   if constexpr (kPlain)        // p = z: the previous direction is never read
 #pragma unroll
     for (int d = 0; d < 3; ++d) ru_[d] = buf_rsrc(a.u[d], 0);
+  if constexpr (kSmooth0)      // z = omega D^-1 b: b in the z slots, D^-1 in the direction slots
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      rz_[d] = buf_rsrc(a.jr[d], nbytes);
+      ru_[d] = buf_rsrc(a.dinv[d], nbytes);
+    }
+  const T om0 = (T)a.omega;
   __amdgpu_buffer_rsrc_t rjb_[3], rjd_[3];
   if constexpr (kRB)
 #pragma unroll
@@ -576,9 +586,15 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     }
   };
   // combine, store the plane into LDS slot `slot`, and return the own values
+  // the vector applied from the raw loads: z, the new direction z + beta p,
+  // or (APPLY_SMOOTH0) omega D^-1 b
+  auto comb = [&](T z, T p) -> T {
+    if constexpr (kSmooth0) return om0 * p * z;
+    else return first ? z : z + tb * p;
+  };
   auto stash = [&](const Raw& R, int slot, T (&vp)[3], T& vg, T& vk, auto RW) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) vp[d] = R.oin ? (first ? R.oz[d] : R.oz[d] + tb * R.op[d]) : T(0);
+    for (int d = 0; d < 3; ++d) vp[d] = R.oin ? comb(R.oz[d], R.op[d]) : T(0);
     vg = R.oin ? R.og : T(0);
     vk = R.oin ? R.ok : T(0);
 #pragma unroll
@@ -587,7 +603,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     sK[slot][c] = vk;
     if (decltype(RW)::value && rg_t < S) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) sP[slot][d][rg_t] = R.hin ? (first ? R.hz[d] : R.hz[d] + tb * R.hp[d]) : T(0);
+      for (int d = 0; d < 3; ++d) sP[slot][d][rg_t] = R.hin ? comb(R.hz[d], R.hp[d]) : T(0);
       sG[slot][rg_t] = R.hin ? R.hg : T(0);
       sK[slot][rg_t] = R.hin ? R.hk : T(0);
     }
@@ -1454,8 +1470,9 @@ template <> struct Vec4<double> { using type = double2; };
 // every component (vectors of 16 bytes); accumulates r.z and r.r.  Without
 // XU, u is updated only when xstep is set, with the steps of this iteration
 // and the previous one (alpha_prev along pp), in the order of two single
-// updates.
-template <typename T, int DIM, bool XU = true>
+// updates.  With NZ (another preconditioner forms z) neither D^-1 nor z is
+// touched and r.z is left at zero.
+template <typename T, int DIM, bool XU = true, bool NZ = false>
 __device__ __forceinline__ void cg_update_range(const UpdArgs<T>& a, int v0, int v1, int vstride, double alpha,
                                                 double& rz, double& rr, bool xstep = false,
                                                 double alpha_prev = 0.0) {
@@ -1475,7 +1492,8 @@ __device__ __forceinline__ void cg_update_range(const UpdArgs<T>& a, int v0, int
       const V* dd = reinterpret_cast<const V*>(a.dinv[c]);
       V* zz = reinterpret_cast<V*>(a.z[c]);
       for (int v = v0; v < v1; v += vstride) {
-        V uv, pv, ppv, rv = rrp[v], qv = qq[v], dv = dd[v], zv;
+        V uv, pv, ppv, rv = rrp[v], qv = qq[v], dv, zv;
+        if constexpr (!NZ) dv = dd[v];
         if constexpr (XM >= 1) {
           uv = uu[v];
           pv = pp[v];
@@ -1497,13 +1515,15 @@ __device__ __forceinline__ void cg_update_range(const UpdArgs<T>& a, int v0, int
             ue[l] = t + al * pe[l];
           }
           re[l] -= al * qe[l];
-          ze[l] = de[l] * re[l];
-          rz += (double)re[l] * (double)ze[l];
+          if constexpr (!NZ) {
+            ze[l] = de[l] * re[l];
+            rz += (double)re[l] * (double)ze[l];
+          }
           rr += (double)re[l] * (double)re[l];
         }
         if constexpr (XM >= 1) uu[v] = uv;
         rrp[v] = rv;
-        zz[v] = zv;
+        if constexpr (!NZ) zz[v] = zv;
       }
     }
   };
@@ -1516,8 +1536,8 @@ __device__ __forceinline__ void cg_update_range(const UpdArgs<T>& a, int v0, int
 // (the previous direction is still held in the other direction buffer); the
 // alpha of every update goes to the device scalars (slot S_ALPHA + parity),
 // and the apply launch that stops the solve after an even iteration adds its
-// step.
-template <typename T, int DIM>
+// step.  NZ: z comes from another preconditioner (not formed here).
+template <typename T, int DIM, bool NZ = false>
 __global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
   constexpr bool XU = DIM != 3;
   __shared__ double red[2 * (NT / 64)];
@@ -1529,8 +1549,8 @@ __global__ __launch_bounds__(NT) void k_cg_update(UpdArgs<T> a) {
   double rz = 0.0, rr = 0.0;
   const bool xstep = !XU && a.parity == 1;
   const double alpha_prev = xstep ? a.scal[S_ALPHA] : 0.0;
-  cg_update_range<T, DIM, XU>(a, blockIdx.x * NT + threadIdx.x, a.n / VN, gridDim.x * NT, alpha, rz, rr, xstep,
-                              alpha_prev);
+  cg_update_range<T, DIM, XU, NZ>(a, blockIdx.x * NT + threadIdx.x, a.n / VN, gridDim.x * NT, alpha, rz, rr, xstep,
+                                  alpha_prev);
   double s0 = rz, s1 = rr;
   block_sum2(s0, s1, red);
   if (threadIdx.x == 0) {

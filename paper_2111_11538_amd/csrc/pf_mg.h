@@ -11,9 +11,10 @@
 // restriction is its transpose divided by 4, which makes the coarse problem
 // the Galerkin one up to the discretisation (the operator carries a factor
 // 1/h, the energy h^(d-1)).  Smoothing is damped Jacobi (k_apply3 in its
-// APPLY_SMOOTH mode); pre- and post-smoothing take the same sweeps and the
-// coarsest level a fixed number of sweeps from zero, so the V-cycle is a
-// fixed symmetric positive definite operator, as CG needs.
+// APPLY_SMOOTH0 mode for the two sweeps from zero, APPLY_SMOOTH for the
+// others); pre- and post-smoothing take the same sweeps and the coarsest
+// level a fixed number of sweeps from zero, so the V-cycle is a fixed
+// symmetric positive definite operator, as CG needs.
 #pragma once
 
 #include "pf_kernels.h"
@@ -88,21 +89,6 @@ __global__ __launch_bounds__(NT) void k_mg_diag(Grid g, T ih, const T* K, const 
 
 // The kernels applied per CG iteration take the solve's scalars and exit at
 // entry once the solve has converged (launches queued past convergence).
-
-// the first sweep from zero: x = omega D^-1 b
-template <typename T>
-__global__ __launch_bounds__(NT) void k_mg_jacobi0(Grid g, T omega, CVec3<T> dinv, CVec3<T> b, Vec3<T> x,
-                                                   const double* scal) {
-  if (scal[S_CONV] != 0.0) return;
-  const long n = (long)g.nx * g.ny * g.nz;
-  for (long q = (long)blockIdx.x * NT + threadIdx.x; q < n; q += (long)gridDim.x * NT) {
-    const int i = (int)(q % g.nx);
-    const long r = q / g.nx;
-    const int e = gidx(g, i, (int)(r % g.ny), (int)(r / g.ny));
-#pragma unroll
-    for (int d = 0; d < 3; ++d) x.a[d][e] = omega * dinv.a[d][e] * b.a[d][e];
-  }
-}
 
 // weights of the transverse interpolation (fine index f of a coarse row of
 // N faces): fine 2J = 3/4 c[J] + 1/4 c[J-1], fine 2J+1 = 3/4 c[J] + 1/4 c[J+1],

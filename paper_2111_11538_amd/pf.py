@@ -99,7 +99,7 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_mech_solve", "pf_cg_c
            "pf_fs_workspace_bytes", "pf_fs_init", "pf_fs_fields", "pf_fs_solve", "pf_fs_timing", "pf_fs_timing_get", "pf_fs_attach",
            "pf_fs_last_error", "pf_fs_destroy")
 PRECOND = {"jacobi": 0, "mg": 1}
-KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn", "species", "precond")
+KERNEL_KINDS = ("apply", "update", "solve_setup", "step", "mu", "other", "nn", "species", "precond", "smooth")
 
 _lib = None
 

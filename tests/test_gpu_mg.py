@@ -147,7 +147,8 @@ def test_mg_bitwise_repeatable():
 
 
 def test_mg_timing_kind():
-    """The cycle's kernels are timed under their own kind."""
+    """The cycle's kernels are timed under their own kinds (the sweeps on the
+    solve's grid apart from the rest of the cycle)."""
     wl = I.workload("core_shell_3d", n=32)
     g = _ctx(wl.shape, wl.params, wl.dt, precision="mixed", plasticity=True, cg_rtol=1e-6, cg_precond="mg")
     g.set_fields(wl.fields)
@@ -156,4 +157,8 @@ def test_mg_timing_kind():
     rep = g.timing_report()
     g.close()
     say(f"  timing: {rep}")
-    assert rep["precond"][1] > 0 and rep["apply"][1] > 0
+    assert rep["precond"][1] > 0 and rep["smooth"][1] > 0 and rep["apply"][1] > 0
+    # four sweeps on the solve's grid per cycle, one cycle per CG iteration
+    # and one before the first (CG apply launches: one per iteration, plus
+    # the one that completes u)
+    assert rep["smooth"][1] <= 4 * rep["apply"][1] + 8
