@@ -497,6 +497,11 @@ struct Impl {
     const long n = (long)g.nx * g.ny * g.nz;
     return dim3((unsigned)std::max(1L, std::min(4096L, (n + NT - 1) / NT)));
   }
+  // one thread per cell of the level (the transfers)
+  static dim3 mg_cell_blocks(const Grid& g) {
+    const long n = (long)g.nx * g.ny * g.nz;
+    return dim3((unsigned)((n + NT - 1) / NT));
+  }
   static Vec3<T> mg_vec(pf_ctx* c, const size_t (&o)[3]) {
     Vec3<T> v;
     for (int d = 0; d < 3; ++d) v.a[d] = c->arr<T>(o[d]);
@@ -582,7 +587,7 @@ struct Impl {
       sweep0(l, m.ox);
       sweep(l, m.ox, m.orr, 0.0);
       const Layout::MGLevel& mc = L.mg[l + 1];
-      timed_launch(c, PF_K_PRECOND, j, k_mg_restrict<T>, mg_blocks(mc.g), dim3(NT), 0, st, m.g, mc.g,
+      timed_launch(c, PF_K_PRECOND, j, k_mg_restrict<T>, mg_cell_blocks(mc.g), dim3(NT), 0, st, m.g, mc.g,
                    mg_cvec(c, m.orr), mg_vec(c, mc.ob), scal);
     }
     {                                            // coarsest level: a fixed number of sweeps from zero
@@ -597,7 +602,7 @@ struct Impl {
     for (int l = last - 1; l >= 0; --l) {        // prolongation and post-smoothing, up to the solve's grid
       const Layout::MGLevel& m = L.mg[l];
       const Layout::MGLevel& mc = L.mg[l + 1];
-      timed_launch(c, PF_K_PRECOND, j, k_mg_prolong<T>, mg_blocks(m.g), dim3(NT), 0, st, m.g, mc.g,
+      timed_launch(c, PF_K_PRECOND, j, k_mg_prolong<T>, mg_cell_blocks(m.g), dim3(NT), 0, st, m.g, mc.g,
                    mg_cvec(c, mc.ox), mg_vec(c, m.ox), scal);
       sweep(l, m.ox, m.oxt, kOmega);
       sweep(l, m.oxt, m.ox, kOmega);             // level 0: z, with the partials of r.z

@@ -592,7 +592,19 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     if constexpr (kSmooth0) return om0 * p * z;
     else return first ? z : z + tb * p;
   };
-  auto stash = [&](const Raw& R, int slot, T (&vp)[3], T& vg, T& vk, auto RW) {
+  // own column's values of one plane (APPLY_SMOOTH0 also keeps b and D^-1,
+  // which its epilogue needs again)
+  struct Own { T p[3], g, k, b[3], d[3]; };
+  auto stash = [&](const Raw& R, int slot, Own& O, auto RW) {
+    T (&vp)[3] = O.p;
+    T& vg = O.g;
+    T& vk = O.k;
+    if constexpr (kSmooth0)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        O.b[d] = R.oin ? R.oz[d] : T(0);
+        O.d[d] = R.oin ? R.op[d] : T(0);
+      }
 #pragma unroll
     for (int d = 0; d < 3; ++d) vp[d] = R.oin ? comb(R.oz[d], R.op[d]) : T(0);
     vg = R.oin ? R.og : T(0);
@@ -672,7 +684,6 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
 
   // LDS slots are numbered relative to k0 (plane m in slot (m - k0) & 1), so
   // inside the plane pairs below every slot index is a constant
-  struct Own { T p[3], g, k; };       // own column's values of one plane
   Own oA, oB;                         // planes k (current) and k+1, roles alternating
   T szz_prev = T(0), sxz_c = T(0), syz_c = T(0);
   // boundary factors (0 / 1) of the own column: edges on the domain boundary
@@ -691,8 +702,8 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     Own ob;
     fetch(ra, k0 - 1, true, RW);
     fetch(rb, k0, true, RW);
-    stash(ra, 1, ob.p, ob.g, ob.k, RW);
-    stash(rb, 0, oA.p, oA.g, oA.k, RW);
+    stash(ra, 1, ob, RW);
+    stash(rb, 0, oA, RW);
     fetch(ra, k0 + 1, true, RW);
     fetch(rb, k0 + 2, k0 + 1 < k1, RW);
     __syncthreads();
@@ -710,7 +721,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     sSyz[0][c] = syz_c;
     ring_items(1, 0, k0, 1, 0, 0, false);
     __syncthreads();
-    stash(ra, 1, oB.p, oB.g, oB.k, RW);
+    stash(ra, 1, oB, RW);
     fetch(ra, k0 + 3, k0 + 2 < k1, RW);
     __syncthreads();
   };
@@ -723,7 +734,13 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     // residual pass: b and D^-1 of the own cell, issued before the stencil so
     // that their latency hides behind it
     T jb[3], jd[3];
-    if constexpr (kRB) {
+    if constexpr (kSmooth0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        jb[d] = C.b[d];
+        jd[d] = C.d[d];
+      }
+    } else if constexpr (kRB) {
       const int eo = own ? (own_e + k * pl) * (int)sizeof(T) : kOutOfRange;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -799,7 +816,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     szz_prev = szz;
     sxz_c = sxz_n;
     syz_c = syz_n;
-    if (k + 1 < k1) stash(R, sk, C.p, C.g, C.k, RW);   // plane k+2 into the slot of plane k
+    if (k + 1 < k1) stash(R, sk, C, RW);   // plane k+2 into the slot of plane k
     fetch(R, k + 4, k + 3 < k1, RW);
     __syncthreads();
   };

@@ -90,118 +90,110 @@ __global__ __launch_bounds__(NT) void k_mg_diag(Grid g, T ih, const T* K, const 
 // The kernels applied per CG iteration take the solve's scalars and exit at
 // entry once the solve has converged (launches queued past convergence).
 
-// weights of the transverse interpolation (fine index f of a coarse row of
-// N faces): fine 2J = 3/4 c[J] + 1/4 c[J-1], fine 2J+1 = 3/4 c[J] + 1/4 c[J+1],
-// with c[-1] = c[0] and c[N] = c[N-1]
-__device__ __forceinline__ void lin_up(int f, int N, int& J0, int& J1, float& w0, float& w1) {
-  const int J = f >> 1;
-  J0 = J;
-  w0 = 0.75f;
-  J1 = (f & 1) ? (J + 1 < N ? J + 1 : J) : (J > 0 ? J - 1 : J);
-  w1 = 0.25f;
-}
+// The transfers run one thread per cell (its three faces), in the
+// precision of the level's vectors, with every load in range (indices
+// clamped, weights zero where a term does not exist) so that a thread's
+// loads issue together.  (Staging a block's tile in LDS was tried: with the
+// little work per cell, the block-wide wait between the loads and the sums
+// made both transfers slower.)
 
-// fine += P coarse, one fine cell (its three faces) per thread
+// fine += P coarse, one fine cell per thread.  Per face component d: along
+// the normal the coincident coarse face (weight 1) or the two coarse faces
+// around a midway fine face (1/2 each; the high wall holds zero and the low
+// roller face is zero); across it, per transverse axis, coarse rows f >> 1
+// (3/4) and its neighbour on the side of f (1/4; clamped at the walls).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_prolong(Grid gf, Grid gc, CVec3<T> xc, Vec3<T> xf, const double* scal) {
   if (scal[S_CONV] != 0.0) return;
-  const long n = (long)gf.nx * gf.ny * gf.nz;
+  const long q = (long)blockIdx.x * NT + threadIdx.x;
+  if (q >= (long)gf.nx * gf.ny * gf.nz) return;
+  const int f[3] = {(int)(q % gf.nx), (int)((q / gf.nx) % gf.ny), (int)(q / ((long)gf.nx * gf.ny))};
   const int nc[3] = {gc.nx, gc.ny, gc.nz};
-  for (long q = (long)blockIdx.x * NT + threadIdx.x; q < n; q += (long)gridDim.x * NT) {
-    const int f[3] = {(int)(q % gf.nx), (int)((q / gf.nx) % gf.ny), (int)(q / ((long)gf.nx * gf.ny))};
-    const int e = gidx(gf, f[0], f[1], f[2]);
+  int t0[3], t1[3];                              // transverse rows per axis
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if (f[d] == 0) continue;                 // roller face
-      // along the normal d
-      int a0 = f[d] >> 1, a1 = a0;
-      float wa0 = 1.f, wa1 = 0.f;
-      if (f[d] & 1) { a1 = a0 + 1; wa0 = 0.5f; wa1 = 0.5f; }
-      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-      int b0, b1, c0, c1;
-      float wb0, wb1, wc0, wc1;
-      lin_up(f[t1], nc[t1], b0, b1, wb0, wb1);
-      lin_up(f[t2], nc[t2], c0, c1, wc0, wc1);
-      double s = 0.0;
-      const int an[2] = {a0, a1};
-      const float wan[2] = {wa0, wa1};
+  for (int a = 0; a < 3; ++a) {
+    t0[a] = f[a] >> 1;
+    t1[a] = (f[a] & 1) ? min(t0[a] + 1, nc[a] - 1) : max(t0[a] - 1, 0);
+  }
+  const T tw[2] = {T(0.75), T(0.25)};
+  const int e = gidx(gf, f[0], f[1], f[2]);
 #pragma unroll
-      for (int ia = 0; ia < 2; ++ia) {
-        const int A = an[ia];
-        if (wan[ia] == 0.f || A <= 0 || A >= nc[d]) continue;   // roller faces of the coarse level
-        const int bb[2] = {b0, b1}, cc[2] = {c0, c1};
-        const float wb[2] = {wb0, wb1}, wc[2] = {wc0, wc1};
+  for (int d = 0; d < 3; ++d) {
+    if (f[d] == 0) continue;                     // roller face
+    const int a0 = f[d] >> 1;
+    const bool odd = f[d] & 1;
+    const int a1 = min(a0 + 1, nc[d] - 1);
+    const T wn[2] = {a0 > 0 ? (odd ? T(0.5) : T(1)) : T(0), (odd && a0 + 1 < nc[d]) ? T(0.5) : T(0)};
+    const int an[2] = {a0, a1};
+    const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
+    const int ru[2] = {t0[u], t1[u]}, rv[2] = {t0[v], t1[v]};
+    T s = T(0);
 #pragma unroll
-        for (int ib = 0; ib < 2; ++ib)
+    for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
-          for (int ic = 0; ic < 2; ++ic) {
-            int idx[3];
-            idx[d] = A;
-            idx[t1] = bb[ib];
-            idx[t2] = cc[ic];
-            s += (double)(wan[ia] * wb[ib] * wc[ic]) * (double)xc.a[d][gidx(gc, idx[0], idx[1], idx[2])];
-          }
-      }
-      xf.a[d][e] += (T)s;
-    }
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int ic = 0; ic < 2; ++ic) {
+          int idx[3];
+          idx[d] = an[ia];
+          idx[u] = ru[ib];
+          idx[v] = rv[ic];
+          s += wn[ia] * tw[ib] * tw[ic] * xc.a[d][gidx(gc, idx[0], idx[1], idx[2])];
+        }
+    xf.a[d][e] += s;
   }
 }
 
-// coarse b = R fine r = P^T r / 4, one coarse cell (its three faces) per thread
+// coarse b = R fine r = P^T r / 4, one coarse cell per thread.  Per face
+// component d (the roller face C = 0 gets zero): along the normal fine
+// faces 2C - 1, 2C, 2C + 1 (1/2, 1, 1/2); per transverse axis the fine rows
+// whose interpolation takes coarse row C, 2C - 1 .. 2C + 2 with weights
+// 1/4, 3/4, 3/4, 1/4 (at a wall the row beyond is absent and the clamped
+// interpolation gives the row at the wall the full weight 1).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_restrict(Grid gf, Grid gc, CVec3<T> rf, Vec3<T> bc, const double* scal) {
   if (scal[S_CONV] != 0.0) return;
-  const long n = (long)gc.nx * gc.ny * gc.nz;
-  const int nf[3] = {gf.nx, gf.ny, gf.nz};
+  const long q = (long)blockIdx.x * NT + threadIdx.x;
+  if (q >= (long)gc.nx * gc.ny * gc.nz) return;
+  const int C[3] = {(int)(q % gc.nx), (int)((q / gc.nx) % gc.ny), (int)(q / ((long)gc.nx * gc.ny))};
   const int nc[3] = {gc.nx, gc.ny, gc.nz};
-  for (long q = (long)blockIdx.x * NT + threadIdx.x; q < n; q += (long)gridDim.x * NT) {
-    const int C[3] = {(int)(q % gc.nx), (int)((q / gc.nx) % gc.ny), (int)(q / ((long)gc.nx * gc.ny))};
-    const int ec = gidx(gc, C[0], C[1], C[2]);
+  int rows[3][4];                                // transverse fine rows per axis
+  T w[3][4];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if (C[d] == 0) {                          // roller face
-        bc.a[d][ec] = T(0);
-        continue;
-      }
-      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-      // transverse: the fine rows whose interpolation uses coarse row C[t]
-      // (the transpose of lin_up), fine indices 2C-1 .. 2C+2
-      auto tw = [&](int t, int off, float& w) -> int {   // off in 0..3 -> fine 2C-1+off
-        const int fi = 2 * C[t] - 1 + off;
-        const int N = nc[t];
-        w = 0.f;
-        if (off == 1) w = 0.75f + (C[t] == 0 ? 0.25f : 0.f);
-        else if (off == 2) w = 0.75f + (C[t] == N - 1 ? 0.25f : 0.f);
-        else if (off == 0) w = C[t] > 0 ? 0.25f : 0.f;
-        else w = C[t] < N - 1 ? 0.25f : 0.f;
-        return fi;
-      };
-      double s = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const int c = C[a], N = nc[a], nf = 2 * N;
+    rows[a][0] = max(2 * c - 1, 0);
+    rows[a][1] = 2 * c;
+    rows[a][2] = 2 * c + 1;
+    rows[a][3] = min(2 * c + 2, nf - 1);
+    w[a][0] = c > 0 ? T(0.25) : T(0);
+    w[a][1] = c > 0 ? T(0.75) : T(1);
+    w[a][2] = c < N - 1 ? T(0.75) : T(1);
+    w[a][3] = c < N - 1 ? T(0.25) : T(0);
+  }
+  const T wn[3] = {T(0.5), T(1), T(0.5)};
+  const int ec = gidx(gc, C[0], C[1], C[2]);
 #pragma unroll
-      for (int sa = -1; sa <= 1; ++sa) {        // along the normal: faces 2C-1, 2C, 2C+1
-        const int fa = 2 * C[d] + sa;
-        if (fa <= 0 || fa >= nf[d]) continue;   // fine roller faces hold nothing
-        const float wa = sa == 0 ? 1.f : 0.5f;
-#pragma unroll
-        for (int ob = 0; ob < 4; ++ob) {
-          float wb;
-          const int fb = tw(t1, ob, wb);
-          if (wb == 0.f) continue;
-#pragma unroll
-          for (int oc = 0; oc < 4; ++oc) {
-            float wc;
-            const int fc = tw(t2, oc, wc);
-            if (wc == 0.f) continue;
-            int idx[3];
-            idx[d] = fa;
-            idx[t1] = fb;
-            idx[t2] = fc;
-            s += (double)(wa * wb * wc) * (double)rf.a[d][gidx(gf, idx[0], idx[1], idx[2])];
-          }
-        }
-      }
-      bc.a[d][ec] = (T)(0.25 * s);
+  for (int d = 0; d < 3; ++d) {
+    if (C[d] == 0) {                             // roller face
+      bc.a[d][ec] = T(0);
+      continue;
     }
+    const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
+    T s = T(0);
+#pragma unroll
+    for (int sa = 0; sa < 3; ++sa)
+#pragma unroll
+      for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int oc = 0; oc < 4; ++oc) {
+          int idx[3];
+          idx[d] = 2 * C[d] - 1 + sa;
+          idx[u] = rows[u][ob];
+          idx[v] = rows[v][oc];
+          s += wn[sa] * w[u][ob] * w[v][oc] * rf.a[d][gidx(gf, idx[0], idx[1], idx[2])];
+        }
+    bc.a[d][ec] = T(0.25) * s;
   }
 }
 
