@@ -86,8 +86,8 @@ typedef struct {
   int species_max_iter;   /* implicit species: CG iteration limit per step (reaching it is an error) */
   double species_rtol;    /* implicit species: stop each species' CG at ||r|| <= species_rtol ||b|| */
   int cg_precond;         /* preconditioner of the equilibrium CG: 0 Jacobi; 1 (3D) a geometric multigrid
-                             V-cycle (levels halve the cells while every side is even and above 8; damped
-                             Jacobi smoothing; see pf_step) */
+                             V-cycle (levels halve the cells while every side is even and above 8; Jacobi
+                             smoothing with Chebyshev steps; see pf_step) */
 } pf_config;
 
 /* Material and model parameters, Table 1 of the paper; phase index 0 ferrite,
@@ -159,7 +159,7 @@ pf_status pf_init(const pf_config *cfg, const pf_params *params, void *workspace
  * coarse levels of half the cells (the same staggered operator at 2h with
  * the moduli averaged over the 8 children), face transfers that are full
  * weighting along the normal and linear across it (restriction = transposed
- * prolongation / 4), two damped Jacobi sweeps (omega 0.4) before and after
+ * prolongation / 4), two Jacobi sweeps with Chebyshev steps before and after
  * each coarse correction and eight on the coarsest level; the solution is
  * the same to cg_rtol, in far fewer iterations.  The CG
  * recurrence scalars and the convergence test live on the device; the host

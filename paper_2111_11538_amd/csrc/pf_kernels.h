@@ -50,7 +50,8 @@ struct ElastArgs {
   T* Gw;
   T* xs[3];                // APPLY_CG (3D): the solution (completed by the launch that stops the solve)
   int it;                  // APPLY_CG (3D): index of this launch in the solve
-  double omega;            // APPLY_SMOOTH: Jacobi damping (0: write the residual instead)
+  double omega;            // APPLY_SMOOTH(0): step of the Jacobi sweep (0: write the residual instead)
+  double omega0;           // APPLY_SMOOTH0: step of the first sweep from zero
 };
 
 // Local tile coordinates: lx = i - i0 + 1 in [0, TX+1], ly = j - j0 + 1 in [0, TY+1].
@@ -407,8 +408,8 @@ struct ApplyTile {
 // (ElastArgs::resid); APPLY_SMOOTH one damped Jacobi sweep of a multigrid
 // level, o1 = z + omega D^-1 (b - A z), or with omega = 0 its residual
 // o1 = b - A z (b in jr), with the partials of b . o1; APPLY_SMOOTH0 the
-// first two sweeps from zero in one pass: z = omega D^-1 b formed from b and
-// D^-1 as the tile is loaded (z not read), then o1 as in APPLY_SMOOTH.
+// first two sweeps from zero in one pass: z = omega0 D^-1 b formed from b
+// and D^-1 as the tile is loaded (z not read), then o1 as in APPLY_SMOOTH.
 enum ApplyMode { APPLY_CG = 0, APPLY_PLAIN = 1, APPLY_RESID = 2, APPLY_SMOOTH = 3, APPLY_SMOOTH0 = 4 };
 
 template <typename T, int BY, int AM>
@@ -548,7 +549,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
       rz_[d] = buf_rsrc(a.jr[d], nbytes);
       ru_[d] = buf_rsrc(a.dinv[d], nbytes);
     }
-  const T om0 = (T)a.omega;
+  const T om0 = (T)a.omega0;
   __amdgpu_buffer_rsrc_t rjb_[3], rjd_[3];
   if constexpr (kRB)
 #pragma unroll

@@ -10,9 +10,10 @@
 // between coarse face centres (3/4, 1/4; constant at the walls); the
 // restriction is its transpose divided by 4, which makes the coarse problem
 // the Galerkin one up to the discretisation (the operator carries a factor
-// 1/h, the energy h^(d-1)).  Smoothing is damped Jacobi (k_apply3 in its
-// APPLY_SMOOTH0 mode for the two sweeps from zero, APPLY_SMOOTH for the
-// others); pre- and post-smoothing take the same sweeps and the coarsest
+// 1/h, the energy h^(d-1)).  Smoothing is Jacobi with Chebyshev steps
+// (k_apply3 in its APPLY_SMOOTH0 mode for the two sweeps from zero,
+// APPLY_SMOOTH for the others); every sweep pair is the same polynomial in
+// D^-1 A, pre- and post-smoothing take the same sweeps and the coarsest
 // level a fixed number of sweeps from zero, so the V-cycle is a fixed
 // symmetric positive definite operator, as CG needs.
 #pragma once
