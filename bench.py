@@ -32,13 +32,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
 
 
-def algorithmic_bytes_per_cell(kind, dim, es):
+def algorithmic_bytes_per_cell(kind, dim, es, precond="jacobi"):
     """Bytes a kernel must move per cell (reads + writes of the arrays the
     method needs), by kernel class; es = element size of the state."""
     nc = 4 if dim == 2 else 6
     if kind == "apply":        # read z, p_old (dim each), K, G; write p_new, q (dim each)
         return (4 * dim + 2) * es
     if kind == "update":
+        if dim == 3 and precond == "mg":   # read r, q, write r; after odd iterations also read u, p, p_prev, write u
+            return 5 * dim * es
         if dim == 3:           # read r, q, D^-1, write r, z; after odd iterations also read u, p, p_prev, write u
             return 7 * dim * es
         return 8 * dim * es    # read u, p, r, q, D^-1; write u, r, z (dim each)
@@ -709,13 +711,13 @@ def main():
     # dominant kernel and its roofline, from the replay's events
     tot_ms, nl = kern[dom]
     avg_s = tot_ms / 1e3 / max(nl, 1)
-    bytes_per_launch = algorithmic_bytes_per_cell(dom, wl.dim, es) * ncell
+    bytes_per_launch = algorithmic_bytes_per_cell(dom, wl.dim, es, precond) * ncell
     achieved = bytes_per_launch / avg_s / 1e9
     tag = f"{wl.name}_{wl.shape[0]}_{'learned' if learned else 'prev'}"
     traffic, traffic_src = profiled_traffic(tag, dom, wl.dim, es)
     kernels = {}
     for k, v in kern.items():
-        b = algorithmic_bytes_per_cell(k, wl.dim, es) * ncell
+        b = algorithmic_bytes_per_cell(k, wl.dim, es, precond) * ncell
         gbs = b / (v[0] / 1e3 / v[1]) / 1e9 if v[1] and b > 0 else None
         kernels[k] = {"total_ms": round(v[0], 3), "launches": v[1],
                       "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None,

@@ -561,7 +561,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   // run a copy of the plane loop without ring loads and stores (RW = false),
   // so that in both copies every load's wait count is exact
   const bool ring_wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) < (TL::NRING + 63) / 64;
-  auto fetch = [&](Raw& R, int kk, bool want, auto RW) {
+  auto fetch = [&](Raw& R, int kk, bool want, auto RW) __attribute__((always_inline)) {
     const bool zin = want && kk >= 0 && kk < g.nz;
     R.oin = own && zin;
     R.hin = rg_in && zin;
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   // own column's values of one plane (APPLY_SMOOTH0 also keeps b and D^-1,
   // which its epilogue needs again)
   struct Own { T p[3], g, k, b[3], d[3]; };
-  auto stash = [&](const Raw& R, int slot, Own& O, auto RW) {
+  auto stash = [&](const Raw& R, int slot, Own& O, auto RW) __attribute__((always_inline)) {
     T (&vp)[3] = O.p;
     T& vg = O.g;
     T& vk = O.k;
@@ -652,7 +652,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   // With at least 3 x 128 threads each group starts on a wave boundary
   // (group g on threads 128 g ..), so no wave runs two groups' code.
   constexpr bool kAligned = NTB >= 3 * 128 && TX + BY <= 128;
-  auto ring_items = [&](int sk, int sk1, int kk_edge, int s0, int s1, int zout, bool cells_and_xy) {
+  auto ring_items = [&](int sk, int sk1, int kk_edge, int s0, int s1, int zout, bool cells_and_xy) __attribute__((always_inline)) {
     for (int w = threadIdx.x; kAligned ? (w < 3 * 128) : (w < TL::NHALO); w += NTB) {
       const int grp = kAligned ? (w >> 7) : w / (TX + BY);
       const int r = kAligned ? (w & 127) : w - grp * (TX + BY);
@@ -684,7 +684,9 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   };
 
   // LDS slots are numbered relative to k0 (plane m in slot (m - k0) & 1), so
-  // inside the plane pairs below every slot index is a constant
+  // inside the plane pairs below every slot index is a constant.  The
+  // lambdas are forced inline: a call left out of line keeps the register
+  // sets it takes by reference in scratch memory.
   Own oA, oB;                         // planes k (current) and k+1, roles alternating
   T szz_prev = T(0), sxz_c = T(0), syz_c = T(0);
   // boundary factors (0 / 1) of the own column: edges on the domain boundary
@@ -699,7 +701,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   // prologue: planes k0-1 (slot 1), k0 (slot 0); sigma_zz of the own cell
   // below; z edges at level k0.  Plane m travels in register set ra when
   // m - k0 is odd.
-  auto prologue = [&](auto RW) {
+  auto prologue = [&](auto RW) __attribute__((always_inline)) {
     Own ob;
     fetch(ra, k0 - 1, true, RW);
     fetch(rb, k0, true, RW);
@@ -730,7 +732,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   // one plane k in slot sk (plane k+1 in slot sk1); C holds its own values,
   // N those of plane k+1.  R carries plane k+2 in (stashed into slot sk and
   // into C, which then holds the plane after N) and is refilled with plane k+4.
-  auto plane = [&](int k, Raw& R, const int sk, Own& C, const Own& N, auto RW) {
+  auto plane = [&](int k, Raw& R, const int sk, Own& C, const Own& N, auto RW) __attribute__((always_inline)) {
     const int sk1 = sk ^ 1;
     // residual pass: b and D^-1 of the own cell, issued before the stencil so
     // that their latency hides behind it
@@ -823,7 +825,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   };
   // pairs of planes, so that every path into a plane has the same loads in
   // flight (the wait counts then let the newer set stay outstanding)
-  auto march = [&](auto RW) {
+  auto march = [&](auto RW) __attribute__((always_inline)) {
     prologue(RW);
     int k = k0;
     for (; k + 1 < k1; k += 2) {
