@@ -224,11 +224,14 @@ typedef enum {
  * mask clears the accumulators and starts recording, 0 stops.  Each recorded
  * launch costs a few microseconds of stream time and the stream is
  * synchronised once per solve while recording; leave it off, or restrict it
- * to one kind, for throughput runs. */
+ * to one kind, for throughput runs.  The events are created without the
+ * system-scope fence (hipEventDisableSystemFence), so that recording them
+ * does not write back and invalidate the caches between kernels. */
 #define PF_TIMING_ALL ((1 << PF_K_COUNT) - 1)
 pf_status pf_timing(pf_ctx *ctx, int kinds);
 
-/* Sampling of the CG kernels (PF_K_APPLY, PF_K_UPDATE) while timing: only
+/* Sampling of the CG kernels (PF_K_APPLY, PF_K_UPDATE and, with the
+ * multigrid preconditioner, PF_K_PRECOND and PF_K_SMOOTH) while timing: only
  * the launches of every `every`-th CG iteration are timed, with the phase
  * advancing by one per solve (solve s times iterations i with (i + s) a
  * multiple of every), so that over many solves every iteration index is

@@ -1182,7 +1182,10 @@ pf_status pf_timing(pf_ctx* c, int kinds) {
   if (kinds) {
     if (c->ev_pool.empty()) {
       c->ev_pool.resize(32768);
-      for (auto& e : c->ev_pool) HIPCHK(c, hipEventCreate(&e));
+      // timing-only events: no system-scope fence (cache write-back and
+      // invalidation) at each record, which would slow the next kernel; every
+      // read of them follows a stream synchronisation
+      for (auto& e : c->ev_pool) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     for (int k = 0; k < PF_K_COUNT; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
   }

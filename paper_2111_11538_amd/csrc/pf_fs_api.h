@@ -470,7 +470,8 @@ pf_status pf_fs_timing(pf_fs* f, int on) {
   fs_flush(f);
   if (on && f->ev.empty()) {
     f->ev.resize(4096);
-    for (auto& e : f->ev) FSCHK(f, hipEventCreate(&e));
+    // timing-only events without the system-scope fence (every read follows a stream synchronisation)
+    for (auto& e : f->ev) FSCHK(f, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   for (int k = 0; k < PF_FS_K_COUNT; ++k) {
     f->t_ms[k] = 0.0;

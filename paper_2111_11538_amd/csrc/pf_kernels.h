@@ -413,7 +413,7 @@ struct ApplyTile {
 enum ApplyMode { APPLY_CG = 0, APPLY_PLAIN = 1, APPLY_RESID = 2, APPLY_SMOOTH = 3, APPLY_SMOOTH0 = 4 };
 
 template <typename T, int BY, int AM>
-__global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_RESID && AM != APPLY_SMOOTH && AM != APPLY_SMOOTH0 ? 4 : 1) void k_apply3(ElastArgs<T> a) {
+__global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_RESID && AM != APPLY_SMOOTH ? 4 : 1) void k_apply3(ElastArgs<T> a) {
   constexpr bool kPlain = AM != APPLY_CG, kResid = AM == APPLY_RESID, kCG = AM == APPLY_CG;
   constexpr bool kSmooth0 = AM == APPLY_SMOOTH0;
   constexpr bool kSmooth = AM == APPLY_SMOOTH || kSmooth0, kRB = kResid || kSmooth;   // kRB: reads b and D^-1
