@@ -12,17 +12,21 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# PF_ORACLE_LIBRARY, if set, names another build of the oracle to load (the
+# sanitizer test's instrumented one)
+LIB_PATH = os.environ.get("PF_ORACLE_LIBRARY") or os.path.join(HERE, "liboracle.so")
+CFLAGS = ["-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-Wall"]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP over independent cell loops)."""
-    if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
-               "-std=c11", "-Wall", "-o", LIB_PATH + ".tmp", os.path.join(HERE, "pf_oracle.c"), "-lm"]
+def build(force: bool = True, out: str | None = None, extra: tuple = ("-O2",)) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP over independent cell loops);
+    `out` and `extra` give another output path and flags (sanitizers)."""
+    path = out or LIB_PATH
+    if force or not os.path.exists(path):
+        cmd = ["gcc"] + list(extra) + CFLAGS + ["-o", path + ".tmp", os.path.join(HERE, "pf_oracle.c"), "-lm"]
         subprocess.check_call(cmd)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+        os.replace(path + ".tmp", path)
+    return path
 
 
 class OrParams(C.Structure):

@@ -18,13 +18,16 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = [HIPCC] + FLAGS + ["-o", LIB + ".tmp"] + SOURCES
+def build(verbose: bool = False, out: str | None = None, extra: tuple = ()) -> str:
+    """Compile ``libpf.so`` (or, with `out`, another copy of it; `extra`
+    appends flags, such as host-pass sanitizers)."""
+    lib = out or LIB
+    cmd = [HIPCC] + FLAGS + list(extra) + ["-o", lib + ".tmp"] + SOURCES
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

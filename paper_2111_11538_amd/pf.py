@@ -3,7 +3,8 @@
 Every numerical step runs in ``libpf.so``'s HIP kernels; this module loads the
 library, mirrors its structs with ctypes and uses PyTorch only to allocate the
 device workspace and to name the stream.  There is no fallback: if the library
-is missing, importing the binding's functions raises.
+is missing, importing the binding's functions raises.  PF_LIBRARY, if set,
+names another build of the same library to load (an instrumented one, say).
 """
 from __future__ import annotations
 
@@ -13,7 +14,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpf.so")
+LIB_PATH = os.environ.get("PF_LIBRARY") or os.path.join(HERE, "libpf.so")
 
 PF_OK, PF_ERR_INVALID_ARG, PF_ERR_HIP, PF_ERR_OOM, PF_ERR_CG_NOT_CONVERGED = 0, 1, 2, 3, 4
 PF_ERR_NONFINITE, PF_ERR_LEDGER, PF_ERR_BAD_STATE, PF_ERR_UNSUPPORTED = 5, 6, 7, 8
