@@ -85,9 +85,9 @@ typedef struct {
                              2: as 1 without the reaction, then the reaction over dt solved exactly per cell */
   int species_max_iter;   /* implicit species: CG iteration limit per step (reaching it is an error) */
   double species_rtol;    /* implicit species: stop each species' CG at ||r|| <= species_rtol ||b|| */
-  int cg_precond;         /* preconditioner of the equilibrium CG: 0 Jacobi; 1 (3D) a geometric multigrid
-                             V-cycle (levels halve the cells while every side is even and above 8; Jacobi
-                             smoothing with Chebyshev steps; see pf_step) */
+  int cg_precond;         /* preconditioner of the equilibrium CG: 0 Jacobi; 1 a geometric multigrid V-cycle
+                             (levels halve the cells while every side is even and above 8; Jacobi smoothing
+                             with Chebyshev steps; see pf_step).  Batches take 0 only. */
 } pf_config;
 
 /* Material and model parameters, Table 1 of the paper; phase index 0 ferrite,
@@ -154,12 +154,13 @@ pf_status pf_init(const pf_config *cfg, const pf_params *params, void *workspace
  * and, after the solve, each cell's reaction over dt (Eq. 27, 28 with
  * m(phi_g^n) frozen) is applied from the exact solution of its rate law,
  * which removes the reaction's limit on dt as well and keeps x_O + x_H2O and
- * x_H + 2 x_H2O of every cell unchanged.  With cg_precond == 1 (3D) the
+ * x_H + 2 x_H2O of every cell unchanged.  With cg_precond == 1 the
  * equilibrium CG is preconditioned by one multigrid V-cycle per iteration:
  * coarse levels of half the cells (the same staggered operator at 2h with
- * the moduli averaged over the 8 children), face transfers that are full
- * weighting along the normal and linear across it (restriction = transposed
- * prolongation / 4), two Jacobi sweeps with Chebyshev steps before and after
+ * the moduli averaged over the 8 (2D: 4) children), face transfers that are
+ * full weighting along the normal and linear across it (restriction =
+ * transposed prolongation / 4, in 2D / 2), two Jacobi sweeps with Chebyshev
+ * steps before and after
  * each coarse correction and eight on the coarsest level; the solution is
  * the same to cg_rtol, in far fewer iterations.  The CG
  * recurrence scalars and the convergence test live on the device; the host

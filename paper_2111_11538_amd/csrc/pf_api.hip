@@ -63,7 +63,7 @@ struct Layout {
   size_t o_sp[8][3];
   size_t o_sp_part, o_sp_scal;
   int nb_sp;
-  // multigrid preconditioner (3D, cg_precond == 1): level 0 is the grid of
+  // multigrid preconditioner (cg_precond == 1): level 0 is the grid of
   // the solve (its K, G, D^-1; b is the CG residual, x the preconditioned z);
   // levels 1 .. mg_n - 1 own their moduli, diagonal, b, x, a second x and r
   struct MGLevel {
@@ -93,7 +93,6 @@ bool valid_cfg(const pf_config* c, char* msg, size_t len) {
   if (c->warm == PF_WARM_LEARNED && (c->dim != 3 || !c->mechanics)) { snprintf(msg, len, "the learned warm start needs dim 3 and mechanics"); return false; }
   if (c->species_implicit < 0 || c->species_implicit > 2) { snprintf(msg, len, "species_implicit must be 0, 1 or 2"); return false; }
   if (c->cg_precond != 0 && c->cg_precond != 1) { snprintf(msg, len, "cg_precond must be 0 or 1"); return false; }
-  if (c->cg_precond == 1 && c->dim != 3) { snprintf(msg, len, "the multigrid preconditioner needs dim 3"); return false; }
   if (c->species_implicit && (!(c->species_rtol > 0.0) || c->species_max_iter < 1)) { snprintf(msg, len, "species_rtol > 0 and species_max_iter >= 1 required"); return false; }
   long long px = (c->nx + 15) / 16 * 16;
   if (px * c->ny * (long long)c->nz >= (1LL << 31) / 8) { snprintf(msg, len, "grid too large for 32-bit indexing"); return false; }
@@ -184,12 +183,23 @@ Layout make_layout(const pf_config* c) {
     L.o_sp_scal = take(SP_COUNT * sizeof(double));
   }
   L.mg_n = 0;
-  if (c->cg_precond == 1 && c->dim == 3) {
-    auto apply_geom = [](Layout::MGLevel& m) {
-      const int nbx = (m.g.nx + TX - 1) / TX, nby8 = (m.g.ny + kApplyBY - 1) / kApplyBY;
-      m.kz = kSlabMax;
-      while (m.kz > 1 && (long long)nbx * nby8 * ((m.g.nz + m.kz - 1) / m.kz) < 512) m.kz /= 2;
-      m.grid = dim3(nbx, nby8, (m.g.nz + m.kz - 1) / m.kz);
+  if (c->cg_precond == 1) {
+    const int dim = c->dim;
+    // apply-kernel grid of a level: 3D 64 x kApplyBY column tiles over slabs
+    // of kz planes, 2D rows of A2W cells over runs of kz rows; kz halved
+    // until the level has 512 blocks or kz is 1
+    auto apply_geom = [dim](Layout::MGLevel& m) {
+      if (dim == 3) {
+        const int nbx = (m.g.nx + TX - 1) / TX, nby8 = (m.g.ny + kApplyBY - 1) / kApplyBY;
+        m.kz = kSlabMax;
+        while (m.kz > 1 && (long long)nbx * nby8 * ((m.g.nz + m.kz - 1) / m.kz) < 512) m.kz /= 2;
+        m.grid = dim3(nbx, nby8, (m.g.nz + m.kz - 1) / m.kz);
+      } else {
+        const int nbx = (m.g.nx + A2W - 1) / A2W;
+        m.kz = 32;
+        while (m.kz > 1 && (long long)nbx * ((m.g.ny + m.kz - 1) / m.kz) < 512) m.kz /= 2;
+        m.grid = dim3(nbx, (m.g.ny + m.kz - 1) / m.kz, 1);
+      }
     };
     Layout::MGLevel& m0 = L.mg[0];
     m0.g = g;
@@ -198,18 +208,19 @@ Layout make_layout(const pf_config* c) {
     m0.oK = L.o_K;
     m0.oG = L.o_G;
     for (int d = 0; d < 3; ++d) {
-      m0.odi[d] = L.o_di[d];
-      m0.ob[d] = L.o_r[d];
-      m0.ox[d] = L.o_z[d];
-      m0.oxt[d] = take(arr);
-      m0.orr[d] = take(arr);
+      m0.odi[d] = d < dim ? L.o_di[d] : 0;
+      m0.ob[d] = d < dim ? L.o_r[d] : 0;
+      m0.ox[d] = d < dim ? L.o_z[d] : 0;
+      m0.oxt[d] = d < dim ? take(arr) : 0;
+      m0.orr[d] = d < dim ? take(arr) : 0;
     }
     L.mg_n = 1;
     while (L.mg_n < Layout::kMGMax) {
       const Grid& f = L.mg[L.mg_n - 1].g;
-      if ((f.nx & 1) || (f.ny & 1) || (f.nz & 1) || std::min(f.nx, std::min(f.ny, f.nz)) <= 8) break;
+      const int lo = dim == 3 ? std::min(f.nx, std::min(f.ny, f.nz)) : std::min(f.nx, f.ny);
+      if ((f.nx & 1) || (f.ny & 1) || (dim == 3 && (f.nz & 1)) || lo <= 8) break;
       Layout::MGLevel& m = L.mg[L.mg_n];
-      m.g.nx = f.nx / 2; m.g.ny = f.ny / 2; m.g.nz = f.nz / 2;
+      m.g.nx = f.nx / 2; m.g.ny = f.ny / 2; m.g.nz = dim == 3 ? f.nz / 2 : 1;
       m.g.px = (m.g.nx + 15) / 16 * 16;
       m.g.n = m.g.px * m.g.ny * m.g.nz;
       m.g.ns = m.g.n;
@@ -219,7 +230,11 @@ Layout make_layout(const pf_config* c) {
       m.oK = take(la);
       m.oG = take(la);
       for (int d = 0; d < 3; ++d) {
-        m.odi[d] = take(la); m.ob[d] = take(la); m.ox[d] = take(la); m.oxt[d] = take(la); m.orr[d] = take(la);
+        if (d < dim) {
+          m.odi[d] = take(la); m.ob[d] = take(la); m.ox[d] = take(la); m.oxt[d] = take(la); m.orr[d] = take(la);
+        } else {
+          m.odi[d] = m.ob[d] = m.ox[d] = m.oxt[d] = m.orr[d] = 0;
+        }
       }
       ++L.mg_n;
     }
@@ -519,10 +534,12 @@ struct Impl {
     for (int l = 1; l < L.mg_n; ++l) {
       const Layout::MGLevel& f = L.mg[l - 1];
       const Layout::MGLevel& m = L.mg[l];
-      timed_launch(c, PF_K_PRECOND, -1, k_mg_coarsen<T>, mg_blocks(m.g), dim3(NT), 0, c->stream, f.g, m.g,
-                   (const T*)c->arr<T>(f.oK), (const T*)c->arr<T>(f.oG), c->arr<T>(m.oK), c->arr<T>(m.oG));
-      timed_launch(c, PF_K_PRECOND, -1, k_mg_diag<T>, mg_blocks(m.g), dim3(NT), 0, c->stream, m.g, (T)(1.0 / m.h),
-                   (const T*)c->arr<T>(m.oK), (const T*)c->arr<T>(m.oG), mg_vec(c, m.odi));
+      timed_launch(c, PF_K_PRECOND, -1, DIM == 3 ? k_mg_coarsen<T> : k_mg_coarsen2<T>, mg_blocks(m.g), dim3(NT), 0,
+                   c->stream, f.g, m.g, (const T*)c->arr<T>(f.oK), (const T*)c->arr<T>(f.oG), c->arr<T>(m.oK),
+                   c->arr<T>(m.oG));
+      timed_launch(c, PF_K_PRECOND, -1, DIM == 3 ? k_mg_diag<T> : k_mg_diag2<T>, mg_blocks(m.g), dim3(NT), 0,
+                   c->stream, m.g, (T)(1.0 / m.h), (const T*)c->arr<T>(m.oK), (const T*)c->arr<T>(m.oG),
+                   mg_vec(c, m.odi));
     }
   }
   // z = M^-1 r: one V-cycle from zero on the CG residual (level 0: b = r,
@@ -565,8 +582,12 @@ struct Impl {
       a.kz = m.kz;
       a.omega = omega;
       a.scal = c->scal();
-      timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH>, m.grid,
-                   dim3(ApplyTile<kApplyBY>::NTB), 0, st, a);
+      if constexpr (DIM == 3)
+        timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH>, m.grid,
+                     dim3(ApplyTile<kApplyBY>::NTB), 0, st, a);
+      else
+        timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply2s<T, APPLY_SMOOTH>, m.grid, dim3(A2W), 0, st,
+                     a);
     };
     // the first two sweeps from zero in one pass
     auto sweep0 = [&](int l, const size_t (&xout)[3]) {
@@ -588,16 +609,20 @@ struct Impl {
       a.omega0 = kStep[0];
       a.omega = kStep[1];
       a.scal = c->scal();
-      timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH0>, m.grid,
-                   dim3(ApplyTile<kApplyBY>::NTB), 0, st, a);
+      if constexpr (DIM == 3)
+        timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH0>, m.grid,
+                     dim3(ApplyTile<kApplyBY>::NTB), 0, st, a);
+      else
+        timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply2s<T, APPLY_SMOOTH0>, m.grid, dim3(A2W), 0, st,
+                     a);
     };
     for (int l = 0; l < last; ++l) {             // pre-smoothing and restriction, down to the coarsest
       const Layout::MGLevel& m = L.mg[l];
       sweep0(l, m.ox);
       sweep(l, m.ox, m.orr, 0.0);
       const Layout::MGLevel& mc = L.mg[l + 1];
-      timed_launch(c, PF_K_PRECOND, j, k_mg_restrict<T>, mg_cell_blocks(mc.g), dim3(NT), 0, st, m.g, mc.g,
-                   mg_cvec(c, m.orr), mg_vec(c, mc.ob), scal);
+      timed_launch(c, PF_K_PRECOND, j, DIM == 3 ? k_mg_restrict<T> : k_mg_restrict2<T>, mg_cell_blocks(mc.g), dim3(NT),
+                   0, st, m.g, mc.g, mg_cvec(c, m.orr), mg_vec(c, mc.ob), scal);
     }
     {                                            // coarsest level: a fixed number of sweeps from zero
       const Layout::MGLevel& m = L.mg[last];
@@ -611,8 +636,8 @@ struct Impl {
     for (int l = last - 1; l >= 0; --l) {        // prolongation and post-smoothing, up to the solve's grid
       const Layout::MGLevel& m = L.mg[l];
       const Layout::MGLevel& mc = L.mg[l + 1];
-      timed_launch(c, PF_K_PRECOND, j, k_mg_prolong<T>, mg_cell_blocks(m.g), dim3(NT), 0, st, m.g, mc.g,
-                   mg_cvec(c, mc.ox), mg_vec(c, m.ox), scal);
+      timed_launch(c, PF_K_PRECOND, j, DIM == 3 ? k_mg_prolong<T> : k_mg_prolong2<T>, mg_cell_blocks(m.g), dim3(NT), 0,
+                   st, m.g, mc.g, mg_cvec(c, mc.ox), mg_vec(c, m.ox), scal);
       sweep(l, m.ox, m.oxt, kStep[0]);
       sweep(l, m.oxt, m.ox, kStep[1]);           // level 0: z, with the partials of r.z
     }
@@ -705,7 +730,7 @@ struct Impl {
       pf_status s = learned_start<T, DIM>(c, e, part_a);
       if (s != PF_OK) return s;
     }
-    const bool mg = DIM == 3 && L.mg_n > 0;
+    const bool mg = L.mg_n > 0;
     if (mg) {                       // z = M^-1 r of the starting residual
       mg_setup(c);
       mg_vcycle(c, e, -1, L.nb_res);

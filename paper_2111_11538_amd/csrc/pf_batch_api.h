@@ -33,6 +33,7 @@ bool valid_batch(const pf_config* c, const pf_extent* ext, int count, char* msg,
   if (c->dim != 2) { snprintf(msg, len, "batches are 2D (dim == 2)"); return false; }
   if (!c->mechanics) { snprintf(msg, len, "batches need mechanics == 1"); return false; }
   if (c->warm != PF_WARM_PREV) { snprintf(msg, len, "batches use warm == PF_WARM_PREV"); return false; }
+  if (c->cg_precond != 0) { snprintf(msg, len, "batches use the Jacobi preconditioner (cg_precond == 0)"); return false; }
   if (!(c->h > 0.0) || !(c->dt > 0.0)) { snprintf(msg, len, "h and dt must be positive"); return false; }
   if (c->precision != PF_FP64 && c->precision != PF_MIXED) { snprintf(msg, len, "unknown precision"); return false; }
   if (!(c->cg_rtol > 0.0) || c->cg_max_iter < 1) { snprintf(msg, len, "cg_rtol > 0 and cg_max_iter >= 1 required"); return false; }

@@ -1152,9 +1152,15 @@ struct Apply2Smem {
   T sSxy[2][W];                          // xy edge stresses at two y levels
 };
 
-template <typename T>
+// AM (the 3D kernel's modes): APPLY_CG inside the CG recurrence; APPLY_SMOOTH
+// one Jacobi sweep of a multigrid level, o1 = z + omega D^-1 (b - A z), or
+// with omega = 0 the residual b - A z (b in jr), with partials of b . o1;
+// APPLY_SMOOTH0 the first two sweeps from zero, z = omega0 D^-1 b formed as
+// the rows are loaded.
+template <typename T, int AM = APPLY_CG>
 __device__ __forceinline__ void apply2_tile(const ElastArgs<T>& a, int bx, int by, double beta, bool first, int pidx,
                                             char* smem) {
+  constexpr bool kSmooth0 = AM == APPLY_SMOOTH0, kSmooth = AM == APPLY_SMOOTH || kSmooth0;
   constexpr int W = A2W + 2;
   Apply2Smem<T>& SM = *reinterpret_cast<Apply2Smem<T>*>(smem);
   auto& sP = SM.sP;
@@ -1177,7 +1183,16 @@ __device__ __forceinline__ void apply2_tile(const ElastArgs<T>& a, int bx, int b
   const int rg_t = threadIdx.x == 0 ? 0 : (threadIdx.x == 1 ? W - 1 : -1);
   const bool rg_ok = rg_t >= 0 && rg_x >= 0 && rg_x < g.nx;
 
-  T oz[2], op[2], og, ok, hz[2], hp[2], hg, hk;
+  // the vector applied: z, or z + beta p (CG), or omega0 D^-1 b (APPLY_SMOOTH0:
+  // b in the z slots, D^-1 in the direction slots)
+  const T* const* zs = kSmooth0 ? a.jr : a.z;
+  const T* const* us = kSmooth0 ? a.dinv : a.u;
+  const T om0 = (T)a.omega0;
+  auto comb = [&](T z, T p) -> T {
+    if constexpr (kSmooth0) return om0 * p * z;
+    else return first ? z : z + tb * p;
+  };
+  T oz[2], op[2] = {T(0), T(0)}, og, ok, hz[2], hp[2] = {T(0), T(0)}, hg, hk;
   bool oin = false, hin = false;
   auto fetch = [&](int jj) {
     const bool yin = jj >= 0 && jj < g.ny;
@@ -1187,17 +1202,19 @@ __device__ __forceinline__ void apply2_tile(const ElastArgs<T>& a, int bx, int b
     const int eh = hin ? jj * g.px + rg_x : 0;
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
-      oz[d] = a.z[d][eo];
-      op[d] = a.u[d][eo];
-      hz[d] = a.z[d][eh];
-      hp[d] = a.u[d][eh];
+      oz[d] = zs[d][eo];
+      hz[d] = zs[d][eh];
+      if constexpr (!kSmooth || kSmooth0) {     // a sweep applies z itself
+        op[d] = us[d][eo];
+        hp[d] = us[d][eh];
+      }
     }
     og = a.G[eo]; ok = a.K[eo];
     hg = a.G[eh]; hk = a.K[eh];
   };
   auto stash = [&](int slot, T (&vp)[2], T& vg, T& vk) {
 #pragma unroll
-    for (int d = 0; d < 2; ++d) vp[d] = oin ? (first ? oz[d] : oz[d] + tb * op[d]) : T(0);
+    for (int d = 0; d < 2; ++d) vp[d] = oin ? comb(oz[d], op[d]) : T(0);
     vg = oin ? og : T(0);
     vk = oin ? ok : T(0);
     sP[slot][0][c] = vp[0];
@@ -1205,7 +1222,7 @@ __device__ __forceinline__ void apply2_tile(const ElastArgs<T>& a, int bx, int b
     sG[slot][c] = vg;
     if (rg_t >= 0) {
 #pragma unroll
-      for (int d = 0; d < 2; ++d) sP[slot][d][rg_t] = hin ? (first ? hz[d] : hz[d] + tb * hp[d]) : T(0);
+      for (int d = 0; d < 2; ++d) sP[slot][d][rg_t] = hin ? comb(hz[d], hp[d]) : T(0);
       sG[slot][rg_t] = hin ? hg : T(0);
       if (rg_t == 0) sK[slot] = hin ? hk : T(0);
     }
@@ -1280,9 +1297,22 @@ __device__ __forceinline__ void apply2_tile(const ElastArgs<T>& a, int bx, int b
       T q0 = T(0), q1 = T(0);
       if (i > 0) q0 = sSxx[c - 1] - sxx + sxy_c - sxy_n;
       if (j > 0) q1 = syy_prev - syy + sxy_c - sSxy[sj][c + 1];
-      a.o1[0][e] = pc[0]; a.o1[1][e] = pc[1];
-      a.o2[0][e] = q0; a.o2[1][e] = q1;
-      acc += (double)pc[0] * (double)q0 + (double)pc[1] * (double)q1;
+      if constexpr (kSmooth) {
+        const T qv[2] = {q0, q1};
+        const T om = (T)a.omega;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          const T jb = a.jr[d][e];
+          const T r = jb - qv[d];
+          const T o = a.omega != 0.0 ? pc[d] + om * a.dinv[d][e] * r : r;
+          a.o1[d][e] = o;
+          acc += (double)jb * (double)o;
+        }
+      } else {
+        a.o1[0][e] = pc[0]; a.o1[1][e] = pc[1];
+        a.o2[0][e] = q0; a.o2[1][e] = q1;
+        acc += (double)pc[0] * (double)q0 + (double)pc[1] * (double)q1;
+      }
     }
     syy_prev = syy;
     sxy_c = sxy_n;
@@ -1460,6 +1490,17 @@ __global__ __launch_bounds__(A2W) void k_apply2(ElastArgs<T> a) {
   }
   __shared__ __align__(16) char smem[sizeof(Apply2Smem<T>)];
   apply2_tile(a, tile % gridDim.x, tile / gridDim.x, beta, first, bid, smem);
+}
+
+// 2D multigrid sweep (AM = APPLY_SMOOTH or APPLY_SMOOTH0) of one level on the
+// row tiles of k_apply2; exits at entry once the solve has converged
+template <typename T, int AM>
+__global__ __launch_bounds__(A2W) void k_apply2s(ElastArgs<T> a) {
+  if (a.scal[S_CONV] != 0.0) return;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  const int tile = xcd_tile(bid, gridDim.x * gridDim.y);
+  __shared__ __align__(16) char smem[sizeof(Apply2Smem<T>)];
+  apply2_tile<T, AM>(a, tile % gridDim.x, tile / gridDim.x, 0.0, true, bid, smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,4 +1,4 @@
-// Geometric multigrid V-cycle as the preconditioner of the 3D equilibrium CG
+// Geometric multigrid V-cycle as the preconditioner of the equilibrium CG
 // (the staggered small-strain operator of Eq. 29, momentum line, and Eq. 32).
 //
 // Level l + 1 has half the cells of level l along every axis (cell size 2h);
@@ -195,6 +195,135 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(Grid gf, Grid gc, CVec3<T> r
           s += wn[sa] * w[u][ob] * w[v][oc] * rf.a[d][gidx(gf, idx[0], idx[1], idx[2])];
         }
     bc.a[d][ec] = T(0.25) * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2D (plane strain) levels: the same construction with two face components,
+// one transverse axis per component, and the restriction the transposed
+// prolongation divided by 2 (the operator carries 1/h, the energy h).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_coarsen2(Grid gf, Grid gc, const T* Kf, const T* Gf, T* Kc, T* Gc) {
+  const long n = (long)gc.nx * gc.ny;
+  for (long q = (long)blockIdx.x * NT + threadIdx.x; q < n; q += (long)gridDim.x * NT) {
+    const int I = (int)(q % gc.nx), J = (int)(q / gc.nx);
+    T sk = T(0), sg = T(0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int e = gidx(gf, 2 * I + (c & 1), 2 * J + (c >> 1), 0);
+      sk += Kf[e];
+      sg += Gf[e];
+    }
+    const int ec = gidx(gc, I, J, 0);
+    Kc[ec] = T(0.25) * sk;
+    Gc[ec] = T(0.25) * sg;
+  }
+}
+
+// Jacobi inverse diagonal of a 2D level: per face, the M of the two cells it
+// separates and the moduli of the 2 interior nodes at its ends, times 1/h
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_diag2(Grid g, T ih, const T* K, const T* G, Vec3<T> dinv) {
+  const long n = (long)g.nx * g.ny;
+  auto Gc = [&](int i, int j) { return G[gidx(g, i, j, 0)]; };
+  auto M = [&](int i, int j) { const int e = gidx(g, i, j, 0); return K[e] + T(4.0 / 3.0) * G[e]; };
+  auto gxy = [&](int i, int j) -> T {
+    return (i > 0 && i < g.nx && j > 0 && j < g.ny)
+               ? T(0.25) * (Gc(i - 1, j - 1) + Gc(i, j - 1) + Gc(i - 1, j) + Gc(i, j)) : T(0);
+  };
+  for (long q = (long)blockIdx.x * NT + threadIdx.x; q < n; q += (long)gridDim.x * NT) {
+    const int i = (int)(q % g.nx), j = (int)(q / g.nx);
+    const int e = gidx(g, i, j, 0);
+    const T d0 = i > 0 ? M(i - 1, j) + M(i, j) + gxy(i, j) + gxy(i, j + 1) : T(0);
+    const T d1 = j > 0 ? M(i, j - 1) + M(i, j) + gxy(i, j) + gxy(i + 1, j) : T(0);
+    dinv.a[0][e] = d0 > T(0) ? T(1) / (d0 * ih) : T(0);
+    dinv.a[1][e] = d1 > T(0) ? T(1) / (d1 * ih) : T(0);
+  }
+}
+
+// fine += P coarse, one fine cell per thread (2D)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_prolong2(Grid gf, Grid gc, CVec3<T> xc, Vec3<T> xf, const double* scal) {
+  if (scal[S_CONV] != 0.0) return;
+  const long q = (long)blockIdx.x * NT + threadIdx.x;
+  if (q >= (long)gf.nx * gf.ny) return;
+  const int f[2] = {(int)(q % gf.nx), (int)(q / gf.nx)};
+  const int nc[2] = {gc.nx, gc.ny};
+  int t0[2], t1[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    t0[a] = f[a] >> 1;
+    t1[a] = (f[a] & 1) ? min(t0[a] + 1, nc[a] - 1) : max(t0[a] - 1, 0);
+  }
+  const T tw[2] = {T(0.75), T(0.25)};
+  const int e = gidx(gf, f[0], f[1], 0);
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    if (f[d] == 0) continue;                     // roller face
+    const int a0 = f[d] >> 1;
+    const bool odd = f[d] & 1;
+    const int a1 = min(a0 + 1, nc[d] - 1);
+    const T wn[2] = {a0 > 0 ? (odd ? T(0.5) : T(1)) : T(0), (odd && a0 + 1 < nc[d]) ? T(0.5) : T(0)};
+    const int an[2] = {a0, a1};
+    const int u = 1 - d;
+    const int ru[2] = {t0[u], t1[u]};
+    T s = T(0);
+#pragma unroll
+    for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib) {
+        int idx[2];
+        idx[d] = an[ia];
+        idx[u] = ru[ib];
+        s += wn[ia] * tw[ib] * xc.a[d][gidx(gc, idx[0], idx[1], 0)];
+      }
+    xf.a[d][e] += s;
+  }
+}
+
+// coarse b = P^T r / 2, one coarse cell per thread (2D)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_restrict2(Grid gf, Grid gc, CVec3<T> rf, Vec3<T> bc, const double* scal) {
+  if (scal[S_CONV] != 0.0) return;
+  const long q = (long)blockIdx.x * NT + threadIdx.x;
+  if (q >= (long)gc.nx * gc.ny) return;
+  const int C[2] = {(int)(q % gc.nx), (int)(q / gc.nx)};
+  const int nc[2] = {gc.nx, gc.ny};
+  int rows[2][4];
+  T w[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int c = C[a], N = nc[a], nf = 2 * N;
+    rows[a][0] = max(2 * c - 1, 0);
+    rows[a][1] = 2 * c;
+    rows[a][2] = 2 * c + 1;
+    rows[a][3] = min(2 * c + 2, nf - 1);
+    w[a][0] = c > 0 ? T(0.25) : T(0);
+    w[a][1] = c > 0 ? T(0.75) : T(1);
+    w[a][2] = c < N - 1 ? T(0.75) : T(1);
+    w[a][3] = c < N - 1 ? T(0.25) : T(0);
+  }
+  const T wn[3] = {T(0.5), T(1), T(0.5)};
+  const int ec = gidx(gc, C[0], C[1], 0);
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    if (C[d] == 0) {                             // roller face
+      bc.a[d][ec] = T(0);
+      continue;
+    }
+    const int u = 1 - d;
+    T s = T(0);
+#pragma unroll
+    for (int sa = 0; sa < 3; ++sa)
+#pragma unroll
+      for (int ob = 0; ob < 4; ++ob) {
+        int idx[2];
+        idx[d] = 2 * C[d] - 1 + sa;
+        idx[u] = rows[u][ob];
+        s += wn[sa] * w[u][ob] * rf.a[d][gidx(gf, idx[0], idx[1], 0)];
+      }
+    bc.a[d][ec] = T(0.5) * s;
   }
 }
 

@@ -83,9 +83,10 @@ def test_workspace_size_and_validation(lib):
 
 
 def test_multigrid_workspace_and_validation(lib):
-    """The multigrid preconditioner adds its levels to the 3D workspace (two
-    more fine vectors and 17 arrays per coarse level, 1/8 of the cells each);
-    it is refused in 2D and for unknown preconditioner codes."""
+    """The multigrid preconditioner adds its levels to the workspace (3D: two
+    more fine vectors and 17 arrays per coarse level, 1/8 of the cells each;
+    2D: 12 arrays per coarse level, 1/4 of the cells each); batches and
+    unknown preconditioner codes are refused."""
     sz = lambda c: lib.pf_workspace_bytes(C.byref(c))
     for prec in ("fp64", "mixed"):
         jac = pf.make_config(3, (32, 32, 32), I.H_DEFAULT, 1e-8, precision=prec)
@@ -98,7 +99,15 @@ def test_multigrid_workspace_and_validation(lib):
         assert want <= extra <= want + 64 * 8192, (prec, extra, want)
     odd = pf.make_config(3, (9, 12, 16), I.H_DEFAULT, 1e-8, cg_precond="mg")
     assert sz(odd) > sz(pf.make_config(3, (9, 12, 16), I.H_DEFAULT, 1e-8))   # one level: Jacobi sweeps only
-    assert sz(pf.make_config(2, (32, 32), I.H_DEFAULT, 1e-8, cg_precond="mg")) == 0
+    jac2 = pf.make_config(2, (64, 64), I.H_DEFAULT, 1e-8)
+    mg2 = pf.make_config(2, (64, 64), I.H_DEFAULT, 1e-8, cg_precond="mg")
+    fine2 = 64 * 64 * 8
+    want2 = 4 * fine2 + 12 * (fine2 // 4 + fine2 // 16 + fine2 // 64)     # levels 32^2, 16^2, 8^2
+    assert want2 <= sz(mg2) - sz(jac2) <= want2 + 64 * 8192
+    ext = (pf.pf_extent * 1)()
+    ext[0].nx, ext[0].ny, ext[0].nz = 64, 64, 1
+    assert lib.pf_batch_workspace_bytes(C.byref(jac2), ext, 1) > 0
+    assert lib.pf_batch_workspace_bytes(C.byref(mg2), ext, 1) == 0
     bad = pf.make_config(3, (32, 32, 32), I.H_DEFAULT, 1e-8)
     bad.cg_precond = 2
     assert sz(bad) == 0

@@ -162,3 +162,112 @@ def test_mg_timing_kind():
     # and one before the first (CG apply launches: one per iteration, plus
     # the one that completes u)
     assert rep["smooth"][1] <= 4 * rep["apply"][1] + 8
+
+
+# ---------------------------------------------------------------------------
+# 2D (plane strain): the same preconditioner on the row-tile apply kernel
+# ---------------------------------------------------------------------------
+def _ctx2(shape, p, dt, **kw):
+    from paper_2111_11538_amd import pf
+    return pf.Context(2, shape, I.H_DEFAULT, dt, p, **kw)
+
+
+@pytest.mark.parametrize("kind,shape", [("porous", (128, 128)), ("core_shell", (64, 96)), ("core_shell", (70, 96))])
+def test_mg_2d_solve_matches_oracle(oracle, kind, shape):
+    """One FP64 solve from zero: u as the oracle's Jacobi-PCG solution to
+    1e-7 at rtol 1e-12 (128^2: five levels; 96x64: four; 96x70: two, 48x35
+    the coarsest), in a fraction of the Jacobi iterations."""
+    say(f"case mg 2d solve {kind} {shape}")
+    if kind == "porous":
+        wl = I.workload("porous_2d", n=shape[0])
+        f, p, dt = wl.fields, wl.params, wl.dt
+    else:
+        n = min(shape)
+        f = I.ic_core_shell(shape, r_core=0.3 * n, frame=2, noise_seed=I.SEED_BASE + 1)
+        p = I.Params()
+        dt = I.stable_dt(p, I.H_DEFAULT, 2)
+    o = oracle.OracleSim(2, shape, I.H_DEFAULT, dt, p, f, plasticity=False, cg_rtol=1e-12)
+    ost = o.mech_solve()
+    g = _ctx2(shape, p, dt, precision="fp64", plasticity=False, cg_rtol=1e-12, cg_precond="mg")
+    g.set_fields(f)
+    gst = g.mech_solve("zero")
+    out = g.fields()
+    g.close()
+    say(f"  iterations: mg {gst['cg_iters']}, oracle Jacobi {ost['cg_iters']}; true rel resid {gst['cg_rel_resid']:.2e}")
+    for c in ("ux", "uy"):
+        assert rel(out[c], getattr(o, c)) < 1e-7, (c, rel(out[c], getattr(o, c)))
+    assert gst["cg_rel_resid"] < 2e-12
+    assert 3 * gst["cg_iters"] < ost["cg_iters"], (gst["cg_iters"], ost["cg_iters"])
+
+
+def test_mg_2d_steps_match_oracle(oracle):
+    """Four coupled plastic FP64 steps of the 64^2 core-shell recipe with the
+    multigrid solve: fields, increments, u and plastic strain as the oracle's."""
+    shape = (64, 64)
+    say(f"case mg 2d steps {shape}")
+    wl = I.workload("core_shell_2d", n=64)
+    f = I.ic_core_shell(shape, r_core=0.3 * 64, frame=2, noise_seed=I.SEED_BASE + 1)
+    o = oracle.OracleSim(2, shape, wl.h, wl.dt, wl.params, f, plasticity=True, cg_rtol=1e-12)
+    g = _ctx2(shape, wl.params, wl.dt, precision="fp64", plasticity=True, cg_rtol=1e-12, cg_precond="mg")
+    g.set_fields(f)
+    f0 = {k: np.array(f[k], dtype=np.float64) for k in NAMES}
+    for _ in range(4):
+        ost = o.step()
+        gst = g.step()
+    out = g.fields()
+    g.close()
+    for k in NAMES:
+        assert rel(out[k], o.f[k]) < 1e-12, k
+        d_or = o.f[k] - f0[k]
+        if np.linalg.norm(d_or) > 0:
+            assert rel(out[k] - f0[k], d_or) < 1e-6, (k, rel(out[k] - f0[k], d_or))
+    for c in ("ux", "uy"):
+        assert rel(out[c], getattr(o, c)) < 1e-7, c
+    if np.max(o.epsP) > 0:
+        assert rel(out["epsP"], o.epsP) < 1e-6
+    assert abs(gst["O_drift"]) < 1e-13 and gst["nonfinite"] == 0
+    say(f"  last step iterations: mg {gst['cg_iters']}, oracle Jacobi {ost['cg_iters']}")
+    assert gst["cg_iters"] < ost["cg_iters"]
+
+
+def test_mg_2d_porous_2048_satisfies_the_oracle_equations(oracle):
+    """The 2048^2 porous recipe in FP32 at rtol 1e-6 (the benchmark's 2D
+    configuration, nine levels down to 8^2): the multigrid solve's
+    displacement satisfies the oracle's own operator and right-hand side to
+    the FP32 bound of the Jacobi path (3e-5), in a small fraction of the
+    Jacobi iterations."""
+    wl = I.workload("porous_2d", n=2048)
+    say(f"case mg 2d {wl.shape} mixed")
+    its = {}
+    for prec in ("jacobi", "mg"):
+        g = _ctx2(wl.shape, wl.params, wl.dt, precision="mixed", plasticity=True, cg_rtol=1e-6, cg_precond=prec)
+        g.set_fields(wl.fields)
+        st = g.mech_solve("zero")
+        its[prec] = st["cg_iters"]
+        if prec == "mg":
+            u = [g.get("ux"), g.get("uy")]
+            gres = st["cg_rel_resid"]
+        g.close()
+    o = oracle.OracleSim(2, wl.shape, wl.h, wl.dt, wl.params, wl.fields, plasticity=True)
+    K, G = o.moduli()
+    b = o.rhs()
+    q = o.apply(K, G, u)
+    ores = np.sqrt(sum(float(np.sum((bb - qq) ** 2)) for bb, qq in zip(b, q)) / sum(float(np.sum(x ** 2)) for x in b))
+    say(f"  iterations: mg {its['mg']}, Jacobi {its['jacobi']}; residual GPU {gres:.2e}, oracle {ores:.2e}")
+    assert ores <= 3e-5, ores
+    assert abs(ores - gres) <= 0.05 * gres, (ores, gres)
+    assert 10 * its["mg"] < its["jacobi"], its
+
+
+def test_mg_2d_bitwise_repeatable():
+    wl = I.workload("porous_2d", n=256)
+    outs = []
+    for _ in range(2):
+        g = _ctx2(wl.shape, wl.params, wl.dt, precision="mixed", plasticity=True, cg_rtol=1e-6, cg_precond="mg")
+        g.set_fields(wl.fields)
+        st = g.step(3)
+        outs.append((g.fields(), st))
+        g.close()
+    for k in outs[0][0]:
+        assert np.array_equal(outs[0][0][k], outs[1][0][k]), k
+    assert outs[0][1]["cg_iters"] == outs[1][1]["cg_iters"]
