@@ -126,10 +126,13 @@ Layout make_layout(const pf_config* c) {
     while (L.kz_cg > 1 && (long long)nbx * nbyc * ((g.nz + L.kz_cg - 1) / L.kz_cg) < 512) L.kz_cg /= 2;
     L.gcg = dim3(nbx, nbyc, (g.nz + L.kz_cg - 1) / L.kz_cg);
   } else {
-    // rows of A2W columns marching along y over kz_ap rows; keep >= 512 blocks
+    // rows of A2W columns marching along y over kz_ap rows; keep >= 2048
+    // blocks (a block is 4 waves: at 2048^2, 512 blocks left the apply and
+    // the multigrid sweeps latency-bound, 47 and 62 us against 39 and 31 us
+    // with 2048; 4096 and 8192 were slower again)
     int nbx2 = (g.nx + A2W - 1) / A2W;
     L.kz_ap = 32;
-    while (L.kz_ap > 1 && (long long)nbx2 * ((g.ny + L.kz_ap - 1) / L.kz_ap) < 512) L.kz_ap /= 2;
+    while (L.kz_ap > 1 && (long long)nbx2 * ((g.ny + L.kz_ap - 1) / L.kz_ap) < 2048) L.kz_ap /= 2;
     L.gap = dim3(nbx2, (g.ny + L.kz_ap - 1) / L.kz_ap, 1);
     L.kz_cg = L.kz_ap;
     L.gcg = L.gap;
@@ -187,7 +190,7 @@ Layout make_layout(const pf_config* c) {
     const int dim = c->dim;
     // apply-kernel grid of a level: 3D 64 x kApplyBY column tiles over slabs
     // of kz planes, 2D rows of A2W cells over runs of kz rows; kz halved
-    // until the level has 512 blocks or kz is 1
+    // until the level has 512 (2D: 2048) blocks or kz is 1
     auto apply_geom = [dim](Layout::MGLevel& m) {
       if (dim == 3) {
         const int nbx = (m.g.nx + TX - 1) / TX, nby8 = (m.g.ny + kApplyBY - 1) / kApplyBY;
@@ -197,7 +200,7 @@ Layout make_layout(const pf_config* c) {
       } else {
         const int nbx = (m.g.nx + A2W - 1) / A2W;
         m.kz = 32;
-        while (m.kz > 1 && (long long)nbx * ((m.g.ny + m.kz - 1) / m.kz) < 512) m.kz /= 2;
+        while (m.kz > 1 && (long long)nbx * ((m.g.ny + m.kz - 1) / m.kz) < 2048) m.kz /= 2;
         m.grid = dim3(nbx, (m.g.ny + m.kz - 1) / m.kz, 1);
       }
     };
