@@ -78,6 +78,7 @@ struct Layout {
   MGLevel mg[kMGMax];
   size_t o_mg_part;
   int nb_mg;               // partials of the level-0 smoothing (its apply grid)
+  int mg_tail;             // 2D: first level (>= 1) the single-block tail kernel runs from, or -1
   size_t total;
 };
 
@@ -186,6 +187,7 @@ Layout make_layout(const pf_config* c) {
     L.o_sp_scal = take(SP_COUNT * sizeof(double));
   }
   L.mg_n = 0;
+  L.mg_tail = -1;
   if (c->cg_precond == 1) {
     const int dim = c->dim;
     // apply-kernel grid of a level: 3D 64 x kApplyBY column tiles over slabs
@@ -241,6 +243,13 @@ Layout make_layout(const pf_config* c) {
       }
       ++L.mg_n;
     }
+    L.mg_tail = -1;
+    if (dim == 2)
+      for (int l = 1; l < L.mg_n; ++l)
+        if ((long long)L.mg[l].g.nx * L.mg[l].g.ny <= kTailCells && L.mg_n - l <= kTailMax) {
+          L.mg_tail = l;
+          break;
+        }
     L.nb_mg = (int)(m0.grid.x * m0.grid.y * m0.grid.z);
     int nb_mg_max = 0;
     for (int l = 0; l < L.mg_n; ++l) nb_mg_max = std::max(nb_mg_max, (int)(L.mg[l].grid.x * L.mg[l].grid.y * L.mg[l].grid.z));
@@ -619,7 +628,10 @@ struct Impl {
         timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply2s<T, APPLY_SMOOTH0>, m.grid, dim3(A2W), 0, st,
                      a);
     };
-    for (int l = 0; l < last; ++l) {             // pre-smoothing and restriction, down to the coarsest
+    // 2D: the levels from mg_tail on run in one single-block launch
+    const int tail = DIM == 2 ? L.mg_tail : -1;
+    const int down_end = tail > 0 ? tail : last;
+    for (int l = 0; l < down_end; ++l) {         // pre-smoothing and restriction, down to the coarsest
       const Layout::MGLevel& m = L.mg[l];
       sweep0(l, m.ox);
       sweep(l, m.ox, m.orr, 0.0);
@@ -627,16 +639,40 @@ struct Impl {
       timed_launch(c, PF_K_PRECOND, j, DIM == 3 ? k_mg_restrict<T> : k_mg_restrict2<T>, mg_cell_blocks(mc.g), dim3(NT),
                    0, st, m.g, mc.g, mg_cvec(c, m.orr), mg_vec(c, mc.ob), scal);
     }
-    {                                            // coarsest level: a fixed number of sweeps from zero
+    static_assert(kCoarseSweeps % 2 == 0, "the coarsest sweeps end in x");
+    if (tail > 0) {                              // the small levels' whole cycle in one launch
+      MGTailArgs<T> ta{};
+      ta.n = last - tail + 1;
+      for (int t = 0; t < ta.n; ++t) {
+        const Layout::MGLevel& m = L.mg[tail + t];
+        MGTailLevel<T>& v = ta.lv[t];
+        v.g = m.g;
+        v.ih = (T)(1.0 / m.h);
+        v.K = c->arr<T>(m.oK);
+        v.G = c->arr<T>(m.oG);
+        for (int d = 0; d < 2; ++d) {
+          v.dinv[d] = c->arr<T>(m.odi[d]);
+          v.b[d] = c->arr<T>(m.ob[d]);
+          v.bw[d] = c->arr<T>(m.ob[d]);
+          v.x[d] = c->arr<T>(m.ox[d]);
+          v.xt[d] = c->arr<T>(m.oxt[d]);
+          v.r[d] = c->arr<T>(m.orr[d]);
+        }
+      }
+      ta.s0 = (T)kStep[0];
+      ta.s1 = (T)kStep[1];
+      ta.coarse_sweeps = kCoarseSweeps;
+      ta.scal = scal;
+      timed_launch(c, PF_K_PRECOND, j, k_mg_tail2<T>, dim3(1), dim3(kTailNT), 0, st, ta);
+    } else {                                     // coarsest level: a fixed number of sweeps from zero
       const Layout::MGLevel& m = L.mg[last];
-      static_assert(kCoarseSweeps % 2 == 0, "the coarsest sweeps end in x");
       sweep0(last, m.ox);
       for (int s = 2; s < kCoarseSweeps; ++s) {
         if (s & 1) sweep(last, m.oxt, m.ox, kStep[1]);
         else sweep(last, m.ox, m.oxt, kStep[0]);
       }
     }
-    for (int l = last - 1; l >= 0; --l) {        // prolongation and post-smoothing, up to the solve's grid
+    for (int l = down_end - 1; l >= 0; --l) {    // prolongation and post-smoothing, up to the solve's grid
       const Layout::MGLevel& m = L.mg[l];
       const Layout::MGLevel& mc = L.mg[l + 1];
       timed_launch(c, PF_K_PRECOND, j, DIM == 3 ? k_mg_prolong<T> : k_mg_prolong2<T>, mg_cell_blocks(m.g), dim3(NT), 0,

@@ -242,13 +242,11 @@ __global__ __launch_bounds__(NT) void k_mg_diag2(Grid g, T ih, const T* K, const
   }
 }
 
-// fine += P coarse, one fine cell per thread (2D)
+// fine += P coarse at fine cell (f0, f1) (2D)
 template <typename T>
-__global__ __launch_bounds__(NT) void k_mg_prolong2(Grid gf, Grid gc, CVec3<T> xc, Vec3<T> xf, const double* scal) {
-  if (scal[S_CONV] != 0.0) return;
-  const long q = (long)blockIdx.x * NT + threadIdx.x;
-  if (q >= (long)gf.nx * gf.ny) return;
-  const int f[2] = {(int)(q % gf.nx), (int)(q / gf.nx)};
+__device__ __forceinline__ void prolong2_cell(const Grid& gf, const Grid& gc, const T* const* xc, T* const* xf, int f0,
+                                              int f1) {
+  const int f[2] = {f0, f1};
   const int nc[2] = {gc.nx, gc.ny};
   int t0[2], t1[2];
 #pragma unroll
@@ -276,19 +274,17 @@ __global__ __launch_bounds__(NT) void k_mg_prolong2(Grid gf, Grid gc, CVec3<T> x
         int idx[2];
         idx[d] = an[ia];
         idx[u] = ru[ib];
-        s += wn[ia] * tw[ib] * xc.a[d][gidx(gc, idx[0], idx[1], 0)];
+        s += wn[ia] * tw[ib] * xc[d][gidx(gc, idx[0], idx[1], 0)];
       }
-    xf.a[d][e] += s;
+    xf[d][e] += s;
   }
 }
 
-// coarse b = P^T r / 2, one coarse cell per thread (2D)
+// coarse b = P^T r / 2 at coarse cell (c0, c1) (2D)
 template <typename T>
-__global__ __launch_bounds__(NT) void k_mg_restrict2(Grid gf, Grid gc, CVec3<T> rf, Vec3<T> bc, const double* scal) {
-  if (scal[S_CONV] != 0.0) return;
-  const long q = (long)blockIdx.x * NT + threadIdx.x;
-  if (q >= (long)gc.nx * gc.ny) return;
-  const int C[2] = {(int)(q % gc.nx), (int)(q / gc.nx)};
+__device__ __forceinline__ void restrict2_cell(const Grid& gf, const Grid& gc, const T* const* rf, T* const* bc, int c0,
+                                               int c1) {
+  const int C[2] = {c0, c1};
   const int nc[2] = {gc.nx, gc.ny};
   int rows[2][4];
   T w[2][4];
@@ -309,7 +305,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict2(Grid gf, Grid gc, CVec3<T> 
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
     if (C[d] == 0) {                             // roller face
-      bc.a[d][ec] = T(0);
+      bc[d][ec] = T(0);
       continue;
     }
     const int u = 1 - d;
@@ -321,9 +317,175 @@ __global__ __launch_bounds__(NT) void k_mg_restrict2(Grid gf, Grid gc, CVec3<T> 
         int idx[2];
         idx[d] = 2 * C[d] - 1 + sa;
         idx[u] = rows[u][ob];
-        s += wn[sa] * w[u][ob] * rf.a[d][gidx(gf, idx[0], idx[1], 0)];
+        s += wn[sa] * w[u][ob] * rf[d][gidx(gf, idx[0], idx[1], 0)];
       }
-    bc.a[d][ec] = T(0.5) * s;
+    bc[d][ec] = T(0.5) * s;
+  }
+}
+
+// fine += P coarse, one fine cell per thread (2D)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_prolong2(Grid gf, Grid gc, CVec3<T> xc, Vec3<T> xf, const double* scal) {
+  if (scal[S_CONV] != 0.0) return;
+  const long q = (long)blockIdx.x * NT + threadIdx.x;
+  if (q >= (long)gf.nx * gf.ny) return;
+  prolong2_cell<T>(gf, gc, xc.a, xf.a, (int)(q % gf.nx), (int)(q / gf.nx));
+}
+
+// coarse b = P^T r / 2, one coarse cell per thread (2D)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_restrict2(Grid gf, Grid gc, CVec3<T> rf, Vec3<T> bc, const double* scal) {
+  if (scal[S_CONV] != 0.0) return;
+  const long q = (long)blockIdx.x * NT + threadIdx.x;
+  if (q >= (long)gc.nx * gc.ny) return;
+  restrict2_cell<T>(gf, gc, rf.a, bc.a, (int)(q % gc.nx), (int)(q / gc.nx));
+}
+
+// ---------------------------------------------------------------------------
+// The small 2D levels in one launch: below about a thousand cells a level's
+// kernels are launch-bound (about 6 us each, some 20 of them per cycle at
+// 2048^2), so one block of 1024 threads runs the whole V-cycle from the
+// first such level down and back, each step a loop over the level's cells
+// and a block barrier.  The steps, their order and the Chebyshev steps are
+// those of the launch-per-step cycle; the operator is the staggered one of
+// the apply kernels evaluated per face from global memory (the level's
+// vectors stay in the caches).
+// ---------------------------------------------------------------------------
+constexpr int kTailNT = 1024;
+constexpr int kTailMax = 6;
+constexpr int kTailCells = 1024;            // levels with at most this many cells go into the tail
+
+template <typename T>
+struct MGTailLevel {
+  Grid g;
+  T ih;
+  const T* K;
+  const T* G;
+  const T* dinv[2];
+  const T* b[2];
+  T* bw[2];                                      // b of levels after the first (written by the restriction)
+  T* x[2];
+  T* xt[2];
+  T* r[2];
+};
+
+template <typename T>
+struct MGTailArgs {
+  MGTailLevel<T> lv[kTailMax];
+  int n;                                         // levels (the last one is the coarsest)
+  T s0, s1;                                      // the Chebyshev steps of a sweep pair
+  int coarse_sweeps;                             // even
+  const double* scal;
+};
+
+// q = A u at the two faces of cell (i, j) of a 2D level (the stencil of
+// k_apply2: sigma from the face displacements, q0 = sxx(i-1) - sxx(i) +
+// sxy(i, j) - sxy(i, j+1), q1 = syy(j-1) - syy(j) + sxy(i, j) - sxy(i+1, j);
+// roller faces (i = 0, j = 0) get zero; the high walls hold zero)
+template <typename T>
+__device__ __forceinline__ void cell_apply2(const MGTailLevel<T>& L, const T* ux, const T* uy, int i, int j, T& q0,
+                                            T& q1) {
+  const Grid& g = L.g;
+  const T ih = L.ih;
+  auto X = [&](int ii, int jj) -> T { return (ii < g.nx && jj < g.ny) ? ux[jj * g.px + ii] : T(0); };
+  auto Y = [&](int ii, int jj) -> T { return (ii < g.nx && jj < g.ny) ? uy[jj * g.px + ii] : T(0); };
+  auto Gc = [&](int ii, int jj) -> T { return L.G[jj * g.px + ii]; };
+  auto snn = [&](int ii, int jj, T& sxx, T& syy) {
+    const T exx = (X(ii + 1, jj) - X(ii, jj)) * ih;
+    const T eyy = (Y(ii, jj + 1) - Y(ii, jj)) * ih;
+    const T tr = exx + eyy;
+    const T G2 = T(2) * Gc(ii, jj);
+    const T lam = L.K[jj * g.px + ii] * tr - G2 * tr * T(1.0 / 3.0);
+    sxx = lam + G2 * exx;
+    syy = lam + G2 * eyy;
+  };
+  auto sxy = [&](int ii, int jj) -> T {
+    if (!(ii > 0 && ii < g.nx && jj > 0 && jj < g.ny)) return T(0);
+    const T ge = T(0.25) * (Gc(ii - 1, jj - 1) + Gc(ii, jj - 1) + Gc(ii - 1, jj) + Gc(ii, jj));
+    return ge * ((X(ii, jj) - X(ii, jj - 1)) + (Y(ii, jj) - Y(ii - 1, jj))) * ih;
+  };
+  T sxx, syy;
+  snn(i, j, sxx, syy);
+  const T sxy0 = sxy(i, j);
+  q0 = T(0);
+  q1 = T(0);
+  if (i > 0) {
+    T lxx, lyy;
+    snn(i - 1, j, lxx, lyy);
+    q0 = lxx - sxx + sxy0 - sxy(i, j + 1);
+  }
+  if (j > 0) {
+    T bxx, byy;
+    snn(i, j - 1, bxx, byy);
+    q1 = byy - syy + sxy0 - sxy(i + 1, j);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTailNT) void k_mg_tail2(MGTailArgs<T> a) {
+  if (a.scal[S_CONV] != 0.0) return;
+  // writes of one step become visible to the whole block at the barrier
+  auto sync = [] {
+    __threadfence_block();
+    __syncthreads();
+  };
+  // xt = s0 D^-1 b (the first sweep from zero)
+  auto jac0 = [&](const MGTailLevel<T>& L) {
+    const int n = L.g.nx * L.g.ny;
+    for (int q = threadIdx.x; q < n; q += kTailNT) {
+      const int e = (q / L.g.nx) * L.g.px + q % L.g.nx;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) L.xt[d][e] = a.s0 * L.dinv[d][e] * L.b[d][e];
+    }
+    sync();
+  };
+  // out = in + step D^-1 (b - A in), or with resid the residual b - A in
+  auto sweep = [&](const MGTailLevel<T>& L, T* const* in, T* const* out, T step, bool resid) {
+    const int n = L.g.nx * L.g.ny;
+    for (int q = threadIdx.x; q < n; q += kTailNT) {
+      const int i = q % L.g.nx, j = q / L.g.nx;
+      T q0, q1;
+      cell_apply2(L, in[0], in[1], i, j, q0, q1);
+      const int e = j * L.g.px + i;
+      const T qv[2] = {q0, q1};
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const T r = L.b[d][e] - qv[d];
+        out[d][e] = resid ? r : in[d][e] + step * L.dinv[d][e] * r;
+      }
+    }
+    sync();
+  };
+  const int last = a.n - 1;
+  for (int l = 0; l < last; ++l) {               // down: two sweeps from zero, residual, restriction
+    const MGTailLevel<T>& L = a.lv[l];
+    jac0(L);
+    sweep(L, L.xt, L.x, a.s1, false);
+    sweep(L, L.x, L.r, T(0), true);
+    const MGTailLevel<T>& C = a.lv[l + 1];
+    const int nc = C.g.nx * C.g.ny;
+    for (int q = threadIdx.x; q < nc; q += kTailNT)
+      restrict2_cell<T>(L.g, C.g, (const T* const*)L.r, C.bw, q % C.g.nx, q / C.g.nx);
+    sync();
+  }
+  {                                              // the coarsest level: sweeps from zero
+    const MGTailLevel<T>& L = a.lv[last];
+    jac0(L);
+    sweep(L, L.xt, L.x, a.s1, false);
+    for (int s = 2; s < a.coarse_sweeps; ++s) {
+      if (s & 1) sweep(L, L.xt, L.x, a.s1, false);
+      else sweep(L, L.x, L.xt, a.s0, false);
+    }
+  }
+  for (int l = last - 1; l >= 0; --l) {          // up: prolongation, two sweeps
+    const MGTailLevel<T>& L = a.lv[l];
+    const MGTailLevel<T>& C = a.lv[l + 1];
+    const int nf = L.g.nx * L.g.ny;
+    for (int q = threadIdx.x; q < nf; q += kTailNT)
+      prolong2_cell<T>(L.g, C.g, (const T* const*)C.x, L.x, q % L.g.nx, q / L.g.nx);
+    sync();
+    sweep(L, L.x, L.xt, a.s0, false);
+    sweep(L, L.xt, L.x, a.s1, false);
   }
 }
 
