@@ -77,6 +77,7 @@ struct Layout {
   int mg_n;
   MGLevel mg[kMGMax];
   size_t o_mg_part;
+  size_t o_mg_tail;        // 2D: the tail kernel's level table (written once per solve)
   int nb_mg;               // partials of the level-0 smoothing (its apply grid)
   int mg_tail;             // 2D: first level (>= 1) the single-block tail kernel runs from, or -1
   size_t total;
@@ -254,6 +255,7 @@ Layout make_layout(const pf_config* c) {
     int nb_mg_max = 0;
     for (int l = 0; l < L.mg_n; ++l) nb_mg_max = std::max(nb_mg_max, (int)(L.mg[l].grid.x * L.mg[l].grid.y * L.mg[l].grid.z));
     L.o_mg_part = take((size_t)nb_mg_max * sizeof(double));
+    L.o_mg_tail = L.mg_tail > 0 ? take(sizeof(MGTailArgs<double>)) : 0;
   }
   if (c->warm == PF_WARM_LEARNED) {
     for (int d = 0; d < 3; ++d) { L.o_uo[d] = take(arr); L.o_du[d] = take(arr); }
@@ -297,6 +299,7 @@ struct pf_ctx {
   char err[512];
   bool bad;
   bool ledger_valid;
+  bool mg_tail_ready;      // the 2D multigrid tail kernel's level table is in the workspace
   int cur;                 // which field buffer holds the current state
   long long steps;
   int last_iters;
@@ -543,6 +546,15 @@ struct Impl {
   // set-up pass wrote (once per solve)
   static void mg_setup(pf_ctx* c) {
     const Layout& L = c->L;
+    if constexpr (DIM == 2)
+      if (L.mg_tail > 0 && !c->mg_tail_ready) {
+        // the tail kernel's level table, passed by pointer (as a kernel
+        // argument, about 1 KB, it cost a device copy per launch); the
+        // workspace addresses it holds are fixed for the context's life
+        MGTailArgs<T> ta = mg_tail_args(c);
+        if (hipMemcpyAsync(c->ws + L.o_mg_tail, &ta, sizeof(ta), hipMemcpyHostToDevice, c->stream) == hipSuccess)
+          c->mg_tail_ready = true;
+      }
     for (int l = 1; l < L.mg_n; ++l) {
       const Layout::MGLevel& f = L.mg[l - 1];
       const Layout::MGLevel& m = L.mg[l];
@@ -557,17 +569,47 @@ struct Impl {
   // z = M^-1 r: one V-cycle from zero on the CG residual (level 0: b = r,
   // x = z), then r.z into the r.z partials CG reads (n_rz slots of part_u).
   // j: the CG launch index the cycle follows (-1: before the first).
+  // Jacobi steps: each pair of sweeps applies (I - s0 D^-1 A)(I - s1 D^-1 A),
+  // the degree-2 Chebyshev polynomial smallest on [lmax / 6, lmax] (its
+  // roots 1 / s at the Chebyshev nodes of that interval).  Power iteration
+  // on the 32^3 porous and core-shell recipes puts the largest eigenvalue
+  // of D^-1 A near 4.26 (the phases' Poisson ratios fix it); lmax = 4.5,
+  // and the pair amplifies only eigenvalues above (s0 + s1) / (s0 s1) = 5.25.
+  static constexpr double kLmax = 4.5, kLmin = kLmax / 6.0;
+  static constexpr double kMid = 0.5 * (kLmax + kLmin), kHalf = 0.5 * (kLmax - kLmin) * 0.70710678118654752;
+  static constexpr double kStep[2] = {1.0 / (kMid + kHalf), 1.0 / (kMid - kHalf)};
+  static constexpr int kCoarseSweeps = 8;
+
+  // 2D: the level table of the single-block tail kernel (levels mg_tail ..)
+  static MGTailArgs<T> mg_tail_args(pf_ctx* c) {
+    const Layout& L = c->L;
+    MGTailArgs<T> ta{};
+    ta.n = L.mg_n - L.mg_tail;
+    for (int t = 0; t < ta.n; ++t) {
+      const Layout::MGLevel& m = L.mg[L.mg_tail + t];
+      MGTailLevel<T>& v = ta.lv[t];
+      v.g = m.g;
+      v.ih = (T)(1.0 / m.h);
+      v.K = c->arr<T>(m.oK);
+      v.G = c->arr<T>(m.oG);
+      for (int d = 0; d < 2; ++d) {
+        v.dinv[d] = c->arr<T>(m.odi[d]);
+        v.b[d] = c->arr<T>(m.ob[d]);
+        v.bw[d] = c->arr<T>(m.ob[d]);
+        v.x[d] = c->arr<T>(m.ox[d]);
+        v.xt[d] = c->arr<T>(m.oxt[d]);
+        v.r[d] = c->arr<T>(m.orr[d]);
+      }
+    }
+    ta.s0 = (T)kStep[0];
+    ta.s1 = (T)kStep[1];
+    ta.coarse_sweeps = kCoarseSweeps;
+    ta.scal = c->scal();
+    return ta;
+  }
+
   static void mg_vcycle(pf_ctx* c, const ElastArgs<T>& e, int j, int n_rz) {
-    // Jacobi steps: each pair of sweeps applies (I - s0 D^-1 A)(I - s1 D^-1 A),
-    // the degree-2 Chebyshev polynomial smallest on [lmax / 6, lmax] (its
-    // roots 1 / s at the Chebyshev nodes of that interval).  Power iteration
-    // on the 32^3 porous and core-shell recipes puts the largest eigenvalue
-    // of D^-1 A near 4.26 (the phases' Poisson ratios fix it); lmax = 4.5,
-    // and the pair amplifies only eigenvalues above (s0 + s1) / (s0 s1) = 5.25.
-    constexpr double kLmax = 4.5, kLmin = kLmax / 6.0;
-    constexpr double kMid = 0.5 * (kLmax + kLmin), kHalf = 0.5 * (kLmax - kLmin) * 0.70710678118654752;
-    constexpr double kStep[2] = {1.0 / (kMid + kHalf), 1.0 / (kMid - kHalf)};
-    constexpr int kNu = 2, kCoarseSweeps = 8;
+    constexpr int kNu = 2;
     static_assert(kNu == 2, "the pre-smoothing is the two-sweep pass from zero; two post-smoothing sweeps");
     const Layout& L = c->L;
     hipStream_t st = c->stream;
@@ -641,29 +683,8 @@ struct Impl {
     }
     static_assert(kCoarseSweeps % 2 == 0, "the coarsest sweeps end in x");
     if (tail > 0) {                              // the small levels' whole cycle in one launch
-      MGTailArgs<T> ta{};
-      ta.n = last - tail + 1;
-      for (int t = 0; t < ta.n; ++t) {
-        const Layout::MGLevel& m = L.mg[tail + t];
-        MGTailLevel<T>& v = ta.lv[t];
-        v.g = m.g;
-        v.ih = (T)(1.0 / m.h);
-        v.K = c->arr<T>(m.oK);
-        v.G = c->arr<T>(m.oG);
-        for (int d = 0; d < 2; ++d) {
-          v.dinv[d] = c->arr<T>(m.odi[d]);
-          v.b[d] = c->arr<T>(m.ob[d]);
-          v.bw[d] = c->arr<T>(m.ob[d]);
-          v.x[d] = c->arr<T>(m.ox[d]);
-          v.xt[d] = c->arr<T>(m.oxt[d]);
-          v.r[d] = c->arr<T>(m.orr[d]);
-        }
-      }
-      ta.s0 = (T)kStep[0];
-      ta.s1 = (T)kStep[1];
-      ta.coarse_sweeps = kCoarseSweeps;
-      ta.scal = scal;
-      timed_launch(c, PF_K_PRECOND, j, k_mg_tail2<T>, dim3(1), dim3(kTailNT), 0, st, ta);
+      timed_launch(c, PF_K_PRECOND, j, k_mg_tail2<T>, dim3(1), dim3(kTailNT), 0, st,
+                   (const MGTailArgs<T>*)c->arr<MGTailArgs<T>>(L.o_mg_tail));
     } else {                                     // coarsest level: a fixed number of sweeps from zero
       const Layout::MGLevel& m = L.mg[last];
       sweep0(last, m.ox);
@@ -1091,6 +1112,7 @@ pf_status pf_init(const pf_config* cfg, const pf_params* params, void* workspace
   c->err[0] = 0;
   c->bad = false;
   c->ledger_valid = false;
+  c->mg_tail_ready = false;
   c->cur = 0;
   c->steps = 0;
   c->last_iters = 0;

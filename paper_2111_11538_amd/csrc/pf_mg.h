@@ -422,7 +422,8 @@ __device__ __forceinline__ void cell_apply2(const MGTailLevel<T>& L, const T* ux
 }
 
 template <typename T>
-__global__ __launch_bounds__(kTailNT) void k_mg_tail2(MGTailArgs<T> a) {
+__global__ __launch_bounds__(kTailNT) void k_mg_tail2(const MGTailArgs<T>* ap) {
+  const MGTailArgs<T>& a = *ap;
   if (a.scal[S_CONV] != 0.0) return;
   // writes of one step become visible to the whole block at the barrier
   auto sync = [] {
