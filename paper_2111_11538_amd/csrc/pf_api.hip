@@ -825,10 +825,15 @@ struct Impl {
     // Launches queued past convergence cost a few microseconds each, a check
     // (with its host synchronisation) some tens: the first chunk covers the
     // smaller of the last two counts, the second reaches the larger one, and
-    // later chunks grow with what has been launched.
+    // later chunks grow with what has been launched.  With the multigrid an
+    // iteration queued past convergence is some 45 launches and a check is
+    // cheap beside an iteration: the first chunk stops at the smaller count
+    // (a solve that needs exactly that many ends there without a queued
+    // iteration), the second at the larger, and later ones go one by one.
     const int p2 = c->prev_iters > 0 ? c->prev_iters : c->last_iters;
     const int lo = std::min(c->last_iters, p2), hi = std::max(c->last_iters, p2);
-    int chunk = c->cg_chunk > 0 ? c->cg_chunk : std::max(2, lo + 2);
+    const bool mg_chunks = L.mg_n > 0;
+    int chunk = c->cg_chunk > 0 ? c->cg_chunk : mg_chunks ? std::max(1, lo) : std::max(2, lo + 2);
     int nchunk = 0;
     auto apply_cg = [&](int j) {       // the apply launch of CG iteration j
       const int par = j & 1;
@@ -888,7 +893,10 @@ struct Impl {
       }
       ++nchunk;
       if (c->cg_chunk > 0) continue;
-      chunk = nchunk == 1 && hi + 2 > launched ? hi + 2 - launched : std::max(4, std::min(64, launched / 4));
+      if (mg_chunks)
+        chunk = nchunk == 1 && hi > launched ? hi - launched : 1;
+      else
+        chunk = nchunk == 1 && hi + 2 > launched ? hi + 2 - launched : std::max(4, std::min(64, launched / 4));
     }
     c->prev_iters = c->last_iters;
     c->last_iters = (int)c->host_scal[S_ITERS];
