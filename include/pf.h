@@ -86,8 +86,8 @@ typedef struct {
   int species_max_iter;   /* implicit species: CG iteration limit per step (reaching it is an error) */
   double species_rtol;    /* implicit species: stop each species' CG at ||r|| <= species_rtol ||b|| */
   int cg_precond;         /* preconditioner of the equilibrium CG: 0 Jacobi; 1 a geometric multigrid V-cycle
-                             (levels halve the cells while every side is even and above 8; Jacobi smoothing
-                             with Chebyshev steps; see pf_step).  Batches take 0 only. */
+                             (levels halve the cells, an odd side n to (n + 1) / 2, while every side is above 8;
+                             Jacobi smoothing with Chebyshev steps; see pf_step).  Batches take 0 only. */
 } pf_config;
 
 /* Material and model parameters, Table 1 of the paper; phase index 0 ferrite,

@@ -224,9 +224,9 @@ Layout make_layout(const pf_config* c) {
     while (L.mg_n < Layout::kMGMax) {
       const Grid& f = L.mg[L.mg_n - 1].g;
       const int lo = dim == 3 ? std::min(f.nx, std::min(f.ny, f.nz)) : std::min(f.nx, f.ny);
-      if ((f.nx & 1) || (f.ny & 1) || (dim == 3 && (f.nz & 1)) || lo <= 8) break;
+      if (lo <= 8) break;
       Layout::MGLevel& m = L.mg[L.mg_n];
-      m.g.nx = f.nx / 2; m.g.ny = f.ny / 2; m.g.nz = dim == 3 ? f.nz / 2 : 1;
+      m.g.nx = (f.nx + 1) / 2; m.g.ny = (f.ny + 1) / 2; m.g.nz = dim == 3 ? (f.nz + 1) / 2 : 1;
       m.g.px = (m.g.nx + 15) / 16 * 16;
       m.g.n = m.g.px * m.g.ny * m.g.nz;
       m.g.ns = m.g.n;

@@ -1,9 +1,10 @@
 // Geometric multigrid V-cycle as the preconditioner of the equilibrium CG
 // (the staggered small-strain operator of Eq. 29, momentum line, and Eq. 32).
 //
-// Level l + 1 has half the cells of level l along every axis (cell size 2h);
+// Level l + 1 has half the cells of level l along every axis (cell size 2h;
+// an odd side of n cells gets (n + 1) / 2, the last covering one fine cell);
 // its operator is the same staggered operator with the moduli K, G averaged
-// over the 8 children and its own Jacobi diagonal.  Transfers act on the
+// over the children and its own Jacobi diagonal.  Transfers act on the
 // face components: the prolongation takes, along the face normal, the
 // coincident coarse face (weight 1) or the mean of the two coarse faces
 // around a midway fine face, and across the normal interpolates linearly
@@ -31,7 +32,8 @@ struct CVec3 {
   const T* a[3];
 };
 
-// moduli of the coarse cells: the mean of their 8 children
+// moduli of the coarse cells: the mean of their children (8; fewer in the
+// last coarse cell along an odd side, which covers one fine cell there)
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_coarsen(Grid gf, Grid gc, const T* Kf, const T* Gf, T* Kc, T* Gc) {
   const long n = (long)gc.nx * gc.ny * gc.nz;
@@ -40,16 +42,39 @@ __global__ __launch_bounds__(NT) void k_mg_coarsen(Grid gf, Grid gc, const T* Kf
     const long r = q / gc.nx;
     const int J = (int)(r % gc.ny), K = (int)(r / gc.ny);
     T sk = T(0), sg = T(0);
+    int cnt = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const int e = gidx(gf, 2 * I + (c & 1), 2 * J + ((c >> 1) & 1), 2 * K + (c >> 2));
+      const int fi = 2 * I + (c & 1), fj = 2 * J + ((c >> 1) & 1), fk = 2 * K + (c >> 2);
+      if (fi >= gf.nx || fj >= gf.ny || fk >= gf.nz) continue;
+      const int e = gidx(gf, fi, fj, fk);
       sk += Kf[e];
       sg += Gf[e];
+      ++cnt;
     }
     const int ec = gidx(gc, I, J, K);
-    Kc[ec] = T(0.125) * sk;
-    Gc[ec] = T(0.125) * sg;
+    Kc[ec] = sk / T(cnt);
+    Gc[ec] = sg / T(cnt);
   }
+}
+
+// transverse fine rows whose interpolation takes coarse row c (the transpose
+// of the prolongation's rows f >> 1 at 3/4 and the neighbour on the side of
+// f at 1/4, clamped at the walls): fine rows 2c - 1 .. 2c + 2 with weights
+// 1/4, 3/4, 3/4, 1/4; at the low wall row 0 takes the full weight 1; at the
+// high wall, the last row 2N - 1 of an even side likewise, and along an odd
+// side (the last coarse cell covering one fine cell) rows beyond the fine
+// grid get weight zero.  Indices are clamped into the grid.
+template <typename T>
+__device__ __forceinline__ void restrict_rows(int c, int N, int nf, int (&r)[4], T (&w)[4]) {
+  r[0] = max(2 * c - 1, 0);
+  r[1] = 2 * c;
+  r[2] = min(2 * c + 1, nf - 1);
+  r[3] = min(2 * c + 2, nf - 1);
+  w[0] = c > 0 ? T(0.25) : T(0);
+  w[1] = c > 0 ? T(0.75) : T(1);
+  w[2] = 2 * c + 1 < nf ? (c < N - 1 ? T(0.75) : T(1)) : T(0);
+  w[3] = 2 * c + 2 < nf ? T(0.25) : T(0);
 }
 
 // Jacobi inverse diagonal of a level from its moduli: per face, the
@@ -158,20 +183,11 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(Grid gf, Grid gc, CVec3<T> r
   if (q >= (long)gc.nx * gc.ny * gc.nz) return;
   const int C[3] = {(int)(q % gc.nx), (int)((q / gc.nx) % gc.ny), (int)(q / ((long)gc.nx * gc.ny))};
   const int nc[3] = {gc.nx, gc.ny, gc.nz};
+  const int nf[3] = {gf.nx, gf.ny, gf.nz};
   int rows[3][4];                                // transverse fine rows per axis
   T w[3][4];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int c = C[a], N = nc[a], nf = 2 * N;
-    rows[a][0] = max(2 * c - 1, 0);
-    rows[a][1] = 2 * c;
-    rows[a][2] = 2 * c + 1;
-    rows[a][3] = min(2 * c + 2, nf - 1);
-    w[a][0] = c > 0 ? T(0.25) : T(0);
-    w[a][1] = c > 0 ? T(0.75) : T(1);
-    w[a][2] = c < N - 1 ? T(0.75) : T(1);
-    w[a][3] = c < N - 1 ? T(0.25) : T(0);
-  }
+  for (int a = 0; a < 3; ++a) restrict_rows<T>(C[a], nc[a], nf[a], rows[a], w[a]);
   const T wn[3] = {T(0.5), T(1), T(0.5)};
   const int ec = gidx(gc, C[0], C[1], C[2]);
 #pragma unroll
@@ -183,17 +199,22 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(Grid gf, Grid gc, CVec3<T> r
     const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
     T s = T(0);
 #pragma unroll
-    for (int sa = 0; sa < 3; ++sa)
+    for (int sa = 0; sa < 3; ++sa) {
+      // along the normal: fine faces 2C - 1, 2C, 2C + 1; the last is the
+      // fine high wall (not stored, zero) at the end of an odd side
+      const int fa = 2 * C[d] - 1 + sa;
+      const T wa = fa < nf[d] ? wn[sa] : T(0);
 #pragma unroll
       for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
         for (int oc = 0; oc < 4; ++oc) {
           int idx[3];
-          idx[d] = 2 * C[d] - 1 + sa;
+          idx[d] = min(fa, nf[d] - 1);
           idx[u] = rows[u][ob];
           idx[v] = rows[v][oc];
-          s += wn[sa] * w[u][ob] * w[v][oc] * rf.a[d][gidx(gf, idx[0], idx[1], idx[2])];
+          s += wa * w[u][ob] * w[v][oc] * rf.a[d][gidx(gf, idx[0], idx[1], idx[2])];
         }
+    }
     bc.a[d][ec] = T(0.25) * s;
   }
 }
@@ -209,15 +230,19 @@ __global__ __launch_bounds__(NT) void k_mg_coarsen2(Grid gf, Grid gc, const T* K
   for (long q = (long)blockIdx.x * NT + threadIdx.x; q < n; q += (long)gridDim.x * NT) {
     const int I = (int)(q % gc.nx), J = (int)(q / gc.nx);
     T sk = T(0), sg = T(0);
+    int cnt = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int e = gidx(gf, 2 * I + (c & 1), 2 * J + (c >> 1), 0);
+      const int fi = 2 * I + (c & 1), fj = 2 * J + (c >> 1);
+      if (fi >= gf.nx || fj >= gf.ny) continue;
+      const int e = gidx(gf, fi, fj, 0);
       sk += Kf[e];
       sg += Gf[e];
+      ++cnt;
     }
     const int ec = gidx(gc, I, J, 0);
-    Kc[ec] = T(0.25) * sk;
-    Gc[ec] = T(0.25) * sg;
+    Kc[ec] = sk / T(cnt);
+    Gc[ec] = sg / T(cnt);
   }
 }
 
@@ -286,20 +311,11 @@ __device__ __forceinline__ void restrict2_cell(const Grid& gf, const Grid& gc, c
                                                int c1) {
   const int C[2] = {c0, c1};
   const int nc[2] = {gc.nx, gc.ny};
+  const int nf[2] = {gf.nx, gf.ny};
   int rows[2][4];
   T w[2][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int c = C[a], N = nc[a], nf = 2 * N;
-    rows[a][0] = max(2 * c - 1, 0);
-    rows[a][1] = 2 * c;
-    rows[a][2] = 2 * c + 1;
-    rows[a][3] = min(2 * c + 2, nf - 1);
-    w[a][0] = c > 0 ? T(0.25) : T(0);
-    w[a][1] = c > 0 ? T(0.75) : T(1);
-    w[a][2] = c < N - 1 ? T(0.75) : T(1);
-    w[a][3] = c < N - 1 ? T(0.25) : T(0);
-  }
+  for (int a = 0; a < 2; ++a) restrict_rows<T>(C[a], nc[a], nf[a], rows[a], w[a]);
   const T wn[3] = {T(0.5), T(1), T(0.5)};
   const int ec = gidx(gc, C[0], C[1], 0);
 #pragma unroll
@@ -311,14 +327,17 @@ __device__ __forceinline__ void restrict2_cell(const Grid& gf, const Grid& gc, c
     const int u = 1 - d;
     T s = T(0);
 #pragma unroll
-    for (int sa = 0; sa < 3; ++sa)
+    for (int sa = 0; sa < 3; ++sa) {
+      const int fa = 2 * C[d] - 1 + sa;            // the last is the fine high wall at the end of an odd side
+      const T wa = fa < nf[d] ? wn[sa] : T(0);
 #pragma unroll
       for (int ob = 0; ob < 4; ++ob) {
         int idx[2];
-        idx[d] = 2 * C[d] - 1 + sa;
+        idx[d] = min(fa, nf[d] - 1);
         idx[u] = rows[u][ob];
-        s += wn[sa] * w[u][ob] * rf[d][gidx(gf, idx[0], idx[1], 0)];
+        s += wa * w[u][ob] * rf[d][gidx(gf, idx[0], idx[1], 0)];
       }
+    }
     bc[d][ec] = T(0.5) * s;
   }
 }

@@ -98,7 +98,7 @@ def test_multigrid_workspace_and_validation(lib):
         want = 6 * fine + 17 * (fine // 8 + fine // 64)
         assert want <= extra <= want + 64 * 8192, (prec, extra, want)
     odd = pf.make_config(3, (9, 12, 16), I.H_DEFAULT, 1e-8, cg_precond="mg")
-    assert sz(odd) > sz(pf.make_config(3, (9, 12, 16), I.H_DEFAULT, 1e-8))   # one level: Jacobi sweeps only
+    assert sz(odd) > sz(pf.make_config(3, (9, 12, 16), I.H_DEFAULT, 1e-8))   # levels 16x12x9 and 8x6x5
     jac2 = pf.make_config(2, (64, 64), I.H_DEFAULT, 1e-8)
     mg2 = pf.make_config(2, (64, 64), I.H_DEFAULT, 1e-8, cg_precond="mg")
     fine2 = 64 * 64 * 8

@@ -68,8 +68,9 @@ def test_full_size_solve_satisfies_the_oracle_equations(oracle, name, n, precisi
 def test_ragged_grid_with_multi_plane_slabs_matches_oracle(oracle, shape, precond):
     """53 x 72 x 130 cells: three tiles across x (the last 2 columns wide),
     nine tile rows, and slabs of two planes with a last slab of one.  With
-    the multigrid preconditioner, 52 x 72 x 132: levels 66 x 36 x 26 and
-    33 x 18 x 13 (ragged tiles on every level; the coarsest has odd sides)."""
+    the multigrid preconditioner, 132 x 72 x 52: levels 66 x 36 x 26,
+    33 x 18 x 13 and 17 x 9 x 7 (ragged tiles on every level; odd sides from
+    the third level on)."""
     from paper_2111_11538_amd import pf
     n = shape[0]
     f = I.ic_core_shell(shape, r_core=0.35 * n, r_shell=0.43 * n, noise_seed=I.SEED_BASE + 7)
