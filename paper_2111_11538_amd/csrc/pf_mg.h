@@ -53,8 +53,9 @@ __global__ __launch_bounds__(NT) void k_mg_coarsen(Grid gf, Grid gc, const T* Kf
       ++cnt;
     }
     const int ec = gidx(gc, I, J, K);
-    Kc[ec] = sk / T(cnt);
-    Gc[ec] = sg / T(cnt);
+    const T inv = cnt == 8 ? T(0.125) : T(1) / T(cnt);
+    Kc[ec] = inv * sk;
+    Gc[ec] = inv * sg;
   }
 }
 
@@ -64,16 +65,19 @@ __global__ __launch_bounds__(NT) void k_mg_coarsen(Grid gf, Grid gc, const T* Kf
 // 1/4, 3/4, 3/4, 1/4; at the low wall row 0 takes the full weight 1; at the
 // high wall, the last row 2N - 1 of an even side likewise, and along an odd
 // side (the last coarse cell covering one fine cell) rows beyond the fine
-// grid get weight zero.  Indices are clamped into the grid.
-template <typename T>
+// grid get weight zero.  Indices are clamped into the grid.  Edge = false is
+// for cells whose row 2c + 1 exists (every cell but the last one along an
+// odd side): the rows 2c, 2c + 1 stay affine in c, which lets the compiler
+// pair their loads along x.
+template <typename T, bool Edge>
 __device__ __forceinline__ void restrict_rows(int c, int N, int nf, int (&r)[4], T (&w)[4]) {
   r[0] = max(2 * c - 1, 0);
   r[1] = 2 * c;
-  r[2] = min(2 * c + 1, nf - 1);
+  r[2] = Edge ? min(2 * c + 1, nf - 1) : 2 * c + 1;
   r[3] = min(2 * c + 2, nf - 1);
   w[0] = c > 0 ? T(0.25) : T(0);
   w[1] = c > 0 ? T(0.75) : T(1);
-  w[2] = 2 * c + 1 < nf ? (c < N - 1 ? T(0.75) : T(1)) : T(0);
+  w[2] = (!Edge || 2 * c + 1 < nf) ? (c < N - 1 ? T(0.75) : T(1)) : T(0);
   w[3] = 2 * c + 2 < nf ? T(0.25) : T(0);
 }
 
@@ -176,18 +180,15 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(Grid gf, Grid gc, CVec3<T> xc
 // whose interpolation takes coarse row C, 2C - 1 .. 2C + 2 with weights
 // 1/4, 3/4, 3/4, 1/4 (at a wall the row beyond is absent and the clamped
 // interpolation gives the row at the wall the full weight 1).
-template <typename T>
-__global__ __launch_bounds__(NT) void k_mg_restrict(Grid gf, Grid gc, CVec3<T> rf, Vec3<T> bc, const double* scal) {
-  if (scal[S_CONV] != 0.0) return;
-  const long q = (long)blockIdx.x * NT + threadIdx.x;
-  if (q >= (long)gc.nx * gc.ny * gc.nz) return;
-  const int C[3] = {(int)(q % gc.nx), (int)((q / gc.nx) % gc.ny), (int)(q / ((long)gc.nx * gc.ny))};
+template <typename T, bool Edge>
+__device__ __forceinline__ void restrict3_cell(const Grid& gf, const Grid& gc, const CVec3<T>& rf, const Vec3<T>& bc,
+                                               const int (&C)[3]) {
   const int nc[3] = {gc.nx, gc.ny, gc.nz};
   const int nf[3] = {gf.nx, gf.ny, gf.nz};
   int rows[3][4];                                // transverse fine rows per axis
   T w[3][4];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) restrict_rows<T>(C[a], nc[a], nf[a], rows[a], w[a]);
+  for (int a = 0; a < 3; ++a) restrict_rows<T, Edge>(C[a], nc[a], nf[a], rows[a], w[a]);
   const T wn[3] = {T(0.5), T(1), T(0.5)};
   const int ec = gidx(gc, C[0], C[1], C[2]);
 #pragma unroll
@@ -197,26 +198,39 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(Grid gf, Grid gc, CVec3<T> r
       continue;
     }
     const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
+    // along the normal: fine faces 2C - 1, 2C, 2C + 1; the last is the fine
+    // high wall (not stored, zero) at the end of an odd side
+    const int fn[3] = {2 * C[d] - 1, 2 * C[d], Edge ? min(2 * C[d] + 1, nf[d] - 1) : 2 * C[d] + 1};
+    const T wa[3] = {wn[0], wn[1], (!Edge || 2 * C[d] + 1 < nf[d]) ? wn[2] : T(0)};
     T s = T(0);
 #pragma unroll
-    for (int sa = 0; sa < 3; ++sa) {
-      // along the normal: fine faces 2C - 1, 2C, 2C + 1; the last is the
-      // fine high wall (not stored, zero) at the end of an odd side
-      const int fa = 2 * C[d] - 1 + sa;
-      const T wa = fa < nf[d] ? wn[sa] : T(0);
+    for (int sa = 0; sa < 3; ++sa)
 #pragma unroll
       for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
         for (int oc = 0; oc < 4; ++oc) {
           int idx[3];
-          idx[d] = min(fa, nf[d] - 1);
+          idx[d] = fn[sa];
           idx[u] = rows[u][ob];
           idx[v] = rows[v][oc];
-          s += wa * w[u][ob] * w[v][oc] * rf.a[d][gidx(gf, idx[0], idx[1], idx[2])];
+          s += wa[sa] * w[u][ob] * w[v][oc] * rf.a[d][gidx(gf, idx[0], idx[1], idx[2])];
         }
-    }
     bc.a[d][ec] = T(0.25) * s;
   }
+}
+
+// one coarse cell per thread; the last cell along an odd side takes the
+// clamped rows
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_restrict(Grid gf, Grid gc, CVec3<T> rf, Vec3<T> bc, const double* scal) {
+  if (scal[S_CONV] != 0.0) return;
+  const long q = (long)blockIdx.x * NT + threadIdx.x;
+  if (q >= (long)gc.nx * gc.ny * gc.nz) return;
+  const int C[3] = {(int)(q % gc.nx), (int)((q / gc.nx) % gc.ny), (int)(q / ((long)gc.nx * gc.ny))};
+  if (2 * C[0] + 1 >= gf.nx || 2 * C[1] + 1 >= gf.ny || 2 * C[2] + 1 >= gf.nz)
+    restrict3_cell<T, true>(gf, gc, rf, bc, C);
+  else
+    restrict3_cell<T, false>(gf, gc, rf, bc, C);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,8 +255,9 @@ __global__ __launch_bounds__(NT) void k_mg_coarsen2(Grid gf, Grid gc, const T* K
       ++cnt;
     }
     const int ec = gidx(gc, I, J, 0);
-    Kc[ec] = sk / T(cnt);
-    Gc[ec] = sg / T(cnt);
+    const T inv = cnt == 4 ? T(0.25) : T(1) / T(cnt);
+    Kc[ec] = inv * sk;
+    Gc[ec] = inv * sg;
   }
 }
 
@@ -306,7 +321,7 @@ __device__ __forceinline__ void prolong2_cell(const Grid& gf, const Grid& gc, co
 }
 
 // coarse b = P^T r / 2 at coarse cell (c0, c1) (2D)
-template <typename T>
+template <typename T, bool Edge>
 __device__ __forceinline__ void restrict2_cell(const Grid& gf, const Grid& gc, const T* const* rf, T* const* bc, int c0,
                                                int c1) {
   const int C[2] = {c0, c1};
@@ -315,7 +330,7 @@ __device__ __forceinline__ void restrict2_cell(const Grid& gf, const Grid& gc, c
   int rows[2][4];
   T w[2][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a) restrict_rows<T>(C[a], nc[a], nf[a], rows[a], w[a]);
+  for (int a = 0; a < 2; ++a) restrict_rows<T, Edge>(C[a], nc[a], nf[a], rows[a], w[a]);
   const T wn[3] = {T(0.5), T(1), T(0.5)};
   const int ec = gidx(gc, C[0], C[1], 0);
 #pragma unroll
@@ -325,21 +340,31 @@ __device__ __forceinline__ void restrict2_cell(const Grid& gf, const Grid& gc, c
       continue;
     }
     const int u = 1 - d;
+    // along the normal: the last is the fine high wall at the end of an odd side
+    const int fn[3] = {2 * C[d] - 1, 2 * C[d], Edge ? min(2 * C[d] + 1, nf[d] - 1) : 2 * C[d] + 1};
+    const T wa[3] = {wn[0], wn[1], (!Edge || 2 * C[d] + 1 < nf[d]) ? wn[2] : T(0)};
     T s = T(0);
 #pragma unroll
-    for (int sa = 0; sa < 3; ++sa) {
-      const int fa = 2 * C[d] - 1 + sa;            // the last is the fine high wall at the end of an odd side
-      const T wa = fa < nf[d] ? wn[sa] : T(0);
+    for (int sa = 0; sa < 3; ++sa)
 #pragma unroll
       for (int ob = 0; ob < 4; ++ob) {
         int idx[2];
-        idx[d] = min(fa, nf[d] - 1);
+        idx[d] = fn[sa];
         idx[u] = rows[u][ob];
-        s += wa * w[u][ob] * rf[d][gidx(gf, idx[0], idx[1], 0)];
+        s += wa[sa] * w[u][ob] * rf[d][gidx(gf, idx[0], idx[1], 0)];
       }
-    }
     bc[d][ec] = T(0.5) * s;
   }
+}
+
+// the 2D cell with the clamped rows only where they are needed
+template <typename T>
+__device__ __forceinline__ void restrict2_at(const Grid& gf, const Grid& gc, const T* const* rf, T* const* bc, int c0,
+                                             int c1) {
+  if (2 * c0 + 1 >= gf.nx || 2 * c1 + 1 >= gf.ny)
+    restrict2_cell<T, true>(gf, gc, rf, bc, c0, c1);
+  else
+    restrict2_cell<T, false>(gf, gc, rf, bc, c0, c1);
 }
 
 // fine += P coarse, one fine cell per thread (2D)
@@ -357,7 +382,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict2(Grid gf, Grid gc, CVec3<T> 
   if (scal[S_CONV] != 0.0) return;
   const long q = (long)blockIdx.x * NT + threadIdx.x;
   if (q >= (long)gc.nx * gc.ny) return;
-  restrict2_cell<T>(gf, gc, rf.a, bc.a, (int)(q % gc.nx), (int)(q / gc.nx));
+  restrict2_at<T>(gf, gc, rf.a, bc.a, (int)(q % gc.nx), (int)(q / gc.nx));
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +510,7 @@ __global__ __launch_bounds__(kTailNT) void k_mg_tail2(const MGTailArgs<T>* ap) {
     const MGTailLevel<T>& C = a.lv[l + 1];
     const int nc = C.g.nx * C.g.ny;
     for (int q = threadIdx.x; q < nc; q += kTailNT)
-      restrict2_cell<T>(L.g, C.g, (const T* const*)L.r, C.bw, q % C.g.nx, q / C.g.nx);
+      restrict2_at<T>(L.g, C.g, (const T* const*)L.r, C.bw, q % C.g.nx, q / C.g.nx);
     sync();
   }
   {                                              // the coarsest level: sweeps from zero
