@@ -121,11 +121,11 @@ __global__ __launch_bounds__(NT) void k_mg_diag(Grid g, T ih, const T* K, const 
 // entry once the solve has converged (launches queued past convergence).
 
 // The transfers run one thread per cell (its three faces), in the
-// precision of the level's vectors, with every load in range (indices
-// clamped, weights zero where a term does not exist) so that a thread's
-// loads issue together.  (Staging a block's tile in LDS was tried: with the
-// little work per cell, the block-wide wait between the loads and the sums
-// made both transfers slower.)
+// precision of the level's vectors, with no branch around a load (indices
+// clamped or range-checked, weights zero where a term does not exist) so
+// that a thread's loads issue together.  (Staging a block's tile in LDS was
+// tried: with the little work per cell, the block-wide wait between the
+// loads and the sums made both transfers slower.)
 
 // fine += P coarse, one fine cell per thread.  Per face component d: along
 // the normal the coincident coarse face (weight 1) or the two coarse faces
@@ -147,9 +147,12 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(Grid gf, Grid gc, CVec3<T> xc
   }
   const T tw[2] = {T(0.75), T(0.25)};
   const int e = gidx(gf, f[0], f[1], f[2]);
+  // all three sums before the stores, so that no coarse load waits behind a
+  // fine store it might alias; the roller face f = 0 sums to zero (both
+  // normal weights vanish) and is left as it is
+  T s[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (f[d] == 0) continue;                     // roller face
     const int a0 = f[d] >> 1;
     const bool odd = f[d] & 1;
     const int a1 = min(a0 + 1, nc[d] - 1);
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(Grid gf, Grid gc, CVec3<T> xc
     const int an[2] = {a0, a1};
     const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
     const int ru[2] = {t0[u], t1[u]}, rv[2] = {t0[v], t1[v]};
-    T s = T(0);
+    s[d] = T(0);
 #pragma unroll
     for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
@@ -168,28 +171,47 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(Grid gf, Grid gc, CVec3<T> xc
           idx[d] = an[ia];
           idx[u] = ru[ib];
           idx[v] = rv[ic];
-          s += wn[ia] * tw[ib] * tw[ic] * xc.a[d][gidx(gc, idx[0], idx[1], idx[2])];
+          s[d] += wn[ia] * tw[ib] * tw[ic] * xc.a[d][gidx(gc, idx[0], idx[1], idx[2])];
         }
-    xf.a[d][e] += s;
   }
+  T o[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) o[d] = xf.a[d][e];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (f[d] != 0) xf.a[d][e] = o[d] + s[d];
 }
 
 // coarse b = R fine r = P^T r / 4, one coarse cell per thread.  Per face
 // component d (the roller face C = 0 gets zero): along the normal fine
-// faces 2C - 1, 2C, 2C + 1 (1/2, 1, 1/2); per transverse axis the fine rows
-// whose interpolation takes coarse row C, 2C - 1 .. 2C + 2 with weights
-// 1/4, 3/4, 3/4, 1/4 (at a wall the row beyond is absent and the clamped
-// interpolation gives the row at the wall the full weight 1).
-template <typename T, bool Edge>
+// faces 2C - 1, 2C, 2C + 1 (1/2, 1, 1/2; the last is the fine high wall,
+// not stored and zero, at the end of an odd side); per transverse axis the
+// fine rows whose interpolation takes coarse row C, 2C - 1 .. 2C + 2 with
+// weights 1/4, 3/4, 3/4, 1/4 (at a wall the row beyond is absent and the
+// clamped interpolation gives the row at the wall the full weight 1; along an
+// odd side the rows past the fine grid of the last coarse cell weigh zero).
+// A zero weight marks exactly the rows outside the fine grid.  The 48 fine
+// values per component are raw buffer loads (one 32-bit offset register
+// each, so the compiler keeps them all in flight): a (y, z) row outside the
+// grid gets an out-of-range offset and reads zero without touching memory,
+// and the x neighbours are immediate offsets from the row's first value, the
+// ones outside the grid zeroed by their weight's select.
+template <typename T>
 __device__ __forceinline__ void restrict3_cell(const Grid& gf, const Grid& gc, const CVec3<T>& rf, const Vec3<T>& bc,
                                                const int (&C)[3]) {
   const int nc[3] = {gc.nx, gc.ny, gc.nz};
   const int nf[3] = {gf.nx, gf.ny, gf.nz};
-  int rows[3][4];                                // transverse fine rows per axis
-  T w[3][4];
+  const int st[3] = {(int)sizeof(T), gf.px * (int)sizeof(T), gf.px * gf.ny * (int)sizeof(T)};
+  const int nbytes = gf.n * (int)sizeof(T);
+  T w[3][4];                                     // transverse weights of rows 2C - 1 .. 2C + 2 per axis
 #pragma unroll
-  for (int a = 0; a < 3; ++a) restrict_rows<T, Edge>(C[a], nc[a], nf[a], rows[a], w[a]);
-  const T wn[3] = {T(0.5), T(1), T(0.5)};
+  for (int a = 0; a < 3; ++a) {
+    const int c = C[a], N = nc[a], n = nf[a];
+    w[a][0] = c > 0 ? T(0.25) : T(0);
+    w[a][1] = c > 0 ? T(0.75) : T(1);
+    w[a][2] = 2 * c + 1 < n ? (c < N - 1 ? T(0.75) : T(1)) : T(0);
+    w[a][3] = 2 * c + 2 < n ? T(0.25) : T(0);
+  }
   const int ec = gidx(gc, C[0], C[1], C[2]);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -197,40 +219,46 @@ __device__ __forceinline__ void restrict3_cell(const Grid& gf, const Grid& gc, c
       bc.a[d][ec] = T(0);
       continue;
     }
-    const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
-    // along the normal: fine faces 2C - 1, 2C, 2C + 1; the last is the fine
-    // high wall (not stored, zero) at the end of an odd side
-    const int fn[3] = {2 * C[d] - 1, 2 * C[d], Edge ? min(2 * C[d] + 1, nf[d] - 1) : 2 * C[d] + 1};
-    const T wa[3] = {wn[0], wn[1], (!Edge || 2 * C[d] + 1 < nf[d]) ? wn[2] : T(0)};
+    T wt[3][4];                                  // weights per axis from fine index 2C - 1 on
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < 4; ++o)
+        wt[a][o] = a != d ? w[a][o]
+                          : (o == 0 ? T(0.5) : o == 1 ? T(1) : o == 2 && 2 * C[d] + 1 < nf[d] ? T(0.5) : T(0));
+    const int cnt[3] = {d == 0 ? 3 : 4, d == 1 ? 3 : 4, d == 2 ? 3 : 4};
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(rf.a[d], nbytes);
+    const int x0 = (2 * C[0] - 1) * st[0];
     T s = T(0);
 #pragma unroll
-    for (int sa = 0; sa < 3; ++sa)
+    for (int oc = 0; oc < cnt[2]; ++oc)
 #pragma unroll
-      for (int ob = 0; ob < 4; ++ob)
+      for (int ob = 0; ob < cnt[1]; ++ob) {
+        const int ro = wt[1][ob] != T(0) && wt[2][oc] != T(0)
+                           ? x0 + (2 * C[1] - 1 + ob) * st[1] + (2 * C[2] - 1 + oc) * st[2]
+                           : kOutOfRange;
+        T sx = T(0);
 #pragma unroll
-        for (int oc = 0; oc < 4; ++oc) {
-          int idx[3];
-          idx[d] = fn[sa];
-          idx[u] = rows[u][ob];
-          idx[v] = rows[v][oc];
-          s += wa[sa] * w[u][ob] * w[v][oc] * rf.a[d][gidx(gf, idx[0], idx[1], idx[2])];
+        for (int oa = 0; oa < cnt[0]; ++oa) {
+          const T v = buf_ld<T>(rs, ro + oa * st[0]);
+          sx += wt[0][oa] != T(0) ? wt[0][oa] * v : T(0);
         }
+        s += wt[1][ob] * wt[2][oc] * sx;
+      }
     bc.a[d][ec] = T(0.25) * s;
   }
 }
 
-// one coarse cell per thread; the last cell along an odd side takes the
-// clamped rows
+// one coarse cell per thread; the occupancy target of at most 6 waves per
+// SIMD lets the scheduler keep a component's loads in flight together (at
+// the default target of 8 it issues them one at a time)
 template <typename T>
-__global__ __launch_bounds__(NT) void k_mg_restrict(Grid gf, Grid gc, CVec3<T> rf, Vec3<T> bc, const double* scal) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, sizeof(T) == 4 ? 6 : 4))) void k_mg_restrict(Grid gf, Grid gc, CVec3<T> rf, Vec3<T> bc, const double* scal) {
   if (scal[S_CONV] != 0.0) return;
   const long q = (long)blockIdx.x * NT + threadIdx.x;
   if (q >= (long)gc.nx * gc.ny * gc.nz) return;
   const int C[3] = {(int)(q % gc.nx), (int)((q / gc.nx) % gc.ny), (int)(q / ((long)gc.nx * gc.ny))};
-  if (2 * C[0] + 1 >= gf.nx || 2 * C[1] + 1 >= gf.ny || 2 * C[2] + 1 >= gf.nz)
-    restrict3_cell<T, true>(gf, gc, rf, bc, C);
-  else
-    restrict3_cell<T, false>(gf, gc, rf, bc, C);
+  restrict3_cell<T>(gf, gc, rf, bc, C);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,9 +324,9 @@ __device__ __forceinline__ void prolong2_cell(const Grid& gf, const Grid& gc, co
   }
   const T tw[2] = {T(0.75), T(0.25)};
   const int e = gidx(gf, f[0], f[1], 0);
+  T s[2];                                        // both sums before the stores, as in 3D
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
-    if (f[d] == 0) continue;                     // roller face
     const int a0 = f[d] >> 1;
     const bool odd = f[d] & 1;
     const int a1 = min(a0 + 1, nc[d] - 1);
@@ -306,7 +334,7 @@ __device__ __forceinline__ void prolong2_cell(const Grid& gf, const Grid& gc, co
     const int an[2] = {a0, a1};
     const int u = 1 - d;
     const int ru[2] = {t0[u], t1[u]};
-    T s = T(0);
+    s[d] = T(0);
 #pragma unroll
     for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
@@ -314,10 +342,15 @@ __device__ __forceinline__ void prolong2_cell(const Grid& gf, const Grid& gc, co
         int idx[2];
         idx[d] = an[ia];
         idx[u] = ru[ib];
-        s += wn[ia] * tw[ib] * xc[d][gidx(gc, idx[0], idx[1], 0)];
+        s[d] += wn[ia] * tw[ib] * xc[d][gidx(gc, idx[0], idx[1], 0)];
       }
-    xf[d][e] += s;
   }
+  T o[2];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) o[d] = xf[d][e];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+    if (f[d] != 0) xf[d][e] = o[d] + s[d];     // the roller face f = 0 is left as it is
 }
 
 // coarse b = P^T r / 2 at coarse cell (c0, c1) (2D)
