@@ -202,6 +202,37 @@ def test_mg_2d_solve_matches_oracle(oracle, kind, shape):
     assert 3 * gst["cg_iters"] < ost["cg_iters"], (gst["cg_iters"], ost["cg_iters"])
 
 
+@pytest.mark.parametrize("dim,shape", [(3, (8, 12, 16)), (3, (20, 24, 7)), (2, (8, 40)), (2, (40, 7))])
+def test_mg_single_level_grid_matches_oracle(oracle, dim, shape):
+    """A grid with a side of at most 8 cells is not coarsened: the V-cycle is
+    the coarsest level's fixed Chebyshev sweeps on the solve's own grid, and
+    r.z comes from the last of them.  One FP64 solve from zero (16x12x8,
+    7x24x20 in 3D; 40x8, 7x40 in 2D): u as the oracle's Jacobi-PCG solution
+    to 1e-7 at rtol 1e-12, the true residual at rtol, in fewer iterations
+    than Jacobi."""
+    say(f"case mg single level {dim}D {shape}")
+    n = min(shape)
+    p = I.Params()
+    if dim == 3:
+        f = I.ic_core_shell(shape, r_core=0.35 * n, r_shell=0.43 * n, noise_seed=I.SEED_BASE + 2)
+    else:
+        f = I.ic_core_shell(shape, r_core=0.3 * n, frame=1, noise_seed=I.SEED_BASE + 1)
+    dt = I.stable_dt(p, I.H_DEFAULT, dim)
+    o = oracle.OracleSim(dim, shape, I.H_DEFAULT, dt, p, f, plasticity=False, cg_rtol=1e-12)
+    ost = o.mech_solve()
+    make = _ctx if dim == 3 else _ctx2
+    g = make(shape, p, dt, precision="fp64", plasticity=False, cg_rtol=1e-12, cg_precond="mg")
+    g.set_fields(f)
+    gst = g.mech_solve("zero")
+    out = g.fields()
+    g.close()
+    say(f"  iterations: mg {gst['cg_iters']}, oracle Jacobi {ost['cg_iters']}; true rel resid {gst['cg_rel_resid']:.2e}")
+    for c in ("ux", "uy", "uz")[:dim]:
+        assert rel(out[c], getattr(o, c)) < 1e-7, (c, rel(out[c], getattr(o, c)))
+    assert gst["cg_rel_resid"] < 2e-12
+    assert gst["cg_iters"] < ost["cg_iters"], (gst["cg_iters"], ost["cg_iters"])
+
+
 def test_mg_2d_steps_match_oracle(oracle):
     """Four coupled plastic FP64 steps of the 64^2 core-shell recipe with the
     multigrid solve: fields, increments, u and plastic strain as the oracle's."""
