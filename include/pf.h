@@ -5,10 +5,10 @@
  *
  * One call of pf_step advances the unknowns of the model's field relations
  * (Section 2.4, Eq. 29): the phase fields phi_f, phi_w (Allen-Cahn, Eq. 29
- * lines 5-6 with Eq. 33), the species x_O, x_H, x_H2O (Eq. 29 lines 1-3 with
+ * rows 5-6 with Eq. 33), the species x_O, x_H, x_H2O (Eq. 29 rows 1-3 with
  * the variational O flux of Eq. 24, Eq. 30 and Section 3.2), the plastic
  * strain (J2 with linear hardening, Eq. 25 and Eq. 34) and the displacement
- * of the quasi-static momentum balance (Eq. 29 line 4), in a small-strain
+ * of the quasi-static momentum balance (Eq. 29 row 4), in a small-strain
  * reading of the kinematics (eigenstrain d_T^(1/3) - 1 from Eq. 9, moduli of
  * Eq. 32).  All arithmetic runs in the library's HIP kernels.
  *
@@ -173,7 +173,7 @@ pf_status pf_init(const pf_config *cfg, const pf_params *params, void *workspace
  * After an error the context is in BAD_STATE until fields are set. */
 pf_status pf_step(pf_ctx *ctx, int nsteps, pf_step_stats *last);
 
-/* Solve only the mechanical equilibrium (Eq. 29 line 4) for the current phase
+/* Solve only the mechanical equilibrium (Eq. 29 row 4) for the current phase
  * fields and plastic strain, starting from zero (PF_WARM_ZERO), from the
  * current displacement (PF_WARM_PREV) or from the learned start
  * (PF_WARM_LEARNED, contexts created with it only).  Fills cg_iters, warm_used and

@@ -1,7 +1,7 @@
 // HIP kernels (gfx950) of the phase-field step.
 //
 //  k_elast      staggered-grid small-strain elasticity (quasi-static momentum
-//               balance, Eq. 29 line 4): q = A p with the CG direction update
+//               balance, Eq. 29 row 4): q = A p with the CG direction update
 //               fused in, the initial residual with the eigenstrain, norms.
 //               LDS-staged 64x4 tiles marching along z (2.5D blocking).
 //  k_cg_update  x += alpha p, r -= alpha q, z = D^-1 r with FP64 partial dots.
