@@ -532,6 +532,11 @@ struct Impl {
     const long n = (long)g.nx * g.ny * g.nz;
     return dim3((unsigned)((n + NT - 1) / NT));
   }
+  // the 3D prolongation: one thread per fine x pair
+  static dim3 mg_pair_blocks(const Grid& g) {
+    const long n = (long)((g.nx + 1) / 2) * g.ny * g.nz;
+    return dim3((unsigned)((n + NT - 1) / NT));
+  }
   static Vec3<T> mg_vec(pf_ctx* c, const size_t (&o)[3]) {
     Vec3<T> v;
     for (int d = 0; d < 3; ++d) v.a[d] = c->arr<T>(o[d]);
@@ -696,7 +701,8 @@ struct Impl {
     for (int l = down_end - 1; l >= 0; --l) {    // prolongation and post-smoothing, up to the solve's grid
       const Layout::MGLevel& m = L.mg[l];
       const Layout::MGLevel& mc = L.mg[l + 1];
-      timed_launch(c, PF_K_PRECOND, j, DIM == 3 ? k_mg_prolong<T> : k_mg_prolong2<T>, mg_cell_blocks(m.g), dim3(NT), 0,
+      timed_launch(c, PF_K_PRECOND, j, DIM == 3 ? k_mg_prolong<T> : k_mg_prolong2<T>,
+                   DIM == 3 ? mg_pair_blocks(m.g) : mg_cell_blocks(m.g), dim3(NT), 0,
                    st, m.g, mc.g, mg_cvec(c, mc.ox), mg_vec(c, m.ox), scal);
       sweep(l, m.ox, m.oxt, kStep[0]);
       sweep(l, m.oxt, m.ox, kStep[1]);           // level 0: z, with the partials of r.z

@@ -19,6 +19,8 @@
 // symmetric positive definite operator, as CG needs.
 #pragma once
 
+#include <type_traits>
+
 #include "pf_kernels.h"
 
 namespace pfk {
@@ -127,59 +129,109 @@ __global__ __launch_bounds__(NT) void k_mg_diag(Grid g, T ih, const T* K, const 
 // tried: with the little work per cell, the block-wide wait between the
 // loads and the sums made both transfers slower.)
 
-// fine += P coarse, one fine cell per thread.  Per face component d: along
-// the normal the coincident coarse face (weight 1) or the two coarse faces
-// around a midway fine face (1/2 each; the high wall holds zero and the low
-// roller face is zero); across it, per transverse axis, coarse rows f >> 1
-// (3/4) and its neighbour on the side of f (1/4; clamped at the walls).
+// fine += P coarse.  Per face component d: along the normal the coincident
+// coarse face (weight 1) or the two coarse faces around a midway fine face
+// (1/2 each; the high wall holds zero and the low roller face is zero);
+// across it, per transverse axis, coarse rows f >> 1 (3/4) and its
+// neighbour on the side of f (1/4; clamped at the walls).  One thread takes
+// the fine x pair 2i, 2i + 1 (the last alone along an odd side): both lie
+// over coarse column i and share their y and z rows, so the pair needs the
+// coarse columns i - 1, i, i + 1 once (32 coarse loads instead of 48), and
+// its fine values are read and written as pairs.  All sums are formed
+// before the stores, so no coarse load waits behind a fine store it might
+// alias.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_prolong(Grid gf, Grid gc, CVec3<T> xc, Vec3<T> xf, const double* scal) {
   if (scal[S_CONV] != 0.0) return;
+  const int hx = (gf.nx + 1) >> 1;
   const long q = (long)blockIdx.x * NT + threadIdx.x;
-  if (q >= (long)gf.nx * gf.ny * gf.nz) return;
-  const int f[3] = {(int)(q % gf.nx), (int)((q / gf.nx) % gf.ny), (int)(q / ((long)gf.nx * gf.ny))};
+  if (q >= (long)hx * gf.ny * gf.nz) return;
+  const int i = (int)(q % hx);
+  const int f[3] = {2 * i, (int)((q / hx) % gf.ny), (int)(q / ((long)hx * gf.ny))};
+  const bool two = 2 * i + 1 < gf.nx;            // the pair's second cell exists
   const int nc[3] = {gc.nx, gc.ny, gc.nz};
-  int t0[3], t1[3];                              // transverse rows per axis
+  const int cx[3] = {max(i - 1, 0), i, min(i + 1, nc[0] - 1)};
+  int t0[3], t1[3];                              // y and z transverse rows
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 1; a < 3; ++a) {
     t0[a] = f[a] >> 1;
     t1[a] = (f[a] & 1) ? min(t0[a] + 1, nc[a] - 1) : max(t0[a] - 1, 0);
   }
   const T tw[2] = {T(0.75), T(0.25)};
-  const int e = gidx(gf, f[0], f[1], f[2]);
-  // all three sums before the stores, so that no coarse load waits behind a
-  // fine store it might alias; the roller face f = 0 sums to zero (both
-  // normal weights vanish) and is left as it is
-  T s[3];
+  // normal weights of the coarse faces a0 = f >> 1 and a0 + 1 (y and z)
+  auto normal = [&](int a, T (&wn)[2], int (&an)[2]) {
+    const int a0 = f[a] >> 1;
+    const bool odd = f[a] & 1;
+    wn[0] = a0 > 0 ? (odd ? T(0.5) : T(1)) : T(0);
+    wn[1] = (odd && a0 + 1 < nc[a]) ? T(0.5) : T(0);
+    an[0] = a0;
+    an[1] = min(a0 + 1, nc[a] - 1);
+  };
+  T s0[3], s1[3];                                // sums of the cells 2i and 2i + 1
+  {                                              // d = 0: x is the normal
+    T v0 = T(0), v1 = T(0);                      // columns i and i + 1 over the y, z rows
+    const int ry[2] = {t0[1], t1[1]}, rz[2] = {t0[2], t1[2]};
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int a0 = f[d] >> 1;
-    const bool odd = f[d] & 1;
-    const int a1 = min(a0 + 1, nc[d] - 1);
-    const T wn[2] = {a0 > 0 ? (odd ? T(0.5) : T(1)) : T(0), (odd && a0 + 1 < nc[d]) ? T(0.5) : T(0)};
-    const int an[2] = {a0, a1};
-    const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
-    const int ru[2] = {t0[u], t1[u]}, rv[2] = {t0[v], t1[v]};
-    s[d] = T(0);
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int ic = 0; ic < 2; ++ic) {
+        const T w = tw[ib] * tw[ic];
+        v0 += w * xc.a[0][gidx(gc, cx[1], ry[ib], rz[ic])];
+        v1 += w * xc.a[0][gidx(gc, cx[2], ry[ib], rz[ic])];
+      }
+    s0[0] = i > 0 ? v0 : T(0);                   // coincident face i (face 0 is the roller)
+    s1[0] = (i > 0 ? T(0.5) * v0 : T(0)) + (i + 1 < nc[0] ? T(0.5) * v1 : T(0));
+  }
+#pragma unroll
+  for (int d = 1; d < 3; ++d) {                  // x transverse: 2i takes i, i - 1; 2i + 1 takes i, i + 1
+    const int o = 3 - d;                         // the other transverse axis
+    T wn[2];
+    int an[2];
+    normal(d, wn, an);
+    const int ro[2] = {t0[o], t1[o]};
+    T a0 = T(0), a1 = T(0);
 #pragma unroll
     for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-        for (int ic = 0; ic < 2; ++ic) {
-          int idx[3];
-          idx[d] = an[ia];
-          idx[u] = ru[ib];
-          idx[v] = rv[ic];
-          s[d] += wn[ia] * tw[ib] * tw[ic] * xc.a[d][gidx(gc, idx[0], idx[1], idx[2])];
-        }
+      for (int ic = 0; ic < 2; ++ic) {
+        int idx[3];
+        idx[d] = an[ia];
+        idx[o] = ro[ic];
+        const T w = wn[ia] * tw[ic];
+        idx[0] = cx[0];
+        const T xm = xc.a[d][gidx(gc, idx[0], idx[1], idx[2])];
+        idx[0] = cx[1];
+        const T x0 = xc.a[d][gidx(gc, idx[0], idx[1], idx[2])];
+        idx[0] = cx[2];
+        const T xp = xc.a[d][gidx(gc, idx[0], idx[1], idx[2])];
+        a0 += w * (tw[0] * x0 + tw[1] * xm);
+        a1 += w * (tw[0] * x0 + tw[1] * xp);
+      }
+    s0[d] = a0;
+    s1[d] = a1;
   }
-  T o[3];
+  // fine values; the second of a lone last cell reads the row's padding
+  // (the pitch exceeds an odd side) and is not written back
+  const int e = gidx(gf, f[0], f[1], f[2]);
+  using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+  T o0[3], o1[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) o[d] = xf.a[d][e];
+  for (int d = 0; d < 3; ++d) {
+    o0[d] = xf.a[d][e];
+    o1[d] = xf.a[d][e + 1];
+  }
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-    if (f[d] != 0) xf.a[d][e] = o[d] + s[d];
+  for (int d = 0; d < 3; ++d) {
+    if (d > 0 && f[d] == 0) continue;            // roller face: left as it is (d = 0 sums to zero there)
+    if (two) {                                   // one paired store (e is even, rows start aligned)
+      V2 v;
+      v.x = o0[d] + s0[d];
+      v.y = o1[d] + s1[d];
+      *reinterpret_cast<V2*>(xf.a[d] + e) = v;
+    } else {
+      xf.a[d][e] = o0[d] + s0[d];
+    }
+  }
 }
 
 // coarse b = R fine r = P^T r / 4, one coarse cell per thread.  Per face
