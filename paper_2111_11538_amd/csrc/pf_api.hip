@@ -72,6 +72,7 @@ struct Layout {
     dim3 grid;             // apply-kernel grid of the level
     double h;
     size_t oK, oG, odi[3], ob[3], ox[3], oxt[3], orr[3];
+    size_t olo[5];         // 3D FP32: bf16 copies of K, G, D^-1 (x, y, z) for the sweeps
   };
   static constexpr int kMGMax = 10;
   int mg_n;
@@ -207,10 +208,15 @@ Layout make_layout(const pf_config* c) {
         m.grid = dim3(nbx, (m.g.ny + m.kz - 1) / m.kz, 1);
       }
     };
+    const bool lo = dim == 3 && L.es == 4;
+    auto take_lo = [&](Layout::MGLevel& m) {
+      for (int a = 0; a < 5; ++a) m.olo[a] = lo ? take(align_up((size_t)m.g.n * 2)) : 0;
+    };
     Layout::MGLevel& m0 = L.mg[0];
     m0.g = g;
     m0.h = c->h;
     apply_geom(m0);
+    take_lo(m0);
     m0.oK = L.o_K;
     m0.oG = L.o_G;
     for (int d = 0; d < 3; ++d) {
@@ -232,6 +238,7 @@ Layout make_layout(const pf_config* c) {
       m.g.ns = m.g.n;
       m.h = 2.0 * L.mg[L.mg_n - 1].h;
       apply_geom(m);
+      take_lo(m);
       const size_t la = align_up((size_t)m.g.n * L.es);
       m.oK = take(la);
       m.oG = take(la);
@@ -570,6 +577,25 @@ struct Impl {
                    c->stream, m.g, (T)(1.0 / m.h), (const T*)c->arr<T>(m.oK), (const T*)c->arr<T>(m.oG),
                    mg_vec(c, m.odi));
     }
+    if constexpr (DIM == 3 && sizeof(T) == 4)    // the sweeps' bf16 K, G, D^-1 of every level
+      for (int l = 0; l < L.mg_n; ++l) {
+        const Layout::MGLevel& m = L.mg[l];
+        MGLoCopy cp;
+        const size_t src[5] = {m.oK, m.oG, m.odi[0], m.odi[1], m.odi[2]};
+        for (int a = 0; a < 5; ++a) {
+          cp.src[a] = (const float*)c->arr<T>(src[a]);
+          cp.dst[a] = c->arr<unsigned short>(m.olo[a]);
+        }
+        timed_launch(c, PF_K_PRECOND, -1, k_mg_lo, mg_blocks(m.g), dim3(NT), 0, c->stream, cp, m.g.n);
+      }
+  }
+  // a level's bf16 copies in the sweep arguments
+  static void mg_lo_args(pf_ctx* c, const Layout::MGLevel& m, ElastArgs<T>& a) {
+    if constexpr (DIM == 3 && sizeof(T) == 4) {
+      a.lo_K = c->arr<unsigned short>(m.olo[0]);
+      a.lo_G = c->arr<unsigned short>(m.olo[1]);
+      for (int d = 0; d < 3; ++d) a.lo_d[d] = c->arr<unsigned short>(m.olo[2 + d]);
+    }
   }
   // z = M^-1 r: one V-cycle from zero on the CG residual (level 0: b = r,
   // x = z), then r.z into the r.z partials CG reads (n_rz slots of part_u).
@@ -641,6 +667,7 @@ struct Impl {
       a.kz = m.kz;
       a.omega = omega;
       a.scal = c->scal();
+      mg_lo_args(c, m, a);
       if constexpr (DIM == 3)
         timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH>, m.grid,
                      dim3(ApplyTile<kApplyBY>::NTB), 0, st, a);
@@ -668,6 +695,7 @@ struct Impl {
       a.omega0 = kStep[0];
       a.omega = kStep[1];
       a.scal = c->scal();
+      mg_lo_args(c, m, a);
       if constexpr (DIM == 3)
         timed_launch(c, l == 0 ? PF_K_SMOOTH : PF_K_PRECOND, j, k_apply3<T, kApplyBY, APPLY_SMOOTH0>, m.grid,
                      dim3(ApplyTile<kApplyBY>::NTB), 0, st, a);

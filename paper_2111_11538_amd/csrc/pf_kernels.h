@@ -52,6 +52,13 @@ struct ElastArgs {
   int it;                  // APPLY_CG (3D): index of this launch in the solve
   double omega;            // APPLY_SMOOTH(0): step of the Jacobi sweep (0: write the residual instead)
   double omega0;           // APPLY_SMOOTH0: step of the first sweep from zero
+  // APPLY_SMOOTH(0) in FP32: bf16 copies of K, G and D^-1 of the level, which
+  // the multigrid sweeps read instead of K, G and dinv (the residual sweep of
+  // the cycle uses the same copies, so every sweep of a level applies one
+  // operator; CG itself keeps the FP32 moduli)
+  const unsigned short* lo_K;
+  const unsigned short* lo_G;
+  const unsigned short* lo_d[3];
 };
 
 // Local tile coordinates: lx = i - i0 + 1 in [0, TX+1], ly = j - j0 + 1 in [0, TY+1].
@@ -417,6 +424,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
   constexpr bool kPlain = AM != APPLY_CG, kResid = AM == APPLY_RESID, kCG = AM == APPLY_CG;
   constexpr bool kSmooth0 = AM == APPLY_SMOOTH0;
   constexpr bool kSmooth = AM == APPLY_SMOOTH || kSmooth0, kRB = kResid || kSmooth;   // kRB: reads b and D^-1
+  constexpr bool kLo = kSmooth && sizeof(T) == 4;   // K, G and D^-1 from their bf16 copies
   using TL = ApplyTile<BY>;
   constexpr int W = TL::W, S = TL::S, NTB = TL::NTB;
   __shared__ T sP[2][3][S];
@@ -539,7 +547,15 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
     rz_[d] = buf_rsrc(a.z[d], nbytes);
     ru_[d] = buf_rsrc(a.u[d], nbytes);
   }
-  const __amdgpu_buffer_rsrc_t rG = buf_rsrc(a.G, nbytes), rK = buf_rsrc(a.K, nbytes);
+  // K, G and D^-1 of a sweep in FP32 are bf16 (half the byte offset of an FP32
+  // element; the out-of-range offset halved is still past the array)
+  const int nb_lo = g.n * 2;
+  auto ld_lo = [&](__amdgpu_buffer_rsrc_t r, int off) __attribute__((always_inline)) -> T {
+    if constexpr (kLo) return (T)buf_ld_bf16(r, off >> 1);
+    else return buf_ld<T>(r, off);
+  };
+  const __amdgpu_buffer_rsrc_t rG = kLo ? buf_rsrc(a.lo_G, nb_lo) : buf_rsrc(a.G, nbytes);
+  const __amdgpu_buffer_rsrc_t rK = kLo ? buf_rsrc(a.lo_K, nb_lo) : buf_rsrc(a.K, nbytes);
   if constexpr (kPlain)        // p = z: the previous direction is never read
 #pragma unroll
     for (int d = 0; d < 3; ++d) ru_[d] = buf_rsrc(a.u[d], 0);
@@ -547,7 +563,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       rz_[d] = buf_rsrc(a.jr[d], nbytes);
-      ru_[d] = buf_rsrc(a.dinv[d], nbytes);
+      ru_[d] = kLo ? buf_rsrc(a.lo_d[d], nb_lo) : buf_rsrc(a.dinv[d], nbytes);
     }
   const T om0 = (T)a.omega0;
   __amdgpu_buffer_rsrc_t rjb_[3], rjd_[3];
@@ -555,7 +571,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       rjb_[d] = buf_rsrc(a.jr[d], nbytes);
-      rjd_[d] = buf_rsrc(a.dinv[d], nbytes);
+      rjd_[d] = kLo ? buf_rsrc(a.lo_d[d], nb_lo) : buf_rsrc(a.dinv[d], nbytes);
     }
   // only the first waves hold ring positions (threads < NRING); the others
   // run a copy of the plane loop without ring loads and stores (RW = false),
@@ -569,17 +585,19 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       R.oz[d] = buf_ld<T>(rz_[d], eo);
-      R.op[d] = buf_ld<T>(ru_[d], eo);
+      if constexpr (kSmooth0) R.op[d] = ld_lo(ru_[d], eo);
+      else R.op[d] = buf_ld<T>(ru_[d], eo);
     }
-    R.og = buf_ld<T>(rG, eo); R.ok = buf_ld<T>(rK, eo);
+    R.og = ld_lo(rG, eo); R.ok = ld_lo(rK, eo);
     if constexpr (decltype(RW)::value) {
       const int eh = R.hin ? (rg_e + kk * pl) * (int)sizeof(T) : kOutOfRange;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         R.hz[d] = buf_ld<T>(rz_[d], eh);
-        R.hp[d] = buf_ld<T>(ru_[d], eh);
+        if constexpr (kSmooth0) R.hp[d] = ld_lo(ru_[d], eh);
+        else R.hp[d] = buf_ld<T>(ru_[d], eh);
       }
-      R.hg = buf_ld<T>(rG, eh); R.hk = buf_ld<T>(rK, eh);
+      R.hg = ld_lo(rG, eh); R.hk = ld_lo(rK, eh);
     } else {
 #pragma unroll
       for (int d = 0; d < 3; ++d) R.hz[d] = R.hp[d] = T(0);
@@ -748,7 +766,7 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         jb[d] = buf_ld<T>(rjb_[d], eo);
-        jd[d] = buf_ld<T>(rjd_[d], eo);
+        jd[d] = ld_lo(rjd_[d], eo);
       }
     }
     // (A) own stresses of plane k and own z edges at level k+1

@@ -34,6 +34,25 @@ struct CVec3 {
   const T* a[3];
 };
 
+// bf16 copies (round to nearest even) of a level's K, G and D^-1 for the
+// FP32 sweeps, once per solve after the levels are set up (the sweeps are
+// bound by the bytes they move; the preconditioner only has to be a fixed
+// symmetric positive definite operator, which these copies keep it)
+struct MGLoCopy {
+  const float* src[5];
+  unsigned short* dst[5];
+};
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__global__ __launch_bounds__(NT) void k_mg_lo(MGLoCopy cp, int n) {
+  for (long q = (long)blockIdx.x * NT + threadIdx.x; q < n; q += (long)gridDim.x * NT)
+#pragma unroll
+    for (int a = 0; a < 5; ++a) cp.dst[a][q] = bf16_rne(cp.src[a][q]);
+}
+
 // moduli of the coarse cells: the mean of their children (8; fewer in the
 // last coarse cell along an odd side, which covers one fine cell there)
 template <typename T>

@@ -84,9 +84,10 @@ def test_workspace_size_and_validation(lib):
 
 def test_multigrid_workspace_and_validation(lib):
     """The multigrid preconditioner adds its levels to the workspace (3D: two
-    more fine vectors and 17 arrays per coarse level, 1/8 of the cells each;
-    2D: 12 arrays per coarse level, 1/4 of the cells each); batches and
-    unknown preconditioner codes are refused."""
+    more fine vectors and 17 arrays per coarse level, 1/8 of the cells each,
+    and in FP32 the sweeps' bf16 copies of K, G and D^-1 on every level; 2D:
+    12 arrays per coarse level, 1/4 of the cells each); batches and unknown
+    preconditioner codes are refused."""
     sz = lambda c: lib.pf_workspace_bytes(C.byref(c))
     for prec in ("fp64", "mixed"):
         jac = pf.make_config(3, (32, 32, 32), I.H_DEFAULT, 1e-8, precision=prec)
@@ -96,6 +97,8 @@ def test_multigrid_workspace_and_validation(lib):
         extra = sz(mg) - sz(jac)
         # level 0: 6 vectors; levels 16^3 and 8^3: 17 arrays each; alignment and stagger slack
         want = 6 * fine + 17 * (fine // 8 + fine // 64)
+        if prec == "mixed":       # 5 bf16 arrays per level (the 8^3 rows padded to 16)
+            want += 5 * 2 * (32 ** 3 + 16 ** 3 + 16 * 8 * 8)
         assert want <= extra <= want + 64 * 8192, (prec, extra, want)
     odd = pf.make_config(3, (9, 12, 16), I.H_DEFAULT, 1e-8, cg_precond="mg")
     assert sz(odd) > sz(pf.make_config(3, (9, 12, 16), I.H_DEFAULT, 1e-8))   # levels 16x12x9 and 8x6x5
