@@ -53,10 +53,10 @@ def algorithmic_bytes_per_cell(kind, dim, es, precond="jacobi"):
         return 4 * es
     if kind == "smooth":
         # multigrid sweeps on the solve's grid, four per cycle: the two-sweep pass from zero (read b, D^-1, K,
-        # G; write x), the residual and two post-smoothing sweeps (read x, b, D^-1, K, G; write x or r); the
-        # 3D FP32 sweeps read D^-1, K and G as bf16 copies (2 bytes each)
+        # G; write x), the residual sweep (read x, b, K, G; write r) and two post-smoothing sweeps (read x, b,
+        # D^-1, K, G; write x); the 3D FP32 sweeps read D^-1, K and G as bf16 copies (2 bytes each)
         lo = 2 if (dim == 3 and es == 4) else es
-        return ((2 * dim * es + (dim + 2) * lo) + 3 * (3 * dim * es + (dim + 2) * lo)) / 4.0
+        return ((2 * dim * es + (dim + 2) * lo) + (3 * dim * es + 2 * lo) + 2 * (3 * dim * es + (dim + 2) * lo)) / 4.0
     if kind == "solve_setup":
         if dim == 3:           # average of the set-up pass (phi_f, phi_w, eps_p -> K, G, b, D^-1), the residual
             # pass (u, K, G, b, D^-1 -> r, z) and the true residual (u, K, G, b -> q)

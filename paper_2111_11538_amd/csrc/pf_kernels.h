@@ -763,10 +763,13 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB, sizeof(T) == 4 && AM != APPLY_R
       }
     } else if constexpr (kRB) {
       const int eo = own ? (own_e + k * pl) * (int)sizeof(T) : kOutOfRange;
+      // the residual sweep (omega = 0) does not use D^-1: its loads are
+      // range-checked to zero and fetch nothing
+      const int eod = (kSmooth && a.omega == 0.0) ? kOutOfRange : eo;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         jb[d] = buf_ld<T>(rjb_[d], eo);
-        jd[d] = ld_lo(rjd_[d], eo);
+        jd[d] = ld_lo(rjd_[d], eod);
       }
     }
     // (A) own stresses of plane k and own z edges at level k+1
@@ -1322,7 +1325,8 @@ __device__ __forceinline__ void apply2_tile(const ElastArgs<T>& a, int bx, int b
         for (int d = 0; d < 2; ++d) {
           const T jb = a.jr[d][e];
           const T r = jb - qv[d];
-          const T o = a.omega != 0.0 ? pc[d] + om * a.dinv[d][e] * r : r;
+          T o = r;                                   // the residual sweep (omega = 0) reads no D^-1
+          if (a.omega != 0.0) o = pc[d] + om * a.dinv[d][e] * r;
           a.o1[d][e] = o;
           acc += (double)jb * (double)o;
         }
