@@ -577,8 +577,8 @@ struct Impl {
                    c->stream, m.g, (T)(1.0 / m.h), (const T*)c->arr<T>(m.oK), (const T*)c->arr<T>(m.oG),
                    mg_vec(c, m.odi));
     }
-    if constexpr (DIM == 3 && sizeof(T) == 4)    // the sweeps' bf16 K, G, D^-1 of every level
-      for (int l = 0; l < L.mg_n; ++l) {
+    if constexpr (DIM == 3 && sizeof(T) == 4)    // the sweeps' bf16 K, G, D^-1 of the coarse levels
+      for (int l = 1; l < L.mg_n; ++l) {
         const Layout::MGLevel& m = L.mg[l];
         MGLoCopy cp;
         const size_t src[5] = {m.oK, m.oG, m.odi[0], m.odi[1], m.odi[2]};
@@ -784,6 +784,8 @@ struct Impl {
         sa.dinv[d] = c->arr<T>(L.o_di[d]);
       }
       sa.kz = L.kz_ap;
+      if (sizeof(T) == 4 && L.mg_n > 0)          // the multigrid sweeps' bf16 copies of level 0
+        for (int a = 0; a < 5; ++a) sa.lo_w[a] = c->arr<unsigned short>(L.mg[0].olo[a]);
       timed_launch(c, PF_K_SOLVE_SETUP, -1, k_setup3<T, kApplyBY>, L.gap, dim3(ApplyTile<kApplyBY>::NTB), 0, st, sa);
       ElastArgs<T> ra = e;
       ra.kz = L.kz_ap;

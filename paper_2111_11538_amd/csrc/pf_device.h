@@ -77,6 +77,12 @@ template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_
 template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+// FP32 to bf16, round to nearest even (finite values)
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
 // a bf16 element (the upper half of an FP32 word) of a raw buffer, as FP32
 __device__ __forceinline__ float buf_ld_bf16(__amdgpu_buffer_rsrc_t r, int off) {
   return __uint_as_float((unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);

@@ -59,6 +59,7 @@ struct ElastArgs {
   const unsigned short* lo_K;
   const unsigned short* lo_G;
   const unsigned short* lo_d[3];
+  unsigned short* lo_w[5]; // k_setup3 (FP32): if set, also writes those copies of K, G, D^-1 (x, y, z)
 };
 
 // Local tile coordinates: lx = i - i0 + 1 in [0, TX+1], ly = j - j0 + 1 in [0, TY+1].
@@ -950,6 +951,10 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
       const int e = own_e + kk * pl;
       a.Kw[e] = mK;
       a.Gw[e] = mG;
+      if (a.lo_w[0]) {
+        a.lo_w[0][e] = bf16_rne((float)mK);
+        a.lo_w[1][e] = bf16_rne((float)mG);
+      }
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) O.n[q] = R.oin ? et + R.op[q] : T(0);
@@ -1127,8 +1132,10 @@ __global__ __launch_bounds__(ApplyTile<BY>::NTB) void k_setup3(ElastArgs<T> a) {
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) {
         const T r = -q[cc];
+        const T di = d[cc] > T(0) ? T(1) / (d[cc] * ih) : T(0);
         a.o1[cc][e] = r;
-        a.dinv[cc][e] = d[cc] > T(0) ? T(1) / (d[cc] * ih) : T(0);
+        a.dinv[cc][e] = di;
+        if (a.lo_w[2 + cc]) a.lo_w[2 + cc][e] = bf16_rne((float)di);
         acc += (double)r * (double)r;
       }
     }

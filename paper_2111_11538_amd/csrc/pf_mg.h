@@ -34,19 +34,15 @@ struct CVec3 {
   const T* a[3];
 };
 
-// bf16 copies (round to nearest even) of a level's K, G and D^-1 for the
-// FP32 sweeps, once per solve after the levels are set up (the sweeps are
+// bf16 copies (round to nearest even) of a coarse level's K, G and D^-1 for
+// the FP32 sweeps, once per solve after the levels are set up (the set-up
+// pass writes those of the solve's grid itself; the sweeps are
 // bound by the bytes they move; the preconditioner only has to be a fixed
 // symmetric positive definite operator, which these copies keep it)
 struct MGLoCopy {
   const float* src[5];
   unsigned short* dst[5];
 };
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
 __global__ __launch_bounds__(NT) void k_mg_lo(MGLoCopy cp, int n) {
   for (long q = (long)blockIdx.x * NT + threadIdx.x; q < n; q += (long)gridDim.x * NT)
 #pragma unroll
