@@ -358,74 +358,48 @@ __global__ __launch_bounds__(CONV_NT) void k_conv32(const uint4* __restrict__ wi
   }
 }
 
-// The output layer (one 16-channel block of which 3 are used) is too light on
-// multiplies for the row shifts to pay: there the three x taps go to three
-// accumulators instead, and the outputs are combined once per tile, by
-// shuffles within the 16-lane rows (acc0[v] + accp[v + 1] + accm[v - 1]; the
-// halo fragment's products complete the edge voxels).
+// The output layer (32 -> 3 channels, one 16-channel block) moves far more
+// bytes than it multiplies, so it marches along z instead: a wave owns one
+// output row (64 voxels of row y) through a run of up to kOutZ planes, and
+// each input plane p it loads (its rows y - 1, y, y + 1) feeds the three
+// output planes p + 1, p and p - 1 it touches (taps dz = -1, 0, +1), kept
+// in three accumulator sets that rotate as the march goes on; output plane
+// p - 1 is complete after plane p and is stored then.  An input row is thus
+// loaded once per plane by the wave instead of three times, and the 8 waves
+// of a block (8 consecutive rows) share their rows through the caches.
+// The x taps are the DPP row shifts of the 32-channel kernel.
+constexpr int kOutZ = 32;
 
-// Value of the neighbouring voxel (dir = +1: voxel lr + 1, dir = -1: voxel lr - 1)
-// within a 16-voxel block; the edge lane takes lane `edge_src` of `edge`.
-__device__ __forceinline__ f32x4 neighbour(const f32x4& cur, const f32x4& edge, int lr, int dir, int edge_src) {
-  f32x4 r;
-  const int src = (lr + dir) & 15;
-  const bool at_edge = dir > 0 ? lr == 15 : lr == 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float a = __shfl(cur[i], src, 16);
-    const float b = __shfl(edge[i], edge_src, 16);
-    r[i] = at_edge ? b : a;
-  }
-  return r;
-}
-
-template <int MB, int EPI>
-__global__ __launch_bounds__(CONV_NT) void k_conv32_acc3(const uint4* __restrict__ wimg, const float* __restrict__ bias,
-                                                    const uint16_t* __restrict__ x, void* __restrict__ out,
-                                                    const uint16_t* __restrict__ mask, Vol v) {
+template <int EPI>
+__global__ __launch_bounds__(CONV_NT) void k_conv32_out(const uint4* __restrict__ wimg, const float* __restrict__ bias,
+                                                        const uint16_t* __restrict__ x, float* __restrict__ out,
+                                                        Vol v) {
+  static_assert(EPI == EPI_LINEAR, "the z march serves the linear output layer");
   constexpr int CIN = 32;
-  constexpr int KC = kTaps;                    // one k chunk per tap
-  constexpr int COUT = MB * 16;
+  constexpr int KC = kTaps;
   extern __shared__ uint4 sW[];
-  for (int i = threadIdx.x; i < MB * KC * 64; i += CONV_NT) sW[i] = wimg[i];
+  for (int i = threadIdx.x; i < KC * 64; i += CONV_NT) sW[i] = wimg[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int lr = lane & 15, lg = lane >> 4;
-  const int nseg = (v.W + SEG - 1) / SEG, nyt = (v.H + CONV_WAVES - 1) / CONV_WAVES;
-  const long ntiles = (long)nseg * nyt * v.D * v.n;
-  // each block walks a contiguous run of tiles, z fastest, so the input planes
-  // shared by consecutive tiles are reused from its XCD's L2
-  const long t0 = ntiles * blockIdx.x / gridDim.x, t1 = ntiles * (blockIdx.x + 1) / gridDim.x;
-  for (long t = t0; t < t1; ++t) {
-    const int z = (int)(t % v.D);
-    long r = t / v.D;
-    const int xs = (int)(r % nseg);
-    r /= nseg;
+  const int nseg = (v.W + SEG - 1) / SEG, nyt = (v.H + CONV_WAVES - 1) / CONV_WAVES, nzc = (v.D + kOutZ - 1) / kOutZ;
+  const long nitems = (long)nseg * nyt * nzc * v.n;
+  for (long t = blockIdx.x; t < nitems; t += gridDim.x) {
+    const int xs = (int)(t % nseg);
+    long r = t / nseg;
     const int y = (int)(r % nyt) * CONV_WAVES + wv;
-    const int n = (int)(r / nyt);
+    r /= nyt;
+    const int zc = (int)(r % nzc);
+    const int n = (int)(r / nzc);
     if (y >= v.H) continue;                     // whole wave; no block barrier follows
     const int x0 = xs * SEG;
-    f32x4 am[MB][NBW], a0[MB][NBW], ap[MB][NBW], hm[MB], hp[MB];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      hm[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      hp[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) {
-        am[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        a0[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        ap[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      }
-    }
-    // Branch-free loads through a buffer resource spanning one input row: the
-    // hardware range check returns zero for voxels outside the row (offset
-    // pushed past the end) and for rows outside the volume (empty range).
-    // b[NBW] is the halo fragment: lane 0 voxel x0 - 1, lane 1 voxel x0 + 64.
+    const int z0 = zc * kOutZ, z1 = min(z0 + kOutZ, v.D);
     const int xh = lr == 0 ? x0 - 1 : (lr == 1 ? x0 + SEG : -1);
-    auto load = [&](int c, uint4 (&b)[NBW + 1]) {   // c = 3 (dz + 1) + (dy + 1)
-      const int zz = z + c / 3 - 1, yy = y + c % 3 - 1;
-      const bool rok = zz >= 0 && zz < v.D && yy >= 0 && yy < v.H;
-      const uint16_t* row = rok ? x + ((((long)n * v.D + zz) * v.H + yy) * v.W) * CIN : x;
+    // fragments of input row (p, yy): four 16-voxel blocks and the halo
+    // (lane 0: voxel x0 - 1, lane 1: voxel x0 + 64); zero outside the volume
+    auto load = [&](int p, int yy, uint4 (&b)[NBW + 1]) __attribute__((always_inline)) {
+      const bool rok = p >= 0 && p < v.D && yy >= 0 && yy < v.H;
+      const uint16_t* row = rok ? x + ((((long)n * v.D + p) * v.H + yy) * v.W) * CIN : x;
       const __amdgpu_buffer_rsrc_t rs =
           __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(row), 0, rok ? v.W * CIN * 2 : 0, kBufferFlags);
 #pragma unroll
@@ -436,74 +410,61 @@ __global__ __launch_bounds__(CONV_NT) void k_conv32_acc3(const uint4* __restrict
         b[nb] = uint4{q[0], q[1], q[2], q[3]};
       }
     };
-    // the fragments of the next (dz, dy) pair are loaded while one is
-    // multiplied (one set plus a copy; a deeper prefetch costs occupancy
-    // here, which this kernel needs more)
-    uint4 bc[NBW + 1], bn[NBW + 1];
-    load(0, bc);
-    for (int c = 0; c < 9; ++c) {
-      if (c + 1 < 9) load(c + 1, bn);
+    // acc[0]: output plane p - 1 (tap dz = +1), acc[1]: p (dz = 0), acc[2]: p + 1 (dz = -1)
+    f32x4 acc[3][NBW];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const bf16x8 wm = as_bf8(sW[(mb * KC + 3 * c + 0) * 64 + lane]);
-        const bf16x8 w0 = as_bf8(sW[(mb * KC + 3 * c + 1) * 64 + lane]);
-        const bf16x8 wp = as_bf8(sW[(mb * KC + 3 * c + 2) * 64 + lane]);
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // one input row (p, y + dyo): its three x shifts times the weights of the
+    // three output planes it reaches
+    auto row_mul = [&](int dy, const uint4 (&bc)[NBW + 1]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        const uint4 bm = dpp4<kRowShr1>(nb > 0 ? dpp4<kRowRor1>(bc[nb - 1]) : bc[NBW], bc[nb]);
+        const uint4 bp = dpp4<kRowShl1>(nb + 1 < NBW ? dpp4<kRowRor15>(bc[nb + 1]) : dpp4<kRowRor14>(bc[NBW]), bc[nb]);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {            // s = 0: dz = +1, 1: dz = 0, 2: dz = -1
+          const int c = 3 * (2 - s) + dy;        // tap row c = 3 (dz + 1) + (dy + 1)
+          const bf16x8 wm = as_bf8(sW[(3 * c + 0) * 64 + lane]);
+          const bf16x8 w0 = as_bf8(sW[(3 * c + 1) * 64 + lane]);
+          const bf16x8 wp = as_bf8(sW[(3 * c + 2) * 64 + lane]);
+          acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, as_bf8(bm), acc[s][nb], 0, 0, 0);
+          acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, as_bf8(bc[nb]), acc[s][nb], 0, 0, 0);
+          acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp, as_bf8(bp), acc[s][nb], 0, 0, 0);
+        }
+      }
+    };
+    // rows in march order: (p, y - 1), (p, y), (p, y + 1), (p + 1, y - 1), ...
+    // for p = z0 - 1 .. z1; the next row's fragments load while one multiplies
+    uint4 bc[NBW + 1], bn[NBW + 1];
+    load(z0 - 1, y - 1, bc);
+    for (int p = z0 - 1; p <= z1; ++p) {
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int pn = dy < 2 ? p : p + 1, yn = dy < 2 ? y + dy : y - 1;
+        if (pn <= z1) load(pn, yn, bn);
+        row_mul(dy, bc);
+#pragma unroll
+        for (int nb = 0; nb <= NBW; ++nb) bc[nb] = bn[nb];
+      }
+      // output plane p - 1 is complete; lane holds out(co = 4 lg + i, voxel = 16 nb + lr)
+      if (p - 1 >= z0 && lg == 0) {
+        const long vrow = (((long)n * v.D + (p - 1)) * v.H + y) * v.W;
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb) {
-          const bf16x8 b = as_bf8(bc[nb]);
-          am[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, b, am[mb][nb], 0, 0, 0);
-          a0[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, b, a0[mb][nb], 0, 0, 0);
-          ap[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp, b, ap[mb][nb], 0, 0, 0);
+          const int xx = x0 + nb * 16 + lr;
+          if (xx < v.W)
+            reinterpret_cast<float4*>(out)[vrow + xx] =
+                make_float4(acc[0][nb][0] + bias[0], acc[0][nb][1] + bias[1], acc[0][nb][2] + bias[2],
+                            acc[0][nb][3] + bias[3]);
         }
-        const bf16x8 h = as_bf8(bc[NBW]);
-        hm[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, h, hm[mb], 0, 0, 0);
-        hp[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wp, h, hp[mb], 0, 0, 0);
       }
 #pragma unroll
-      for (int nb = 0; nb <= NBW; ++nb) bc[nb] = bn[nb];
-    }
-    // out(voxel u) = a0[u] + ap[u + 1] + am[u - 1]; lane holds co = 16 mb + 4 lg + i
-    const long vrow = (((long)n * v.D + z) * v.H + y) * v.W;
-#pragma unroll
-    for (int nb = 0; nb < NBW; ++nb) {
-      f32x4 o[MB];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const f32x4 fp = nb + 1 < NBW ? neighbour(ap[mb][nb], ap[mb][nb + 1], lr, +1, 0)
-                                      : neighbour(ap[mb][nb], hp[mb], lr, +1, 1);
-        const f32x4 fm = nb > 0 ? neighbour(am[mb][nb], am[mb][nb - 1], lr, -1, 15)
-                                : neighbour(am[mb][nb], hm[mb], lr, -1, 0);
-        o[mb] = a0[mb][nb] + fp + fm;
-      }
-      const int xx = x0 + nb * 16 + lr;
-      if (xx >= v.W) continue;
-      const long vox = vrow + xx;
-      if constexpr (EPI == EPI_LINEAR) {
-        if (lg == 0)
-          reinterpret_cast<float4*>(out)[vox] =
-              make_float4(o[0][0] + bias[0], o[0][1] + bias[1], o[0][2] + bias[2], o[0][3] + bias[3]);
-      } else {
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const int co0 = mb * 16 + lg * 4;
-          float q[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) q[i] = o[mb][i];
-          if constexpr (EPI == EPI_RELU) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) q[i] = fmaxf(q[i] + bias[co0 + i], 0.f);
-          } else {
-            const uint2 mk = *reinterpret_cast<const uint2*>(mask + vox * COUT + co0);
-            if (!bf_pos(mk.x & 0xFFFFu)) q[0] = 0.f;
-            if (!bf_pos(mk.x >> 16)) q[1] = 0.f;
-            if (!bf_pos(mk.y & 0xFFFFu)) q[2] = 0.f;
-            if (!bf_pos(mk.y >> 16)) q[3] = 0.f;
-          }
-          uint2 st;
-          st.x = pack2(q[0], q[1]);
-          st.y = pack2(q[2], q[3]);
-          *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + vox * COUT + co0) = st;
-        }
+      for (int nb = 0; nb < NBW; ++nb) {
+        acc[0][nb] = acc[1][nb];
+        acc[1][nb] = acc[2][nb];
+        acc[2][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
     }
   }

@@ -109,6 +109,13 @@ static int conv32_grid(const Vol& v, int cap) {
   return (int)std::max(1LL, std::min(nt, (long long)cap));
 }
 
+// the output layer's z march: one block per (volume, row tile, x segment, z run)
+static int conv_out_grid(const Vol& v, int cap) {
+  long long nt = (long long)((v.W + pfn::SEG - 1) / pfn::SEG) * ((v.H + pfn::CONV_WAVES - 1) / pfn::CONV_WAVES) *
+                 ((v.D + pfn::kOutZ - 1) / pfn::kOutZ) * v.n;
+  return (int)std::max(1LL, std::min(nt, (long long)cap));
+}
+
 static int conv_grid(const Vol& v, int cap) {
   long long nt = (long long)((v.W + pfn::SEG - 1) / pfn::SEG) * ((v.H + pfn::CONV_WAVES - 1) / pfn::CONV_WAVES) * v.D * v.n;
   return (int)std::max(1LL, std::min(nt, (long long)cap));
@@ -126,8 +133,8 @@ static pf_status nn_conv_fwd(pf_nn* nn, int l, const uint16_t* x, void* y, const
     hipLaunchKernelGGL((pfn::k_conv32<2, pfn::EPI_RELU>), dim3(conv32_grid(v, 512)), dim3(pfn::CONV_NT), smem, st, w,
                        (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
   else
-    hipLaunchKernelGGL((pfn::k_conv32_acc3<1, pfn::EPI_LINEAR>), dim3(conv32_grid(v, 512)), dim3(pfn::CONV_NT), smem, st, w,
-                       (const float*)nn->bias_p[l], x, y, (const uint16_t*)nullptr, v);
+    hipLaunchKernelGGL((pfn::k_conv32_out<pfn::EPI_LINEAR>), dim3(conv_out_grid(v, 2048)), dim3(pfn::CONV_NT), smem, st,
+                       w, (const float*)nn->bias_p[l], x, (float*)y, v);
   NNLAUNCH(nn);
   return PF_OK;
 }
