@@ -130,6 +130,26 @@ def test_mg_mixed_porous_64():
         assert d < 1e-3, (c, d)
 
 
+def test_mg_bf16_sweeps_keep_the_iteration_count():
+    """In FP32 the 3D sweeps read bf16 copies of K, G and D^-1, so the cycle
+    preconditions with a slightly perturbed operator (relative 2^-9 per
+    coefficient); the FP64 cycle reads the exact ones.  On the 64^3 porous
+    recipe from zero at rtol 1e-6 the FP32 solve may not need noticeably
+    more iterations than the FP64 one (a copy of the wrong array, a wrong
+    offset or a broken rounding would show as many more)."""
+    wl = I.workload("porous_3d", n=64)
+    say(f"case mg bf16 sweeps {wl.shape}")
+    its = {}
+    for prec in ("fp64", "mixed"):
+        g = _ctx(wl.shape, wl.params, wl.dt, precision=prec, plasticity=True, cg_rtol=1e-6, cg_precond="mg")
+        g.set_fields(wl.fields)
+        st = g.mech_solve("zero")
+        g.close()
+        its[prec] = st["cg_iters"]
+        say(f"  {prec}: {st['cg_iters']} iterations, true rel resid {st['cg_rel_resid']:.2e}")
+    assert its["mixed"] <= its["fp64"] + 2, its
+
+
 def test_mg_bitwise_repeatable():
     """Fixed-order reductions throughout the cycle: two runs of three mixed
     steps give the same bits."""
