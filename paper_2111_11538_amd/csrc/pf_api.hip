@@ -718,6 +718,26 @@ struct Impl {
     if (tail > 0) {                              // the small levels' whole cycle in one launch
       timed_launch(c, PF_K_PRECOND, j, k_mg_tail2<T>, dim3(1), dim3(kTailNT), 0, st,
                    (const MGTailArgs<T>*)c->arr<MGTailArgs<T>>(L.o_mg_tail));
+    } else if (DIM == 3 && last >= 1 &&
+               (long)L.mg[last].g.nx * L.mg[last].g.ny * L.mg[last].g.nz <= kCoarseLdsCells * 4 / (long)sizeof(T)) {
+      // a small coarsest level (not the solve's own grid, whose last sweep
+      // forms the r.z partials): its sweeps in one block, in LDS
+      const Layout::MGLevel& m = L.mg[last];
+      CoarseArgs<T> ca{};
+      ca.g = m.g;
+      ca.ih = (T)(1.0 / m.h);
+      ca.K = c->arr<T>(m.oK);
+      ca.G = c->arr<T>(m.oG);
+      for (int d = 0; d < 3; ++d) {
+        ca.b[d] = c->arr<T>(m.ob[d]);
+        ca.dinv[d] = c->arr<T>(m.odi[d]);
+        ca.x[d] = c->arr<T>(m.ox[d]);
+      }
+      ca.s0 = (T)kStep[0];
+      ca.s1 = (T)kStep[1];
+      ca.sweeps = kCoarseSweeps;
+      ca.scal = scal;
+      timed_launch(c, PF_K_PRECOND, j, k_mg_coarse3<T>, dim3(1), dim3(kCoarseNT), 0, st, ca);
     } else {                                     // coarsest level: a fixed number of sweeps from zero
       const Layout::MGLevel& m = L.mg[last];
       sweep0(last, m.ox);

@@ -329,6 +329,129 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, sizeof(T)
 }
 
 // ---------------------------------------------------------------------------
+// The coarsest 3D level's sweeps in one block: at 8^3 each of its 7 launches
+// (the pass from zero and 6 sweeps) costs about 5 us whatever its work, so a
+// level of at most kCoarseLdsCells cells (FP32; half as many in FP64) is
+// staged in LDS (b, K, G, D^-1 and two iterates, compact x-fastest) and
+// swept there, a block barrier between sweeps.  The steps are those of the
+// launch path (s0 D^-1 b, then alternately s1 and s0); the operator is the
+// apply kernel's staggered one per face, from the level's FP32 moduli (every
+// sweep of the level is here, so the level applies one operator).
+// ---------------------------------------------------------------------------
+constexpr int kCoarseNT = 1024;
+constexpr int kCoarseLdsCells = 2048;
+
+template <typename T>
+struct CoarseArgs {
+  Grid g;
+  T ih;
+  const T* K;
+  const T* G;
+  const T* b[3];
+  const T* dinv[3];
+  T* x[3];                 // out: the level's iterate after the sweeps
+  T s0, s1;
+  int sweeps;              // even, at least 2
+  const double* scal;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kCoarseNT) void k_mg_coarse3(CoarseArgs<T> a) {
+  if (a.scal[S_CONV] != 0.0) return;
+  constexpr int NMAX = kCoarseLdsCells * 4 / (int)sizeof(T);
+  __shared__ T sK[NMAX], sG[NMAX], sb[3][NMAX], sd[3][NMAX], sx[2][3][NMAX];
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, n = nx * ny * nz;
+  const T ih = a.ih;
+  for (int q = threadIdx.x; q < n; q += kCoarseNT) {
+    const int i = q % nx, j = (q / nx) % ny, k = q / (nx * ny);
+    const int e = gidx(a.g, i, j, k);
+    sK[q] = a.K[e];
+    sG[q] = a.G[e];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      sb[d][q] = a.b[d][e];
+      sd[d][q] = a.dinv[d][e];
+      sx[0][d][q] = a.s0 * a.dinv[d][e] * a.b[d][e];   // the first sweep from zero
+    }
+  }
+  __syncthreads();
+  auto at = [&](int i, int j, int k) { return (k * ny + j) * nx + i; };
+  // x[d] at a face; the high walls (index n_d) hold zero
+  auto X = [&](const int src, int d, int i, int j, int k) -> T {
+    return (i < nx && j < ny && k < nz) ? sx[src][d][at(i, j, k)] : T(0);
+  };
+  auto Gc = [&](int i, int j, int k) -> T { return sG[at(i, j, k)]; };
+  auto snn = [&](int src, int i, int j, int k, T& sxx, T& syy, T& szz) {
+    const T exx = (X(src, 0, i + 1, j, k) - X(src, 0, i, j, k)) * ih;
+    const T eyy = (X(src, 1, i, j + 1, k) - X(src, 1, i, j, k)) * ih;
+    const T ezz = (X(src, 2, i, j, k + 1) - X(src, 2, i, j, k)) * ih;
+    const T tr = exx + eyy + ezz;
+    const T G2 = T(2) * Gc(i, j, k);
+    const T lam = sK[at(i, j, k)] * tr - G2 * tr * T(1.0 / 3.0);
+    sxx = lam + G2 * exx;
+    syy = lam + G2 * eyy;
+    szz = lam + G2 * ezz;
+  };
+  // shear stresses on the interior edges (zero on the boundary)
+  auto sxy = [&](int src, int i, int j, int k) -> T {
+    if (!(i > 0 && i < nx && j > 0 && j < ny && k < nz)) return T(0);
+    const T ge = T(0.25) * (Gc(i - 1, j - 1, k) + Gc(i, j - 1, k) + Gc(i - 1, j, k) + Gc(i, j, k));
+    return ge * ((X(src, 0, i, j, k) - X(src, 0, i, j - 1, k)) + (X(src, 1, i, j, k) - X(src, 1, i - 1, j, k))) * ih;
+  };
+  auto sxz = [&](int src, int i, int j, int k) -> T {
+    if (!(k > 0 && k < nz && i > 0 && i < nx && j < ny)) return T(0);
+    const T ge = T(0.25) * (Gc(i - 1, j, k - 1) + Gc(i, j, k - 1) + Gc(i - 1, j, k) + Gc(i, j, k));
+    return ge * ((X(src, 0, i, j, k) - X(src, 0, i, j, k - 1)) + (X(src, 2, i, j, k) - X(src, 2, i - 1, j, k))) * ih;
+  };
+  auto syz = [&](int src, int i, int j, int k) -> T {
+    if (!(k > 0 && k < nz && j > 0 && j < ny && i < nx)) return T(0);
+    const T ge = T(0.25) * (Gc(i, j - 1, k - 1) + Gc(i, j, k - 1) + Gc(i, j - 1, k) + Gc(i, j, k));
+    return ge * ((X(src, 1, i, j, k) - X(src, 1, i, j, k - 1)) + (X(src, 2, i, j, k) - X(src, 2, i, j - 1, k))) * ih;
+  };
+  // one sweep src -> dst: x + omega D^-1 (b - A x) at every face
+  auto sweep = [&](int src, int dst, T om) {
+    for (int q = threadIdx.x; q < n; q += kCoarseNT) {
+      const int i = q % nx, j = (q / nx) % ny, k = q / (nx * ny);
+      T sxx, syy, szz;
+      snn(src, i, j, k, sxx, syy, szz);
+      const T exy = sxy(src, i, j, k), exz = sxz(src, i, j, k), eyz = syz(src, i, j, k);
+      T qv[3] = {T(0), T(0), T(0)};
+      if (i > 0) {
+        T lxx, lyy, lzz;
+        snn(src, i - 1, j, k, lxx, lyy, lzz);
+        qv[0] = lxx - sxx + exy - sxy(src, i, j + 1, k) + exz - sxz(src, i, j, k + 1);
+      }
+      if (j > 0) {
+        T bxx, byy, bzz;
+        snn(src, i, j - 1, k, bxx, byy, bzz);
+        qv[1] = byy - syy + exy - sxy(src, i + 1, j, k) + eyz - syz(src, i, j, k + 1);
+      }
+      if (k > 0) {
+        T dxx, dyy, dzz;
+        snn(src, i, j, k - 1, dxx, dyy, dzz);
+        qv[2] = dzz - szz + exz - sxz(src, i + 1, j, k) + eyz - syz(src, i, j + 1, k);
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sx[dst][d][q] = sx[src][d][q] + om * sd[d][q] * (sb[d][q] - qv[d]);
+    }
+    __syncthreads();
+  };
+  // sweep 0 (from zero) was formed while staging; sweeps 1 .. n - 1
+  // alternate the steps s1, s0, s1, ...
+  int cur = 0;
+  for (int s = 1; s < a.sweeps; ++s) {
+    sweep(cur, cur ^ 1, (s & 1) ? a.s1 : a.s0);
+    cur ^= 1;
+  }
+  for (int q = threadIdx.x; q < n; q += kCoarseNT) {
+    const int i = q % nx, j = (q / nx) % ny, k = q / (nx * ny);
+    const int e = gidx(a.g, i, j, k);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.x[d][e] = sx[cur][d][q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 2D (plane strain) levels: the same construction with two face components,
 // one transverse axis per component, and the restriction the transposed
 // prolongation divided by 2 (the operator carries 1/h, the energy h).
