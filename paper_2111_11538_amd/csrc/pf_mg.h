@@ -335,11 +335,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, sizeof(T)
 // staged in LDS (b, K, G, D^-1 and two iterates, compact x-fastest) and
 // swept there, a block barrier between sweeps.  The steps are those of the
 // launch path (s0 D^-1 b, then alternately s1 and s0); the operator is the
-// apply kernel's staggered one per face, from the level's FP32 moduli (every
-// sweep of the level is here, so the level applies one operator).
+// apply kernel's staggered one, from the level's FP32 moduli (every sweep of
+// the level is here, so the level applies one operator): per sweep the cell
+// and edge stresses once, then the forces on the faces, a barrier between.
 // ---------------------------------------------------------------------------
 constexpr int kCoarseNT = 1024;
-constexpr int kCoarseLdsCells = 2048;
+constexpr int kCoarseLdsCells = 1536;
 
 template <typename T>
 struct CoarseArgs {
@@ -359,7 +360,9 @@ template <typename T>
 __global__ __launch_bounds__(kCoarseNT) void k_mg_coarse3(CoarseArgs<T> a) {
   if (a.scal[S_CONV] != 0.0) return;
   constexpr int NMAX = kCoarseLdsCells * 4 / (int)sizeof(T);
-  __shared__ T sK[NMAX], sG[NMAX], sb[3][NMAX], sd[3][NMAX], sx[2][3][NMAX];
+  // moduli, b, D^-1, two iterates; per sweep the cell normal stresses and the
+  // shear stresses of the edges at each cell's low corner
+  __shared__ T sK[NMAX], sG[NMAX], sb[3][NMAX], sd[3][NMAX], sx[2][3][NMAX], sn[3][NMAX], se[3][NMAX];
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz, n = nx * ny * nz;
   const T ih = a.ih;
   for (int q = threadIdx.x; q < n; q += kCoarseNT) {
@@ -375,62 +378,59 @@ __global__ __launch_bounds__(kCoarseNT) void k_mg_coarse3(CoarseArgs<T> a) {
     }
   }
   __syncthreads();
-  auto at = [&](int i, int j, int k) { return (k * ny + j) * nx + i; };
-  // x[d] at a face; the high walls (index n_d) hold zero
-  auto X = [&](const int src, int d, int i, int j, int k) -> T {
-    return (i < nx && j < ny && k < nz) ? sx[src][d][at(i, j, k)] : T(0);
-  };
-  auto Gc = [&](int i, int j, int k) -> T { return sG[at(i, j, k)]; };
-  auto snn = [&](int src, int i, int j, int k, T& sxx, T& syy, T& szz) {
-    const T exx = (X(src, 0, i + 1, j, k) - X(src, 0, i, j, k)) * ih;
-    const T eyy = (X(src, 1, i, j + 1, k) - X(src, 1, i, j, k)) * ih;
-    const T ezz = (X(src, 2, i, j, k + 1) - X(src, 2, i, j, k)) * ih;
-    const T tr = exx + eyy + ezz;
-    const T G2 = T(2) * Gc(i, j, k);
-    const T lam = sK[at(i, j, k)] * tr - G2 * tr * T(1.0 / 3.0);
-    sxx = lam + G2 * exx;
-    syy = lam + G2 * eyy;
-    szz = lam + G2 * ezz;
-  };
-  // shear stresses on the interior edges (zero on the boundary)
-  auto sxy = [&](int src, int i, int j, int k) -> T {
-    if (!(i > 0 && i < nx && j > 0 && j < ny && k < nz)) return T(0);
-    const T ge = T(0.25) * (Gc(i - 1, j - 1, k) + Gc(i, j - 1, k) + Gc(i - 1, j, k) + Gc(i, j, k));
-    return ge * ((X(src, 0, i, j, k) - X(src, 0, i, j - 1, k)) + (X(src, 1, i, j, k) - X(src, 1, i - 1, j, k))) * ih;
-  };
-  auto sxz = [&](int src, int i, int j, int k) -> T {
-    if (!(k > 0 && k < nz && i > 0 && i < nx && j < ny)) return T(0);
-    const T ge = T(0.25) * (Gc(i - 1, j, k - 1) + Gc(i, j, k - 1) + Gc(i - 1, j, k) + Gc(i, j, k));
-    return ge * ((X(src, 0, i, j, k) - X(src, 0, i, j, k - 1)) + (X(src, 2, i, j, k) - X(src, 2, i - 1, j, k))) * ih;
-  };
-  auto syz = [&](int src, int i, int j, int k) -> T {
-    if (!(k > 0 && k < nz && j > 0 && j < ny && i < nx)) return T(0);
-    const T ge = T(0.25) * (Gc(i, j - 1, k - 1) + Gc(i, j, k - 1) + Gc(i, j - 1, k) + Gc(i, j, k));
-    return ge * ((X(src, 1, i, j, k) - X(src, 1, i, j, k - 1)) + (X(src, 2, i, j, k) - X(src, 2, i, j - 1, k))) * ih;
-  };
+  const int sy = nx, sz = nx * ny;                 // compact strides
   // one sweep src -> dst: x + omega D^-1 (b - A x) at every face
   auto sweep = [&](int src, int dst, T om) {
+    const T* X0 = sx[src][0];
+    const T* X1 = sx[src][1];
+    const T* X2 = sx[src][2];
+    // (a) per cell: its normal stresses, and the shear stresses of the three
+    // edges at its low corner (zero on the boundary); x beyond a high wall is 0
     for (int q = threadIdx.x; q < n; q += kCoarseNT) {
       const int i = q % nx, j = (q / nx) % ny, k = q / (nx * ny);
-      T sxx, syy, szz;
-      snn(src, i, j, k, sxx, syy, szz);
-      const T exy = sxy(src, i, j, k), exz = sxz(src, i, j, k), eyz = syz(src, i, j, k);
+      const T x0 = X0[q], x1 = X1[q], x2 = X2[q];
+      const T exx = ((i + 1 < nx ? X0[q + 1] : T(0)) - x0) * ih;
+      const T eyy = ((j + 1 < ny ? X1[q + sy] : T(0)) - x1) * ih;
+      const T ezz = ((k + 1 < nz ? X2[q + sz] : T(0)) - x2) * ih;
+      const T tr = exx + eyy + ezz;
+      const T G2 = T(2) * sG[q];
+      const T lam = sK[q] * tr - G2 * tr * T(1.0 / 3.0);
+      sn[0][q] = lam + G2 * exx;
+      sn[1][q] = lam + G2 * eyy;
+      sn[2][q] = lam + G2 * ezz;
+      T exy = T(0), exz = T(0), eyz = T(0);
+      if (i > 0 && j > 0) {
+        const T ge = T(0.25) * (sG[q - 1 - sy] + sG[q - sy] + sG[q - 1] + sG[q]);
+        exy = ge * ((x0 - X0[q - sy]) + (x1 - X1[q - 1])) * ih;
+      }
+      if (i > 0 && k > 0) {
+        const T ge = T(0.25) * (sG[q - 1 - sz] + sG[q - sz] + sG[q - 1] + sG[q]);
+        exz = ge * ((x0 - X0[q - sz]) + (x2 - X2[q - 1])) * ih;
+      }
+      if (j > 0 && k > 0) {
+        const T ge = T(0.25) * (sG[q - sy - sz] + sG[q - sz] + sG[q - sy] + sG[q]);
+        eyz = ge * ((x1 - X1[q - sz]) + (x2 - X2[q - sy])) * ih;
+      }
+      se[0][q] = exy;
+      se[1][q] = exz;
+      se[2][q] = eyz;
+    }
+    __syncthreads();
+    // (b) per face: the divergence of the stresses (roller faces i, j, k = 0
+    // get zero; the edges past the high walls carry none)
+    for (int q = threadIdx.x; q < n; q += kCoarseNT) {
+      const int i = q % nx, j = (q / nx) % ny, k = q / (nx * ny);
+      const T exy = se[0][q], exz = se[1][q], eyz = se[2][q];
       T qv[3] = {T(0), T(0), T(0)};
-      if (i > 0) {
-        T lxx, lyy, lzz;
-        snn(src, i - 1, j, k, lxx, lyy, lzz);
-        qv[0] = lxx - sxx + exy - sxy(src, i, j + 1, k) + exz - sxz(src, i, j, k + 1);
-      }
-      if (j > 0) {
-        T bxx, byy, bzz;
-        snn(src, i, j - 1, k, bxx, byy, bzz);
-        qv[1] = byy - syy + exy - sxy(src, i + 1, j, k) + eyz - syz(src, i, j, k + 1);
-      }
-      if (k > 0) {
-        T dxx, dyy, dzz;
-        snn(src, i, j, k - 1, dxx, dyy, dzz);
-        qv[2] = dzz - szz + exz - sxz(src, i + 1, j, k) + eyz - syz(src, i, j + 1, k);
-      }
+      if (i > 0)
+        qv[0] = sn[0][q - 1] - sn[0][q] + exy - (j + 1 < ny ? se[0][q + sy] : T(0)) + exz -
+                (k + 1 < nz ? se[1][q + sz] : T(0));
+      if (j > 0)
+        qv[1] = sn[1][q - sy] - sn[1][q] + exy - (i + 1 < nx ? se[0][q + 1] : T(0)) + eyz -
+                (k + 1 < nz ? se[2][q + sz] : T(0));
+      if (k > 0)
+        qv[2] = sn[2][q - sz] - sn[2][q] + exz - (i + 1 < nx ? se[1][q + 1] : T(0)) + eyz -
+                (j + 1 < ny ? se[2][q + sy] : T(0));
 #pragma unroll
       for (int d = 0; d < 3; ++d) sx[dst][d][q] = sx[src][d][q] + om * sd[d][q] * (sb[d][q] - qv[d]);
     }
