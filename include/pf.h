@@ -161,8 +161,11 @@ pf_status pf_init(const pf_config *cfg, const pf_params *params, void *workspace
  * full weighting along the normal and linear across it (restriction =
  * transposed prolongation / 4, in 2D / 2), two Jacobi sweeps with Chebyshev
  * steps before and after
- * each coarse correction and eight on the coarsest level; the solution is
- * the same to cg_rtol, in far fewer iterations.  The CG
+ * each coarse correction and eight on the coarsest level (in 3D PF_MIXED the
+ * sweeps read bf16 copies of each level's moduli and diagonal, which keeps
+ * the cycle a fixed symmetric positive definite operator; CG itself keeps
+ * the FP32 moduli); the solution is the same to cg_rtol, in far fewer
+ * iterations.  The CG
  * recurrence scalars and the convergence test live on the device; the host
  * reads the convergence flag once per chunk of queued CG launches (a stream
  * synchronisation per chunk, see pf_cg_chunk: launches queued past
